@@ -1,0 +1,512 @@
+/*
+ * FP64 CPU oracle of the GNN track-finding hot path (ETX4VELO, thesis ch. 8-9).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this library.  It shares no code with the
+ * HIP path: every step below is written from its definition in the thesis,
+ * in double precision, with plain loops, one event at a time.
+ *
+ * Steps (one event, hits indexed 0..n-1 in the caller's order):
+ *   features    ch. 8 "Hit Embedding and Rough Graph Construction" (normalised
+ *               cylindrical input of the embedding) and ch. 8 "Graph Neural
+ *               Network and Classifiers" (normalised Cartesian node input)
+ *   embedding   the embedding MLP (Linear, ReLU between layers, linear output)
+ *   radius      the squared-distance equation of ch. 8 and the k-NN algorithm of
+ *               ch. 9 "k-NN Implementation": brute force over the next
+ *               `window` planes, d^2 < r^2, keep the k_max smallest by (d^2, j)
+ *   gnn         ch. 8 "Graph Neural Network": node/edge encoders, the message
+ *               equation (concatenated out-sum and in-sum), residual node and
+ *               edge updates with distinct networks per step, edge classifier
+ *   components  ch. 9 "WCC Implementation" (DFS/BFS weakly connected
+ *               components); the label is the smallest hit index in the
+ *               component
+ *
+ * Optional quantisation (thesis ch. 4 "Quantization", symmetric scale
+ * x = S x_q): every GEMM operand is replaced by its exactly rounded BF16 or
+ * FP8-E4M3 value (after division by its per-tensor scale) before the FP64
+ * product.  qmode 0 disables it.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* quantisers written from the number formats' definitions                   */
+/* ------------------------------------------------------------------------ */
+
+/* Round x to the nearest value with `mbits` fraction bits and minimum normal
+ * exponent emin (subnormals below it), ties to even; saturate at +-maxv. */
+static double round_format(double x, int mbits, int emin, double maxv) {
+  if (x != x) return x;
+  double a = fabs(x);
+  if (a == 0.0) return x;
+  int e;
+  frexp(a, &e);            /* a = f * 2^e, f in [0.5, 1) -> leading bit is 2^(e-1) */
+  int lead = e - 1;
+  if (lead < emin) lead = emin;            /* subnormal spacing */
+  double ulp = ldexp(1.0, lead - mbits);
+  double q = a / ulp;                       /* exact: power-of-two scaling */
+  double r = nearbyint(q);                  /* default rounding mode: ties to even */
+  double v = r * ulp;
+  if (v > maxv) v = maxv;
+  return x < 0 ? -v : v;
+}
+
+double oracle_round_bf16(double x) { return round_format(x, 7, -126, 3.3895313892515355e38); }
+double oracle_round_e4m3(double x) { return round_format(x, 3, -6, 448.0); }
+
+typedef struct {
+  int mode;          /* 0 none, 1 bf16, 2 fp8 e4m3 with per-tensor scales */
+} qctx;
+
+/* quantise a GEMM operand: value -> S * round(value / S) */
+static double qv(int mode, double x, double scale) {
+  if (mode == 1) return oracle_round_bf16(x);
+  if (mode == 2) return scale * oracle_round_e4m3(x / scale);
+  return x;
+}
+
+/* ------------------------------------------------------------------------ */
+/* features                                                                  */
+/* ------------------------------------------------------------------------ */
+
+void oracle_features(int64_t n, const float* x, const float* y, const float* z,
+                     double r_scale, double z_scale, double* cyl, double* cart) {
+  for (int64_t i = 0; i < n; ++i) {
+    double xi = x[i], yi = y[i], zi = z[i];
+    double r = hypot(xi, yi);
+    double phi = atan2(yi, xi);
+    cyl[3 * i + 0] = r / r_scale;
+    cyl[3 * i + 1] = phi / M_PI;
+    cyl[3 * i + 2] = zi / z_scale;
+    cart[3 * i + 0] = xi / r_scale;
+    cart[3 * i + 1] = yi / r_scale;
+    cart[3 * i + 2] = zi / z_scale;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* dense layers                                                              */
+/* ------------------------------------------------------------------------ */
+
+/* out[m] = b[m] + sum_k q(in[k]) q(W[k][m]);  W row-major [K][M] */
+static void linear(const double* in, int K, const double* W, const double* b, int M,
+                   double* out, int qmode, double s_in, double s_w) {
+  for (int m = 0; m < M; ++m) {
+    double acc = 0.0;
+    for (int k = 0; k < K; ++k) acc += qv(qmode, in[k], s_in) * qv(qmode, W[(int64_t)k * M + m], s_w);
+    out[m] = acc + b[m];
+  }
+}
+
+/* LayerNorm over the feature axis (biased variance, eps 1e-5, no affine), then ReLU */
+static void layernorm_relu(double* v, int n) {
+  double mean = 0.0;
+  for (int i = 0; i < n; ++i) mean += v[i];
+  mean /= n;
+  double var = 0.0;
+  for (int i = 0; i < n; ++i) var += (v[i] - mean) * (v[i] - mean);
+  var /= n;
+  double inv = 1.0 / sqrt(var + 1e-5);
+  for (int i = 0; i < n; ++i) {
+    double t = (v[i] - mean) * inv;
+    v[i] = t > 0.0 ? t : 0.0;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* embedding MLP                                                             */
+/* ------------------------------------------------------------------------ */
+
+/* dims[0..n_layers]: widths (dims[0] = 3); params: W0 b0 W1 b1 ...;
+ * hidden layers use ReLU, the output layer is linear.  qscale (may be NULL):
+ * per layer (input scale, weight scale). */
+void oracle_embed(int64_t n, const double* cyl, int n_layers, const int* dims,
+                  const double* params, double* emb, int qmode, const double* qscale) {
+  int maxw = 0;
+  for (int l = 0; l <= n_layers; ++l) if (dims[l] > maxw) maxw = dims[l];
+  double* a = (double*)malloc(sizeof(double) * maxw);
+  double* b = (double*)malloc(sizeof(double) * maxw);
+  for (int64_t i = 0; i < n; ++i) {
+    for (int k = 0; k < dims[0]; ++k) a[k] = cyl[3 * i + k];
+    const double* p = params;
+    for (int l = 0; l < n_layers; ++l) {
+      int K = dims[l], M = dims[l + 1];
+      double si = qscale ? qscale[2 * l] : 1.0, sw = qscale ? qscale[2 * l + 1] : 1.0;
+      /* the first layer (K = 3 coordinates) is never quantised */
+      linear(a, K, p, p + (int64_t)K * M, M, b, l == 0 ? 0 : qmode, si, sw);
+      p += (int64_t)K * M + M;
+      if (l + 1 < n_layers)
+        for (int m = 0; m < M; ++m) b[m] = b[m] > 0.0 ? b[m] : 0.0;
+      memcpy(a, b, sizeof(double) * M);
+    }
+    for (int m = 0; m < dims[n_layers]; ++m) emb[i * dims[n_layers] + m] = a[m];
+  }
+  free(a);
+  free(b);
+}
+
+/* ------------------------------------------------------------------------ */
+/* radius graph (brute force, the definition)                                */
+/* ------------------------------------------------------------------------ */
+
+typedef struct { double d2; int32_t j; } cand_t;
+
+static int cand_cmp(const void* A, const void* B) {
+  const cand_t* a = (const cand_t*)A;
+  const cand_t* b = (const cand_t*)B;
+  if (a->d2 < b->d2) return -1;
+  if (a->d2 > b->d2) return 1;
+  return (a->j > b->j) - (a->j < b->j);
+}
+
+static int int_cmp(const void* A, const void* B) {
+  int32_t a = *(const int32_t*)A, b = *(const int32_t*)B;
+  return (a > b) - (a < b);
+}
+
+/* Edges i -> j with 1 <= plane_j - plane_i <= window and d^2(e_i, e_j) < r^2,
+ * at most k_max per source (smallest (d^2, j)), sorted by (i, j).
+ * Writes at most cap edges; returns the number of edges the graph has. */
+int64_t oracle_radius(int64_t n, const int32_t* plane, const double* emb, int D,
+                      double radius, int k_max, int window,
+                      int32_t* src, int32_t* dst, int64_t cap) {
+  double r2 = radius * radius;
+  cand_t* c = (cand_t*)malloc(sizeof(cand_t) * (n > 0 ? n : 1));
+  int32_t* sel = (int32_t*)malloc(sizeof(int32_t) * (k_max > 0 ? k_max : 1));
+  int64_t E = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    int nc = 0;
+    for (int64_t j = 0; j < n; ++j) {
+      int dp = plane[j] - plane[i];
+      if (dp < 1 || dp > window) continue;
+      double d2 = 0.0;
+      for (int k = 0; k < D; ++k) {
+        double t = emb[i * D + k] - emb[j * D + k];
+        d2 += t * t;
+      }
+      if (d2 < r2) { c[nc].d2 = d2; c[nc].j = (int32_t)j; ++nc; }
+    }
+    qsort(c, nc, sizeof(cand_t), cand_cmp);
+    int keep = nc < k_max ? nc : k_max;
+    for (int t = 0; t < keep; ++t) sel[t] = c[t].j;
+    qsort(sel, keep, sizeof(int32_t), int_cmp);
+    for (int t = 0; t < keep; ++t) {
+      if (E < cap) { src[E] = (int32_t)i; dst[E] = sel[t]; }
+      ++E;
+    }
+  }
+  free(c);
+  free(sel);
+  return E;
+}
+
+/* Per-source candidate statistics used by the decidability rule of the parity
+ * protocol: for source i, the distance gap at the k boundary and the closest
+ * |d - r| over its candidate window.  dist_gap[i] = +inf when fewer than
+ * k_max+1 candidates lie inside r. */
+void oracle_radius_margins(int64_t n, const int32_t* plane, const double* emb, int D,
+                           double radius, int k_max, int window,
+                           double* r_margin, double* k_gap) {
+  cand_t* c = (cand_t*)malloc(sizeof(cand_t) * (n > 0 ? n : 1));
+  double r2 = radius * radius;
+  for (int64_t i = 0; i < n; ++i) {
+    int nc = 0;
+    double rm = INFINITY;
+    for (int64_t j = 0; j < n; ++j) {
+      int dp = plane[j] - plane[i];
+      if (dp < 1 || dp > window) continue;
+      double d2 = 0.0;
+      for (int k = 0; k < D; ++k) {
+        double t = emb[i * D + k] - emb[j * D + k];
+        d2 += t * t;
+      }
+      double dm = fabs(sqrt(d2) - radius);
+      if (dm < rm) rm = dm;
+      if (d2 < r2) { c[nc].d2 = d2; c[nc].j = (int32_t)j; ++nc; }
+    }
+    r_margin[i] = rm;
+    if (nc > k_max && k_max > 0) {
+      qsort(c, nc, sizeof(cand_t), cand_cmp);
+      k_gap[i] = sqrt(c[k_max].d2) - sqrt(c[k_max - 1].d2);
+    } else {
+      k_gap[i] = INFINITY;
+    }
+  }
+  free(c);
+}
+
+/* ------------------------------------------------------------------------ */
+/* interaction network                                                       */
+/* ------------------------------------------------------------------------ */
+
+/* Two Blocks: Block(x) = ReLU(LN(x W + b)).  p points at W1 b1 W2 b2. */
+static const double* mlp2(const double* in, int K, int H, const double* p, double* tmp, double* out,
+                          int qmode, const double* qs) {
+  linear(in, K, p, p + (int64_t)K * H, H, tmp, qmode, qs ? qs[0] : 1.0, qs ? qs[1] : 1.0);
+  layernorm_relu(tmp, H);
+  p += (int64_t)K * H + H;
+  linear(tmp, H, p, p + (int64_t)H * H, H, out, qmode, qs ? qs[2] : 1.0, qs ? qs[3] : 1.0);
+  layernorm_relu(out, H);
+  return p + (int64_t)H * H + H;
+}
+
+/* Parameter block order: node encoder (3->H->H), edge encoder (2H->H->H),
+ * then per step k: node net k (3H->H->H), edge net k (3H->H->H), then the
+ * classifier Block(H->H) and Linear(H->1).
+ * qscale (NULL unless qmode): 4 scales per MLP2 in the same order, the edge
+ * storage scale per step (S entries, qmode 2 stores edge encodings as
+ * FP8 with that scale; qmode 1 stores them as BF16), then 4 classifier scales.
+ * Edge features are the stored/quantised residual stream in qmode > 0:
+ * e <- q(e + f(...)) after every update, q(e0) after the encoder. */
+void oracle_gnn(int64_t n, const double* cart, int64_t E, const int32_t* src, const int32_t* dst,
+                int H, int S, const double* params, double* logit, int qmode, const double* qscale) {
+  double* h = (double*)calloc((size_t)n * H + 1, sizeof(double));
+  double* e = (double*)calloc((size_t)E * H + 1, sizeof(double));
+  double* mo = (double*)calloc((size_t)n * H + 1, sizeof(double));
+  double* mi = (double*)calloc((size_t)n * H + 1, sizeof(double));
+  double* in = (double*)malloc(sizeof(double) * 3 * H);
+  double* tmp = (double*)malloc(sizeof(double) * H);
+  double* out = (double*)malloc(sizeof(double) * H);
+  const double* p = params;
+  const double* qs = qscale;
+  const double* qstore = qscale ? qscale + 4 * (2 + 2 * S) : NULL;
+
+  /* node encoder: h0 = MLP(x/R, y/R, z/Z); its first layer stays unquantised */
+  for (int64_t l = 0; l < n; ++l) {
+    linear(cart + 3 * l, 3, p, p + 3 * H, H, tmp, 0, 1.0, 1.0);
+    layernorm_relu(tmp, H);
+    const double* p2 = p + 3 * H + H;
+    linear(tmp, H, p2, p2 + (int64_t)H * H, H, h + l * H, qmode, qs ? qs[2] : 1.0, qs ? qs[3] : 1.0);
+    layernorm_relu(h + l * H, H);
+  }
+  p += 3 * H + H + (int64_t)H * H + H;
+  if (qs) qs += 4;
+  /* storage rounding of h (the next GEMM operand) happens inside linear() */
+
+  /* edge encoder: e0_ij = MLP([h_i, h_j]) */
+  for (int64_t t = 0; t < E; ++t) {
+    memcpy(in, h + (int64_t)src[t] * H, sizeof(double) * H);
+    memcpy(in + H, h + (int64_t)dst[t] * H, sizeof(double) * H);
+    mlp2(in, 2 * H, H, p, tmp, e + t * H, qmode, qs);
+    if (qmode) for (int c = 0; c < H; ++c) e[t * H + c] = qv(qmode, e[t * H + c], qstore[0]);
+  }
+  p += (int64_t)2 * H * H + H + (int64_t)H * H + H;
+  if (qs) qs += 4;
+
+  for (int k = 0; k < S; ++k) {
+    /* messages: m_l = [sum_{l->j} e_lj, sum_{i->l} e_il] in edge order */
+    memset(mo, 0, sizeof(double) * n * H);
+    memset(mi, 0, sizeof(double) * n * H);
+    for (int64_t t = 0; t < E; ++t)
+      for (int c = 0; c < H; ++c) {
+        mo[(int64_t)src[t] * H + c] += e[t * H + c];
+        mi[(int64_t)dst[t] * H + c] += e[t * H + c];
+      }
+    /* node update with residual: h <- h + MLP_k([h, mo, mi]) */
+    const double* pn = p;
+    for (int64_t l = 0; l < n; ++l) {
+      memcpy(in, h + l * H, sizeof(double) * H);
+      memcpy(in + H, mo + l * H, sizeof(double) * H);
+      memcpy(in + 2 * H, mi + l * H, sizeof(double) * H);
+      mlp2(in, 3 * H, H, pn, tmp, out, qmode, qs);
+      for (int c = 0; c < H; ++c) h[l * H + c] += out[c];
+    }
+    p += (int64_t)3 * H * H + H + (int64_t)H * H + H;
+    if (qs) qs += 4;
+    /* edge update with residual, using the updated h */
+    const double* pe = p;
+    for (int64_t t = 0; t < E; ++t) {
+      memcpy(in, e + t * H, sizeof(double) * H);
+      memcpy(in + H, h + (int64_t)src[t] * H, sizeof(double) * H);
+      memcpy(in + 2 * H, h + (int64_t)dst[t] * H, sizeof(double) * H);
+      mlp2(in, 3 * H, H, pe, tmp, out, qmode, qs);
+      for (int c = 0; c < H; ++c) {
+        double v = e[t * H + c] + out[c];
+        e[t * H + c] = qmode ? qv(qmode, v, qstore[(k + 1 < S) ? k + 1 : k]) : v;
+      }
+    }
+    p += (int64_t)3 * H * H + H + (int64_t)H * H + H;
+    if (qs) qs += 4;
+  }
+
+  /* classifier: Linear(H->1)(Block(H->H)(e)) */
+  for (int64_t t = 0; t < E; ++t) {
+    linear(e + t * H, H, p, p + (int64_t)H * H, H, tmp, qmode, qs ? qs[0] : 1.0, qs ? qs[1] : 1.0);
+    layernorm_relu(tmp, H);
+    const double* pc = p + (int64_t)H * H + H;
+    double acc = 0.0;
+    for (int c = 0; c < H; ++c) acc += tmp[c] * pc[c];
+    logit[t] = acc + pc[H];
+  }
+  free(h); free(e); free(mo); free(mi); free(in); free(tmp); free(out);
+}
+
+/* ------------------------------------------------------------------------ */
+/* connected components (BFS)                                                */
+/* ------------------------------------------------------------------------ */
+
+/* Undirected graph of the kept edges; label = smallest hit index of the
+ * component (singletons label themselves). */
+void oracle_components(int64_t n, int64_t E, const int32_t* src, const int32_t* dst,
+                       const uint8_t* keep, int32_t* label) {
+  int64_t* deg = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+  for (int64_t t = 0; t < E; ++t)
+    if (keep[t]) { deg[src[t] + 1]++; deg[dst[t] + 1]++; }
+  for (int64_t i = 0; i < n; ++i) deg[i + 1] += deg[i];
+  int32_t* adj = (int32_t*)malloc(sizeof(int32_t) * (deg[n] + 1));
+  int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (n + 1));
+  memcpy(fill, deg, sizeof(int64_t) * (n + 1));
+  for (int64_t t = 0; t < E; ++t)
+    if (keep[t]) { adj[fill[src[t]]++] = dst[t]; adj[fill[dst[t]]++] = src[t]; }
+  int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (n + 1));
+  for (int64_t i = 0; i < n; ++i) label[i] = -1;
+  /* visiting roots in increasing index order makes each root its component's minimum */
+  for (int64_t r = 0; r < n; ++r) {
+    if (label[r] >= 0) continue;
+    int64_t qh = 0, qt = 0;
+    queue[qt++] = (int32_t)r;
+    label[r] = (int32_t)r;
+    while (qh < qt) {
+      int32_t u = queue[qh++];
+      for (int64_t a = deg[u]; a < deg[u + 1]; ++a) {
+        int32_t v = adj[a];
+        if (label[v] < 0) { label[v] = (int32_t)r; queue[qt++] = v; }
+      }
+    }
+  }
+  free(deg); free(adj); free(fill); free(queue);
+}
+
+/* ------------------------------------------------------------------------ */
+/* prefilter features and MLP (forward, loss, backward) for the learned part */
+/* ------------------------------------------------------------------------ */
+
+/* f = (dx, dy, dz, dr, dphi, d_emb) of candidate edge i -> j, normalised by
+ * (R_s, R_s, Z_s, R_s, pi, 1); dphi wrapped to (-pi, pi]. */
+void oracle_prefilter_features(int64_t E, const int32_t* src, const int32_t* dst,
+                               const float* x, const float* y, const float* z,
+                               const double* emb, int D, double r_scale, double z_scale, double* f) {
+  for (int64_t t = 0; t < E; ++t) {
+    int32_t i = src[t], j = dst[t];
+    double xi = x[i], yi = y[i], zi = z[i], xj = x[j], yj = y[j], zj = z[j];
+    double dphi = atan2(yj, xj) - atan2(yi, xi);
+    while (dphi > M_PI) dphi -= 2.0 * M_PI;
+    while (dphi <= -M_PI) dphi += 2.0 * M_PI;
+    double d2 = 0.0;
+    for (int k = 0; k < D; ++k) {
+      double u = emb[(int64_t)j * D + k] - emb[(int64_t)i * D + k];
+      d2 += u * u;
+    }
+    f[6 * t + 0] = (xj - xi) / r_scale;
+    f[6 * t + 1] = (yj - yi) / r_scale;
+    f[6 * t + 2] = (zj - zi) / z_scale;
+    f[6 * t + 3] = (hypot(xj, yj) - hypot(xi, yi)) / r_scale;
+    f[6 * t + 4] = dphi / M_PI;
+    f[6 * t + 5] = sqrt(d2);
+  }
+}
+
+/* Prefilter MLP 6 -> P -> P -> 1 with ReLU; params W1 b1 W2 b2 W3 b3.
+ * Forward logits for E edges. With qmode 1 the GEMM operands (inputs,
+ * hidden activations, weights) are rounded to BF16. */
+void oracle_prefilter_forward(int64_t E, const double* f, int P, const double* params,
+                              double* logit, int qmode) {
+  const double* W1 = params;
+  const double* b1 = W1 + 6 * P;
+  const double* W2 = b1 + P;
+  const double* b2 = W2 + P * P;
+  const double* W3 = b2 + P;
+  const double* b3 = W3 + P;
+  double* a1 = (double*)malloc(sizeof(double) * P);
+  double* a2 = (double*)malloc(sizeof(double) * P);
+  for (int64_t t = 0; t < E; ++t) {
+    linear(f + 6 * t, 6, W1, b1, P, a1, qmode, 1.0, 1.0);
+    for (int c = 0; c < P; ++c) a1[c] = a1[c] > 0 ? a1[c] : 0;
+    linear(a1, P, W2, b2, P, a2, qmode, 1.0, 1.0);
+    for (int c = 0; c < P; ++c) a2[c] = a2[c] > 0 ? a2[c] : 0;
+    double o;
+    linear(a2, P, W3, b3, 1, &o, qmode, 1.0, 1.0);
+    logit[t] = o;
+  }
+  free(a1); free(a2);
+}
+
+/* Mean class-weighted binary cross-entropy over E edges and its gradient
+ * with respect to every parameter (reverse-mode chain rule, thesis ch. 4
+ * "Backpropagation"), written out layer by layer.
+ * loss = (1/E) sum_t w_t * [softplus(-z) if y=1 else softplus(z)], w_t = pos_w for y=1.
+ * grad has the layout of params.  Returns the loss. */
+double oracle_prefilter_loss_grad(int64_t E, const double* f, const uint8_t* label, int P,
+                                  const double* params, double pos_w, double* grad, int qmode) {
+  const double* W1 = params;
+  const double* b1 = W1 + 6 * P;
+  const double* W2 = b1 + P;
+  const double* b2 = W2 + P * P;
+  const double* W3 = b2 + P;
+  const double* b3 = W3 + P;
+  int64_t np = 6 * P + P + P * P + P + P + 1;
+  double* gW1 = grad;
+  double* gb1 = gW1 + 6 * P;
+  double* gW2 = gb1 + P;
+  double* gb2 = gW2 + P * P;
+  double* gW3 = gb2 + P;
+  double* gb3 = gW3 + P;
+  memset(grad, 0, sizeof(double) * np);
+  double* a1 = (double*)malloc(sizeof(double) * P);
+  double* a2 = (double*)malloc(sizeof(double) * P);
+  double* d1 = (double*)malloc(sizeof(double) * P);
+  double* d2 = (double*)malloc(sizeof(double) * P);
+  double loss = 0.0;
+  for (int64_t t = 0; t < E; ++t) {
+    const double* in = f + 6 * t;
+    linear(in, 6, W1, b1, P, a1, qmode, 1.0, 1.0);
+    for (int c = 0; c < P; ++c) a1[c] = a1[c] > 0 ? a1[c] : 0;
+    linear(a1, P, W2, b2, P, a2, qmode, 1.0, 1.0);
+    for (int c = 0; c < P; ++c) a2[c] = a2[c] > 0 ? a2[c] : 0;
+    double z;
+    linear(a2, P, W3, b3, 1, &z, qmode, 1.0, 1.0);
+    double y = label[t] ? 1.0 : 0.0;
+    double w = label[t] ? pos_w : 1.0;
+    /* softplus(v) = log(1 + exp(v)), evaluated stably */
+    double v = y > 0.5 ? -z : z;
+    double sp = v > 0 ? v + log1p(exp(-v)) : log1p(exp(v));
+    loss += w * sp;
+    double sig = 1.0 / (1.0 + exp(-z));
+    double dz = w * (sig - y) / (double)E;
+    /* output layer */
+    for (int c = 0; c < P; ++c) gW3[c] += qv(qmode, a2[c], 1.0) * dz;
+    gb3[0] += dz;
+    for (int c = 0; c < P; ++c) d2[c] = (a2[c] > 0 ? 1.0 : 0.0) * qv(qmode, W3[c], 1.0) * dz;
+    /* hidden layer 2 */
+    for (int k = 0; k < P; ++k)
+      for (int c = 0; c < P; ++c) gW2[k * P + c] += qv(qmode, a1[k], 1.0) * d2[c];
+    for (int c = 0; c < P; ++c) gb2[c] += d2[c];
+    for (int k = 0; k < P; ++k) {
+      double s = 0.0;
+      for (int c = 0; c < P; ++c) s += qv(qmode, W2[k * P + c], 1.0) * d2[c];
+      d1[k] = (a1[k] > 0 ? 1.0 : 0.0) * s;
+    }
+    /* hidden layer 1 */
+    for (int k = 0; k < 6; ++k)
+      for (int c = 0; c < P; ++c) gW1[k * P + c] += qv(qmode, in[k], 1.0) * d1[c];
+    for (int c = 0; c < P; ++c) gb1[c] += d1[c];
+  }
+  free(a1); free(a2); free(d1); free(d2);
+  return E > 0 ? loss / (double)E : 0.0;
+}
+
+/* One Adam step (Kingma & Ba, cited in thesis ch. 4 "Gradient Descent"):
+ * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2; mhat = m/(1-b1^t); vhat = v/(1-b2^t);
+ * p -= lr mhat / (sqrt(vhat) + eps).  t is the 1-based step number. */
+void oracle_adam(int64_t np, double* p, double* m, double* v, const double* g,
+                 double lr, double b1, double b2, double eps, int64_t t) {
+  double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
+  for (int64_t i = 0; i < np; ++i) {
+    m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+    v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+    double mh = m[i] / c1, vh = v[i] / c2;
+    p[i] -= lr * mh / (sqrt(vh) + eps);
+  }
+}

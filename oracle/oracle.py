@@ -1,0 +1,257 @@
+"""Python driver of the FP64 CPU oracle (``etx_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the test-suite, the smoke check and the
+benchmark's CPU-baseline leg, never by the library.  It marshals numpy arrays
+into the C oracle and strings its steps together per event, exactly in the
+order of the thesis's pipeline (ch. 8 "The ETX4VELO Pipeline" without the
+triplet stage, as run on GPU in ch. 9):
+
+    features -> embedding MLP -> radius graph (k_max cap) -> interaction
+    network -> sigmoid score -> score cut (s >= threshold) -> components.
+
+Events are independent, so ``run_batch`` spreads them over a thread pool
+(ctypes releases the GIL during each C call).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "etx_oracle.c")
+_LIB = os.path.join(_HERE, "_build", "liboracle.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with plain gcc -O2 (no BLAS, no SIMD intrinsics)."""
+    os.makedirs(os.path.dirname(_LIB), exist_ok=True)
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared",
+                               _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = C.CDLL(_LIB)
+        P = C.c_void_p
+        i64, i32, dbl = C.c_int64, C.c_int, C.c_double
+        L.oracle_features.argtypes = [i64, P, P, P, dbl, dbl, P, P]
+        L.oracle_embed.argtypes = [i64, P, i32, P, P, P, i32, P]
+        L.oracle_radius.argtypes = [i64, P, P, i32, dbl, i32, i32, P, P, i64]
+        L.oracle_radius.restype = i64
+        L.oracle_radius_margins.argtypes = [i64, P, P, i32, dbl, i32, i32, P, P]
+        L.oracle_gnn.argtypes = [i64, P, i64, P, P, i32, i32, P, P, i32, P]
+        L.oracle_components.argtypes = [i64, i64, P, P, P, P]
+        L.oracle_round_bf16.argtypes = [dbl]
+        L.oracle_round_bf16.restype = dbl
+        L.oracle_round_e4m3.argtypes = [dbl]
+        L.oracle_round_e4m3.restype = dbl
+        L.oracle_prefilter_features.argtypes = [i64, P, P, P, P, P, P, i32, dbl, dbl, P]
+        L.oracle_prefilter_forward.argtypes = [i64, P, i32, P, P, i32]
+        L.oracle_prefilter_loss_grad.argtypes = [i64, P, P, i32, P, dbl, P, i32]
+        L.oracle_prefilter_loss_grad.restype = dbl
+        L.oracle_adam.argtypes = [i64, P, P, P, P, dbl, dbl, dbl, dbl, i64]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+# ---------------------------------------------------------------------------
+# single steps
+# ---------------------------------------------------------------------------
+
+def features(x, y, z, r_scale: float, z_scale: float) -> Tuple[np.ndarray, np.ndarray]:
+    x, y, z = _c(x, np.float32), _c(y, np.float32), _c(z, np.float32)
+    n = len(x)
+    cyl = np.zeros((n, 3)); cart = np.zeros((n, 3))
+    lib().oracle_features(n, _p(x), _p(y), _p(z), float(r_scale), float(z_scale), _p(cyl), _p(cart))
+    return cyl, cart
+
+
+def _flat(layers) -> np.ndarray:
+    parts = []
+    for W, b in layers:
+        parts.append(np.asarray(W, np.float64).ravel())
+        parts.append(np.asarray(b, np.float64).ravel())
+    return np.concatenate(parts) if parts else np.zeros(0)
+
+
+def embed(cyl: np.ndarray, layers, qmode: int = 0, qscale=None) -> np.ndarray:
+    cyl = _c(cyl, np.float64)
+    dims = np.array([layers[0][0].shape[0]] + [W.shape[1] for W, _ in layers], dtype=np.int32)
+    n = len(cyl)
+    out = np.zeros((n, int(dims[-1])))
+    params = _flat(layers)
+    qs = None if qscale is None else _c(qscale, np.float64)
+    lib().oracle_embed(n, _p(cyl), len(layers), _p(dims), _p(params), _p(out), qmode,
+                       _p(qs) if qs is not None else None)
+    return out
+
+
+def radius_graph(plane, emb, radius: float, k_max: int, window: int) -> Tuple[np.ndarray, np.ndarray]:
+    plane = _c(plane, np.int32)
+    emb = _c(emb, np.float64)
+    n, D = emb.shape if emb.ndim == 2 else (0, 1)
+    cap = max(1, n * k_max)
+    src = np.zeros(cap, np.int32); dst = np.zeros(cap, np.int32)
+    E = lib().oracle_radius(n, _p(plane), _p(emb), D, float(radius), k_max, window, _p(src), _p(dst), cap)
+    assert E <= cap
+    return src[:E].copy(), dst[:E].copy()
+
+
+def radius_margins(plane, emb, radius: float, k_max: int, window: int) -> Tuple[np.ndarray, np.ndarray]:
+    plane = _c(plane, np.int32)
+    emb = _c(emb, np.float64)
+    n, D = emb.shape
+    rm = np.zeros(n); kg = np.zeros(n)
+    lib().oracle_radius_margins(n, _p(plane), _p(emb), D, float(radius), k_max, window, _p(rm), _p(kg))
+    return rm, kg
+
+
+def gnn_param_blocks(weights) -> list:
+    """The interaction-network layers in the oracle's parameter order."""
+    S = sum(1 for k in weights if k.startswith("node") and k[4:].isdigit())
+    blocks = list(weights["node_enc"]) + list(weights["edge_enc"])
+    for k in range(S):
+        blocks += list(weights[f"node{k}"]) + list(weights[f"edge{k}"])
+    blocks += list(weights["cls"])
+    return blocks
+
+
+def gnn(cart, src, dst, weights, H: int, S: int, qmode: int = 0, qscale=None) -> np.ndarray:
+    cart = _c(cart, np.float64)
+    src = _c(src, np.int32); dst = _c(dst, np.int32)
+    params = _flat(gnn_param_blocks(weights))
+    E = len(src)
+    logit = np.zeros(max(E, 1))
+    qs = None if qscale is None else _c(qscale, np.float64)
+    lib().oracle_gnn(len(cart), _p(cart), E, _p(src), _p(dst), H, S, _p(params), _p(logit), qmode,
+                     _p(qs) if qs is not None else None)
+    return logit[:E].copy()
+
+
+def components(n: int, src, dst, keep) -> np.ndarray:
+    src = _c(src, np.int32); dst = _c(dst, np.int32)
+    keep = _c(keep, np.uint8)
+    lab = np.zeros(max(n, 1), np.int32)
+    lib().oracle_components(n, len(src), _p(src), _p(dst), _p(keep), _p(lab))
+    return lab[:n].copy()
+
+
+def sigmoid(z: np.ndarray) -> np.ndarray:
+    return 1.0 / (1.0 + np.exp(-z))
+
+
+def round_bf16(x: float) -> float:
+    return lib().oracle_round_bf16(float(x))
+
+
+def round_e4m3(x: float) -> float:
+    return lib().oracle_round_e4m3(float(x))
+
+
+# ---------------------------------------------------------------------------
+# whole pipeline
+# ---------------------------------------------------------------------------
+
+def run_event(ev: Dict[str, np.ndarray], w, weights, with_margins: bool = False) -> Dict[str, np.ndarray]:
+    """The full hot path on one event.  ``w`` carries the workload constants
+    (r_scale, z_scale, radius, k_max, plane_window, gnn_hidden, gnn_steps,
+    threshold); ``weights`` the network parameters."""
+    cyl, cart = features(ev["x"], ev["y"], ev["z"], w.r_scale, w.z_scale)
+    emb = embed(cyl, weights["emb"])
+    r32 = float(np.float32(w.radius))
+    src, dst = radius_graph(ev["plane"], emb, r32, w.k_max, w.plane_window)
+    logit = gnn(cart, src, dst, weights, w.gnn_hidden, w.gnn_steps)
+    score = sigmoid(logit)
+    keep = score >= w.threshold
+    labels = components(len(cyl), src, dst, keep)
+    out = dict(emb=emb, src=src, dst=dst, logit=logit, score=score, keep=keep, labels=labels)
+    if with_margins:
+        rm, kg = radius_margins(ev["plane"], emb, r32, w.k_max, w.plane_window)
+        out["r_margin"], out["k_gap"] = rm, kg
+    return out
+
+
+def run_batch(batch: Dict[str, np.ndarray], w, weights, events: Optional[Sequence[int]] = None,
+              threads: Optional[int] = None, with_margins: bool = False) -> List[Dict[str, np.ndarray]]:
+    hit_off = batch["hit_off"]
+    idx = list(range(len(hit_off) - 1)) if events is None else list(events)
+
+    def one(i):
+        a, b = int(hit_off[i]), int(hit_off[i + 1])
+        ev = {k: batch[k][a:b] for k in ("x", "y", "z", "plane")}
+        return run_event(ev, w, weights, with_margins)
+
+    nt = threads or os.cpu_count() or 1
+    if nt <= 1 or len(idx) <= 1:
+        return [one(i) for i in idx]
+    with ThreadPoolExecutor(max_workers=nt) as ex:
+        return list(ex.map(one, idx))
+
+
+# ---------------------------------------------------------------------------
+# learned prefilter (forward / loss / gradient / Adam)
+# ---------------------------------------------------------------------------
+
+def prefilter_features(src, dst, x, y, z, emb, r_scale, z_scale) -> np.ndarray:
+    src = _c(src, np.int32); dst = _c(dst, np.int32)
+    x, y, z = _c(x, np.float32), _c(y, np.float32), _c(z, np.float32)
+    emb = _c(emb, np.float64)
+    E = len(src)
+    f = np.zeros((max(E, 1), 6))
+    lib().oracle_prefilter_features(E, _p(src), _p(dst), _p(x), _p(y), _p(z), _p(emb),
+                                    emb.shape[1], float(r_scale), float(z_scale), _p(f))
+    return f[:E].copy()
+
+
+def prefilter_forward(f, layers, qmode: int = 0) -> np.ndarray:
+    f = _c(f, np.float64)
+    P = layers[0][0].shape[1]
+    params = _flat(layers)
+    out = np.zeros(max(len(f), 1))
+    lib().oracle_prefilter_forward(len(f), _p(f), P, _p(params), _p(out), qmode)
+    return out[:len(f)].copy()
+
+
+def prefilter_loss_grad(f, labels, layers, pos_weight: float, qmode: int = 0) -> Tuple[float, np.ndarray]:
+    f = _c(f, np.float64)
+    lab = _c(labels, np.uint8)
+    P = layers[0][0].shape[1]
+    params = _flat(layers)
+    g = np.zeros_like(params)
+    loss = lib().oracle_prefilter_loss_grad(len(f), _p(f), _p(lab), P, _p(params), float(pos_weight), _p(g), qmode)
+    return loss, g
+
+
+def adam(p, m, v, g, lr, b1=0.9, b2=0.999, eps=1e-8, t=1):
+    for a in (p, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = _c(g, np.float64)
+    lib().oracle_adam(len(p), _p(p), _p(m), _p(v), _p(g), float(lr), float(b1), float(b2), float(eps), int(t))
+
+
+if __name__ == "__main__":
+    print(build())
+    sys.exit(0)
