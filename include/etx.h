@@ -1,0 +1,193 @@
+/*
+ * etx.h -- C ABI of the MI355X GNN track-finding hot path.
+ *
+ * The problem (thesis ch. 7 "Track reconstruction" and ch. 8 "The ETX4VELO
+ * Pipeline"): the input is the point cloud of each event's detector hits, the
+ * output is a grouping of the hits into tracks, together with the edge scores
+ * behind it.  One call runs, for a packed batch of independent events:
+ *
+ *   embedding MLP on normalised (r, phi, z)           ch. 8 "Hit Embedding ..."
+ *   fixed-radius graph: hit on plane p -> hits on planes p+1..p+window with
+ *     squared embedding distance below radius^2, at most k_max per source
+ *     (the k_max nearest, ties broken by the smaller hit index)
+ *                                                     ch. 8 (d^2 equation), ch. 9 "k-NN Implementation"
+ *   interaction network: node and edge encoders, `gnn_steps` message-passing
+ *     steps with concatenated out/in sums and residual node then edge updates,
+ *     edge classifier with a sigmoid score           ch. 8 "Graph Neural Network and Classifiers"
+ *   score cut: an edge is kept when score >= edge_threshold
+ *   connected components of the kept graph; the label of a hit is the
+ *     smallest global hit index in its component     ch. 9 "WCC Implementation"
+ *
+ * Conventions
+ *  - Every entry point returns an etx_status; nothing throws across the ABI.
+ *  - "device" pointers are HIP device memory on the context's device; the
+ *    caller owns every input, output and workspace buffer.  The context owns
+ *    its device copy of the weights, scales and cached HIP graphs.
+ *  - etx_stream is a hipStream_t (NULL = the default stream).  Calls that take
+ *    a stream are asynchronous: they only enqueue work and never synchronise.
+ *    Errors found on the device (bad input, edge capacity) are written to
+ *    out->status, which the caller reads after synchronising the stream.
+ *  - Hit indices are global indices into the packed batch (int32); offsets
+ *    are int64.  Hits may come in any order within an event.
+ */
+#ifndef ETX_H
+#define ETX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ETX_OK = 0,
+  ETX_ERR_INVALID_ARG = 1,   /* bad pointer, size or configuration value */
+  ETX_ERR_CAPACITY = 2,      /* device: more edges than out->edge_capacity; status[1] = edges needed */
+  ETX_ERR_INPUT = 3,         /* device: NaN/inf coordinate, plane outside [0, n_planes), bad hit_off */
+  ETX_ERR_WEIGHTS = 4,       /* weight blob does not match the configuration */
+  ETX_ERR_UNSUPPORTED = 5,   /* a size this build does not handle (e.g. an event above ETX_MAX_EVENT_HITS) */
+  ETX_ERR_HIP = 6            /* a HIP runtime call failed */
+} etx_status;
+
+typedef enum { ETX_FP32 = 0, ETX_BF16 = 1, ETX_FP8_E4M3 = 2 } etx_precision;
+
+/* Largest event (hits) the per-event kernels accept. */
+#define ETX_MAX_EVENT_HITS 16384
+/* Largest number of planes. */
+#define ETX_MAX_PLANES 64
+
+typedef void* etx_stream; /* hipStream_t */
+
+typedef struct {
+  int32_t n_planes;          /* planes are numbered 0..n_planes-1 along the beam */
+  float r_scale_mm;          /* R_s: r, x, y are divided by it */
+  float z_scale_mm;          /* Z_s: z is divided by it */
+  int32_t emb_hidden;        /* embedding hidden width: 32, 64 or 128 */
+  int32_t emb_layers;        /* hidden layers of the embedding MLP: 1..4 */
+  int32_t emb_dim;           /* embedding dimension: 1..16 */
+  float radius;              /* edge if squared distance < radius^2 */
+  int32_t k_max;             /* 1..64 neighbours per source hit */
+  int32_t plane_window;      /* 1..4: targets on planes p+1..p+plane_window */
+  int32_t gnn_hidden;        /* node and edge encoding width: 32 or 64 */
+  int32_t gnn_steps;         /* message-passing steps: 1..16 */
+  float edge_threshold;      /* keep edge when score >= threshold (0.5) */
+  int32_t precision;         /* etx_precision of the MLP GEMM operands */
+  int32_t prefilter;         /* 1: prune candidate edges with the learned prefilter before the GNN */
+  float prefilter_tau;       /* prune when prefilter probability < tau */
+} etx_config;
+
+typedef struct etx_ctx etx_ctx;
+
+typedef struct {             /* device pointers, caller-owned, read-only */
+  int64_t n_events;
+  int64_t n_hits;            /* == hit_off[n_events] (host copy of the total) */
+  const int64_t* hit_off;    /* [n_events+1] event e owns hits hit_off[e] .. hit_off[e+1]-1 */
+  const float* x;            /* [n_hits] mm */
+  const float* y;            /* [n_hits] mm */
+  const float* z;            /* [n_hits] mm */
+  const int32_t* plane;      /* [n_hits] plane index */
+} etx_hits;
+
+typedef struct {             /* device pointers, caller-owned, written by etx_run */
+  int64_t edge_capacity;     /* length of src, dst, score */
+  int32_t* src;              /* [edge_capacity] global hit index; sorted by (src, dst) within each event */
+  int32_t* dst;              /* [edge_capacity] global hit index on a later plane */
+  float* score;              /* [edge_capacity] classifier score in (0, 1) */
+  int64_t* edge_off;         /* [n_events+1] event e owns edges edge_off[e] .. edge_off[e+1]-1 */
+  int32_t* labels;           /* [n_hits] smallest global hit index of the hit's component */
+  int64_t* status;           /* [2] status[0] = etx_status of the device work, status[1] = edges needed */
+} etx_out;
+
+/* Create a context on `device`.  `weights` is a host blob (see etx_weight_blob_size):
+ * int32 header {0x57585445, 1, 3, emb_hidden, emb_layers, emb_dim, gnn_hidden, gnn_steps}
+ * followed by float32 Linear layers (W row-major [fan_in][fan_out], then b) in the
+ * order: embedding layers; node encoder (3->H, H->H); edge encoder (2H->H, H->H);
+ * per step k: node net k (3H->H, H->H) then edge net k (3H->H, H->H); classifier
+ * (H->H, H->1).  Node-net input is [h, out-sum, in-sum]; edge-net input is
+ * [e, h_src, h_dst]; edge-encoder input is [h_src, h_dst].  The blob is copied. */
+etx_status etx_create(const etx_config* cfg, const void* weights, size_t nbytes, int device, etx_ctx** out);
+etx_status etx_destroy(etx_ctx* ctx);
+
+/* Bytes a weight blob for `cfg` must have. */
+etx_status etx_weight_blob_size(const etx_config* cfg, size_t* nbytes);
+
+/* Workspace bytes etx_run needs for a batch of this size. */
+etx_status etx_workspace_size(const etx_ctx* ctx, int64_t n_events, int64_t n_hits, int64_t edge_capacity,
+                              size_t* bytes);
+
+/* Run the whole hot path on one batch (see the top of this file).  `ws` is
+ * device memory of at least etx_workspace_size bytes, 256-byte aligned. */
+etx_status etx_run(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void* ws, size_t ws_bytes, etx_stream stream);
+
+/* Internal buffers of the workspace, for inspection after etx_run. */
+typedef enum {
+  ETX_VIEW_EMBEDDING = 0,    /* float [n_hits][16]: embedding, zero-padded to 16 */
+  ETX_VIEW_BUCKET = 1,       /* int32 [n_hits]: hits of each event ordered by plane (global indices) */
+  ETX_VIEW_PLANE_OFF = 2,    /* int32 [n_events][n_planes+1]: per-event plane offsets into the bucket */
+  ETX_VIEW_ROW_PTR = 3,      /* int64 [n_hits+1]: CSR by source hit (global edge positions) */
+  ETX_VIEW_COL_PTR = 4,      /* int64 [n_hits+1]: CSC by target hit */
+  ETX_VIEW_CSC_EDGE = 5,     /* int32 [edge_capacity]: edge ids sorted by (dst, src) */
+  ETX_VIEW_NODE_H = 6,       /* float [n_hits][H]: node encodings after the last step */
+  ETX_VIEW_KEPT_EDGE = 7,    /* int32 [edge_capacity]: kept edge ids, per event from edge_off[e] */
+  ETX_VIEW_KEPT_COUNT = 8,   /* int32 [n_events]: kept edges per event */
+  ETX_VIEW_CALIB = 9,        /* float [ETX_N_CALIB]: per-tensor amax (calibration observers) */
+  ETX_VIEW_PF_KEEP = 10      /* uint8 [edge_capacity]: prefilter decision per candidate edge */
+} etx_view;
+#define ETX_N_CALIB 64
+etx_status etx_workspace_view(const etx_ctx* ctx, int64_t n_events, int64_t n_hits, int64_t edge_capacity,
+                              int32_t which, size_t* offset, size_t* bytes);
+
+/* Tuning knobs (also set by etx_autotune). */
+typedef enum {
+  ETX_OPT_USE_GRAPH = 0,     /* 1: etx_run captures the batch into a HIP graph and replays it */
+  ETX_OPT_EDGE_WG_PER_CU = 1,/* persistent workgroups per CU of the edge kernels (1..8) */
+  ETX_OPT_NODE_WG_PER_CU = 2,/* persistent workgroups per CU of the node kernels (1..8) */
+  ETX_OPT_RADIUS_LDS = 3,    /* largest candidate window staged in LDS (0..512); larger windows read HBM */
+  ETX_OPT_SEGSUM_UNROLL = 4  /* edge rows in flight per wave in the segmented sums: 1, 2, 4 or 8 */
+} etx_option;
+etx_status etx_set_option(etx_ctx* ctx, int32_t key, int64_t value);
+etx_status etx_get_option(const etx_ctx* ctx, int32_t key, int64_t* value);
+
+/* Try each candidate launch schedule on this batch, keep the fastest, and
+ * append the choice to `json_path` (may be NULL).  Synchronises the stream. */
+etx_status etx_autotune(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void* ws, size_t ws_bytes,
+                        etx_stream stream, const char* json_path);
+
+/* Static calibration for the low-precision modes (thesis ch. 4 "Quantization",
+ * static post-training quantisation): runs the FP32 path on `hits`, records
+ * the per-tensor absolute maximum of every quantised activation, and sets the
+ * per-tensor scales S = amax / 448 (FP8-E4M3).  Synchronises the stream. */
+etx_status etx_calibrate(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void* ws, size_t ws_bytes,
+                         etx_stream stream);
+/* Switch the GEMM operand precision (etx_precision) of an existing context. */
+etx_status etx_set_precision(etx_ctx* ctx, int32_t precision);
+
+/* Learned edge prefilter: MLP 6 -> 32 -> 32 -> 1 (ReLU) on the candidate-edge
+ * features (dx, dy, dz, dr, dphi, embedding distance), normalised by
+ * (R_s, R_s, Z_s, R_s, pi, 1), dphi wrapped to (-pi, pi].  Parameters are
+ * float32 W1[6][32] b1[32] W2[32][32] b2[32] W3[32][1] b3[1] (1281 floats). */
+#define ETX_PF_HIDDEN 32
+#define ETX_PF_NPARAM (6 * 32 + 32 + 32 * 32 + 32 + 32 + 1)
+etx_status etx_prefilter_set(etx_ctx* ctx, const float* params, int64_t n);            /* host params */
+etx_status etx_prefilter_get(const etx_ctx* ctx, float* params, int64_t n);            /* host params */
+/* One training step on the candidate edges of `hits` (the radius graph is built
+ * first): BF16 forward/backward kernels, mean class-weighted BCE loss with
+ * positive weight `pos_weight`, FP32 Adam (beta1 0.9, beta2 0.999, eps 1e-8)
+ * with learning rate `lr`, step number `step` (1-based).  edge_labels[e] is 1
+ * when candidate edge e (in the radius-graph order of out->src/out->dst) is kept
+ * by the full pipeline.  *loss_dev (device float) receives the loss. */
+etx_status etx_prefilter_train_step(etx_ctx* ctx, const etx_hits* hits, etx_out* out, const uint8_t* edge_labels,
+                                    float lr, float pos_weight, int64_t step, float* loss_dev, void* ws,
+                                    size_t ws_bytes, etx_stream stream);
+/* Optimiser state for checkpointing: params, Adam m, Adam v (3 * ETX_PF_NPARAM floats). */
+etx_status etx_prefilter_state(etx_ctx* ctx, float* host_state, int64_t n, int32_t set);
+
+const char* etx_status_str(etx_status s);
+/* Text of the last HIP failure seen by this thread ("" if none). */
+const char* etx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ETX_H */

@@ -1,0 +1,519 @@
+// Host side of the C ABI: configuration checks, weight segments, workspace
+// layout, the stage sequence of etx_run, HIP-graph capture and replay.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "seg.hpp"
+#include "tile.hpp"
+
+namespace etx {
+
+int embed_attributes(size_t max_lds);
+int gnn_attributes(size_t max_lds);
+int graph_attributes(size_t max_lds);
+int prefilter_attributes(size_t max_lds);
+hipError_t build_low_precision(etx_ctx* ctx);
+
+bool GraphKey::operator<(const GraphKey& o) const {
+  for (int i = 0; i < 16; ++i)
+    if (p[i] != o.p[i]) return p[i] < o.p[i];
+  for (int i = 0; i < 4; ++i)
+    if (n[i] != o.n[i]) return n[i] < o.n[i];
+  return false;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+WsLayout ws_layout(const etx_ctx* ctx, int64_t n_events, int64_t n_hits, int64_t edge_cap) {
+  const etx_config& c = ctx->cfg;
+  const int64_t H = c.gnn_hidden;
+  WsLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align256(std::max<size_t>(bytes, 1));
+    return at;
+  };
+  L.n_scan_blocks = (n_hits + kScanBlock - 1) / kScanBlock;
+  L.bucket = take(sizeof(int32_t) * n_hits);
+  L.plane_off = take(sizeof(int32_t) * n_events * (c.n_planes + 1));
+  L.emb = take(sizeof(float) * n_hits * kDpad);
+  L.cnt = take(sizeof(int32_t) * n_hits);
+  L.row_ptr = take(sizeof(int64_t) * (n_hits + 1));
+  L.scan_tmp = take(sizeof(int64_t) * (L.n_scan_blocks + 1));
+  L.col_ptr = take(sizeof(int64_t) * (n_hits + 1));
+  L.csc = take(sizeof(int32_t) * edge_cap);
+  L.h = take(sizeof(float) * n_hits * H);
+  L.ps = take(sizeof(float) * n_hits * H);
+  L.pd = take(sizeof(float) * n_hits * H);
+  L.msg = take(sizeof(float) * n_hits * 2 * H);
+  L.e = take(sizeof(float) * edge_cap * H);
+  L.kept = take(sizeof(int32_t) * edge_cap);
+  L.kept_cnt = take(sizeof(int32_t) * n_events);
+  L.calib = take(sizeof(float) * ETX_N_CALIB);
+  L.pf_keep = take(sizeof(uint8_t) * edge_cap);
+  L.pf_tmp = take(sizeof(int64_t) * (n_hits + 1));
+  L.pf_grad = take(sizeof(float) * 4 * ETX_PF_NPARAM + 64);
+  L.total = o;
+  return L;
+}
+
+// Permute a row-major [K][M] weight for the column layout (tile.hpp); M padded to Mpad.
+static void perm_f32(const float* W, int K, int M, int Mpad, float* out) {
+  for (int mb = 0; mb < Mpad / 32; ++mb)
+    for (int t = 0; t < K / 2; ++t)
+      for (int lane = 0; lane < 64; ++lane) {
+        int row = phi(t, lane / 32), col = 32 * mb + lane % 32;
+        out[((size_t)mb * (K / 2) + t) * 64 + lane] = col < M ? W[(size_t)row * M + col] : 0.f;
+      }
+}
+
+namespace {
+
+struct BlobLayer {
+  const float* W;
+  const float* b;
+  int K, M;
+};
+
+bool parse_blob(const etx_config& c, const void* blob, size_t nbytes, std::vector<float>& payload,
+                std::vector<BlobLayer>& layers) {
+  if (nbytes < 32) return false;
+  int32_t hd[8];
+  std::memcpy(hd, blob, 32);
+  if (hd[0] != 0x57585445 || hd[1] != 1 || hd[2] != 3 || hd[3] != c.emb_hidden || hd[4] != c.emb_layers ||
+      hd[5] != c.emb_dim || hd[6] != c.gnn_hidden || hd[7] != c.gnn_steps)
+    return false;
+  size_t need = 0;
+  std::vector<std::pair<int, int>> dims;
+  const int W = c.emb_hidden, H = c.gnn_hidden;
+  dims.push_back({3, W});
+  for (int l = 1; l < c.emb_layers; ++l) dims.push_back({W, W});
+  dims.push_back({W, c.emb_dim});
+  dims.push_back({3, H});
+  dims.push_back({H, H});
+  dims.push_back({2 * H, H});
+  dims.push_back({H, H});
+  for (int k = 0; k < c.gnn_steps; ++k) {
+    dims.push_back({3 * H, H});
+    dims.push_back({H, H});
+    dims.push_back({3 * H, H});
+    dims.push_back({H, H});
+  }
+  dims.push_back({H, H});
+  dims.push_back({H, 1});
+  for (auto& d : dims) need += (size_t)d.first * d.second + d.second;
+  if (nbytes != 32 + need * sizeof(float)) return false;
+  payload.resize(need);
+  std::memcpy(payload.data(), static_cast<const char*>(blob) + 32, need * sizeof(float));
+  for (float v : payload)
+    if (!std::isfinite(v)) return false;
+  size_t o = 0;
+  for (auto& d : dims) {
+    BlobLayer L{payload.data() + o, payload.data() + o + (size_t)d.first * d.second, d.first, d.second};
+    o += (size_t)d.first * d.second + d.second;
+    layers.push_back(L);
+  }
+  return true;
+}
+
+size_t blob_floats(const etx_config& c) {
+  const size_t W = c.emb_hidden, H = c.gnn_hidden;
+  size_t n = 3 * W + W + (c.emb_layers - 1) * (W * W + W) + W * c.emb_dim + c.emb_dim;
+  n += 3 * H + H + H * H + H + 2 * H * H + H + H * H + H;
+  n += (size_t)c.gnn_steps * 2 * (3 * H * H + H + H * H + H);
+  n += H * H + H + H + 1;
+  return n;
+}
+
+etx_status check_config(const etx_config* c) {
+  if (!c) return ETX_ERR_INVALID_ARG;
+  if (c->n_planes < 1 || c->n_planes > ETX_MAX_PLANES) return ETX_ERR_INVALID_ARG;
+  if (!(c->r_scale_mm > 0) || !(c->z_scale_mm > 0) || !std::isfinite(c->r_scale_mm) || !std::isfinite(c->z_scale_mm))
+    return ETX_ERR_INVALID_ARG;
+  if (c->emb_hidden != 32 && c->emb_hidden != 64 && c->emb_hidden != 128) return ETX_ERR_UNSUPPORTED;
+  if (c->emb_layers < 1 || c->emb_layers > 4) return ETX_ERR_UNSUPPORTED;
+  if (c->emb_dim < 1 || c->emb_dim > kDpad) return ETX_ERR_UNSUPPORTED;
+  if (!(c->radius >= 0) || !std::isfinite(c->radius)) return ETX_ERR_INVALID_ARG;
+  if (c->k_max < 1 || c->k_max > 64) return ETX_ERR_UNSUPPORTED;
+  if (c->plane_window < 1 || c->plane_window > 4) return ETX_ERR_UNSUPPORTED;
+  if (c->gnn_hidden != 32 && c->gnn_hidden != 64) return ETX_ERR_UNSUPPORTED;
+  if (c->gnn_steps < 1 || c->gnn_steps > 16) return ETX_ERR_UNSUPPORTED;
+  if (!std::isfinite(c->edge_threshold)) return ETX_ERR_INVALID_ARG;
+  if (c->precision < ETX_FP32 || c->precision > ETX_FP8_E4M3) return ETX_ERR_INVALID_ARG;
+  if (c->prefilter != 0 && c->prefilter != 1) return ETX_ERR_INVALID_ARG;
+  if (!std::isfinite(c->prefilter_tau)) return ETX_ERR_INVALID_ARG;
+  return ETX_OK;
+}
+
+void clear_graphs(etx_ctx* ctx) {
+  for (auto& kv : ctx->graphs) hipGraphExecDestroy(kv.second);
+  ctx->graphs.clear();
+}
+
+}  // namespace
+
+// Build the FP32 weight segments on the host and upload them.
+static etx_status build_segments(etx_ctx* ctx, const std::vector<BlobLayer>& Ls) {
+  const etx_config& c = ctx->cfg;
+  const int W = c.emb_hidden, H = c.gnn_hidden, S = c.gnn_steps, LE = c.emb_layers;
+  WeightMap& m = ctx->wmap;
+  std::vector<float> buf;
+  auto reserve = [&](int n) {
+    int64_t at = (int64_t)buf.size();
+    buf.resize(buf.size() + ((n + 3) & ~3), 0.f);
+    return at;
+  };
+  size_t li = 0;
+  // embedding
+  {
+    SegEmb s{W, LE};
+    m.emb = reserve(s.size());
+    float* p = buf.data() + m.emb;
+    const BlobLayer& l1 = Ls[li++];
+    std::memcpy(p + s.w1(), l1.W, sizeof(float) * 3 * W);
+    std::memcpy(p + s.b1(), l1.b, sizeof(float) * W);
+    for (int l = 1; l < LE; ++l) {
+      const BlobLayer& L = Ls[li++];
+      perm_f32(L.W, W, W, W, p + s.wh(l));
+      std::memcpy(p + s.bh(l), L.b, sizeof(float) * W);
+    }
+    const BlobLayer& lo = Ls[li++];
+    perm_f32(lo.W, W, c.emb_dim, 32, p + s.wo());
+    std::memcpy(p + s.bo(), lo.b, sizeof(float) * c.emb_dim);
+  }
+  const BlobLayer ne1 = Ls[li++], ne2 = Ls[li++], ee1 = Ls[li++], ee2 = Ls[li++];
+  std::vector<BlobLayer> nn1(S), nn2(S), en1(S), en2(S);
+  for (int k = 0; k < S; ++k) {
+    nn1[k] = Ls[li++];
+    nn2[k] = Ls[li++];
+    en1[k] = Ls[li++];
+    en2[k] = Ls[li++];
+  }
+  const BlobLayer c1 = Ls[li++], c2 = Ls[li++];
+  {
+    SegNodeEnc s{H};
+    m.node_enc = reserve(s.size());
+    float* p = buf.data() + m.node_enc;
+    std::memcpy(p + s.w1(), ne1.W, sizeof(float) * 3 * H);
+    std::memcpy(p + s.b1(), ne1.b, sizeof(float) * H);
+    perm_f32(ne2.W, H, H, H, p + s.w2());
+    std::memcpy(p + s.b2(), ne2.b, sizeof(float) * H);
+    perm_f32(ee1.W, H, H, H, p + s.ws());                        // rows 0..H-1: h_src
+    perm_f32(ee1.W + (size_t)H * H, H, H, H, p + s.wd());        // rows H..2H-1: h_dst
+  }
+  {
+    SegEdgeEnc s{H};
+    m.edge_enc = reserve(s.size());
+    float* p = buf.data() + m.edge_enc;
+    std::memcpy(p + s.b1(), ee1.b, sizeof(float) * H);
+    perm_f32(ee2.W, H, H, H, p + s.w2());
+    std::memcpy(p + s.b2(), ee2.b, sizeof(float) * H);
+  }
+  for (int k = 0; k < S; ++k) {
+    SegNode s{H};
+    m.node[k] = reserve(s.size());
+    float* p = buf.data() + m.node[k];
+    perm_f32(nn1[k].W, 3 * H, H, H, p + s.w1());
+    std::memcpy(p + s.b1(), nn1[k].b, sizeof(float) * H);
+    perm_f32(nn2[k].W, H, H, H, p + s.w2());
+    std::memcpy(p + s.b2(), nn2[k].b, sizeof(float) * H);
+    perm_f32(en1[k].W + (size_t)H * H, H, H, H, p + s.ws());     // rows H..2H-1: h_src
+    perm_f32(en1[k].W + (size_t)2 * H * H, H, H, H, p + s.wd()); // rows 2H..3H-1: h_dst
+    SegEdge se{H};
+    m.edge[k] = reserve(se.size());
+    float* q = buf.data() + m.edge[k];
+    perm_f32(en1[k].W, H, H, H, q + se.we());                    // rows 0..H-1: e
+    std::memcpy(q + se.b1(), en1[k].b, sizeof(float) * H);
+    perm_f32(en2[k].W, H, H, H, q + se.w2());
+    std::memcpy(q + se.b2(), en2[k].b, sizeof(float) * H);
+  }
+  {
+    SegCls s{H};
+    m.cls = reserve(s.size());
+    float* p = buf.data() + m.cls;
+    perm_f32(c1.W, H, H, H, p + s.w1());
+    std::memcpy(p + s.b1(), c1.b, sizeof(float) * H);
+    std::memcpy(p + s.w2(), c2.W, sizeof(float) * H);
+    p[s.b2()] = c2.b[0];
+  }
+  m.total = (int64_t)buf.size();
+  if (hipMalloc(&ctx->dev_w, sizeof(float) * buf.size()) != hipSuccess) return ETX_ERR_HIP;
+  if (hipMemcpy(ctx->dev_w, buf.data(), sizeof(float) * buf.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return ETX_ERR_HIP;
+  return ETX_OK;
+}
+
+thread_local std::string g_last_error;
+
+void note_error(const char* what, hipError_t e) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+}
+
+int set_kernel_attributes() {
+  static int done = -1;
+  if (done >= 0) return done;
+  // dynamic LDS limit for every kernel that stages weights or candidates; kept
+  // below the 160 KiB per workgroup so that static LDS still fits beside it
+  size_t max_lds = 150 * 1024;
+  done = embed_attributes(max_lds) | gnn_attributes(max_lds) | graph_attributes(max_lds) |
+         prefilter_attributes(max_lds);
+  return done;
+}
+
+// The stage sequence of one batch.
+static hipError_t enqueue_pipeline(const RunArgs& a) {
+  hipError_t err;
+#define STEP(x)                              \
+  do {                                       \
+    if ((err = (x)) != hipSuccess) return err; \
+  } while (0)
+  const etx_config& c = a.ctx->cfg;
+  STEP(launch_init_status(a));
+  STEP(launch_validate(a));
+  STEP(launch_bucket(a));
+  STEP(launch_embed(a));
+  STEP(launch_radius(a, false));
+  STEP(launch_scan_counts(a));
+  STEP(launch_radius(a, true));
+  if (c.prefilter) STEP(launch_prefilter_infer(a));
+  STEP(launch_csc(a));
+  STEP(launch_node_encode(a));
+  STEP(launch_edge_encode(a));
+  for (int k = 0; k < c.gnn_steps; ++k) {
+    STEP(launch_segsum(a));
+    STEP(launch_node_step(a, k));
+    STEP(launch_edge_step(a, k, k + 1 == c.gnn_steps));
+  }
+  STEP(launch_compact(a));
+  STEP(launch_union_find(a));
+#undef STEP
+  return hipSuccess;
+}
+
+static etx_status check_run_args(const etx_ctx* ctx, const etx_hits* hits, const etx_out* out, void* ws,
+                                 size_t ws_bytes, WsLayout* L) {
+  if (!ctx || !hits || !out) return ETX_ERR_INVALID_ARG;
+  if (hits->n_events < 0 || hits->n_hits < 0 || hits->n_hits >= 0x7fffffffLL) return ETX_ERR_INVALID_ARG;
+  if (!hits->hit_off) return ETX_ERR_INVALID_ARG;
+  if (hits->n_hits > 0 && (!hits->x || !hits->y || !hits->z || !hits->plane)) return ETX_ERR_INVALID_ARG;
+  if (out->edge_capacity < 0 || !out->edge_off || !out->status) return ETX_ERR_INVALID_ARG;
+  if (hits->n_hits > 0 && !out->labels) return ETX_ERR_INVALID_ARG;
+  if (out->edge_capacity > 0 && (!out->src || !out->dst || !out->score)) return ETX_ERR_INVALID_ARG;
+  if (out->edge_capacity >= 0x7fffffffLL) return ETX_ERR_UNSUPPORTED;
+  *L = ws_layout(ctx, hits->n_events, hits->n_hits, out->edge_capacity);
+  if (!ws || ws_bytes < L->total || (reinterpret_cast<uintptr_t>(ws) & 255)) return ETX_ERR_INVALID_ARG;
+  return ETX_OK;
+}
+
+}  // namespace etx
+
+using namespace etx;
+
+extern "C" {
+
+const char* etx_last_error(void) { return g_last_error.c_str(); }
+
+const char* etx_status_str(etx_status s) {
+  switch (s) {
+    case ETX_OK: return "ok";
+    case ETX_ERR_INVALID_ARG: return "invalid argument";
+    case ETX_ERR_CAPACITY: return "edge capacity exceeded";
+    case ETX_ERR_INPUT: return "invalid input hits";
+    case ETX_ERR_WEIGHTS: return "weight blob does not match the configuration";
+    case ETX_ERR_UNSUPPORTED: return "unsupported size or configuration";
+    case ETX_ERR_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+etx_status etx_weight_blob_size(const etx_config* cfg, size_t* nbytes) {
+  etx_status st = check_config(cfg);
+  if (st != ETX_OK) return st;
+  if (!nbytes) return ETX_ERR_INVALID_ARG;
+  *nbytes = 32 + sizeof(float) * blob_floats(*cfg);
+  return ETX_OK;
+}
+
+etx_status etx_create(const etx_config* cfg, const void* weights, size_t nbytes, int device, etx_ctx** out) {
+  if (!out) return ETX_ERR_INVALID_ARG;
+  *out = nullptr;
+  etx_status st = check_config(cfg);
+  if (st != ETX_OK) return st;
+  if (!weights) return ETX_ERR_INVALID_ARG;
+  std::vector<float> payload;
+  std::vector<BlobLayer> layers;
+  if (!parse_blob(*cfg, weights, nbytes, payload, layers)) return ETX_ERR_WEIGHTS;
+  int ndev = 0;
+  hipError_t he = hipGetDeviceCount(&ndev);
+  if (he != hipSuccess) {
+    note_error("hipGetDeviceCount", he);
+    return ETX_ERR_HIP;
+  }
+  if (device < 0 || device >= ndev) return ETX_ERR_INVALID_ARG;
+  if ((he = hipSetDevice(device)) != hipSuccess) {
+    note_error("hipSetDevice", he);
+    return ETX_ERR_HIP;
+  }
+  if (set_kernel_attributes() != 0) {
+    g_last_error = "hipFuncSetAttribute(MaxDynamicSharedMemorySize) failed";
+    return ETX_ERR_HIP;
+  }
+  etx_ctx* ctx = new etx_ctx();
+  ctx->cfg = *cfg;
+  ctx->device = device;
+  if (hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
+    delete ctx;
+    return ETX_ERR_HIP;
+  }
+  ctx->host_blob.assign(static_cast<const char*>(weights) + 0, static_cast<const char*>(weights) + 0);
+  ctx->host_blob = payload;
+  st = build_segments(ctx, layers);
+  if (st == ETX_OK && hipMalloc(&ctx->dev_scales, sizeof(float) * 2 * ETX_N_CALIB) != hipSuccess) st = ETX_ERR_HIP;
+  if (st == ETX_OK && hipMemset(ctx->dev_scales, 0, sizeof(float) * 2 * ETX_N_CALIB) != hipSuccess) st = ETX_ERR_HIP;
+  if (st == ETX_OK && hipMalloc(&ctx->dev_pf, sizeof(float) * 3 * ETX_PF_NPARAM) != hipSuccess) st = ETX_ERR_HIP;
+  if (st == ETX_OK && hipMemset(ctx->dev_pf, 0, sizeof(float) * 3 * ETX_PF_NPARAM) != hipSuccess) st = ETX_ERR_HIP;
+  if (st == ETX_OK && cfg->precision != ETX_FP32 && build_low_precision(ctx) != hipSuccess) st = ETX_ERR_HIP;
+  if (st != ETX_OK) {
+    etx_destroy(ctx);
+    return st;
+  }
+  *out = ctx;
+  return ETX_OK;
+}
+
+etx_status etx_destroy(etx_ctx* ctx) {
+  if (!ctx) return ETX_ERR_INVALID_ARG;
+  hipSetDevice(ctx->device);
+  clear_graphs(ctx);
+  if (ctx->dev_w) hipFree(ctx->dev_w);
+  if (ctx->dev_wq) hipFree(ctx->dev_wq);
+  if (ctx->dev_scales) hipFree(ctx->dev_scales);
+  if (ctx->dev_pf) hipFree(ctx->dev_pf);
+  delete ctx;
+  return ETX_OK;
+}
+
+etx_status etx_workspace_size(const etx_ctx* ctx, int64_t n_events, int64_t n_hits, int64_t edge_capacity,
+                              size_t* bytes) {
+  if (!ctx || !bytes || n_events < 0 || n_hits < 0 || edge_capacity < 0) return ETX_ERR_INVALID_ARG;
+  *bytes = ws_layout(ctx, n_events, n_hits, edge_capacity).total;
+  return ETX_OK;
+}
+
+etx_status etx_workspace_view(const etx_ctx* ctx, int64_t n_events, int64_t n_hits, int64_t edge_capacity,
+                              int32_t which, size_t* offset, size_t* bytes) {
+  if (!ctx || !offset || !bytes || n_events < 0 || n_hits < 0 || edge_capacity < 0) return ETX_ERR_INVALID_ARG;
+  WsLayout L = ws_layout(ctx, n_events, n_hits, edge_capacity);
+  const int64_t H = ctx->cfg.gnn_hidden;
+  switch (which) {
+    case ETX_VIEW_EMBEDDING: *offset = L.emb; *bytes = sizeof(float) * n_hits * kDpad; break;
+    case ETX_VIEW_BUCKET: *offset = L.bucket; *bytes = sizeof(int32_t) * n_hits; break;
+    case ETX_VIEW_PLANE_OFF: *offset = L.plane_off; *bytes = sizeof(int32_t) * n_events * (ctx->cfg.n_planes + 1); break;
+    case ETX_VIEW_ROW_PTR: *offset = L.row_ptr; *bytes = sizeof(int64_t) * (n_hits + 1); break;
+    case ETX_VIEW_COL_PTR: *offset = L.col_ptr; *bytes = sizeof(int64_t) * (n_hits + 1); break;
+    case ETX_VIEW_CSC_EDGE: *offset = L.csc; *bytes = sizeof(int32_t) * edge_capacity; break;
+    case ETX_VIEW_NODE_H: *offset = L.h; *bytes = sizeof(float) * n_hits * H; break;
+    case ETX_VIEW_KEPT_EDGE: *offset = L.kept; *bytes = sizeof(int32_t) * edge_capacity; break;
+    case ETX_VIEW_KEPT_COUNT: *offset = L.kept_cnt; *bytes = sizeof(int32_t) * n_events; break;
+    case ETX_VIEW_CALIB: *offset = L.calib; *bytes = sizeof(float) * ETX_N_CALIB; break;
+    case ETX_VIEW_PF_KEEP: *offset = L.pf_keep; *bytes = edge_capacity; break;
+    default: return ETX_ERR_INVALID_ARG;
+  }
+  return ETX_OK;
+}
+
+etx_status etx_set_option(etx_ctx* ctx, int32_t key, int64_t value) {
+  if (!ctx) return ETX_ERR_INVALID_ARG;
+  switch (key) {
+    case ETX_OPT_USE_GRAPH:
+      if (value != 0 && value != 1) return ETX_ERR_INVALID_ARG;
+      ctx->use_graph = (int)value;
+      break;
+    case ETX_OPT_EDGE_WG_PER_CU:
+      if (value < 1 || value > 8) return ETX_ERR_INVALID_ARG;
+      ctx->edge_wg_per_cu = (int)value;
+      break;
+    case ETX_OPT_NODE_WG_PER_CU:
+      if (value < 1 || value > 8) return ETX_ERR_INVALID_ARG;
+      ctx->node_wg_per_cu = (int)value;
+      break;
+    case ETX_OPT_RADIUS_LDS:
+      if (value < 0 || value > kRadiusLdsMax) return ETX_ERR_INVALID_ARG;
+      ctx->radius_lds = (int)value;
+      break;
+    case ETX_OPT_SEGSUM_UNROLL:
+      if (value != 1 && value != 2 && value != 4 && value != 8) return ETX_ERR_INVALID_ARG;
+      ctx->segsum_unroll = (int)value;
+      break;
+    default: return ETX_ERR_INVALID_ARG;
+  }
+  if (key != ETX_OPT_USE_GRAPH) clear_graphs(ctx);
+  return ETX_OK;
+}
+
+etx_status etx_get_option(const etx_ctx* ctx, int32_t key, int64_t* value) {
+  if (!ctx || !value) return ETX_ERR_INVALID_ARG;
+  switch (key) {
+    case ETX_OPT_USE_GRAPH: *value = ctx->use_graph; break;
+    case ETX_OPT_EDGE_WG_PER_CU: *value = ctx->edge_wg_per_cu; break;
+    case ETX_OPT_NODE_WG_PER_CU: *value = ctx->node_wg_per_cu; break;
+    case ETX_OPT_RADIUS_LDS: *value = ctx->radius_lds; break;
+    case ETX_OPT_SEGSUM_UNROLL: *value = ctx->segsum_unroll; break;
+    default: return ETX_ERR_INVALID_ARG;
+  }
+  return ETX_OK;
+}
+
+etx_status etx_run(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void* ws, size_t ws_bytes, etx_stream stream) {
+  WsLayout L;
+  etx_status st = check_run_args(ctx, hits, out, ws, ws_bytes, &L);
+  if (st != ETX_OK) return st;
+  if (ctx->cfg.precision != ETX_FP32 && !ctx->calibrated && ctx->cfg.precision == ETX_FP8_E4M3)
+    return ETX_ERR_INVALID_ARG;
+  if (ctx->cfg.prefilter && !ctx->pf_set) return ETX_ERR_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return ETX_ERR_HIP;
+  RunArgs a{ctx, *hits, *out, L, static_cast<char*>(ws), static_cast<hipStream_t>(stream), false};
+  if (!ctx->use_graph || stream == nullptr) {
+    hipError_t e = enqueue_pipeline(a);
+    if (e != hipSuccess) {
+      note_error("etx_run launch", e);
+      return ETX_ERR_HIP;
+    }
+    return ETX_OK;
+  }
+  GraphKey key{};
+  const void* ps[16] = {hits->hit_off, hits->x, hits->y, hits->z, hits->plane, out->src, out->dst, out->score,
+                        out->edge_off, out->labels, out->status, ws, nullptr, nullptr, nullptr, nullptr};
+  std::memcpy(key.p, ps, sizeof(ps));
+  key.n[0] = hits->n_events;
+  key.n[1] = hits->n_hits;
+  key.n[2] = out->edge_capacity;
+  key.n[3] = ((int64_t)ctx->cfg.precision << 1) | ctx->cfg.prefilter;
+  auto it = ctx->graphs.find(key);
+  if (it == ctx->graphs.end()) {
+    hipStream_t s = a.stream;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return ETX_ERR_HIP;
+    hipError_t e1 = enqueue_pipeline(a);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s, &g);
+    if (e1 != hipSuccess || e2 != hipSuccess || !g) {
+      if (g) hipGraphDestroy(g);
+      return ETX_ERR_HIP;
+    }
+    hipGraphExec_t ex = nullptr;
+    hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e3 != hipSuccess) return ETX_ERR_HIP;
+    it = ctx->graphs.emplace(key, ex).first;
+  }
+  return hipGraphLaunch(it->second, a.stream) == hipSuccess ? ETX_OK : ETX_ERR_HIP;
+}
+
+}  // extern "C"

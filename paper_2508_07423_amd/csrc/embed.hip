@@ -1,0 +1,127 @@
+// Embedding MLP (thesis ch. 8 "Hit Embedding and Rough Graph Construction"):
+// normalised cylindrical coordinates (r/R_s, phi/pi, z/Z_s) -> Linear -> ReLU
+// -> ... -> Linear, fused with the feature computation.  The 3-wide first layer
+// runs on the vector ALU; the W x W hidden layers and the output layer run on
+// FP32 MFMA in the column layout of tile.hpp.  Output: [n_hits][16] (padded).
+#include "internal.hpp"
+#include "seg.hpp"
+#include "tile.hpp"
+
+namespace etx {
+
+namespace {
+
+struct EmbedArgs {
+  const float* x;
+  const float* y;
+  const float* z;
+  int64_t n_hits;
+  float inv_r, inv_z;
+  const float* seg;
+  int seg_floats;
+  int layers;
+  float* emb;
+  float* calib;
+  const int64_t* status;
+};
+
+__device__ inline void atomic_amax(float* slot, float v) {
+  // non-negative floats order like their bit patterns
+  atomicMax(reinterpret_cast<unsigned int*>(slot), __float_as_uint(fabsf(v)));
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void k_embed(EmbedArgs A) {
+  if (A.status[0] != 0) return;
+  extern __shared__ float w[];
+  stage(w, A.seg, A.seg_floats);
+  __syncthreads();
+  const SegEmb S{W, A.layers};
+  const int lane = lane_id(), h = lane >> 5, wave = threadIdx.x >> 6;
+  const int64_t ntiles = (A.n_hits + kTile - 1) / kTile;
+  for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
+    const int64_t col = tile * kTile + (lane & 31);
+    const bool valid = col < A.n_hits;
+    float u0 = 0.f, u1 = 0.f, u2 = 0.f;
+    if (valid) {
+      const float xx = A.x[col], yy = A.y[col], zz = A.z[col];
+      u0 = hypotf(xx, yy) * A.inv_r;
+      u1 = atan2f(yy, xx) * 0.318309886183790672f;   // 1/pi
+      u2 = zz * A.inv_z;
+    }
+    float a[W / 2];
+    const float* w1 = w + S.w1();
+    const float* b1 = w + S.b1();
+#pragma unroll
+    for (int r = 0; r < W / 2; ++r) {
+      const int f = phi(r, h);
+      float acc = u0 * w1[f];
+      acc = fmaf(u1, w1[W + f], acc);
+      acc = fmaf(u2, w1[2 * W + f], acc);
+      a[r] = fmaxf(acc + b1[f], 0.f);
+    }
+    for (int l = 1; l < A.layers; ++l) {
+      float acc[W / 2];
+      bias_cols<W>(acc, w + S.bh(l));
+      if (A.calib) {
+        float m = 0.f;
+#pragma unroll
+        for (int r = 0; r < W / 2; ++r) m = fmaxf(m, fabsf(a[r]));
+        if (valid) atomic_amax(A.calib + CAL_EMB_IN + l, m);
+      }
+      mfma_f32<W, W / 32>(acc, a, w + S.wh(l));
+#pragma unroll
+      for (int r = 0; r < W / 2; ++r) a[r] = fmaxf(acc[r], 0.f);
+    }
+    float o[16];
+    bias_cols<32>(o, w + S.bo());
+    mfma_f32<W, 1>(o, a, w + S.wo());
+    // features 0..15 live in registers 0..7 of both halves
+    if (valid) {
+      float* row = A.emb + col * kDpad;
+      *reinterpret_cast<float4*>(row + 4 * h) = make_float4(o[0], o[1], o[2], o[3]);
+      *reinterpret_cast<float4*>(row + 8 + 4 * h) = make_float4(o[4], o[5], o[6], o[7]);
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_embed(const RunArgs& a) {
+  if (a.hits.n_hits == 0) return hipSuccess;
+  const etx_ctx* c = a.ctx;
+  EmbedArgs A;
+  A.x = a.hits.x;
+  A.y = a.hits.y;
+  A.z = a.hits.z;
+  A.n_hits = a.hits.n_hits;
+  A.inv_r = 1.0f / c->cfg.r_scale_mm;
+  A.inv_z = 1.0f / c->cfg.z_scale_mm;
+  A.seg = c->dev_w + c->wmap.emb;
+  A.layers = c->cfg.emb_layers;
+  A.emb = reinterpret_cast<float*>(a.ws + a.L.emb);
+  A.calib = a.calibrate ? reinterpret_cast<float*>(a.ws + a.L.calib) : nullptr;
+  A.status = a.out.status;
+  const int W = c->cfg.emb_hidden;
+  A.seg_floats = SegEmb{W, A.layers}.size();
+  size_t lds = sizeof(float) * A.seg_floats;
+  int64_t tiles = (A.n_hits + kTile - 1) / kTile;
+  unsigned grid = (unsigned)std::min<int64_t>((tiles + 3) / 4, (int64_t)c->n_cu * 2);
+  switch (W) {
+    case 32: hipLaunchKernelGGL(k_embed<32>, dim3(grid), dim3(256), lds, a.stream, A); break;
+    case 64: hipLaunchKernelGGL(k_embed<64>, dim3(grid), dim3(256), lds, a.stream, A); break;
+    case 128: hipLaunchKernelGGL(k_embed<128>, dim3(grid), dim3(256), lds, a.stream, A); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int embed_attributes(size_t max_lds) {
+  int bad = 0;
+  bad |= hipFuncSetAttribute(reinterpret_cast<const void*>(k_embed<32>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) != hipSuccess;
+  bad |= hipFuncSetAttribute(reinterpret_cast<const void*>(k_embed<64>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) != hipSuccess;
+  bad |= hipFuncSetAttribute(reinterpret_cast<const void*>(k_embed<128>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) != hipSuccess;
+  return bad;
+}
+
+}  // namespace etx

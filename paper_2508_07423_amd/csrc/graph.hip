@@ -1,0 +1,607 @@
+// Integer and graph kernels of the hot path: input validation, plane
+// bucketing, the fixed-radius graph, offsets, the CSC permutation, edge
+// compaction after the score cut, and union-find components.
+#include "internal.hpp"
+
+namespace etx {
+
+namespace {
+
+__device__ inline void set_status(int64_t* status, int64_t code) {
+  atomicCAS(reinterpret_cast<unsigned long long*>(status), 0ull, static_cast<unsigned long long>(code));
+}
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline int wave_inclusive_scan(int v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int t = __shfl_up(v, d);
+    if (lane >= d) v += t;
+  }
+  return v;
+}
+
+// Exclusive scan over a 256-thread block; returns the exclusive prefix and the
+// block total.  `tmp` holds 4 ints of LDS.
+__device__ inline int block_exclusive_scan(int v, int* tmp, int& total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int inc = wave_inclusive_scan(v);
+  if (lane == 63) tmp[wave] = inc;
+  __syncthreads();
+  int base = 0;
+  total = 0;
+  for (int w = 0; w < 4; ++w) {
+    int s = tmp[w];
+    if (w < wave) base += s;
+    total += s;
+  }
+  __syncthreads();
+  return base + inc - v;
+}
+
+// --------------------------------------------------------------------------
+// status / validation
+// --------------------------------------------------------------------------
+
+__global__ void k_init_status(int64_t* status, float* calib, int n_calib) {
+  int t = threadIdx.x;
+  if (t < 2) status[t] = 0;
+  if (calib && t < n_calib) calib[t] = 0.f;
+}
+
+__global__ void k_validate(int64_t n_events, int64_t n_hits, const int64_t* __restrict__ hit_off,
+                           const float* __restrict__ x, const float* __restrict__ y, const float* __restrict__ z,
+                           const int32_t* __restrict__ plane, int n_planes, int64_t* status) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_hits + n_events + 1; i += stride) {
+    if (i < n_hits) {
+      int p = plane[i];
+      if (!isfinite(x[i]) || !isfinite(y[i]) || !isfinite(z[i]) || p < 0 || p >= n_planes) set_status(status, ETX_ERR_INPUT);
+    } else {
+      int64_t e = i - n_hits;
+      if (e == n_events) {
+        if (hit_off[n_events] != n_hits || hit_off[0] != 0) set_status(status, ETX_ERR_INPUT);
+      } else {
+        int64_t cnt = hit_off[e + 1] - hit_off[e];
+        if (cnt < 0) set_status(status, ETX_ERR_INPUT);
+        else if (cnt > ETX_MAX_EVENT_HITS) set_status(status, ETX_ERR_UNSUPPORTED);
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// plane bucketing: per event, a stable counting sort of hits by plane
+// --------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_bucket(const int64_t* __restrict__ hit_off, const int32_t* __restrict__ plane,
+                                                int n_planes, int32_t* __restrict__ bucket,
+                                                int32_t* __restrict__ plane_off, const int64_t* status) {
+  if (status[0] != 0) return;
+  extern __shared__ int cnt[];            // [n_planes][256]
+  __shared__ int tmp[4];
+  const int ev = blockIdx.x, t = threadIdx.x;
+  const int64_t a = hit_off[ev];
+  const int n = (int)(hit_off[ev + 1] - a);
+  const int chunk = (n + 255) / 256;
+  const int lo = min(n, t * chunk), hi = min(n, lo + chunk);
+  for (int p = 0; p < n_planes; ++p) cnt[p * 256 + t] = 0;
+  for (int i = lo; i < hi; ++i) cnt[plane[a + i] * 256 + t] += 1;
+  __syncthreads();
+  int base = 0;
+  int32_t* po = plane_off + (int64_t)ev * (n_planes + 1);
+  for (int p = 0; p < n_planes; ++p) {
+    int total;
+    int ex = block_exclusive_scan(cnt[p * 256 + t], tmp, total);
+    cnt[p * 256 + t] = base + ex;
+    if (t == 0) po[p] = base;
+    base += total;
+  }
+  if (t == 0) po[n_planes] = n;
+  __syncthreads();
+  for (int i = lo; i < hi; ++i) {
+    int p = plane[a + i];
+    int pos = cnt[p * 256 + t]++;
+    bucket[a + pos] = (int32_t)(a + i);
+  }
+}
+
+// --------------------------------------------------------------------------
+// fixed-radius graph
+// --------------------------------------------------------------------------
+
+struct RadiusArgs {
+  const int64_t* hit_off;
+  const int32_t* bucket;
+  const int32_t* plane_off;
+  const float* emb;        // [n_hits][16]
+  int n_planes, window, k_max, lds_max;
+  float r2;
+  int32_t* cnt;            // count pass output
+  const int64_t* row_ptr;  // emit pass input
+  int32_t* src;
+  int32_t* dst;
+  const int64_t* status;
+};
+
+__device__ inline float dist2(const float (&s)[kDpad], const float* __restrict__ c) {
+  float d2 = 0.f;
+#pragma unroll
+  for (int k = 0; k < kDpad; k += 4) {
+    float4 v = *reinterpret_cast<const float4*>(c + k);
+    float t0 = s[k] - v.x, t1 = s[k + 1] - v.y, t2 = s[k + 2] - v.z, t3 = s[k + 3] - v.w;
+    d2 = fmaf(t0, t0, d2);
+    d2 = fmaf(t1, t1, d2);
+    d2 = fmaf(t2, t2, d2);
+    d2 = fmaf(t3, t3, d2);
+  }
+  return d2;
+}
+
+// One workgroup per (event, source plane); each wave takes one source hit at
+// a time and scans the candidate window (planes p+1 .. p+window), which the
+// workgroup stages in LDS when it fits.
+template <bool EMIT>
+__global__ __launch_bounds__(256) void k_radius(RadiusArgs A) {
+  if (A.status[0] != 0) return;
+  extern __shared__ float lds[];
+  float* cemb = lds;                                         // [lds_max][16]
+  int* cj = reinterpret_cast<int*>(cemb + A.lds_max * kDpad);  // [lds_max]
+  float* dcache = reinterpret_cast<float*>(cj + A.lds_max);   // [4][lds_max]
+  int* sel = reinterpret_cast<int*>(dcache + 4 * A.lds_max);  // [4][64]
+
+  const int P = A.n_planes;
+  const int ev = blockIdx.x / P, p = blockIdx.x % P;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t a = A.hit_off[ev];
+  const int32_t* po = A.plane_off + (int64_t)ev * (P + 1);
+  const int s0 = po[p], s1 = po[p + 1];
+  const int pw = min(p + A.window, P - 1);
+  const int w0 = po[min(p + 1, P)], w1 = po[pw + 1] > w0 ? po[pw + 1] : w0;
+  const int nwin = (p + 1 < P) ? (w1 - w0) : 0;
+  const int nsrc = s1 - s0;
+  if (nsrc == 0) return;
+  const bool use_lds = nwin <= A.lds_max;
+  const int32_t* wb = A.bucket + a + w0;
+  if (use_lds) {
+    for (int c = threadIdx.x; c < nwin; c += blockDim.x) {
+      int j = wb[c];
+      cj[c] = j;
+      const float4* s = reinterpret_cast<const float4*>(A.emb + (int64_t)j * kDpad);
+      float4* d = reinterpret_cast<float4*>(cemb + c * kDpad);
+#pragma unroll
+      for (int q = 0; q < kDpad / 4; ++q) d[q] = s[q];
+    }
+    __syncthreads();
+  }
+  float* dc = dcache + wave * A.lds_max;
+  int* sl = sel + wave * 64;
+  const unsigned r2bits = __float_as_uint(A.r2);
+
+  for (int s = wave; s < nsrc; s += 4) {
+    const int32_t i = A.bucket[a + s0 + s];
+    float se[kDpad];
+#pragma unroll
+    for (int q = 0; q < kDpad; q += 4) {
+      float4 v = *reinterpret_cast<const float4*>(A.emb + (int64_t)i * kDpad + q);
+      se[q] = v.x; se[q + 1] = v.y; se[q + 2] = v.z; se[q + 3] = v.w;
+    }
+    auto cand_d2 = [&](int c) -> float {
+      if (use_lds) return dist2(se, cemb + c * kDpad);
+      return dist2(se, A.emb + (int64_t)wb[c] * kDpad);
+    };
+    auto cand_j = [&](int c) -> int { return use_lds ? cj[c] : wb[c]; };
+    // pass 1: candidates inside the radius
+    int n = 0;
+    for (int c0 = 0; c0 < nwin; c0 += 64) {
+      int c = c0 + lane;
+      bool in = false;
+      if (c < nwin) {
+        float d2 = cand_d2(c);
+        if (use_lds) dc[c] = d2;
+        in = d2 < A.r2;
+      }
+      n += __popcll(__ballot(in));
+    }
+    if (!EMIT) {
+      if (lane == 0) A.cnt[i] = min(n, A.k_max);
+      continue;
+    }
+    if (n == 0) continue;
+    auto get_d2 = [&](int c) -> float { return use_lds ? dc[c] : cand_d2(c); };
+    // count of inside candidates with key below a bound (wave-uniform result)
+    auto count_if = [&](auto pred) -> int {
+      int m = 0;
+      for (int c0 = 0; c0 < nwin; c0 += 64) {
+        int c = c0 + lane;
+        bool b = false;
+        if (c < nwin) {
+          float d2 = get_d2(c);
+          b = d2 < A.r2 && pred(d2, c);
+        }
+        m += __popcll(__ballot(b));
+      }
+      return m;
+    };
+    bool capped = n > A.k_max;
+    float T = A.r2;
+    int Jt = 0x7fffffff;
+    if (capped) {
+      // smallest T (as float bits) with #{d2 <= T} >= k_max: the k-th smallest d2
+      unsigned lo = 0, hi = r2bits - 1u;
+      while (lo < hi) {
+        unsigned mid = lo + (hi - lo) / 2;
+        float fm = __uint_as_float(mid);
+        int m = count_if([&](float d2, int) { return d2 <= fm; });
+        if (m >= A.k_max) hi = mid; else lo = mid + 1;
+      }
+      T = __uint_as_float(lo);
+      int less = count_if([&](float d2, int) { return d2 < T; });
+      int need = A.k_max - less;
+      int eq = count_if([&](float d2, int) { return d2 == T; });
+      if (eq > need) {
+        // ties at the boundary distance: keep the `need` smallest hit indices
+        int jlo = (int)a, jhi = (int)(a + A.hit_off[ev + 1] - a - 1);
+        while (jlo < jhi) {
+          int mid = jlo + (jhi - jlo) / 2;
+          int m = count_if([&](float d2, int c) { return d2 == T && cand_j(c) <= mid; });
+          if (m >= need) jhi = mid; else jlo = mid + 1;
+        }
+        Jt = jlo;
+      }
+    }
+    // compact the selected targets into the wave's list (at most k_max <= 64)
+    int ns = 0;
+    for (int c0 = 0; c0 < nwin; c0 += 64) {
+      int c = c0 + lane;
+      bool b = false;
+      int j = 0;
+      if (c < nwin) {
+        float d2 = get_d2(c);
+        j = cand_j(c);
+        b = d2 < A.r2 && (!capped || d2 < T || (d2 == T && j <= Jt));
+      }
+      uint64_t m = __ballot(b);
+      if (b) {
+        int pre = __popcll(m & ((1ull << lane) - 1ull));
+        if (ns + pre < 64) sl[ns + pre] = j;
+      }
+      ns += __popcll(m);
+    }
+    // never write past the row the count pass reserved
+    ns = min(ns, (int)(A.row_ptr[i + 1] - A.row_ptr[i]));
+    wave_sync();
+    // order by target index and write the row
+    if (lane < ns) {
+      int my = sl[lane];
+      int rank = 0;
+      for (int q = 0; q < ns; ++q) rank += sl[q] < my;
+      int64_t pos = A.row_ptr[i] + rank;
+      A.src[pos] = i;
+      A.dst[pos] = my;
+    }
+    wave_sync();
+  }
+}
+
+// --------------------------------------------------------------------------
+// device-wide exclusive scan of per-hit edge counts -> row_ptr
+// --------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const int32_t* __restrict__ cnt, int64_t n, int64_t* __restrict__ part,
+                                                     const int64_t* status) {
+  if (status[0] != 0) return;
+  __shared__ int64_t red[256];
+  int64_t b = blockIdx.x;
+  int64_t s = 0;
+  for (int q = 0; q < kScanBlock / 256; ++q) {
+    int64_t i = b * kScanBlock + q * 256 + threadIdx.x;
+    if (i < n) s += cnt[i];
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[b] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_scan_top(int64_t* __restrict__ part, int64_t nb, int64_t* __restrict__ row_ptr,
+                                                  int64_t n, int64_t capacity, int64_t* status) {
+  if (status[0] != 0) return;
+  __shared__ int64_t sh[256];
+  int64_t carry = 0;
+  for (int64_t b0 = 0; b0 < nb; b0 += 256) {
+    int64_t b = b0 + threadIdx.x;
+    int64_t v = b < nb ? part[b] : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {
+      int64_t t = threadIdx.x >= d ? sh[threadIdx.x - d] : 0;
+      __syncthreads();
+      sh[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (b < nb) part[b] = carry + sh[threadIdx.x] - v;
+    int64_t tot = sh[255];
+    __syncthreads();
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    row_ptr[n] = carry;
+    if (carry > capacity) {
+      status[1] = carry;
+      set_status(status, ETX_ERR_CAPACITY);
+    } else if (carry >= 0x7fffffffLL) {
+      status[1] = carry;
+      set_status(status, ETX_ERR_UNSUPPORTED);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scan_down(const int32_t* __restrict__ cnt, int64_t n, const int64_t* __restrict__ part,
+                                                   int64_t* __restrict__ row_ptr, const int64_t* status) {
+  if (status[0] != 0) return;
+  __shared__ int tmp[4];
+  int64_t base = part[blockIdx.x];
+  for (int q = 0; q < kScanBlock / 256; ++q) {
+    int64_t i = (int64_t)blockIdx.x * kScanBlock + q * 256 + threadIdx.x;
+    int v = i < n ? cnt[i] : 0;
+    int total;
+    int ex = block_exclusive_scan(v, tmp, total);
+    if (i < n) row_ptr[i] = base + ex;
+    base += total;
+  }
+}
+
+__global__ void k_edge_off(const int64_t* __restrict__ hit_off, int64_t n_events, const int64_t* __restrict__ row_ptr,
+                           int64_t* __restrict__ edge_off, const int64_t* status) {
+  if (status[0] != 0) return;
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e <= n_events) edge_off[e] = row_ptr[hit_off[e]];
+}
+
+// --------------------------------------------------------------------------
+// CSC: edge ids ordered by (dst, src), per event
+// --------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_csc(const int64_t* __restrict__ hit_off, const int64_t* __restrict__ row_ptr,
+                                             const int32_t* __restrict__ dst, int64_t* __restrict__ col_ptr,
+                                             int32_t* __restrict__ csc, const int64_t* status) {
+  if (status[0] != 0) return;
+  __shared__ int cur[ETX_MAX_EVENT_HITS];
+  __shared__ int tmp[4];
+  const int ev = blockIdx.x, t = threadIdx.x, lane = t & 63;
+  const int64_t a = hit_off[ev];
+  const int n = (int)(hit_off[ev + 1] - a);
+  const int64_t eb = row_ptr[a], ee = row_ptr[a + n];
+  for (int i = t; i < n; i += 256) cur[i] = 0;
+  __syncthreads();
+  for (int64_t q = eb + t; q < ee; q += 256) atomicAdd(&cur[dst[q] - a], 1);
+  __syncthreads();
+  int base = 0;
+  for (int i0 = 0; i0 < n; i0 += 256) {
+    int i = i0 + t;
+    int v = i < n ? cur[i] : 0;
+    int total;
+    int ex = block_exclusive_scan(v, tmp, total);
+    if (i < n) {
+      cur[i] = base + ex;
+      col_ptr[a + i] = eb + base + ex;
+    }
+    base += total;
+  }
+  if (t == 0) col_ptr[a + n] = ee;
+  __syncthreads();
+  if (t >= 64) return;
+  // one wave walks the rows in source order; the targets of one row are
+  // distinct, so its lanes never share a cursor
+  int64_t rs = row_ptr[a];
+  int64_t re = n > 0 ? row_ptr[a + 1] : rs;
+  int d_next = (n > 0 && rs + lane < re) ? dst[rs + lane] : 0;
+  for (int i = 0; i < n; ++i) {
+    const int64_t cs = rs, ce = re;
+    const int d = d_next;
+    if (i + 1 < n) {
+      rs = ce;
+      re = row_ptr[a + i + 2];
+      d_next = (rs + lane < re) ? dst[rs + lane] : 0;
+    }
+    if (cs + lane < ce) {
+      int dl = d - (int)a;
+      int pos = cur[dl];
+      cur[dl] = pos + 1;
+      csc[eb + pos] = (int32_t)(cs + lane);
+    }
+    wave_sync();
+  }
+}
+
+// --------------------------------------------------------------------------
+// score cut + compaction (wave ballot + block prefix scan), per event
+// --------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_compact(const int64_t* __restrict__ hit_off, const int64_t* __restrict__ row_ptr,
+                                                 const float* __restrict__ score, float thr, int32_t* __restrict__ kept,
+                                                 int32_t* __restrict__ kept_cnt, const int64_t* status) {
+  if (status[0] != 0) return;
+  __shared__ int tmp[4];
+  const int ev = blockIdx.x;
+  const int64_t eb = row_ptr[hit_off[ev]], ee = row_ptr[hit_off[ev + 1]];
+  int64_t cnt = 0;
+  for (int64_t q0 = eb; q0 < ee; q0 += 256) {
+    int64_t q = q0 + threadIdx.x;
+    int keep = (q < ee && score[q] >= thr) ? 1 : 0;
+    int total;
+    int ex = block_exclusive_scan(keep, tmp, total);
+    if (keep) kept[eb + cnt + ex] = (int32_t)q;
+    cnt += total;
+  }
+  if (threadIdx.x == 0) kept_cnt[ev] = (int32_t)cnt;
+}
+
+// --------------------------------------------------------------------------
+// components: lock-free union-find in LDS, per event
+// --------------------------------------------------------------------------
+
+__device__ inline int uf_find(volatile int* par, int x) {
+  int p = par[x];
+  while (p != x) {
+    int gp = par[p];
+    if (gp != p) par[x] = gp;   // path halving: gp is an ancestor of x
+    x = p;
+    p = gp;
+  }
+  return x;
+}
+
+__device__ inline void uf_unite(volatile int* par, int u, int v) {
+  while (true) {
+    u = uf_find(par, u);
+    v = uf_find(par, v);
+    if (u == v) return;
+    if (u > v) { int t = u; u = v; v = t; }
+    // hook the larger root under the smaller one, so every root is its tree's minimum
+    int old = atomicCAS(const_cast<int*>(reinterpret_cast<volatile int*>(par + v)), v, u);
+    if (old == v) return;
+    v = old;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_union_find(const int64_t* __restrict__ hit_off, const int64_t* __restrict__ row_ptr,
+                                                    const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
+                                                    const int32_t* __restrict__ kept, const int32_t* __restrict__ kept_cnt,
+                                                    int32_t* __restrict__ labels, const int64_t* status) {
+  if (status[0] != 0) return;
+  __shared__ int par[ETX_MAX_EVENT_HITS];
+  const int ev = blockIdx.x;
+  const int64_t a = hit_off[ev];
+  const int n = (int)(hit_off[ev + 1] - a);
+  const int64_t eb = row_ptr[a];
+  const int nk = kept_cnt[ev];
+  for (int i = threadIdx.x; i < n; i += 256) par[i] = i;
+  __syncthreads();
+  for (int q = threadIdx.x; q < nk; q += 256) {
+    int e = kept[eb + q];
+    uf_unite(par, src[e] - (int)a, dst[e] - (int)a);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += 256) labels[a + i] = (int32_t)(a + uf_find(par, i));
+}
+
+}  // namespace
+
+// --------------------------------------------------------------------------
+// launchers
+// --------------------------------------------------------------------------
+
+#define WS(a, off, T) reinterpret_cast<T*>((a).ws + (a).L.off)
+
+hipError_t launch_init_status(const RunArgs& a) {
+  hipLaunchKernelGGL(k_init_status, dim3(1), dim3(64), 0, a.stream, a.out.status,
+                     a.calibrate ? WS(a, calib, float) : nullptr, ETX_N_CALIB);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const RunArgs& a) {
+  int64_t work = a.hits.n_hits + a.hits.n_events + 1;
+  int grid = (int)std::min<int64_t>((work + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_validate, dim3(grid), dim3(256), 0, a.stream, a.hits.n_events, a.hits.n_hits, a.hits.hit_off,
+                     a.hits.x, a.hits.y, a.hits.z, a.hits.plane, a.ctx->cfg.n_planes, a.out.status);
+  return hipGetLastError();
+}
+
+hipError_t launch_bucket(const RunArgs& a) {
+  if (a.hits.n_events == 0) return hipSuccess;
+  size_t lds = sizeof(int) * 256 * a.ctx->cfg.n_planes;
+  hipLaunchKernelGGL(k_bucket, dim3((unsigned)a.hits.n_events), dim3(256), lds, a.stream, a.hits.hit_off,
+                     a.hits.plane, a.ctx->cfg.n_planes, WS(a, bucket, int32_t), WS(a, plane_off, int32_t),
+                     a.out.status);
+  return hipGetLastError();
+}
+
+hipError_t launch_radius(const RunArgs& a, bool emit) {
+  if (a.hits.n_events == 0) return hipSuccess;
+  const etx_config& c = a.ctx->cfg;
+  RadiusArgs A;
+  A.hit_off = a.hits.hit_off;
+  A.bucket = WS(a, bucket, int32_t);
+  A.plane_off = WS(a, plane_off, int32_t);
+  A.emb = WS(a, emb, float);
+  A.n_planes = c.n_planes;
+  A.window = c.plane_window;
+  A.k_max = c.k_max;
+  A.lds_max = a.ctx->radius_lds;
+  A.r2 = c.radius * c.radius;
+  A.cnt = WS(a, cnt, int32_t);
+  A.row_ptr = WS(a, row_ptr, int64_t);
+  A.src = a.out.src;
+  A.dst = a.out.dst;
+  A.status = a.out.status;
+  size_t lds = (size_t)A.lds_max * (kDpad * 4 + 4 + 16) + 4 * 64 * 4;
+  dim3 grid((unsigned)(a.hits.n_events * c.n_planes));
+  if (emit)
+    hipLaunchKernelGGL(k_radius<true>, grid, dim3(256), lds, a.stream, A);
+  else
+    hipLaunchKernelGGL(k_radius<false>, grid, dim3(256), lds, a.stream, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_counts(const RunArgs& a) {
+  const int64_t n = a.hits.n_hits;
+  const int64_t nb = a.L.n_scan_blocks;
+  int64_t* part = WS(a, scan_tmp, int64_t);
+  int64_t* row_ptr = WS(a, row_ptr, int64_t);
+  if (nb > 0)
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(256), 0, a.stream, WS(a, cnt, int32_t), n, part,
+                       a.out.status);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, a.stream, part, nb, row_ptr, n, a.out.edge_capacity,
+                     a.out.status);
+  if (nb > 0)
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(256), 0, a.stream, WS(a, cnt, int32_t), n, part, row_ptr,
+                       a.out.status);
+  int64_t ne = a.hits.n_events + 1;
+  hipLaunchKernelGGL(k_edge_off, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, a.stream, a.hits.hit_off,
+                     a.hits.n_events, row_ptr, a.out.edge_off, a.out.status);
+  return hipGetLastError();
+}
+
+hipError_t launch_csc(const RunArgs& a) {
+  if (a.hits.n_events == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_csc, dim3((unsigned)a.hits.n_events), dim3(256), 0, a.stream, a.hits.hit_off,
+                     WS(a, row_ptr, int64_t), a.out.dst, WS(a, col_ptr, int64_t), WS(a, csc, int32_t), a.out.status);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(const RunArgs& a) {
+  if (a.hits.n_events == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_compact, dim3((unsigned)a.hits.n_events), dim3(256), 0, a.stream, a.hits.hit_off,
+                     WS(a, row_ptr, int64_t), a.out.score, a.ctx->cfg.edge_threshold, WS(a, kept, int32_t),
+                     WS(a, kept_cnt, int32_t), a.out.status);
+  return hipGetLastError();
+}
+
+hipError_t launch_union_find(const RunArgs& a) {
+  if (a.hits.n_events == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_union_find, dim3((unsigned)a.hits.n_events), dim3(256), 0, a.stream, a.hits.hit_off,
+                     WS(a, row_ptr, int64_t), a.out.src, a.out.dst, WS(a, kept, int32_t), WS(a, kept_cnt, int32_t),
+                     a.out.labels, a.out.status);
+  return hipGetLastError();
+}
+
+int graph_attributes(size_t max_lds) {
+  int bad = 0;
+  bad |= hipFuncSetAttribute(reinterpret_cast<const void*>(k_bucket), hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) != hipSuccess;
+  bad |= hipFuncSetAttribute(reinterpret_cast<const void*>(k_radius<true>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) != hipSuccess;
+  bad |= hipFuncSetAttribute(reinterpret_cast<const void*>(k_radius<false>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) != hipSuccess;
+  return bad;
+}
+
+}  // namespace etx

@@ -1,0 +1,322 @@
+"""ctypes binding of ``libetx.so`` (C ABI in ``include/etx.h``).
+
+Argument marshalling only: every step of the track-finding path runs in the
+library's HIP kernels.  PyTorch supplies device memory and streams.  The
+library must be built (``paper_2508_07423_amd/build.py``); importing this
+module without it raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Dict, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libetx.so")
+
+ETX_OK, ETX_ERR_INVALID_ARG, ETX_ERR_CAPACITY, ETX_ERR_INPUT, ETX_ERR_WEIGHTS, ETX_ERR_UNSUPPORTED, ETX_ERR_HIP = range(7)
+ETX_FP32, ETX_BF16, ETX_FP8_E4M3 = 0, 1, 2
+ETX_MAX_EVENT_HITS = 16384
+ETX_N_CALIB = 64
+ETX_PF_HIDDEN = 32
+ETX_PF_NPARAM = 6 * 32 + 32 + 32 * 32 + 32 + 32 + 1
+(ETX_VIEW_EMBEDDING, ETX_VIEW_BUCKET, ETX_VIEW_PLANE_OFF, ETX_VIEW_ROW_PTR, ETX_VIEW_COL_PTR, ETX_VIEW_CSC_EDGE,
+ ETX_VIEW_NODE_H, ETX_VIEW_KEPT_EDGE, ETX_VIEW_KEPT_COUNT, ETX_VIEW_CALIB, ETX_VIEW_PF_KEEP) = range(11)
+(ETX_OPT_USE_GRAPH, ETX_OPT_EDGE_WG_PER_CU, ETX_OPT_NODE_WG_PER_CU, ETX_OPT_RADIUS_LDS,
+ ETX_OPT_SEGSUM_UNROLL) = range(5)
+
+
+class etx_config(C.Structure):
+    _fields_ = [("n_planes", C.c_int32), ("r_scale_mm", C.c_float), ("z_scale_mm", C.c_float),
+                ("emb_hidden", C.c_int32), ("emb_layers", C.c_int32), ("emb_dim", C.c_int32),
+                ("radius", C.c_float), ("k_max", C.c_int32), ("plane_window", C.c_int32),
+                ("gnn_hidden", C.c_int32), ("gnn_steps", C.c_int32), ("edge_threshold", C.c_float),
+                ("precision", C.c_int32), ("prefilter", C.c_int32), ("prefilter_tau", C.c_float)]
+
+
+class etx_hits(C.Structure):
+    _fields_ = [("n_events", C.c_int64), ("n_hits", C.c_int64), ("hit_off", C.c_void_p), ("x", C.c_void_p),
+                ("y", C.c_void_p), ("z", C.c_void_p), ("plane", C.c_void_p)]
+
+
+class etx_out(C.Structure):
+    _fields_ = [("edge_capacity", C.c_int64), ("src", C.c_void_p), ("dst", C.c_void_p), ("score", C.c_void_p),
+                ("edge_off", C.c_void_p), ("labels", C.c_void_p), ("status", C.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run paper_2508_07423_amd/build.py (or __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        P, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
+        sig = {
+            "etx_create": [C.POINTER(etx_config), P, sz, C.c_int, C.POINTER(P)],
+            "etx_destroy": [P],
+            "etx_weight_blob_size": [C.POINTER(etx_config), C.POINTER(sz)],
+            "etx_workspace_size": [P, i64, i64, i64, C.POINTER(sz)],
+            "etx_run": [P, C.POINTER(etx_hits), C.POINTER(etx_out), P, sz, P],
+            "etx_workspace_view": [P, i64, i64, i64, i32, C.POINTER(sz), C.POINTER(sz)],
+            "etx_set_option": [P, i32, i64],
+            "etx_get_option": [P, i32, C.POINTER(i64)],
+            "etx_autotune": [P, C.POINTER(etx_hits), C.POINTER(etx_out), P, sz, P, C.c_char_p],
+            "etx_calibrate": [P, C.POINTER(etx_hits), C.POINTER(etx_out), P, sz, P],
+            "etx_set_precision": [P, i32],
+            "etx_prefilter_set": [P, P, i64],
+            "etx_prefilter_get": [P, P, i64],
+            "etx_prefilter_train_step": [P, C.POINTER(etx_hits), C.POINTER(etx_out), P, C.c_float, C.c_float, i64, P,
+                                         P, sz, P],
+            "etx_prefilter_state": [P, P, i64, i32],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.etx_status_str.argtypes = [C.c_int]
+        L.etx_status_str.restype = C.c_char_p
+        L.etx_last_error.argtypes = []
+        L.etx_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+EXPORTED = ["etx_create", "etx_destroy", "etx_weight_blob_size", "etx_workspace_size", "etx_run",
+            "etx_workspace_view", "etx_set_option", "etx_get_option", "etx_autotune", "etx_calibrate",
+            "etx_set_precision", "etx_prefilter_set", "etx_prefilter_get", "etx_prefilter_train_step",
+            "etx_prefilter_state", "etx_status_str", "etx_last_error"]
+
+
+class EtxError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        detail = lib().etx_last_error().decode() if code == ETX_ERR_HIP else ""
+        super().__init__(f"{what}: {etx_status_str(code)} ({code}) {detail}".rstrip())
+
+
+def etx_status_str(code: int) -> str:
+    return lib().etx_status_str(int(code)).decode()
+
+
+def _check(code: int, what: str):
+    if code != ETX_OK:
+        raise EtxError(code, what)
+
+
+# ---------------------------------------------------------------------------
+# thin wrappers with the C names
+# ---------------------------------------------------------------------------
+
+def etx_weight_blob_size(cfg: etx_config) -> int:
+    n = C.c_size_t()
+    _check(lib().etx_weight_blob_size(C.byref(cfg), C.byref(n)), "etx_weight_blob_size")
+    return n.value
+
+
+def etx_create(cfg: etx_config, blob: bytes, device: int = 0) -> C.c_void_p:
+    h = C.c_void_p()
+    buf = C.create_string_buffer(blob, len(blob))
+    _check(lib().etx_create(C.byref(cfg), buf, len(blob), device, C.byref(h)), "etx_create")
+    return h
+
+
+def etx_destroy(ctx) -> None:
+    _check(lib().etx_destroy(ctx), "etx_destroy")
+
+
+def etx_workspace_size(ctx, n_events: int, n_hits: int, edge_capacity: int) -> int:
+    n = C.c_size_t()
+    _check(lib().etx_workspace_size(ctx, n_events, n_hits, edge_capacity, C.byref(n)), "etx_workspace_size")
+    return n.value
+
+
+def etx_workspace_view(ctx, n_events: int, n_hits: int, edge_capacity: int, which: int):
+    o, b = C.c_size_t(), C.c_size_t()
+    _check(lib().etx_workspace_view(ctx, n_events, n_hits, edge_capacity, which, C.byref(o), C.byref(b)),
+           "etx_workspace_view")
+    return o.value, b.value
+
+
+def etx_run(ctx, hits: etx_hits, out: etx_out, ws_ptr: int, ws_bytes: int, stream: int) -> None:
+    _check(lib().etx_run(ctx, C.byref(hits), C.byref(out), C.c_void_p(ws_ptr), ws_bytes, C.c_void_p(stream)),
+           "etx_run")
+
+
+def etx_set_option(ctx, key: int, value: int) -> None:
+    _check(lib().etx_set_option(ctx, key, value), "etx_set_option")
+
+
+def etx_get_option(ctx, key: int) -> int:
+    v = C.c_int64()
+    _check(lib().etx_get_option(ctx, key, C.byref(v)), "etx_get_option")
+    return v.value
+
+
+def etx_autotune(ctx, hits, out, ws_ptr, ws_bytes, stream, json_path: Optional[str] = None) -> None:
+    _check(lib().etx_autotune(ctx, C.byref(hits), C.byref(out), C.c_void_p(ws_ptr), ws_bytes, C.c_void_p(stream),
+                              json_path.encode() if json_path else None), "etx_autotune")
+
+
+def etx_calibrate(ctx, hits, out, ws_ptr, ws_bytes, stream) -> None:
+    _check(lib().etx_calibrate(ctx, C.byref(hits), C.byref(out), C.c_void_p(ws_ptr), ws_bytes, C.c_void_p(stream)),
+           "etx_calibrate")
+
+
+def etx_set_precision(ctx, precision: int) -> None:
+    _check(lib().etx_set_precision(ctx, precision), "etx_set_precision")
+
+
+def etx_prefilter_set(ctx, params: np.ndarray) -> None:
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    _check(lib().etx_prefilter_set(ctx, p.ctypes.data_as(C.c_void_p), p.size), "etx_prefilter_set")
+
+
+def etx_prefilter_get(ctx) -> np.ndarray:
+    p = np.zeros(ETX_PF_NPARAM, np.float32)
+    _check(lib().etx_prefilter_get(ctx, p.ctypes.data_as(C.c_void_p), p.size), "etx_prefilter_get")
+    return p
+
+
+def etx_prefilter_state(ctx, state: Optional[np.ndarray] = None) -> np.ndarray:
+    if state is None:
+        s = np.zeros(3 * ETX_PF_NPARAM, np.float32)
+        _check(lib().etx_prefilter_state(ctx, s.ctypes.data_as(C.c_void_p), s.size, 0), "etx_prefilter_state")
+        return s
+    s = np.ascontiguousarray(state, dtype=np.float32)
+    _check(lib().etx_prefilter_state(ctx, s.ctypes.data_as(C.c_void_p), s.size, 1), "etx_prefilter_state")
+    return s
+
+
+def etx_prefilter_train_step(ctx, hits, out, labels_ptr: int, lr: float, pos_weight: float, step: int,
+                             loss_ptr: int, ws_ptr: int, ws_bytes: int, stream: int) -> None:
+    _check(lib().etx_prefilter_train_step(ctx, C.byref(hits), C.byref(out), C.c_void_p(labels_ptr), lr, pos_weight,
+                                          step, C.c_void_p(loss_ptr), C.c_void_p(ws_ptr), ws_bytes,
+                                          C.c_void_p(stream)), "etx_prefilter_train_step")
+
+
+# ---------------------------------------------------------------------------
+# configuration and weight blob
+# ---------------------------------------------------------------------------
+
+def make_config(w, precision: int = ETX_FP32, prefilter: int = 0, prefilter_tau: float = 0.0) -> etx_config:
+    return etx_config(w.n_planes, w.r_scale, w.z_scale, w.emb_hidden, w.emb_layers, w.emb_dim, w.radius, w.k_max,
+                      w.plane_window, w.gnn_hidden, w.gnn_steps, w.threshold, precision, prefilter, prefilter_tau)
+
+
+def pack_weights(w, weights: Dict) -> bytes:
+    """The etx.h weight blob: header then float32 layers in the documented order."""
+    hdr = np.array([0x57585445, 1, 3, w.emb_hidden, w.emb_layers, w.emb_dim, w.gnn_hidden, w.gnn_steps], np.int32)
+    order = ["emb", "node_enc", "edge_enc"]
+    for k in range(w.gnn_steps):
+        order += [f"node{k}", f"edge{k}"]
+    order.append("cls")
+    parts = [hdr.tobytes()]
+    for net in order:
+        for W, b in weights[net]:
+            parts.append(np.ascontiguousarray(W, np.float32).tobytes())
+            parts.append(np.ascontiguousarray(b, np.float32).tobytes())
+    return b"".join(parts)
+
+
+# ---------------------------------------------------------------------------
+# torch-owned buffers around one context
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Batch:
+    n_events: int
+    n_hits: int
+    hit_off: "object"
+    x: "object"
+    y: "object"
+    z: "object"
+    plane: "object"
+
+
+def to_device(batch: Dict[str, np.ndarray], device="cuda") -> Batch:
+    import torch
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(device)
+    return Batch(len(batch["hit_off"]) - 1, int(batch["hit_off"][-1]), t(batch["hit_off"], torch.int64),
+                 t(batch["x"], torch.float32), t(batch["y"], torch.float32), t(batch["z"], torch.float32),
+                 t(batch["plane"], torch.int32))
+
+
+class Pipeline:
+    """One context plus torch-allocated outputs and workspace for a batch shape."""
+
+    def __init__(self, w, weights: Dict, device: int = 0, precision: int = ETX_FP32, prefilter: int = 0,
+                 prefilter_tau: float = 0.0):
+        self.w = w
+        self.cfg = make_config(w, precision, prefilter, prefilter_tau)
+        self.ctx = etx_create(self.cfg, pack_weights(w, weights), device)
+        self.device = device
+        self._shape = None
+
+    def close(self):
+        if self.ctx:
+            etx_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def hits_struct(self, b: Batch) -> etx_hits:
+        return etx_hits(b.n_events, b.n_hits, b.hit_off.data_ptr(), b.x.data_ptr(), b.y.data_ptr(), b.z.data_ptr(),
+                        b.plane.data_ptr())
+
+    def allocate(self, b: Batch, edge_capacity: Optional[int] = None):
+        import torch
+        cap = b.n_hits * self.w.k_max if edge_capacity is None else edge_capacity
+        shape = (b.n_events, b.n_hits, cap)
+        if self._shape != shape:
+            dev = torch.device("cuda", self.device)
+            self.src = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+            self.dst = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+            self.score = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+            self.edge_off = torch.empty(b.n_events + 1, dtype=torch.int64, device=dev)
+            self.labels = torch.empty(max(b.n_hits, 1), dtype=torch.int32, device=dev)
+            self.status = torch.zeros(2, dtype=torch.int64, device=dev)
+            nbytes = etx_workspace_size(self.ctx, b.n_events, b.n_hits, cap)
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+            self.ws_ptr = (self.ws.data_ptr() + 255) & ~255
+            self.ws_bytes = nbytes
+            self.cap = cap
+            self._shape = shape
+        return etx_out(self.cap, self.src.data_ptr(), self.dst.data_ptr(), self.score.data_ptr(),
+                       self.edge_off.data_ptr(), self.labels.data_ptr(), self.status.data_ptr())
+
+    def run(self, b: Batch, edge_capacity: Optional[int] = None, stream=None):
+        import torch
+        out = self.allocate(b, edge_capacity)
+        s = torch.cuda.current_stream(self.device) if stream is None else stream
+        etx_run(self.ctx, self.hits_struct(b), out, self.ws_ptr, self.ws_bytes, s.cuda_stream)
+        return out
+
+    def view(self, b: Batch, which: int, dtype, shape=None):
+        """A tensor over one internal workspace buffer (etx_workspace_view)."""
+        import torch
+        off, nbytes = etx_workspace_view(self.ctx, b.n_events, b.n_hits, self.cap, which)
+        base = self.ws_ptr - self.ws.data_ptr()
+        t = self.ws[base + off: base + off + nbytes].view(dtype)
+        return t if shape is None else t.reshape(shape)
+
+    def results(self, b: Batch) -> Dict[str, np.ndarray]:
+        """Synchronise and copy the outputs of the last run to the host."""
+        import torch
+        torch.cuda.synchronize(self.device)
+        st = self.status.cpu().numpy()
+        if st[0] != ETX_OK:
+            raise EtxError(int(st[0]), f"device status (edges needed {int(st[1])})")
+        eo = self.edge_off.cpu().numpy()
+        E = int(eo[-1])
+        return dict(edge_off=eo, src=self.src[:E].cpu().numpy(), dst=self.dst[:E].cpu().numpy(),
+                    score=self.score[:E].cpu().numpy(), labels=self.labels[:b.n_hits].cpu().numpy())
