@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Events/s of the GNN track-finding hot path on one MI355X.
+
+One step = one pass of the whole path (features, embedding MLP, radius graph,
+interaction network, score cut, components) over one batch of synthetic
+events already resident in HBM.  The default workload is the full-size plain
+FP32 batch: 1000 events, 26 planes at z in [-290, 750] mm, Poisson(200)
+tracks per event (~2500 hits incl. 5 % noise), embedding 3-128-128-12, radius
+0.12, at most 64 neighbours, interaction network hidden 64 with 8 steps,
+random Xavier weights.
+
+Prints one JSON line with the throughput, the roofline of the dominant kernel
+(timed live with HIP events on the stream the kernels run on) and the FP64
+CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--events", type=int, default=None, help="override the number of events")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
+    ap.add_argument("--graph", type=int, default=0, help="replay the batch as one captured HIP graph")
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--cpu-threads", type=int, default=None)
+    ap.add_argument("--profile-stages", type=int, default=1)
+    return ap.parse_args()
+
+
+def stage_roofline(stage, ms_total, launches, n_edges, n_hits, H, dtype):
+    """Algorithmic work per launch of a stage and its roofline."""
+    if launches == 0 or ms_total <= 0:
+        return None
+    t = ms_total / launches * 1e-3          # seconds per launch
+    if stage in ("edge_step", "edge_step_final"):
+        # edge net: Linear(3H->H) + Linear(H->H) per edge; the last step adds the classifier Linear(H->H)+Linear(H->1)
+        flops = n_edges * (8 * H * H + (2 * H * H + 2 * H if stage == "edge_step_final" else 0))
+        achieved = flops / t / 1e12
+        peak = PEAK_TFLOPS[dtype]
+        return dict(bound="mfma", achieved=achieved, peak=peak, unit="TFLOP/s", frac=achieved / peak,
+                    units_per_launch=n_edges, per_unit=f"{8 * H * H} flop/edge")
+    if stage == "node_step":
+        flops = n_hits * (2 * 3 * H * H + 2 * H * H + 2 * 2 * H * H)
+        achieved = flops / t / 1e12
+        peak = PEAK_TFLOPS[dtype]
+        return dict(bound="mfma", achieved=achieved, peak=peak, unit="TFLOP/s", frac=achieved / peak,
+                    units_per_launch=n_hits, per_unit=f"{12 * H * H} flop/hit")
+    if stage == "segsum":
+        # each edge encoding read once, one 4-byte CSC index per edge, both sums written
+        es = 4
+        nbytes = n_edges * (H * es + 4) + n_hits * (2 * H * 4 + 16)
+        achieved = nbytes / t / 1e9
+        return dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s", frac=achieved / PEAK_HBM_GBS,
+                    units_per_launch=n_edges, per_unit=f"{H * es + 4} B/edge + {2 * H * 4 + 16} B/hit")
+    return None
+
+
+def cpu_baseline(w, weights, batch, threads):
+    from oracle import oracle as O
+    O.lib()
+    n = min(threads, len(batch["hit_off"]) - 1)
+    t0 = time.perf_counter()
+    O.run_batch(batch, w, weights, events=list(range(n)), threads=threads)
+    dt = time.perf_counter() - t0
+    return dict(value=n / dt, unit="events/s", cores=threads, kind="oracle",
+                sample=f"first {n} events of the same batch, one oracle thread per event ({dt:.1f} s wall)")
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} (WORLD_SIZE {world}) is not supported: "
+              "events are independent, so a multi-GPU run would split the batch by events with no exchange.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2508_07423_amd import etx, synth
+
+    w = synth.WORKLOADS[args.workload]
+    n_events = args.events or w.n_events
+    prec = {"fp32": etx.ETX_FP32, "bf16": etx.ETX_BF16, "fp8": etx.ETX_FP8_E4M3}[args.precision]
+    dtype = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8"}[args.precision]
+    t_gen = time.perf_counter()
+    batch = synth.generate_batch(w, n_events)
+    weights = synth.xavier_weights(w)
+    print(f"[bench] workload {w.name}: {n_events} events, {int(batch['hit_off'][-1])} hits "
+          f"(generated in {time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
+
+    p = etx.Pipeline(w, weights, precision=prec)
+    b = etx.to_device(batch)
+    stream = torch.cuda.Stream()
+    if prec != etx.ETX_FP32:
+        with torch.cuda.stream(stream):
+            out = p.allocate(b)
+            etx.etx_calibrate(p.ctx, p.hits_struct(b), out, p.ws_ptr, p.ws_bytes, stream.cuda_stream)
+    if args.graph:
+        etx.etx_set_option(p.ctx, etx.ETX_OPT_USE_GRAPH, 1)
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            p.run(b, stream=stream)
+        stream.synchronize()
+        res = p.results(b)
+        n_edges = int(res["edge_off"][-1])
+        print(f"[bench] warmup done: {n_edges} edges ({n_edges / b.n_hits:.1f}/hit), "
+              f"kept {(res['score'] >= 0.5).mean():.3f}", file=sys.stderr, flush=True)
+        if args.profile_stages and not args.graph:
+            etx.etx_set_option(p.ctx, etx.ETX_OPT_PROFILE, 1)
+            etx.etx_profile_reset(p.ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            p.run(b, stream=stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    st = p.status.cpu().numpy()
+    if st[0] != etx.ETX_OK:
+        raise SystemExit(f"device status {st[0]} ({etx.etx_status_str(int(st[0]))})")
+    dt = t1 - t0
+    value = n_events * args.steps / dt
+    stages = {}
+    roof = None
+    if args.profile_stages and not args.graph:
+        prof = etx.etx_profile_read(p.ctx)
+        etx.etx_set_option(p.ctx, etx.ETX_OPT_PROFILE, 0)
+        stages = {k: dict(ms=round(v[0] / args.steps, 3), launches=v[1]) for k, v in prof.items() if v[1] > 0}
+        gnn = {k: v for k, v in prof.items() if k in ("edge_step", "edge_step_final", "segsum", "node_step")}
+        dom = max(gnn, key=lambda k: gnn[k][0])
+        roof = stage_roofline(dom, gnn[dom][0], gnn[dom][1], n_edges, b.n_hits, w.gnn_hidden, dtype)
+        if roof is not None:
+            roof = dict(kernel=dom, **{k: (round(v, 4) if isinstance(v, float) else v) for k, v in roof.items()},
+                        traffic=None)
+        print(f"[bench] stages (ms/step): " + ", ".join(f"{k} {v['ms']}" for k, v in stages.items()),
+              file=sys.stderr, flush=True)
+    cpu = None
+    if args.cpu_baseline:
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        print(f"[bench] timing the FP64 oracle on {threads} events with {threads} threads", file=sys.stderr,
+              flush=True)
+        cpu = cpu_baseline(w, weights, batch, threads)
+    line = {
+        "metric": "events/s (GNN track finding, 1 GPU) at fixed track efficiency vs plain FP32",
+        "value": round(value, 2),
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic (seeded straight-track events, random Xavier weights)",
+        "config": {
+            "workload": f"{w.name}: {n_events} events, {w.n_planes} planes, tracks {w.tracks[0]}({w.tracks[1]}), "
+                        f"emb 3-{w.emb_hidden}x{w.emb_layers}-{w.emb_dim}, radius {w.radius}, k {w.k_max}, "
+                        f"IN hidden {w.gnn_hidden} x {w.gnn_steps} steps, {args.precision}"
+                        + (", hip graph" if args.graph else ""),
+            "events": n_events, "hits": int(b.n_hits), "edges": n_edges,
+        },
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "stages_ms_per_step": stages,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

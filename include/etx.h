@@ -144,10 +144,20 @@ typedef enum {
   ETX_OPT_EDGE_WG_PER_CU = 1,/* persistent workgroups per CU of the edge kernels (1..8) */
   ETX_OPT_NODE_WG_PER_CU = 2,/* persistent workgroups per CU of the node kernels (1..8) */
   ETX_OPT_RADIUS_LDS = 3,    /* largest candidate window staged in LDS (0..512); larger windows read HBM */
-  ETX_OPT_SEGSUM_UNROLL = 4  /* edge rows in flight per wave in the segmented sums: 1, 2, 4 or 8 */
+  ETX_OPT_SEGSUM_UNROLL = 4, /* edge rows in flight per wave in the segmented sums: 1, 2, 4 or 8 */
+  ETX_OPT_PROFILE = 5        /* 1: time every stage of eager runs with HIP events on the run's stream */
 } etx_option;
 etx_status etx_set_option(etx_ctx* ctx, int32_t key, int64_t value);
 etx_status etx_get_option(const etx_ctx* ctx, int32_t key, int64_t* value);
+
+/* Stage timing: with ETX_OPT_PROFILE set, every eager etx_run records a pair of
+ * HIP events around each stage on its stream.  etx_profile_read waits for the
+ * recorded events, adds their durations to running totals per stage (indices
+ * 0..n_stages-1, names from etx_stage_name) and returns the totals and launch
+ * counts; etx_profile_reset clears them. */
+etx_status etx_profile_read(etx_ctx* ctx, int32_t n_stages, double* total_ms, int64_t* launches);
+etx_status etx_profile_reset(etx_ctx* ctx);
+const char* etx_stage_name(int32_t stage);   /* "" for an unknown stage */
 
 /* Try each candidate launch schedule on this batch, keep the fastest, and
  * append the choice to `json_path` (may be NULL).  Synchronises the stream. */

@@ -267,32 +267,60 @@ int set_kernel_attributes() {
   return done;
 }
 
+static const char* kStageNames[] = {"init",      "validate",   "bucket",      "embed",       "radius_count",
+                                     "scan",      "radius_emit", "prefilter",  "csc",         "node_encode",
+                                     "edge_encode", "segsum",    "node_step",   "edge_step",   "edge_step_final",
+                                     "compact",   "union_find"};
+constexpr int kNumStages = sizeof(kStageNames) / sizeof(kStageNames[0]);
+
+// Record a pair of HIP events around one stage on the stage's stream.
+struct StageTimer {
+  etx_ctx* ctx;
+  hipStream_t s;
+  int idx = -1;
+  StageTimer(const RunArgs& a, int stage) : ctx(const_cast<etx_ctx*>(a.ctx)), s(a.stream) {
+    if (!ctx->profile) return;
+    if (ctx->n_marks == ctx->marks.size()) {
+      etx_ctx::Mark m{stage, nullptr, nullptr};
+      if (hipEventCreate(&m.start) != hipSuccess || hipEventCreate(&m.end) != hipSuccess) return;
+      ctx->marks.push_back(m);
+    }
+    idx = (int)ctx->n_marks++;
+    ctx->marks[idx].stage = stage;
+    hipEventRecord(ctx->marks[idx].start, s);
+  }
+  ~StageTimer() {
+    if (idx >= 0) hipEventRecord(ctx->marks[idx].end, s);
+  }
+};
+
 // The stage sequence of one batch.
 static hipError_t enqueue_pipeline(const RunArgs& a) {
   hipError_t err;
-#define STEP(x)                              \
-  do {                                       \
+#define STEP(stage, x)                         \
+  do {                                         \
+    StageTimer timer_(a, stage);               \
     if ((err = (x)) != hipSuccess) return err; \
   } while (0)
   const etx_config& c = a.ctx->cfg;
-  STEP(launch_init_status(a));
-  STEP(launch_validate(a));
-  STEP(launch_bucket(a));
-  STEP(launch_embed(a));
-  STEP(launch_radius(a, false));
-  STEP(launch_scan_counts(a));
-  STEP(launch_radius(a, true));
-  if (c.prefilter) STEP(launch_prefilter_infer(a));
-  STEP(launch_csc(a));
-  STEP(launch_node_encode(a));
-  STEP(launch_edge_encode(a));
+  STEP(0, launch_init_status(a));
+  STEP(1, launch_validate(a));
+  STEP(2, launch_bucket(a));
+  STEP(3, launch_embed(a));
+  STEP(4, launch_radius(a, false));
+  STEP(5, launch_scan_counts(a));
+  STEP(6, launch_radius(a, true));
+  if (c.prefilter) STEP(7, launch_prefilter_infer(a));
+  STEP(8, launch_csc(a));
+  STEP(9, launch_node_encode(a));
+  STEP(10, launch_edge_encode(a));
   for (int k = 0; k < c.gnn_steps; ++k) {
-    STEP(launch_segsum(a));
-    STEP(launch_node_step(a, k));
-    STEP(launch_edge_step(a, k, k + 1 == c.gnn_steps));
+    STEP(11, launch_segsum(a));
+    STEP(12, launch_node_step(a, k));
+    STEP(k + 1 == c.gnn_steps ? 14 : 13, launch_edge_step(a, k, k + 1 == c.gnn_steps));
   }
-  STEP(launch_compact(a));
-  STEP(launch_union_find(a));
+  STEP(15, launch_compact(a));
+  STEP(16, launch_union_find(a));
 #undef STEP
   return hipSuccess;
 }
@@ -392,6 +420,10 @@ etx_status etx_destroy(etx_ctx* ctx) {
   if (!ctx) return ETX_ERR_INVALID_ARG;
   hipSetDevice(ctx->device);
   clear_graphs(ctx);
+  for (auto& m : ctx->marks) {
+    hipEventDestroy(m.start);
+    hipEventDestroy(m.end);
+  }
   if (ctx->dev_w) hipFree(ctx->dev_w);
   if (ctx->dev_wq) hipFree(ctx->dev_wq);
   if (ctx->dev_scales) hipFree(ctx->dev_scales);
@@ -452,9 +484,46 @@ etx_status etx_set_option(etx_ctx* ctx, int32_t key, int64_t value) {
       if (value != 1 && value != 2 && value != 4 && value != 8) return ETX_ERR_INVALID_ARG;
       ctx->segsum_unroll = (int)value;
       break;
+    case ETX_OPT_PROFILE:
+      if (value != 0 && value != 1) return ETX_ERR_INVALID_ARG;
+      ctx->profile = (int)value;
+      return ETX_OK;
     default: return ETX_ERR_INVALID_ARG;
   }
   if (key != ETX_OPT_USE_GRAPH) clear_graphs(ctx);
+  return ETX_OK;
+}
+
+const char* etx_stage_name(int32_t stage) {
+  return (stage >= 0 && stage < kNumStages) ? kStageNames[stage] : "";
+}
+
+etx_status etx_profile_read(etx_ctx* ctx, int32_t n_stages, double* total_ms, int64_t* launches) {
+  if (!ctx || !total_ms || !launches || n_stages < 0) return ETX_ERR_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return ETX_ERR_HIP;
+  for (size_t i = 0; i < ctx->n_marks; ++i) {
+    const etx_ctx::Mark& m = ctx->marks[i];
+    if (hipEventSynchronize(m.end) != hipSuccess) return ETX_ERR_HIP;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, m.start, m.end) != hipSuccess) return ETX_ERR_HIP;
+    ctx->stage_ms[m.stage] += ms;
+    ctx->stage_launches[m.stage] += 1;
+  }
+  ctx->n_marks = 0;
+  for (int i = 0; i < n_stages; ++i) {
+    total_ms[i] = i < kNumStages ? ctx->stage_ms[i] : 0.0;
+    launches[i] = i < kNumStages ? ctx->stage_launches[i] : 0;
+  }
+  return ETX_OK;
+}
+
+etx_status etx_profile_reset(etx_ctx* ctx) {
+  if (!ctx) return ETX_ERR_INVALID_ARG;
+  ctx->n_marks = 0;
+  for (int i = 0; i < 32; ++i) {
+    ctx->stage_ms[i] = 0;
+    ctx->stage_launches[i] = 0;
+  }
   return ETX_OK;
 }
 
@@ -466,6 +535,7 @@ etx_status etx_get_option(const etx_ctx* ctx, int32_t key, int64_t* value) {
     case ETX_OPT_NODE_WG_PER_CU: *value = ctx->node_wg_per_cu; break;
     case ETX_OPT_RADIUS_LDS: *value = ctx->radius_lds; break;
     case ETX_OPT_SEGSUM_UNROLL: *value = ctx->segsum_unroll; break;
+    case ETX_OPT_PROFILE: *value = ctx->profile; break;
     default: return ETX_ERR_INVALID_ARG;
   }
   return ETX_OK;
@@ -500,7 +570,10 @@ etx_status etx_run(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void* ws, s
   if (it == ctx->graphs.end()) {
     hipStream_t s = a.stream;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return ETX_ERR_HIP;
+    const int prof = ctx->profile;
+    ctx->profile = 0;
     hipError_t e1 = enqueue_pipeline(a);
+    ctx->profile = prof;
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(s, &g);
     if (e1 != hipSuccess || e2 != hipSuccess || !g) {

@@ -80,6 +80,13 @@ struct etx_ctx {
   int segsum_unroll = 4;
   int use_graph = 0;
   std::map<etx::GraphKey, hipGraphExec_t> graphs;
+  // stage timing with HIP events (ETX_OPT_PROFILE)
+  int profile = 0;
+  struct Mark { int stage; hipEvent_t start, end; };
+  std::vector<Mark> marks;
+  size_t n_marks = 0;
+  double stage_ms[32] = {};
+  int64_t stage_launches[32] = {};
 };
 
 namespace etx {

@@ -26,7 +26,8 @@ ETX_PF_NPARAM = 6 * 32 + 32 + 32 * 32 + 32 + 32 + 1
 (ETX_VIEW_EMBEDDING, ETX_VIEW_BUCKET, ETX_VIEW_PLANE_OFF, ETX_VIEW_ROW_PTR, ETX_VIEW_COL_PTR, ETX_VIEW_CSC_EDGE,
  ETX_VIEW_NODE_H, ETX_VIEW_KEPT_EDGE, ETX_VIEW_KEPT_COUNT, ETX_VIEW_CALIB, ETX_VIEW_PF_KEEP) = range(11)
 (ETX_OPT_USE_GRAPH, ETX_OPT_EDGE_WG_PER_CU, ETX_OPT_NODE_WG_PER_CU, ETX_OPT_RADIUS_LDS,
- ETX_OPT_SEGSUM_UNROLL) = range(5)
+ ETX_OPT_SEGSUM_UNROLL, ETX_OPT_PROFILE) = range(6)
+N_STAGES = 17
 
 
 class etx_config(C.Structure):
@@ -74,6 +75,8 @@ def lib():
             "etx_prefilter_train_step": [P, C.POINTER(etx_hits), C.POINTER(etx_out), P, C.c_float, C.c_float, i64, P,
                                          P, sz, P],
             "etx_prefilter_state": [P, P, i64, i32],
+            "etx_profile_read": [P, i32, P, P],
+            "etx_profile_reset": [P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -81,6 +84,8 @@ def lib():
             f.restype = C.c_int
         L.etx_status_str.argtypes = [C.c_int]
         L.etx_status_str.restype = C.c_char_p
+        L.etx_stage_name.argtypes = [C.c_int32]
+        L.etx_stage_name.restype = C.c_char_p
         L.etx_last_error.argtypes = []
         L.etx_last_error.restype = C.c_char_p
         _lib = L
@@ -90,7 +95,8 @@ def lib():
 EXPORTED = ["etx_create", "etx_destroy", "etx_weight_blob_size", "etx_workspace_size", "etx_run",
             "etx_workspace_view", "etx_set_option", "etx_get_option", "etx_autotune", "etx_calibrate",
             "etx_set_precision", "etx_prefilter_set", "etx_prefilter_get", "etx_prefilter_train_step",
-            "etx_prefilter_state", "etx_status_str", "etx_last_error"]
+            "etx_prefilter_state", "etx_status_str", "etx_last_error", "etx_profile_read", "etx_profile_reset",
+            "etx_stage_name"]
 
 
 class EtxError(RuntimeError):
@@ -198,6 +204,22 @@ def etx_prefilter_train_step(ctx, hits, out, labels_ptr: int, lr: float, pos_wei
     _check(lib().etx_prefilter_train_step(ctx, C.byref(hits), C.byref(out), C.c_void_p(labels_ptr), lr, pos_weight,
                                           step, C.c_void_p(loss_ptr), C.c_void_p(ws_ptr), ws_bytes,
                                           C.c_void_p(stream)), "etx_prefilter_train_step")
+
+
+def etx_stage_name(stage: int) -> str:
+    return lib().etx_stage_name(stage).decode()
+
+
+def etx_profile_read(ctx) -> Dict[str, tuple]:
+    ms = np.zeros(N_STAGES, np.float64)
+    n = np.zeros(N_STAGES, np.int64)
+    _check(lib().etx_profile_read(ctx, N_STAGES, ms.ctypes.data_as(C.c_void_p), n.ctypes.data_as(C.c_void_p)),
+           "etx_profile_read")
+    return {etx_stage_name(i): (float(ms[i]), int(n[i])) for i in range(N_STAGES)}
+
+
+def etx_profile_reset(ctx) -> None:
+    _check(lib().etx_profile_reset(ctx), "etx_profile_reset")
 
 
 # ---------------------------------------------------------------------------
