@@ -66,11 +66,11 @@ WsLayout ws_layout(const etx_ctx* ctx, int64_t n_events, int64_t n_hits, int64_t
 
 // Permute a row-major [K][M] weight for the column layout (tile.hpp); M padded to Mpad.
 static void perm_f32(const float* W, int K, int M, int Mpad, float* out) {
-  for (int mb = 0; mb < Mpad / 32; ++mb)
-    for (int t = 0; t < K / 2; ++t)
+  for (int mb = 0; mb < Mpad / 16; ++mb)
+    for (int t = 0; t < K / 4; ++t)
       for (int lane = 0; lane < 64; ++lane) {
-        int row = phi(t, lane / 32), col = 32 * mb + lane % 32;
-        out[((size_t)mb * (K / 2) + t) * 64 + lane] = col < M ? W[(size_t)row * M + col] : 0.f;
+        int row = phi(t, lane / 16), col = 16 * mb + lane % 16;
+        out[((size_t)mb * (K / 4) + t) * 64 + lane] = col < M ? W[(size_t)row * M + col] : 0.f;
       }
 }
 
@@ -185,7 +185,7 @@ static etx_status build_segments(etx_ctx* ctx, const std::vector<BlobLayer>& Ls)
       std::memcpy(p + s.bh(l), L.b, sizeof(float) * W);
     }
     const BlobLayer& lo = Ls[li++];
-    perm_f32(lo.W, W, c.emb_dim, 32, p + s.wo());
+    perm_f32(lo.W, W, c.emb_dim, 16, p + s.wo());
     std::memcpy(p + s.bo(), lo.b, sizeof(float) * c.emb_dim);
   }
   const BlobLayer ne1 = Ls[li++], ne2 = Ls[li++], ee1 = Ls[li++], ee2 = Ls[li++];

@@ -37,10 +37,10 @@ __global__ __launch_bounds__(256) void k_embed(EmbedArgs A) {
   stage(w, A.seg, A.seg_floats);
   __syncthreads();
   const SegEmb S{W, A.layers};
-  const int lane = lane_id(), h = lane >> 5, wave = threadIdx.x >> 6;
-  const int64_t ntiles = (A.n_hits + kTile - 1) / kTile;
+  const int lane = lane_id(), g = lane_group(), wave = threadIdx.x >> 6;
+  const int64_t ntiles = (A.n_hits + kCols - 1) / kCols;
   for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
-    const int64_t col = tile * kTile + (lane & 31);
+    const int64_t col = tile * kCols + (lane & 15);
     const bool valid = col < A.n_hits;
     float u0 = 0.f, u1 = 0.f, u2 = 0.f;
     if (valid) {
@@ -49,39 +49,35 @@ __global__ __launch_bounds__(256) void k_embed(EmbedArgs A) {
       u1 = atan2f(yy, xx) * 0.318309886183790672f;   // 1/pi
       u2 = zz * A.inv_z;
     }
-    float a[W / 2];
+    float a[W / 4];
     const float* w1 = w + S.w1();
     const float* b1 = w + S.b1();
 #pragma unroll
-    for (int r = 0; r < W / 2; ++r) {
-      const int f = phi(r, h);
+    for (int r = 0; r < W / 4; ++r) {
+      const int f = phi(r, g);
       float acc = u0 * w1[f];
       acc = fmaf(u1, w1[W + f], acc);
       acc = fmaf(u2, w1[2 * W + f], acc);
       a[r] = fmaxf(acc + b1[f], 0.f);
     }
     for (int l = 1; l < A.layers; ++l) {
-      float acc[W / 2];
+      float acc[W / 4];
       bias_cols<W>(acc, w + S.bh(l));
       if (A.calib) {
         float m = 0.f;
 #pragma unroll
-        for (int r = 0; r < W / 2; ++r) m = fmaxf(m, fabsf(a[r]));
+        for (int r = 0; r < W / 4; ++r) m = fmaxf(m, fabsf(a[r]));
         if (valid) atomic_amax(A.calib + CAL_EMB_IN + l, m);
       }
-      mfma_f32<W, W / 32>(acc, a, w + S.wh(l));
+      mfma_f32<W, W / 16>(acc, a, w + S.wh(l));
 #pragma unroll
-      for (int r = 0; r < W / 2; ++r) a[r] = fmaxf(acc[r], 0.f);
+      for (int r = 0; r < W / 4; ++r) a[r] = fmaxf(acc[r], 0.f);
     }
-    float o[16];
-    bias_cols<32>(o, w + S.bo());
+    float o[4];
+    bias_cols<16>(o, w + S.bo());
     mfma_f32<W, 1>(o, a, w + S.wo());
-    // features 0..15 live in registers 0..7 of both halves
-    if (valid) {
-      float* row = A.emb + col * kDpad;
-      *reinterpret_cast<float4*>(row + 4 * h) = make_float4(o[0], o[1], o[2], o[3]);
-      *reinterpret_cast<float4*>(row + 8 + 4 * h) = make_float4(o[4], o[5], o[6], o[7]);
-    }
+    // features 4g .. 4g+3 of the 16 padded outputs
+    if (valid) *reinterpret_cast<float4*>(A.emb + col * kDpad + 4 * g) = make_float4(o[0], o[1], o[2], o[3]);
   }
 }
 
@@ -105,7 +101,7 @@ hipError_t launch_embed(const RunArgs& a) {
   const int W = c->cfg.emb_hidden;
   A.seg_floats = SegEmb{W, A.layers}.size();
   size_t lds = sizeof(float) * A.seg_floats;
-  int64_t tiles = (A.n_hits + kTile - 1) / kTile;
+  int64_t tiles = (A.n_hits + kCols - 1) / kCols;
   unsigned grid = (unsigned)std::min<int64_t>((tiles + 3) / 4, (int64_t)c->n_cu * 2);
   switch (W) {
     case 32: hipLaunchKernelGGL(k_embed<32>, dim3(grid), dim3(256), lds, a.stream, A); break;

@@ -65,16 +65,16 @@ struct GnnArgs {
 // node encoder (+ edge-encoder source/target products)
 // --------------------------------------------------------------------------
 template <int H>
-__global__ __launch_bounds__(256) void k_node_encode(GnnArgs A) {
+__global__ __launch_bounds__(1024) void k_node_encode(GnnArgs A) {
   if (A.status[0] != 0) return;
   extern __shared__ float w[];
   stage(w, A.seg, A.seg_floats);
   __syncthreads();
   constexpr SegNodeEnc S{H};
-  const int lane = lane_id(), h = lane >> 5, wave = threadIdx.x >> 6;
-  const int64_t ntiles = (A.n_hits + kTile - 1) / kTile;
-  for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
-    const int64_t col = tile * kTile + (lane & 31);
+  const int lane = lane_id(), g = lane_group(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int64_t ntiles = (A.n_hits + kCols - 1) / kCols;
+  for (int64_t tile = (int64_t)blockIdx.x * nw + wave; tile < ntiles; tile += (int64_t)gridDim.x * nw) {
+    const int64_t col = tile * kCols + (lane & 15);
     const bool valid = col < A.n_hits;
     float v0 = 0.f, v1 = 0.f, v2 = 0.f;
     if (valid) {
@@ -82,33 +82,33 @@ __global__ __launch_bounds__(256) void k_node_encode(GnnArgs A) {
       v1 = A.y[col] * A.inv_r;
       v2 = A.z[col] * A.inv_z;
     }
-    float a[H / 2];
+    float a[H / 4];
     const float* w1 = w + S.w1();
     const float* b1 = w + S.b1();
 #pragma unroll
-    for (int r = 0; r < H / 2; ++r) {
-      const int f = phi(r, h);
+    for (int r = 0; r < H / 4; ++r) {
+      const int f = phi(r, g);
       float acc = v0 * w1[f];
       acc = fmaf(v1, w1[H + f], acc);
       acc = fmaf(v2, w1[2 * H + f], acc);
       a[r] = acc + b1[f];
     }
     ln_relu<H>(a);
-    observe<H / 2>(A.calib, CAL_NE_L2, a, valid);
-    float hh[H / 2];
+    observe<H / 4>(A.calib, CAL_NE_L2, a, valid);
+    float hh[H / 4];
     bias_cols<H>(hh, w + S.b2());
-    mfma_f32<H, H / 32>(hh, a, w + S.w2());
+    mfma_f32<H, H / 16>(hh, a, w + S.w2());
     ln_relu<H>(hh);
     store_cols<H>(A.h + col * H, hh, valid);
-    observe<H / 2>(A.calib, CAL_H0, hh, valid);
-    float q[H / 2];
+    observe<H / 4>(A.calib, CAL_H0, hh, valid);
+    float q[H / 4];
 #pragma unroll
-    for (int r = 0; r < H / 2; ++r) q[r] = 0.f;
-    mfma_f32<H, H / 32>(q, hh, w + S.ws());
+    for (int r = 0; r < H / 4; ++r) q[r] = 0.f;
+    mfma_f32<H, H / 16>(q, hh, w + S.ws());
     store_cols<H>(A.ps + col * H, q, valid);
 #pragma unroll
-    for (int r = 0; r < H / 2; ++r) q[r] = 0.f;
-    mfma_f32<H, H / 32>(q, hh, w + S.wd());
+    for (int r = 0; r < H / 4; ++r) q[r] = 0.f;
+    mfma_f32<H, H / 16>(q, hh, w + S.wd());
     store_cols<H>(A.pd + col * H, q, valid);
   }
 }
@@ -117,30 +117,30 @@ __global__ __launch_bounds__(256) void k_node_encode(GnnArgs A) {
 // edge encoder
 // --------------------------------------------------------------------------
 template <int H>
-__global__ __launch_bounds__(256) void k_edge_encode(GnnArgs A) {
+__global__ __launch_bounds__(512) void k_edge_encode(GnnArgs A) {
   if (A.status[0] != 0) return;
   extern __shared__ float w[];
   stage(w, A.seg, A.seg_floats);
   __syncthreads();
   constexpr SegEdgeEnc S{H};
-  const int lane = lane_id(), wave = threadIdx.x >> 6;
+  const int lane = lane_id(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int64_t E = A.row_ptr[A.n_hits];
-  const int64_t ntiles = (E + kTile - 1) / kTile;
-  for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
-    const int64_t col = tile * kTile + (lane & 31);
+  const int64_t ntiles = (E + kCols - 1) / kCols;
+  for (int64_t tile = (int64_t)blockIdx.x * nw + wave; tile < ntiles; tile += (int64_t)gridDim.x * nw) {
+    const int64_t col = tile * kCols + (lane & 15);
     const bool valid = col < E;
     const int s = valid ? A.src[col] : 0, d = valid ? A.dst[col] : 0;
-    float a[H / 2];
+    float a[H / 4];
     bias_cols<H>(a, w + S.b1());
     add_cols<H>(a, A.ps + (int64_t)s * H, valid);
     add_cols<H>(a, A.pd + (int64_t)d * H, valid);
     ln_relu<H>(a);
-    observe<H / 2>(A.calib, CAL_EE_L2, a, valid);
-    float o[H / 2];
+    observe<H / 4>(A.calib, CAL_EE_L2, a, valid);
+    float o[H / 4];
     bias_cols<H>(o, w + S.b2());
-    mfma_f32<H, H / 32>(o, a, w + S.w2());
+    mfma_f32<H, H / 16>(o, a, w + S.w2());
     ln_relu<H>(o);
-    observe<H / 2>(A.calib, CAL_E, o, valid);
+    observe<H / 4>(A.calib, CAL_E, o, valid);
     store_cols<H>(A.e + col * H, o, valid);
   }
 }
@@ -198,43 +198,43 @@ __global__ __launch_bounds__(256) void k_segsum(GnnArgs A) {
 // node update k (+ edge net k source/target products)
 // --------------------------------------------------------------------------
 template <int H>
-__global__ __launch_bounds__(256) void k_node_step(GnnArgs A) {
+__global__ __launch_bounds__(1024) void k_node_step(GnnArgs A) {
   if (A.status[0] != 0) return;
   extern __shared__ float w[];
   stage(w, A.seg, A.seg_floats);
   __syncthreads();
   constexpr SegNode S{H};
-  const int lane = lane_id(), wave = threadIdx.x >> 6;
-  const int64_t ntiles = (A.n_hits + kTile - 1) / kTile;
-  for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
-    const int64_t col = tile * kTile + (lane & 31);
+  const int lane = lane_id(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int64_t ntiles = (A.n_hits + kCols - 1) / kCols;
+  for (int64_t tile = (int64_t)blockIdx.x * nw + wave; tile < ntiles; tile += (int64_t)gridDim.x * nw) {
+    const int64_t col = tile * kCols + (lane & 15);
     const bool valid = col < A.n_hits;
-    float x[3 * H / 2];
+    float x[3 * H / 4];
     load_cols<H>(x, A.h + col * H, valid);
-    load_cols<H>(x + H / 2, A.msg + col * 2 * H, valid);
-    load_cols<H>(x + H, A.msg + col * 2 * H + H, valid);
-    observe<3 * H / 2>(A.calib, CAL_NN_IN + A.step, x, valid);
-    float a[H / 2];
+    load_cols<H>(x + H / 4, A.msg + col * 2 * H, valid);
+    load_cols<H>(x + H / 2, A.msg + col * 2 * H + H, valid);
+    observe<3 * H / 4>(A.calib, CAL_NN_IN + A.step, x, valid);
+    float a[H / 4];
     bias_cols<H>(a, w + S.b1());
-    mfma_f32<3 * H, H / 32>(a, x, w + S.w1());
+    mfma_f32<3 * H, H / 16>(a, x, w + S.w1());
     ln_relu<H>(a);
-    observe<H / 2>(A.calib, CAL_NN_L2, a, valid);
-    float o[H / 2];
+    observe<H / 4>(A.calib, CAL_NN_L2, a, valid);
+    float o[H / 4];
     bias_cols<H>(o, w + S.b2());
-    mfma_f32<H, H / 32>(o, a, w + S.w2());
+    mfma_f32<H, H / 16>(o, a, w + S.w2());
     ln_relu<H>(o);
 #pragma unroll
-    for (int r = 0; r < H / 2; ++r) o[r] += x[r];
+    for (int r = 0; r < H / 4; ++r) o[r] += x[r];
     store_cols<H>(A.h + col * H, o, valid);
-    observe<H / 2>(A.calib, CAL_H0 + 1 + A.step, o, valid);
-    float q[H / 2];
+    observe<H / 4>(A.calib, CAL_H0 + 1 + A.step, o, valid);
+    float q[H / 4];
 #pragma unroll
-    for (int r = 0; r < H / 2; ++r) q[r] = 0.f;
-    mfma_f32<H, H / 32>(q, o, w + S.ws());
+    for (int r = 0; r < H / 4; ++r) q[r] = 0.f;
+    mfma_f32<H, H / 16>(q, o, w + S.ws());
     store_cols<H>(A.ps + col * H, q, valid);
 #pragma unroll
-    for (int r = 0; r < H / 2; ++r) q[r] = 0.f;
-    mfma_f32<H, H / 32>(q, o, w + S.wd());
+    for (int r = 0; r < H / 4; ++r) q[r] = 0.f;
+    mfma_f32<H, H / 16>(q, o, w + S.wd());
     store_cols<H>(A.pd + col * H, q, valid);
   }
 }
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(256) void k_node_step(GnnArgs A) {
 // edge update k; the last step also runs the classifier and writes scores
 // --------------------------------------------------------------------------
 template <int H, bool FINAL>
-__global__ __launch_bounds__(256) void k_edge_step(GnnArgs A) {
+__global__ __launch_bounds__(512) void k_edge_step(GnnArgs A) {
   if (A.status[0] != 0) return;
   extern __shared__ float w[];
   constexpr SegEdge S{H};
@@ -252,44 +252,44 @@ __global__ __launch_bounds__(256) void k_edge_step(GnnArgs A) {
   if (FINAL) stage(w + S.size(), A.seg2, A.seg2_floats);
   __syncthreads();
   const float* wc = w + S.size();
-  const int lane = lane_id(), h = lane >> 5, wave = threadIdx.x >> 6;
+  const int lane = lane_id(), g = lane_group(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int64_t E = A.row_ptr[A.n_hits];
-  const int64_t ntiles = (E + kTile - 1) / kTile;
-  for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
-    const int64_t col = tile * kTile + (lane & 31);
+  const int64_t ntiles = (E + kCols - 1) / kCols;
+  for (int64_t tile = (int64_t)blockIdx.x * nw + wave; tile < ntiles; tile += (int64_t)gridDim.x * nw) {
+    const int64_t col = tile * kCols + (lane & 15);
     const bool valid = col < E;
     const int s = valid ? A.src[col] : 0, d = valid ? A.dst[col] : 0;
-    float e[H / 2];
+    float e[H / 4];
     load_cols<H>(e, A.e + col * H, valid);
-    float a[H / 2];
+    float a[H / 4];
     bias_cols<H>(a, w + S.b1());
     add_cols<H>(a, A.ps + (int64_t)s * H, valid);
     add_cols<H>(a, A.pd + (int64_t)d * H, valid);
-    mfma_f32<H, H / 32>(a, e, w + S.we());
+    mfma_f32<H, H / 16>(a, e, w + S.we());
     ln_relu<H>(a);
-    observe<H / 2>(A.calib, CAL_EN_L2, a, valid);
-    float o[H / 2];
+    observe<H / 4>(A.calib, CAL_EN_L2, a, valid);
+    float o[H / 4];
     bias_cols<H>(o, w + S.b2());
-    mfma_f32<H, H / 32>(o, a, w + S.w2());
+    mfma_f32<H, H / 16>(o, a, w + S.w2());
     ln_relu<H>(o);
 #pragma unroll
-    for (int r = 0; r < H / 2; ++r) o[r] += e[r];
-    observe<H / 2>(A.calib, CAL_E + 1 + A.step, o, valid);
+    for (int r = 0; r < H / 4; ++r) o[r] += e[r];
+    observe<H / 4>(A.calib, CAL_E + 1 + A.step, o, valid);
     if (!FINAL) {
       store_cols<H>(A.e + col * H, o, valid);
     } else {
-      observe<H / 2>(A.calib, CAL_CLS_IN, o, valid);
-      float c[H / 2];
+      observe<H / 4>(A.calib, CAL_CLS_IN, o, valid);
+      float c[H / 4];
       bias_cols<H>(c, wc + C.b1());
-      mfma_f32<H, H / 32>(c, o, wc + C.w1());
+      mfma_f32<H, H / 16>(c, o, wc + C.w1());
       ln_relu<H>(c);
-      observe<H / 2>(A.calib, CAL_CLS_L2, c, valid);
+      observe<H / 4>(A.calib, CAL_CLS_L2, c, valid);
       float dot = 0.f;
 #pragma unroll
-      for (int r = 0; r < H / 2; ++r) dot = fmaf(c[r], wc[C.w2() + phi(r, h)], dot);
-      dot += __shfl_xor(dot, 32);
+      for (int r = 0; r < H / 4; ++r) dot = fmaf(c[r], wc[C.w2() + phi(r, g)], dot);
+      dot = col_sum(dot);
       const float logit = dot + wc[C.b2()];
-      if (valid && h == 0) A.score[col] = 1.0f / (1.0f + expf(-logit));
+      if (valid && g == 0) A.score[col] = 1.0f / (1.0f + expf(-logit));
     }
   }
 }
@@ -326,9 +326,13 @@ static GnnArgs gnn_args(const RunArgs& a) {
   return A;
 }
 
+constexpr int kNodeThreads = 1024;   // 16 waves: the node kernels hold up to 98 KiB of weights in LDS
+constexpr int kEdgeThreads = 512;
+
 static unsigned node_grid(const RunArgs& a, int per_cu) {
-  int64_t tiles = (a.hits.n_hits + kTile - 1) / kTile;
-  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, (int64_t)a.ctx->n_cu * per_cu));
+  int64_t tiles = (a.hits.n_hits + kCols - 1) / kCols;
+  int64_t waves = kNodeThreads / 64;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles + waves - 1) / waves, (int64_t)a.ctx->n_cu * per_cu));
 }
 
 #define DISPATCH_H(H_, ...)                    \
@@ -346,7 +350,7 @@ hipError_t launch_node_encode(const RunArgs& a) {
   A.seg_floats = SegNodeEnc{Hh}.size();
   size_t lds = sizeof(float) * A.seg_floats;
   unsigned grid = node_grid(a, a.ctx->node_wg_per_cu);
-  DISPATCH_H(Hh, hipLaunchKernelGGL(k_node_encode<H>, dim3(grid), dim3(256), lds, a.stream, A));
+  DISPATCH_H(Hh, hipLaunchKernelGGL(k_node_encode<H>, dim3(grid), dim3(kNodeThreads), lds, a.stream, A));
   return hipGetLastError();
 }
 
@@ -358,7 +362,7 @@ hipError_t launch_edge_encode(const RunArgs& a) {
   A.seg_floats = SegEdgeEnc{Hh}.size();
   size_t lds = sizeof(float) * A.seg_floats;
   unsigned grid = (unsigned)(a.ctx->n_cu * a.ctx->edge_wg_per_cu);
-  DISPATCH_H(Hh, hipLaunchKernelGGL(k_edge_encode<H>, dim3(grid), dim3(256), lds, a.stream, A));
+  DISPATCH_H(Hh, hipLaunchKernelGGL(k_edge_encode<H>, dim3(grid), dim3(kEdgeThreads), lds, a.stream, A));
   return hipGetLastError();
 }
 
@@ -388,7 +392,7 @@ hipError_t launch_node_step(const RunArgs& a, int k) {
   A.step = k;
   size_t lds = sizeof(float) * A.seg_floats;
   unsigned grid = node_grid(a, a.ctx->node_wg_per_cu);
-  DISPATCH_H(Hh, hipLaunchKernelGGL(k_node_step<H>, dim3(grid), dim3(256), lds, a.stream, A));
+  DISPATCH_H(Hh, hipLaunchKernelGGL(k_node_step<H>, dim3(grid), dim3(kNodeThreads), lds, a.stream, A));
   return hipGetLastError();
 }
 
@@ -404,9 +408,9 @@ hipError_t launch_edge_step(const RunArgs& a, int k, bool final_step) {
   size_t lds = sizeof(float) * (A.seg_floats + (final_step ? A.seg2_floats : 0));
   unsigned grid = (unsigned)(a.ctx->n_cu * a.ctx->edge_wg_per_cu);
   if (final_step) {
-    DISPATCH_H(Hh, hipLaunchKernelGGL((k_edge_step<H, true>), dim3(grid), dim3(256), lds, a.stream, A));
+    DISPATCH_H(Hh, hipLaunchKernelGGL((k_edge_step<H, true>), dim3(grid), dim3(kEdgeThreads), lds, a.stream, A));
   } else {
-    DISPATCH_H(Hh, hipLaunchKernelGGL((k_edge_step<H, false>), dim3(grid), dim3(256), lds, a.stream, A));
+    DISPATCH_H(Hh, hipLaunchKernelGGL((k_edge_step<H, false>), dim3(grid), dim3(kEdgeThreads), lds, a.stream, A));
   }
   return hipGetLastError();
 }

@@ -75,7 +75,7 @@ struct etx_ctx {
   bool pf_set = false;
   // tuning
   int edge_wg_per_cu = 2;
-  int node_wg_per_cu = 2;
+  int node_wg_per_cu = 1;
   int radius_lds = etx::kRadiusLdsMax;
   int segsum_unroll = 4;
   int use_graph = 0;

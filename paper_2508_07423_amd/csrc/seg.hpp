@@ -8,7 +8,7 @@
 
 namespace etx {
 
-// embedding: nat(3,W) b1[W] | per extra hidden layer: perm(W,W) b[W] | perm(W,32) bo[32]
+// embedding: nat(3,W) b1[W] | per extra hidden layer: perm(W,W) b[W] | perm(W,16) bo[16]
 struct SegEmb {
   int W, L;
   __host__ __device__ constexpr int w1() const { return 0; }
@@ -16,8 +16,8 @@ struct SegEmb {
   __host__ __device__ constexpr int wh(int l) const { return 4 * W + (l - 1) * (W * W + W); }   // l = 1..L-1
   __host__ __device__ constexpr int bh(int l) const { return wh(l) + W * W; }
   __host__ __device__ constexpr int wo() const { return 4 * W + (L - 1) * (W * W + W); }
-  __host__ __device__ constexpr int bo() const { return wo() + 32 * W; }
-  __host__ __device__ constexpr int size() const { return bo() + 32; }
+  __host__ __device__ constexpr int bo() const { return wo() + 16 * W; }
+  __host__ __device__ constexpr int size() const { return bo() + 16; }
 };
 
 // node encoder: nat(3,H) b1[H] perm(H,H) b2[H] | edge-encoder products perm(H,H) (source) perm(H,H) (target)
