@@ -143,7 +143,7 @@ typedef enum {
   ETX_OPT_USE_GRAPH = 0,     /* 1: etx_run captures the batch into a HIP graph and replays it */
   ETX_OPT_EDGE_WG_PER_CU = 1,/* persistent workgroups per CU of the edge kernels (1..8) */
   ETX_OPT_NODE_WG_PER_CU = 2,/* persistent workgroups per CU of the node kernels (1..8) */
-  ETX_OPT_RADIUS_LDS = 3,    /* largest candidate window staged in LDS (0..512); larger windows read HBM */
+  ETX_OPT_RADIUS_LDS = 3,    /* 1: stage and sort candidate windows in LDS when they fit; 0: always read HBM */
   ETX_OPT_SEGSUM_UNROLL = 4, /* edge rows in flight per wave in the segmented sums: 1, 2, 4 or 8 */
   ETX_OPT_PROFILE = 5        /* 1: time every stage of eager runs with HIP events on the run's stream */
 } etx_option;

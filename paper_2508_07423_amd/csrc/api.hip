@@ -17,6 +17,7 @@ namespace etx {
 int embed_attributes(size_t max_lds);
 int gnn_attributes(size_t max_lds);
 int graph_attributes(size_t max_lds);
+int radius_attributes(size_t max_lds);
 int prefilter_attributes(size_t max_lds);
 hipError_t build_low_precision(etx_ctx* ctx);
 
@@ -263,7 +264,7 @@ int set_kernel_attributes() {
   // below the 160 KiB per workgroup so that static LDS still fits beside it
   size_t max_lds = 150 * 1024;
   done = embed_attributes(max_lds) | gnn_attributes(max_lds) | graph_attributes(max_lds) |
-         prefilter_attributes(max_lds);
+         radius_attributes(max_lds) | prefilter_attributes(max_lds);
   return done;
 }
 
@@ -477,7 +478,7 @@ etx_status etx_set_option(etx_ctx* ctx, int32_t key, int64_t value) {
       ctx->node_wg_per_cu = (int)value;
       break;
     case ETX_OPT_RADIUS_LDS:
-      if (value < 0 || value > kRadiusLdsMax) return ETX_ERR_INVALID_ARG;
+      if (value != 0 && value != 1) return ETX_ERR_INVALID_ARG;
       ctx->radius_lds = (int)value;
       break;
     case ETX_OPT_SEGSUM_UNROLL:

@@ -1,6 +1,6 @@
 // Integer and graph kernels of the hot path: input validation, plane
-// bucketing, the fixed-radius graph, offsets, the CSC permutation, edge
-// compaction after the score cut, and union-find components.
+// bucketing, edge offsets, the CSC permutation, edge compaction after the
+// score cut, and union-find components.
 #include "internal.hpp"
 
 namespace etx {
@@ -109,184 +109,6 @@ __global__ __launch_bounds__(256) void k_bucket(const int64_t* __restrict__ hit_
     int p = plane[a + i];
     int pos = cnt[p * 256 + t]++;
     bucket[a + pos] = (int32_t)(a + i);
-  }
-}
-
-// --------------------------------------------------------------------------
-// fixed-radius graph
-// --------------------------------------------------------------------------
-
-struct RadiusArgs {
-  const int64_t* hit_off;
-  const int32_t* bucket;
-  const int32_t* plane_off;
-  const float* emb;        // [n_hits][16]
-  int n_planes, window, k_max, lds_max;
-  float r2;
-  int32_t* cnt;            // count pass output
-  const int64_t* row_ptr;  // emit pass input
-  int32_t* src;
-  int32_t* dst;
-  const int64_t* status;
-};
-
-__device__ inline float dist2(const float (&s)[kDpad], const float* __restrict__ c) {
-  float d2 = 0.f;
-#pragma unroll
-  for (int k = 0; k < kDpad; k += 4) {
-    float4 v = *reinterpret_cast<const float4*>(c + k);
-    float t0 = s[k] - v.x, t1 = s[k + 1] - v.y, t2 = s[k + 2] - v.z, t3 = s[k + 3] - v.w;
-    d2 = fmaf(t0, t0, d2);
-    d2 = fmaf(t1, t1, d2);
-    d2 = fmaf(t2, t2, d2);
-    d2 = fmaf(t3, t3, d2);
-  }
-  return d2;
-}
-
-// One workgroup per (event, source plane); each wave takes one source hit at
-// a time and scans the candidate window (planes p+1 .. p+window), which the
-// workgroup stages in LDS when it fits.
-template <bool EMIT>
-__global__ __launch_bounds__(256) void k_radius(RadiusArgs A) {
-  if (A.status[0] != 0) return;
-  extern __shared__ float lds[];
-  float* cemb = lds;                                         // [lds_max][16]
-  int* cj = reinterpret_cast<int*>(cemb + A.lds_max * kDpad);  // [lds_max]
-  float* dcache = reinterpret_cast<float*>(cj + A.lds_max);   // [4][lds_max]
-  int* sel = reinterpret_cast<int*>(dcache + 4 * A.lds_max);  // [4][64]
-
-  const int P = A.n_planes;
-  const int ev = blockIdx.x / P, p = blockIdx.x % P;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t a = A.hit_off[ev];
-  const int32_t* po = A.plane_off + (int64_t)ev * (P + 1);
-  const int s0 = po[p], s1 = po[p + 1];
-  const int pw = min(p + A.window, P - 1);
-  const int w0 = po[min(p + 1, P)], w1 = po[pw + 1] > w0 ? po[pw + 1] : w0;
-  const int nwin = (p + 1 < P) ? (w1 - w0) : 0;
-  const int nsrc = s1 - s0;
-  if (nsrc == 0) return;
-  const bool use_lds = nwin <= A.lds_max;
-  const int32_t* wb = A.bucket + a + w0;
-  if (use_lds) {
-    for (int c = threadIdx.x; c < nwin; c += blockDim.x) {
-      int j = wb[c];
-      cj[c] = j;
-      const float4* s = reinterpret_cast<const float4*>(A.emb + (int64_t)j * kDpad);
-      float4* d = reinterpret_cast<float4*>(cemb + c * kDpad);
-#pragma unroll
-      for (int q = 0; q < kDpad / 4; ++q) d[q] = s[q];
-    }
-    __syncthreads();
-  }
-  float* dc = dcache + wave * A.lds_max;
-  int* sl = sel + wave * 64;
-  const unsigned r2bits = __float_as_uint(A.r2);
-
-  for (int s = wave; s < nsrc; s += 4) {
-    const int32_t i = A.bucket[a + s0 + s];
-    float se[kDpad];
-#pragma unroll
-    for (int q = 0; q < kDpad; q += 4) {
-      float4 v = *reinterpret_cast<const float4*>(A.emb + (int64_t)i * kDpad + q);
-      se[q] = v.x; se[q + 1] = v.y; se[q + 2] = v.z; se[q + 3] = v.w;
-    }
-    auto cand_d2 = [&](int c) -> float {
-      if (use_lds) return dist2(se, cemb + c * kDpad);
-      return dist2(se, A.emb + (int64_t)wb[c] * kDpad);
-    };
-    auto cand_j = [&](int c) -> int { return use_lds ? cj[c] : wb[c]; };
-    // pass 1: candidates inside the radius
-    int n = 0;
-    for (int c0 = 0; c0 < nwin; c0 += 64) {
-      int c = c0 + lane;
-      bool in = false;
-      if (c < nwin) {
-        float d2 = cand_d2(c);
-        if (use_lds) dc[c] = d2;
-        in = d2 < A.r2;
-      }
-      n += __popcll(__ballot(in));
-    }
-    if (!EMIT) {
-      if (lane == 0) A.cnt[i] = min(n, A.k_max);
-      continue;
-    }
-    if (n == 0) continue;
-    auto get_d2 = [&](int c) -> float { return use_lds ? dc[c] : cand_d2(c); };
-    // count of inside candidates with key below a bound (wave-uniform result)
-    auto count_if = [&](auto pred) -> int {
-      int m = 0;
-      for (int c0 = 0; c0 < nwin; c0 += 64) {
-        int c = c0 + lane;
-        bool b = false;
-        if (c < nwin) {
-          float d2 = get_d2(c);
-          b = d2 < A.r2 && pred(d2, c);
-        }
-        m += __popcll(__ballot(b));
-      }
-      return m;
-    };
-    bool capped = n > A.k_max;
-    float T = A.r2;
-    int Jt = 0x7fffffff;
-    if (capped) {
-      // smallest T (as float bits) with #{d2 <= T} >= k_max: the k-th smallest d2
-      unsigned lo = 0, hi = r2bits - 1u;
-      while (lo < hi) {
-        unsigned mid = lo + (hi - lo) / 2;
-        float fm = __uint_as_float(mid);
-        int m = count_if([&](float d2, int) { return d2 <= fm; });
-        if (m >= A.k_max) hi = mid; else lo = mid + 1;
-      }
-      T = __uint_as_float(lo);
-      int less = count_if([&](float d2, int) { return d2 < T; });
-      int need = A.k_max - less;
-      int eq = count_if([&](float d2, int) { return d2 == T; });
-      if (eq > need) {
-        // ties at the boundary distance: keep the `need` smallest hit indices
-        int jlo = (int)a, jhi = (int)(a + A.hit_off[ev + 1] - a - 1);
-        while (jlo < jhi) {
-          int mid = jlo + (jhi - jlo) / 2;
-          int m = count_if([&](float d2, int c) { return d2 == T && cand_j(c) <= mid; });
-          if (m >= need) jhi = mid; else jlo = mid + 1;
-        }
-        Jt = jlo;
-      }
-    }
-    // compact the selected targets into the wave's list (at most k_max <= 64)
-    int ns = 0;
-    for (int c0 = 0; c0 < nwin; c0 += 64) {
-      int c = c0 + lane;
-      bool b = false;
-      int j = 0;
-      if (c < nwin) {
-        float d2 = get_d2(c);
-        j = cand_j(c);
-        b = d2 < A.r2 && (!capped || d2 < T || (d2 == T && j <= Jt));
-      }
-      uint64_t m = __ballot(b);
-      if (b) {
-        int pre = __popcll(m & ((1ull << lane) - 1ull));
-        if (ns + pre < 64) sl[ns + pre] = j;
-      }
-      ns += __popcll(m);
-    }
-    // never write past the row the count pass reserved
-    ns = min(ns, (int)(A.row_ptr[i + 1] - A.row_ptr[i]));
-    wave_sync();
-    // order by target index and write the row
-    if (lane < ns) {
-      int my = sl[lane];
-      int rank = 0;
-      for (int q = 0; q < ns; ++q) rank += sl[q] < my;
-      int64_t pos = A.row_ptr[i] + rank;
-      A.src[pos] = i;
-      A.dst[pos] = my;
-    }
-    wave_sync();
   }
 }
 
@@ -527,33 +349,6 @@ hipError_t launch_bucket(const RunArgs& a) {
   return hipGetLastError();
 }
 
-hipError_t launch_radius(const RunArgs& a, bool emit) {
-  if (a.hits.n_events == 0) return hipSuccess;
-  const etx_config& c = a.ctx->cfg;
-  RadiusArgs A;
-  A.hit_off = a.hits.hit_off;
-  A.bucket = WS(a, bucket, int32_t);
-  A.plane_off = WS(a, plane_off, int32_t);
-  A.emb = WS(a, emb, float);
-  A.n_planes = c.n_planes;
-  A.window = c.plane_window;
-  A.k_max = c.k_max;
-  A.lds_max = a.ctx->radius_lds;
-  A.r2 = c.radius * c.radius;
-  A.cnt = WS(a, cnt, int32_t);
-  A.row_ptr = WS(a, row_ptr, int64_t);
-  A.src = a.out.src;
-  A.dst = a.out.dst;
-  A.status = a.out.status;
-  size_t lds = (size_t)A.lds_max * (kDpad * 4 + 4 + 16) + 4 * 64 * 4;
-  dim3 grid((unsigned)(a.hits.n_events * c.n_planes));
-  if (emit)
-    hipLaunchKernelGGL(k_radius<true>, grid, dim3(256), lds, a.stream, A);
-  else
-    hipLaunchKernelGGL(k_radius<false>, grid, dim3(256), lds, a.stream, A);
-  return hipGetLastError();
-}
-
 hipError_t launch_scan_counts(const RunArgs& a) {
   const int64_t n = a.hits.n_hits;
   const int64_t nb = a.L.n_scan_blocks;
@@ -599,8 +394,6 @@ hipError_t launch_union_find(const RunArgs& a) {
 int graph_attributes(size_t max_lds) {
   int bad = 0;
   bad |= hipFuncSetAttribute(reinterpret_cast<const void*>(k_bucket), hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) != hipSuccess;
-  bad |= hipFuncSetAttribute(reinterpret_cast<const void*>(k_radius<true>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) != hipSuccess;
-  bad |= hipFuncSetAttribute(reinterpret_cast<const void*>(k_radius<false>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) != hipSuccess;
   return bad;
 }
 

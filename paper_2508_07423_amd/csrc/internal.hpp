@@ -15,7 +15,6 @@ namespace etx {
 constexpr int kTile = 32;          // columns (hits or edges) per wave tile
 constexpr int kDpad = 16;          // padded embedding width in HBM
 constexpr int kScanBlock = 1024;   // elements per block of the device-wide scan
-constexpr int kRadiusLdsMax = 512; // candidate embeddings staged per radius workgroup
 
 // Calibration observer slots (absolute maxima of quantised activations).
 enum CalibSlot {
@@ -76,7 +75,7 @@ struct etx_ctx {
   // tuning
   int edge_wg_per_cu = 2;
   int node_wg_per_cu = 1;
-  int radius_lds = etx::kRadiusLdsMax;
+  int radius_lds = 1;
   int segsum_unroll = 4;
   int use_graph = 0;
   std::map<etx::GraphKey, hipGraphExec_t> graphs;

@@ -1,0 +1,396 @@
+// Fixed-radius graph in embedding space (thesis ch. 8, squared-distance
+// equation; ch. 9 "k-NN Implementation"): a hit on plane p connects to hits on
+// planes p+1 .. p+window whose squared embedding distance is below r^2,
+// keeping at most k_max per source: the k_max smallest by (d^2, target index).
+//
+// One workgroup per (event, source plane).  The candidate window (hits of the
+// next planes) is staged in LDS and sorted along its widest embedding axis, a
+// one-dimensional cell list: a source only scans candidates whose coordinate
+// on that axis lies within r of its own, which is exact because a distance
+// below r bounds every coordinate difference.  Each wave handles one source
+// at a time: in-radius candidates are compacted into an LDS list with a wave
+// ballot and prefix count, the k_max boundary is found by a bisection on the
+// float bits of d^2 (ties at the boundary resolved by the target index), and
+// the kept targets are ranked by index and written as one CSR row.  Windows
+// larger than the LDS capacity are read from HBM without the sort.
+#include "internal.hpp"
+
+namespace etx {
+
+namespace {
+
+constexpr int kRadiusThreads = 512;     // 8 waves
+constexpr int kRadiusWaves = kRadiusThreads / 64;
+constexpr int kList = 256;              // per-wave list of in-radius candidates
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct RadiusArgs {
+  const int64_t* hit_off;
+  const int32_t* bucket;
+  const int32_t* plane_off;
+  const float* emb;        // [n_hits][kDpad]
+  int n_planes, window, k_max, dim;
+  int stage_window;        // 0: always read the window from HBM
+  float r2, r;
+  int32_t* cnt;            // count pass output
+  const int64_t* row_ptr;  // emit pass input
+  int32_t* src;
+  int32_t* dst;
+  const int64_t* status;
+};
+
+template <int DP>
+__device__ inline float dist2(const float (&s)[DP], const float* c) {
+  float d2 = 0.f;
+#pragma unroll
+  for (int k = 0; k < DP; k += 4) {
+    float4 v = *reinterpret_cast<const float4*>(c + k);
+    float t0 = s[k] - v.x, t1 = s[k + 1] - v.y, t2 = s[k + 2] - v.z, t3 = s[k + 3] - v.w;
+    d2 = fmaf(t0, t0, d2);
+    d2 = fmaf(t1, t1, d2);
+    d2 = fmaf(t2, t2, d2);
+    d2 = fmaf(t3, t3, d2);
+  }
+  return d2;
+}
+
+// LDS capacity of the staged window for a padded embedding width DP.
+template <int DP>
+struct RadiusLds {
+  static constexpr int cap = DP <= 8 ? 1024 : 512;
+  static constexpr size_t bytes = (size_t)cap * (DP * 4 + 12) + kRadiusWaves * (kList * 8 + 64 * 4) + 64;
+};
+
+template <bool EMIT, int DP>
+__global__ __launch_bounds__(kRadiusThreads) void k_radius(RadiusArgs A) {
+  if (A.status[0] != 0) return;
+  constexpr int CAP = RadiusLds<DP>::cap;
+  extern __shared__ float lds[];
+  float* cemb = lds;                                              // [CAP][DP]
+  int* cj = reinterpret_cast<int*>(cemb + CAP * DP);              // [CAP] target hit index
+  float* skey = reinterpret_cast<float*>(cj + CAP);               // [CAP] sorted axis coordinate
+  int* sidx = reinterpret_cast<int*>(skey + CAP);                 // [CAP] slot of the sorted entry
+  float* ld2 = reinterpret_cast<float*>(sidx + CAP);              // [waves][kList]
+  int* lj = reinterpret_cast<int*>(ld2 + kRadiusWaves * kList);   // [waves][kList]
+  int* sel = lj + kRadiusWaves * kList;                           // [waves][64]
+  int* misc = sel + kRadiusWaves * 64;                            // [16]
+
+  const int P = A.n_planes;
+  const int ev = blockIdx.x / P, p = blockIdx.x % P;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t a = A.hit_off[ev];
+  const int32_t* po = A.plane_off + (int64_t)ev * (P + 1);
+  const int s0 = po[p], s1 = po[p + 1];
+  const int nsrc = s1 - s0;
+  if (nsrc == 0) return;
+  int nwin = 0, w0 = s1;
+  if (p + 1 < P) {
+    w0 = po[p + 1];
+    nwin = po[min(p + A.window, P - 1) + 1] - w0;
+  }
+  const int32_t* wb = A.bucket + a + w0;
+  const bool staged = A.stage_window && nwin <= CAP;
+  int npow = 1;
+  while (npow < nwin) npow <<= 1;
+  if (staged && nwin > 0) {
+    // stage the window and find its widest axis
+    float lo[DP], hi[DP];
+#pragma unroll
+    for (int k = 0; k < DP; ++k) {
+      lo[k] = INFINITY;
+      hi[k] = -INFINITY;
+    }
+    for (int c = threadIdx.x; c < nwin; c += kRadiusThreads) {
+      int j = wb[c];
+      cj[c] = j;
+#pragma unroll
+      for (int q = 0; q < DP; q += 4) {
+        float4 v = *reinterpret_cast<const float4*>(A.emb + (int64_t)j * kDpad + q);
+        *reinterpret_cast<float4*>(cemb + c * DP + q) = v;
+        lo[q] = fminf(lo[q], v.x); hi[q] = fmaxf(hi[q], v.x);
+        lo[q + 1] = fminf(lo[q + 1], v.y); hi[q + 1] = fmaxf(hi[q + 1], v.y);
+        lo[q + 2] = fminf(lo[q + 2], v.z); hi[q + 2] = fmaxf(hi[q + 2], v.z);
+        lo[q + 3] = fminf(lo[q + 3], v.w); hi[q + 3] = fmaxf(hi[q + 3], v.w);
+      }
+    }
+    // block max of each axis range through the per-wave lists (reused as scratch)
+#pragma unroll
+    for (int k = 0; k < DP; ++k) {
+      float l = lo[k], h = hi[k];
+      for (int d = 32; d > 0; d >>= 1) {
+        l = fminf(l, __shfl_xor(l, d));
+        h = fmaxf(h, __shfl_xor(h, d));
+      }
+      if (lane == 0) {
+        ld2[wave * DP + k] = l;
+        ld2[kRadiusWaves * DP + wave * DP + k] = h;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int best = 0;
+      float bw = -1.f;
+      for (int k = 0; k < A.dim; ++k) {
+        float l = INFINITY, h = -INFINITY;
+        for (int w = 0; w < kRadiusWaves; ++w) {
+          l = fminf(l, ld2[w * DP + k]);
+          h = fmaxf(h, ld2[kRadiusWaves * DP + w * DP + k]);
+        }
+        if (h - l > bw) {
+          bw = h - l;
+          best = k;
+        }
+      }
+      misc[0] = best;
+    }
+    __syncthreads();
+    const int axis = misc[0];
+    for (int c = threadIdx.x; c < npow; c += kRadiusThreads) {
+      skey[c] = c < nwin ? cemb[c * DP + axis] : INFINITY;
+      sidx[c] = c;
+    }
+    __syncthreads();
+    // bitonic sort of (key, slot) by key, then slot
+    for (int k = 2; k <= npow; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int i = threadIdx.x; i < npow; i += kRadiusThreads) {
+          int ij = i ^ j;
+          if (ij > i) {
+            float ki = skey[i], kk = skey[ij];
+            int ii = sidx[i], ik = sidx[ij];
+            bool gt = ki > kk || (ki == kk && ii > ik);
+            bool up = (i & k) == 0;
+            if (gt == up) {
+              skey[i] = kk; skey[ij] = ki;
+              sidx[i] = ik; sidx[ij] = ii;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+  const int axis = (staged && nwin > 0) ? misc[0] : 0;
+  float* wl2 = ld2 + wave * kList;
+  int* wlj = lj + wave * kList;
+  int* sl = sel + wave * 64;
+  const unsigned r2bits = __float_as_uint(A.r2);
+
+  for (int s = wave; s < nsrc; s += kRadiusWaves) {
+    const int32_t i = A.bucket[a + s0 + s];
+    float se[DP];
+#pragma unroll
+    for (int q = 0; q < DP; q += 4) {
+      float4 v = *reinterpret_cast<const float4*>(A.emb + (int64_t)i * kDpad + q);
+      se[q] = v.x; se[q + 1] = v.y; se[q + 2] = v.z; se[q + 3] = v.w;
+    }
+    // candidate range [cb, ce)
+    int cb = 0, ce = nwin;
+    if (staged && nwin > 0) {
+      float sa = 0.f;
+#pragma unroll
+      for (int k = 0; k < DP; ++k)
+        if (k == axis) sa = se[k];
+      // a candidate whose axis coordinate differs by more than `reach` cannot be
+      // inside r; the slack covers the rounding of the coordinates and of d^2
+      const float reach = A.r * (1.0f + 1.0f / 65536.0f) + fabsf(sa) * (1.0f / 1048576.0f) + 1e-30f;
+      const float klo = sa - reach, khi = sa + reach;
+      int lo = 0, hi = nwin;       // first key >= klo
+      while (lo < hi) {
+        int m = (lo + hi) >> 1;
+        if (skey[m] < klo) lo = m + 1; else hi = m;
+      }
+      cb = lo;
+      hi = nwin;                   // first key > khi
+      while (lo < hi) {
+        int m = (lo + hi) >> 1;
+        if (skey[m] <= khi) lo = m + 1; else hi = m;
+      }
+      ce = lo;
+    }
+    auto cand = [&](int c, int& j) -> float {
+      if (staged) {
+        const int slot = sidx[c];
+        j = cj[slot];
+        return dist2<DP>(se, cemb + slot * DP);
+      }
+      j = wb[c];
+      return dist2<DP>(se, A.emb + (int64_t)j * kDpad);
+    };
+    // pass 1: in-radius candidates, compacted into the wave's list
+    int n = 0;
+    for (int c0 = cb; c0 < ce; c0 += 64) {
+      const int c = c0 + lane;
+      bool in = false;
+      float d2 = 0.f;
+      int j = 0;
+      if (c < ce) {
+        d2 = cand(c, j);
+        in = d2 < A.r2;
+      }
+      const uint64_t m = __ballot(in);
+      if (EMIT && in) {
+        const int pos = n + __popcll(m & ((1ull << lane) - 1ull));
+        if (pos < kList) {
+          wl2[pos] = d2;
+          wlj[pos] = j;
+        }
+      }
+      n += __popcll(m);
+    }
+    if (!EMIT) {
+      if (lane == 0) A.cnt[i] = min(n, A.k_max);
+      continue;
+    }
+    if (n == 0) continue;
+    wave_sync();
+    const bool listed = n <= kList;
+    // wave-uniform count of in-radius candidates satisfying pred(d2, j)
+    auto count_if = [&](auto pred) -> int {
+      int m = 0;
+      if (listed) {
+        for (int q0 = 0; q0 < n; q0 += 64) {
+          const int q = q0 + lane;
+          const bool b = q < n && pred(wl2[q], wlj[q]);
+          m += __popcll(__ballot(b));
+        }
+      } else {
+        for (int c0 = cb; c0 < ce; c0 += 64) {
+          const int c = c0 + lane;
+          bool b = false;
+          if (c < ce) {
+            int j;
+            const float d2 = cand(c, j);
+            b = d2 < A.r2 && pred(d2, j);
+          }
+          m += __popcll(__ballot(b));
+        }
+      }
+      return m;
+    };
+    const bool capped = n > A.k_max;
+    float T = A.r2;
+    int Jt = 0x7fffffff;
+    if (capped) {
+      // smallest T (as float bits) with #{d2 <= T} >= k_max: the k-th smallest d2
+      unsigned lo = 0, hi = r2bits - 1u;
+      while (lo < hi) {
+        const unsigned mid = lo + (hi - lo) / 2;
+        const float fm = __uint_as_float(mid);
+        const int m = count_if([&](float d2, int) { return d2 <= fm; });
+        if (m >= A.k_max) hi = mid; else lo = mid + 1;
+      }
+      T = __uint_as_float(lo);
+      const int less = count_if([&](float d2, int) { return d2 < T; });
+      const int need = A.k_max - less;
+      const int eq = count_if([&](float d2, int) { return d2 == T; });
+      if (eq > need) {
+        // ties at the boundary distance: keep the `need` smallest hit indices
+        int jlo = (int)a, jhi = (int)(A.hit_off[ev + 1] - 1);
+        while (jlo < jhi) {
+          const int mid = jlo + (jhi - jlo) / 2;
+          const int m = count_if([&](float d2, int j) { return d2 == T && j <= mid; });
+          if (m >= need) jhi = mid; else jlo = mid + 1;
+        }
+        Jt = jlo;
+      }
+    }
+    // compact the kept targets (at most k_max <= 64) into the wave's row buffer
+    int ns = 0;
+    auto keep = [&](float d2, int j) { return d2 < A.r2 && (!capped || d2 < T || (d2 == T && j <= Jt)); };
+    if (listed) {
+      for (int q0 = 0; q0 < n; q0 += 64) {
+        const int q = q0 + lane;
+        const bool b = q < n && keep(wl2[q], wlj[q]);
+        const uint64_t m = __ballot(b);
+        if (b) {
+          const int pos = ns + __popcll(m & ((1ull << lane) - 1ull));
+          if (pos < 64) sl[pos] = wlj[q];
+        }
+        ns += __popcll(m);
+      }
+    } else {
+      for (int c0 = cb; c0 < ce; c0 += 64) {
+        const int c = c0 + lane;
+        bool b = false;
+        int j = 0;
+        if (c < ce) {
+          const float d2 = cand(c, j);
+          b = keep(d2, j);
+        }
+        const uint64_t m = __ballot(b);
+        if (b) {
+          const int pos = ns + __popcll(m & ((1ull << lane) - 1ull));
+          if (pos < 64) sl[pos] = j;
+        }
+        ns += __popcll(m);
+      }
+    }
+    // never write past the row the count pass reserved
+    ns = min(ns, (int)(A.row_ptr[i + 1] - A.row_ptr[i]));
+    wave_sync();
+    if (lane < ns) {
+      const int my = sl[lane];
+      int rank = 0;
+      for (int q = 0; q < ns; ++q) rank += sl[q] < my;
+      const int64_t pos = A.row_ptr[i] + rank;
+      A.src[pos] = i;
+      A.dst[pos] = my;
+    }
+    wave_sync();
+  }
+}
+
+}  // namespace
+
+hipError_t launch_radius(const RunArgs& a, bool emit) {
+  if (a.hits.n_events == 0) return hipSuccess;
+  const etx_config& c = a.ctx->cfg;
+  RadiusArgs A;
+  A.hit_off = a.hits.hit_off;
+  A.bucket = reinterpret_cast<const int32_t*>(a.ws + a.L.bucket);
+  A.plane_off = reinterpret_cast<const int32_t*>(a.ws + a.L.plane_off);
+  A.emb = reinterpret_cast<const float*>(a.ws + a.L.emb);
+  A.n_planes = c.n_planes;
+  A.window = c.plane_window;
+  A.k_max = c.k_max;
+  A.dim = c.emb_dim;
+  A.r = c.radius;
+  A.r2 = c.radius * c.radius;
+  A.cnt = reinterpret_cast<int32_t*>(a.ws + a.L.cnt);
+  A.row_ptr = reinterpret_cast<const int64_t*>(a.ws + a.L.row_ptr);
+  A.src = a.out.src;
+  A.dst = a.out.dst;
+  A.status = a.out.status;
+  dim3 grid((unsigned)(a.hits.n_events * c.n_planes));
+  const bool small = c.emb_dim <= 8;
+  A.stage_window = a.ctx->radius_lds;
+#define LAUNCH_R(E_, D_) \
+  hipLaunchKernelGGL((k_radius<E_, D_>), grid, dim3(kRadiusThreads), RadiusLds<D_>::bytes, a.stream, A)
+  if (small) {
+    if (emit) LAUNCH_R(true, 8); else LAUNCH_R(false, 8);
+  } else {
+    if (emit) LAUNCH_R(true, 16); else LAUNCH_R(false, 16);
+  }
+#undef LAUNCH_R
+  return hipGetLastError();
+}
+
+int radius_attributes(size_t max_lds) {
+  int bad = 0;
+  auto set = [&](const void* f) {
+    bad |= hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) != hipSuccess;
+  };
+  set(reinterpret_cast<const void*>(k_radius<true, 8>));
+  set(reinterpret_cast<const void*>(k_radius<false, 8>));
+  set(reinterpret_cast<const void*>(k_radius<true, 16>));
+  set(reinterpret_cast<const void*>(k_radius<false, 16>));
+  return bad;
+}
+
+}  // namespace etx

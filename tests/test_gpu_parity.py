@@ -156,7 +156,7 @@ def test_radius_global_fallback_and_unroll_identical(c1_run):
         for k in ("src", "dst", "score", "labels", "edge_off"):
             assert np.array_equal(g[k], res[k]), k
     finally:
-        etx.etx_set_option(p.ctx, etx.ETX_OPT_RADIUS_LDS, 512)
+        etx.etx_set_option(p.ctx, etx.ETX_OPT_RADIUS_LDS, 1)
         etx.etx_set_option(p.ctx, etx.ETX_OPT_SEGSUM_UNROLL, 4)
         etx.etx_set_option(p.ctx, etx.ETX_OPT_EDGE_WG_PER_CU, 2)
 
