@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--events", type=int, default=None, help="override the number of events")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--graph", type=int, default=0, help="replay the batch as one captured HIP graph")
+    ap.add_argument("--autotune", type=int, default=0, help="tune the launch schedule on the batch before timing")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-threads", type=int, default=None)
     ap.add_argument("--profile-stages", type=int, default=1)
@@ -108,12 +109,24 @@ def main():
           f"(generated in {time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
 
     p = etx.Pipeline(w, weights, precision=prec)
-    b = etx.to_device(batch)
     stream = torch.cuda.Stream()
-    if prec != etx.ETX_FP32:
+    if prec == etx.ETX_FP8_E4M3:
+        # static calibration on events of a disjoint seed space
+        cal = etx.to_device(synth.generate_batch(w, 20, seed_space=1000 + w.cid))
+        with torch.cuda.stream(stream):
+            p.calibrate(cal, stream=stream)
+        del cal
+    b = etx.to_device(batch)
+    tuned = None
+    if args.autotune:
         with torch.cuda.stream(stream):
             out = p.allocate(b)
-            etx.etx_calibrate(p.ctx, p.hits_struct(b), out, p.ws_ptr, p.ws_bytes, stream.cuda_stream)
+            path = os.path.join(ROOT, "gpurun_out", "autotune.jsonl") if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None
+            etx.etx_autotune(p.ctx, p.hits_struct(b), out, p.ws_ptr, p.ws_bytes, stream.cuda_stream, path)
+        tuned = {k: etx.etx_get_option(p.ctx, v) for k, v in (("edge_wg_per_cu", etx.ETX_OPT_EDGE_WG_PER_CU),
+                                                               ("node_wg_per_cu", etx.ETX_OPT_NODE_WG_PER_CU),
+                                                               ("segsum_unroll", etx.ETX_OPT_SEGSUM_UNROLL))}
+        print(f"[bench] autotuned: {tuned}", file=sys.stderr, flush=True)
     if args.graph:
         etx.etx_set_option(p.ctx, etx.ETX_OPT_USE_GRAPH, 1)
     with torch.cuda.stream(stream):
@@ -176,7 +189,7 @@ def main():
                         f"emb 3-{w.emb_hidden}x{w.emb_layers}-{w.emb_dim}, radius {w.radius}, k {w.k_max}, "
                         f"IN hidden {w.gnn_hidden} x {w.gnn_steps} steps, {args.precision}"
                         + (", hip graph" if args.graph else ""),
-            "events": n_events, "hits": int(b.n_hits), "edges": n_edges,
+            "events": n_events, "hits": int(b.n_hits), "edges": n_edges, "schedule": tuned,
         },
         "roofline": roof,
         "cpu_baseline": cpu,

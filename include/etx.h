@@ -132,7 +132,8 @@ typedef enum {
   ETX_VIEW_KEPT_EDGE = 7,    /* int32 [edge_capacity]: kept edge ids, per event from edge_off[e] */
   ETX_VIEW_KEPT_COUNT = 8,   /* int32 [n_events]: kept edges per event */
   ETX_VIEW_CALIB = 9,        /* float [ETX_N_CALIB]: per-tensor amax (calibration observers) */
-  ETX_VIEW_PF_KEEP = 10      /* uint8 [edge_capacity]: prefilter decision per candidate edge */
+  ETX_VIEW_PF_KEEP = 10,     /* uint8 [edge_capacity]: prefilter decision per candidate edge */
+  ETX_VIEW_PF_GRAD = 11      /* float [ETX_PF_NPARAM + 1]: last prefilter gradient, then the loss */
 } etx_view;
 #define ETX_N_CALIB 64
 etx_status etx_workspace_view(const etx_ctx* ctx, int64_t n_events, int64_t n_hits, int64_t edge_capacity,
@@ -170,8 +171,19 @@ etx_status etx_autotune(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void* 
  * per-tensor scales S = amax / 448 (FP8-E4M3).  Synchronises the stream. */
 etx_status etx_calibrate(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void* ws, size_t ws_bytes,
                          etx_stream stream);
-/* Switch the GEMM operand precision (etx_precision) of an existing context. */
+/* Switch the GEMM operand precision (etx_precision) of an existing context
+ * (all three weight formats are built at etx_create). */
 etx_status etx_set_precision(etx_ctx* ctx, int32_t precision);
+/* Copy the first n (<= 256) per-tensor scales: activation slots 0..63 (0..7
+ * embedding layer inputs; 8 + {0 node-encoder layer-2 input, 1 node
+ * encodings, 2 out-sums, 3 in-sums, 4 edge-encoder layer-2 input, 5 node-net
+ * layer-2 inputs, 6 edge-net layer-2 inputs, 7 + k stored edge encodings e_k}),
+ * weight slots 64..255.  Every scale is a power of two >= amax / 448. */
+etx_status etx_get_scales(const etx_ctx* ctx, float* scales, int32_t n);
+/* Round n device floats through the library's operand format: out = in
+ * rounded to BF16 (nearest even), or scale * E4M3(in / scale) (nearest even,
+ * saturating at +-448); FP32 copies.  Asynchronous on `stream`. */
+etx_status etx_quantize(int32_t precision, const float* in, float* out, int64_t n, float scale, etx_stream stream);
 
 /* Learned edge prefilter: MLP 6 -> 32 -> 32 -> 1 (ReLU) on the candidate-edge
  * features (dx, dy, dz, dr, dphi, embedding distance), normalised by

@@ -22,9 +22,11 @@
  *               component
  *
  * Optional quantisation (thesis ch. 4 "Quantization", symmetric scale
- * x = S x_q): every GEMM operand is replaced by its exactly rounded BF16 or
- * FP8-E4M3 value (after division by its per-tensor scale) before the FP64
- * product.  qmode 0 disables it.
+ * x = S x_q with a per-tensor scale): every GEMM operand is replaced by its
+ * exactly rounded BF16 (qmode 1) or FP8-E4M3 (qmode 2, value / S rounded, then
+ * times S) value before the FP64 product.  Scales are powers of two chosen
+ * from the tensor's absolute maximum (static calibration: the maxima come
+ * from an unquantised run of this oracle).  qmode 0 disables it.
  */
 #include <math.h>
 #include <stdint.h>
@@ -56,15 +58,33 @@ static double round_format(double x, int mbits, int emin, double maxv) {
 double oracle_round_bf16(double x) { return round_format(x, 7, -126, 3.3895313892515355e38); }
 double oracle_round_e4m3(double x) { return round_format(x, 3, -6, 448.0); }
 
-typedef struct {
-  int mode;          /* 0 none, 1 bf16, 2 fp8 e4m3 with per-tensor scales */
-} qctx;
-
-/* quantise a GEMM operand: value -> S * round(value / S) */
+/* quantise a GEMM operand: value -> S * round(value / S) (S = 1 for BF16) */
 static double qv(int mode, double x, double scale) {
   if (mode == 1) return oracle_round_bf16(x);
   if (mode == 2) return scale * oracle_round_e4m3(x / scale);
   return x;
+}
+
+/* Per-tensor scale from an absolute maximum: the power of two at or above
+ * amax / 448, so that amax maps inside the E4M3 range (1 when amax is 0). */
+double oracle_pow2_scale(double amax) {
+  if (!(amax > 0.0)) return 1.0;
+  int e;
+  double f = frexp(amax / 448.0, &e);   /* amax/448 = f 2^e, f in [0.5, 1) */
+  return ldexp(1.0, f == 0.5 ? e - 1 : e);
+}
+
+/* weight scale of a K x M layer */
+static double wscale(const double* W, int64_t n) {
+  double m = 0.0;
+  for (int64_t i = 0; i < n; ++i) m = fabs(W[i]) > m ? fabs(W[i]) : m;
+  return oracle_pow2_scale(m);
+}
+
+static void observe(double* amax, int slot, const double* v, int n) {
+  if (!amax) return;
+  for (int i = 0; i < n; ++i)
+    if (fabs(v[i]) > amax[slot]) amax[slot] = fabs(v[i]);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -100,6 +120,18 @@ static void linear(const double* in, int K, const double* W, const double* b, in
   }
 }
 
+/* Same for an input made of `nb` consecutive blocks of `bk` features, block b
+ * quantised with its own scale s_in[b] (one weight scale for the matrix). */
+static void linear_blocks(const double* in, int nb, int bk, const double* W, const double* b, int M, double* out,
+                          int qmode, const double* s_in, double s_w) {
+  for (int m = 0; m < M; ++m) {
+    double acc = 0.0;
+    for (int k = 0; k < nb * bk; ++k)
+      acc += qv(qmode, in[k], s_in ? s_in[k / bk] : 1.0) * qv(qmode, W[(int64_t)k * M + m], s_w);
+    out[m] = acc + b[m];
+  }
+}
+
 /* LayerNorm over the feature axis (biased variance, eps 1e-5, no affine), then ReLU */
 static void layernorm_relu(double* v, int n) {
   double mean = 0.0;
@@ -120,22 +152,32 @@ static void layernorm_relu(double* v, int n) {
 /* ------------------------------------------------------------------------ */
 
 /* dims[0..n_layers]: widths (dims[0] = 3); params: W0 b0 W1 b1 ...;
- * hidden layers use ReLU, the output layer is linear.  qscale (may be NULL):
- * per layer (input scale, weight scale). */
-void oracle_embed(int64_t n, const double* cyl, int n_layers, const int* dims,
-                  const double* params, double* emb, int qmode, const double* qscale) {
+ * hidden layers use ReLU, the output layer is linear.  With qmode the GEMM
+ * operands of layers l >= 1 are quantised: input with act_scale[l] (FP8),
+ * weights with their per-layer power-of-two scale; the 3-wide first layer is
+ * not.  amax (may be NULL): running max |input| of layer l in amax[l]. */
+void oracle_embed(int64_t n, const double* cyl, int n_layers, const int* dims, const double* params, double* emb,
+                  int qmode, const double* act_scale, double* amax) {
   int maxw = 0;
   for (int l = 0; l <= n_layers; ++l) if (dims[l] > maxw) maxw = dims[l];
   double* a = (double*)malloc(sizeof(double) * maxw);
   double* b = (double*)malloc(sizeof(double) * maxw);
+  double ws[16];
+  {
+    const double* p = params;
+    for (int l = 0; l < n_layers && l < 16; ++l) {
+      ws[l] = wscale(p, (int64_t)dims[l] * dims[l + 1]);
+      p += (int64_t)dims[l] * dims[l + 1] + dims[l + 1];
+    }
+  }
   for (int64_t i = 0; i < n; ++i) {
     for (int k = 0; k < dims[0]; ++k) a[k] = cyl[3 * i + k];
     const double* p = params;
     for (int l = 0; l < n_layers; ++l) {
       int K = dims[l], M = dims[l + 1];
-      double si = qscale ? qscale[2 * l] : 1.0, sw = qscale ? qscale[2 * l + 1] : 1.0;
-      /* the first layer (K = 3 coordinates) is never quantised */
-      linear(a, K, p, p + (int64_t)K * M, M, b, l == 0 ? 0 : qmode, si, sw);
+      if (l > 0) observe(amax, l, a, K);
+      double si = (act_scale && l > 0) ? act_scale[l] : 1.0;
+      linear(a, K, p, p + (int64_t)K * M, M, b, l == 0 ? 0 : qmode, si, ws[l]);
       p += (int64_t)K * M + M;
       if (l + 1 < n_layers)
         for (int m = 0; m < M; ++m) b[m] = b[m] > 0.0 ? b[m] : 0.0;
@@ -241,27 +283,27 @@ void oracle_radius_margins(int64_t n, const int32_t* plane, const double* emb, i
 /* interaction network                                                       */
 /* ------------------------------------------------------------------------ */
 
-/* Two Blocks: Block(x) = ReLU(LN(x W + b)).  p points at W1 b1 W2 b2. */
-static const double* mlp2(const double* in, int K, int H, const double* p, double* tmp, double* out,
-                          int qmode, const double* qs) {
-  linear(in, K, p, p + (int64_t)K * H, H, tmp, qmode, qs ? qs[0] : 1.0, qs ? qs[1] : 1.0);
-  layernorm_relu(tmp, H);
-  p += (int64_t)K * H + H;
-  linear(tmp, H, p, p + (int64_t)H * H, H, out, qmode, qs ? qs[2] : 1.0, qs ? qs[3] : 1.0);
-  layernorm_relu(out, H);
-  return p + (int64_t)H * H + H;
-}
+/* Activation-scale slots of the quantised interaction network (qmode 2) and
+ * of the amax observers; the same tensors are quantised in qmode 1 (BF16,
+ * no scale):
+ *   0 node-encoder layer-2 input      1 node encodings h (every GEMM use)
+ *   2 out-sums mo                     3 in-sums mi
+ *   4 edge-encoder layer-2 input      5 node-net layer-2 inputs
+ *   6 edge-net layer-2 inputs         7 + k: edge encodings e_k, k = 0..S
+ * Edge encodings are stored quantised (e_k <- q(e_k) after the encoder and
+ * after every update) and enter the edge net and the classifier in that form;
+ * the sums are taken in full precision over the stored values; h keeps a full
+ * precision residual copy and is quantised where it enters a GEMM. */
+enum { Q_NE2 = 0, Q_H = 1, Q_MO = 2, Q_MI = 3, Q_EE2 = 4, Q_NN2 = 5, Q_EN2 = 6, Q_E = 7 };
 
 /* Parameter block order: node encoder (3->H->H), edge encoder (2H->H->H),
  * then per step k: node net k (3H->H->H), edge net k (3H->H->H), then the
- * classifier Block(H->H) and Linear(H->1).
- * qscale (NULL unless qmode): 4 scales per MLP2 in the same order, the edge
- * storage scale per step (S entries, qmode 2 stores edge encodings as
- * FP8 with that scale; qmode 1 stores them as BF16), then 4 classifier scales.
- * Edge features are the stored/quantised residual stream in qmode > 0:
- * e <- q(e + f(...)) after every update, q(e0) after the encoder. */
+ * classifier Block(H->H) and Linear(H->1).  Block(x) = ReLU(LN(x W + b)).
+ * qmode 0: plain FP64.  act_scale: [8 + S] slots above (qmode 2).  amax
+ * (may be NULL, [8 + S]): running max |x| of every quantised tensor. */
 void oracle_gnn(int64_t n, const double* cart, int64_t E, const int32_t* src, const int32_t* dst,
-                int H, int S, const double* params, double* logit, int qmode, const double* qscale) {
+                int H, int S, const double* params, double* logit, int qmode, const double* act_scale,
+                double* amax) {
   double* h = (double*)calloc((size_t)n * H + 1, sizeof(double));
   double* e = (double*)calloc((size_t)E * H + 1, sizeof(double));
   double* mo = (double*)calloc((size_t)n * H + 1, sizeof(double));
@@ -269,31 +311,43 @@ void oracle_gnn(int64_t n, const double* cart, int64_t E, const int32_t* src, co
   double* in = (double*)malloc(sizeof(double) * 3 * H);
   double* tmp = (double*)malloc(sizeof(double) * H);
   double* out = (double*)malloc(sizeof(double) * H);
+  const double one[3] = {1.0, 1.0, 1.0};
+#define SC(slot) (act_scale ? act_scale[slot] : 1.0)
+  const int64_t HH = (int64_t)H * H;
   const double* p = params;
-  const double* qs = qscale;
-  const double* qstore = qscale ? qscale + 4 * (2 + 2 * S) : NULL;
 
-  /* node encoder: h0 = MLP(x/R, y/R, z/Z); its first layer stays unquantised */
-  for (int64_t l = 0; l < n; ++l) {
-    linear(cart + 3 * l, 3, p, p + 3 * H, H, tmp, 0, 1.0, 1.0);
-    layernorm_relu(tmp, H);
-    const double* p2 = p + 3 * H + H;
-    linear(tmp, H, p2, p2 + (int64_t)H * H, H, h + l * H, qmode, qs ? qs[2] : 1.0, qs ? qs[3] : 1.0);
-    layernorm_relu(h + l * H, H);
+  /* node encoder: h0 = Block(Block(x/R, y/R, z/Z)); the 3-wide layer is not quantised */
+  {
+    const double *W1 = p, *b1 = p + 3 * H, *W2 = b1 + H, *b2 = W2 + HH;
+    double s2 = wscale(W2, HH);
+    for (int64_t l = 0; l < n; ++l) {
+      linear(cart + 3 * l, 3, W1, b1, H, tmp, 0, 1.0, 1.0);
+      layernorm_relu(tmp, H);
+      observe(amax, Q_NE2, tmp, H);
+      linear(tmp, H, W2, b2, H, h + l * H, qmode, SC(Q_NE2), s2);
+      layernorm_relu(h + l * H, H);
+    }
+    p = b2 + H;
   }
-  p += 3 * H + H + (int64_t)H * H + H;
-  if (qs) qs += 4;
-  /* storage rounding of h (the next GEMM operand) happens inside linear() */
-
-  /* edge encoder: e0_ij = MLP([h_i, h_j]) */
-  for (int64_t t = 0; t < E; ++t) {
-    memcpy(in, h + (int64_t)src[t] * H, sizeof(double) * H);
-    memcpy(in + H, h + (int64_t)dst[t] * H, sizeof(double) * H);
-    mlp2(in, 2 * H, H, p, tmp, e + t * H, qmode, qs);
-    if (qmode) for (int c = 0; c < H; ++c) e[t * H + c] = qv(qmode, e[t * H + c], qstore[0]);
+  /* edge encoder: e0_ij = Block(Block([h_i, h_j])) */
+  {
+    const double *W1 = p, *b1 = p + 2 * HH, *W2 = b1 + H, *b2 = W2 + HH;
+    double s1 = wscale(W1, 2 * HH), s2 = wscale(W2, HH);
+    double sh[2] = {SC(Q_H), SC(Q_H)};
+    for (int64_t l = 0; l < n; ++l) observe(amax, Q_H, h + l * H, H);
+    for (int64_t t = 0; t < E; ++t) {
+      memcpy(in, h + (int64_t)src[t] * H, sizeof(double) * H);
+      memcpy(in + H, h + (int64_t)dst[t] * H, sizeof(double) * H);
+      linear_blocks(in, 2, H, W1, b1, H, tmp, qmode, qmode == 2 ? sh : NULL, s1);
+      layernorm_relu(tmp, H);
+      observe(amax, Q_EE2, tmp, H);
+      linear(tmp, H, W2, b2, H, e + t * H, qmode, SC(Q_EE2), s2);
+      layernorm_relu(e + t * H, H);
+      observe(amax, Q_E + 0, e + t * H, H);
+      if (qmode) for (int c = 0; c < H; ++c) e[t * H + c] = qv(qmode, e[t * H + c], SC(Q_E + 0));
+    }
+    p = b2 + H;
   }
-  p += (int64_t)2 * H * H + H + (int64_t)H * H + H;
-  if (qs) qs += 4;
 
   for (int k = 0; k < S; ++k) {
     /* messages: m_l = [sum_{l->j} e_lj, sum_{i->l} e_il] in edge order */
@@ -304,42 +358,63 @@ void oracle_gnn(int64_t n, const double* cart, int64_t E, const int32_t* src, co
         mo[(int64_t)src[t] * H + c] += e[t * H + c];
         mi[(int64_t)dst[t] * H + c] += e[t * H + c];
       }
-    /* node update with residual: h <- h + MLP_k([h, mo, mi]) */
-    const double* pn = p;
-    for (int64_t l = 0; l < n; ++l) {
-      memcpy(in, h + l * H, sizeof(double) * H);
-      memcpy(in + H, mo + l * H, sizeof(double) * H);
-      memcpy(in + 2 * H, mi + l * H, sizeof(double) * H);
-      mlp2(in, 3 * H, H, pn, tmp, out, qmode, qs);
-      for (int c = 0; c < H; ++c) h[l * H + c] += out[c];
-    }
-    p += (int64_t)3 * H * H + H + (int64_t)H * H + H;
-    if (qs) qs += 4;
-    /* edge update with residual, using the updated h */
-    const double* pe = p;
-    for (int64_t t = 0; t < E; ++t) {
-      memcpy(in, e + t * H, sizeof(double) * H);
-      memcpy(in + H, h + (int64_t)src[t] * H, sizeof(double) * H);
-      memcpy(in + 2 * H, h + (int64_t)dst[t] * H, sizeof(double) * H);
-      mlp2(in, 3 * H, H, pe, tmp, out, qmode, qs);
-      for (int c = 0; c < H; ++c) {
-        double v = e[t * H + c] + out[c];
-        e[t * H + c] = qmode ? qv(qmode, v, qstore[(k + 1 < S) ? k + 1 : k]) : v;
+    /* node update with residual: h <- h + Block(Block([h, mo, mi])) */
+    {
+      const double *W1 = p, *b1 = p + 3 * HH, *W2 = b1 + H, *b2 = W2 + HH;
+      double s1 = wscale(W1, 3 * HH), s2 = wscale(W2, HH);
+      double sb[3] = {SC(Q_H), SC(Q_MO), SC(Q_MI)};
+      for (int64_t l = 0; l < n; ++l) {
+        memcpy(in, h + l * H, sizeof(double) * H);
+        memcpy(in + H, mo + l * H, sizeof(double) * H);
+        memcpy(in + 2 * H, mi + l * H, sizeof(double) * H);
+        observe(amax, Q_H, in, H);
+        observe(amax, Q_MO, in + H, H);
+        observe(amax, Q_MI, in + 2 * H, H);
+        linear_blocks(in, 3, H, W1, b1, H, tmp, qmode, qmode == 2 ? sb : (qmode ? one : NULL), s1);
+        layernorm_relu(tmp, H);
+        observe(amax, Q_NN2, tmp, H);
+        linear(tmp, H, W2, b2, H, out, qmode, SC(Q_NN2), s2);
+        layernorm_relu(out, H);
+        for (int c = 0; c < H; ++c) h[l * H + c] += out[c];
       }
+      p = b2 + H;
     }
-    p += (int64_t)3 * H * H + H + (int64_t)H * H + H;
-    if (qs) qs += 4;
+    /* edge update with residual, using the updated h */
+    {
+      const double *W1 = p, *b1 = p + 3 * HH, *W2 = b1 + H, *b2 = W2 + HH;
+      double s1 = wscale(W1, 3 * HH), s2 = wscale(W2, HH);
+      double sb[3] = {SC(Q_E + k), SC(Q_H), SC(Q_H)};
+      for (int64_t l = 0; l < n; ++l) observe(amax, Q_H, h + l * H, H);
+      for (int64_t t = 0; t < E; ++t) {
+        memcpy(in, e + t * H, sizeof(double) * H);
+        memcpy(in + H, h + (int64_t)src[t] * H, sizeof(double) * H);
+        memcpy(in + 2 * H, h + (int64_t)dst[t] * H, sizeof(double) * H);
+        linear_blocks(in, 3, H, W1, b1, H, tmp, qmode, qmode == 2 ? sb : (qmode ? one : NULL), s1);
+        layernorm_relu(tmp, H);
+        observe(amax, Q_EN2, tmp, H);
+        linear(tmp, H, W2, b2, H, out, qmode, SC(Q_EN2), s2);
+        layernorm_relu(out, H);
+        for (int c = 0; c < H; ++c) out[c] += e[t * H + c];
+        observe(amax, Q_E + k + 1, out, H);
+        for (int c = 0; c < H; ++c) e[t * H + c] = qmode ? qv(qmode, out[c], SC(Q_E + k + 1)) : out[c];
+      }
+      p = b2 + H;
+    }
   }
 
-  /* classifier: Linear(H->1)(Block(H->H)(e)) */
-  for (int64_t t = 0; t < E; ++t) {
-    linear(e + t * H, H, p, p + (int64_t)H * H, H, tmp, qmode, qs ? qs[0] : 1.0, qs ? qs[1] : 1.0);
-    layernorm_relu(tmp, H);
-    const double* pc = p + (int64_t)H * H + H;
-    double acc = 0.0;
-    for (int c = 0; c < H; ++c) acc += tmp[c] * pc[c];
-    logit[t] = acc + pc[H];
+  /* classifier: Linear(H->1)(Block(H->H)(e)); the input is the stored e_S */
+  {
+    const double *W1 = p, *b1 = p + HH, *w2 = b1 + H, *b2 = w2 + H;
+    double s1 = wscale(W1, HH);
+    for (int64_t t = 0; t < E; ++t) {
+      linear(e + t * H, H, W1, b1, H, tmp, qmode, SC(Q_E + S), s1);
+      layernorm_relu(tmp, H);
+      double acc = 0.0;
+      for (int c = 0; c < H; ++c) acc += tmp[c] * w2[c];
+      logit[t] = acc + b2[0];
+    }
   }
+#undef SC
   free(h); free(e); free(mo); free(mi); free(in); free(tmp); free(out);
 }
 
@@ -409,8 +484,9 @@ void oracle_prefilter_features(int64_t E, const int32_t* src, const int32_t* dst
 }
 
 /* Prefilter MLP 6 -> P -> P -> 1 with ReLU; params W1 b1 W2 b2 W3 b3.
- * Forward logits for E edges. With qmode 1 the GEMM operands (inputs,
- * hidden activations, weights) are rounded to BF16. */
+ * Forward logits for E edges.  With qmode 1 the operands of the P x P product
+ * (hidden activations and W2) are rounded to BF16; the 6-wide input layer
+ * and the P -> 1 output layer stay in full precision. */
 void oracle_prefilter_forward(int64_t E, const double* f, int P, const double* params,
                               double* logit, int qmode) {
   const double* W1 = params;
@@ -422,12 +498,12 @@ void oracle_prefilter_forward(int64_t E, const double* f, int P, const double* p
   double* a1 = (double*)malloc(sizeof(double) * P);
   double* a2 = (double*)malloc(sizeof(double) * P);
   for (int64_t t = 0; t < E; ++t) {
-    linear(f + 6 * t, 6, W1, b1, P, a1, qmode, 1.0, 1.0);
+    linear(f + 6 * t, 6, W1, b1, P, a1, 0, 1.0, 1.0);
     for (int c = 0; c < P; ++c) a1[c] = a1[c] > 0 ? a1[c] : 0;
     linear(a1, P, W2, b2, P, a2, qmode, 1.0, 1.0);
     for (int c = 0; c < P; ++c) a2[c] = a2[c] > 0 ? a2[c] : 0;
     double o;
-    linear(a2, P, W3, b3, 1, &o, qmode, 1.0, 1.0);
+    linear(a2, P, W3, b3, 1, &o, 0, 1.0, 1.0);
     logit[t] = o;
   }
   free(a1); free(a2);
@@ -437,6 +513,8 @@ void oracle_prefilter_forward(int64_t E, const double* f, int P, const double* p
  * with respect to every parameter (reverse-mode chain rule, thesis ch. 4
  * "Backpropagation"), written out layer by layer.
  * loss = (1/E) sum_t w_t * [softplus(-z) if y=1 else softplus(z)], w_t = pos_w for y=1.
+ * With qmode 1 the two P x P products (forward a1 W2 and backward W2 delta2)
+ * take BF16-rounded operands; the weight gradients are full precision.
  * grad has the layout of params.  Returns the loss. */
 double oracle_prefilter_loss_grad(int64_t E, const double* f, const uint8_t* label, int P,
                                   const double* params, double pos_w, double* grad, int qmode) {
@@ -461,12 +539,12 @@ double oracle_prefilter_loss_grad(int64_t E, const double* f, const uint8_t* lab
   double loss = 0.0;
   for (int64_t t = 0; t < E; ++t) {
     const double* in = f + 6 * t;
-    linear(in, 6, W1, b1, P, a1, qmode, 1.0, 1.0);
+    linear(in, 6, W1, b1, P, a1, 0, 1.0, 1.0);
     for (int c = 0; c < P; ++c) a1[c] = a1[c] > 0 ? a1[c] : 0;
     linear(a1, P, W2, b2, P, a2, qmode, 1.0, 1.0);
     for (int c = 0; c < P; ++c) a2[c] = a2[c] > 0 ? a2[c] : 0;
     double z;
-    linear(a2, P, W3, b3, 1, &z, qmode, 1.0, 1.0);
+    linear(a2, P, W3, b3, 1, &z, 0, 1.0, 1.0);
     double y = label[t] ? 1.0 : 0.0;
     double w = label[t] ? pos_w : 1.0;
     /* softplus(v) = log(1 + exp(v)), evaluated stably */
@@ -476,21 +554,21 @@ double oracle_prefilter_loss_grad(int64_t E, const double* f, const uint8_t* lab
     double sig = 1.0 / (1.0 + exp(-z));
     double dz = w * (sig - y) / (double)E;
     /* output layer */
-    for (int c = 0; c < P; ++c) gW3[c] += qv(qmode, a2[c], 1.0) * dz;
+    for (int c = 0; c < P; ++c) gW3[c] += a2[c] * dz;
     gb3[0] += dz;
-    for (int c = 0; c < P; ++c) d2[c] = (a2[c] > 0 ? 1.0 : 0.0) * qv(qmode, W3[c], 1.0) * dz;
+    for (int c = 0; c < P; ++c) d2[c] = (a2[c] > 0 ? 1.0 : 0.0) * W3[c] * dz;
     /* hidden layer 2 */
     for (int k = 0; k < P; ++k)
-      for (int c = 0; c < P; ++c) gW2[k * P + c] += qv(qmode, a1[k], 1.0) * d2[c];
+      for (int c = 0; c < P; ++c) gW2[k * P + c] += a1[k] * d2[c];
     for (int c = 0; c < P; ++c) gb2[c] += d2[c];
     for (int k = 0; k < P; ++k) {
       double s = 0.0;
-      for (int c = 0; c < P; ++c) s += qv(qmode, W2[k * P + c], 1.0) * d2[c];
+      for (int c = 0; c < P; ++c) s += qv(qmode, W2[k * P + c], 1.0) * qv(qmode, d2[c], 1.0);
       d1[k] = (a1[k] > 0 ? 1.0 : 0.0) * s;
     }
     /* hidden layer 1 */
     for (int k = 0; k < 6; ++k)
-      for (int c = 0; c < P; ++c) gW1[k * P + c] += qv(qmode, in[k], 1.0) * d1[c];
+      for (int c = 0; c < P; ++c) gW1[k * P + c] += in[k] * d1[c];
     for (int c = 0; c < P; ++c) gb1[c] += d1[c];
   }
   free(a1); free(a2); free(d1); free(d2);

@@ -50,11 +50,13 @@ def lib():
         P = C.c_void_p
         i64, i32, dbl = C.c_int64, C.c_int, C.c_double
         L.oracle_features.argtypes = [i64, P, P, P, dbl, dbl, P, P]
-        L.oracle_embed.argtypes = [i64, P, i32, P, P, P, i32, P]
+        L.oracle_embed.argtypes = [i64, P, i32, P, P, P, i32, P, P]
         L.oracle_radius.argtypes = [i64, P, P, i32, dbl, i32, i32, P, P, i64]
         L.oracle_radius.restype = i64
         L.oracle_radius_margins.argtypes = [i64, P, P, i32, dbl, i32, i32, P, P]
-        L.oracle_gnn.argtypes = [i64, P, i64, P, P, i32, i32, P, P, i32, P]
+        L.oracle_gnn.argtypes = [i64, P, i64, P, P, i32, i32, P, P, i32, P, P]
+        L.oracle_pow2_scale.argtypes = [dbl]
+        L.oracle_pow2_scale.restype = dbl
         L.oracle_components.argtypes = [i64, i64, P, P, P, P]
         L.oracle_round_bf16.argtypes = [dbl]
         L.oracle_round_bf16.restype = dbl
@@ -97,15 +99,18 @@ def _flat(layers) -> np.ndarray:
     return np.concatenate(parts) if parts else np.zeros(0)
 
 
-def embed(cyl: np.ndarray, layers, qmode: int = 0, qscale=None) -> np.ndarray:
+def embed(cyl: np.ndarray, layers, qmode: int = 0, act_scale=None, amax=None) -> np.ndarray:
+    """Embedding MLP.  qmode 1/2 quantise the GEMM operands of layers >= 1
+    (act_scale[l]: scale of layer l's input in FP8); amax (float64 array of
+    len(layers)) receives the running max |input| of each layer."""
     cyl = _c(cyl, np.float64)
     dims = np.array([layers[0][0].shape[0]] + [W.shape[1] for W, _ in layers], dtype=np.int32)
     n = len(cyl)
     out = np.zeros((n, int(dims[-1])))
     params = _flat(layers)
-    qs = None if qscale is None else _c(qscale, np.float64)
+    qs = None if act_scale is None else _c(act_scale, np.float64)
     lib().oracle_embed(n, _p(cyl), len(layers), _p(dims), _p(params), _p(out), qmode,
-                       _p(qs) if qs is not None else None)
+                       _p(qs) if qs is not None else None, _p(amax) if amax is not None else None)
     return out
 
 
@@ -139,16 +144,39 @@ def gnn_param_blocks(weights) -> list:
     return blocks
 
 
-def gnn(cart, src, dst, weights, H: int, S: int, qmode: int = 0, qscale=None) -> np.ndarray:
+def gnn(cart, src, dst, weights, H: int, S: int, qmode: int = 0, act_scale=None, amax=None) -> np.ndarray:
+    """Interaction-network logits.  act_scale / amax: the 8 + S activation
+    slots documented in etx_oracle.c (qmode 2 / observers)."""
     cart = _c(cart, np.float64)
     src = _c(src, np.int32); dst = _c(dst, np.int32)
     params = _flat(gnn_param_blocks(weights))
     E = len(src)
     logit = np.zeros(max(E, 1))
-    qs = None if qscale is None else _c(qscale, np.float64)
+    qs = None if act_scale is None else _c(act_scale, np.float64)
     lib().oracle_gnn(len(cart), _p(cart), E, _p(src), _p(dst), H, S, _p(params), _p(logit), qmode,
-                     _p(qs) if qs is not None else None)
+                     _p(qs) if qs is not None else None, _p(amax) if amax is not None else None)
     return logit[:E].copy()
+
+
+def pow2_scale(amax: float) -> float:
+    return lib().oracle_pow2_scale(float(amax))
+
+
+def calibrate(events, w, weights):
+    """Static calibration in FP64: run the unquantised pipeline on `events`
+    (list of dicts with x, y, z, plane), record the absolute maximum of every
+    quantised tensor, and return the power-of-two scales
+    (embedding layer-input scales, interaction-network slot scales)."""
+    n_emb = len(weights["emb"])
+    am_e = np.zeros(n_emb)
+    am_g = np.zeros(8 + w.gnn_steps)
+    r32 = float(np.float32(w.radius))
+    for ev in events:
+        cyl, cart = features(ev["x"], ev["y"], ev["z"], w.r_scale, w.z_scale)
+        emb = embed(cyl, weights["emb"], amax=am_e)
+        src, dst = radius_graph(ev["plane"], emb, r32, w.k_max, w.plane_window)
+        gnn(cart, src, dst, weights, w.gnn_hidden, w.gnn_steps, amax=am_g)
+    return (np.array([pow2_scale(a) for a in am_e]), np.array([pow2_scale(a) for a in am_g]), am_e, am_g)
 
 
 def components(n: int, src, dst, keep) -> np.ndarray:
@@ -175,15 +203,18 @@ def round_e4m3(x: float) -> float:
 # whole pipeline
 # ---------------------------------------------------------------------------
 
-def run_event(ev: Dict[str, np.ndarray], w, weights, with_margins: bool = False) -> Dict[str, np.ndarray]:
+def run_event(ev: Dict[str, np.ndarray], w, weights, with_margins: bool = False, qmode: int = 0,
+              scales=None) -> Dict[str, np.ndarray]:
     """The full hot path on one event.  ``w`` carries the workload constants
     (r_scale, z_scale, radius, k_max, plane_window, gnn_hidden, gnn_steps,
-    threshold); ``weights`` the network parameters."""
+    threshold); ``weights`` the network parameters.  qmode 1 (BF16) or 2 (FP8,
+    ``scales`` from ``calibrate``) quantises the GEMM operands."""
     cyl, cart = features(ev["x"], ev["y"], ev["z"], w.r_scale, w.z_scale)
-    emb = embed(cyl, weights["emb"])
+    es, gs = (scales[0], scales[1]) if scales is not None else (None, None)
+    emb = embed(cyl, weights["emb"], qmode, es)
     r32 = float(np.float32(w.radius))
     src, dst = radius_graph(ev["plane"], emb, r32, w.k_max, w.plane_window)
-    logit = gnn(cart, src, dst, weights, w.gnn_hidden, w.gnn_steps)
+    logit = gnn(cart, src, dst, weights, w.gnn_hidden, w.gnn_steps, qmode, gs)
     score = sigmoid(logit)
     keep = score >= w.threshold
     labels = components(len(cyl), src, dst, keep)
@@ -195,14 +226,15 @@ def run_event(ev: Dict[str, np.ndarray], w, weights, with_margins: bool = False)
 
 
 def run_batch(batch: Dict[str, np.ndarray], w, weights, events: Optional[Sequence[int]] = None,
-              threads: Optional[int] = None, with_margins: bool = False) -> List[Dict[str, np.ndarray]]:
+              threads: Optional[int] = None, with_margins: bool = False, qmode: int = 0,
+              scales=None) -> List[Dict[str, np.ndarray]]:
     hit_off = batch["hit_off"]
     idx = list(range(len(hit_off) - 1)) if events is None else list(events)
 
     def one(i):
         a, b = int(hit_off[i]), int(hit_off[i + 1])
         ev = {k: batch[k][a:b] for k in ("x", "y", "z", "plane")}
-        return run_event(ev, w, weights, with_margins)
+        return run_event(ev, w, weights, with_margins, qmode, scales)
 
     nt = threads or os.cpu_count() or 1
     if nt <= 1 or len(idx) <= 1:

@@ -19,7 +19,6 @@ int gnn_attributes(size_t max_lds);
 int graph_attributes(size_t max_lds);
 int radius_attributes(size_t max_lds);
 int prefilter_attributes(size_t max_lds);
-hipError_t build_low_precision(etx_ctx* ctx);
 
 bool GraphKey::operator<(const GraphKey& o) const {
   for (int i = 0; i < 16; ++i)
@@ -60,19 +59,90 @@ WsLayout ws_layout(const etx_ctx* ctx, int64_t n_events, int64_t n_hits, int64_t
   L.calib = take(sizeof(float) * ETX_N_CALIB);
   L.pf_keep = take(sizeof(uint8_t) * edge_cap);
   L.pf_tmp = take(sizeof(int64_t) * (n_hits + 1));
-  L.pf_grad = take(sizeof(float) * 4 * ETX_PF_NPARAM + 64);
+  const bool pf = c.prefilter != 0;
+  L.cand_src = take(pf ? sizeof(int32_t) * edge_cap : 0);
+  L.cand_dst = take(pf ? sizeof(int32_t) * edge_cap : 0);
+  L.pf_part = take(sizeof(float) * (size_t)kPfMaxWaves * kPfGradStride);
+  L.pf_grad = take(sizeof(float) * kPfGradStride);
   L.total = o;
   return L;
 }
 
-// Permute a row-major [K][M] weight for the column layout (tile.hpp); M padded to Mpad.
-static void perm_f32(const float* W, int K, int M, int Mpad, float* out) {
+// ---------------------------------------------------------------------------
+// host-side number formats
+// ---------------------------------------------------------------------------
+
+static uint16_t host_bf16(float x) {
+  uint32_t b;
+  std::memcpy(&b, &x, 4);
+  if ((b & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((b >> 16) | 0x40u);   // quiet NaN
+  b += 0x7fffu + ((b >> 16) & 1u);                                          // round to nearest even
+  return (uint16_t)(b >> 16);
+}
+
+// OCP E4M3: round to nearest even, saturate to +-448.
+static uint8_t host_e4m3(double x) {
+  uint8_t sign = std::signbit(x) ? 0x80 : 0;
+  double a = std::fabs(x);
+  if (!(a == a)) return 0;
+  if (a > 448.0) a = 448.0;
+  int e;
+  std::frexp(a, &e);                     // a = f 2^e, f in [0.5, 1)
+  int lead = std::max(e - 1, -6);        // subnormal spacing below 2^-6
+  double q = std::nearbyint(a / std::ldexp(1.0, lead - 3));   // ties to even
+  double v = q * std::ldexp(1.0, lead - 3);
+  if (v > 448.0) v = 448.0;
+  if (v == 0.0) return sign;
+  int ve;
+  double vf = std::frexp(v, &ve);        // v = vf 2^ve
+  int E = ve - 1 + 7;                    // biased exponent
+  uint8_t code;
+  if (E <= 0) code = (uint8_t)std::lround(v / std::ldexp(1.0, -9));      // subnormal
+  else code = (uint8_t)((E << 3) | (int)std::lround((vf * 2.0 - 1.0) * 8.0));
+  return sign | code;
+}
+
+// Power of two at or above amax / 448 (1 when amax is 0).
+static float pow2_scale(double amax) {
+  if (!(amax > 0.0)) return 1.0f;
+  int e;
+  double f = std::frexp(amax / 448.0, &e);
+  return (float)std::ldexp(1.0, f == 0.5 ? e - 1 : e);
+}
+
+// Write a row-major [K][M] weight (M padded to Mpad) permuted for the column
+// layout of tile.hpp in operand format `prec`; FP8 stores W / scale.
+static void put_perm(char* out, const float* W, int K, int M, int Mpad, int prec, float scale) {
   for (int mb = 0; mb < Mpad / 16; ++mb)
-    for (int t = 0; t < K / 4; ++t)
-      for (int lane = 0; lane < 64; ++lane) {
-        int row = phi(t, lane / 16), col = 16 * mb + lane % 16;
-        out[((size_t)mb * (K / 4) + t) * 64 + lane] = col < M ? W[(size_t)row * M + col] : 0.f;
+    for (int lane = 0; lane < 64; ++lane) {
+      const int col = 16 * mb + lane % 16, g = lane / 16;
+      if (prec == ETX_FP32) {
+        for (int t = 0; t < K / 4; ++t) {
+          const int row = phi(t, g);
+          float v = col < M ? W[(size_t)row * M + col] : 0.f;
+          std::memcpy(out + (((size_t)mb * (K / 4) + t) * 64 + lane) * 4, &v, 4);
+        }
+      } else {
+        for (int t = 0; t < K / 32; ++t)
+          for (int q = 0; q < 8; ++q) {
+            const int row = phi(8 * t + q, g);
+            const float v = col < M ? W[(size_t)row * M + col] : 0.f;
+            const size_t at = (((size_t)mb * (K / 32) + t) * 64 + lane) * 8 + q;
+            if (prec == ETX_BF16) {
+              uint16_t b = host_bf16(v);
+              std::memcpy(out + at * 2, &b, 2);
+            } else {
+              out[at] = (char)host_e4m3((double)v / scale);
+            }
+          }
       }
+    }
+}
+
+static float layer_amax(const float* W, size_t n) {
+  float m = 0.f;
+  for (size_t i = 0; i < n; ++i) m = std::max(m, std::fabs(W[i]));
+  return m;
 }
 
 namespace {
@@ -160,34 +230,35 @@ void clear_graphs(etx_ctx* ctx) {
 
 }  // namespace
 
-// Build the FP32 weight segments on the host and upload them.
-static etx_status build_segments(etx_ctx* ctx, const std::vector<BlobLayer>& Ls) {
+// Build the weight segments of one operand precision on the host and upload them.
+static etx_status build_segments(etx_ctx* ctx, const std::vector<BlobLayer>& Ls, int prec) {
   const etx_config& c = ctx->cfg;
   const int W = c.emb_hidden, H = c.gnn_hidden, S = c.gnn_steps, LE = c.emb_layers;
-  WeightMap& m = ctx->wmap;
-  std::vector<float> buf;
+  const int ES = kPrecBytes[prec];
+  WeightMap& m = ctx->wmap[prec];
+  std::vector<char> buf;
   auto reserve = [&](int n) {
     int64_t at = (int64_t)buf.size();
-    buf.resize(buf.size() + ((n + 3) & ~3), 0.f);
+    buf.resize(buf.size() + ((n + 15) & ~15), 0);
     return at;
   };
+  auto put_vec = [&](int64_t at, const float* v, int n) { std::memcpy(buf.data() + at, v, sizeof(float) * n); };
+  const float* sc = ctx->host_scales;
   size_t li = 0;
-  // embedding
   {
-    SegEmb s{W, LE};
+    SegEmb s{W, LE, ES};
     m.emb = reserve(s.size());
-    float* p = buf.data() + m.emb;
     const BlobLayer& l1 = Ls[li++];
-    std::memcpy(p + s.w1(), l1.W, sizeof(float) * 3 * W);
-    std::memcpy(p + s.b1(), l1.b, sizeof(float) * W);
+    put_vec(m.emb + s.w1(), l1.W, 3 * W);
+    put_vec(m.emb + s.b1(), l1.b, W);
     for (int l = 1; l < LE; ++l) {
       const BlobLayer& L = Ls[li++];
-      perm_f32(L.W, W, W, W, p + s.wh(l));
-      std::memcpy(p + s.bh(l), L.b, sizeof(float) * W);
+      put_perm(buf.data() + m.emb + s.wh(l), L.W, W, W, W, prec, sc[SW_EMB + l]);
+      put_vec(m.emb + s.bh(l), L.b, W);
     }
     const BlobLayer& lo = Ls[li++];
-    perm_f32(lo.W, W, c.emb_dim, 16, p + s.wo());
-    std::memcpy(p + s.bo(), lo.b, sizeof(float) * c.emb_dim);
+    put_perm(buf.data() + m.emb + s.wo(), lo.W, W, c.emb_dim, 16, prec, sc[SW_EMB + LE]);
+    put_vec(m.emb + s.bo(), lo.b, c.emb_dim);
   }
   const BlobLayer ne1 = Ls[li++], ne2 = Ls[li++], ee1 = Ls[li++], ee2 = Ls[li++];
   std::vector<BlobLayer> nn1(S), nn2(S), en1(S), en2(S);
@@ -198,57 +269,73 @@ static etx_status build_segments(etx_ctx* ctx, const std::vector<BlobLayer>& Ls)
     en2[k] = Ls[li++];
   }
   const BlobLayer c1 = Ls[li++], c2 = Ls[li++];
+  const size_t HH = (size_t)H * H;
   {
-    SegNodeEnc s{H};
+    SegNodeEnc s{H, ES};
     m.node_enc = reserve(s.size());
-    float* p = buf.data() + m.node_enc;
-    std::memcpy(p + s.w1(), ne1.W, sizeof(float) * 3 * H);
-    std::memcpy(p + s.b1(), ne1.b, sizeof(float) * H);
-    perm_f32(ne2.W, H, H, H, p + s.w2());
-    std::memcpy(p + s.b2(), ne2.b, sizeof(float) * H);
-    perm_f32(ee1.W, H, H, H, p + s.ws());                        // rows 0..H-1: h_src
-    perm_f32(ee1.W + (size_t)H * H, H, H, H, p + s.wd());        // rows H..2H-1: h_dst
+    put_vec(m.node_enc + s.w1(), ne1.W, 3 * H);
+    put_vec(m.node_enc + s.b1(), ne1.b, H);
+    put_perm(buf.data() + m.node_enc + s.w2(), ne2.W, H, H, H, prec, sc[SW_NE2]);
+    put_vec(m.node_enc + s.b2(), ne2.b, H);
+    put_perm(buf.data() + m.node_enc + s.ws(), ee1.W, H, H, H, prec, sc[SW_EE1]);        // rows 0..H-1: h_src
+    put_perm(buf.data() + m.node_enc + s.wd(), ee1.W + HH, H, H, H, prec, sc[SW_EE1]);   // rows H..2H-1: h_dst
   }
   {
-    SegEdgeEnc s{H};
+    SegEdgeEnc s{H, ES};
     m.edge_enc = reserve(s.size());
-    float* p = buf.data() + m.edge_enc;
-    std::memcpy(p + s.b1(), ee1.b, sizeof(float) * H);
-    perm_f32(ee2.W, H, H, H, p + s.w2());
-    std::memcpy(p + s.b2(), ee2.b, sizeof(float) * H);
+    put_vec(m.edge_enc + s.b1(), ee1.b, H);
+    put_perm(buf.data() + m.edge_enc + s.w2(), ee2.W, H, H, H, prec, sc[SW_EE2]);
+    put_vec(m.edge_enc + s.b2(), ee2.b, H);
   }
   for (int k = 0; k < S; ++k) {
-    SegNode s{H};
+    SegNode s{H, ES};
     m.node[k] = reserve(s.size());
-    float* p = buf.data() + m.node[k];
-    perm_f32(nn1[k].W, 3 * H, H, H, p + s.w1());
-    std::memcpy(p + s.b1(), nn1[k].b, sizeof(float) * H);
-    perm_f32(nn2[k].W, H, H, H, p + s.w2());
-    std::memcpy(p + s.b2(), nn2[k].b, sizeof(float) * H);
-    perm_f32(en1[k].W + (size_t)H * H, H, H, H, p + s.ws());     // rows H..2H-1: h_src
-    perm_f32(en1[k].W + (size_t)2 * H * H, H, H, H, p + s.wd()); // rows 2H..3H-1: h_dst
-    SegEdge se{H};
+    put_perm(buf.data() + m.node[k] + s.w1(), nn1[k].W, 3 * H, H, H, prec, sc[SW_STEP + 4 * k]);
+    put_vec(m.node[k] + s.b1(), nn1[k].b, H);
+    put_perm(buf.data() + m.node[k] + s.w2(), nn2[k].W, H, H, H, prec, sc[SW_STEP + 4 * k + 1]);
+    put_vec(m.node[k] + s.b2(), nn2[k].b, H);
+    put_perm(buf.data() + m.node[k] + s.ws(), en1[k].W + HH, H, H, H, prec, sc[SW_STEP + 4 * k + 2]);      // h_src rows
+    put_perm(buf.data() + m.node[k] + s.wd(), en1[k].W + 2 * HH, H, H, H, prec, sc[SW_STEP + 4 * k + 2]);  // h_dst rows
+    SegEdge se{H, ES};
     m.edge[k] = reserve(se.size());
-    float* q = buf.data() + m.edge[k];
-    perm_f32(en1[k].W, H, H, H, q + se.we());                    // rows 0..H-1: e
-    std::memcpy(q + se.b1(), en1[k].b, sizeof(float) * H);
-    perm_f32(en2[k].W, H, H, H, q + se.w2());
-    std::memcpy(q + se.b2(), en2[k].b, sizeof(float) * H);
+    put_perm(buf.data() + m.edge[k] + se.we(), en1[k].W, H, H, H, prec, sc[SW_STEP + 4 * k + 2]);          // e rows
+    put_vec(m.edge[k] + se.b1(), en1[k].b, H);
+    put_perm(buf.data() + m.edge[k] + se.w2(), en2[k].W, H, H, H, prec, sc[SW_STEP + 4 * k + 3]);
+    put_vec(m.edge[k] + se.b2(), en2[k].b, H);
   }
   {
-    SegCls s{H};
+    SegCls s{H, ES};
     m.cls = reserve(s.size());
-    float* p = buf.data() + m.cls;
-    perm_f32(c1.W, H, H, H, p + s.w1());
-    std::memcpy(p + s.b1(), c1.b, sizeof(float) * H);
-    std::memcpy(p + s.w2(), c2.W, sizeof(float) * H);
-    p[s.b2()] = c2.b[0];
+    put_perm(buf.data() + m.cls + s.w1(), c1.W, H, H, H, prec, sc[SW_CLS1]);
+    put_vec(m.cls + s.b1(), c1.b, H);
+    put_vec(m.cls + s.w2(), c2.W, H);
+    put_vec(m.cls + s.b2(), c2.b, 1);
   }
   m.total = (int64_t)buf.size();
-  if (hipMalloc(&ctx->dev_w, sizeof(float) * buf.size()) != hipSuccess) return ETX_ERR_HIP;
-  if (hipMemcpy(ctx->dev_w, buf.data(), sizeof(float) * buf.size(), hipMemcpyHostToDevice) != hipSuccess)
-    return ETX_ERR_HIP;
+  if (hipMalloc(&ctx->seg_base[prec], buf.size()) != hipSuccess) return ETX_ERR_HIP;
+  if (hipMemcpy(ctx->seg_base[prec], buf.data(), buf.size(), hipMemcpyHostToDevice) != hipSuccess) return ETX_ERR_HIP;
   return ETX_OK;
+}
+
+// Per-layer power-of-two weight scales (FP8 operands) into host_scales[64..].
+static void weight_scales(etx_ctx* ctx, const std::vector<BlobLayer>& Ls) {
+  const etx_config& c = ctx->cfg;
+  const int S = c.gnn_steps, LE = c.emb_layers;
+  float* sc = ctx->host_scales;
+  for (int i = 0; i < N_SCALES; ++i) sc[i] = 1.0f;
+  auto amax = [&](const BlobLayer& L) { return layer_amax(L.W, (size_t)L.K * L.M); };
+  size_t li = 0;
+  for (int l = 0; l <= LE; ++l) {
+    const BlobLayer& L = Ls[li++];
+    if (l >= 1) sc[SW_EMB + l] = pow2_scale(amax(L));
+  }
+  li++;                                           // node encoder layer 1 (FP32)
+  sc[SW_NE2] = pow2_scale(amax(Ls[li++]));
+  sc[SW_EE1] = pow2_scale(amax(Ls[li++]));
+  sc[SW_EE2] = pow2_scale(amax(Ls[li++]));
+  for (int k = 0; k < S; ++k)
+    for (int j = 0; j < 4; ++j) sc[SW_STEP + 4 * k + j] = pow2_scale(amax(Ls[li++]));
+  sc[SW_CLS1] = pow2_scale(amax(Ls[li++]));
 }
 
 thread_local std::string g_last_error;
@@ -308,15 +395,23 @@ static hipError_t enqueue_pipeline(const RunArgs& a) {
   STEP(1, launch_validate(a));
   STEP(2, launch_bucket(a));
   STEP(3, launch_embed(a));
-  STEP(4, launch_radius(a, false));
-  STEP(5, launch_scan_counts(a));
-  STEP(6, launch_radius(a, true));
-  if (c.prefilter) STEP(7, launch_prefilter_infer(a));
+  const bool pf = c.prefilter != 0;
+  STEP(4, launch_radius(a, false, pf));
+  STEP(5, launch_scan_counts(a, pf));
+  STEP(6, launch_radius(a, true, pf));
+  if (pf) {
+    // learned prefilter: keep flags on the candidates, then the surviving
+    // edges become the graph of the rest of the path
+    STEP(7, launch_prefilter_infer(a));
+    STEP(7, launch_prefilter_count(a));
+    STEP(7, launch_scan_counts(a, false));
+    STEP(7, launch_prefilter_compact(a));
+  }
   STEP(8, launch_csc(a));
   STEP(9, launch_node_encode(a));
   STEP(10, launch_edge_encode(a));
   for (int k = 0; k < c.gnn_steps; ++k) {
-    STEP(11, launch_segsum(a));
+    STEP(11, launch_segsum(a, k));
     STEP(12, launch_node_step(a, k));
     STEP(k + 1 == c.gnn_steps ? 14 : 13, launch_edge_step(a, k, k + 1 == c.gnn_steps));
   }
@@ -401,14 +496,14 @@ etx_status etx_create(const etx_config* cfg, const void* weights, size_t nbytes,
     delete ctx;
     return ETX_ERR_HIP;
   }
-  ctx->host_blob.assign(static_cast<const char*>(weights) + 0, static_cast<const char*>(weights) + 0);
-  ctx->host_blob = payload;
-  st = build_segments(ctx, layers);
-  if (st == ETX_OK && hipMalloc(&ctx->dev_scales, sizeof(float) * 2 * ETX_N_CALIB) != hipSuccess) st = ETX_ERR_HIP;
-  if (st == ETX_OK && hipMemset(ctx->dev_scales, 0, sizeof(float) * 2 * ETX_N_CALIB) != hipSuccess) st = ETX_ERR_HIP;
+  weight_scales(ctx, layers);
+  st = ETX_OK;
+  for (int p = 0; p < 3 && st == ETX_OK; ++p) st = build_segments(ctx, layers, p);
+  if (st == ETX_OK && hipMalloc(&ctx->dev_scales, sizeof(float) * N_SCALES) != hipSuccess) st = ETX_ERR_HIP;
+  if (st == ETX_OK && hipMemcpy(ctx->dev_scales, ctx->host_scales, sizeof(float) * N_SCALES, hipMemcpyHostToDevice) != hipSuccess)
+    st = ETX_ERR_HIP;
   if (st == ETX_OK && hipMalloc(&ctx->dev_pf, sizeof(float) * 3 * ETX_PF_NPARAM) != hipSuccess) st = ETX_ERR_HIP;
   if (st == ETX_OK && hipMemset(ctx->dev_pf, 0, sizeof(float) * 3 * ETX_PF_NPARAM) != hipSuccess) st = ETX_ERR_HIP;
-  if (st == ETX_OK && cfg->precision != ETX_FP32 && build_low_precision(ctx) != hipSuccess) st = ETX_ERR_HIP;
   if (st != ETX_OK) {
     etx_destroy(ctx);
     return st;
@@ -425,8 +520,8 @@ etx_status etx_destroy(etx_ctx* ctx) {
     hipEventDestroy(m.start);
     hipEventDestroy(m.end);
   }
-  if (ctx->dev_w) hipFree(ctx->dev_w);
-  if (ctx->dev_wq) hipFree(ctx->dev_wq);
+  for (int p = 0; p < 3; ++p)
+    if (ctx->seg_base[p]) hipFree(ctx->seg_base[p]);
   if (ctx->dev_scales) hipFree(ctx->dev_scales);
   if (ctx->dev_pf) hipFree(ctx->dev_pf);
   delete ctx;
@@ -457,6 +552,7 @@ etx_status etx_workspace_view(const etx_ctx* ctx, int64_t n_events, int64_t n_hi
     case ETX_VIEW_KEPT_COUNT: *offset = L.kept_cnt; *bytes = sizeof(int32_t) * n_events; break;
     case ETX_VIEW_CALIB: *offset = L.calib; *bytes = sizeof(float) * ETX_N_CALIB; break;
     case ETX_VIEW_PF_KEEP: *offset = L.pf_keep; *bytes = edge_capacity; break;
+    case ETX_VIEW_PF_GRAD: *offset = L.pf_grad; *bytes = sizeof(float) * (ETX_PF_NPARAM + 1); break;
     default: return ETX_ERR_INVALID_ARG;
   }
   return ETX_OK;
@@ -546,11 +642,11 @@ etx_status etx_run(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void* ws, s
   WsLayout L;
   etx_status st = check_run_args(ctx, hits, out, ws, ws_bytes, &L);
   if (st != ETX_OK) return st;
-  if (ctx->cfg.precision != ETX_FP32 && !ctx->calibrated && ctx->cfg.precision == ETX_FP8_E4M3)
-    return ETX_ERR_INVALID_ARG;
+  if (ctx->cfg.precision == ETX_FP8_E4M3 && !ctx->calibrated) return ETX_ERR_INVALID_ARG;
   if (ctx->cfg.prefilter && !ctx->pf_set) return ETX_ERR_INVALID_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return ETX_ERR_HIP;
-  RunArgs a{ctx, *hits, *out, L, static_cast<char*>(ws), static_cast<hipStream_t>(stream), false};
+  RunArgs a{ctx, *hits, *out, L, static_cast<char*>(ws), static_cast<hipStream_t>(stream), false,
+            ctx->cfg.precision};
   if (!ctx->use_graph || stream == nullptr) {
     hipError_t e = enqueue_pipeline(a);
     if (e != hipSuccess) {
@@ -588,6 +684,131 @@ etx_status etx_run(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void* ws, s
     it = ctx->graphs.emplace(key, ex).first;
   }
   return hipGraphLaunch(it->second, a.stream) == hipSuccess ? ETX_OK : ETX_ERR_HIP;
+}
+
+etx_status etx_calibrate(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void* ws, size_t ws_bytes,
+                         etx_stream stream) {
+  WsLayout L;
+  etx_status st = check_run_args(ctx, hits, out, ws, ws_bytes, &L);
+  if (st != ETX_OK) return st;
+  if (ctx->cfg.prefilter) return ETX_ERR_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return ETX_ERR_HIP;
+  RunArgs a{ctx, *hits, *out, L, static_cast<char*>(ws), static_cast<hipStream_t>(stream), true, ETX_FP32};
+  hipError_t e = enqueue_pipeline(a);
+  if (e == hipSuccess) e = hipStreamSynchronize(a.stream);
+  int64_t status[2] = {0, 0};
+  float amax[ETX_N_CALIB];
+  if (e == hipSuccess) e = hipMemcpy(status, out->status, sizeof(status), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(amax, a.ws + L.calib, sizeof(amax), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) {
+    note_error("etx_calibrate", e);
+    return ETX_ERR_HIP;
+  }
+  if (status[0] != ETX_OK) return (etx_status)status[0];
+  for (int i = 0; i < ETX_N_CALIB; ++i) ctx->host_scales[i] = pow2_scale(amax[i]);
+  if ((e = hipMemcpy(ctx->dev_scales, ctx->host_scales, sizeof(float) * ETX_N_CALIB, hipMemcpyHostToDevice)) !=
+      hipSuccess) {
+    note_error("etx_calibrate upload", e);
+    return ETX_ERR_HIP;
+  }
+  ctx->calibrated = true;
+  clear_graphs(ctx);
+  return ETX_OK;
+}
+
+etx_status etx_set_precision(etx_ctx* ctx, int32_t precision) {
+  if (!ctx || precision < ETX_FP32 || precision > ETX_FP8_E4M3) return ETX_ERR_INVALID_ARG;
+  ctx->cfg.precision = precision;
+  clear_graphs(ctx);
+  return ETX_OK;
+}
+
+etx_status etx_get_scales(const etx_ctx* ctx, float* scales, int32_t n) {
+  if (!ctx || !scales || n < 0 || n > N_SCALES) return ETX_ERR_INVALID_ARG;
+  std::memcpy(scales, ctx->host_scales, sizeof(float) * n);
+  return ETX_OK;
+}
+
+etx_status etx_quantize(int32_t precision, const float* in, float* out, int64_t n, float scale, etx_stream stream) {
+  if (precision < ETX_FP32 || precision > ETX_FP8_E4M3 || n < 0 || (n > 0 && (!in || !out)) || !(scale > 0))
+    return ETX_ERR_INVALID_ARG;
+  if (n == 0) return ETX_OK;
+  hipError_t e = launch_quantize(precision, in, out, n, scale, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) {
+    note_error("etx_quantize", e);
+    return ETX_ERR_HIP;
+  }
+  return ETX_OK;
+}
+
+etx_status etx_prefilter_set(etx_ctx* ctx, const float* params, int64_t n) {
+  if (!ctx || !params || n != ETX_PF_NPARAM) return ETX_ERR_INVALID_ARG;
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(params[i])) return ETX_ERR_WEIGHTS;
+  if (hipSetDevice(ctx->device) != hipSuccess) return ETX_ERR_HIP;
+  std::vector<float> st(3 * ETX_PF_NPARAM, 0.f);
+  std::memcpy(st.data(), params, sizeof(float) * ETX_PF_NPARAM);
+  hipError_t e = hipMemcpy(ctx->dev_pf, st.data(), sizeof(float) * st.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    note_error("etx_prefilter_set", e);
+    return ETX_ERR_HIP;
+  }
+  ctx->pf_set = true;
+  clear_graphs(ctx);
+  return ETX_OK;
+}
+
+etx_status etx_prefilter_get(const etx_ctx* ctx, float* params, int64_t n) {
+  if (!ctx || !params || n != ETX_PF_NPARAM) return ETX_ERR_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return ETX_ERR_HIP;
+  hipError_t e = hipMemcpy(params, ctx->dev_pf, sizeof(float) * ETX_PF_NPARAM, hipMemcpyDeviceToHost);
+  return e == hipSuccess ? ETX_OK : ETX_ERR_HIP;
+}
+
+etx_status etx_prefilter_state(etx_ctx* ctx, float* host_state, int64_t n, int32_t set) {
+  if (!ctx || !host_state || n != 3 * ETX_PF_NPARAM || (set != 0 && set != 1)) return ETX_ERR_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return ETX_ERR_HIP;
+  hipError_t e = set ? hipMemcpy(ctx->dev_pf, host_state, sizeof(float) * n, hipMemcpyHostToDevice)
+                     : hipMemcpy(host_state, ctx->dev_pf, sizeof(float) * n, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) {
+    note_error("etx_prefilter_state", e);
+    return ETX_ERR_HIP;
+  }
+  if (set) {
+    ctx->pf_set = true;
+    clear_graphs(ctx);
+  }
+  return ETX_OK;
+}
+
+etx_status etx_prefilter_train_step(etx_ctx* ctx, const etx_hits* hits, etx_out* out, const uint8_t* edge_labels,
+                                    float lr, float pos_weight, int64_t step, float* loss_dev, void* ws,
+                                    size_t ws_bytes, etx_stream stream) {
+  WsLayout L;
+  etx_status st = check_run_args(ctx, hits, out, ws, ws_bytes, &L);
+  if (st != ETX_OK) return st;
+  if (!edge_labels || !(lr > 0) || !(pos_weight > 0) || step < 1 || !ctx->pf_set) return ETX_ERR_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return ETX_ERR_HIP;
+  RunArgs a{ctx, *hits, *out, L, static_cast<char*>(ws), static_cast<hipStream_t>(stream), false, ETX_FP32};
+  hipError_t e;
+#define STEP(x)                                   \
+  do {                                            \
+    if ((e = (x)) != hipSuccess) {                \
+      note_error("etx_prefilter_train_step", e);  \
+      return ETX_ERR_HIP;                         \
+    }                                             \
+  } while (0)
+  // the candidate graph (unpruned) of the batch, then one optimiser step
+  STEP(launch_init_status(a));
+  STEP(launch_validate(a));
+  STEP(launch_bucket(a));
+  STEP(launch_embed(a));
+  STEP(launch_radius(a, false, false));
+  STEP(launch_scan_counts(a, false));
+  STEP(launch_radius(a, true, false));
+  STEP(launch_prefilter_train(a, edge_labels, lr, pos_weight, step, loss_dev));
+#undef STEP
+  return ETX_OK;
 }
 
 }  // extern "C"

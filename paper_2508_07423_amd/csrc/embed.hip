@@ -1,8 +1,9 @@
 // Embedding MLP (thesis ch. 8 "Hit Embedding and Rough Graph Construction"):
 // normalised cylindrical coordinates (r/R_s, phi/pi, z/Z_s) -> Linear -> ReLU
 // -> ... -> Linear, fused with the feature computation.  The 3-wide first layer
-// runs on the vector ALU; the W x W hidden layers and the output layer run on
-// FP32 MFMA in the column layout of tile.hpp.  Output: [n_hits][16] (padded).
+// runs on the vector ALU in FP32; the W x W hidden layers and the output layer
+// run on MFMA in the column layout of tile.hpp with operands in precision P.
+// Output: [n_hits][16] FP32 (padded).
 #include "internal.hpp"
 #include "seg.hpp"
 #include "tile.hpp"
@@ -17,11 +18,12 @@ struct EmbedArgs {
   const float* z;
   int64_t n_hits;
   float inv_r, inv_z;
-  const float* seg;
-  int seg_floats;
+  const char* seg;
+  int seg_bytes;
   int layers;
   float* emb;
   float* calib;
+  const float* sc;
   const int64_t* status;
 };
 
@@ -30,13 +32,14 @@ __device__ inline void atomic_amax(float* slot, float v) {
   atomicMax(reinterpret_cast<unsigned int*>(slot), __float_as_uint(fabsf(v)));
 }
 
-template <int W>
+template <int W, int P>
 __global__ __launch_bounds__(256) void k_embed(EmbedArgs A) {
   if (A.status[0] != 0) return;
-  extern __shared__ float w[];
-  stage(w, A.seg, A.seg_floats);
+  extern __shared__ float lds[];
+  char* w = reinterpret_cast<char*>(lds);
+  stage(lds, reinterpret_cast<const float*>(A.seg), A.seg_bytes / 4);
   __syncthreads();
-  const SegEmb S{W, A.layers};
+  const SegEmb S{W, A.layers, PrecBytes<P>::value};
   const int lane = lane_id(), g = lane_group(), wave = threadIdx.x >> 6;
   const int64_t ntiles = (A.n_hits + kCols - 1) / kCols;
   for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
@@ -50,8 +53,8 @@ __global__ __launch_bounds__(256) void k_embed(EmbedArgs A) {
       u2 = zz * A.inv_z;
     }
     float a[W / 4];
-    const float* w1 = w + S.w1();
-    const float* b1 = w + S.b1();
+    const float* w1 = reinterpret_cast<const float*>(w + S.w1());
+    const float* b1 = reinterpret_cast<const float*>(w + S.b1());
 #pragma unroll
     for (int r = 0; r < W / 4; ++r) {
       const int f = phi(r, g);
@@ -60,22 +63,27 @@ __global__ __launch_bounds__(256) void k_embed(EmbedArgs A) {
       acc = fmaf(u2, w1[2 * W + f], acc);
       a[r] = fmaxf(acc + b1[f], 0.f);
     }
+    auto observe = [&](int l) {
+      if (!A.calib) return;
+      float m = 0.f;
+#pragma unroll
+      for (int r = 0; r < W / 4; ++r) m = fmaxf(m, fabsf(a[r]));
+      if (valid) atomic_amax(A.calib + SC_EMB + l, m);
+    };
     for (int l = 1; l < A.layers; ++l) {
       float acc[W / 4];
-      bias_cols<W>(acc, w + S.bh(l));
-      if (A.calib) {
-        float m = 0.f;
-#pragma unroll
-        for (int r = 0; r < W / 4; ++r) m = fmaxf(m, fabsf(a[r]));
-        if (valid) atomic_amax(A.calib + CAL_EMB_IN + l, m);
-      }
-      mfma_f32<W, W / 16>(acc, a, w + S.wh(l));
+      bias_cols<W>(acc, reinterpret_cast<const float*>(w + S.bh(l)));
+      observe(l);
+      const float s = A.sc[SC_EMB + l];
+      gemm<P, W, W / 16>(acc, a, w + S.wh(l), 1.0f / s, s * A.sc[SW_EMB + l]);
 #pragma unroll
       for (int r = 0; r < W / 4; ++r) a[r] = fmaxf(acc[r], 0.f);
     }
     float o[4];
-    bias_cols<16>(o, w + S.bo());
-    mfma_f32<W, 1>(o, a, w + S.wo());
+    bias_cols<16>(o, reinterpret_cast<const float*>(w + S.bo()));
+    observe(A.layers);
+    const float so = A.sc[SC_EMB + A.layers];
+    gemm<P, W, 1>(o, a, w + S.wo(), 1.0f / so, so * A.sc[SW_EMB + A.layers]);
     // features 4g .. 4g+3 of the 16 padded outputs
     if (valid) *reinterpret_cast<float4*>(A.emb + col * kDpad + 4 * g) = make_float4(o[0], o[1], o[2], o[3]);
   }
@@ -93,30 +101,48 @@ hipError_t launch_embed(const RunArgs& a) {
   A.n_hits = a.hits.n_hits;
   A.inv_r = 1.0f / c->cfg.r_scale_mm;
   A.inv_z = 1.0f / c->cfg.z_scale_mm;
-  A.seg = c->dev_w + c->wmap.emb;
+  A.seg = static_cast<const char*>(c->seg_base[a.prec]) + c->wmap[a.prec].emb;
   A.layers = c->cfg.emb_layers;
+  A.sc = c->dev_scales;
   A.emb = reinterpret_cast<float*>(a.ws + a.L.emb);
   A.calib = a.calibrate ? reinterpret_cast<float*>(a.ws + a.L.calib) : nullptr;
   A.status = a.out.status;
   const int W = c->cfg.emb_hidden;
-  A.seg_floats = SegEmb{W, A.layers}.size();
-  size_t lds = sizeof(float) * A.seg_floats;
+  A.seg_bytes = SegEmb{W, A.layers, kPrecBytes[a.prec]}.size();
+  size_t lds = A.seg_bytes;
   int64_t tiles = (A.n_hits + kCols - 1) / kCols;
   unsigned grid = (unsigned)std::min<int64_t>((tiles + 3) / 4, (int64_t)c->n_cu * 2);
-  switch (W) {
-    case 32: hipLaunchKernelGGL(k_embed<32>, dim3(grid), dim3(256), lds, a.stream, A); break;
-    case 64: hipLaunchKernelGGL(k_embed<64>, dim3(grid), dim3(256), lds, a.stream, A); break;
-    case 128: hipLaunchKernelGGL(k_embed<128>, dim3(grid), dim3(256), lds, a.stream, A); break;
+#define EMB(W_, P_) hipLaunchKernelGGL((k_embed<W_, P_>), dim3(grid), dim3(256), lds, a.stream, A)
+  switch (W * 4 + a.prec) {
+    case 32 * 4 + 0: EMB(32, 0); break;
+    case 32 * 4 + 1: EMB(32, 1); break;
+    case 32 * 4 + 2: EMB(32, 2); break;
+    case 64 * 4 + 0: EMB(64, 0); break;
+    case 64 * 4 + 1: EMB(64, 1); break;
+    case 64 * 4 + 2: EMB(64, 2); break;
+    case 128 * 4 + 0: EMB(128, 0); break;
+    case 128 * 4 + 1: EMB(128, 1); break;
+    case 128 * 4 + 2: EMB(128, 2); break;
     default: return hipErrorInvalidValue;
   }
+#undef EMB
   return hipGetLastError();
 }
 
 int embed_attributes(size_t max_lds) {
   int bad = 0;
-  bad |= hipFuncSetAttribute(reinterpret_cast<const void*>(k_embed<32>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) != hipSuccess;
-  bad |= hipFuncSetAttribute(reinterpret_cast<const void*>(k_embed<64>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) != hipSuccess;
-  bad |= hipFuncSetAttribute(reinterpret_cast<const void*>(k_embed<128>), hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) != hipSuccess;
+  auto set = [&](const void* f) {
+    bad |= hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) != hipSuccess;
+  };
+  set(reinterpret_cast<const void*>(k_embed<32, 0>));
+  set(reinterpret_cast<const void*>(k_embed<32, 1>));
+  set(reinterpret_cast<const void*>(k_embed<32, 2>));
+  set(reinterpret_cast<const void*>(k_embed<64, 0>));
+  set(reinterpret_cast<const void*>(k_embed<64, 1>));
+  set(reinterpret_cast<const void*>(k_embed<64, 2>));
+  set(reinterpret_cast<const void*>(k_embed<128, 0>));
+  set(reinterpret_cast<const void*>(k_embed<128, 1>));
+  set(reinterpret_cast<const void*>(k_embed<128, 2>));
   return bad;
 }
 

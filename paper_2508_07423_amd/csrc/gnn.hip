@@ -14,6 +14,13 @@
 // per-edge work is one H x H product per layer.  Messages are atomic-free
 // segmented sums: out-sums over the source-major edge list (CSR rows),
 // in-sums through the (dst, src)-ordered CSC permutation.
+//
+// Every MLP kernel is instantiated for the GEMM operand precision P (FP32,
+// BF16, FP8-E4M3 with per-tensor power-of-two scales).  Accumulation,
+// LayerNorm, residual node encodings, the message sums and the scores stay
+// FP32.  The edge encodings, the largest tensor, are stored in the operand
+// format (FP8 with the per-step scale of the stored tensor), which is also
+// the operand the next edge-net product reads.
 #include "internal.hpp"
 #include "seg.hpp"
 #include "tile.hpp"
@@ -46,32 +53,101 @@ struct GnnArgs {
   const int32_t* csc;
   const int32_t* src;
   const int32_t* dst;
-  const float* seg;         // weight segment of the kernel
-  const float* seg2;        // classifier segment (final edge step)
-  int seg_floats, seg2_floats;
+  const char* seg;          // weight segment of the kernel
+  const char* seg2;         // classifier segment (final edge step)
+  int seg_bytes, seg2_bytes;
   float* h;                 // [n_hits][H]
   float* ps;                // [n_hits][H] h W_src (source product)
   float* pd;                // [n_hits][H] h W_dst (target product)
   float* msg;               // [n_hits][2H] (out-sum, in-sum)
-  float* e;                 // [edges][H]
+  void* e;                  // [edges][H] edge encodings in the operand format
   float* score;             // [edges]
-  float* calib;
+  float* calib;             // amax observers (calibration runs, FP32 only)
+  const float* sc;          // per-tensor scales (seg.hpp ScaleSlot)
   int step;
-  int unroll;
   const int64_t* status;
 };
+
+__device__ inline void stage_bytes(char* dst, const char* src, int n) {
+  stage(reinterpret_cast<float*>(dst), reinterpret_cast<const float*>(src), n / 4);
+}
+
+// scale of an activation slot and of a weight slot
+__device__ inline float asc(const GnnArgs& A, int q) { return A.sc[SC_GNN + q]; }
+__device__ inline float wsc(const GnnArgs& A, int s) { return A.sc[s]; }
+
+// --------------------------------------------------------------------------
+// edge-encoding rows in the operand format
+// --------------------------------------------------------------------------
+
+// Column-layout load of an edge row: ef gets the values (FP8: decoded times
+// `scale`), words the raw FP8 codes (4 per word, FP8 only).
+template <int P, int H>
+__device__ inline void load_e(float* ef, uint32_t* words, const void* e, int64_t col, bool valid, float scale) {
+  const int g = lane_group();
+  if constexpr (P == P_F32) {
+    load_cols<H>(ef, static_cast<const float*>(e) + col * H, valid);
+  } else if constexpr (P == P_BF16) {
+    const uint16_t* row = static_cast<const uint16_t*>(e) + col * H;
+#pragma unroll
+    for (int c = 0; c < H / 16; ++c) {
+      uint2 v = valid ? *reinterpret_cast<const uint2*>(row + 16 * c + 4 * g) : make_uint2(0u, 0u);
+      ef[4 * c + 0] = bf16_value(v.x & 0xffffu);
+      ef[4 * c + 1] = bf16_value(v.x >> 16);
+      ef[4 * c + 2] = bf16_value(v.y & 0xffffu);
+      ef[4 * c + 3] = bf16_value(v.y >> 16);
+    }
+  } else {
+    const uint8_t* row = static_cast<const uint8_t*>(e) + col * H;
+#pragma unroll
+    for (int c = 0; c < H / 16; ++c) {
+      const uint32_t w = valid ? *reinterpret_cast<const uint32_t*>(row + 16 * c + 4 * g) : 0u;
+      words[c] = w;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) ef[4 * c + q] = e4m3_decode((w >> (8 * q)) & 0xffu) * scale;
+    }
+  }
+}
+
+template <int P, int H>
+__device__ inline void store_e(void* e, int64_t col, const float* o, bool valid, float inv_scale) {
+  const int g = lane_group();
+  if (!valid) return;
+  if constexpr (P == P_F32) {
+    store_cols<H>(static_cast<float*>(e) + col * H, o, valid);
+  } else if constexpr (P == P_BF16) {
+    uint16_t* row = static_cast<uint16_t*>(e) + col * H;
+#pragma unroll
+    for (int c = 0; c < H / 16; ++c)
+      *reinterpret_cast<uint2*>(row + 16 * c + 4 * g) =
+          make_uint2(bf16_bits(o[4 * c]) | (bf16_bits(o[4 * c + 1]) << 16),
+                     bf16_bits(o[4 * c + 2]) | (bf16_bits(o[4 * c + 3]) << 16));
+  } else {
+    uint8_t* row = static_cast<uint8_t*>(e) + col * H;
+#pragma unroll
+    for (int c = 0; c < H / 16; ++c) {
+      uint32_t w = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) w |= e4m3_encode(o[4 * c + q] * inv_scale) << (8 * q);
+      *reinterpret_cast<uint32_t*>(row + 16 * c + 4 * g) = w;
+    }
+  }
+}
 
 // --------------------------------------------------------------------------
 // node encoder (+ edge-encoder source/target products)
 // --------------------------------------------------------------------------
-template <int H>
+template <int H, int P>
 __global__ __launch_bounds__(1024) void k_node_encode(GnnArgs A) {
   if (A.status[0] != 0) return;
-  extern __shared__ float w[];
-  stage(w, A.seg, A.seg_floats);
+  extern __shared__ float lds[];
+  char* w = reinterpret_cast<char*>(lds);
+  stage_bytes(w, A.seg, A.seg_bytes);
   __syncthreads();
-  constexpr SegNodeEnc S{H};
+  constexpr SegNodeEnc S{H, PrecBytes<P>::value};
   const int lane = lane_id(), g = lane_group(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const float s_ne2 = asc(A, Q_NE2), s_h = asc(A, Q_H);
+  const float o_ne2 = s_ne2 * wsc(A, SW_NE2), o_h = s_h * wsc(A, SW_EE1);
   const int64_t ntiles = (A.n_hits + kCols - 1) / kCols;
   for (int64_t tile = (int64_t)blockIdx.x * nw + wave; tile < ntiles; tile += (int64_t)gridDim.x * nw) {
     const int64_t col = tile * kCols + (lane & 15);
@@ -83,8 +159,8 @@ __global__ __launch_bounds__(1024) void k_node_encode(GnnArgs A) {
       v2 = A.z[col] * A.inv_z;
     }
     float a[H / 4];
-    const float* w1 = w + S.w1();
-    const float* b1 = w + S.b1();
+    const float* w1 = reinterpret_cast<const float*>(w + S.w1());
+    const float* b1 = reinterpret_cast<const float*>(w + S.b1());
 #pragma unroll
     for (int r = 0; r < H / 4; ++r) {
       const int f = phi(r, g);
@@ -94,21 +170,21 @@ __global__ __launch_bounds__(1024) void k_node_encode(GnnArgs A) {
       a[r] = acc + b1[f];
     }
     ln_relu<H>(a);
-    observe<H / 4>(A.calib, CAL_NE_L2, a, valid);
+    observe<H / 4>(A.calib, SC_GNN + Q_NE2, a, valid);
     float hh[H / 4];
-    bias_cols<H>(hh, w + S.b2());
-    mfma_f32<H, H / 16>(hh, a, w + S.w2());
+    bias_cols<H>(hh, reinterpret_cast<const float*>(w + S.b2()));
+    gemm<P, H, H / 16>(hh, a, w + S.w2(), 1.0f / s_ne2, o_ne2);
     ln_relu<H>(hh);
     store_cols<H>(A.h + col * H, hh, valid);
-    observe<H / 4>(A.calib, CAL_H0, hh, valid);
+    observe<H / 4>(A.calib, SC_GNN + Q_H, hh, valid);
     float q[H / 4];
 #pragma unroll
     for (int r = 0; r < H / 4; ++r) q[r] = 0.f;
-    mfma_f32<H, H / 16>(q, hh, w + S.ws());
+    gemm<P, H, H / 16>(q, hh, w + S.ws(), 1.0f / s_h, o_h);
     store_cols<H>(A.ps + col * H, q, valid);
 #pragma unroll
     for (int r = 0; r < H / 4; ++r) q[r] = 0.f;
-    mfma_f32<H, H / 16>(q, hh, w + S.wd());
+    gemm<P, H, H / 16>(q, hh, w + S.wd(), 1.0f / s_h, o_h);
     store_cols<H>(A.pd + col * H, q, valid);
   }
 }
@@ -116,14 +192,17 @@ __global__ __launch_bounds__(1024) void k_node_encode(GnnArgs A) {
 // --------------------------------------------------------------------------
 // edge encoder
 // --------------------------------------------------------------------------
-template <int H>
+template <int H, int P>
 __global__ __launch_bounds__(512) void k_edge_encode(GnnArgs A) {
   if (A.status[0] != 0) return;
-  extern __shared__ float w[];
-  stage(w, A.seg, A.seg_floats);
+  extern __shared__ float lds[];
+  char* w = reinterpret_cast<char*>(lds);
+  stage_bytes(w, A.seg, A.seg_bytes);
   __syncthreads();
-  constexpr SegEdgeEnc S{H};
+  constexpr SegEdgeEnc S{H, PrecBytes<P>::value};
   const int lane = lane_id(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const float s_ee2 = asc(A, Q_EE2), o_ee2 = s_ee2 * wsc(A, SW_EE2);
+  const float inv_e0 = 1.0f / asc(A, Q_E + 0);
   const int64_t E = A.row_ptr[A.n_hits];
   const int64_t ntiles = (E + kCols - 1) / kCols;
   for (int64_t tile = (int64_t)blockIdx.x * nw + wave; tile < ntiles; tile += (int64_t)gridDim.x * nw) {
@@ -131,65 +210,105 @@ __global__ __launch_bounds__(512) void k_edge_encode(GnnArgs A) {
     const bool valid = col < E;
     const int s = valid ? A.src[col] : 0, d = valid ? A.dst[col] : 0;
     float a[H / 4];
-    bias_cols<H>(a, w + S.b1());
+    bias_cols<H>(a, reinterpret_cast<const float*>(w + S.b1()));
     add_cols<H>(a, A.ps + (int64_t)s * H, valid);
     add_cols<H>(a, A.pd + (int64_t)d * H, valid);
     ln_relu<H>(a);
-    observe<H / 4>(A.calib, CAL_EE_L2, a, valid);
+    observe<H / 4>(A.calib, SC_GNN + Q_EE2, a, valid);
     float o[H / 4];
-    bias_cols<H>(o, w + S.b2());
-    mfma_f32<H, H / 16>(o, a, w + S.w2());
+    bias_cols<H>(o, reinterpret_cast<const float*>(w + S.b2()));
+    gemm<P, H, H / 16>(o, a, w + S.w2(), 1.0f / s_ee2, o_ee2);
     ln_relu<H>(o);
-    observe<H / 4>(A.calib, CAL_E, o, valid);
-    store_cols<H>(A.e + col * H, o, valid);
+    observe<H / 4>(A.calib, SC_GNN + Q_E, o, valid);
+    store_e<P, H>(A.e, col, o, valid, inv_e0);
   }
 }
 
 // --------------------------------------------------------------------------
-// messages: segmented out-sums (CSR rows) and in-sums (CSC), one wave per node
+// messages: segmented out-sums (CSR rows) and in-sums (CSC), one wave per
+// node; each lane reads 16 bytes of a row, several rows in flight per wave
 // --------------------------------------------------------------------------
-template <int H, int U>
+template <int P>
+__device__ inline void add_chunk(float* acc, uint4 v) {
+  constexpr int FPL = 16 / PrecBytes<P>::value;
+  if constexpr (P == P_F32) {
+    acc[0] += __uint_as_float(v.x); acc[1] += __uint_as_float(v.y);
+    acc[2] += __uint_as_float(v.z); acc[3] += __uint_as_float(v.w);
+  } else if constexpr (P == P_BF16) {
+    const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      acc[2 * i] += bf16_value(u[i] & 0xffffu);
+      acc[2 * i + 1] += bf16_value(u[i] >> 16);
+    }
+  } else {
+    const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[4 * i + q] += e4m3_decode((u[i] >> (8 * q)) & 0xffu);
+  }
+  (void)FPL;
+}
+
+template <int H, int P, int U>
 __global__ __launch_bounds__(256) void k_segsum(GnnArgs A) {
   if (A.status[0] != 0) return;
-  constexpr int NS = 64 / H;          // edge streams per wave (1 for H=64, 2 for H=32)
-  const int lane = lane_id(), f = lane % H, sub = lane / H, wave = threadIdx.x >> 6;
+  constexpr int ES = PrecBytes<P>::value;
+  constexpr int FPL = 16 / ES;         // features per lane
+  constexpr int LPR = H / FPL;         // lanes per row
+  constexpr int NS = 64 / LPR;         // rows in flight per load instruction
+  const int lane = lane_id(), fl = lane % LPR, st = lane / LPR, wave = threadIdx.x >> 6;
+  const char* eb = static_cast<const char*>(A.e);
+  const float scale = P == P_FP8 ? asc(A, Q_E + A.step) : 1.0f;
   for (int64_t node = (int64_t)blockIdx.x * 4 + wave; node < A.n_hits; node += (int64_t)gridDim.x * 4) {
-    // out-sum over the contiguous row
+    float mo[FPL], mi[FPL];
+#pragma unroll
+    for (int i = 0; i < FPL; ++i) mo[i] = mi[i] = 0.f;
     const int64_t rb = A.row_ptr[node], re = A.row_ptr[node + 1];
-    float mo = 0.f;
-    for (int64_t t = rb + sub; t < re; t += NS * U) {
-      float v[U];
+    for (int64_t t = rb + st; t < re; t += NS * U) {
+      uint4 v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int64_t q = t + (int64_t)u * NS;
-        v[u] = q < re ? A.e[q * H + f] : 0.f;
+        v[u] = q < re ? *reinterpret_cast<const uint4*>(eb + (q * H + fl * FPL) * ES) : make_uint4(0u, 0u, 0u, 0u);
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) mo += v[u];
+      for (int u = 0; u < U; ++u) add_chunk<P>(mo, v[u]);
     }
-    // in-sum through the CSC permutation
     const int64_t cb = A.col_ptr[node], ce = A.col_ptr[node + 1];
-    float mi = 0.f;
-    for (int64_t t = cb + sub; t < ce; t += NS * U) {
+    for (int64_t t = cb + st; t < ce; t += NS * U) {
       int id[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int64_t q = t + (int64_t)u * NS;
         id[u] = q < ce ? A.csc[q] : -1;
       }
-      float v[U];
+      uint4 v[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) v[u] = id[u] >= 0 ? A.e[(int64_t)id[u] * H + f] : 0.f;
+      for (int u = 0; u < U; ++u)
+        v[u] = id[u] >= 0 ? *reinterpret_cast<const uint4*>(eb + ((int64_t)id[u] * H + fl * FPL) * ES)
+                          : make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
-      for (int u = 0; u < U; ++u) mi += v[u];
+      for (int u = 0; u < U; ++u) add_chunk<P>(mi, v[u]);
     }
-    if (NS == 2) {
-      mo += __shfl_xor(mo, 32);
-      mi += __shfl_xor(mi, 32);
-    }
-    if (sub == 0) {
-      A.msg[node * 2 * H + f] = mo;
-      A.msg[node * 2 * H + H + f] = mi;
+    // combine the row streams of the wave in a fixed order
+#pragma unroll
+    for (int m = LPR; m < 64; m <<= 1)
+#pragma unroll
+      for (int i = 0; i < FPL; ++i) {
+        mo[i] += __shfl_xor(mo[i], m);
+        mi[i] += __shfl_xor(mi[i], m);
+      }
+    if (st == 0) {
+      float* out = A.msg + node * 2 * H + fl * FPL;
+#pragma unroll
+      for (int i = 0; i < FPL; i += 4) {
+        *reinterpret_cast<float4*>(out + i) = make_float4(mo[i] * scale, mo[i + 1] * scale, mo[i + 2] * scale,
+                                                          mo[i + 3] * scale);
+        *reinterpret_cast<float4*>(out + H + i) = make_float4(mi[i] * scale, mi[i + 1] * scale, mi[i + 2] * scale,
+                                                              mi[i + 3] * scale);
+      }
     }
   }
 }
@@ -197,14 +316,18 @@ __global__ __launch_bounds__(256) void k_segsum(GnnArgs A) {
 // --------------------------------------------------------------------------
 // node update k (+ edge net k source/target products)
 // --------------------------------------------------------------------------
-template <int H>
+template <int H, int P>
 __global__ __launch_bounds__(1024) void k_node_step(GnnArgs A) {
   if (A.status[0] != 0) return;
-  extern __shared__ float w[];
-  stage(w, A.seg, A.seg_floats);
+  extern __shared__ float lds[];
+  char* w = reinterpret_cast<char*>(lds);
+  stage_bytes(w, A.seg, A.seg_bytes);
   __syncthreads();
-  constexpr SegNode S{H};
+  constexpr SegNode S{H, PrecBytes<P>::value};
   const int lane = lane_id(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int k = A.step;
+  const float s_h = asc(A, Q_H), s_mo = asc(A, Q_MO), s_mi = asc(A, Q_MI), s_nn2 = asc(A, Q_NN2);
+  const float w1s = wsc(A, SW_STEP + 4 * k), w2s = wsc(A, SW_STEP + 4 * k + 1), wes = wsc(A, SW_STEP + 4 * k + 2);
   const int64_t ntiles = (A.n_hits + kCols - 1) / kCols;
   for (int64_t tile = (int64_t)blockIdx.x * nw + wave; tile < ntiles; tile += (int64_t)gridDim.x * nw) {
     const int64_t col = tile * kCols + (lane & 15);
@@ -213,28 +336,38 @@ __global__ __launch_bounds__(1024) void k_node_step(GnnArgs A) {
     load_cols<H>(x, A.h + col * H, valid);
     load_cols<H>(x + H / 4, A.msg + col * 2 * H, valid);
     load_cols<H>(x + H / 2, A.msg + col * 2 * H + H, valid);
-    observe<3 * H / 4>(A.calib, CAL_NN_IN + A.step, x, valid);
+    observe<H / 4>(A.calib, SC_GNN + Q_H, x, valid);
+    observe<H / 4>(A.calib, SC_GNN + Q_MO, x + H / 4, valid);
+    observe<H / 4>(A.calib, SC_GNN + Q_MI, x + H / 2, valid);
     float a[H / 4];
-    bias_cols<H>(a, w + S.b1());
-    mfma_f32<3 * H, H / 16>(a, x, w + S.w1());
+    bias_cols<H>(a, reinterpret_cast<const float*>(w + S.b1()));
+    if constexpr (P == P_FP8) {
+      // the three input blocks carry their own activation scales
+      const uint64_t* w1 = reinterpret_cast<const uint64_t*>(w + S.w1());
+      mfma_fp8<3 * H, H / 16, 0, H / 32>(a, x, w1, 1.0f / s_h, s_h * w1s);
+      mfma_fp8<3 * H, H / 16, H / 32, 2 * H / 32>(a, x, w1, 1.0f / s_mo, s_mo * w1s);
+      mfma_fp8<3 * H, H / 16, 2 * H / 32, 3 * H / 32>(a, x, w1, 1.0f / s_mi, s_mi * w1s);
+    } else {
+      gemm<P, 3 * H, H / 16>(a, x, w + S.w1(), 1.f, 1.f);
+    }
     ln_relu<H>(a);
-    observe<H / 4>(A.calib, CAL_NN_L2, a, valid);
+    observe<H / 4>(A.calib, SC_GNN + Q_NN2, a, valid);
     float o[H / 4];
-    bias_cols<H>(o, w + S.b2());
-    mfma_f32<H, H / 16>(o, a, w + S.w2());
+    bias_cols<H>(o, reinterpret_cast<const float*>(w + S.b2()));
+    gemm<P, H, H / 16>(o, a, w + S.w2(), 1.0f / s_nn2, s_nn2 * w2s);
     ln_relu<H>(o);
 #pragma unroll
     for (int r = 0; r < H / 4; ++r) o[r] += x[r];
     store_cols<H>(A.h + col * H, o, valid);
-    observe<H / 4>(A.calib, CAL_H0 + 1 + A.step, o, valid);
+    observe<H / 4>(A.calib, SC_GNN + Q_H, o, valid);
     float q[H / 4];
 #pragma unroll
     for (int r = 0; r < H / 4; ++r) q[r] = 0.f;
-    mfma_f32<H, H / 16>(q, o, w + S.ws());
+    gemm<P, H, H / 16>(q, o, w + S.ws(), 1.0f / s_h, s_h * wes);
     store_cols<H>(A.ps + col * H, q, valid);
 #pragma unroll
     for (int r = 0; r < H / 4; ++r) q[r] = 0.f;
-    mfma_f32<H, H / 16>(q, o, w + S.wd());
+    gemm<P, H, H / 16>(q, o, w + S.wd(), 1.0f / s_h, s_h * wes);
     store_cols<H>(A.pd + col * H, q, valid);
   }
 }
@@ -242,17 +375,22 @@ __global__ __launch_bounds__(1024) void k_node_step(GnnArgs A) {
 // --------------------------------------------------------------------------
 // edge update k; the last step also runs the classifier and writes scores
 // --------------------------------------------------------------------------
-template <int H, bool FINAL>
+template <int H, bool FINAL, int P>
 __global__ __launch_bounds__(512) void k_edge_step(GnnArgs A) {
   if (A.status[0] != 0) return;
-  extern __shared__ float w[];
-  constexpr SegEdge S{H};
-  constexpr SegCls C{H};
-  stage(w, A.seg, A.seg_floats);
-  if (FINAL) stage(w + S.size(), A.seg2, A.seg2_floats);
+  extern __shared__ float lds[];
+  char* w = reinterpret_cast<char*>(lds);
+  constexpr int ES = PrecBytes<P>::value;
+  constexpr SegEdge S{H, ES};
+  constexpr SegCls C{H, ES};
+  stage_bytes(w, A.seg, A.seg_bytes);
+  if (FINAL) stage_bytes(w + S.size(), A.seg2, A.seg2_bytes);
   __syncthreads();
-  const float* wc = w + S.size();
+  const char* wc = w + S.size();
   const int lane = lane_id(), g = lane_group(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int k = A.step;
+  const float s_e = asc(A, Q_E + k), s_en2 = asc(A, Q_EN2), s_next = asc(A, Q_E + k + 1);
+  const float w1s = wsc(A, SW_STEP + 4 * k + 2), w2s = wsc(A, SW_STEP + 4 * k + 3), wcs = wsc(A, SW_CLS1);
   const int64_t E = A.row_ptr[A.n_hits];
   const int64_t ntiles = (E + kCols - 1) / kCols;
   for (int64_t tile = (int64_t)blockIdx.x * nw + wave; tile < ntiles; tile += (int64_t)gridDim.x * nw) {
@@ -260,35 +398,39 @@ __global__ __launch_bounds__(512) void k_edge_step(GnnArgs A) {
     const bool valid = col < E;
     const int s = valid ? A.src[col] : 0, d = valid ? A.dst[col] : 0;
     float e[H / 4];
-    load_cols<H>(e, A.e + col * H, valid);
+    uint32_t ew[H / 16];
+    load_e<P, H>(e, ew, A.e, col, valid, s_e);
     float a[H / 4];
-    bias_cols<H>(a, w + S.b1());
+    bias_cols<H>(a, reinterpret_cast<const float*>(w + S.b1()));
     add_cols<H>(a, A.ps + (int64_t)s * H, valid);
     add_cols<H>(a, A.pd + (int64_t)d * H, valid);
-    mfma_f32<H, H / 16>(a, e, w + S.we());
+    if constexpr (P == P_FP8)
+      mfma_fp8_codes<H, H / 16>(a, ew, reinterpret_cast<const uint64_t*>(w + S.we()), s_e * w1s);
+    else
+      gemm<P, H, H / 16>(a, e, w + S.we(), 1.f, 1.f);
     ln_relu<H>(a);
-    observe<H / 4>(A.calib, CAL_EN_L2, a, valid);
+    observe<H / 4>(A.calib, SC_GNN + Q_EN2, a, valid);
     float o[H / 4];
-    bias_cols<H>(o, w + S.b2());
-    mfma_f32<H, H / 16>(o, a, w + S.w2());
+    bias_cols<H>(o, reinterpret_cast<const float*>(w + S.b2()));
+    gemm<P, H, H / 16>(o, a, w + S.w2(), 1.0f / s_en2, s_en2 * w2s);
     ln_relu<H>(o);
 #pragma unroll
     for (int r = 0; r < H / 4; ++r) o[r] += e[r];
-    observe<H / 4>(A.calib, CAL_E + 1 + A.step, o, valid);
+    observe<H / 4>(A.calib, SC_GNN + Q_E + k + 1, o, valid);
     if (!FINAL) {
-      store_cols<H>(A.e + col * H, o, valid);
+      store_e<P, H>(A.e, col, o, valid, 1.0f / s_next);
     } else {
-      observe<H / 4>(A.calib, CAL_CLS_IN, o, valid);
+      // classifier on the final edge encodings (quantised like a stored e_S)
       float c[H / 4];
-      bias_cols<H>(c, wc + C.b1());
-      mfma_f32<H, H / 16>(c, o, wc + C.w1());
+      bias_cols<H>(c, reinterpret_cast<const float*>(wc + C.b1()));
+      gemm<P, H, H / 16>(c, o, wc + C.w1(), 1.0f / s_next, s_next * wcs);
       ln_relu<H>(c);
-      observe<H / 4>(A.calib, CAL_CLS_L2, c, valid);
+      const float* w2 = reinterpret_cast<const float*>(wc + C.w2());
       float dot = 0.f;
 #pragma unroll
-      for (int r = 0; r < H / 4; ++r) dot = fmaf(c[r], wc[C.w2() + phi(r, g)], dot);
+      for (int r = 0; r < H / 4; ++r) dot = fmaf(c[r], w2[phi(r, g)], dot);
       dot = col_sum(dot);
-      const float logit = dot + wc[C.b2()];
+      const float logit = dot + reinterpret_cast<const float*>(wc + C.b2())[0];
       if (valid && g == 0) A.score[col] = 1.0f / (1.0f + expf(-logit));
     }
   }
@@ -318,11 +460,11 @@ static GnnArgs gnn_args(const RunArgs& a) {
   A.ps = reinterpret_cast<float*>(a.ws + a.L.ps);
   A.pd = reinterpret_cast<float*>(a.ws + a.L.pd);
   A.msg = reinterpret_cast<float*>(a.ws + a.L.msg);
-  A.e = reinterpret_cast<float*>(a.ws + a.L.e);
+  A.e = a.ws + a.L.e;
   A.score = a.out.score;
   A.calib = a.calibrate ? reinterpret_cast<float*>(a.ws + a.L.calib) : nullptr;
+  A.sc = c->dev_scales;
   A.status = a.out.status;
-  A.unroll = c->segsum_unroll;
   return A;
 }
 
@@ -335,22 +477,30 @@ static unsigned node_grid(const RunArgs& a, int per_cu) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles + waves - 1) / waves, (int64_t)a.ctx->n_cu * per_cu));
 }
 
-#define DISPATCH_H(H_, ...)                    \
-  switch (H_) {                                \
-    case 32: { constexpr int H = 32; __VA_ARGS__; } break; \
-    case 64: { constexpr int H = 64; __VA_ARGS__; } break; \
-    default: return hipErrorInvalidValue;      \
+static const char* seg_ptr(const RunArgs& a, int64_t off) {
+  return static_cast<const char*>(a.ctx->seg_base[a.prec]) + off;
+}
+
+#define DISPATCH_HP(H_, P_, ...)                                            \
+  switch ((H_) * 4 + (P_)) {                                                \
+    case 32 * 4 + 0: { constexpr int H = 32, P = 0; __VA_ARGS__; } break;  \
+    case 32 * 4 + 1: { constexpr int H = 32, P = 1; __VA_ARGS__; } break;  \
+    case 32 * 4 + 2: { constexpr int H = 32, P = 2; __VA_ARGS__; } break;  \
+    case 64 * 4 + 0: { constexpr int H = 64, P = 0; __VA_ARGS__; } break;  \
+    case 64 * 4 + 1: { constexpr int H = 64, P = 1; __VA_ARGS__; } break;  \
+    case 64 * 4 + 2: { constexpr int H = 64, P = 2; __VA_ARGS__; } break;  \
+    default: return hipErrorInvalidValue;                                   \
   }
 
 hipError_t launch_node_encode(const RunArgs& a) {
   if (a.hits.n_hits == 0) return hipSuccess;
   GnnArgs A = gnn_args(a);
   const int Hh = a.ctx->cfg.gnn_hidden;
-  A.seg = a.ctx->dev_w + a.ctx->wmap.node_enc;
-  A.seg_floats = SegNodeEnc{Hh}.size();
-  size_t lds = sizeof(float) * A.seg_floats;
+  const WeightMap& m = a.ctx->wmap[a.prec];
+  A.seg = seg_ptr(a, m.node_enc);
+  A.seg_bytes = SegNodeEnc{Hh, kPrecBytes[a.prec]}.size();
   unsigned grid = node_grid(a, a.ctx->node_wg_per_cu);
-  DISPATCH_H(Hh, hipLaunchKernelGGL(k_node_encode<H>, dim3(grid), dim3(kNodeThreads), lds, a.stream, A));
+  DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_node_encode<H, P>), dim3(grid), dim3(kNodeThreads), A.seg_bytes, a.stream, A));
   return hipGetLastError();
 }
 
@@ -358,21 +508,22 @@ hipError_t launch_edge_encode(const RunArgs& a) {
   if (a.hits.n_hits == 0) return hipSuccess;
   GnnArgs A = gnn_args(a);
   const int Hh = a.ctx->cfg.gnn_hidden;
-  A.seg = a.ctx->dev_w + a.ctx->wmap.edge_enc;
-  A.seg_floats = SegEdgeEnc{Hh}.size();
-  size_t lds = sizeof(float) * A.seg_floats;
+  const WeightMap& m = a.ctx->wmap[a.prec];
+  A.seg = seg_ptr(a, m.edge_enc);
+  A.seg_bytes = SegEdgeEnc{Hh, kPrecBytes[a.prec]}.size();
   unsigned grid = (unsigned)(a.ctx->n_cu * a.ctx->edge_wg_per_cu);
-  DISPATCH_H(Hh, hipLaunchKernelGGL(k_edge_encode<H>, dim3(grid), dim3(kEdgeThreads), lds, a.stream, A));
+  DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_edge_encode<H, P>), dim3(grid), dim3(kEdgeThreads), A.seg_bytes, a.stream, A));
   return hipGetLastError();
 }
 
-hipError_t launch_segsum(const RunArgs& a) {
+hipError_t launch_segsum(const RunArgs& a, int k) {
   if (a.hits.n_hits == 0) return hipSuccess;
   GnnArgs A = gnn_args(a);
+  A.step = k;
   const int Hh = a.ctx->cfg.gnn_hidden;
   unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((a.hits.n_hits + 3) / 4, (int64_t)a.ctx->n_cu * 32));
   const int U = a.ctx->segsum_unroll;
-#define SEG_U(U_) DISPATCH_H(Hh, hipLaunchKernelGGL((k_segsum<H, U_>), dim3(grid), dim3(256), 0, a.stream, A))
+#define SEG_U(U_) DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_segsum<H, P, U_>), dim3(grid), dim3(256), 0, a.stream, A))
   switch (U) {
     case 1: SEG_U(1); break;
     case 2: SEG_U(2); break;
@@ -387,12 +538,12 @@ hipError_t launch_node_step(const RunArgs& a, int k) {
   if (a.hits.n_hits == 0) return hipSuccess;
   GnnArgs A = gnn_args(a);
   const int Hh = a.ctx->cfg.gnn_hidden;
-  A.seg = a.ctx->dev_w + a.ctx->wmap.node[k];
-  A.seg_floats = SegNode{Hh}.size();
+  const WeightMap& m = a.ctx->wmap[a.prec];
+  A.seg = seg_ptr(a, m.node[k]);
+  A.seg_bytes = SegNode{Hh, kPrecBytes[a.prec]}.size();
   A.step = k;
-  size_t lds = sizeof(float) * A.seg_floats;
   unsigned grid = node_grid(a, a.ctx->node_wg_per_cu);
-  DISPATCH_H(Hh, hipLaunchKernelGGL(k_node_step<H>, dim3(grid), dim3(kNodeThreads), lds, a.stream, A));
+  DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_node_step<H, P>), dim3(grid), dim3(kNodeThreads), A.seg_bytes, a.stream, A));
   return hipGetLastError();
 }
 
@@ -400,36 +551,56 @@ hipError_t launch_edge_step(const RunArgs& a, int k, bool final_step) {
   if (a.hits.n_hits == 0) return hipSuccess;
   GnnArgs A = gnn_args(a);
   const int Hh = a.ctx->cfg.gnn_hidden;
-  A.seg = a.ctx->dev_w + a.ctx->wmap.edge[k];
-  A.seg_floats = SegEdge{Hh}.size();
-  A.seg2 = a.ctx->dev_w + a.ctx->wmap.cls;
-  A.seg2_floats = SegCls{Hh}.size();
+  const WeightMap& m = a.ctx->wmap[a.prec];
+  A.seg = seg_ptr(a, m.edge[k]);
+  A.seg_bytes = SegEdge{Hh, kPrecBytes[a.prec]}.size();
+  A.seg2 = seg_ptr(a, m.cls);
+  A.seg2_bytes = SegCls{Hh, kPrecBytes[a.prec]}.size();
   A.step = k;
-  size_t lds = sizeof(float) * (A.seg_floats + (final_step ? A.seg2_floats : 0));
+  size_t lds = A.seg_bytes + (final_step ? A.seg2_bytes : 0);
   unsigned grid = (unsigned)(a.ctx->n_cu * a.ctx->edge_wg_per_cu);
   if (final_step) {
-    DISPATCH_H(Hh, hipLaunchKernelGGL((k_edge_step<H, true>), dim3(grid), dim3(kEdgeThreads), lds, a.stream, A));
+    DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_edge_step<H, true, P>), dim3(grid), dim3(kEdgeThreads), lds, a.stream, A));
   } else {
-    DISPATCH_H(Hh, hipLaunchKernelGGL((k_edge_step<H, false>), dim3(grid), dim3(kEdgeThreads), lds, a.stream, A));
+    DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_edge_step<H, false, P>), dim3(grid), dim3(kEdgeThreads), lds, a.stream, A));
   }
   return hipGetLastError();
 }
 
-int gnn_attributes(size_t max_lds) {
-  int bad = 0;
+__global__ void k_quantize(int prec, const float* __restrict__ in, float* __restrict__ out, int64_t n, float scale) {
+  const float inv = 1.0f / scale;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float x = in[i];
+    out[i] = prec == P_BF16 ? bf16_value(bf16_bits(x)) : (prec == P_FP8 ? e4m3_decode(e4m3_encode(x * inv)) * scale : x);
+  }
+}
+
+hipError_t launch_quantize(int prec, const float* in, float* out, int64_t n, float scale, hipStream_t s) {
+  unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_quantize, dim3(grid), dim3(256), 0, s, prec, in, out, n, scale);
+  return hipGetLastError();
+}
+
+template <int H, int P>
+static void set_gnn_attr(int& bad, size_t max_lds) {
   auto set = [&](const void* f) {
     bad |= hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) != hipSuccess;
   };
-  set(reinterpret_cast<const void*>(k_node_encode<32>));
-  set(reinterpret_cast<const void*>(k_node_encode<64>));
-  set(reinterpret_cast<const void*>(k_node_step<32>));
-  set(reinterpret_cast<const void*>(k_node_step<64>));
-  set(reinterpret_cast<const void*>(k_edge_step<32, true>));
-  set(reinterpret_cast<const void*>(k_edge_step<64, true>));
-  set(reinterpret_cast<const void*>(k_edge_step<32, false>));
-  set(reinterpret_cast<const void*>(k_edge_step<64, false>));
-  set(reinterpret_cast<const void*>(k_edge_encode<32>));
-  set(reinterpret_cast<const void*>(k_edge_encode<64>));
+  set(reinterpret_cast<const void*>(k_node_encode<H, P>));
+  set(reinterpret_cast<const void*>(k_node_step<H, P>));
+  set(reinterpret_cast<const void*>(k_edge_step<H, true, P>));
+  set(reinterpret_cast<const void*>(k_edge_step<H, false, P>));
+  set(reinterpret_cast<const void*>(k_edge_encode<H, P>));
+}
+
+int gnn_attributes(size_t max_lds) {
+  int bad = 0;
+  set_gnn_attr<32, 0>(bad, max_lds);
+  set_gnn_attr<32, 1>(bad, max_lds);
+  set_gnn_attr<32, 2>(bad, max_lds);
+  set_gnn_attr<64, 0>(bad, max_lds);
+  set_gnn_attr<64, 1>(bad, max_lds);
+  set_gnn_attr<64, 2>(bad, max_lds);
   return bad;
 }
 

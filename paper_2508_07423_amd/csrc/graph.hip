@@ -349,11 +349,13 @@ hipError_t launch_bucket(const RunArgs& a) {
   return hipGetLastError();
 }
 
-hipError_t launch_scan_counts(const RunArgs& a) {
+hipError_t launch_scan_counts(const RunArgs& a, bool candidates) {
+  // counts (ws.cnt) -> CSR offsets: the candidate offsets of the prefilter
+  // path, or the main row_ptr (+ per-event edge offsets)
   const int64_t n = a.hits.n_hits;
   const int64_t nb = a.L.n_scan_blocks;
   int64_t* part = WS(a, scan_tmp, int64_t);
-  int64_t* row_ptr = WS(a, row_ptr, int64_t);
+  int64_t* row_ptr = candidates ? WS(a, pf_tmp, int64_t) : WS(a, row_ptr, int64_t);
   if (nb > 0)
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(256), 0, a.stream, WS(a, cnt, int32_t), n, part,
                        a.out.status);
@@ -362,9 +364,11 @@ hipError_t launch_scan_counts(const RunArgs& a) {
   if (nb > 0)
     hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(256), 0, a.stream, WS(a, cnt, int32_t), n, part, row_ptr,
                        a.out.status);
-  int64_t ne = a.hits.n_events + 1;
-  hipLaunchKernelGGL(k_edge_off, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, a.stream, a.hits.hit_off,
-                     a.hits.n_events, row_ptr, a.out.edge_off, a.out.status);
+  if (!candidates) {
+    int64_t ne = a.hits.n_events + 1;
+    hipLaunchKernelGGL(k_edge_off, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, a.stream, a.hits.hit_off,
+                       a.hits.n_events, row_ptr, a.out.edge_off, a.out.status);
+  }
   return hipGetLastError();
 }
 

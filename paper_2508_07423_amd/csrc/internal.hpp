@@ -16,22 +16,9 @@ constexpr int kTile = 32;          // columns (hits or edges) per wave tile
 constexpr int kDpad = 16;          // padded embedding width in HBM
 constexpr int kScanBlock = 1024;   // elements per block of the device-wide scan
 
-// Calibration observer slots (absolute maxima of quantised activations).
-enum CalibSlot {
-  CAL_EMB_IN = 0,                  // + layer (embedding GEMM inputs, layers >= 1), 4 slots
-  CAL_NE_L2 = 4,                   // node encoder layer-2 input
-  CAL_H0 = 5,                      // node encodings (inputs of Ws/Wd products), per step: CAL_H0 + k
-  CAL_EE_L2 = 22,                  // edge encoder layer-2 input
-  CAL_E = 23,                      // stored edge encodings: CAL_E + k (k = 0..S)
-  CAL_NN_IN = 40,                  // node net k layer-1 input [h, mo, mi] (one scale): + k
-  // the remaining slots hold layer-2 inputs and classifier inputs
-  CAL_NN_L2 = 56,                  // node net layer-2 inputs (shared over steps)
-  CAL_EN_L2 = 57,                  // edge net layer-2 inputs (shared over steps)
-  CAL_CLS_IN = 58,                 // classifier layer-1 input
-  CAL_CLS_L2 = 59,                 // classifier hidden
-};
+constexpr int kPrecBytes[3] = {4, 2, 1};   // GEMM operand bytes: FP32, BF16, FP8
 
-// Offsets (in floats) of the per-kernel weight segments in the device buffer.
+// Offsets (in bytes) of the per-kernel weight segments in a precision's device buffer.
 struct WeightMap {
   int64_t emb = 0;                 // embedding segment
   int64_t node_enc = 0;            // node encoder + edge-encoder source/target products
@@ -45,7 +32,7 @@ struct WeightMap {
 // Byte offsets of the workspace buffers.
 struct WsLayout {
   size_t bucket, plane_off, emb, cnt, row_ptr, scan_tmp, col_ptr, csc, h, ps, pd, msg, e, kept, kept_cnt,
-      calib, pf_keep, pf_tmp, pf_grad, total;
+      calib, pf_keep, pf_tmp, cand_src, cand_dst, pf_part, pf_grad, total;
   int64_t n_scan_blocks;
 };
 
@@ -61,14 +48,11 @@ struct etx_ctx {
   etx_config cfg;
   int device = 0;
   int n_cu = 256;
-  float* dev_w = nullptr;          // FP32 weight segments
-  etx::WeightMap wmap;
-  void* dev_wq = nullptr;          // low-precision (BF16/FP8) weight copies
-  int64_t wq_bytes = 0;
-  std::vector<int64_t> wq_off;     // per-layer offsets into dev_wq (bytes)
-  float* dev_scales = nullptr;     // [ETX_N_CALIB] activation scales + weight scales
+  void* seg_base[3] = {};          // weight segments per operand precision (FP32, BF16, FP8)
+  etx::WeightMap wmap[3];
+  float* dev_scales = nullptr;     // [256] per-tensor scales: activations 0..63, weights 64..255
+  float host_scales[256] = {};
   bool calibrated = false;
-  std::vector<float> host_blob;    // the weight payload (for etx_set_precision rebuilds)
   // prefilter (params, Adam m, v) in FP32 on the device
   float* dev_pf = nullptr;
   bool pf_set = false;
@@ -99,15 +83,16 @@ struct RunArgs {
   WsLayout L;
   char* ws;
   hipStream_t stream;
-  bool calibrate;                  // record amax observers
+  bool calibrate;                  // record amax observers (FP32 run)
+  int prec;                        // GEMM operand precision of this run (etx_precision)
 };
 
 // launchers (graph.hip)
 hipError_t launch_init_status(const RunArgs& a);
 hipError_t launch_validate(const RunArgs& a);
 hipError_t launch_bucket(const RunArgs& a);
-hipError_t launch_radius(const RunArgs& a, bool emit);
-hipError_t launch_scan_counts(const RunArgs& a);
+hipError_t launch_radius(const RunArgs& a, bool emit, bool candidates);
+hipError_t launch_scan_counts(const RunArgs& a, bool candidates);
 hipError_t launch_csc(const RunArgs& a);
 hipError_t launch_compact(const RunArgs& a);
 hipError_t launch_union_find(const RunArgs& a);
@@ -116,13 +101,18 @@ hipError_t launch_embed(const RunArgs& a);
 // launchers (gnn.hip)
 hipError_t launch_node_encode(const RunArgs& a);
 hipError_t launch_edge_encode(const RunArgs& a);
-hipError_t launch_segsum(const RunArgs& a);
+hipError_t launch_segsum(const RunArgs& a, int k);
 hipError_t launch_node_step(const RunArgs& a, int k);
 hipError_t launch_edge_step(const RunArgs& a, int k, bool final_step);
 // launchers (prefilter.hip)
-hipError_t launch_prefilter_infer(const RunArgs& a);
+hipError_t launch_prefilter_infer(const RunArgs& a);        // candidates -> keep flags -> compacted edges
+hipError_t launch_prefilter_count(const RunArgs& a);
+hipError_t launch_prefilter_compact(const RunArgs& a);
 hipError_t launch_prefilter_train(const RunArgs& a, const uint8_t* labels, float lr, float pos_weight, int64_t step,
                                   float* loss_dev);
+constexpr int kPfGradStride = 1320;                         // floats per wave partial of the prefilter gradient
+constexpr int kPfMaxWaves = 256 * 2 * 8;                    // partial slots (CUs x workgroups x waves)
+hipError_t launch_quantize(int prec, const float* in, float* out, int64_t n, float scale, hipStream_t s);
 
 int set_kernel_attributes();
 

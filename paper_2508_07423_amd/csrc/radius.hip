@@ -348,7 +348,7 @@ __global__ __launch_bounds__(kRadiusThreads) void k_radius(RadiusArgs A) {
 
 }  // namespace
 
-hipError_t launch_radius(const RunArgs& a, bool emit) {
+hipError_t launch_radius(const RunArgs& a, bool emit, bool candidates) {
   if (a.hits.n_events == 0) return hipSuccess;
   const etx_config& c = a.ctx->cfg;
   RadiusArgs A;
@@ -363,9 +363,10 @@ hipError_t launch_radius(const RunArgs& a, bool emit) {
   A.r = c.radius;
   A.r2 = c.radius * c.radius;
   A.cnt = reinterpret_cast<int32_t*>(a.ws + a.L.cnt);
-  A.row_ptr = reinterpret_cast<const int64_t*>(a.ws + a.L.row_ptr);
-  A.src = a.out.src;
-  A.dst = a.out.dst;
+  // with the prefilter the candidate graph goes to workspace buffers first
+  A.row_ptr = reinterpret_cast<const int64_t*>(a.ws + (candidates ? a.L.pf_tmp : a.L.row_ptr));
+  A.src = candidates ? reinterpret_cast<int32_t*>(a.ws + a.L.cand_src) : a.out.src;
+  A.dst = candidates ? reinterpret_cast<int32_t*>(a.ws + a.L.cand_dst) : a.out.dst;
   A.status = a.out.status;
   dim3 grid((unsigned)(a.hits.n_events * c.n_planes));
   const bool small = c.emb_dim <= 8;

@@ -132,6 +132,102 @@ __device__ inline void mfma_bf16(float* acc, const float* x, const bf16x8* __res
     for (int v = 0; v < 4; ++v) acc[4 * mb + v] = c[mb][v];
 }
 
+// ---------------------------------------------------------------------------
+// low-precision formats
+// ---------------------------------------------------------------------------
+
+enum Prec { P_F32 = 0, P_BF16 = 1, P_FP8 = 2 };
+template <int P>
+struct PrecBytes { static constexpr int value = P == P_F32 ? 4 : (P == P_BF16 ? 2 : 1); };
+
+// OCP FP8 E4M3 (bias 7, 3 mantissa bits, subnormals, max 448, no infinity):
+// round to nearest even, saturate to +-448 (NaN maps to 0).
+__device__ inline uint32_t e4m3_encode(float x) {
+  const uint32_t sign = (__float_as_uint(x) >> 24) & 0x80u;
+  float a = fabsf(x);
+  if (!(a == a)) return 0u;
+  a = fminf(a, 448.f);
+  uint32_t code;
+  if (a < 0.015625f) {                                   // below 2^-6: spacing 2^-9
+    code = (uint32_t)__builtin_rintf(a * 512.f);         // 8 is the smallest normal
+  } else {
+    const int e = (int)((__float_as_uint(a) >> 23) & 0xffu) - 127;        // -6 .. 8
+    const float m = a * __uint_as_float((uint32_t)(127 - e) << 23);       // a / 2^e in [1, 2)
+    const uint32_t q = (uint32_t)__builtin_rintf((m - 1.f) * 8.f);        // 0 .. 8 (8 carries)
+    code = min(((uint32_t)(e + 7) << 3) + q, 0x7Eu);
+  }
+  return sign | code;
+}
+
+__device__ inline float e4m3_decode(uint32_t c) {
+  const uint32_t e = (c >> 3) & 15u, m = c & 7u;
+  const float v = e ? __uint_as_float(((e + 120u) << 23) | (m << 20)) : (float)m * 0.001953125f;
+  return __uint_as_float(__float_as_uint(v) | ((c & 0x80u) << 24));
+}
+
+__device__ inline uint32_t bf16_bits(float x) { return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)x); }
+__device__ inline float bf16_value(uint32_t b) { return __uint_as_float(b << 16); }
+
+// FP8 operands, K-steps of 32: lane group g supplies registers 8t..8t+7 as
+// codes of x * inv_s; w holds 8 codes per lane per step (same order as BF16).
+// acc += out_scale * (W_q^T x_q).
+// T0..T1 restricts the K-steps (one input block of a concatenated operand).
+template <int K, int MB, int T0 = 0, int T1 = K / 32>
+__device__ inline void mfma_fp8(float* acc, const float* x, const uint64_t* __restrict__ w, float inv_s,
+                                float out_scale) {
+  const int lane = lane_id();
+  floatx4 c[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) c[mb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = T0; t < T1; ++t) {
+    uint64_t b = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) b |= (uint64_t)e4m3_encode(x[8 * t + q] * inv_s) << (8 * q);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+      c[mb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8((long)w[(mb * (K / 32) + t) * 64 + lane], (long)b, c[mb], 0, 0, 0);
+  }
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[4 * mb + v] = fmaf(out_scale, c[mb][v], acc[4 * mb + v]);
+}
+
+// Same with the operand already as FP8 codes: word c of a lane holds the codes
+// of registers 4c .. 4c+3 (the stored edge encodings).
+template <int K, int MB>
+__device__ inline void mfma_fp8_codes(float* acc, const uint32_t* xw, const uint64_t* __restrict__ w, float out_scale) {
+  const int lane = lane_id();
+  floatx4 c[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) c[mb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < K / 32; ++t) {
+    const uint64_t b = (uint64_t)xw[2 * t] | ((uint64_t)xw[2 * t + 1] << 32);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+      c[mb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8((long)w[(mb * (K / 32) + t) * 64 + lane], (long)b, c[mb], 0, 0, 0);
+  }
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[4 * mb + v] = fmaf(out_scale, c[mb][v], acc[4 * mb + v]);
+}
+
+// One Linear layer in precision P: acc += W^T x with weights w (permuted for
+// P); FP8 quantises x with inv_s and rescales the product by out_scale.
+template <int P, int K, int MB>
+__device__ inline void gemm(float* acc, const float* x, const void* w, float inv_s, float out_scale) {
+  if constexpr (P == P_F32) {
+    mfma_f32<K, MB>(acc, x, static_cast<const float*>(w));
+  } else if constexpr (P == P_BF16) {
+    mfma_bf16<K, MB>(acc, x, static_cast<const bf16x8*>(w));
+  } else {
+    mfma_fp8<K, MB>(acc, x, static_cast<const uint64_t*>(w), inv_s, out_scale);
+  }
+}
+
 // Sum over the four lanes of a column.
 __device__ inline float col_sum(float s) {
   s += __shfl_xor(s, 16);

@@ -24,7 +24,7 @@ ETX_N_CALIB = 64
 ETX_PF_HIDDEN = 32
 ETX_PF_NPARAM = 6 * 32 + 32 + 32 * 32 + 32 + 32 + 1
 (ETX_VIEW_EMBEDDING, ETX_VIEW_BUCKET, ETX_VIEW_PLANE_OFF, ETX_VIEW_ROW_PTR, ETX_VIEW_COL_PTR, ETX_VIEW_CSC_EDGE,
- ETX_VIEW_NODE_H, ETX_VIEW_KEPT_EDGE, ETX_VIEW_KEPT_COUNT, ETX_VIEW_CALIB, ETX_VIEW_PF_KEEP) = range(11)
+ ETX_VIEW_NODE_H, ETX_VIEW_KEPT_EDGE, ETX_VIEW_KEPT_COUNT, ETX_VIEW_CALIB, ETX_VIEW_PF_KEEP, ETX_VIEW_PF_GRAD) = range(12)
 (ETX_OPT_USE_GRAPH, ETX_OPT_EDGE_WG_PER_CU, ETX_OPT_NODE_WG_PER_CU, ETX_OPT_RADIUS_LDS,
  ETX_OPT_SEGSUM_UNROLL, ETX_OPT_PROFILE) = range(6)
 N_STAGES = 17
@@ -76,6 +76,8 @@ def lib():
                                          P, sz, P],
             "etx_prefilter_state": [P, P, i64, i32],
             "etx_profile_read": [P, i32, P, P],
+            "etx_get_scales": [P, P, i32],
+            "etx_quantize": [i32, P, P, i64, C.c_float, P],
             "etx_profile_reset": [P],
         }
         for name, args in sig.items():
@@ -96,7 +98,7 @@ EXPORTED = ["etx_create", "etx_destroy", "etx_weight_blob_size", "etx_workspace_
             "etx_workspace_view", "etx_set_option", "etx_get_option", "etx_autotune", "etx_calibrate",
             "etx_set_precision", "etx_prefilter_set", "etx_prefilter_get", "etx_prefilter_train_step",
             "etx_prefilter_state", "etx_status_str", "etx_last_error", "etx_profile_read", "etx_profile_reset",
-            "etx_stage_name"]
+            "etx_stage_name", "etx_get_scales", "etx_quantize"]
 
 
 class EtxError(RuntimeError):
@@ -176,6 +178,17 @@ def etx_calibrate(ctx, hits, out, ws_ptr, ws_bytes, stream) -> None:
 
 def etx_set_precision(ctx, precision: int) -> None:
     _check(lib().etx_set_precision(ctx, precision), "etx_set_precision")
+
+
+def etx_get_scales(ctx, n: int = 256) -> np.ndarray:
+    s = np.zeros(n, np.float32)
+    _check(lib().etx_get_scales(ctx, s.ctypes.data_as(C.c_void_p), n), "etx_get_scales")
+    return s
+
+
+def etx_quantize(precision: int, in_ptr: int, out_ptr: int, n: int, scale: float, stream: int) -> None:
+    _check(lib().etx_quantize(precision, C.c_void_p(in_ptr), C.c_void_p(out_ptr), n, scale, C.c_void_p(stream)),
+           "etx_quantize")
 
 
 def etx_prefilter_set(ctx, params: np.ndarray) -> None:
@@ -315,6 +328,26 @@ class Pipeline:
             self._shape = shape
         return etx_out(self.cap, self.src.data_ptr(), self.dst.data_ptr(), self.score.data_ptr(),
                        self.edge_off.data_ptr(), self.labels.data_ptr(), self.status.data_ptr())
+
+    def calibrate(self, b: Batch, stream=None):
+        """Static calibration of the per-tensor scales on batch ``b`` (etx_calibrate)."""
+        import torch
+        out = self.allocate(b)
+        s = torch.cuda.current_stream(self.device) if stream is None else stream
+        etx_calibrate(self.ctx, self.hits_struct(b), out, self.ws_ptr, self.ws_bytes, s.cuda_stream)
+
+    def prefilter_train_step(self, b: Batch, labels, lr: float, pos_weight: float, step: int, stream=None):
+        """One on-device training step of the prefilter on the candidate edges
+        of ``b`` (labels: uint8 device tensor in candidate order); returns the
+        device loss tensor."""
+        import torch
+        out = self.allocate(b)
+        if not hasattr(self, "_loss"):
+            self._loss = torch.zeros(1, dtype=torch.float32, device=torch.device("cuda", self.device))
+        s = torch.cuda.current_stream(self.device) if stream is None else stream
+        etx_prefilter_train_step(self.ctx, self.hits_struct(b), out, labels.data_ptr(), lr, pos_weight, step,
+                                 self._loss.data_ptr(), self.ws_ptr, self.ws_bytes, s.cuda_stream)
+        return self._loss
 
     def run(self, b: Batch, edge_capacity: Optional[int] = None, stream=None):
         import torch

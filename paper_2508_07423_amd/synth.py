@@ -18,6 +18,7 @@ drawn with seed ``s`` uses ``SeedSequence([s, l])``.
 """
 from __future__ import annotations
 
+import os
 from dataclasses import dataclass, field, replace
 from typing import Dict, List, Optional, Tuple
 
@@ -219,3 +220,23 @@ def xavier_prefilter(seed: int = 7, hidden: int = 32) -> List[Tuple[np.ndarray, 
         a = np.sqrt(6.0 / (fi + fo))
         out.append((rng.uniform(-a, a, (fi, fo)).astype(np.float32), np.zeros(fo, np.float32)))
     return out
+
+
+def load_weights(path: str) -> Dict[str, List[Tuple[np.ndarray, np.ndarray]]]:
+    """Weights written by train_weights.save (npz, no pickled objects)."""
+    z = np.load(path, allow_pickle=False)
+    out: Dict[str, List[Tuple[np.ndarray, np.ndarray]]] = {}
+    keys = sorted({k.rsplit(".", 2)[0] for k in z.files})
+    for net in keys:
+        n = len([k for k in z.files if k.startswith(net + ".") and k.endswith(".W")])
+        out[net] = [(z[f"{net}.{i}.W"].astype(np.float32), z[f"{net}.{i}.b"].astype(np.float32)) for i in range(n)]
+    return out
+
+
+TRAINED_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights")
+
+
+def trained_weights(w: Workload) -> Dict[str, List[Tuple[np.ndarray, np.ndarray]]]:
+    """The committed trained weight set of a workload's network (train_weights.py)."""
+    name = {"c1": "c3", "c3": "c3", "c5": "c3", "c2": "c2", "c4": "c2"}[w.name]
+    return load_weights(os.path.join(TRAINED_DIR, f"{name}_trained.npz"))

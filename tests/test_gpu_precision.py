@@ -1,0 +1,137 @@
+"""Low-precision operands (BF16, FP8-E4M3 with per-tensor power-of-two
+scales) against the quantised FP64 oracle, which rounds the same operands
+exactly (thesis ch. 4 "Quantization": x = S x_q, x_q = round(x / S), clipped).
+
+The GPU differs from the quantised oracle only by FP32 accumulation order and
+by the rare activation that lands within FP32 rounding of a BF16/FP8 rounding
+boundary; the error bounds below are set for that.  The error against the
+plain FP64 oracle is reported (the precision cost), not bounded tightly.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2508_07423_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _etx():
+    from paper_2508_07423_amd import etx
+    return etx
+
+
+def gpu_quantize(prec, x, scale):
+    etx = _etx()
+    t = torch.as_tensor(np.asarray(x, np.float32)).cuda()
+    o = torch.empty_like(t)
+    etx.etx_quantize(prec, t.data_ptr(), o.data_ptr(), t.numel(), scale, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    return o.cpu().numpy().astype(np.float64)
+
+
+def e4m3_values():
+    v = []
+    for code in range(256):
+        s, e, m = code >> 7, (code >> 3) & 15, code & 7
+        if e == 15 and m == 7:
+            continue
+        x = (m / 8) * 2.0 ** -6 if e == 0 else (1 + m / 8) * 2.0 ** (e - 7)
+        v.append(-x if s else x)
+    return np.unique(np.array(v))
+
+
+@pytest.mark.parametrize("scale", [1.0, 2.0 ** -7, 2.0 ** 5])
+def test_fp8_cast_matches_oracle_exhaustively(scale):
+    etx = _etx()
+    vals = e4m3_values()
+    pos = vals[vals >= 0]
+    mids = 0.5 * (pos[:-1] + pos[1:])
+    x = np.concatenate([vals, mids, -mids, np.nextafter(mids.astype(np.float32), np.float32(0)),
+                        np.nextafter(mids.astype(np.float32), np.float32(1e9)), [448.0, 464.0, 500.0, 1e6, -1e6, 0.0],
+                        np.random.default_rng(0).normal(0, 50, 4000), np.random.default_rng(1).normal(0, 0.01, 4000)])
+    x = (x.astype(np.float32).astype(np.float64) * scale).astype(np.float32)
+    got = gpu_quantize(etx.ETX_FP8_E4M3, x, scale)
+    ref = np.array([scale * O.round_e4m3(float(v) / scale) for v in x])
+    bad = np.nonzero(got != ref)[0]
+    assert len(bad) == 0, list(zip(x[bad][:5], got[bad][:5], ref[bad][:5]))
+
+
+def test_bf16_cast_matches_oracle():
+    etx = _etx()
+    rng = np.random.default_rng(3)
+    x = np.concatenate([rng.normal(0, 1, 20000), rng.normal(0, 1e-30, 1000), rng.normal(0, 1e30, 1000)]).astype(np.float32)
+    # exact midpoints between neighbouring BF16 values (finite, normal range)
+    b = (rng.integers(0, 2 ** 15, 4000).astype(np.uint32) << 16) | 0x8000
+    mid = b.view(np.float32)
+    mid = mid[np.isfinite(mid) & (np.abs(mid) >= np.float32(2.0 ** -126))]
+    x = np.concatenate([x, mid])
+    got = gpu_quantize(etx.ETX_BF16, x, 1.0)
+    ref = np.array([O.round_bf16(float(v)) for v in x])
+    bad = np.nonzero(got != ref)[0]
+    assert len(bad) == 0, [(float(x[i]), got[i], ref[i]) for i in bad[:8]]
+
+
+def _run(w, W, batch, prec, cal=None):
+    etx = _etx()
+    p = etx.Pipeline(w, W, precision=prec)
+    if cal is not None:
+        p.calibrate(etx.to_device(cal))
+    b = etx.to_device(batch)
+    p.run(b)
+    return p, p.results(b)
+
+
+def _score_stats(gpu, ref):
+    d = np.abs(gpu.astype(np.float64) - ref)
+    return dict(max=float(d.max()), mean=float(d.mean()), p99=float(np.quantile(d, 0.99)))
+
+
+def test_bf16_pipeline_against_quantised_oracle():
+    etx = _etx()
+    w = synth.C1
+    W = synth.xavier_weights(w)
+    batch = synth.generate_batch(w, 1)
+    ev = synth.event_slice(batch, 0)
+    p, res = _run(w, W, batch, etx.ETX_BF16)
+    ref_q = O.run_event(ev, w, W, qmode=1)
+    ref_64 = O.run_event(ev, w, W)
+    assert np.array_equal(res["src"], ref_q["src"]) and np.array_equal(res["dst"], ref_q["dst"])
+    sq = _score_stats(res["score"], ref_q["score"])
+    print("bf16 vs quantised oracle", sq)
+    print("bf16 vs fp64 oracle", _score_stats(res["score"], O.sigmoid(O.gnn(
+        O.features(ev["x"], ev["y"], ev["z"], w.r_scale, w.z_scale)[1], res["src"], res["dst"], W,
+        w.gnn_hidden, w.gnn_steps))))
+    assert sq["mean"] <= 1e-4 and sq["max"] <= 1e-2
+    # embedding in BF16 agrees with the quantised oracle embedding
+    emb = p.view(etx.to_device(batch), etx.ETX_VIEW_EMBEDDING, torch.float32, (len(ev["x"]), 16)).cpu().numpy()
+    assert np.abs(emb[:, :w.emb_dim] - ref_q["emb"]).max() <= 1e-3
+
+
+def test_fp8_calibration_and_pipeline_against_quantised_oracle():
+    etx = _etx()
+    w = synth.C1
+    W = synth.xavier_weights(w)
+    cal = synth.generate_batch(w, 3, seed_space=1001)
+    batch = synth.generate_batch(w, 1)
+    ev = synth.event_slice(batch, 0)
+    p, res = _run(w, W, batch, etx.ETX_FP8_E4M3, cal)
+    # the oracle calibrates itself on the same events
+    es, gs, _, _ = O.calibrate([synth.event_slice(cal, i) for i in range(3)], w, W)
+    sc = etx.etx_get_scales(p.ctx)
+    L = w.emb_layers
+    assert np.array_equal(sc[1:L + 1], es[1:L + 1].astype(np.float32))
+    assert np.array_equal(sc[8:8 + 8 + w.gnn_steps], gs.astype(np.float32))
+    ref_q = O.run_event(ev, w, W, qmode=2, scales=(es, gs))
+    common = np.array_equal(res["src"], ref_q["src"]) and np.array_equal(res["dst"], ref_q["dst"])
+    _, cart = O.features(ev["x"], ev["y"], ev["z"], w.r_scale, w.z_scale)
+    if not common:   # FP8 embedding: compare the GNN on the GPU's own edge list
+        ref_q_s = O.sigmoid(O.gnn(cart, res["src"], res["dst"], W, w.gnn_hidden, w.gnn_steps, 2, gs))
+    else:
+        ref_q_s = ref_q["score"]
+    sq = _score_stats(res["score"], ref_q_s)
+    s64 = O.sigmoid(O.gnn(cart, res["src"], res["dst"], W, w.gnn_hidden, w.gnn_steps))
+    print("fp8 edges equal to quantised oracle:", common, "vs quantised oracle", sq,
+          "vs fp64 oracle", _score_stats(res["score"], s64))
+    assert sq["mean"] <= 2e-3 and sq["max"] <= 0.1
