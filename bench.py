@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--graph", type=int, default=0, help="replay the batch as one captured HIP graph")
     ap.add_argument("--autotune", type=int, default=0, help="tune the launch schedule on the batch before timing")
+    ap.add_argument("--copy-gib", type=float, default=0.0,
+                    help="only run a plain device-to-device copy of this many GiB (counter calibration) and exit")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-threads", type=int, default=None)
     ap.add_argument("--profile-stages", type=int, default=1)
@@ -52,13 +54,21 @@ def stage_roofline(stage, ms_total, launches, n_edges, n_hits, H, dtype):
     if launches == 0 or ms_total <= 0:
         return None
     t = ms_total / launches * 1e-3          # seconds per launch
+    es = {"f32": 4, "bf16": 2, "fp8": 1}[dtype]
     if stage in ("edge_step", "edge_step_final"):
-        # edge net: Linear(3H->H) + Linear(H->H) per edge; the last step adds the classifier Linear(H->H)+Linear(H->1)
+        # edge net: Linear(3H->H) + Linear(H->H) per edge (the last step adds the
+        # classifier Linear(H->H) + Linear(H->1)); bytes: e read and written once
+        # (the last step writes a 4-byte score instead), src and dst indices
         flops = n_edges * (8 * H * H + (2 * H * H + 2 * H if stage == "edge_step_final" else 0))
-        achieved = flops / t / 1e12
+        nbytes = n_edges * (H * es + (4 if stage == "edge_step_final" else H * es) + 8)
         peak = PEAK_TFLOPS[dtype]
-        return dict(bound="mfma", achieved=achieved, peak=peak, unit="TFLOP/s", frac=achieved / peak,
-                    units_per_launch=n_edges, per_unit=f"{8 * H * H} flop/edge")
+        if flops / (peak * 1e12) >= nbytes / (PEAK_HBM_GBS * 1e9):
+            achieved = flops / t / 1e12
+            return dict(bound="mfma", achieved=achieved, peak=peak, unit="TFLOP/s", frac=achieved / peak,
+                        units_per_launch=n_edges, per_unit=f"{8 * H * H} flop/edge")
+        achieved = nbytes / t / 1e9
+        return dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s", frac=achieved / PEAK_HBM_GBS,
+                    units_per_launch=n_edges, per_unit=f"{nbytes // max(n_edges, 1)} B/edge")
     if stage == "node_step":
         flops = n_hits * (2 * 3 * H * H + 2 * H * H + 2 * 2 * H * H)
         achieved = flops / t / 1e12
@@ -67,12 +77,48 @@ def stage_roofline(stage, ms_total, launches, n_edges, n_hits, H, dtype):
                     units_per_launch=n_hits, per_unit=f"{12 * H * H} flop/hit")
     if stage == "segsum":
         # each edge encoding read once, one 4-byte CSC index per edge, both sums written
-        es = 4
         nbytes = n_edges * (H * es + 4) + n_hits * (2 * H * 4 + 16)
         achieved = nbytes / t / 1e9
         return dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s", frac=achieved / PEAK_HBM_GBS,
                     units_per_launch=n_edges, per_unit=f"{H * es + 4} B/edge + {2 * H * 4 + 16} B/hit")
     return None
+
+
+def kernel_source_hash(kernel):
+    """sha256 of the HIP source that defines a stage's kernel."""
+    import hashlib
+    src = {"edge_step": "gnn.hip", "edge_step_final": "gnn.hip", "segsum": "gnn.hip", "node_step": "gnn.hip"}[kernel]
+    h = hashlib.sha256()
+    for f in (src, "tile.hpp"):
+        with open(os.path.join(ROOT, "paper_2508_07423_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload, dtype):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current source of the kernel (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        recs = json.load(f)
+    for r in recs:
+        if r["kernel"] == kernel and r["workload"] == workload and r["dtype"] == dtype:
+            return r["bytes_per_launch"] if r["source_sha256"] == kernel_source_hash(kernel) else None
+    return None
+
+
+def copy_calibration(gib):
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}), flush=True)
 
 
 def cpu_baseline(w, weights, batch, threads):
@@ -88,6 +134,9 @@ def cpu_baseline(w, weights, batch, threads):
 
 def main():
     args = parse()
+    if args.copy_gib > 0:
+        copy_calibration(args.copy_gib)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} (WORLD_SIZE {world}) is not supported: "
@@ -162,7 +211,7 @@ def main():
         roof = stage_roofline(dom, gnn[dom][0], gnn[dom][1], n_edges, b.n_hits, w.gnn_hidden, dtype)
         if roof is not None:
             roof = dict(kernel=dom, **{k: (round(v, 4) if isinstance(v, float) else v) for k, v in roof.items()},
-                        traffic=None)
+                        traffic=measured_traffic(dom, w.name, dtype))
         print(f"[bench] stages (ms/step): " + ", ".join(f"{k} {v['ms']}" for k, v in stages.items()),
               file=sys.stderr, flush=True)
     cpu = None

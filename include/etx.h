@@ -133,7 +133,8 @@ typedef enum {
   ETX_VIEW_KEPT_COUNT = 8,   /* int32 [n_events]: kept edges per event */
   ETX_VIEW_CALIB = 9,        /* float [ETX_N_CALIB]: per-tensor amax (calibration observers) */
   ETX_VIEW_PF_KEEP = 10,     /* uint8 [edge_capacity]: prefilter decision per candidate edge */
-  ETX_VIEW_PF_GRAD = 11      /* float [ETX_PF_NPARAM + 1]: last prefilter gradient, then the loss */
+  ETX_VIEW_PF_GRAD = 11,     /* float [ETX_PF_NPARAM + 1]: last prefilter gradient, then the loss */
+  ETX_VIEW_PF_PROB = 12      /* float [edge_capacity]: prefilter probability per candidate edge */
 } etx_view;
 #define ETX_N_CALIB 64
 etx_status etx_workspace_view(const etx_ctx* ctx, int64_t n_events, int64_t n_hits, int64_t edge_capacity,
@@ -202,6 +203,8 @@ etx_status etx_prefilter_get(const etx_ctx* ctx, float* params, int64_t n);     
 etx_status etx_prefilter_train_step(etx_ctx* ctx, const etx_hits* hits, etx_out* out, const uint8_t* edge_labels,
                                     float lr, float pos_weight, int64_t step, float* loss_dev, void* ws,
                                     size_t ws_bytes, etx_stream stream);
+/* Turn the prefilter on or off and set its threshold (keep when p >= tau). */
+etx_status etx_prefilter_config(etx_ctx* ctx, int32_t enabled, float tau);
 /* Optimiser state for checkpointing: params, Adam m, Adam v (3 * ETX_PF_NPARAM floats). */
 etx_status etx_prefilter_state(etx_ctx* ctx, float* host_state, int64_t n, int32_t set);
 

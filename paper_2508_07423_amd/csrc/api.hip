@@ -59,9 +59,9 @@ WsLayout ws_layout(const etx_ctx* ctx, int64_t n_events, int64_t n_hits, int64_t
   L.calib = take(sizeof(float) * ETX_N_CALIB);
   L.pf_keep = take(sizeof(uint8_t) * edge_cap);
   L.pf_tmp = take(sizeof(int64_t) * (n_hits + 1));
-  const bool pf = c.prefilter != 0;
-  L.cand_src = take(pf ? sizeof(int32_t) * edge_cap : 0);
-  L.cand_dst = take(pf ? sizeof(int32_t) * edge_cap : 0);
+  L.cand_src = take(sizeof(int32_t) * edge_cap);
+  L.cand_dst = take(sizeof(int32_t) * edge_cap);
+  L.pf_prob = take(sizeof(float) * edge_cap);
   L.pf_part = take(sizeof(float) * (size_t)kPfMaxWaves * kPfGradStride);
   L.pf_grad = take(sizeof(float) * kPfGradStride);
   L.total = o;
@@ -553,6 +553,7 @@ etx_status etx_workspace_view(const etx_ctx* ctx, int64_t n_events, int64_t n_hi
     case ETX_VIEW_CALIB: *offset = L.calib; *bytes = sizeof(float) * ETX_N_CALIB; break;
     case ETX_VIEW_PF_KEEP: *offset = L.pf_keep; *bytes = edge_capacity; break;
     case ETX_VIEW_PF_GRAD: *offset = L.pf_grad; *bytes = sizeof(float) * (ETX_PF_NPARAM + 1); break;
+    case ETX_VIEW_PF_PROB: *offset = L.pf_prob; *bytes = sizeof(float) * edge_capacity; break;
     default: return ETX_ERR_INVALID_ARG;
   }
   return ETX_OK;
@@ -808,6 +809,14 @@ etx_status etx_prefilter_train_step(etx_ctx* ctx, const etx_hits* hits, etx_out*
   STEP(launch_radius(a, true, false));
   STEP(launch_prefilter_train(a, edge_labels, lr, pos_weight, step, loss_dev));
 #undef STEP
+  return ETX_OK;
+}
+
+etx_status etx_prefilter_config(etx_ctx* ctx, int32_t enabled, float tau) {
+  if (!ctx || (enabled != 0 && enabled != 1) || !std::isfinite(tau)) return ETX_ERR_INVALID_ARG;
+  ctx->cfg.prefilter = enabled;
+  ctx->cfg.prefilter_tau = tau;
+  clear_graphs(ctx);
   return ETX_OK;
 }
 

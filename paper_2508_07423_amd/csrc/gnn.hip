@@ -103,8 +103,10 @@ __device__ inline void load_e(float* ef, uint32_t* words, const void* e, int64_t
     for (int c = 0; c < H / 16; ++c) {
       const uint32_t w = valid ? *reinterpret_cast<const uint32_t*>(row + 16 * c + 4 * g) : 0u;
       words[c] = w;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) ef[4 * c + q] = e4m3_decode((w >> (8 * q)) & 0xffu) * scale;
+      ef[4 * c + 0] = e4m3_byte<0>(w) * scale;
+      ef[4 * c + 1] = e4m3_byte<1>(w) * scale;
+      ef[4 * c + 2] = e4m3_byte<2>(w) * scale;
+      ef[4 * c + 3] = e4m3_byte<3>(w) * scale;
     }
   }
 }
@@ -125,20 +127,23 @@ __device__ inline void store_e(void* e, int64_t col, const float* o, bool valid,
   } else {
     uint8_t* row = static_cast<uint8_t*>(e) + col * H;
 #pragma unroll
-    for (int c = 0; c < H / 16; ++c) {
-      uint32_t w = 0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) w |= e4m3_encode(o[4 * c + q] * inv_scale) << (8 * q);
-      *reinterpret_cast<uint32_t*>(row + 16 * c + 4 * g) = w;
-    }
+    for (int c = 0; c < H / 16; ++c)
+      *reinterpret_cast<uint32_t*>(row + 16 * c + 4 * g) =
+          e4m3_encode4(o[4 * c] * inv_scale, o[4 * c + 1] * inv_scale, o[4 * c + 2] * inv_scale,
+                       o[4 * c + 3] * inv_scale);
   }
 }
 
 // --------------------------------------------------------------------------
 // node encoder (+ edge-encoder source/target products)
 // --------------------------------------------------------------------------
+// FP32 node kernels hold up to 98 KiB of weights in LDS: one 16-wave workgroup
+// per CU; the low-precision segments are 2-4x smaller and run 8-wave groups.
+template <int P>
+struct NodeThreads { static constexpr int value = P == P_F32 ? 1024 : 512; };
+
 template <int H, int P>
-__global__ __launch_bounds__(1024) void k_node_encode(GnnArgs A) {
+__global__ __launch_bounds__(NodeThreads<P>::value) void k_node_encode(GnnArgs A) {
   if (A.status[0] != 0) return;
   extern __shared__ float lds[];
   char* w = reinterpret_cast<char*>(lds);
@@ -244,9 +249,12 @@ __device__ inline void add_chunk(float* acc, uint4 v) {
   } else {
     const uint32_t u[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc[4 * i + q] += e4m3_decode((u[i] >> (8 * q)) & 0xffu);
+    for (int i = 0; i < 4; ++i) {
+      acc[4 * i + 0] += e4m3_byte<0>(u[i]);
+      acc[4 * i + 1] += e4m3_byte<1>(u[i]);
+      acc[4 * i + 2] += e4m3_byte<2>(u[i]);
+      acc[4 * i + 3] += e4m3_byte<3>(u[i]);
+    }
   }
   (void)FPL;
 }
@@ -317,7 +325,7 @@ __global__ __launch_bounds__(256) void k_segsum(GnnArgs A) {
 // node update k (+ edge net k source/target products)
 // --------------------------------------------------------------------------
 template <int H, int P>
-__global__ __launch_bounds__(1024) void k_node_step(GnnArgs A) {
+__global__ __launch_bounds__(NodeThreads<P>::value) void k_node_step(GnnArgs A) {
   if (A.status[0] != 0) return;
   extern __shared__ float lds[];
   char* w = reinterpret_cast<char*>(lds);
@@ -468,12 +476,15 @@ static GnnArgs gnn_args(const RunArgs& a) {
   return A;
 }
 
-constexpr int kNodeThreads = 1024;   // 16 waves: the node kernels hold up to 98 KiB of weights in LDS
 constexpr int kEdgeThreads = 512;
+
+static int node_threads(int prec) { return prec == P_F32 ? 1024 : 512; }
 
 static unsigned node_grid(const RunArgs& a, int per_cu) {
   int64_t tiles = (a.hits.n_hits + kCols - 1) / kCols;
-  int64_t waves = kNodeThreads / 64;
+  int64_t waves = node_threads(a.prec) / 64;
+  // low-precision node kernels run two 8-wave groups per CU for each FP32 group
+  if (a.prec != P_F32) per_cu *= 2;
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles + waves - 1) / waves, (int64_t)a.ctx->n_cu * per_cu));
 }
 
@@ -500,7 +511,7 @@ hipError_t launch_node_encode(const RunArgs& a) {
   A.seg = seg_ptr(a, m.node_enc);
   A.seg_bytes = SegNodeEnc{Hh, kPrecBytes[a.prec]}.size();
   unsigned grid = node_grid(a, a.ctx->node_wg_per_cu);
-  DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_node_encode<H, P>), dim3(grid), dim3(kNodeThreads), A.seg_bytes, a.stream, A));
+  DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_node_encode<H, P>), dim3(grid), dim3(node_threads(P)), A.seg_bytes, a.stream, A));
   return hipGetLastError();
 }
 
@@ -543,7 +554,7 @@ hipError_t launch_node_step(const RunArgs& a, int k) {
   A.seg_bytes = SegNode{Hh, kPrecBytes[a.prec]}.size();
   A.step = k;
   unsigned grid = node_grid(a, a.ctx->node_wg_per_cu);
-  DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_node_step<H, P>), dim3(grid), dim3(kNodeThreads), A.seg_bytes, a.stream, A));
+  DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_node_step<H, P>), dim3(grid), dim3(node_threads(P)), A.seg_bytes, a.stream, A));
   return hipGetLastError();
 }
 

@@ -224,25 +224,38 @@ __global__ __launch_bounds__(256) void k_csc(const int64_t* __restrict__ hit_off
   __syncthreads();
   if (t >= 64) return;
   // one wave walks the rows in source order; the targets of one row are
-  // distinct, so its lanes never share a cursor
-  int64_t rs = row_ptr[a];
-  int64_t re = n > 0 ? row_ptr[a + 1] : rs;
-  int d_next = (n > 0 && rs + lane < re) ? dst[rs + lane] : 0;
-  for (int i = 0; i < n; ++i) {
-    const int64_t cs = rs, ce = re;
-    const int d = d_next;
-    if (i + 1 < n) {
-      rs = ce;
-      re = row_ptr[a + i + 2];
-      d_next = (rs + lane < re) ? dst[rs + lane] : 0;
+  // distinct, so its lanes never share a cursor.  Row bounds and targets are
+  // loaded kRow rows ahead so that HBM latency overlaps the LDS updates.
+  constexpr int kRow = 8;
+  int64_t rb[kRow + 1];
+  int dd[kRow];
+  auto load_block = [&](int i0, int64_t (&b)[kRow + 1], int (&d)[kRow]) {
+#pragma unroll
+    for (int q = 0; q <= kRow; ++q) b[q] = row_ptr[a + min(i0 + q, n)];
+#pragma unroll
+    for (int q = 0; q < kRow; ++q) d[q] = (b[q] + lane < b[q + 1]) ? dst[b[q] + lane] : 0;
+  };
+  if (n > 0) load_block(0, rb, dd);
+  for (int i0 = 0; i0 < n; i0 += kRow) {
+    int64_t nb[kRow + 1];
+    int nd[kRow];
+    if (i0 + kRow < n) load_block(i0 + kRow, nb, nd);
+#pragma unroll
+    for (int q = 0; q < kRow; ++q) {
+      if (rb[q] + lane < rb[q + 1]) {
+        const int dl = dd[q] - (int)a;
+        const int pos = cur[dl];
+        cur[dl] = pos + 1;
+        csc[eb + pos] = (int32_t)(rb[q] + lane);
+      }
+      wave_sync();
     }
-    if (cs + lane < ce) {
-      int dl = d - (int)a;
-      int pos = cur[dl];
-      cur[dl] = pos + 1;
-      csc[eb + pos] = (int32_t)(cs + lane);
+    if (i0 + kRow < n) {
+#pragma unroll
+      for (int q = 0; q <= kRow; ++q) rb[q] = nb[q];
+#pragma unroll
+      for (int q = 0; q < kRow; ++q) dd[q] = nd[q];
     }
-    wave_sync();
   }
 }
 

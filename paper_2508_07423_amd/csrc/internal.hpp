@@ -32,7 +32,7 @@ struct WeightMap {
 // Byte offsets of the workspace buffers.
 struct WsLayout {
   size_t bucket, plane_off, emb, cnt, row_ptr, scan_tmp, col_ptr, csc, h, ps, pd, msg, e, kept, kept_cnt,
-      calib, pf_keep, pf_tmp, cand_src, cand_dst, pf_part, pf_grad, total;
+      calib, pf_keep, pf_tmp, cand_src, cand_dst, pf_prob, pf_part, pf_grad, total;
   int64_t n_scan_blocks;
 };
 

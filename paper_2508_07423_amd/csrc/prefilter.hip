@@ -46,6 +46,7 @@ struct PfArgs {
   const float* params;       // FP32 parameters (device)
   float inv_r, inv_z, tau;
   uint8_t* keep;             // inference output [candidates]
+  float* prob;               // inference output: probability per candidate
   const uint8_t* label;      // training labels [candidates]
   float pos_weight;
   float* partial;            // [waves][kPfGradStride]
@@ -161,7 +162,10 @@ __global__ __launch_bounds__(kPfThreads) void k_pf(PfArgs A) {
     const float z3 = col_sum(dot) + L.b3[0];
     const float prob = 1.0f / (1.0f + expf(-z3));
     if (!TRAIN) {
-      if (valid && g == 0) A.keep[col] = prob >= A.tau ? 1 : 0;
+      if (valid && g == 0) {
+        A.keep[col] = prob >= A.tau ? 1 : 0;
+        A.prob[col] = prob;
+      }
       continue;
     }
     const bool y = valid && A.label[col] != 0;
@@ -317,6 +321,7 @@ PfArgs pf_args(const RunArgs& a, bool candidates) {
   A.inv_z = 1.0f / a.ctx->cfg.z_scale_mm;
   A.tau = a.ctx->cfg.prefilter_tau;
   A.keep = reinterpret_cast<uint8_t*>(a.ws + a.L.pf_keep);
+  A.prob = reinterpret_cast<float*>(a.ws + a.L.pf_prob);
   A.partial = reinterpret_cast<float*>(a.ws + a.L.pf_part);
   A.status = a.out.status;
   return A;

@@ -9,8 +9,8 @@
 // on that axis lies within r of its own, which is exact because a distance
 // below r bounds every coordinate difference.  Each wave handles one source
 // at a time: in-radius candidates are compacted into an LDS list with a wave
-// ballot and prefix count, the k_max boundary is found by a bisection on the
-// float bits of d^2 (ties at the boundary resolved by the target index), and
+// ballot and prefix count, the k_max boundary is found by a radix select on
+// the float bits of d^2 (ties at the boundary resolved by the target index), and
 // the kept targets are ranked by index and written as one CSR row.  Windows
 // larger than the LDS capacity are read from HBM without the sort.
 #include "internal.hpp"
@@ -63,7 +63,7 @@ __device__ inline float dist2(const float (&s)[DP], const float* c) {
 template <int DP>
 struct RadiusLds {
   static constexpr int cap = DP <= 8 ? 1024 : 512;
-  static constexpr size_t bytes = (size_t)cap * (DP * 4 + 12) + kRadiusWaves * (kList * 8 + 64 * 4) + 64;
+  static constexpr size_t bytes = (size_t)cap * (DP * 4 + 12) + kRadiusWaves * (kList * 8 + 64 * 4 + 256 * 4) + 64;
 };
 
 template <bool EMIT, int DP>
@@ -78,7 +78,8 @@ __global__ __launch_bounds__(kRadiusThreads) void k_radius(RadiusArgs A) {
   float* ld2 = reinterpret_cast<float*>(sidx + CAP);              // [waves][kList]
   int* lj = reinterpret_cast<int*>(ld2 + kRadiusWaves * kList);   // [waves][kList]
   int* sel = lj + kRadiusWaves * kList;                           // [waves][64]
-  int* misc = sel + kRadiusWaves * 64;                            // [16]
+  int* hist = sel + kRadiusWaves * 64;                            // [waves][256] radix-select histogram
+  int* misc = hist + kRadiusWaves * 256;                          // [16]
 
   const int P = A.n_planes;
   const int ev = blockIdx.x / P, p = blockIdx.x % P;
@@ -179,6 +180,7 @@ __global__ __launch_bounds__(kRadiusThreads) void k_radius(RadiusArgs A) {
   float* wl2 = ld2 + wave * kList;
   int* wlj = lj + wave * kList;
   int* sl = sel + wave * 64;
+  int* hw = hist + wave * 256;
   const unsigned r2bits = __float_as_uint(A.r2);
 
   for (int s = wave; s < nsrc; s += kRadiusWaves) {
@@ -276,7 +278,64 @@ __global__ __launch_bounds__(kRadiusThreads) void k_radius(RadiusArgs A) {
     const bool capped = n > A.k_max;
     float T = A.r2;
     int Jt = 0x7fffffff;
-    if (capped) {
+    if (capped && listed) {
+      // radix select of the k-th smallest d2 over the list: four 8-bit digits of
+      // its float bits (non-negative floats order like their bits)
+      unsigned prefix = 0;
+      int need = A.k_max, eq = 0;
+      for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 24 - 8 * pass;
+        for (int b = lane; b < 256; b += 64) hw[b] = 0;
+        wave_sync();
+        for (int q = lane; q < n; q += 64) {
+          const unsigned key = __float_as_uint(wl2[q]);
+          if (pass == 0 || (key >> (shift + 8)) == (prefix >> (shift + 8))) atomicAdd(&hw[(key >> shift) & 255u], 1);
+        }
+        wave_sync();
+        int c[4], sum = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          c[i] = hw[4 * lane + i];
+          sum += c[i];
+        }
+        int incl = sum;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+          const int t = __shfl_up(incl, d);
+          if (lane >= d) incl += t;
+        }
+        int run = incl - sum, bin = -1, before = 0, cnt = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (bin < 0 && run < need && need <= run + c[i]) {
+            bin = 4 * lane + i;
+            before = run;
+            cnt = c[i];
+          }
+          run += c[i];
+        }
+        const uint64_t m = __ballot(bin >= 0);
+        const int src_lane = __ffsll((unsigned long long)m) - 1;
+        bin = __shfl(bin, src_lane);
+        before = __shfl(before, src_lane);
+        cnt = __shfl(cnt, src_lane);
+        prefix |= (unsigned)bin << shift;
+        need -= before;
+        eq = cnt;
+        wave_sync();
+      }
+      T = __uint_as_float(prefix);
+      if (eq > need) {
+        // ties at the boundary distance: keep the `need` smallest hit indices
+        int jlo = (int)a, jhi = (int)(A.hit_off[ev + 1] - 1);
+        while (jlo < jhi) {
+          const int mid = jlo + (jhi - jlo) / 2;
+          const int m = count_if([&](float d2, int j) { return d2 == T && j <= mid; });
+          if (m >= need) jhi = mid; else jlo = mid + 1;
+        }
+        Jt = jlo;
+      }
+    } else if (capped) {
       // smallest T (as float bits) with #{d2 <= T} >= k_max: the k-th smallest d2
       unsigned lo = 0, hi = r2bits - 1u;
       while (lo < hi) {

@@ -125,6 +125,7 @@ __device__ inline void mfma_bf16(float* acc, const float* x, const bf16x8* __res
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
       c[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[(mb * (K / 32) + t) * 64 + lane], b, c[mb], 0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
   }
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb)
@@ -140,30 +141,25 @@ enum Prec { P_F32 = 0, P_BF16 = 1, P_FP8 = 2 };
 template <int P>
 struct PrecBytes { static constexpr int value = P == P_F32 ? 4 : (P == P_BF16 ? 2 : 1); };
 
-// OCP FP8 E4M3 (bias 7, 3 mantissa bits, subnormals, max 448, no infinity):
-// round to nearest even, saturate to +-448 (NaN maps to 0).
-__device__ inline uint32_t e4m3_encode(float x) {
-  const uint32_t sign = (__float_as_uint(x) >> 24) & 0x80u;
-  float a = fabsf(x);
-  if (!(a == a)) return 0u;
-  a = fminf(a, 448.f);
-  uint32_t code;
-  if (a < 0.015625f) {                                   // below 2^-6: spacing 2^-9
-    code = (uint32_t)__builtin_rintf(a * 512.f);         // 8 is the smallest normal
-  } else {
-    const int e = (int)((__float_as_uint(a) >> 23) & 0xffu) - 127;        // -6 .. 8
-    const float m = a * __uint_as_float((uint32_t)(127 - e) << 23);       // a / 2^e in [1, 2)
-    const uint32_t q = (uint32_t)__builtin_rintf((m - 1.f) * 8.f);        // 0 .. 8 (8 carries)
-    code = min(((uint32_t)(e + 7) << 3) + q, 0x7Eu);
-  }
-  return sign | code;
+// OCP FP8 E4M3 (bias 7, 3 mantissa bits, subnormals, max 448, no infinity),
+// converted by the gfx950 instructions v_cvt_pk_fp8_f32 (round to nearest
+// even) and v_cvt_f32_fp8.  The clamp keeps values beyond the largest finite
+// code at +-448 (saturation).
+__device__ inline float e4m3_clamp(float x) { return fminf(fmaxf(x, -448.f), 448.f); }
+
+// four values -> four codes, value q in byte q
+__device__ inline uint32_t e4m3_encode4(float a, float b, float c, float d) {
+  const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(e4m3_clamp(a), e4m3_clamp(b), 0, false);
+  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(e4m3_clamp(c), e4m3_clamp(d), lo, true);
 }
 
-__device__ inline float e4m3_decode(uint32_t c) {
-  const uint32_t e = (c >> 3) & 15u, m = c & 7u;
-  const float v = e ? __uint_as_float(((e + 120u) << 23) | (m << 20)) : (float)m * 0.001953125f;
-  return __uint_as_float(__float_as_uint(v) | ((c & 0x80u) << 24));
-}
+__device__ inline uint32_t e4m3_encode(float x) { return e4m3_encode4(x, 0.f, 0.f, 0.f) & 0xffu; }
+
+// byte Q of a word of codes -> value
+template <int Q>
+__device__ inline float e4m3_byte(uint32_t w) { return __builtin_amdgcn_cvt_f32_fp8((int)w, Q); }
+
+__device__ inline float e4m3_decode(uint32_t c) { return e4m3_byte<0>(c); }
 
 __device__ inline uint32_t bf16_bits(float x) { return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)x); }
 __device__ inline float bf16_value(uint32_t b) { return __uint_as_float(b << 16); }
@@ -181,12 +177,13 @@ __device__ inline void mfma_fp8(float* acc, const float* x, const uint64_t* __re
   for (int mb = 0; mb < MB; ++mb) c[mb] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int t = T0; t < T1; ++t) {
-    uint64_t b = 0;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) b |= (uint64_t)e4m3_encode(x[8 * t + q] * inv_s) << (8 * q);
+    const float* xs = x + 8 * t;
+    const uint64_t b = (uint64_t)e4m3_encode4(xs[0] * inv_s, xs[1] * inv_s, xs[2] * inv_s, xs[3] * inv_s) |
+                       ((uint64_t)e4m3_encode4(xs[4] * inv_s, xs[5] * inv_s, xs[6] * inv_s, xs[7] * inv_s) << 32);
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
       c[mb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8((long)w[(mb * (K / 32) + t) * 64 + lane], (long)b, c[mb], 0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
   }
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb)
@@ -208,6 +205,7 @@ __device__ inline void mfma_fp8_codes(float* acc, const uint32_t* xw, const uint
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
       c[mb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8((long)w[(mb * (K / 32) + t) * 64 + lane], (long)b, c[mb], 0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
   }
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb)

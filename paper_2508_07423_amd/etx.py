@@ -24,7 +24,8 @@ ETX_N_CALIB = 64
 ETX_PF_HIDDEN = 32
 ETX_PF_NPARAM = 6 * 32 + 32 + 32 * 32 + 32 + 32 + 1
 (ETX_VIEW_EMBEDDING, ETX_VIEW_BUCKET, ETX_VIEW_PLANE_OFF, ETX_VIEW_ROW_PTR, ETX_VIEW_COL_PTR, ETX_VIEW_CSC_EDGE,
- ETX_VIEW_NODE_H, ETX_VIEW_KEPT_EDGE, ETX_VIEW_KEPT_COUNT, ETX_VIEW_CALIB, ETX_VIEW_PF_KEEP, ETX_VIEW_PF_GRAD) = range(12)
+ ETX_VIEW_NODE_H, ETX_VIEW_KEPT_EDGE, ETX_VIEW_KEPT_COUNT, ETX_VIEW_CALIB, ETX_VIEW_PF_KEEP, ETX_VIEW_PF_GRAD,
+ ETX_VIEW_PF_PROB) = range(13)
 (ETX_OPT_USE_GRAPH, ETX_OPT_EDGE_WG_PER_CU, ETX_OPT_NODE_WG_PER_CU, ETX_OPT_RADIUS_LDS,
  ETX_OPT_SEGSUM_UNROLL, ETX_OPT_PROFILE) = range(6)
 N_STAGES = 17
@@ -77,6 +78,7 @@ def lib():
             "etx_prefilter_state": [P, P, i64, i32],
             "etx_profile_read": [P, i32, P, P],
             "etx_get_scales": [P, P, i32],
+            "etx_prefilter_config": [P, i32, C.c_float],
             "etx_quantize": [i32, P, P, i64, C.c_float, P],
             "etx_profile_reset": [P],
         }
@@ -98,7 +100,7 @@ EXPORTED = ["etx_create", "etx_destroy", "etx_weight_blob_size", "etx_workspace_
             "etx_workspace_view", "etx_set_option", "etx_get_option", "etx_autotune", "etx_calibrate",
             "etx_set_precision", "etx_prefilter_set", "etx_prefilter_get", "etx_prefilter_train_step",
             "etx_prefilter_state", "etx_status_str", "etx_last_error", "etx_profile_read", "etx_profile_reset",
-            "etx_stage_name", "etx_get_scales", "etx_quantize"]
+            "etx_stage_name", "etx_get_scales", "etx_quantize", "etx_prefilter_config"]
 
 
 class EtxError(RuntimeError):
@@ -194,6 +196,10 @@ def etx_quantize(precision: int, in_ptr: int, out_ptr: int, n: int, scale: float
 def etx_prefilter_set(ctx, params: np.ndarray) -> None:
     p = np.ascontiguousarray(params, dtype=np.float32)
     _check(lib().etx_prefilter_set(ctx, p.ctypes.data_as(C.c_void_p), p.size), "etx_prefilter_set")
+
+
+def etx_prefilter_config(ctx, enabled: int, tau: float) -> None:
+    _check(lib().etx_prefilter_config(ctx, enabled, tau), "etx_prefilter_config")
 
 
 def etx_prefilter_get(ctx) -> np.ndarray:

@@ -1,0 +1,93 @@
+"""Track efficiency with trained weights: the FP32 path against the oracle,
+the precision cost of BF16 and FP8 operands, and what the learned prefilter
+gains over the unpruned pipeline (which stays its fallback and judge).
+
+The weights come from paper_2508_07423_amd/train_weights.py (generator events
+of a disjoint seed space); with random weights the network keeps all or no
+edges and efficiency says nothing.
+"""
+import os
+import time
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2508_07423_amd import evaluate, synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+HAVE = {name: os.path.exists(os.path.join(synth.TRAINED_DIR, f"{name}_trained.npz")) for name in ("c2", "c3")}
+
+
+def _etx():
+    from paper_2508_07423_amd import etx
+    return etx
+
+
+def run_labels(w, W, batch, prec=0, cal=None, prefilter=None):
+    etx = _etx()
+    p = etx.Pipeline(w, W, precision=prec)
+    if cal is not None:
+        p.calibrate(etx.to_device(cal))
+    if prefilter is not None:
+        etx.etx_prefilter_set(p.ctx, prefilter[0])
+        etx.etx_prefilter_config(p.ctx, 1, prefilter[1])
+    b = etx.to_device(batch)
+    p.run(b)
+    res = p.results(b)
+    return p, b, res
+
+
+@pytest.mark.skipif(not HAVE["c3"], reason="trained weights not built")
+def test_fp32_efficiency_matches_oracle_and_precisions_within_half_percent():
+    etx = _etx()
+    w = synth.C3
+    W = synth.trained_weights(w)
+    batch = synth.generate_batch(w, 40)
+    _, _, r32 = run_labels(w, W, batch)
+    m32 = evaluate.batch_metrics(r32["labels"], batch)
+    print("fp32", m32, "edges/hit", len(r32["src"]) / len(batch["x"]), "kept", float((r32["score"] >= 0.5).mean()))
+    assert m32["efficiency"] > 0.5
+    # the oracle on a few events reaches the same tracks
+    ev_idx = [0, 1, 2]
+    refs = O.run_batch(batch, w, W, events=ev_idx)
+    lab_or = np.concatenate([r["labels"] + int(batch["hit_off"][i]) for i, r in zip(ev_idx, refs)])
+    n3 = int(batch["hit_off"][3])
+    m_or = evaluate.batch_metrics(np.concatenate([lab_or, np.arange(n3, len(batch["x"]))]), batch, ev_idx)
+    m_gpu = evaluate.batch_metrics(r32["labels"], batch, ev_idx)
+    print("oracle", m_or, "gpu", m_gpu)
+    assert abs(m_or["efficiency"] - m_gpu["efficiency"]) <= 0.005
+    cal = synth.generate_batch(w, 10, seed_space=1000 + w.cid)
+    for prec, name in ((etx.ETX_BF16, "bf16"), (etx.ETX_FP8_E4M3, "fp8")):
+        _, _, r = run_labels(w, W, batch, prec, cal if prec == etx.ETX_FP8_E4M3 else None)
+        m = evaluate.batch_metrics(r["labels"], batch)
+        common = np.array_equal(r["src"], r32["src"]) and np.array_equal(r["dst"], r32["dst"])
+        err = np.abs(r["score"] - r32["score"]) if common else None
+        print(name, m, "same edges" if common else "different edges",
+              "" if err is None else f"score err vs fp32 max {err.max():.3e} mean {err.mean():.3e}")
+        assert abs(m["efficiency"] - m32["efficiency"]) <= 0.005, name
+
+
+@pytest.mark.skipif(not HAVE["c3"], reason="trained weights not built")
+def test_learned_prefilter_gain():
+    from paper_2508_07423_amd import prefilter_train as PT
+    etx = _etx()
+    w = synth.C5
+    W = synth.trained_weights(w)
+    t0 = time.time()
+    tr = PT.train_prefilter(w, W, n_events=1500, batch_events=150, epochs=2, lr=3e-3, pos_weight=4.0)
+    print(f"prefilter trained in {time.time() - t0:.1f} s, loss {tr['history'][0]:.4f} -> {tr['history'][-1]:.4f}")
+    assert tr["history"][-1] < tr["history"][0]
+    val = synth.generate_batch(w, 100, seed_space=6000 + w.cid)
+    sel = PT.choose_tau(w, W, tr["params"], val, recall=0.995)
+    print("tau", sel)
+    batch = synth.generate_batch(w, 400)
+    _, b0, r0 = run_labels(w, W, batch)
+    p1, b1, r1 = run_labels(w, W, batch, prefilter=(tr["params"], sel["tau"]))
+    m0, m1 = evaluate.batch_metrics(r0["labels"], batch), evaluate.batch_metrics(r1["labels"], batch)
+    e0, e1 = len(r0["src"]), len(r1["src"])
+    print("unpruned", m0, e0, "pruned", m1, e1)
+    assert e1 < 0.9 * e0
+    assert m1["efficiency"] >= m0["efficiency"] - 0.005
