@@ -143,6 +143,8 @@ def main():
               "events are independent, so a multi-GPU run would split the batch by events with no exchange.",
               file=sys.stderr)
         sys.exit(2)
+    if args.steps < 1:
+        raise SystemExit("--steps must be at least 1")
 
     import torch
     from paper_2508_07423_amd import etx, synth
@@ -172,7 +174,9 @@ def main():
             out = p.allocate(b)
             path = os.path.join(ROOT, "gpurun_out", "autotune.jsonl") if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None
             etx.etx_autotune(p.ctx, p.hits_struct(b), out, p.ws_ptr, p.ws_bytes, stream.cuda_stream, path)
-        tuned = {k: etx.etx_get_option(p.ctx, v) for k, v in (("edge_wg_per_cu", etx.ETX_OPT_EDGE_WG_PER_CU),
+        tuned = {k: etx.etx_get_option(p.ctx, v) for k, v in (("edge_threads", etx.ETX_OPT_EDGE_WG_SIZE),
+                                                               ("edge_wg_per_cu", etx.ETX_OPT_EDGE_WG_PER_CU),
+                                                               ("edge_pipeline", etx.ETX_OPT_EDGE_PIPELINE),
                                                                ("node_wg_per_cu", etx.ETX_OPT_NODE_WG_PER_CU),
                                                                ("segsum_unroll", etx.ETX_OPT_SEGSUM_UNROLL))}
         print(f"[bench] autotuned: {tuned}", file=sys.stderr, flush=True)
@@ -182,10 +186,10 @@ def main():
         for _ in range(args.warmup):
             p.run(b, stream=stream)
         stream.synchronize()
-        res = p.results(b)
-        n_edges = int(res["edge_off"][-1])
-        print(f"[bench] warmup done: {n_edges} edges ({n_edges / b.n_hits:.1f}/hit), "
-              f"kept {(res['score'] >= 0.5).mean():.3f}", file=sys.stderr, flush=True)
+        if args.warmup > 0:
+            res = p.results(b)
+            print(f"[bench] warmup done: {int(res['edge_off'][-1])} edges ({int(res['edge_off'][-1]) / b.n_hits:.1f}"
+                  f"/hit), kept {(res['score'] >= 0.5).mean():.3f}", file=sys.stderr, flush=True)
         if args.profile_stages and not args.graph:
             etx.etx_set_option(p.ctx, etx.ETX_OPT_PROFILE, 1)
             etx.etx_profile_reset(p.ctx)
@@ -195,9 +199,8 @@ def main():
             p.run(b, stream=stream)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-    st = p.status.cpu().numpy()
-    if st[0] != etx.ETX_OK:
-        raise SystemExit(f"device status {st[0]} ({etx.etx_status_str(int(st[0]))})")
+    res = p.results(b)      # raises on a non-zero device status
+    n_edges = int(res["edge_off"][-1])
     dt = t1 - t0
     value = n_events * args.steps / dt
     stages = {}

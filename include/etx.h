@@ -147,7 +147,10 @@ typedef enum {
   ETX_OPT_NODE_WG_PER_CU = 2,/* persistent workgroups per CU of the node kernels (1..8) */
   ETX_OPT_RADIUS_LDS = 3,    /* 1: stage and sort candidate windows in LDS when they fit; 0: always read HBM */
   ETX_OPT_SEGSUM_UNROLL = 4, /* edge rows in flight per wave in the segmented sums: 1, 2, 4 or 8 */
-  ETX_OPT_PROFILE = 5        /* 1: time every stage of eager runs with HIP events on the run's stream */
+  ETX_OPT_PROFILE = 5,       /* 1: time every stage of eager runs with HIP events on the run's stream */
+  ETX_OPT_EDGE_PIPELINE = 6, /* software pipeline of the per-edge kernels: 0 none, 1 prefetch the next
+                                tile's indices and edge rows, 2 also its node-product gathers */
+  ETX_OPT_EDGE_WG_SIZE = 7   /* threads per workgroup of the per-edge kernels: 256 or 512 */
 } etx_option;
 etx_status etx_set_option(etx_ctx* ctx, int32_t key, int64_t value);
 etx_status etx_get_option(const etx_ctx* ctx, int32_t key, int64_t* value);

@@ -54,6 +54,7 @@ WsLayout ws_layout(const etx_ctx* ctx, int64_t n_events, int64_t n_hits, int64_t
   L.pd = take(sizeof(float) * n_hits * H);
   L.msg = take(sizeof(float) * n_hits * 2 * H);
   L.e = take(sizeof(float) * edge_cap * H);
+  L.opart = take(sizeof(float) * 2 * ((edge_cap + kEdgeTile - 1) / kEdgeTile) * H);
   L.kept = take(sizeof(int32_t) * edge_cap);
   L.kept_cnt = take(sizeof(int32_t) * n_events);
   L.calib = take(sizeof(float) * ETX_N_CALIB);
@@ -586,6 +587,14 @@ etx_status etx_set_option(etx_ctx* ctx, int32_t key, int64_t value) {
       if (value != 0 && value != 1) return ETX_ERR_INVALID_ARG;
       ctx->profile = (int)value;
       return ETX_OK;
+    case ETX_OPT_EDGE_PIPELINE:
+      if (value < 0 || value > 2) return ETX_ERR_INVALID_ARG;
+      ctx->edge_pipeline = (int)value;
+      break;
+    case ETX_OPT_EDGE_WG_SIZE:
+      if (value != 256 && value != 512) return ETX_ERR_INVALID_ARG;
+      ctx->edge_threads = (int)value;
+      break;
     default: return ETX_ERR_INVALID_ARG;
   }
   if (key != ETX_OPT_USE_GRAPH) clear_graphs(ctx);
@@ -633,6 +642,8 @@ etx_status etx_get_option(const etx_ctx* ctx, int32_t key, int64_t* value) {
     case ETX_OPT_NODE_WG_PER_CU: *value = ctx->node_wg_per_cu; break;
     case ETX_OPT_RADIUS_LDS: *value = ctx->radius_lds; break;
     case ETX_OPT_SEGSUM_UNROLL: *value = ctx->segsum_unroll; break;
+    case ETX_OPT_EDGE_PIPELINE: *value = ctx->edge_pipeline; break;
+    case ETX_OPT_EDGE_WG_SIZE: *value = ctx->edge_threads; break;
     case ETX_OPT_PROFILE: *value = ctx->profile; break;
     default: return ETX_ERR_INVALID_ARG;
   }

@@ -1,7 +1,9 @@
-// Launch-schedule autotuner: times the batch with each candidate value of the
-// launch knobs (persistent workgroups per CU of the edge and node kernels,
-// rows in flight of the segmented sums) and keeps the fastest, one knob at a
-// time, judging each knob by the HIP-event time of the stages it drives.
+// Launch-schedule autotuner: times the batch with each candidate setting of
+// the launch knobs (workgroup size and persistent workgroups per CU of the
+// edge kernels, their software-pipeline depth, workgroups per CU of the node
+// kernels, rows in flight of the segmented sums) and keeps the fastest, one
+// knob at a time, judging each knob by the HIP-event time of the stages it
+// drives.
 #include <chrono>
 #include <cstdio>
 #include <string>
@@ -14,12 +16,19 @@ extern "C" etx_status etx_profile_reset(etx_ctx* ctx);
 
 namespace {
 
+// A knob sets one or more options together; each candidate gives one value per key.
 struct Knob {
-  int32_t key;
+  std::vector<int32_t> keys;
   const char* name;
-  std::vector<int64_t> values;
+  std::vector<std::vector<int64_t>> values;
   std::vector<int> stages;   // stage indices whose time the knob drives
 };
+
+std::string join(const std::vector<int64_t>& v) {
+  std::string s;
+  for (size_t i = 0; i < v.size(); ++i) s += (i ? "x" : "") + std::to_string(v[i]);
+  return s;
+}
 
 // stage indices as listed by etx_stage_name
 constexpr int ST_NODE_ENC = 9, ST_EDGE_ENC = 10, ST_SEGSUM = 11, ST_NODE_STEP = 12, ST_EDGE_STEP = 13,
@@ -48,10 +57,14 @@ double timed_run(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void* ws, siz
 extern "C" etx_status etx_autotune(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void* ws, size_t ws_bytes,
                                    etx_stream stream, const char* json_path) {
   if (!ctx || !hits || !out) return ETX_ERR_INVALID_ARG;
+  const std::vector<int> edge_stages = {ST_EDGE_ENC, ST_EDGE_STEP, ST_EDGE_FINAL};
   std::vector<Knob> knobs = {
-      {ETX_OPT_EDGE_WG_PER_CU, "edge_wg_per_cu", {1, 2, 3, 4}, {ST_EDGE_ENC, ST_EDGE_STEP, ST_EDGE_FINAL}},
-      {ETX_OPT_NODE_WG_PER_CU, "node_wg_per_cu", {1, 2}, {ST_NODE_ENC, ST_NODE_STEP}},
-      {ETX_OPT_SEGSUM_UNROLL, "segsum_unroll", {2, 4, 8}, {ST_SEGSUM}},
+      {{ETX_OPT_EDGE_WG_SIZE, ETX_OPT_EDGE_WG_PER_CU}, "edge_threads_x_wg_per_cu",
+       {{512, 1}, {512, 2}, {512, 3}, {512, 4}, {256, 2}, {256, 3}, {256, 4}, {256, 5}, {256, 6}, {256, 8}},
+       edge_stages},
+      {{ETX_OPT_EDGE_PIPELINE}, "edge_pipeline", {{0}, {1}, {2}}, edge_stages},
+      {{ETX_OPT_NODE_WG_PER_CU}, "node_wg_per_cu", {{1}, {2}}, {ST_NODE_ENC, ST_NODE_STEP}},
+      {{ETX_OPT_SEGSUM_UNROLL}, "segsum_unroll", {{2}, {4}, {8}}, {ST_SEGSUM}},
   };
   const int prev_profile = ctx->profile, prev_graph = ctx->use_graph;
   ctx->profile = 1;
@@ -63,15 +76,16 @@ extern "C" etx_status etx_autotune(etx_ctx* ctx, const etx_hits* hits, etx_out* 
                        ", \"precision\": " + std::to_string(ctx->cfg.precision) + ", \"choice\": {";
   for (size_t ki = 0; ki < knobs.size() && st == ETX_OK; ++ki) {
     const Knob& k = knobs[ki];
-    int64_t best_v = 0;
+    std::vector<int64_t> best_v;
     double best_t = 1e30;
     std::string trials;
-    for (int64_t v : k.values) {
-      if ((st = etx_set_option(ctx, k.key, v)) != ETX_OK) break;
+    for (const std::vector<int64_t>& v : k.values) {
+      for (size_t j = 0; j < k.keys.size() && st == ETX_OK; ++j) st = etx_set_option(ctx, k.keys[j], v[j]);
+      if (st != ETX_OK) break;
       double t = timed_run(ctx, hits, out, ws, ws_bytes, stream, k.stages, &st);
       if (st != ETX_OK) break;
-      char buf[64];
-      std::snprintf(buf, sizeof(buf), "%s\"%lld\": %.3f", trials.empty() ? "" : ", ", (long long)v, t);
+      char buf[96];
+      std::snprintf(buf, sizeof(buf), "%s\"%s\": %.3f", trials.empty() ? "" : ", ", join(v).c_str(), t);
       trials += buf;
       if (t < best_t) {
         best_t = t;
@@ -79,10 +93,8 @@ extern "C" etx_status etx_autotune(etx_ctx* ctx, const etx_hits* hits, etx_out* 
       }
     }
     if (st != ETX_OK) break;
-    etx_set_option(ctx, k.key, best_v);
-    char buf[128];
-    std::snprintf(buf, sizeof(buf), "%s\"%s\": %lld", ki ? ", " : "", k.name, (long long)best_v);
-    record += buf;
+    for (size_t j = 0; j < k.keys.size(); ++j) etx_set_option(ctx, k.keys[j], best_v[j]);
+    record += std::string(ki ? ", " : "") + "\"" + k.name + "\": \"" + join(best_v) + "\"";
     record += std::string(", \"") + k.name + "_ms\": {" + trials + "}";
   }
   ctx->profile = prev_profile;

@@ -12,8 +12,9 @@
 // = a W_a + b W_b + c W_c.  The node-side products (h W_src, h W_dst) are
 // computed once per node in the node kernels and gathered per edge, so the
 // per-edge work is one H x H product per layer.  Messages are atomic-free
-// segmented sums: out-sums over the source-major edge list (CSR rows),
-// in-sums through the (dst, src)-ordered CSC permutation.
+// segmented sums: the out-sums (runs of the source-major edge list) are
+// reduced in registers by the kernels that write the edge encodings, the
+// in-sums gathered through the (dst, src)-ordered CSC permutation.
 //
 // Every MLP kernel is instantiated for the GEMM operand precision P (FP32,
 // BF16, FP8-E4M3 with per-tensor power-of-two scales).  Accumulation,
@@ -61,6 +62,7 @@ struct GnnArgs {
   float* pd;                // [n_hits][H] h W_dst (target product)
   float* msg;               // [n_hits][2H] (out-sum, in-sum)
   void* e;                  // [edges][H] edge encodings in the operand format
+  float* opart;             // [2 x edge tiles][H] out-sum partials of source rows that cross a tile
   float* score;             // [edges]
   float* calib;             // amax observers (calibration runs, FP32 only)
   const float* sc;          // per-tensor scales (seg.hpp ScaleSlot)
@@ -80,28 +82,40 @@ __device__ inline float wsc(const GnnArgs& A, int s) { return A.sc[s]; }
 // edge-encoding rows in the operand format
 // --------------------------------------------------------------------------
 
-// Column-layout load of an edge row: ef gets the values (FP8: decoded times
-// `scale`), words the raw FP8 codes (4 per word, FP8 only).
+// Raw column-layout chunks of an edge row (4 features per chunk in the operand
+// format), fetched ahead of use by the software-pipelined edge kernels.
+template <int P> struct EChunk;
+template <> struct EChunk<P_F32> { using T = float4; };
+template <> struct EChunk<P_BF16> { using T = uint2; };
+template <> struct EChunk<P_FP8> { using T = uint32_t; };
+
 template <int P, int H>
-__device__ inline void load_e(float* ef, uint32_t* words, const void* e, int64_t col, bool valid, float scale) {
+struct RawE { typename EChunk<P>::T v[H / 16]; };
+
+// col must address a stored row (callers clamp the tail of the last tile).
+template <int P, int H>
+__device__ inline void fetch_e(RawE<P, H>& r, const void* e, int64_t col) {
+  using T = typename EChunk<P>::T;
   const int g = lane_group();
-  if constexpr (P == P_F32) {
-    load_cols<H>(ef, static_cast<const float*>(e) + col * H, valid);
-  } else if constexpr (P == P_BF16) {
-    const uint16_t* row = static_cast<const uint16_t*>(e) + col * H;
+  const T* row = reinterpret_cast<const T*>(static_cast<const char*>(e) + col * H * PrecBytes<P>::value);
 #pragma unroll
-    for (int c = 0; c < H / 16; ++c) {
-      uint2 v = valid ? *reinterpret_cast<const uint2*>(row + 16 * c + 4 * g) : make_uint2(0u, 0u);
-      ef[4 * c + 0] = bf16_value(v.x & 0xffffu);
-      ef[4 * c + 1] = bf16_value(v.x >> 16);
-      ef[4 * c + 2] = bf16_value(v.y & 0xffffu);
-      ef[4 * c + 3] = bf16_value(v.y >> 16);
-    }
-  } else {
-    const uint8_t* row = static_cast<const uint8_t*>(e) + col * H;
+  for (int c = 0; c < H / 16; ++c) r.v[c] = row[4 * c + g];
+}
+
+// ef gets the values (FP8: decoded times `scale`), words the raw FP8 codes.
+template <int P, int H>
+__device__ inline void decode_e(float* ef, uint32_t* words, const RawE<P, H>& r, float scale) {
 #pragma unroll
-    for (int c = 0; c < H / 16; ++c) {
-      const uint32_t w = valid ? *reinterpret_cast<const uint32_t*>(row + 16 * c + 4 * g) : 0u;
+  for (int c = 0; c < H / 16; ++c) {
+    if constexpr (P == P_F32) {
+      ef[4 * c + 0] = r.v[c].x; ef[4 * c + 1] = r.v[c].y; ef[4 * c + 2] = r.v[c].z; ef[4 * c + 3] = r.v[c].w;
+    } else if constexpr (P == P_BF16) {
+      ef[4 * c + 0] = bf16_value(r.v[c].x & 0xffffu);
+      ef[4 * c + 1] = bf16_value(r.v[c].x >> 16);
+      ef[4 * c + 2] = bf16_value(r.v[c].y & 0xffffu);
+      ef[4 * c + 3] = bf16_value(r.v[c].y >> 16);
+    } else {
+      const uint32_t w = r.v[c];
       words[c] = w;
       ef[4 * c + 0] = e4m3_byte<0>(w) * scale;
       ef[4 * c + 1] = e4m3_byte<1>(w) * scale;
@@ -111,26 +125,206 @@ __device__ inline void load_e(float* ef, uint32_t* words, const void* e, int64_t
   }
 }
 
-template <int P, int H>
-__device__ inline void store_e(void* e, int64_t col, const float* o, bool valid, float inv_scale) {
+// The source and target node-product rows of an edge (FP32), gathered ahead.
+template <int H>
+struct NodeRows { float4 s[H / 16], d[H / 16]; };
+
+template <int H>
+__device__ inline void fetch_rows(NodeRows<H>& n, const float* ps, const float* pd, int src, int dst) {
   const int g = lane_group();
-  if (!valid) return;
+  const float4* rs = reinterpret_cast<const float4*>(ps + (int64_t)src * H);
+  const float4* rd = reinterpret_cast<const float4*>(pd + (int64_t)dst * H);
+#pragma unroll
+  for (int c = 0; c < H / 16; ++c) {
+    n.s[c] = rs[4 * c + g];
+    n.d[c] = rd[4 * c + g];
+  }
+}
+
+// a += source row, then a += target row (a fixed order for every pipeline depth)
+template <int H>
+__device__ inline void add_rows(float* a, const NodeRows<H>& n) {
+#pragma unroll
+  for (int c = 0; c < H / 16; ++c) {
+    a[4 * c + 0] += n.s[c].x; a[4 * c + 1] += n.s[c].y; a[4 * c + 2] += n.s[c].z; a[4 * c + 3] += n.s[c].w;
+  }
+#pragma unroll
+  for (int c = 0; c < H / 16; ++c) {
+    a[4 * c + 0] += n.d[c].x; a[4 * c + 1] += n.d[c].y; a[4 * c + 2] += n.d[c].z; a[4 * c + 3] += n.d[c].w;
+  }
+}
+
+// Software pipeline over a wave's tiles (tile, tile + stride, ...): with
+// depth 0 every tile loads its own operands; depth 1 issues the next tile's
+// edge indices and edge row before the current tile's arithmetic; depth 2
+// keeps the indices two tiles ahead and also issues the next tile's
+// node-product gathers early.  The arithmetic is the same at every depth.
+// Columns past the last edge (the tail of the last tile, tiles beyond the
+// end) read the last edge instead, so every load is unconditional; their
+// results are never stored.
+template <int P, int H, int PIPE>
+struct EdgeFeed {
+  const int32_t* src;
+  const int32_t* dst;
+  const void* e;
+  const float* ps;
+  const float* pd;
+  int64_t E, stride;
+  int lane16;
+  int s1 = 0, d1 = 0;           // indices of the next tile (depth 2)
+  int s0 = 0, d0 = 0;           // indices of the fetched tile
+  RawE<P, H> raw;
+  NodeRows<H> rows;
+  bool want_e;
+
+  __device__ int64_t col(int64_t t) const { return t * kCols + lane16; }
+  __device__ int64_t clamped(int64_t t) const { return min(col(t), E - 1); }
+  __device__ void idx(int64_t t, int& s, int& d) const {
+    const int64_t c = clamped(t);
+    s = src[c];
+    d = dst[c];
+  }
+  // operands of tile t into the feed registers
+  __device__ void fetch(int64_t t) {
+    if constexpr (PIPE == 2) {
+      s0 = s1; d0 = d1;
+      idx(t + stride, s1, d1);
+    } else {
+      idx(t, s0, d0);
+    }
+    if (want_e) fetch_e<P, H>(raw, e, clamped(t));
+    if constexpr (PIPE == 2) fetch_rows<H>(rows, ps, pd, s0, d0);
+  }
+  __device__ void start(int64_t t) {
+    if constexpr (PIPE == 2) idx(t, s1, d1);
+    if constexpr (PIPE >= 1) fetch(t);
+  }
+  // hand out tile t's operands (and its column's source node, -1 past the
+  // last edge) and issue tile t + stride's
+  __device__ void next(int64_t t, RawE<P, H>& r, NodeRows<H>& n, int& src_node) {
+    const bool v = col(t) < E;
+    if constexpr (PIPE == 0) {
+      fetch(t);
+      r = raw;
+      fetch_rows<H>(n, ps, pd, s0, d0);
+      src_node = v ? s0 : -1;
+    } else if constexpr (PIPE == 1) {
+      r = raw;
+      fetch_rows<H>(n, ps, pd, s0, d0);
+      src_node = v ? s0 : -1;
+      fetch(t + stride);
+    } else {
+      r = raw;
+      n = rows;
+      src_node = v ? s0 : -1;
+      fetch(t + stride);
+    }
+  }
+};
+
+// Store an edge row in the operand format.  q (if not null) receives the
+// values as stored (FP8: decoded times `scale`), the terms of the message sums.
+template <int P, int H>
+__device__ inline void store_e(void* e, int64_t col, const float* o, bool valid, float inv_scale, float scale = 1.f,
+                               float* q = nullptr) {
+  const int g = lane_group();
   if constexpr (P == P_F32) {
-    store_cols<H>(static_cast<float*>(e) + col * H, o, valid);
+    if (valid) store_cols<H>(static_cast<float*>(e) + col * H, o, valid);
+    if (q) {
+#pragma unroll
+      for (int r = 0; r < H / 4; ++r) q[r] = o[r];
+    }
   } else if constexpr (P == P_BF16) {
     uint16_t* row = static_cast<uint16_t*>(e) + col * H;
 #pragma unroll
-    for (int c = 0; c < H / 16; ++c)
-      *reinterpret_cast<uint2*>(row + 16 * c + 4 * g) =
-          make_uint2(bf16_bits(o[4 * c]) | (bf16_bits(o[4 * c + 1]) << 16),
-                     bf16_bits(o[4 * c + 2]) | (bf16_bits(o[4 * c + 3]) << 16));
+    for (int c = 0; c < H / 16; ++c) {
+      const uint32_t b0 = bf16_bits(o[4 * c]), b1 = bf16_bits(o[4 * c + 1]);
+      const uint32_t b2 = bf16_bits(o[4 * c + 2]), b3 = bf16_bits(o[4 * c + 3]);
+      if (valid) *reinterpret_cast<uint2*>(row + 16 * c + 4 * g) = make_uint2(b0 | (b1 << 16), b2 | (b3 << 16));
+      if (q) {
+        q[4 * c + 0] = bf16_value(b0);
+        q[4 * c + 1] = bf16_value(b1);
+        q[4 * c + 2] = bf16_value(b2);
+        q[4 * c + 3] = bf16_value(b3);
+      }
+    }
   } else {
     uint8_t* row = static_cast<uint8_t*>(e) + col * H;
 #pragma unroll
-    for (int c = 0; c < H / 16; ++c)
-      *reinterpret_cast<uint32_t*>(row + 16 * c + 4 * g) =
-          e4m3_encode4(o[4 * c] * inv_scale, o[4 * c + 1] * inv_scale, o[4 * c + 2] * inv_scale,
-                       o[4 * c + 3] * inv_scale);
+    for (int c = 0; c < H / 16; ++c) {
+      const uint32_t w = e4m3_encode4(o[4 * c] * inv_scale, o[4 * c + 1] * inv_scale, o[4 * c + 2] * inv_scale,
+                                      o[4 * c + 3] * inv_scale);
+      if (valid) *reinterpret_cast<uint32_t*>(row + 16 * c + 4 * g) = w;
+      if (q) {
+        q[4 * c + 0] = e4m3_byte<0>(w) * scale;
+        q[4 * c + 1] = e4m3_byte<1>(w) * scale;
+        q[4 * c + 2] = e4m3_byte<2>(w) * scale;
+        q[4 * c + 3] = e4m3_byte<3>(w) * scale;
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// out-sums fused into the edge kernels
+// --------------------------------------------------------------------------
+// Edges are source-major, so the out-sum of a node is the sum over one
+// contiguous run of edge columns.  A wave tile (16 consecutive edges, one per
+// lane of each 16-lane DPP row) reduces its runs with a segmented scan along
+// the row; the last column of each run then holds the run's sum.  A run that
+// lies inside the tile is the node's whole row and is written straight to the
+// message buffer; a run cut by a tile boundary goes to the tile's partial
+// slots (0: the run that began before the tile, 1: the run that continues
+// past it), which the message kernel adds up in tile order.
+
+// Row shifts within the 16-lane DPP rows.  Lanes whose source is outside
+// the row read 0 (values) or -2 (keys); the moves run with the whole wave
+// active, never under a lane-dependent branch, since a lane whose source lane
+// is inactive would read the fallback value too.
+template <int N>
+__device__ inline float row_shr_f(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x110 + N, 0xf, 0xf, true));
+}
+template <int N>
+__device__ inline int row_shr_i(int v) {
+  return __builtin_amdgcn_update_dpp(-2, v, 0x110 + N, 0xf, 0xf, false);
+}
+__device__ inline int row_shl1_i(int v) { return __builtin_amdgcn_update_dpp(-2, v, 0x101, 0xf, 0xf, false); }
+
+// inclusive segmented sums along the 16 columns; key is non-decreasing in the
+// column.  Each step is v += (same run ? 1 : 0) * v[column - 2^i], a single
+// multiply-add whose first operand is the row-shifted register.
+template <int N>
+__device__ inline void seg_scan_cols(float* v, int key) {
+  const int j = lane_id() & 15;
+  const int k1 = row_shr_i<1>(key), k2 = row_shr_i<2>(key), k4 = row_shr_i<4>(key), k8 = row_shr_i<8>(key);
+  const float m1 = ((j >= 1) & (k1 == key)) ? 1.f : 0.f, m2 = ((j >= 2) & (k2 == key)) ? 1.f : 0.f;
+  const float m4 = ((j >= 4) & (k4 == key)) ? 1.f : 0.f, m8 = ((j >= 8) & (k8 == key)) ? 1.f : 0.f;
+#pragma unroll
+  for (int r = 0; r < N; ++r) v[r] = fmaf(row_shr_f<1>(v[r]), m1, v[r]);
+#pragma unroll
+  for (int r = 0; r < N; ++r) v[r] = fmaf(row_shr_f<2>(v[r]), m2, v[r]);
+#pragma unroll
+  for (int r = 0; r < N; ++r) v[r] = fmaf(row_shr_f<4>(v[r]), m4, v[r]);
+#pragma unroll
+  for (int r = 0; r < N; ++r) v[r] = fmaf(row_shr_f<8>(v[r]), m8, v[r]);
+}
+
+// q: stored values of this lane's column; key: its source node (-1 past the
+// last edge).  Called by the whole wave.
+template <int H>
+__device__ inline void out_sums(const GnnArgs& A, int64_t tile, int64_t E, int key, float* q) {
+  const int64_t c0 = tile * kCols;
+  const int kb = c0 > 0 ? A.src[c0 - 1] : -1;
+  const int ka = c0 + kCols < E ? A.src[c0 + kCols] : -1;
+  const int key0 = __builtin_amdgcn_readlane(key, 0), key15 = __builtin_amdgcn_readlane(key, 15);
+  seg_scan_cols<H / 4>(q, key);
+  const int knext = row_shl1_i(key);
+  const bool last = ((lane_id() & 15) == 15) | (knext != key);
+  if (key >= 0 && last) {
+    const bool before = key == key0 && kb == key, after = key == key15 && ka == key;
+    float* dst = (!before && !after) ? A.msg + (int64_t)key * 2 * H : A.opart + (tile * 2 + (before ? 0 : 1)) * H;
+    store_cols<H>(dst, q, true);
   }
 }
 
@@ -197,7 +391,7 @@ __global__ __launch_bounds__(NodeThreads<P>::value) void k_node_encode(GnnArgs A
 // --------------------------------------------------------------------------
 // edge encoder
 // --------------------------------------------------------------------------
-template <int H, int P>
+template <int H, int P, int PIPE>
 __global__ __launch_bounds__(512) void k_edge_encode(GnnArgs A) {
   if (A.status[0] != 0) return;
   extern __shared__ float lds[];
@@ -207,17 +401,24 @@ __global__ __launch_bounds__(512) void k_edge_encode(GnnArgs A) {
   constexpr SegEdgeEnc S{H, PrecBytes<P>::value};
   const int lane = lane_id(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const float s_ee2 = asc(A, Q_EE2), o_ee2 = s_ee2 * wsc(A, SW_EE2);
-  const float inv_e0 = 1.0f / asc(A, Q_E + 0);
+  const float s_e0 = asc(A, Q_E + 0), inv_e0 = 1.0f / s_e0;
   const int64_t E = A.row_ptr[A.n_hits];
   const int64_t ntiles = (E + kCols - 1) / kCols;
-  for (int64_t tile = (int64_t)blockIdx.x * nw + wave; tile < ntiles; tile += (int64_t)gridDim.x * nw) {
+  const int64_t stride = (int64_t)gridDim.x * nw;
+  EdgeFeed<P, H, PIPE> feed{A.src, A.dst, nullptr, A.ps, A.pd, E, stride, lane & 15};
+  feed.want_e = false;
+  int64_t tile = (int64_t)blockIdx.x * nw + wave;
+  if (tile < ntiles) feed.start(tile);
+  for (; tile < ntiles; tile += stride) {
     const int64_t col = tile * kCols + (lane & 15);
     const bool valid = col < E;
-    const int s = valid ? A.src[col] : 0, d = valid ? A.dst[col] : 0;
+    RawE<P, H> unused;
+    NodeRows<H> rows;
+    int key;
+    feed.next(tile, unused, rows, key);
     float a[H / 4];
     bias_cols<H>(a, reinterpret_cast<const float*>(w + S.b1()));
-    add_cols<H>(a, A.ps + (int64_t)s * H, valid);
-    add_cols<H>(a, A.pd + (int64_t)d * H, valid);
+    add_rows<H>(a, rows);
     ln_relu<H>(a);
     observe<H / 4>(A.calib, SC_GNN + Q_EE2, a, valid);
     float o[H / 4];
@@ -225,13 +426,15 @@ __global__ __launch_bounds__(512) void k_edge_encode(GnnArgs A) {
     gemm<P, H, H / 16>(o, a, w + S.w2(), 1.0f / s_ee2, o_ee2);
     ln_relu<H>(o);
     observe<H / 4>(A.calib, SC_GNN + Q_E, o, valid);
-    store_e<P, H>(A.e, col, o, valid, inv_e0);
+    store_e<P, H>(A.e, col, o, valid, inv_e0, s_e0, o);
+    out_sums<H>(A, tile, E, key, o);
   }
 }
 
 // --------------------------------------------------------------------------
-// messages: segmented out-sums (CSR rows) and in-sums (CSC), one wave per
-// node; each lane reads 16 bytes of a row, several rows in flight per wave
+// messages, one wave per node: the out-sum from the edge kernels' tile
+// partials, the in-sum through the CSC permutation (each lane reads 16 bytes
+// of an edge row, several rows in flight per wave)
 // --------------------------------------------------------------------------
 template <int P>
 __device__ inline void add_chunk(float* acc, uint4 v) {
@@ -266,24 +469,37 @@ __global__ __launch_bounds__(256) void k_segsum(GnnArgs A) {
   constexpr int FPL = 16 / ES;         // features per lane
   constexpr int LPR = H / FPL;         // lanes per row
   constexpr int NS = 64 / LPR;         // rows in flight per load instruction
+  constexpr int LPO = H / 4;           // lanes per FP32 partial row
+  constexpr int NSO = 64 / LPO;
   const int lane = lane_id(), fl = lane % LPR, st = lane / LPR, wave = threadIdx.x >> 6;
+  const int flo = lane % LPO, sto = lane / LPO;
   const char* eb = static_cast<const char*>(A.e);
   const float scale = P == P_FP8 ? asc(A, Q_E + A.step) : 1.0f;
   for (int64_t node = (int64_t)blockIdx.x * 4 + wave; node < A.n_hits; node += (int64_t)gridDim.x * 4) {
-    float mo[FPL], mi[FPL];
-#pragma unroll
-    for (int i = 0; i < FPL; ++i) mo[i] = mi[i] = 0.f;
+    // out-sum: a source row inside one edge tile was written whole by the edge
+    // kernel; a longer row is its tile partials, first tile's slot 1 then
+    // slot 0 of each later tile
     const int64_t rb = A.row_ptr[node], re = A.row_ptr[node + 1];
-    for (int64_t t = rb + st; t < re; t += NS * U) {
-      uint4 v[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t q = t + (int64_t)u * NS;
-        v[u] = q < re ? *reinterpret_cast<const uint4*>(eb + (q * H + fl * FPL) * ES) : make_uint4(0u, 0u, 0u, 0u);
+    const int64_t t0 = rb / kCols, t1 = re > rb ? (re - 1) / kCols : t0;
+    if (re == rb || t1 > t0) {
+      float4 mo = make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int64_t i = sto; re > rb && i <= t1 - t0; i += NSO) {
+        const float4 v = *reinterpret_cast<const float4*>(A.opart + ((t0 + i) * 2 + (i == 0 ? 1 : 0)) * H + 4 * flo);
+        mo.x += v.x; mo.y += v.y; mo.z += v.z; mo.w += v.w;
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) add_chunk<P>(mo, v[u]);
+      for (int m = LPO; m < 64; m <<= 1) {
+        mo.x += __shfl_xor(mo.x, m);
+        mo.y += __shfl_xor(mo.y, m);
+        mo.z += __shfl_xor(mo.z, m);
+        mo.w += __shfl_xor(mo.w, m);
+      }
+      if (sto == 0) *reinterpret_cast<float4*>(A.msg + node * 2 * H + 4 * flo) = mo;
     }
+    // in-sum through the CSC permutation
+    float mi[FPL];
+#pragma unroll
+    for (int i = 0; i < FPL; ++i) mi[i] = 0.f;
     const int64_t cb = A.col_ptr[node], ce = A.col_ptr[node + 1];
     for (int64_t t = cb + st; t < ce; t += NS * U) {
       int id[U];
@@ -304,19 +520,13 @@ __global__ __launch_bounds__(256) void k_segsum(GnnArgs A) {
 #pragma unroll
     for (int m = LPR; m < 64; m <<= 1)
 #pragma unroll
-      for (int i = 0; i < FPL; ++i) {
-        mo[i] += __shfl_xor(mo[i], m);
-        mi[i] += __shfl_xor(mi[i], m);
-      }
+      for (int i = 0; i < FPL; ++i) mi[i] += __shfl_xor(mi[i], m);
     if (st == 0) {
-      float* out = A.msg + node * 2 * H + fl * FPL;
+      float* out = A.msg + node * 2 * H + H + fl * FPL;
 #pragma unroll
-      for (int i = 0; i < FPL; i += 4) {
-        *reinterpret_cast<float4*>(out + i) = make_float4(mo[i] * scale, mo[i + 1] * scale, mo[i + 2] * scale,
-                                                          mo[i + 3] * scale);
-        *reinterpret_cast<float4*>(out + H + i) = make_float4(mi[i] * scale, mi[i + 1] * scale, mi[i + 2] * scale,
-                                                              mi[i + 3] * scale);
-      }
+      for (int i = 0; i < FPL; i += 4)
+        *reinterpret_cast<float4*>(out + i) = make_float4(mi[i] * scale, mi[i + 1] * scale, mi[i + 2] * scale,
+                                                          mi[i + 3] * scale);
     }
   }
 }
@@ -383,7 +593,7 @@ __global__ __launch_bounds__(NodeThreads<P>::value) void k_node_step(GnnArgs A) 
 // --------------------------------------------------------------------------
 // edge update k; the last step also runs the classifier and writes scores
 // --------------------------------------------------------------------------
-template <int H, bool FINAL, int P>
+template <int H, bool FINAL, int P, int PIPE>
 __global__ __launch_bounds__(512) void k_edge_step(GnnArgs A) {
   if (A.status[0] != 0) return;
   extern __shared__ float lds[];
@@ -401,32 +611,50 @@ __global__ __launch_bounds__(512) void k_edge_step(GnnArgs A) {
   const float w1s = wsc(A, SW_STEP + 4 * k + 2), w2s = wsc(A, SW_STEP + 4 * k + 3), wcs = wsc(A, SW_CLS1);
   const int64_t E = A.row_ptr[A.n_hits];
   const int64_t ntiles = (E + kCols - 1) / kCols;
-  for (int64_t tile = (int64_t)blockIdx.x * nw + wave; tile < ntiles; tile += (int64_t)gridDim.x * nw) {
+  const int64_t stride = (int64_t)gridDim.x * nw;
+  EdgeFeed<P, H, PIPE> feed{A.src, A.dst, A.e, A.ps, A.pd, E, stride, lane & 15};
+  feed.want_e = true;
+  int64_t tile = (int64_t)blockIdx.x * nw + wave;
+  if (tile < ntiles) feed.start(tile);
+  for (; tile < ntiles; tile += stride) {
     const int64_t col = tile * kCols + (lane & 15);
     const bool valid = col < E;
-    const int s = valid ? A.src[col] : 0, d = valid ? A.dst[col] : 0;
-    float e[H / 4];
-    uint32_t ew[H / 16];
-    load_e<P, H>(e, ew, A.e, col, valid, s_e);
+    RawE<P, H> raw;
+    NodeRows<H> rows;
+    int key;
+    feed.next(tile, raw, rows, key);
+    // layer 1: b1 + W_e e (the stored operand as it is), then the gathered
+    // h W_src and h W_dst rows
     float a[H / 4];
     bias_cols<H>(a, reinterpret_cast<const float*>(w + S.b1()));
-    add_cols<H>(a, A.ps + (int64_t)s * H, valid);
-    add_cols<H>(a, A.pd + (int64_t)d * H, valid);
-    if constexpr (P == P_FP8)
-      mfma_fp8_codes<H, H / 16>(a, ew, reinterpret_cast<const uint64_t*>(w + S.we()), s_e * w1s);
-    else
-      gemm<P, H, H / 16>(a, e, w + S.we(), 1.f, 1.f);
+    if constexpr (P == P_FP8) {
+      mfma_fp8_codes<H, H / 16>(a, raw.v, reinterpret_cast<const uint64_t*>(w + S.we()), s_e * w1s);
+    } else if constexpr (P == P_BF16) {
+      mfma_bf16_words<H, H / 16>(a, raw.v, reinterpret_cast<const bf16x8*>(w + S.we()));
+    } else {
+      float ef[H / 4];
+      uint32_t unused[H / 16];
+      decode_e<P, H>(ef, unused, raw, s_e);
+      gemm<P, H, H / 16>(a, ef, w + S.we(), 1.f, 1.f);
+    }
+    add_rows<H>(a, rows);
     ln_relu<H>(a);
     observe<H / 4>(A.calib, SC_GNN + Q_EN2, a, valid);
     float o[H / 4];
     bias_cols<H>(o, reinterpret_cast<const float*>(w + S.b2()));
     gemm<P, H, H / 16>(o, a, w + S.w2(), 1.0f / s_en2, s_en2 * w2s);
     ln_relu<H>(o);
+    {
+      float e[H / 4];
+      uint32_t unused[H / 16];
+      decode_e<P, H>(e, unused, raw, s_e);
 #pragma unroll
-    for (int r = 0; r < H / 4; ++r) o[r] += e[r];
+      for (int r = 0; r < H / 4; ++r) o[r] += e[r];
+    }
     observe<H / 4>(A.calib, SC_GNN + Q_E + k + 1, o, valid);
     if (!FINAL) {
-      store_e<P, H>(A.e, col, o, valid, 1.0f / s_next);
+      store_e<P, H>(A.e, col, o, valid, 1.0f / s_next, s_next, o);
+      out_sums<H>(A, tile, E, key, o);
     } else {
       // classifier on the final edge encodings (quantised like a stored e_S)
       float c[H / 4];
@@ -469,14 +697,13 @@ static GnnArgs gnn_args(const RunArgs& a) {
   A.pd = reinterpret_cast<float*>(a.ws + a.L.pd);
   A.msg = reinterpret_cast<float*>(a.ws + a.L.msg);
   A.e = a.ws + a.L.e;
+  A.opart = reinterpret_cast<float*>(a.ws + a.L.opart);
   A.score = a.out.score;
   A.calib = a.calibrate ? reinterpret_cast<float*>(a.ws + a.L.calib) : nullptr;
   A.sc = c->dev_scales;
   A.status = a.out.status;
   return A;
 }
-
-constexpr int kEdgeThreads = 512;
 
 static int node_threads(int prec) { return prec == P_F32 ? 1024 : 512; }
 
@@ -523,7 +750,11 @@ hipError_t launch_edge_encode(const RunArgs& a) {
   A.seg = seg_ptr(a, m.edge_enc);
   A.seg_bytes = SegEdgeEnc{Hh, kPrecBytes[a.prec]}.size();
   unsigned grid = (unsigned)(a.ctx->n_cu * a.ctx->edge_wg_per_cu);
-  DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_edge_encode<H, P>), dim3(grid), dim3(kEdgeThreads), A.seg_bytes, a.stream, A));
+  switch (a.ctx->edge_pipeline) {
+    case 0: DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_edge_encode<H, P, 0>), dim3(grid), dim3(a.ctx->edge_threads), A.seg_bytes, a.stream, A)); break;
+    case 2: DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_edge_encode<H, P, 2>), dim3(grid), dim3(a.ctx->edge_threads), A.seg_bytes, a.stream, A)); break;
+    default: DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_edge_encode<H, P, 1>), dim3(grid), dim3(a.ctx->edge_threads), A.seg_bytes, a.stream, A)); break;
+  }
   return hipGetLastError();
 }
 
@@ -570,11 +801,17 @@ hipError_t launch_edge_step(const RunArgs& a, int k, bool final_step) {
   A.step = k;
   size_t lds = A.seg_bytes + (final_step ? A.seg2_bytes : 0);
   unsigned grid = (unsigned)(a.ctx->n_cu * a.ctx->edge_wg_per_cu);
-  if (final_step) {
-    DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_edge_step<H, true, P>), dim3(grid), dim3(kEdgeThreads), lds, a.stream, A));
-  } else {
-    DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_edge_step<H, false, P>), dim3(grid), dim3(kEdgeThreads), lds, a.stream, A));
+#define EDGE_STEP(F_, PIPE_) \
+  DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_edge_step<H, F_, P, PIPE_>), dim3(grid), dim3(a.ctx->edge_threads), lds, a.stream, A))
+  switch (a.ctx->edge_pipeline * 2 + (final_step ? 1 : 0)) {
+    case 0: EDGE_STEP(false, 0); break;
+    case 1: EDGE_STEP(true, 0); break;
+    case 4: EDGE_STEP(false, 2); break;
+    case 5: EDGE_STEP(true, 2); break;
+    case 3: EDGE_STEP(true, 1); break;
+    default: EDGE_STEP(false, 1); break;
   }
+#undef EDGE_STEP
   return hipGetLastError();
 }
 
@@ -599,9 +836,15 @@ static void set_gnn_attr(int& bad, size_t max_lds) {
   };
   set(reinterpret_cast<const void*>(k_node_encode<H, P>));
   set(reinterpret_cast<const void*>(k_node_step<H, P>));
-  set(reinterpret_cast<const void*>(k_edge_step<H, true, P>));
-  set(reinterpret_cast<const void*>(k_edge_step<H, false, P>));
-  set(reinterpret_cast<const void*>(k_edge_encode<H, P>));
+  set(reinterpret_cast<const void*>(k_edge_step<H, true, P, 0>));
+  set(reinterpret_cast<const void*>(k_edge_step<H, false, P, 0>));
+  set(reinterpret_cast<const void*>(k_edge_step<H, true, P, 1>));
+  set(reinterpret_cast<const void*>(k_edge_step<H, false, P, 1>));
+  set(reinterpret_cast<const void*>(k_edge_step<H, true, P, 2>));
+  set(reinterpret_cast<const void*>(k_edge_step<H, false, P, 2>));
+  set(reinterpret_cast<const void*>(k_edge_encode<H, P, 0>));
+  set(reinterpret_cast<const void*>(k_edge_encode<H, P, 1>));
+  set(reinterpret_cast<const void*>(k_edge_encode<H, P, 2>));
 }
 
 int gnn_attributes(size_t max_lds) {

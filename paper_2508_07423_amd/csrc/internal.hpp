@@ -12,7 +12,7 @@
 
 namespace etx {
 
-constexpr int kTile = 32;          // columns (hits or edges) per wave tile
+constexpr int kEdgeTile = 16;      // edges per wave tile of the MLP kernels (the MFMA column count)
 constexpr int kDpad = 16;          // padded embedding width in HBM
 constexpr int kScanBlock = 1024;   // elements per block of the device-wide scan
 
@@ -31,7 +31,7 @@ struct WeightMap {
 
 // Byte offsets of the workspace buffers.
 struct WsLayout {
-  size_t bucket, plane_off, emb, cnt, row_ptr, scan_tmp, col_ptr, csc, h, ps, pd, msg, e, kept, kept_cnt,
+  size_t bucket, plane_off, emb, cnt, row_ptr, scan_tmp, col_ptr, csc, h, ps, pd, msg, e, opart, kept, kept_cnt,
       calib, pf_keep, pf_tmp, cand_src, cand_dst, pf_prob, pf_part, pf_grad, total;
   int64_t n_scan_blocks;
 };
@@ -57,10 +57,12 @@ struct etx_ctx {
   float* dev_pf = nullptr;
   bool pf_set = false;
   // tuning
-  int edge_wg_per_cu = 2;
+  int edge_wg_per_cu = 3;
   int node_wg_per_cu = 1;
   int radius_lds = 1;
   int segsum_unroll = 4;
+  int edge_pipeline = 1;
+  int edge_threads = 512;
   int use_graph = 0;
   std::map<etx::GraphKey, hipGraphExec_t> graphs;
   // stage timing with HIP events (ETX_OPT_PROFILE)

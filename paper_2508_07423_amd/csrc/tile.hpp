@@ -133,6 +133,30 @@ __device__ inline void mfma_bf16(float* acc, const float* x, const bf16x8* __res
     for (int v = 0; v < 4; ++v) acc[4 * mb + v] = c[mb][v];
 }
 
+// Same with the operand already in BF16: xr[c] packs registers 4c .. 4c+3
+// (low half first), so K-step t is xr[2t], xr[2t+1] as they are.
+template <int K, int MB>
+__device__ inline void mfma_bf16_words(float* acc, const uint2* xr, const bf16x8* __restrict__ w) {
+  const int lane = lane_id();
+  floatx4 c[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) c[mb][v] = acc[4 * mb + v];
+#pragma unroll
+  for (int t = 0; t < K / 32; ++t) {
+    const bf16x8 b = __builtin_bit_cast(bf16x8, make_uint4(xr[2 * t].x, xr[2 * t].y, xr[2 * t + 1].x, xr[2 * t + 1].y));
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+      c[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[(mb * (K / 32) + t) * 64 + lane], b, c[mb], 0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[4 * mb + v] = c[mb][v];
+}
+
 // ---------------------------------------------------------------------------
 // low-precision formats
 // ---------------------------------------------------------------------------

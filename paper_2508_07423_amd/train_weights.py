@@ -116,7 +116,7 @@ def knn_pairs(emb, plane, r2, k, window=2):
         return torch.cat(src), torch.cat(dst)
 
 
-def train_embedding(nets, events, w, epochs, lr, w_genuine=3.0, log=print):
+def train_embedding(nets, events, w, epochs, lr, w_genuine=3.0, log=print, on_epoch=None):
     torch = _torch()
     opt = torch.optim.Adam(nets.params(["emb"]), lr=lr)
     margin = w.radius ** 2 / 0.9
@@ -161,6 +161,8 @@ def train_embedding(nets, events, w, epochs, lr, w_genuine=3.0, log=print):
             opt.step()
             tot += float(loss)
         log(f"[emb] epoch {ep} loss {tot / len(events):.5f}")
+        if on_epoch is not None:
+            on_epoch("emb", ep)
 
 
 def block(x, Wb):
@@ -195,7 +197,7 @@ def focal_loss(logit, y, alpha=0.25, gamma=2.0):
     return (a * (1 - pt) ** gamma * ce).mean()
 
 
-def train_gnn(nets, events, w, epochs, lr, log=print):
+def train_gnn(nets, events, w, epochs, lr, log=print, on_epoch=None):
     torch = _torch()
     names = ["node_enc", "edge_enc", "cls"] + [f"node{k}" for k in range(w.gnn_steps)] + \
             [f"edge{k}" for k in range(w.gnn_steps)]
@@ -219,9 +221,15 @@ def train_gnn(nets, events, w, epochs, lr, log=print):
             tot += float(loss)
             acc += float(((logit > 0).float() == y).float().mean())
         log(f"[gnn] epoch {ep} loss {tot / len(events):.5f} edge accuracy {acc / len(events):.4f}")
+        if on_epoch is not None:
+            on_epoch("gnn", ep)
 
 
-def train(w, n_events: int, epochs_emb: int, epochs_gnn: int, seed: int = 5, threads: int = 8, log=print) -> Dict:
+def train(w, n_events: int, epochs_emb: int, epochs_gnn: int, seed: int = 5, threads: int = 8, log=print,
+          init: Dict = None, checkpoint: str = None) -> Dict:
+    """Train both phases; ``init`` starts from a saved weight set (with
+    ``epochs_emb=0`` it resumes at the GNN phase), ``checkpoint`` is rewritten
+    after every epoch so an interrupted run leaves its latest weights."""
     torch = _torch()
     torch.manual_seed(seed)
     torch.set_num_threads(threads)
@@ -231,10 +239,19 @@ def train(w, n_events: int, epochs_emb: int, epochs_gnn: int, seed: int = 5, thr
         ev["true"] = true_edges(ev["plane"], ev["particle"], ev["z"])
         evs.append(ev)
     nets = Nets(w, seed)
+    if init is not None:
+        nets.p = {k: [(torch.tensor(W, requires_grad=True), torch.tensor(b, requires_grad=True)) for W, b in v]
+                  for k, v in init.items()}
+
+    def on_epoch(phase, ep):
+        if checkpoint is not None:
+            save(nets.export(), checkpoint)
+            log(f"[{phase}] checkpoint after epoch {ep}: {checkpoint}")
+
     t0 = time.time()
-    train_embedding(nets, evs, w, epochs_emb, 3e-3, log=log)
+    train_embedding(nets, evs, w, epochs_emb, 3e-3, log=log, on_epoch=on_epoch)
     log(f"[emb] {time.time() - t0:.0f} s")
-    train_gnn(nets, evs, w, epochs_gnn, 2e-3, log=log)
+    train_gnn(nets, evs, w, epochs_gnn, 2e-3, log=log, on_epoch=on_epoch)
     log(f"[gnn] {time.time() - t0:.0f} s")
     return nets.export()
 
@@ -245,7 +262,9 @@ def save(weights: Dict, path: str) -> None:
         for i, (W, b) in enumerate(v):
             flat[f"{k}.{i}.W"] = W
             flat[f"{k}.{i}.b"] = b
-    np.savez(path, **flat)
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, **flat)
+    os.replace(tmp, path)      # an interrupted run never leaves a torn file
 
 
 if __name__ == "__main__":
@@ -255,10 +274,14 @@ if __name__ == "__main__":
     ap.add_argument("--epochs-emb", type=int, default=6)
     ap.add_argument("--epochs-gnn", type=int, default=6)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--threads", type=int, default=8)
+    ap.add_argument("--resume", default=None, help="start from this saved weight set")
     a = ap.parse_args()
     w = synth.WORKLOADS[a.workload]
-    W = train(w, a.events, a.epochs_emb, a.epochs_gnn, log=lambda s: print(s, flush=True))
     out = a.out or os.path.join(HERE, "weights", f"{w.name}_trained.npz")
     os.makedirs(os.path.dirname(out), exist_ok=True)
+    init = synth.load_weights(a.resume) if a.resume else None
+    W = train(w, a.events, a.epochs_emb, a.epochs_gnn, threads=a.threads, log=lambda s: print(s, flush=True),
+              init=init, checkpoint=out)
     save(W, out)
     print(out)

@@ -158,7 +158,34 @@ def test_radius_global_fallback_and_unroll_identical(c1_run):
     finally:
         etx.etx_set_option(p.ctx, etx.ETX_OPT_RADIUS_LDS, 1)
         etx.etx_set_option(p.ctx, etx.ETX_OPT_SEGSUM_UNROLL, 4)
-        etx.etx_set_option(p.ctx, etx.ETX_OPT_EDGE_WG_PER_CU, 2)
+        etx.etx_set_option(p.ctx, etx.ETX_OPT_EDGE_WG_PER_CU, 3)
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_edge_schedules_bit_identical(prec):
+    """Every software-pipeline depth and workgroup shape of the edge kernels
+    computes the same bits (a multi-event c3 batch: many tiles per wave)."""
+    etx = _etx()
+    w = synth.C3
+    W = centred_weights(w)
+    batch = synth.generate_batch(w, 8)
+    p = etx.Pipeline(w, W, precision=prec)
+    if prec == etx.ETX_FP8_E4M3:
+        p.calibrate(etx.to_device(synth.generate_batch(w, 4, seed_space=1000 + w.cid)))
+    b = etx.to_device(batch)
+    ref = None
+    for threads, per_cu in ((512, 2), (256, 1), (256, 5)):
+        for pipe in (0, 1, 2):
+            etx.etx_set_option(p.ctx, etx.ETX_OPT_EDGE_WG_SIZE, threads)
+            etx.etx_set_option(p.ctx, etx.ETX_OPT_EDGE_WG_PER_CU, per_cu)
+            etx.etx_set_option(p.ctx, etx.ETX_OPT_EDGE_PIPELINE, pipe)
+            p.run(b)
+            r = p.results(b)
+            if ref is None:
+                ref = r
+                continue
+            for k in ("src", "dst", "score", "labels", "edge_off"):
+                assert np.array_equal(r[k], ref[k]), (threads, per_cu, pipe, k)
 
 
 def test_permutation_equivariance_gpu():
