@@ -150,7 +150,10 @@ typedef enum {
   ETX_OPT_PROFILE = 5,       /* 1: time every stage of eager runs with HIP events on the run's stream */
   ETX_OPT_EDGE_PIPELINE = 6, /* software pipeline of the per-edge kernels: 0 none, 1 prefetch the next
                                 tile's indices and edge rows, 2 also its node-product gathers */
-  ETX_OPT_EDGE_WG_SIZE = 7   /* threads per workgroup of the per-edge kernels: 256 or 512 */
+  ETX_OPT_EDGE_WG_SIZE = 7,  /* threads per workgroup of the per-edge kernels: 256 or 512 */
+  ETX_OPT_EDGE_WREG = 8,     /* 1: FP32 edge-update kernels keep their weights in registers (0: read LDS) */
+  ETX_OPT_EMBED_PRECISION = 9 /* GEMM operand precision of the embedding MLP (etx_precision), or -1 (default):
+                                 the same as the configuration's precision */
 } etx_option;
 etx_status etx_set_option(etx_ctx* ctx, int32_t key, int64_t value);
 etx_status etx_get_option(const etx_ctx* ctx, int32_t key, int64_t* value);

@@ -204,14 +204,15 @@ def round_e4m3(x: float) -> float:
 # ---------------------------------------------------------------------------
 
 def run_event(ev: Dict[str, np.ndarray], w, weights, with_margins: bool = False, qmode: int = 0,
-              scales=None) -> Dict[str, np.ndarray]:
+              scales=None, emb_qmode: Optional[int] = None) -> Dict[str, np.ndarray]:
     """The full hot path on one event.  ``w`` carries the workload constants
     (r_scale, z_scale, radius, k_max, plane_window, gnn_hidden, gnn_steps,
     threshold); ``weights`` the network parameters.  qmode 1 (BF16) or 2 (FP8,
-    ``scales`` from ``calibrate``) quantises the GEMM operands."""
+    ``scales`` from ``calibrate``) quantises the GEMM operands; ``emb_qmode``
+    gives the embedding its own mode (default: qmode)."""
     cyl, cart = features(ev["x"], ev["y"], ev["z"], w.r_scale, w.z_scale)
     es, gs = (scales[0], scales[1]) if scales is not None else (None, None)
-    emb = embed(cyl, weights["emb"], qmode, es)
+    emb = embed(cyl, weights["emb"], qmode if emb_qmode is None else emb_qmode, es)
     r32 = float(np.float32(w.radius))
     src, dst = radius_graph(ev["plane"], emb, r32, w.k_max, w.plane_window)
     logit = gnn(cart, src, dst, weights, w.gnn_hidden, w.gnn_steps, qmode, gs)
@@ -227,14 +228,14 @@ def run_event(ev: Dict[str, np.ndarray], w, weights, with_margins: bool = False,
 
 def run_batch(batch: Dict[str, np.ndarray], w, weights, events: Optional[Sequence[int]] = None,
               threads: Optional[int] = None, with_margins: bool = False, qmode: int = 0,
-              scales=None) -> List[Dict[str, np.ndarray]]:
+              scales=None, emb_qmode: Optional[int] = None) -> List[Dict[str, np.ndarray]]:
     hit_off = batch["hit_off"]
     idx = list(range(len(hit_off) - 1)) if events is None else list(events)
 
     def one(i):
         a, b = int(hit_off[i]), int(hit_off[i + 1])
         ev = {k: batch[k][a:b] for k in ("x", "y", "z", "plane")}
-        return run_event(ev, w, weights, with_margins, qmode, scales)
+        return run_event(ev, w, weights, with_margins, qmode, scales, emb_qmode)
 
     nt = threads or os.cpu_count() or 1
     if nt <= 1 or len(idx) <= 1:

@@ -595,6 +595,14 @@ etx_status etx_set_option(etx_ctx* ctx, int32_t key, int64_t value) {
       if (value != 256 && value != 512) return ETX_ERR_INVALID_ARG;
       ctx->edge_threads = (int)value;
       break;
+    case ETX_OPT_EDGE_WREG:
+      if (value != 0 && value != 1) return ETX_ERR_INVALID_ARG;
+      ctx->edge_wreg = (int)value;
+      break;
+    case ETX_OPT_EMBED_PRECISION:
+      if (value < -1 || value > ETX_FP8_E4M3) return ETX_ERR_INVALID_ARG;
+      ctx->emb_precision = (int)value;
+      break;
     default: return ETX_ERR_INVALID_ARG;
   }
   if (key != ETX_OPT_USE_GRAPH) clear_graphs(ctx);
@@ -644,6 +652,8 @@ etx_status etx_get_option(const etx_ctx* ctx, int32_t key, int64_t* value) {
     case ETX_OPT_SEGSUM_UNROLL: *value = ctx->segsum_unroll; break;
     case ETX_OPT_EDGE_PIPELINE: *value = ctx->edge_pipeline; break;
     case ETX_OPT_EDGE_WG_SIZE: *value = ctx->edge_threads; break;
+    case ETX_OPT_EDGE_WREG: *value = ctx->edge_wreg; break;
+    case ETX_OPT_EMBED_PRECISION: *value = ctx->emb_precision; break;
     case ETX_OPT_PROFILE: *value = ctx->profile; break;
     default: return ETX_ERR_INVALID_ARG;
   }
@@ -654,7 +664,8 @@ etx_status etx_run(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void* ws, s
   WsLayout L;
   etx_status st = check_run_args(ctx, hits, out, ws, ws_bytes, &L);
   if (st != ETX_OK) return st;
-  if (ctx->cfg.precision == ETX_FP8_E4M3 && !ctx->calibrated) return ETX_ERR_INVALID_ARG;
+  if ((ctx->cfg.precision == ETX_FP8_E4M3 || ctx->emb_precision == ETX_FP8_E4M3) && !ctx->calibrated)
+    return ETX_ERR_INVALID_ARG;
   if (ctx->cfg.prefilter && !ctx->pf_set) return ETX_ERR_INVALID_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return ETX_ERR_HIP;
   RunArgs a{ctx, *hits, *out, L, static_cast<char*>(ws), static_cast<hipStream_t>(stream), false,

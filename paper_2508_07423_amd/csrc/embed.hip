@@ -94,6 +94,8 @@ __global__ __launch_bounds__(256) void k_embed(EmbedArgs A) {
 hipError_t launch_embed(const RunArgs& a) {
   if (a.hits.n_hits == 0) return hipSuccess;
   const etx_ctx* c = a.ctx;
+  // the embedding may run at its own operand precision (calibration runs stay FP32)
+  const int prec = (!a.calibrate && c->emb_precision >= 0) ? c->emb_precision : a.prec;
   EmbedArgs A;
   A.x = a.hits.x;
   A.y = a.hits.y;
@@ -101,19 +103,19 @@ hipError_t launch_embed(const RunArgs& a) {
   A.n_hits = a.hits.n_hits;
   A.inv_r = 1.0f / c->cfg.r_scale_mm;
   A.inv_z = 1.0f / c->cfg.z_scale_mm;
-  A.seg = static_cast<const char*>(c->seg_base[a.prec]) + c->wmap[a.prec].emb;
+  A.seg = static_cast<const char*>(c->seg_base[prec]) + c->wmap[prec].emb;
   A.layers = c->cfg.emb_layers;
   A.sc = c->dev_scales;
   A.emb = reinterpret_cast<float*>(a.ws + a.L.emb);
   A.calib = a.calibrate ? reinterpret_cast<float*>(a.ws + a.L.calib) : nullptr;
   A.status = a.out.status;
   const int W = c->cfg.emb_hidden;
-  A.seg_bytes = SegEmb{W, A.layers, kPrecBytes[a.prec]}.size();
+  A.seg_bytes = SegEmb{W, A.layers, kPrecBytes[prec]}.size();
   size_t lds = A.seg_bytes;
   int64_t tiles = (A.n_hits + kCols - 1) / kCols;
   unsigned grid = (unsigned)std::min<int64_t>((tiles + 3) / 4, (int64_t)c->n_cu * 2);
 #define EMB(W_, P_) hipLaunchKernelGGL((k_embed<W_, P_>), dim3(grid), dim3(256), lds, a.stream, A)
-  switch (W * 4 + a.prec) {
+  switch (W * 4 + prec) {
     case 32 * 4 + 0: EMB(32, 0); break;
     case 32 * 4 + 1: EMB(32, 1); break;
     case 32 * 4 + 2: EMB(32, 2); break;

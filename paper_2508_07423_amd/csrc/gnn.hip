@@ -82,45 +82,66 @@ __device__ inline float wsc(const GnnArgs& A, int s) { return A.sc[s]; }
 // edge-encoding rows in the operand format
 // --------------------------------------------------------------------------
 
-// Raw column-layout chunks of an edge row (4 features per chunk in the operand
-// format), fetched ahead of use by the software-pipelined edge kernels.
-template <int P> struct EChunk;
-template <> struct EChunk<P_F32> { using T = float4; };
-template <> struct EChunk<P_BF16> { using T = uint2; };
-template <> struct EChunk<P_FP8> { using T = uint32_t; };
+// Stored edge-row layout.  Lane group g of a column holds registers
+// r = 0 .. H/4-1 (features phi(r, g)); in the operand format these are
+// LB = H/4 * ES bytes, kept in the row as contiguous 16-byte chunks: chunk q
+// of group g at byte 64 q + 16 g (rows of FP8 at H = 32 have 8 bytes per
+// group, at byte 8 g).  Every load or store instruction of a wave then moves
+// 64 contiguous bytes per column, and a chunk of BF16 or FP8 codes is
+// directly the MFMA operand of one 32-wide K-step.  FP32 rows are the plain
+// feature order.
+template <int P, int H>
+struct ELayout {
+  static constexpr int ES = PrecBytes<P>::value;
+  static constexpr int LB = H / 4 * ES;                 // bytes per lane group
+  static constexpr int NQ = LB >= 16 ? LB / 16 : 1;     // 16-byte chunks per lane group
+  static constexpr int ROW = H * ES;                    // bytes per row
+  // feature stored at byte b of a row
+  __host__ __device__ static constexpr int feature(int b) {
+    return LB >= 16 ? phi((b / 64) * (16 / ES) + (b % 16) / ES, (b % 64) / 16) : phi((b % LB) / ES, b / LB);
+  }
+};
 
 template <int P, int H>
-struct RawE { typename EChunk<P>::T v[H / 16]; };
+struct RawE { uint4 v[ELayout<P, H>::NQ]; };
 
 // col must address a stored row (callers clamp the tail of the last tile).
 template <int P, int H>
 __device__ inline void fetch_e(RawE<P, H>& r, const void* e, int64_t col) {
-  using T = typename EChunk<P>::T;
+  using L = ELayout<P, H>;
   const int g = lane_group();
-  const T* row = reinterpret_cast<const T*>(static_cast<const char*>(e) + col * H * PrecBytes<P>::value);
+  const char* row = static_cast<const char*>(e) + col * L::ROW;
+  if constexpr (L::LB >= 16) {
 #pragma unroll
-  for (int c = 0; c < H / 16; ++c) r.v[c] = row[4 * c + g];
+    for (int q = 0; q < L::NQ; ++q) r.v[q] = *reinterpret_cast<const uint4*>(row + 64 * q + 16 * g);
+  } else {
+    const uint2 h = *reinterpret_cast<const uint2*>(row + L::LB * g);
+    r.v[0] = make_uint4(h.x, h.y, 0u, 0u);
+  }
 }
 
-// ef gets the values (FP8: decoded times `scale`), words the raw FP8 codes.
+// 32-bit word i of a lane group's bytes
 template <int P, int H>
-__device__ inline void decode_e(float* ef, uint32_t* words, const RawE<P, H>& r, float scale) {
+__device__ inline uint32_t raw_word(const RawE<P, H>& r, int i) {
+  const uint4 c = r.v[i / 4];
+  return (i % 4) == 0 ? c.x : (i % 4) == 1 ? c.y : (i % 4) == 2 ? c.z : c.w;
+}
+
+// Register values of the row (FP8: decoded times `scale`).
+template <int P, int H>
+__device__ inline void decode_e(float* ef, const RawE<P, H>& r, float scale) {
 #pragma unroll
-  for (int c = 0; c < H / 16; ++c) {
+  for (int x = 0; x < H / 4; ++x) {
     if constexpr (P == P_F32) {
-      ef[4 * c + 0] = r.v[c].x; ef[4 * c + 1] = r.v[c].y; ef[4 * c + 2] = r.v[c].z; ef[4 * c + 3] = r.v[c].w;
+      ef[x] = __uint_as_float(raw_word<P, H>(r, x));
     } else if constexpr (P == P_BF16) {
-      ef[4 * c + 0] = bf16_value(r.v[c].x & 0xffffu);
-      ef[4 * c + 1] = bf16_value(r.v[c].x >> 16);
-      ef[4 * c + 2] = bf16_value(r.v[c].y & 0xffffu);
-      ef[4 * c + 3] = bf16_value(r.v[c].y >> 16);
+      const uint32_t w = raw_word<P, H>(r, x / 2);
+      ef[x] = bf16_value((x % 2) ? (w >> 16) : (w & 0xffffu));
     } else {
-      const uint32_t w = r.v[c];
-      words[c] = w;
-      ef[4 * c + 0] = e4m3_byte<0>(w) * scale;
-      ef[4 * c + 1] = e4m3_byte<1>(w) * scale;
-      ef[4 * c + 2] = e4m3_byte<2>(w) * scale;
-      ef[4 * c + 3] = e4m3_byte<3>(w) * scale;
+      const uint32_t w = raw_word<P, H>(r, x / 4);
+      const float v = (x % 4) == 0 ? e4m3_byte<0>(w) : (x % 4) == 1 ? e4m3_byte<1>(w)
+                    : (x % 4) == 2 ? e4m3_byte<2>(w) : e4m3_byte<3>(w);
+      ef[x] = v * scale;
     }
   }
 }
@@ -227,41 +248,47 @@ struct EdgeFeed {
 template <int P, int H>
 __device__ inline void store_e(void* e, int64_t col, const float* o, bool valid, float inv_scale, float scale = 1.f,
                                float* q = nullptr) {
+  using L = ELayout<P, H>;
   const int g = lane_group();
+  char* row = static_cast<char*>(e) + col * L::ROW;
+  uint32_t w[L::NQ * 4];
   if constexpr (P == P_F32) {
-    if (valid) store_cols<H>(static_cast<float*>(e) + col * H, o, valid);
+#pragma unroll
+    for (int x = 0; x < H / 4; ++x) w[x] = __float_as_uint(o[x]);
     if (q) {
 #pragma unroll
-      for (int r = 0; r < H / 4; ++r) q[r] = o[r];
+      for (int x = 0; x < H / 4; ++x) q[x] = o[x];
     }
   } else if constexpr (P == P_BF16) {
-    uint16_t* row = static_cast<uint16_t*>(e) + col * H;
 #pragma unroll
-    for (int c = 0; c < H / 16; ++c) {
-      const uint32_t b0 = bf16_bits(o[4 * c]), b1 = bf16_bits(o[4 * c + 1]);
-      const uint32_t b2 = bf16_bits(o[4 * c + 2]), b3 = bf16_bits(o[4 * c + 3]);
-      if (valid) *reinterpret_cast<uint2*>(row + 16 * c + 4 * g) = make_uint2(b0 | (b1 << 16), b2 | (b3 << 16));
+    for (int x = 0; x < H / 8; ++x) {
+      const uint32_t b0 = bf16_bits(o[2 * x]), b1 = bf16_bits(o[2 * x + 1]);
+      w[x] = b0 | (b1 << 16);
       if (q) {
-        q[4 * c + 0] = bf16_value(b0);
-        q[4 * c + 1] = bf16_value(b1);
-        q[4 * c + 2] = bf16_value(b2);
-        q[4 * c + 3] = bf16_value(b3);
+        q[2 * x] = bf16_value(b0);
+        q[2 * x + 1] = bf16_value(b1);
       }
     }
   } else {
-    uint8_t* row = static_cast<uint8_t*>(e) + col * H;
 #pragma unroll
-    for (int c = 0; c < H / 16; ++c) {
-      const uint32_t w = e4m3_encode4(o[4 * c] * inv_scale, o[4 * c + 1] * inv_scale, o[4 * c + 2] * inv_scale,
-                                      o[4 * c + 3] * inv_scale);
-      if (valid) *reinterpret_cast<uint32_t*>(row + 16 * c + 4 * g) = w;
+    for (int x = 0; x < H / 16; ++x) {
+      w[x] = e4m3_encode4(o[4 * x] * inv_scale, o[4 * x + 1] * inv_scale, o[4 * x + 2] * inv_scale,
+                          o[4 * x + 3] * inv_scale);
       if (q) {
-        q[4 * c + 0] = e4m3_byte<0>(w) * scale;
-        q[4 * c + 1] = e4m3_byte<1>(w) * scale;
-        q[4 * c + 2] = e4m3_byte<2>(w) * scale;
-        q[4 * c + 3] = e4m3_byte<3>(w) * scale;
+        q[4 * x + 0] = e4m3_byte<0>(w[x]) * scale;
+        q[4 * x + 1] = e4m3_byte<1>(w[x]) * scale;
+        q[4 * x + 2] = e4m3_byte<2>(w[x]) * scale;
+        q[4 * x + 3] = e4m3_byte<3>(w[x]) * scale;
       }
     }
+  }
+  if (!valid) return;
+  if constexpr (L::LB >= 16) {
+#pragma unroll
+    for (int c = 0; c < L::NQ; ++c)
+      *reinterpret_cast<uint4*>(row + 64 * c + 16 * g) = make_uint4(w[4 * c], w[4 * c + 1], w[4 * c + 2], w[4 * c + 3]);
+  } else {
+    *reinterpret_cast<uint2*>(row + L::LB * g) = make_uint2(w[0], w[1]);
   }
 }
 
@@ -522,11 +549,13 @@ __global__ __launch_bounds__(256) void k_segsum(GnnArgs A) {
 #pragma unroll
       for (int i = 0; i < FPL; ++i) mi[i] += __shfl_xor(mi[i], m);
     if (st == 0) {
-      float* out = A.msg + node * 2 * H + H + fl * FPL;
+      // value i of chunk fl is the feature stored at byte 16 fl + i ES; runs of
+      // four values are four consecutive features
+      float* out = A.msg + node * 2 * H + H;
 #pragma unroll
       for (int i = 0; i < FPL; i += 4)
-        *reinterpret_cast<float4*>(out + i) = make_float4(mi[i] * scale, mi[i + 1] * scale, mi[i + 2] * scale,
-                                                          mi[i + 3] * scale);
+        *reinterpret_cast<float4*>(out + ELayout<P, H>::feature(16 * fl + i * ES)) =
+            make_float4(mi[i] * scale, mi[i + 1] * scale, mi[i + 2] * scale, mi[i + 3] * scale);
     }
   }
 }
@@ -593,7 +622,9 @@ __global__ __launch_bounds__(NodeThreads<P>::value) void k_node_step(GnnArgs A) 
 // --------------------------------------------------------------------------
 // edge update k; the last step also runs the classifier and writes scores
 // --------------------------------------------------------------------------
-template <int H, bool FINAL, int P, int PIPE>
+// WR (FP32 only): both H x H weight matrices stay in registers for the whole
+// persistent loop instead of being read from LDS by every MFMA.
+template <int H, bool FINAL, int P, int PIPE, bool WR>
 __global__ __launch_bounds__(512) void k_edge_step(GnnArgs A) {
   if (A.status[0] != 0) return;
   extern __shared__ float lds[];
@@ -614,6 +645,12 @@ __global__ __launch_bounds__(512) void k_edge_step(GnnArgs A) {
   const int64_t stride = (int64_t)gridDim.x * nw;
   EdgeFeed<P, H, PIPE> feed{A.src, A.dst, A.e, A.ps, A.pd, E, stride, lane & 15};
   feed.want_e = true;
+  static_assert(!WR || P == P_F32, "register-resident weights are FP32 only");
+  float wr_e[WR ? H * H / 64 : 1], wr_2[WR ? H * H / 64 : 1];
+  if constexpr (WR) {
+    load_wreg<H, H / 16>(wr_e, reinterpret_cast<const float*>(w + S.we()));
+    load_wreg<H, H / 16>(wr_2, reinterpret_cast<const float*>(w + S.w2()));
+  }
   int64_t tile = (int64_t)blockIdx.x * nw + wave;
   if (tile < ntiles) feed.start(tile);
   for (; tile < ntiles; tile += stride) {
@@ -628,26 +665,31 @@ __global__ __launch_bounds__(512) void k_edge_step(GnnArgs A) {
     float a[H / 4];
     bias_cols<H>(a, reinterpret_cast<const float*>(w + S.b1()));
     if constexpr (P == P_FP8) {
-      mfma_fp8_codes<H, H / 16>(a, raw.v, reinterpret_cast<const uint64_t*>(w + S.we()), s_e * w1s);
+      mfma_fp8_codes<H, H / 16>(a, reinterpret_cast<const uint32_t*>(raw.v), reinterpret_cast<const uint64_t*>(w + S.we()),
+                                s_e * w1s);
     } else if constexpr (P == P_BF16) {
-      mfma_bf16_words<H, H / 16>(a, raw.v, reinterpret_cast<const bf16x8*>(w + S.we()));
+      mfma_bf16_chunks<H, H / 16>(a, raw.v, reinterpret_cast<const bf16x8*>(w + S.we()));
     } else {
       float ef[H / 4];
-      uint32_t unused[H / 16];
-      decode_e<P, H>(ef, unused, raw, s_e);
-      gemm<P, H, H / 16>(a, ef, w + S.we(), 1.f, 1.f);
+      decode_e<P, H>(ef, raw, s_e);
+      if constexpr (WR)
+        mfma_f32_reg<H, H / 16>(a, ef, wr_e);
+      else
+        gemm<P, H, H / 16>(a, ef, w + S.we(), 1.f, 1.f);
     }
     add_rows<H>(a, rows);
     ln_relu<H>(a);
     observe<H / 4>(A.calib, SC_GNN + Q_EN2, a, valid);
     float o[H / 4];
     bias_cols<H>(o, reinterpret_cast<const float*>(w + S.b2()));
-    gemm<P, H, H / 16>(o, a, w + S.w2(), 1.0f / s_en2, s_en2 * w2s);
+    if constexpr (WR)
+      mfma_f32_reg<H, H / 16>(o, a, wr_2);
+    else
+      gemm<P, H, H / 16>(o, a, w + S.w2(), 1.0f / s_en2, s_en2 * w2s);
     ln_relu<H>(o);
     {
       float e[H / 4];
-      uint32_t unused[H / 16];
-      decode_e<P, H>(e, unused, raw, s_e);
+      decode_e<P, H>(e, raw, s_e);
 #pragma unroll
       for (int r = 0; r < H / 4; ++r) o[r] += e[r];
     }
@@ -801,8 +843,17 @@ hipError_t launch_edge_step(const RunArgs& a, int k, bool final_step) {
   A.step = k;
   size_t lds = A.seg_bytes + (final_step ? A.seg2_bytes : 0);
   unsigned grid = (unsigned)(a.ctx->n_cu * a.ctx->edge_wg_per_cu);
-#define EDGE_STEP(F_, PIPE_) \
-  DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_edge_step<H, F_, P, PIPE_>), dim3(grid), dim3(a.ctx->edge_threads), lds, a.stream, A))
+#define EDGE_STEP(F_, PIPE_)                                                                           \
+  if (a.prec == P_F32 && a.ctx->edge_wreg) {                                                          \
+    if (Hh == 64)                                                                                     \
+      hipLaunchKernelGGL((k_edge_step<64, F_, P_F32, PIPE_, true>), dim3(grid), dim3(a.ctx->edge_threads), lds, a.stream, A); \
+    else if (Hh == 32)                                                                                \
+      hipLaunchKernelGGL((k_edge_step<32, F_, P_F32, PIPE_, true>), dim3(grid), dim3(a.ctx->edge_threads), lds, a.stream, A); \
+    else                                                                                              \
+      return hipErrorInvalidValue;                                                                    \
+  } else {                                                                                            \
+    DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_edge_step<H, F_, P, PIPE_, false>), dim3(grid), dim3(a.ctx->edge_threads), lds, a.stream, A)); \
+  }
   switch (a.ctx->edge_pipeline * 2 + (final_step ? 1 : 0)) {
     case 0: EDGE_STEP(false, 0); break;
     case 1: EDGE_STEP(true, 0); break;
@@ -836,12 +887,20 @@ static void set_gnn_attr(int& bad, size_t max_lds) {
   };
   set(reinterpret_cast<const void*>(k_node_encode<H, P>));
   set(reinterpret_cast<const void*>(k_node_step<H, P>));
-  set(reinterpret_cast<const void*>(k_edge_step<H, true, P, 0>));
-  set(reinterpret_cast<const void*>(k_edge_step<H, false, P, 0>));
-  set(reinterpret_cast<const void*>(k_edge_step<H, true, P, 1>));
-  set(reinterpret_cast<const void*>(k_edge_step<H, false, P, 1>));
-  set(reinterpret_cast<const void*>(k_edge_step<H, true, P, 2>));
-  set(reinterpret_cast<const void*>(k_edge_step<H, false, P, 2>));
+  set(reinterpret_cast<const void*>(k_edge_step<H, true, P, 0, false>));
+  set(reinterpret_cast<const void*>(k_edge_step<H, false, P, 0, false>));
+  set(reinterpret_cast<const void*>(k_edge_step<H, true, P, 1, false>));
+  set(reinterpret_cast<const void*>(k_edge_step<H, false, P, 1, false>));
+  set(reinterpret_cast<const void*>(k_edge_step<H, true, P, 2, false>));
+  set(reinterpret_cast<const void*>(k_edge_step<H, false, P, 2, false>));
+  if constexpr (P == P_F32) {
+    set(reinterpret_cast<const void*>(k_edge_step<H, true, P, 0, true>));
+    set(reinterpret_cast<const void*>(k_edge_step<H, false, P, 0, true>));
+    set(reinterpret_cast<const void*>(k_edge_step<H, true, P, 1, true>));
+    set(reinterpret_cast<const void*>(k_edge_step<H, false, P, 1, true>));
+    set(reinterpret_cast<const void*>(k_edge_step<H, true, P, 2, true>));
+    set(reinterpret_cast<const void*>(k_edge_step<H, false, P, 2, true>));
+  }
   set(reinterpret_cast<const void*>(k_edge_encode<H, P, 0>));
   set(reinterpret_cast<const void*>(k_edge_encode<H, P, 1>));
   set(reinterpret_cast<const void*>(k_edge_encode<H, P, 2>));

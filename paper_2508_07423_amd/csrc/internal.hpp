@@ -63,6 +63,8 @@ struct etx_ctx {
   int segsum_unroll = 4;
   int edge_pipeline = 1;
   int edge_threads = 512;
+  int edge_wreg = 0;
+  int emb_precision = -1;          // -1: cfg.precision
   int use_graph = 0;
   std::map<etx::GraphKey, hipGraphExec_t> graphs;
   // stage timing with HIP events (ETX_OPT_PROFILE)

@@ -107,6 +107,34 @@ __device__ inline void mfma_f32(float* acc, const float* x, const float* __restr
     for (int v = 0; v < 4; ++v) acc[4 * mb + v] = c[mb][v];
 }
 
+// The same product with the layer's weights held in registers for the
+// whole kernel (wr[i] = w[i*64 + lane], i = mb*(K/4) + t): no LDS traffic
+// and no waits inside the MFMA chain.
+template <int K, int MB>
+__device__ inline void load_wreg(float* wr, const float* __restrict__ w) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int i = 0; i < MB * (K / 4); ++i) wr[i] = w[i * 64 + lane];
+}
+
+template <int K, int MB>
+__device__ inline void mfma_f32_reg(float* acc, const float* x, const float* wr) {
+  floatx4 c[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) c[mb][v] = acc[4 * mb + v];
+#pragma unroll
+  for (int t = 0; t < K / 4; ++t)
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+      c[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(wr[mb * (K / 4) + t], x[t], c[mb], 0, 0, 0);
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[4 * mb + v] = c[mb][v];
+}
+
 // BF16 operands, K-steps of 32: lane group g supplies registers 8t..8t+7.
 //   w[(mb*(K/32) + t)*64 + lane][q] = W[phi(8t+q, lane/16)][16*mb + lane%16], q = 0..7.
 template <int K, int MB>
@@ -133,10 +161,10 @@ __device__ inline void mfma_bf16(float* acc, const float* x, const bf16x8* __res
     for (int v = 0; v < 4; ++v) acc[4 * mb + v] = c[mb][v];
 }
 
-// Same with the operand already in BF16: xr[c] packs registers 4c .. 4c+3
-// (low half first), so K-step t is xr[2t], xr[2t+1] as they are.
+// Same with the operand already in BF16: chunk t holds registers 8t .. 8t+7
+// (low half first), the K-step's operand as it is.
 template <int K, int MB>
-__device__ inline void mfma_bf16_words(float* acc, const uint2* xr, const bf16x8* __restrict__ w) {
+__device__ inline void mfma_bf16_chunks(float* acc, const uint4* xr, const bf16x8* __restrict__ w) {
   const int lane = lane_id();
   floatx4 c[MB];
 #pragma unroll
@@ -145,7 +173,7 @@ __device__ inline void mfma_bf16_words(float* acc, const uint2* xr, const bf16x8
     for (int v = 0; v < 4; ++v) c[mb][v] = acc[4 * mb + v];
 #pragma unroll
   for (int t = 0; t < K / 32; ++t) {
-    const bf16x8 b = __builtin_bit_cast(bf16x8, make_uint4(xr[2 * t].x, xr[2 * t].y, xr[2 * t + 1].x, xr[2 * t + 1].y));
+    const bf16x8 b = __builtin_bit_cast(bf16x8, xr[t]);
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
       c[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[(mb * (K / 32) + t) * 64 + lane], b, c[mb], 0, 0, 0);

@@ -174,18 +174,20 @@ def test_edge_schedules_bit_identical(prec):
         p.calibrate(etx.to_device(synth.generate_batch(w, 4, seed_space=1000 + w.cid)))
     b = etx.to_device(batch)
     ref = None
-    for threads, per_cu in ((512, 2), (256, 1), (256, 5)):
-        for pipe in (0, 1, 2):
-            etx.etx_set_option(p.ctx, etx.ETX_OPT_EDGE_WG_SIZE, threads)
-            etx.etx_set_option(p.ctx, etx.ETX_OPT_EDGE_WG_PER_CU, per_cu)
-            etx.etx_set_option(p.ctx, etx.ETX_OPT_EDGE_PIPELINE, pipe)
-            p.run(b)
-            r = p.results(b)
-            if ref is None:
-                ref = r
-                continue
-            for k in ("src", "dst", "score", "labels", "edge_off"):
-                assert np.array_equal(r[k], ref[k]), (threads, per_cu, pipe, k)
+    for wreg in ((0, 1) if prec == etx.ETX_FP32 else (0,)):
+        for threads, per_cu in ((512, 2), (256, 1), (256, 5)):
+            for pipe in (0, 1, 2):
+                etx.etx_set_option(p.ctx, etx.ETX_OPT_EDGE_WREG, wreg)
+                etx.etx_set_option(p.ctx, etx.ETX_OPT_EDGE_WG_SIZE, threads)
+                etx.etx_set_option(p.ctx, etx.ETX_OPT_EDGE_WG_PER_CU, per_cu)
+                etx.etx_set_option(p.ctx, etx.ETX_OPT_EDGE_PIPELINE, pipe)
+                p.run(b)
+                r = p.results(b)
+                if ref is None:
+                    ref = r
+                    continue
+                for k in ("src", "dst", "score", "labels", "edge_off"):
+                    assert np.array_equal(r[k], ref[k]), (wreg, threads, per_cu, pipe, k)
 
 
 def test_permutation_equivariance_gpu():

@@ -141,3 +141,36 @@ def test_fp8_calibration_and_pipeline_against_quantised_oracle():
           "vs fp64 oracle", _score_stats(res["score"], s64))
     s64s = _score_stats(res["score"], s64)
     assert sq["mean"] <= 0.5 * s64s["mean"] and sq["max"] <= 0.1
+
+
+def test_fp8_network_with_bf16_embedding():
+    """Per-network precision: an FP8-E4M3 interaction network behind a BF16
+    embedding (the embedding's output is compared against the radius, so its
+    coordinates need more mantissa than the network's operands)."""
+    etx = _etx()
+    w = synth.C1
+    W = synth.xavier_weights(w)
+    cal = synth.generate_batch(w, 3, seed_space=1001)
+    batch = synth.generate_batch(w, 1)
+    ev = synth.event_slice(batch, 0)
+    p = etx.Pipeline(w, W, precision=etx.ETX_FP8_E4M3)
+    p.calibrate(etx.to_device(cal))
+    etx.etx_set_option(p.ctx, etx.ETX_OPT_EMBED_PRECISION, etx.ETX_BF16)
+    assert etx.etx_get_option(p.ctx, etx.ETX_OPT_EMBED_PRECISION) == etx.ETX_BF16
+    for bad in (-2, 3):
+        with pytest.raises(etx.EtxError):
+            etx.etx_set_option(p.ctx, etx.ETX_OPT_EMBED_PRECISION, bad)
+    b = etx.to_device(batch)
+    p.run(b)
+    res = p.results(b)
+    es, gs, _, _ = O.calibrate([synth.event_slice(cal, i) for i in range(3)], w, W)
+    ref = O.run_event(ev, w, W, qmode=2, scales=(es, gs), emb_qmode=1)
+    ref_bf16 = O.run_event(ev, w, W, qmode=1)
+    # the BF16 embedding gives the BF16 pipeline's edge list
+    assert np.array_equal(res["src"], ref["src"]) and np.array_equal(res["dst"], ref["dst"])
+    assert np.array_equal(ref["src"], ref_bf16["src"]) and np.array_equal(ref["dst"], ref_bf16["dst"])
+    _, cart = O.features(ev["x"], ev["y"], ev["z"], w.r_scale, w.z_scale)
+    sq = _score_stats(res["score"], ref["score"])
+    s64 = _score_stats(res["score"], O.sigmoid(O.gnn(cart, res["src"], res["dst"], W, w.gnn_hidden, w.gnn_steps)))
+    print("fp8 network + bf16 embedding: vs quantised oracle", sq, "vs fp64 oracle", s64)
+    assert sq["mean"] <= 0.5 * s64["mean"] and sq["max"] <= 0.1
