@@ -183,6 +183,12 @@ __device__ inline void add_rows(float* a, const NodeRows<H>& n) {
 // Columns past the last edge (the tail of the last tile, tiles beyond the
 // end) read the last edge instead, so every load is unconditional; their
 // results are never stored.
+// Tile indices: the column's source and target, and the sources of the edges
+// just before and just after the tile (-1 past either end of the list).
+struct TileIdx {
+  int s, d, before, after;
+};
+
 template <int P, int H, int PIPE>
 struct EdgeFeed {
   const int32_t* src;
@@ -192,54 +198,58 @@ struct EdgeFeed {
   const float* pd;
   int64_t E, stride;
   int lane16;
-  int s1 = 0, d1 = 0;           // indices of the next tile (depth 2)
-  int s0 = 0, d0 = 0;           // indices of the fetched tile
+  TileIdx i1{0, 0, -1, -1};     // indices of the next tile (depth 2)
+  TileIdx i0{0, 0, -1, -1};     // indices of the fetched tile
   RawE<P, H> raw;
   NodeRows<H> rows;
   bool want_e;
 
   __device__ int64_t col(int64_t t) const { return t * kCols + lane16; }
   __device__ int64_t clamped(int64_t t) const { return min(col(t), E - 1); }
-  __device__ void idx(int64_t t, int& s, int& d) const {
-    const int64_t c = clamped(t);
-    s = src[c];
-    d = dst[c];
+  __device__ void idx(int64_t t, TileIdx& x) const {
+    const int64_t c = clamped(t), c0 = t * kCols;
+    x.s = src[c];
+    x.d = dst[c];
+    const int b = src[max(min(c0 - 1, E - 1), (int64_t)0)], a = src[min(c0 + kCols, E - 1)];
+    x.before = c0 > 0 ? b : -1;
+    x.after = c0 + kCols < E ? a : -1;
   }
   // operands of tile t into the feed registers
   __device__ void fetch(int64_t t) {
     if constexpr (PIPE == 2) {
-      s0 = s1; d0 = d1;
-      idx(t + stride, s1, d1);
+      i0 = i1;
+      idx(t + stride, i1);
     } else {
-      idx(t, s0, d0);
+      idx(t, i0);
     }
     if (want_e) fetch_e<P, H>(raw, e, clamped(t));
-    if constexpr (PIPE == 2) fetch_rows<H>(rows, ps, pd, s0, d0);
+    if constexpr (PIPE == 2) fetch_rows<H>(rows, ps, pd, i0.s, i0.d);
   }
   __device__ void start(int64_t t) {
-    if constexpr (PIPE == 2) idx(t, s1, d1);
+    if constexpr (PIPE == 2) idx(t, i1);
     if constexpr (PIPE >= 1) fetch(t);
   }
-  // hand out tile t's operands (and its column's source node, -1 past the
-  // last edge) and issue tile t + stride's
-  __device__ void next(int64_t t, RawE<P, H>& r, NodeRows<H>& n, int& src_node) {
+  // hand out tile t's operands and indices (key: the column's source node,
+  // -1 past the last edge) and issue tile t + stride's
+  __device__ void next(int64_t t, RawE<P, H>& r, NodeRows<H>& n, TileIdx& x, int& key) {
     const bool v = col(t) < E;
     if constexpr (PIPE == 0) {
       fetch(t);
       r = raw;
-      fetch_rows<H>(n, ps, pd, s0, d0);
-      src_node = v ? s0 : -1;
+      fetch_rows<H>(n, ps, pd, i0.s, i0.d);
+      x = i0;
     } else if constexpr (PIPE == 1) {
       r = raw;
-      fetch_rows<H>(n, ps, pd, s0, d0);
-      src_node = v ? s0 : -1;
+      fetch_rows<H>(n, ps, pd, i0.s, i0.d);
+      x = i0;
       fetch(t + stride);
     } else {
       r = raw;
       n = rows;
-      src_node = v ? s0 : -1;
+      x = i0;
       fetch(t + stride);
     }
+    key = v ? x.s : -1;
   }
 };
 
@@ -338,18 +348,16 @@ __device__ inline void seg_scan_cols(float* v, int key) {
 }
 
 // q: stored values of this lane's column; key: its source node (-1 past the
-// last edge).  Called by the whole wave.
+// last edge); x.before / x.after: sources of the neighbouring edges of the
+// tile.  Called by the whole wave.
 template <int H>
-__device__ inline void out_sums(const GnnArgs& A, int64_t tile, int64_t E, int key, float* q) {
-  const int64_t c0 = tile * kCols;
-  const int kb = c0 > 0 ? A.src[c0 - 1] : -1;
-  const int ka = c0 + kCols < E ? A.src[c0 + kCols] : -1;
+__device__ inline void out_sums(const GnnArgs& A, int64_t tile, const TileIdx& x, int key, float* q) {
   const int key0 = __builtin_amdgcn_readlane(key, 0), key15 = __builtin_amdgcn_readlane(key, 15);
   seg_scan_cols<H / 4>(q, key);
   const int knext = row_shl1_i(key);
   const bool last = ((lane_id() & 15) == 15) | (knext != key);
   if (key >= 0 && last) {
-    const bool before = key == key0 && kb == key, after = key == key15 && ka == key;
+    const bool before = key == key0 && x.before == key, after = key == key15 && x.after == key;
     float* dst = (!before && !after) ? A.msg + (int64_t)key * 2 * H : A.opart + (tile * 2 + (before ? 0 : 1)) * H;
     store_cols<H>(dst, q, true);
   }
@@ -441,8 +449,9 @@ __global__ __launch_bounds__(512) void k_edge_encode(GnnArgs A) {
     const bool valid = col < E;
     RawE<P, H> unused;
     NodeRows<H> rows;
+    TileIdx ti;
     int key;
-    feed.next(tile, unused, rows, key);
+    feed.next(tile, unused, rows, ti, key);
     float a[H / 4];
     bias_cols<H>(a, reinterpret_cast<const float*>(w + S.b1()));
     add_rows<H>(a, rows);
@@ -454,7 +463,7 @@ __global__ __launch_bounds__(512) void k_edge_encode(GnnArgs A) {
     ln_relu<H>(o);
     observe<H / 4>(A.calib, SC_GNN + Q_E, o, valid);
     store_e<P, H>(A.e, col, o, valid, inv_e0, s_e0, o);
-    out_sums<H>(A, tile, E, key, o);
+    out_sums<H>(A, tile, ti, key, o);
   }
 }
 
@@ -658,8 +667,9 @@ __global__ __launch_bounds__(512) void k_edge_step(GnnArgs A) {
     const bool valid = col < E;
     RawE<P, H> raw;
     NodeRows<H> rows;
+    TileIdx ti;
     int key;
-    feed.next(tile, raw, rows, key);
+    feed.next(tile, raw, rows, ti, key);
     // layer 1: b1 + W_e e (the stored operand as it is), then the gathered
     // h W_src and h W_dst rows
     float a[H / 4];
@@ -696,7 +706,7 @@ __global__ __launch_bounds__(512) void k_edge_step(GnnArgs A) {
     observe<H / 4>(A.calib, SC_GNN + Q_E + k + 1, o, valid);
     if (!FINAL) {
       store_e<P, H>(A.e, col, o, valid, 1.0f / s_next, s_next, o);
-      out_sums<H>(A, tile, E, key, o);
+      out_sums<H>(A, tile, ti, key, o);
     } else {
       // classifier on the final edge encodings (quantised like a stored e_S)
       float c[H / 4];

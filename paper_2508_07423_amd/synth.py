@@ -54,6 +54,10 @@ class Workload:
     hit_efficiency: float = 0.98
     smear_xy: float = 0.012
     noise_fraction: float = 0.05
+    # hit order inside an event: "readout" = plane by plane, by azimuth within a
+    # plane (the order a module-by-module detector readout delivers, as the
+    # thesis's GPU framework stores its hits); "shuffled" = random
+    hit_order: str = "readout"
 
     @property
     def n_planes(self) -> int:
@@ -105,7 +109,7 @@ def _n_tracks(w: Workload, rng: np.random.Generator) -> int:
 
 
 def generate_event(w: Workload, index: int, seed_space: Optional[int] = None) -> Dict[str, np.ndarray]:
-    """One event as SoA arrays in a random (shuffled) hit order.
+    """One event as SoA arrays, hits in the workload's order (``hit_order``).
 
     Returns x, y, z (float32, mm), plane (int32), particle (int32, -1 = noise).
     """
@@ -148,6 +152,10 @@ def generate_event(w: Workload, index: int, seed_space: Optional[int] = None) ->
     plane = np.concatenate([plane, npl])
     part = np.concatenate([part, np.full(n_noise, -1, np.int32)])
     order = rng.permutation(len(x))
+    if w.hit_order == "readout":
+        order = np.lexsort((np.arctan2(y, x), plane))
+    elif w.hit_order != "shuffled":
+        raise ValueError(f"unknown hit order {w.hit_order!r}")
     return dict(x=x[order].astype(np.float32), y=y[order].astype(np.float32),
                 z=z[order].astype(np.float32), plane=plane[order].astype(np.int32),
                 particle=part[order].astype(np.int32))

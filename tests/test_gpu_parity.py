@@ -250,6 +250,16 @@ def check_invariants(w, batch, res):
     assert np.array_equal(lab, O.components(n, src, dst, k))
 
 
+def test_shuffled_hit_order_parity():
+    """Hits in random order (no readout locality) give the same results."""
+    w = synth.C3.with_(hit_order="shuffled")
+    W = centred_weights(w)
+    batch = synth.generate_batch(w, 3)
+    p, b, res = run_gpu(w, W, batch)
+    for i in range(3):
+        event_parity(w, W, batch, res, i)
+
+
 def test_uneven_batch_c1_net_parity():
     """Uneven event sizes (20..600 tracks) with the one-event network."""
     w = synth.C3
