@@ -36,7 +36,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c5"],
+                    help="c5: the c3 workload with trained weights and the learned prefilter, trained before timing")
+    ap.add_argument("--pf-train-events", type=int, default=50000, help="c5: prefilter training events")
+    ap.add_argument("--pf-recall", type=float, default=0.995, help="c5: positive-edge recall that fixes tau")
     ap.add_argument("--events", type=int, default=None, help="override the number of events")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--graph", type=int, default=0, help="replay the batch as one captured HIP graph")
@@ -160,11 +163,33 @@ def main():
     dtype = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8"}[args.precision]
     t_gen = time.perf_counter()
     batch = synth.generate_batch(w, n_events)
-    weights = synth.xavier_weights(w)
+    use_pf = w.name == "c5"
+    # the prefilter learns from what the full pipeline keeps, which needs a trained network
+    weights = synth.trained_weights(w) if use_pf else synth.xavier_weights(w)
     print(f"[bench] workload {w.name}: {n_events} events, {int(batch['hit_off'][-1])} hits "
           f"(generated in {time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
 
+    pf_info = None
+    if use_pf:
+        from paper_2508_07423_amd import evaluate
+        from paper_2508_07423_amd import prefilter_train as PT
+        t_tr = time.perf_counter()
+        tr = PT.train_prefilter(w, weights, n_events=args.pf_train_events, batch_events=20, lr=1e-2,
+                                log=lambda m: print(m, file=sys.stderr, flush=True))
+        t_tr = time.perf_counter() - t_tr
+        sel = PT.choose_tau(w, weights, tr["params"], synth.generate_batch(w, 100, seed_space=6000 + w.cid),
+                            recall=args.pf_recall)
+        print(f"[bench] prefilter: {args.pf_train_events} training events, {tr['steps']} steps in {t_tr:.1f} s, "
+              f"tau {sel['tau']:.4f} keeps {sel['kept_fraction']:.3f} of validation candidates", file=sys.stderr,
+              flush=True)
+        pf_info = dict(train_events=args.pf_train_events, train_steps=tr["steps"], train_s=round(t_tr, 1),
+                       tau=round(sel["tau"], 5), recall_target=args.pf_recall,
+                       validation_kept=round(sel["kept_fraction"], 4))
+
     p = etx.Pipeline(w, weights, precision=prec)
+    if use_pf:
+        etx.etx_prefilter_set(p.ctx, tr["params"])
+        etx.etx_prefilter_config(p.ctx, 1, sel["tau"])
     stream = torch.cuda.Stream()
     if prec == etx.ETX_FP8_E4M3:
         # static calibration on events of a disjoint seed space
@@ -222,6 +247,27 @@ def main():
                         traffic=measured_traffic(dom, w.name, dtype))
         print(f"[bench] stages (ms/step): " + ", ".join(f"{k} {v['ms']}" for k, v in stages.items()),
               file=sys.stderr, flush=True)
+    if use_pf:
+        # the unpruned pipeline on the same batch: its throughput and efficiency are the reference
+        p0 = etx.Pipeline(w, weights, precision=prec)
+        if args.graph:
+            etx.etx_set_option(p0.ctx, etx.ETX_OPT_USE_GRAPH, 1)
+        with torch.cuda.stream(stream):
+            for _ in range(args.warmup):
+                p0.run(b, stream=stream)
+            torch.cuda.synchronize()
+            u0 = time.perf_counter()
+            for _ in range(args.steps):
+                p0.run(b, stream=stream)
+            torch.cuda.synchronize()
+            u1 = time.perf_counter()
+        r0 = p0.results(b)
+        m0, m1 = evaluate.batch_metrics(r0["labels"], batch), evaluate.batch_metrics(res["labels"], batch)
+        pf_info.update(edges_unpruned=int(r0["edge_off"][-1]), edges_kept=n_edges,
+                       kept_fraction=round(n_edges / max(int(r0["edge_off"][-1]), 1), 4),
+                       unpruned_events_per_s=round(n_events * args.steps / (u1 - u0), 2),
+                       efficiency=round(m1["efficiency"], 5), efficiency_unpruned=round(m0["efficiency"], 5))
+        p0.close()
     cpu = None
     if args.cpu_baseline:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
@@ -240,7 +286,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": dtype,
-        "data": "synthetic (seeded straight-track events, random Xavier weights)",
+        "data": "synthetic (seeded straight-track events, " + ("trained weights, learned prefilter)" if use_pf
+                                                                  else "random Xavier weights)"),
         "config": {
             "workload": f"{w.name}: {n_events} events, {w.n_planes} planes, tracks {w.tracks[0]}({w.tracks[1]}), "
                         f"emb 3-{w.emb_hidden}x{w.emb_layers}-{w.emb_dim}, radius {w.radius}, k {w.k_max}, "
@@ -250,6 +297,7 @@ def main():
         },
         "roofline": roof,
         "cpu_baseline": cpu,
+        "prefilter": pf_info,
         "stages_ms_per_step": stages,
     }
     print(json.dumps(line), flush=True)

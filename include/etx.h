@@ -152,8 +152,15 @@ typedef enum {
                                 tile's indices and edge rows, 2 also its node-product gathers */
   ETX_OPT_EDGE_WG_SIZE = 7,  /* threads per workgroup of the per-edge kernels: 256 or 512 */
   ETX_OPT_EDGE_WREG = 8,     /* 1: FP32 edge-update kernels keep their weights in registers (0: read LDS) */
-  ETX_OPT_EMBED_PRECISION = 9 /* GEMM operand precision of the embedding MLP (etx_precision), or -1 (default):
-                                 the same as the configuration's precision */
+  ETX_OPT_EMBED_PRECISION = 9, /* GEMM operand precision of the embedding MLP (etx_precision), or -1 (default):
+                                  the same as the configuration's precision */
+  ETX_OPT_OUTSUM_LDS = 10,    /* 1: hidden size 64 reduces the out-sums through an LDS transpose (0: DPP scan) */
+  ETX_OPT_F32_SPLIT = 11,     /* 1: in FP32 runs the edge kernels compute their GEMMs on the BF16 matrix cores with
+                                 every FP32 operand split exactly into three BF16 parts (six partial products,
+                                 FP32 accumulation; error at FP32 rounding level); 0: FP32 matrix cores */
+  ETX_OPT_RADIUS_SINGLE_PASS = 12 /* 1 (default): the radius search selects each source's neighbours once into
+                                     k_max workspace slots per hit and the CSR rows are copied after the scan;
+                                     0: a count pass and an emit pass */
 } etx_option;
 etx_status etx_set_option(etx_ctx* ctx, int32_t key, int64_t value);
 etx_status etx_get_option(const etx_ctx* ctx, int32_t key, int64_t* value);

@@ -45,6 +45,7 @@ WsLayout ws_layout(const etx_ctx* ctx, int64_t n_events, int64_t n_hits, int64_t
   L.plane_off = take(sizeof(int32_t) * n_events * (c.n_planes + 1));
   L.emb = take(sizeof(float) * n_hits * kDpad);
   L.cnt = take(sizeof(int32_t) * n_hits);
+  L.slots = take(sizeof(int32_t) * n_hits * c.k_max);
   L.row_ptr = take(sizeof(int64_t) * (n_hits + 1));
   L.scan_tmp = take(sizeof(int64_t) * (L.n_scan_blocks + 1));
   L.col_ptr = take(sizeof(int64_t) * (n_hits + 1));
@@ -113,6 +114,13 @@ static float pow2_scale(double amax) {
 
 // Write a row-major [K][M] weight (M padded to Mpad) permuted for the column
 // layout of tile.hpp in operand format `prec`; FP8 stores W / scale.
+static float bf16_float(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
 static void put_perm(char* out, const float* W, int K, int M, int Mpad, int prec, float scale) {
   for (int mb = 0; mb < Mpad / 16; ++mb)
     for (int lane = 0; lane < 64; ++lane) {
@@ -129,7 +137,17 @@ static void put_perm(char* out, const float* W, int K, int M, int Mpad, int prec
             const int row = phi(8 * t + q, g);
             const float v = col < M ? W[(size_t)row * M + col] : 0.f;
             const size_t at = (((size_t)mb * (K / 32) + t) * 64 + lane) * 8 + q;
-            if (prec == ETX_BF16) {
+            if (prec == kF32Split) {
+              // three BF16 planes: hi, mid, lo with v = hi + mid + lo to 24 bits
+              const size_t plane = (size_t)Mpad * K;
+              const uint16_t h = host_bf16(v);
+              const float r = v - bf16_float(h);
+              const uint16_t m = host_bf16(r);
+              const uint16_t l = host_bf16(r - bf16_float(m));
+              std::memcpy(out + at * 2, &h, 2);
+              std::memcpy(out + (plane + at) * 2, &m, 2);
+              std::memcpy(out + (2 * plane + at) * 2, &l, 2);
+            } else if (prec == ETX_BF16) {
               uint16_t b = host_bf16(v);
               std::memcpy(out + at * 2, &b, 2);
             } else {
@@ -397,9 +415,15 @@ static hipError_t enqueue_pipeline(const RunArgs& a) {
   STEP(2, launch_bucket(a));
   STEP(3, launch_embed(a));
   const bool pf = c.prefilter != 0;
-  STEP(4, launch_radius(a, false, pf));
-  STEP(5, launch_scan_counts(a, pf));
-  STEP(6, launch_radius(a, true, pf));
+  if (a.ctx->radius_single) {
+    STEP(4, launch_radius(a, 2, pf));
+    STEP(5, launch_scan_counts(a, pf));
+    STEP(6, launch_slots_copy(a, pf));
+  } else {
+    STEP(4, launch_radius(a, 0, pf));
+    STEP(5, launch_scan_counts(a, pf));
+    STEP(6, launch_radius(a, 1, pf));
+  }
   if (pf) {
     // learned prefilter: keep flags on the candidates, then the surviving
     // edges become the graph of the rest of the path
@@ -499,7 +523,7 @@ etx_status etx_create(const etx_config* cfg, const void* weights, size_t nbytes,
   }
   weight_scales(ctx, layers);
   st = ETX_OK;
-  for (int p = 0; p < 3 && st == ETX_OK; ++p) st = build_segments(ctx, layers, p);
+  for (int p = 0; p < 4 && st == ETX_OK; ++p) st = build_segments(ctx, layers, p);
   if (st == ETX_OK && hipMalloc(&ctx->dev_scales, sizeof(float) * N_SCALES) != hipSuccess) st = ETX_ERR_HIP;
   if (st == ETX_OK && hipMemcpy(ctx->dev_scales, ctx->host_scales, sizeof(float) * N_SCALES, hipMemcpyHostToDevice) != hipSuccess)
     st = ETX_ERR_HIP;
@@ -521,7 +545,7 @@ etx_status etx_destroy(etx_ctx* ctx) {
     hipEventDestroy(m.start);
     hipEventDestroy(m.end);
   }
-  for (int p = 0; p < 3; ++p)
+  for (int p = 0; p < 4; ++p)
     if (ctx->seg_base[p]) hipFree(ctx->seg_base[p]);
   if (ctx->dev_scales) hipFree(ctx->dev_scales);
   if (ctx->dev_pf) hipFree(ctx->dev_pf);
@@ -603,6 +627,18 @@ etx_status etx_set_option(etx_ctx* ctx, int32_t key, int64_t value) {
       if (value < -1 || value > ETX_FP8_E4M3) return ETX_ERR_INVALID_ARG;
       ctx->emb_precision = (int)value;
       break;
+    case ETX_OPT_OUTSUM_LDS:
+      if (value != 0 && value != 1) return ETX_ERR_INVALID_ARG;
+      ctx->outsum_lds = (int)value;
+      break;
+    case ETX_OPT_F32_SPLIT:
+      if (value != 0 && value != 1) return ETX_ERR_INVALID_ARG;
+      ctx->f32_split = (int)value;
+      break;
+    case ETX_OPT_RADIUS_SINGLE_PASS:
+      if (value != 0 && value != 1) return ETX_ERR_INVALID_ARG;
+      ctx->radius_single = (int)value;
+      break;
     default: return ETX_ERR_INVALID_ARG;
   }
   if (key != ETX_OPT_USE_GRAPH) clear_graphs(ctx);
@@ -654,6 +690,9 @@ etx_status etx_get_option(const etx_ctx* ctx, int32_t key, int64_t* value) {
     case ETX_OPT_EDGE_WG_SIZE: *value = ctx->edge_threads; break;
     case ETX_OPT_EDGE_WREG: *value = ctx->edge_wreg; break;
     case ETX_OPT_EMBED_PRECISION: *value = ctx->emb_precision; break;
+    case ETX_OPT_OUTSUM_LDS: *value = ctx->outsum_lds; break;
+    case ETX_OPT_F32_SPLIT: *value = ctx->f32_split; break;
+    case ETX_OPT_RADIUS_SINGLE_PASS: *value = ctx->radius_single; break;
     case ETX_OPT_PROFILE: *value = ctx->profile; break;
     default: return ETX_ERR_INVALID_ARG;
   }
@@ -826,9 +865,15 @@ etx_status etx_prefilter_train_step(etx_ctx* ctx, const etx_hits* hits, etx_out*
   STEP(launch_validate(a));
   STEP(launch_bucket(a));
   STEP(launch_embed(a));
-  STEP(launch_radius(a, false, false));
-  STEP(launch_scan_counts(a, false));
-  STEP(launch_radius(a, true, false));
+  if (ctx->radius_single) {
+    STEP(launch_radius(a, 2, false));
+    STEP(launch_scan_counts(a, false));
+    STEP(launch_slots_copy(a, false));
+  } else {
+    STEP(launch_radius(a, 0, false));
+    STEP(launch_scan_counts(a, false));
+    STEP(launch_radius(a, 1, false));
+  }
   STEP(launch_prefilter_train(a, edge_labels, lr, pos_weight, step, loss_dev));
 #undef STEP
   return ETX_OK;

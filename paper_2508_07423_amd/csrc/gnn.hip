@@ -22,6 +22,8 @@
 // FP32.  The edge encodings, the largest tensor, are stored in the operand
 // format (FP8 with the per-step scale of the stored tensor), which is also
 // the operand the next edge-net product reads.
+#include <type_traits>
+
 #include "internal.hpp"
 #include "seg.hpp"
 #include "tile.hpp"
@@ -92,7 +94,7 @@ __device__ inline float wsc(const GnnArgs& A, int s) { return A.sc[s]; }
 // feature order.
 template <int P, int H>
 struct ELayout {
-  static constexpr int ES = PrecBytes<P>::value;
+  static constexpr int ES = PrecBytes<StorePrec<P>::value>::value;
   static constexpr int LB = H / 4 * ES;                 // bytes per lane group
   static constexpr int NQ = LB >= 16 ? LB / 16 : 1;     // 16-byte chunks per lane group
   static constexpr int ROW = H * ES;                    // bytes per row
@@ -132,7 +134,7 @@ template <int P, int H>
 __device__ inline void decode_e(float* ef, const RawE<P, H>& r, float scale) {
 #pragma unroll
   for (int x = 0; x < H / 4; ++x) {
-    if constexpr (P == P_F32) {
+    if constexpr (StorePrec<P>::value == P_F32) {
       ef[x] = __uint_as_float(raw_word<P, H>(r, x));
     } else if constexpr (P == P_BF16) {
       const uint32_t w = raw_word<P, H>(r, x / 2);
@@ -262,7 +264,7 @@ __device__ inline void store_e(void* e, int64_t col, const float* o, bool valid,
   const int g = lane_group();
   char* row = static_cast<char*>(e) + col * L::ROW;
   uint32_t w[L::NQ * 4];
-  if constexpr (P == P_F32) {
+  if constexpr (StorePrec<P>::value == P_F32) {
 #pragma unroll
     for (int x = 0; x < H / 4; ++x) w[x] = __float_as_uint(o[x]);
     if (q) {
@@ -363,6 +365,53 @@ __device__ inline void out_sums(const GnnArgs& A, int64_t tile, const TileIdx& x
   }
 }
 
+// The same out-sums through LDS (H = 64: one lane per feature).  The tile is
+// transposed into the wave's buffer (row f holds feature f of the 16 columns,
+// rows padded to 20 floats so that the writes of a half-wave hit distinct
+// banks); lane f then adds its row along the columns, closing a run wherever
+// the (wave-uniform) source changes, and writes each run's sum as one
+// coalesced 256-byte row.  Both orders are fixed.
+constexpr int kOutRow = 20;                     // floats per transposed feature row
+constexpr int kOutBufFloats = 64 * kOutRow;     // per wave
+
+template <int H>
+__device__ inline void out_sums_lds(const GnnArgs& A, int64_t tile, const TileIdx& x, int key, const float* q,
+                                    float* buf) {
+  static_assert(H == 64, "one lane per feature");
+  const int lane = lane_id(), j = lane & 15, g = lane_group();
+#pragma unroll
+  for (int r = 0; r < H / 4; ++r) buf[phi(r, g) * kOutRow + j] = q[r];
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  float v[16];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const float4 t = *reinterpret_cast<const float4*>(buf + lane * kOutRow + 4 * c);
+    v[4 * c] = t.x; v[4 * c + 1] = t.y; v[4 * c + 2] = t.z; v[4 * c + 3] = t.w;
+  }
+  int k[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) k[c] = __builtin_amdgcn_readlane(key, c);
+  const int before = __builtin_amdgcn_readfirstlane(x.before), after = __builtin_amdgcn_readfirstlane(x.after);
+  float acc = 0.f;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    acc += v[c];
+    if (c == 15 || k[c + 1 < 16 ? c + 1 : 15] != k[c]) {
+      if (k[c] >= 0) {
+        const bool b = k[c] == k[0] && before == k[c], a = c == 15 && after == k[c];
+        float* dst = (!b && !a) ? A.msg + (int64_t)k[c] * 2 * H : A.opart + (tile * 2 + (b ? 0 : 1)) * H;
+        dst[lane] = acc;
+      }
+      acc = 0.f;
+    }
+  }
+  // the next tile's writes must not overtake this tile's reads
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // --------------------------------------------------------------------------
 // node encoder (+ edge-encoder source/target products)
 // --------------------------------------------------------------------------
@@ -426,7 +475,9 @@ __global__ __launch_bounds__(NodeThreads<P>::value) void k_node_encode(GnnArgs A
 // --------------------------------------------------------------------------
 // edge encoder
 // --------------------------------------------------------------------------
-template <int H, int P, int PIPE>
+// OL (H = 64): out-sums through an LDS transpose instead of the DPP scan; the
+// wave buffers follow the weight segment in LDS.
+template <int H, int P, int PIPE, bool OL>
 __global__ __launch_bounds__(512) void k_edge_encode(GnnArgs A) {
   if (A.status[0] != 0) return;
   extern __shared__ float lds[];
@@ -463,14 +514,19 @@ __global__ __launch_bounds__(512) void k_edge_encode(GnnArgs A) {
     ln_relu<H>(o);
     observe<H / 4>(A.calib, SC_GNN + Q_E, o, valid);
     store_e<P, H>(A.e, col, o, valid, inv_e0, s_e0, o);
-    out_sums<H>(A, tile, ti, key, o);
+    if constexpr (OL)
+      out_sums_lds<H>(A, tile, ti, key, o, reinterpret_cast<float*>(w + A.seg_bytes) + wave * kOutBufFloats);
+    else
+      out_sums<H>(A, tile, ti, key, o);
   }
 }
 
 // --------------------------------------------------------------------------
-// messages, one wave per node: the out-sum from the edge kernels' tile
-// partials, the in-sum through the CSC permutation (each lane reads 16 bytes
-// of an edge row, several rows in flight per wave)
+// messages: the out-sum from the edge kernels' tile partials, the in-sum
+// through the CSC permutation.  A node is handled by one lane group as wide
+// as a stored edge row (each lane reads 16 bytes of it), so a wave serves
+// several nodes at once and needs no cross-lane reduction; the additions run
+// in CSC order.
 // --------------------------------------------------------------------------
 template <int P>
 __device__ inline void add_chunk(float* acc, uint4 v) {
@@ -502,48 +558,47 @@ template <int H, int P, int U>
 __global__ __launch_bounds__(256) void k_segsum(GnnArgs A) {
   if (A.status[0] != 0) return;
   constexpr int ES = PrecBytes<P>::value;
-  constexpr int FPL = 16 / ES;         // features per lane
-  constexpr int LPR = H / FPL;         // lanes per row
-  constexpr int NS = 64 / LPR;         // rows in flight per load instruction
-  constexpr int LPO = H / 4;           // lanes per FP32 partial row
-  constexpr int NSO = 64 / LPO;
-  const int lane = lane_id(), fl = lane % LPR, st = lane / LPR, wave = threadIdx.x >> 6;
-  const int flo = lane % LPO, sto = lane / LPO;
+  constexpr int FPL = 16 / ES;         // features per lane of a stored edge row (16-byte chunks)
+  constexpr int LPR = H / FPL;         // lanes per node: one lane group reads a whole row
+  constexpr int NPW = 64 / LPR;        // nodes per wave
+  constexpr int OPL = H / LPR;         // out-sum features per lane
+  const int lane = lane_id(), fl = lane % LPR, sg = lane / LPR, wave = threadIdx.x >> 6;
   const char* eb = static_cast<const char*>(A.e);
   const float scale = P == P_FP8 ? asc(A, Q_E + A.step) : 1.0f;
-  for (int64_t node = (int64_t)blockIdx.x * 4 + wave; node < A.n_hits; node += (int64_t)gridDim.x * 4) {
+  const int64_t stride = (int64_t)gridDim.x * 4 * NPW;
+  for (int64_t node = ((int64_t)blockIdx.x * 4 + wave) * NPW + sg; node - sg < A.n_hits; node += stride) {
+    const bool live = node < A.n_hits;
+    float* out = A.msg + node * 2 * H;
     // out-sum: a source row inside one edge tile was written whole by the edge
     // kernel; a longer row is its tile partials, first tile's slot 1 then
     // slot 0 of each later tile
-    const int64_t rb = A.row_ptr[node], re = A.row_ptr[node + 1];
+    const int64_t rb = live ? A.row_ptr[node] : 0, re = live ? A.row_ptr[node + 1] : 0;
     const int64_t t0 = rb / kCols, t1 = re > rb ? (re - 1) / kCols : t0;
-    if (re == rb || t1 > t0) {
-      float4 mo = make_float4(0.f, 0.f, 0.f, 0.f);
-      for (int64_t i = sto; re > rb && i <= t1 - t0; i += NSO) {
-        const float4 v = *reinterpret_cast<const float4*>(A.opart + ((t0 + i) * 2 + (i == 0 ? 1 : 0)) * H + 4 * flo);
-        mo.x += v.x; mo.y += v.y; mo.z += v.z; mo.w += v.w;
+    if (live && (re == rb || t1 > t0)) {
+      float mo[OPL];
+#pragma unroll
+      for (int x = 0; x < OPL; ++x) mo[x] = 0.f;
+      for (int64_t i = 0; re > rb && i <= t1 - t0; ++i) {
+        const float* prow = A.opart + ((t0 + i) * 2 + (i == 0 ? 1 : 0)) * H + fl * OPL;
+#pragma unroll
+        for (int x = 0; x < OPL; x += 4) {
+          const float4 v = *reinterpret_cast<const float4*>(prow + x);
+          mo[x] += v.x; mo[x + 1] += v.y; mo[x + 2] += v.z; mo[x + 3] += v.w;
+        }
       }
 #pragma unroll
-      for (int m = LPO; m < 64; m <<= 1) {
-        mo.x += __shfl_xor(mo.x, m);
-        mo.y += __shfl_xor(mo.y, m);
-        mo.z += __shfl_xor(mo.z, m);
-        mo.w += __shfl_xor(mo.w, m);
-      }
-      if (sto == 0) *reinterpret_cast<float4*>(A.msg + node * 2 * H + 4 * flo) = mo;
+      for (int x = 0; x < OPL; x += 4)
+        *reinterpret_cast<float4*>(out + fl * OPL + x) = make_float4(mo[x], mo[x + 1], mo[x + 2], mo[x + 3]);
     }
-    // in-sum through the CSC permutation
+    // in-sum through the CSC permutation, U rows in flight per node
     float mi[FPL];
 #pragma unroll
-    for (int i = 0; i < FPL; ++i) mi[i] = 0.f;
-    const int64_t cb = A.col_ptr[node], ce = A.col_ptr[node + 1];
-    for (int64_t t = cb + st; t < ce; t += NS * U) {
+    for (int x = 0; x < FPL; ++x) mi[x] = 0.f;
+    const int64_t cb = live ? A.col_ptr[node] : 0, ce = live ? A.col_ptr[node + 1] : 0;
+    for (int64_t t = cb; t < ce; t += U) {
       int id[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int64_t q = t + (int64_t)u * NS;
-        id[u] = q < ce ? A.csc[q] : -1;
-      }
+      for (int u = 0; u < U; ++u) id[u] = t + u < ce ? A.csc[t + u] : -1;
       uint4 v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u)
@@ -552,19 +607,13 @@ __global__ __launch_bounds__(256) void k_segsum(GnnArgs A) {
 #pragma unroll
       for (int u = 0; u < U; ++u) add_chunk<P>(mi, v[u]);
     }
-    // combine the row streams of the wave in a fixed order
-#pragma unroll
-    for (int m = LPR; m < 64; m <<= 1)
-#pragma unroll
-      for (int i = 0; i < FPL; ++i) mi[i] += __shfl_xor(mi[i], m);
-    if (st == 0) {
-      // value i of chunk fl is the feature stored at byte 16 fl + i ES; runs of
+    if (live) {
+      // value x of chunk fl is the feature stored at byte 16 fl + x ES; runs of
       // four values are four consecutive features
-      float* out = A.msg + node * 2 * H + H;
 #pragma unroll
-      for (int i = 0; i < FPL; i += 4)
-        *reinterpret_cast<float4*>(out + ELayout<P, H>::feature(16 * fl + i * ES)) =
-            make_float4(mi[i] * scale, mi[i + 1] * scale, mi[i + 2] * scale, mi[i + 3] * scale);
+      for (int x = 0; x < FPL; x += 4)
+        *reinterpret_cast<float4*>(out + H + ELayout<P, H>::feature(16 * fl + x * ES)) =
+            make_float4(mi[x] * scale, mi[x + 1] * scale, mi[x + 2] * scale, mi[x + 3] * scale);
     }
   }
 }
@@ -632,8 +681,9 @@ __global__ __launch_bounds__(NodeThreads<P>::value) void k_node_step(GnnArgs A) 
 // edge update k; the last step also runs the classifier and writes scores
 // --------------------------------------------------------------------------
 // WR (FP32 only): both H x H weight matrices stay in registers for the whole
-// persistent loop instead of being read from LDS by every MFMA.
-template <int H, bool FINAL, int P, int PIPE, bool WR>
+// persistent loop instead of being read from LDS by every MFMA.  OL as in the
+// edge encoder (steps before the last).
+template <int H, bool FINAL, int P, int PIPE, bool WR, bool OL>
 __global__ __launch_bounds__(512) void k_edge_step(GnnArgs A) {
   if (A.status[0] != 0) return;
   extern __shared__ float lds[];
@@ -706,7 +756,10 @@ __global__ __launch_bounds__(512) void k_edge_step(GnnArgs A) {
     observe<H / 4>(A.calib, SC_GNN + Q_E + k + 1, o, valid);
     if (!FINAL) {
       store_e<P, H>(A.e, col, o, valid, 1.0f / s_next, s_next, o);
-      out_sums<H>(A, tile, ti, key, o);
+      if constexpr (OL)
+        out_sums_lds<H>(A, tile, ti, key, o, reinterpret_cast<float*>(w + A.seg_bytes) + wave * kOutBufFloats);
+      else
+        out_sums<H>(A, tile, ti, key, o);
     } else {
       // classifier on the final edge encodings (quantised like a stored e_S)
       float c[H / 4];
@@ -794,20 +847,87 @@ hipError_t launch_node_encode(const RunArgs& a) {
   return hipGetLastError();
 }
 
+// The edge-kernel instantiation for a run-time launch schedule (also used to
+// set the LDS attribute of every instantiation once).
+template <int H, int P>
+static const void* edge_encode_kernel(int pipe, bool ol) {
+  auto pick = [&](auto PI) -> const void* {
+    constexpr int pi = decltype(PI)::value;
+    if constexpr (H == 64) {
+      if (ol) return reinterpret_cast<const void*>(k_edge_encode<H, P, pi, true>);
+    }
+    return reinterpret_cast<const void*>(k_edge_encode<H, P, pi, false>);
+  };
+  switch (pipe) {
+    case 0: return pick(std::integral_constant<int, 0>{});
+    case 2: return pick(std::integral_constant<int, 2>{});
+    default: return pick(std::integral_constant<int, 1>{});
+  }
+}
+
+template <int H, int P>
+static const void* edge_step_kernel(bool fin, int pipe, bool wr, bool ol) {
+  auto pick_o = [&](auto F, auto PI, auto WRC) -> const void* {
+    constexpr bool f = decltype(F)::value, wv = decltype(WRC)::value;
+    constexpr int pi = decltype(PI)::value;
+    if constexpr (H == 64 && !f) {
+      if (ol) return reinterpret_cast<const void*>(k_edge_step<H, f, P, pi, wv, true>);
+    }
+    return reinterpret_cast<const void*>(k_edge_step<H, f, P, pi, wv, false>);
+  };
+  auto pick_w = [&](auto F, auto PI) -> const void* {
+    if constexpr (P == P_F32) {
+      if (wr) return pick_o(F, PI, std::true_type{});
+    }
+    return pick_o(F, PI, std::false_type{});
+  };
+  auto pick_p = [&](auto F) -> const void* {
+    switch (pipe) {
+      case 0: return pick_w(F, std::integral_constant<int, 0>{});
+      case 2: return pick_w(F, std::integral_constant<int, 2>{});
+      default: return pick_w(F, std::integral_constant<int, 1>{});
+    }
+  };
+  return fin ? pick_p(std::true_type{}) : pick_p(std::false_type{});
+}
+
+static bool outsum_lds(const RunArgs& a) { return a.ctx->outsum_lds && a.ctx->cfg.gnn_hidden == 64; }
+
+static size_t outsum_lds_bytes(const RunArgs& a) {
+  return outsum_lds(a) ? (size_t)(a.ctx->edge_threads / 64) * kOutBufFloats * sizeof(float) : 0;
+}
+
+// precision of the edge kernels' GEMMs (FP32 runs may use the split form)
+static int edge_prec(const RunArgs& a) { return (a.prec == P_F32 && a.ctx->f32_split) ? kF32Split : a.prec; }
+
 hipError_t launch_edge_encode(const RunArgs& a) {
   if (a.hits.n_hits == 0) return hipSuccess;
   GnnArgs A = gnn_args(a);
   const int Hh = a.ctx->cfg.gnn_hidden;
-  const WeightMap& m = a.ctx->wmap[a.prec];
-  A.seg = seg_ptr(a, m.edge_enc);
-  A.seg_bytes = SegEdgeEnc{Hh, kPrecBytes[a.prec]}.size();
-  unsigned grid = (unsigned)(a.ctx->n_cu * a.ctx->edge_wg_per_cu);
-  switch (a.ctx->edge_pipeline) {
-    case 0: DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_edge_encode<H, P, 0>), dim3(grid), dim3(a.ctx->edge_threads), A.seg_bytes, a.stream, A)); break;
-    case 2: DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_edge_encode<H, P, 2>), dim3(grid), dim3(a.ctx->edge_threads), A.seg_bytes, a.stream, A)); break;
-    default: DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_edge_encode<H, P, 1>), dim3(grid), dim3(a.ctx->edge_threads), A.seg_bytes, a.stream, A)); break;
+  const int kp = edge_prec(a);
+  const WeightMap& m = a.ctx->wmap[kp];
+  A.seg = static_cast<const char*>(a.ctx->seg_base[kp]) + m.edge_enc;
+  A.seg_bytes = SegEdgeEnc{Hh, kPrecBytes[kp]}.size();
+  const unsigned grid = (unsigned)(a.ctx->n_cu * a.ctx->edge_wg_per_cu);
+  const size_t lds = A.seg_bytes + outsum_lds_bytes(a);
+  const int pipe = a.ctx->edge_pipeline;
+  const bool ol = outsum_lds(a);
+  const void* fn = nullptr;
+#define ENC_K(H_, P_) edge_encode_kernel<H_, P_>(pipe, ol)
+  switch (Hh * 4 + kp) {
+    case 32 * 4 + 0: fn = ENC_K(32, 0); break;
+    case 32 * 4 + 1: fn = ENC_K(32, 1); break;
+    case 32 * 4 + 2: fn = ENC_K(32, 2); break;
+    case 32 * 4 + 3: fn = ENC_K(32, 3); break;
+    case 64 * 4 + 0: fn = ENC_K(64, 0); break;
+    case 64 * 4 + 1: fn = ENC_K(64, 1); break;
+    case 64 * 4 + 2: fn = ENC_K(64, 2); break;
+    case 64 * 4 + 3: fn = ENC_K(64, 3); break;
+    default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
+#undef ENC_K
+  void* args[] = {&A};
+  return hipLaunchKernel(fn, dim3(grid), dim3(a.ctx->edge_threads), args, lds, a.stream);
 }
 
 hipError_t launch_segsum(const RunArgs& a, int k) {
@@ -845,35 +965,35 @@ hipError_t launch_edge_step(const RunArgs& a, int k, bool final_step) {
   if (a.hits.n_hits == 0) return hipSuccess;
   GnnArgs A = gnn_args(a);
   const int Hh = a.ctx->cfg.gnn_hidden;
-  const WeightMap& m = a.ctx->wmap[a.prec];
-  A.seg = seg_ptr(a, m.edge[k]);
-  A.seg_bytes = SegEdge{Hh, kPrecBytes[a.prec]}.size();
-  A.seg2 = seg_ptr(a, m.cls);
-  A.seg2_bytes = SegCls{Hh, kPrecBytes[a.prec]}.size();
+  const int kp = edge_prec(a);
+  const WeightMap& m = a.ctx->wmap[kp];
+  const char* base = static_cast<const char*>(a.ctx->seg_base[kp]);
+  A.seg = base + m.edge[k];
+  A.seg_bytes = SegEdge{Hh, kPrecBytes[kp]}.size();
+  A.seg2 = base + m.cls;
+  A.seg2_bytes = SegCls{Hh, kPrecBytes[kp]}.size();
   A.step = k;
-  size_t lds = A.seg_bytes + (final_step ? A.seg2_bytes : 0);
-  unsigned grid = (unsigned)(a.ctx->n_cu * a.ctx->edge_wg_per_cu);
-#define EDGE_STEP(F_, PIPE_)                                                                           \
-  if (a.prec == P_F32 && a.ctx->edge_wreg) {                                                          \
-    if (Hh == 64)                                                                                     \
-      hipLaunchKernelGGL((k_edge_step<64, F_, P_F32, PIPE_, true>), dim3(grid), dim3(a.ctx->edge_threads), lds, a.stream, A); \
-    else if (Hh == 32)                                                                                \
-      hipLaunchKernelGGL((k_edge_step<32, F_, P_F32, PIPE_, true>), dim3(grid), dim3(a.ctx->edge_threads), lds, a.stream, A); \
-    else                                                                                              \
-      return hipErrorInvalidValue;                                                                    \
-  } else {                                                                                            \
-    DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_edge_step<H, F_, P, PIPE_, false>), dim3(grid), dim3(a.ctx->edge_threads), lds, a.stream, A)); \
+  const bool ol = !final_step && outsum_lds(a);
+  const size_t lds = A.seg_bytes + (final_step ? A.seg2_bytes : 0) + (ol ? outsum_lds_bytes(a) : 0);
+  const unsigned grid = (unsigned)(a.ctx->n_cu * a.ctx->edge_wg_per_cu);
+  const int pipe = a.ctx->edge_pipeline;
+  const bool wr = a.ctx->edge_wreg != 0;
+  const void* fn = nullptr;
+#define STEP_K(H_, P_) edge_step_kernel<H_, P_>(final_step, pipe, wr, ol)
+  switch (Hh * 4 + kp) {
+    case 32 * 4 + 0: fn = STEP_K(32, 0); break;
+    case 32 * 4 + 1: fn = STEP_K(32, 1); break;
+    case 32 * 4 + 2: fn = STEP_K(32, 2); break;
+    case 32 * 4 + 3: fn = STEP_K(32, 3); break;
+    case 64 * 4 + 0: fn = STEP_K(64, 0); break;
+    case 64 * 4 + 1: fn = STEP_K(64, 1); break;
+    case 64 * 4 + 2: fn = STEP_K(64, 2); break;
+    case 64 * 4 + 3: fn = STEP_K(64, 3); break;
+    default: return hipErrorInvalidValue;
   }
-  switch (a.ctx->edge_pipeline * 2 + (final_step ? 1 : 0)) {
-    case 0: EDGE_STEP(false, 0); break;
-    case 1: EDGE_STEP(true, 0); break;
-    case 4: EDGE_STEP(false, 2); break;
-    case 5: EDGE_STEP(true, 2); break;
-    case 3: EDGE_STEP(true, 1); break;
-    default: EDGE_STEP(false, 1); break;
-  }
-#undef EDGE_STEP
-  return hipGetLastError();
+#undef STEP_K
+  void* args[] = {&A};
+  return hipLaunchKernel(fn, dim3(grid), dim3(a.ctx->edge_threads), args, lds, a.stream);
 }
 
 __global__ void k_quantize(int prec, const float* __restrict__ in, float* __restrict__ out, int64_t n, float scale) {
@@ -897,27 +1017,30 @@ static void set_gnn_attr(int& bad, size_t max_lds) {
   };
   set(reinterpret_cast<const void*>(k_node_encode<H, P>));
   set(reinterpret_cast<const void*>(k_node_step<H, P>));
-  set(reinterpret_cast<const void*>(k_edge_step<H, true, P, 0, false>));
-  set(reinterpret_cast<const void*>(k_edge_step<H, false, P, 0, false>));
-  set(reinterpret_cast<const void*>(k_edge_step<H, true, P, 1, false>));
-  set(reinterpret_cast<const void*>(k_edge_step<H, false, P, 1, false>));
-  set(reinterpret_cast<const void*>(k_edge_step<H, true, P, 2, false>));
-  set(reinterpret_cast<const void*>(k_edge_step<H, false, P, 2, false>));
-  if constexpr (P == P_F32) {
-    set(reinterpret_cast<const void*>(k_edge_step<H, true, P, 0, true>));
-    set(reinterpret_cast<const void*>(k_edge_step<H, false, P, 0, true>));
-    set(reinterpret_cast<const void*>(k_edge_step<H, true, P, 1, true>));
-    set(reinterpret_cast<const void*>(k_edge_step<H, false, P, 1, true>));
-    set(reinterpret_cast<const void*>(k_edge_step<H, true, P, 2, true>));
-    set(reinterpret_cast<const void*>(k_edge_step<H, false, P, 2, true>));
-  }
-  set(reinterpret_cast<const void*>(k_edge_encode<H, P, 0>));
-  set(reinterpret_cast<const void*>(k_edge_encode<H, P, 1>));
-  set(reinterpret_cast<const void*>(k_edge_encode<H, P, 2>));
+  for (int fin = 0; fin < 2; ++fin)
+    for (int pipe = 0; pipe < 3; ++pipe)
+      for (int wr = 0; wr < 2; ++wr)
+        for (int ol = 0; ol < 2; ++ol) set(edge_step_kernel<H, P>(fin, pipe, wr, ol));
+  for (int pipe = 0; pipe < 3; ++pipe)
+    for (int ol = 0; ol < 2; ++ol) set(edge_encode_kernel<H, P>(pipe, ol));
+}
+
+template <int H>
+static void set_split_attr(int& bad, size_t max_lds) {
+  auto set = [&](const void* f) {
+    bad |= hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) != hipSuccess;
+  };
+  for (int fin = 0; fin < 2; ++fin)
+    for (int pipe = 0; pipe < 3; ++pipe)
+      for (int ol = 0; ol < 2; ++ol) set(edge_step_kernel<H, P_F32X>(fin, pipe, false, ol));
+  for (int pipe = 0; pipe < 3; ++pipe)
+    for (int ol = 0; ol < 2; ++ol) set(edge_encode_kernel<H, P_F32X>(pipe, ol));
 }
 
 int gnn_attributes(size_t max_lds) {
   int bad = 0;
+  set_split_attr<32>(bad, max_lds);
+  set_split_attr<64>(bad, max_lds);
   set_gnn_attr<32, 0>(bad, max_lds);
   set_gnn_attr<32, 1>(bad, max_lds);
   set_gnn_attr<32, 2>(bad, max_lds);

@@ -16,7 +16,8 @@ constexpr int kEdgeTile = 16;      // edges per wave tile of the MLP kernels (th
 constexpr int kDpad = 16;          // padded embedding width in HBM
 constexpr int kScanBlock = 1024;   // elements per block of the device-wide scan
 
-constexpr int kPrecBytes[3] = {4, 2, 1};   // GEMM operand bytes: FP32, BF16, FP8
+constexpr int kPrecBytes[4] = {4, 2, 1, 6};   // weight bytes: FP32, BF16, FP8, FP32 as three BF16 parts
+constexpr int kF32Split = 3;                  // segment set of the split-FP32 edge kernels
 
 // Offsets (in bytes) of the per-kernel weight segments in a precision's device buffer.
 struct WeightMap {
@@ -31,7 +32,7 @@ struct WeightMap {
 
 // Byte offsets of the workspace buffers.
 struct WsLayout {
-  size_t bucket, plane_off, emb, cnt, row_ptr, scan_tmp, col_ptr, csc, h, ps, pd, msg, e, opart, kept, kept_cnt,
+  size_t bucket, plane_off, emb, cnt, slots, row_ptr, scan_tmp, col_ptr, csc, h, ps, pd, msg, e, opart, kept, kept_cnt,
       calib, pf_keep, pf_tmp, cand_src, cand_dst, pf_prob, pf_part, pf_grad, total;
   int64_t n_scan_blocks;
 };
@@ -48,8 +49,8 @@ struct etx_ctx {
   etx_config cfg;
   int device = 0;
   int n_cu = 256;
-  void* seg_base[3] = {};          // weight segments per operand precision (FP32, BF16, FP8)
-  etx::WeightMap wmap[3];
+  void* seg_base[4] = {};          // weight segments per operand precision (FP32, BF16, FP8, split FP32)
+  etx::WeightMap wmap[4];
   float* dev_scales = nullptr;     // [256] per-tensor scales: activations 0..63, weights 64..255
   float host_scales[256] = {};
   bool calibrated = false;
@@ -57,14 +58,17 @@ struct etx_ctx {
   float* dev_pf = nullptr;
   bool pf_set = false;
   // tuning
-  int edge_wg_per_cu = 3;
+  int edge_wg_per_cu = 8;
   int node_wg_per_cu = 1;
   int radius_lds = 1;
   int segsum_unroll = 4;
   int edge_pipeline = 1;
-  int edge_threads = 512;
+  int edge_threads = 256;
   int edge_wreg = 0;
   int emb_precision = -1;          // -1: cfg.precision
+  int outsum_lds = 1;
+  int f32_split = 0;               // FP32 runs: edge-kernel GEMMs as split BF16 products
+  int radius_single = 1;           // radius graph: one selection pass + slot copy (0: count and emit passes)
   int use_graph = 0;
   std::map<etx::GraphKey, hipGraphExec_t> graphs;
   // stage timing with HIP events (ETX_OPT_PROFILE)
@@ -95,7 +99,9 @@ struct RunArgs {
 hipError_t launch_init_status(const RunArgs& a);
 hipError_t launch_validate(const RunArgs& a);
 hipError_t launch_bucket(const RunArgs& a);
-hipError_t launch_radius(const RunArgs& a, bool emit, bool candidates);
+// radius graph passes (mode: 0 count, 1 emit CSR rows, 2 select into slots)
+hipError_t launch_radius(const RunArgs& a, int mode, bool candidates);
+hipError_t launch_slots_copy(const RunArgs& a, bool candidates);
 hipError_t launch_scan_counts(const RunArgs& a, bool candidates);
 hipError_t launch_csc(const RunArgs& a);
 hipError_t launch_compact(const RunArgs& a);

@@ -37,8 +37,9 @@ struct RadiusArgs {
   int n_planes, window, k_max, dim;
   int stage_window;        // 0: always read the window from HBM
   float r2, r;
-  int32_t* cnt;            // count pass output
+  int32_t* cnt;            // count pass output (and the select pass's)
   const int64_t* row_ptr;  // emit pass input
+  int32_t* slots;          // select pass output: [n_hits][k_max] kept targets, ascending
   int32_t* src;
   int32_t* dst;
   const int64_t* status;
@@ -66,8 +67,15 @@ struct RadiusLds {
   static constexpr size_t bytes = (size_t)cap * (DP * 4 + 12) + kRadiusWaves * (kList * 8 + 64 * 4 + 256 * 4) + 64;
 };
 
-template <bool EMIT, int DP>
+// MODE: 0 counts the kept neighbours of every source; 1 writes them as CSR rows
+// at the offsets the count pass produced; 2 does the whole selection once,
+// writing each source's kept targets (ascending) to its k_max slots and its
+// count, so that the CSR rows are a copy after the scan.
+enum RadiusMode { R_COUNT = 0, R_EMIT = 1, R_SELECT = 2 };
+
+template <int MODE, int DP>
 __global__ __launch_bounds__(kRadiusThreads) void k_radius(RadiusArgs A) {
+  constexpr bool EMIT = MODE != R_COUNT;
   if (A.status[0] != 0) return;
   constexpr int CAP = RadiusLds<DP>::cap;
   extern __shared__ float lds[];
@@ -249,7 +257,10 @@ __global__ __launch_bounds__(kRadiusThreads) void k_radius(RadiusArgs A) {
       if (lane == 0) A.cnt[i] = min(n, A.k_max);
       continue;
     }
-    if (n == 0) continue;
+    if (n == 0) {
+      if (MODE == R_SELECT && lane == 0) A.cnt[i] = 0;
+      continue;
+    }
     wave_sync();
     const bool listed = n <= kList;
     // wave-uniform count of in-radius candidates satisfying pred(d2, j)
@@ -390,24 +401,64 @@ __global__ __launch_bounds__(kRadiusThreads) void k_radius(RadiusArgs A) {
         ns += __popcll(m);
       }
     }
-    // never write past the row the count pass reserved
-    ns = min(ns, (int)(A.row_ptr[i + 1] - A.row_ptr[i]));
+    if (MODE == R_SELECT) {
+      ns = min(ns, A.k_max);
+      if (lane == 0) A.cnt[i] = ns;
+    } else {
+      // never write past the row the count pass reserved
+      ns = min(ns, (int)(A.row_ptr[i + 1] - A.row_ptr[i]));
+    }
     wave_sync();
     if (lane < ns) {
       const int my = sl[lane];
       int rank = 0;
       for (int q = 0; q < ns; ++q) rank += sl[q] < my;
-      const int64_t pos = A.row_ptr[i] + rank;
-      A.src[pos] = i;
-      A.dst[pos] = my;
+      if (MODE == R_SELECT) {
+        A.slots[(int64_t)i * A.k_max + rank] = my;
+      } else {
+        const int64_t pos = A.row_ptr[i] + rank;
+        A.src[pos] = i;
+        A.dst[pos] = my;
+      }
     }
     wave_sync();
   }
 }
 
+// CSR rows from the select pass's slots: thread (source i, rank r) copies
+// slot r of source i when r is below its count.
+__global__ void k_slots_to_csr(const int32_t* __restrict__ slots, const int64_t* __restrict__ row_ptr, int64_t n_hits,
+                               int k_max, int32_t* __restrict__ src, int32_t* __restrict__ dst, const int64_t* status) {
+  if (status[0] != 0) return;
+  const int64_t total = n_hits * k_max;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = t / k_max;
+    const int r = (int)(t - i * k_max);
+    const int64_t b = row_ptr[i];
+    if (r < row_ptr[i + 1] - b) {
+      src[b + r] = (int32_t)i;
+      dst[b + r] = slots[t];
+    }
+  }
+}
+
 }  // namespace
 
-hipError_t launch_radius(const RunArgs& a, bool emit, bool candidates) {
+hipError_t launch_slots_copy(const RunArgs& a, bool candidates) {
+  const int64_t n = a.hits.n_hits;
+  if (n == 0) return hipSuccess;
+  const int k = a.ctx->cfg.k_max;
+  const int64_t total = n * k;
+  const unsigned grid = (unsigned)std::min<int64_t>((total + 255) / 256, (int64_t)a.ctx->n_cu * 32);
+  hipLaunchKernelGGL(k_slots_to_csr, dim3(grid), dim3(256), 0, a.stream,
+                     reinterpret_cast<const int32_t*>(a.ws + a.L.slots),
+                     reinterpret_cast<const int64_t*>(a.ws + (candidates ? a.L.pf_tmp : a.L.row_ptr)), n, k,
+                     candidates ? reinterpret_cast<int32_t*>(a.ws + a.L.cand_src) : a.out.src,
+                     candidates ? reinterpret_cast<int32_t*>(a.ws + a.L.cand_dst) : a.out.dst, a.out.status);
+  return hipGetLastError();
+}
+
+hipError_t launch_radius(const RunArgs& a, int mode, bool candidates) {
   if (a.hits.n_events == 0) return hipSuccess;
   const etx_config& c = a.ctx->cfg;
   RadiusArgs A;
@@ -426,17 +477,25 @@ hipError_t launch_radius(const RunArgs& a, bool emit, bool candidates) {
   A.row_ptr = reinterpret_cast<const int64_t*>(a.ws + (candidates ? a.L.pf_tmp : a.L.row_ptr));
   A.src = candidates ? reinterpret_cast<int32_t*>(a.ws + a.L.cand_src) : a.out.src;
   A.dst = candidates ? reinterpret_cast<int32_t*>(a.ws + a.L.cand_dst) : a.out.dst;
+  A.slots = reinterpret_cast<int32_t*>(a.ws + a.L.slots);
   A.status = a.out.status;
   dim3 grid((unsigned)(a.hits.n_events * c.n_planes));
   const bool small = c.emb_dim <= 8;
   A.stage_window = a.ctx->radius_lds;
-#define LAUNCH_R(E_, D_) \
-  hipLaunchKernelGGL((k_radius<E_, D_>), grid, dim3(kRadiusThreads), RadiusLds<D_>::bytes, a.stream, A)
-  if (small) {
-    if (emit) LAUNCH_R(true, 8); else LAUNCH_R(false, 8);
-  } else {
-    if (emit) LAUNCH_R(true, 16); else LAUNCH_R(false, 16);
+#define LAUNCH_R(M_, D_) \
+  hipLaunchKernelGGL((k_radius<M_, D_>), grid, dim3(kRadiusThreads), RadiusLds<D_>::bytes, a.stream, A)
+#define BY_MODE(D_)                                  \
+  switch (mode) {                                    \
+    case R_COUNT: LAUNCH_R(R_COUNT, D_); break;      \
+    case R_EMIT: LAUNCH_R(R_EMIT, D_); break;        \
+    default: LAUNCH_R(R_SELECT, D_); break;          \
   }
+  if (small) {
+    BY_MODE(8);
+  } else {
+    BY_MODE(16);
+  }
+#undef BY_MODE
 #undef LAUNCH_R
   return hipGetLastError();
 }
@@ -446,10 +505,12 @@ int radius_attributes(size_t max_lds) {
   auto set = [&](const void* f) {
     bad |= hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) != hipSuccess;
   };
-  set(reinterpret_cast<const void*>(k_radius<true, 8>));
-  set(reinterpret_cast<const void*>(k_radius<false, 8>));
-  set(reinterpret_cast<const void*>(k_radius<true, 16>));
-  set(reinterpret_cast<const void*>(k_radius<false, 16>));
+  set(reinterpret_cast<const void*>(k_radius<R_COUNT, 8>));
+  set(reinterpret_cast<const void*>(k_radius<R_EMIT, 8>));
+  set(reinterpret_cast<const void*>(k_radius<R_SELECT, 8>));
+  set(reinterpret_cast<const void*>(k_radius<R_COUNT, 16>));
+  set(reinterpret_cast<const void*>(k_radius<R_EMIT, 16>));
+  set(reinterpret_cast<const void*>(k_radius<R_SELECT, 16>));
   return bad;
 }
 

@@ -189,9 +189,15 @@ __device__ inline void mfma_bf16_chunks(float* acc, const uint4* xr, const bf16x
 // low-precision formats
 // ---------------------------------------------------------------------------
 
-enum Prec { P_F32 = 0, P_BF16 = 1, P_FP8 = 2 };
+// P_F32X: FP32 operands on the BF16 matrix cores, each operand split into
+// three BF16 parts (below); FP32 everywhere else.
+enum Prec { P_F32 = 0, P_BF16 = 1, P_FP8 = 2, P_F32X = 3 };
+// bytes per weight element of a GEMM in precision P (P_F32X: three BF16 planes)
 template <int P>
-struct PrecBytes { static constexpr int value = P == P_F32 ? 4 : (P == P_BF16 ? 2 : 1); };
+struct PrecBytes { static constexpr int value = P == P_F32 ? 4 : P == P_BF16 ? 2 : P == P_FP8 ? 1 : 6; };
+// storage format of activations in precision P
+template <int P>
+struct StorePrec { static constexpr int value = P == P_F32X ? P_F32 : P; };
 
 // OCP FP8 E4M3 (bias 7, 3 mantissa bits, subnormals, max 448, no infinity),
 // converted by the gfx950 instructions v_cvt_pk_fp8_f32 (round to nearest
@@ -265,6 +271,59 @@ __device__ inline void mfma_fp8_codes(float* acc, const uint32_t* xw, const uint
     for (int v = 0; v < 4; ++v) acc[4 * mb + v] = fmaf(out_scale, c[mb][v], acc[4 * mb + v]);
 }
 
+// FP32 product on the BF16 matrix cores.  Each FP32 value is split exactly
+// into three BF16 parts, x = hi + mid + lo (hi = bf16(x), mid = bf16(x - hi),
+// lo = bf16(x - hi - mid); both differences are exact in FP32, and lo is
+// within 2^-25 |x| of the remainder); w holds the same parts of W as three
+// consecutive BF16 planes in the BF16 layout.  The six products down to
+// 2^-16 relative (lo*hi, hi*lo, mid*mid, mid*hi, hi*mid, hi*hi: BF16 x BF16
+// products are exact in FP32) accumulate in FP32; the terms left out
+// (mid*lo, lo*mid, lo*lo) are below 2^-23 relative together, the size of
+// FP32 rounding.
+__device__ inline void split3(const float* x, bf16x8& h, bf16x8& m, bf16x8& l) {
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const __bf16 bh = (__bf16)x[q];
+    const float r = x[q] - (float)bh;
+    const __bf16 bm = (__bf16)r;
+    h[q] = bh;
+    m[q] = bm;
+    l[q] = (__bf16)(r - (float)bm);
+  }
+}
+
+template <int K, int MB>
+__device__ inline void mfma_split(float* acc, const float* x, const bf16x8* __restrict__ w) {
+  constexpr int PLANE = MB * (K / 32) * 64;
+  const int lane = lane_id();
+  floatx4 c[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) c[mb][v] = acc[4 * mb + v];
+#pragma unroll
+  for (int t = 0; t < K / 32; ++t) {
+    bf16x8 xh, xm, xl;
+    split3(x + 8 * t, xh, xm, xl);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const int i = (mb * (K / 32) + t) * 64 + lane;
+      const bf16x8 wh = w[i], wm = w[PLANE + i], wl = w[2 * PLANE + i];
+      c[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl, xh, c[mb], 0, 0, 0);
+      c[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, xl, c[mb], 0, 0, 0);
+      c[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wm, xm, c[mb], 0, 0, 0);
+      c[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wm, xh, c[mb], 0, 0, 0);
+      c[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, xm, c[mb], 0, 0, 0);
+      c[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, xh, c[mb], 0, 0, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[4 * mb + v] = c[mb][v];
+}
+
 // One Linear layer in precision P: acc += W^T x with weights w (permuted for
 // P); FP8 quantises x with inv_s and rescales the product by out_scale.
 template <int P, int K, int MB>
@@ -273,6 +332,8 @@ __device__ inline void gemm(float* acc, const float* x, const void* w, float inv
     mfma_f32<K, MB>(acc, x, static_cast<const float*>(w));
   } else if constexpr (P == P_BF16) {
     mfma_bf16<K, MB>(acc, x, static_cast<const bf16x8*>(w));
+  } else if constexpr (P == P_F32X) {
+    mfma_split<K, MB>(acc, x, static_cast<const bf16x8*>(w));
   } else {
     mfma_fp8<K, MB>(acc, x, static_cast<const uint64_t*>(w), inv_s, out_scale);
   }

@@ -30,12 +30,14 @@ def labels_from_full_pipeline(pipe: "etx.Pipeline", b: "etx.Batch", threshold: f
     return (pipe.score[:max(E, 1)] >= threshold).to(torch.uint8), E
 
 
-def train_prefilter(w, weights: Dict, n_events: int, batch_events: int, epochs: int = 1, lr: float = 3e-3,
+def train_prefilter(w, weights: Dict, n_events: int, batch_events: int = 20, epochs: int = 1, lr: float = 1e-2,
                     pos_weight: float = 4.0, seed_space: Optional[int] = None, init_seed: int = 7,
                     log: Callable[[str], None] = print, device: int = 0) -> Dict:
     """Train on ``n_events`` generated events (disjoint seed space) in
     minibatches of ``batch_events``; returns params, optimiser state and the
-    loss history."""
+    loss history.  Every step averages over all candidate edges of its events
+    (tens of thousands per event), so small event batches (many Adam steps)
+    train far better than large ones."""
     import torch
     ss = 5000 + w.cid if seed_space is None else seed_space
     pipe = etx.Pipeline(w, weights, device=device)

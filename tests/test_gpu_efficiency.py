@@ -128,9 +128,9 @@ def test_learned_prefilter_gain():
     w = synth.C5
     W = synth.trained_weights(w)
     t0 = time.time()
-    tr = PT.train_prefilter(w, W, n_events=1500, batch_events=150, epochs=2, lr=3e-3, pos_weight=4.0)
+    tr = PT.train_prefilter(w, W, n_events=4000, batch_events=20, epochs=1, lr=1e-2, pos_weight=4.0)
     print(f"prefilter trained in {time.time() - t0:.1f} s, loss {tr['history'][0]:.4f} -> {tr['history'][-1]:.4f}")
-    assert tr["history"][-1] < tr["history"][0]
+    assert np.mean(tr["history"][-10:]) < 0.5 * tr["history"][0]
     val = synth.generate_batch(w, 100, seed_space=6000 + w.cid)
     sel = PT.choose_tau(w, W, tr["params"], val, recall=0.995)
     print("tau", sel)
@@ -140,5 +140,5 @@ def test_learned_prefilter_gain():
     m0, m1 = evaluate.batch_metrics(r0["labels"], batch), evaluate.batch_metrics(r1["labels"], batch)
     e0, e1 = len(r0["src"]), len(r1["src"])
     print("unpruned", m0, e0, "pruned", m1, e1)
-    assert e1 < 0.9 * e0
+    assert e1 < 0.85 * e0
     assert m1["efficiency"] >= m0["efficiency"] - 0.005

@@ -158,7 +158,7 @@ def test_radius_global_fallback_and_unroll_identical(c1_run):
     finally:
         etx.etx_set_option(p.ctx, etx.ETX_OPT_RADIUS_LDS, 1)
         etx.etx_set_option(p.ctx, etx.ETX_OPT_SEGSUM_UNROLL, 4)
-        etx.etx_set_option(p.ctx, etx.ETX_OPT_EDGE_WG_PER_CU, 3)
+        etx.etx_set_option(p.ctx, etx.ETX_OPT_EDGE_WG_PER_CU, 8)
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2])
@@ -174,6 +174,7 @@ def test_edge_schedules_bit_identical(prec):
         p.calibrate(etx.to_device(synth.generate_batch(w, 4, seed_space=1000 + w.cid)))
     b = etx.to_device(batch)
     ref = None
+    etx.etx_set_option(p.ctx, etx.ETX_OPT_OUTSUM_LDS, 1)      # no effect at hidden size 32
     for wreg in ((0, 1) if prec == etx.ETX_FP32 else (0,)):
         for threads, per_cu in ((512, 2), (256, 1), (256, 5)):
             for pipe in (0, 1, 2):
@@ -215,14 +216,23 @@ def test_permutation_equivariance_gpu():
     assert len(pairs) == len(np.unique(c0)) == len(np.unique(c1))
 
 
-@pytest.mark.parametrize("n_events", [2])
-def test_full_geometry_batch_parity(n_events):
+@pytest.mark.parametrize("outsum_lds,f32_split", [(0, 0), (1, 0), (1, 1)])
+def test_full_geometry_batch_parity(outsum_lds, f32_split, n_events=2):
     """Full-size geometry and network (26 planes, emb 3-128-128-12, radius 0.12,
-    k 64, hidden 64, 8 steps) on a few events; oracle event by event."""
+    k 64, hidden 64, 8 steps) on a few events; oracle event by event.  Both
+    out-sum reductions of hidden size 64 (DPP scan, LDS transpose) and the
+    FP32 GEMMs on FP32 matrix cores or as split BF16 products, all to the
+    FP32 tolerance."""
+    etx = _etx()
     w = synth.C2
     W = centred_weights(w, shift=None)
     batch = synth.generate_batch(w, n_events)
-    p, b, res = run_gpu(w, W, batch)
+    p = etx.Pipeline(w, W)
+    etx.etx_set_option(p.ctx, etx.ETX_OPT_OUTSUM_LDS, outsum_lds)
+    etx.etx_set_option(p.ctx, etx.ETX_OPT_F32_SPLIT, f32_split)
+    b = etx.to_device(batch)
+    p.run(b)
+    res = p.results(b)
     # the oracle costs ~25 s per event of this size: check event 0 element by
     # element, the others by invariants that hold at any size
     ref, n_undec, frac = event_parity(w, W, batch, res, 0)
@@ -248,6 +258,69 @@ def check_invariants(w, batch, res):
     k = score >= np.float32(0.5)
     assert np.all(lab[src[k]] == lab[dst[k]])
     assert np.array_equal(lab, O.components(n, src, dst, k))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_outsum_lds_schedules_bit_identical(prec):
+    """Hidden size 64 with the LDS out-sums: every pipeline depth and
+    workgroup shape computes the same bits (two full-size events)."""
+    etx = _etx()
+    w = synth.C2
+    W = centred_weights(w)
+    batch = synth.generate_batch(w, 2)
+    p = etx.Pipeline(w, W, precision=prec)
+    etx.etx_set_option(p.ctx, etx.ETX_OPT_OUTSUM_LDS, 1)
+    b = etx.to_device(batch)
+    ref = None
+    for threads, per_cu in ((512, 2), (256, 3)):
+        for pipe in (0, 1, 2):
+            etx.etx_set_option(p.ctx, etx.ETX_OPT_EDGE_WG_SIZE, threads)
+            etx.etx_set_option(p.ctx, etx.ETX_OPT_EDGE_WG_PER_CU, per_cu)
+            etx.etx_set_option(p.ctx, etx.ETX_OPT_EDGE_PIPELINE, pipe)
+            p.run(b)
+            r = p.results(b)
+            if ref is None:
+                ref = r
+                continue
+            for k in ("src", "dst", "score", "labels", "edge_off"):
+                assert np.array_equal(r[k], ref[k]), (threads, per_cu, pipe, k)
+
+
+@pytest.mark.parametrize("wl", ["c1", "c3"])
+def test_f32_split_parity(wl):
+    """FP32 GEMMs as split BF16 products: edges, scores (1e-5) and labels as
+    the FP64 oracle, event by event, for the hidden-32 networks."""
+    etx = _etx()
+    w = synth.WORKLOADS[wl]
+    W = centred_weights(w)
+    batch = synth.generate_batch(w, 1 if wl == "c1" else 4)
+    p = etx.Pipeline(w, W)
+    etx.etx_set_option(p.ctx, etx.ETX_OPT_F32_SPLIT, 1)
+    b = etx.to_device(batch)
+    p.run(b)
+    res = p.results(b)
+    for i in range(len(batch["hit_off"]) - 1):
+        event_parity(w, W, batch, res, i)
+
+
+@pytest.mark.parametrize("wl,n", [("c1", 1), ("c3", 6), ("c2", 2)])
+def test_radius_single_pass_identical(wl, n):
+    """The one-pass radius search (selection into slots, then a copy) and the
+    count + emit passes give the same graph and outputs, bit for bit."""
+    etx = _etx()
+    w = synth.WORKLOADS[wl]
+    W = centred_weights(w)
+    batch = synth.generate_batch(w, n)
+    p = etx.Pipeline(w, W)
+    b = etx.to_device(batch)
+    out = {}
+    for single in (1, 0):
+        etx.etx_set_option(p.ctx, etx.ETX_OPT_RADIUS_SINGLE_PASS, single)
+        p.run(b)
+        out[single] = p.results(b)
+    etx.etx_set_option(p.ctx, etx.ETX_OPT_RADIUS_SINGLE_PASS, 1)
+    for k in ("src", "dst", "score", "labels", "edge_off"):
+        assert np.array_equal(out[0][k], out[1][k]), k
 
 
 def test_shuffled_hit_order_parity():
