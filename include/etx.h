@@ -221,6 +221,20 @@ etx_status etx_prefilter_config(etx_ctx* ctx, int32_t enabled, float tau);
 /* Optimiser state for checkpointing: params, Adam m, Adam v (3 * ETX_PF_NPARAM floats). */
 etx_status etx_prefilter_state(etx_ctx* ctx, float* host_state, int64_t n, int32_t set);
 
+/* Checkpoint of a context: configuration, weight blob, per-tensor scales and
+ * calibration flag, prefilter parameters with their Adam moments, and the
+ * launch options (the state that training, calibration and tuning build up).
+ * etx_save with buf == NULL stores the byte count in *nbytes; with a buffer of
+ * *nbytes bytes it writes the checkpoint (ETX_ERR_INVALID_ARG and the needed
+ * size if it is too small).  The prefilter moments are read from the device,
+ * so the call waits for the device.  etx_load creates a context on `device`
+ * from such a buffer (ETX_ERR_INVALID_ARG for a buffer that is not one, of
+ * this library's layout and size), exactly as etx_create would with the saved
+ * configuration and weights, then restores the rest.  Plain host memory; the
+ * format is this library's own (native byte order). */
+etx_status etx_save(const etx_ctx* ctx, void* buf, size_t* nbytes);
+etx_status etx_load(const void* buf, size_t nbytes, int device, etx_ctx** out);
+
 const char* etx_status_str(etx_status s);
 /* Text of the last HIP failure seen by this thread ("" if none). */
 const char* etx_last_error(void);

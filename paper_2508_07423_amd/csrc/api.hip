@@ -66,6 +66,7 @@ WsLayout ws_layout(const etx_ctx* ctx, int64_t n_events, int64_t n_hits, int64_t
   L.pf_prob = take(sizeof(float) * edge_cap);
   L.pf_part = take(sizeof(float) * (size_t)kPfMaxWaves * kPfGradStride);
   L.pf_grad = take(sizeof(float) * kPfGradStride);
+  L.pf_polar = take(sizeof(float) * 2 * n_hits);
   L.total = o;
   return L;
 }
@@ -517,6 +518,7 @@ etx_status etx_create(const etx_config* cfg, const void* weights, size_t nbytes,
   etx_ctx* ctx = new etx_ctx();
   ctx->cfg = *cfg;
   ctx->device = device;
+  ctx->blob.assign(static_cast<const char*>(weights), static_cast<const char*>(weights) + nbytes);
   if (hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
     delete ctx;
     return ETX_ERR_HIP;
@@ -840,6 +842,112 @@ etx_status etx_prefilter_state(etx_ctx* ctx, float* host_state, int64_t n, int32
     ctx->pf_set = true;
     clear_graphs(ctx);
   }
+  return ETX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// checkpoints: everything a context holds beyond its buffers
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct SaveHeader {
+  uint32_t magic, version, config_bytes, n_scales, n_pf, n_options;
+  uint64_t blob_bytes;
+  int32_t calibrated, pf_set;
+};
+constexpr uint32_t kSaveMagic = 0x53585445;   // "ETXS"
+constexpr int kSavedOptions = 13;             // etx_option keys 0 .. 12
+
+size_t save_bytes(const etx_ctx* ctx) {
+  return sizeof(SaveHeader) + sizeof(etx_config) + sizeof(float) * (N_SCALES + 3 * ETX_PF_NPARAM) +
+         sizeof(int64_t) * kSavedOptions + ctx->blob.size();
+}
+
+}  // namespace
+
+etx_status etx_save(const etx_ctx* ctx, void* buf, size_t* nbytes) {
+  if (!ctx || !nbytes) return ETX_ERR_INVALID_ARG;
+  const size_t need = save_bytes(ctx);
+  if (!buf) {
+    *nbytes = need;
+    return ETX_OK;
+  }
+  if (*nbytes < need) {
+    *nbytes = need;
+    return ETX_ERR_INVALID_ARG;
+  }
+  char* o = static_cast<char*>(buf);
+  SaveHeader h{kSaveMagic, 1, (uint32_t)sizeof(etx_config), (uint32_t)N_SCALES, (uint32_t)(3 * ETX_PF_NPARAM),
+               (uint32_t)kSavedOptions, (uint64_t)ctx->blob.size(), ctx->calibrated ? 1 : 0, ctx->pf_set ? 1 : 0};
+  std::memcpy(o, &h, sizeof h);
+  o += sizeof h;
+  std::memcpy(o, &ctx->cfg, sizeof(etx_config));
+  o += sizeof(etx_config);
+  std::memcpy(o, ctx->host_scales, sizeof(float) * N_SCALES);
+  o += sizeof(float) * N_SCALES;
+  if (hipSetDevice(ctx->device) != hipSuccess) return ETX_ERR_HIP;
+  hipError_t e = hipMemcpy(o, ctx->dev_pf, sizeof(float) * 3 * ETX_PF_NPARAM, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) {
+    note_error("etx_save", e);
+    return ETX_ERR_HIP;
+  }
+  o += sizeof(float) * 3 * ETX_PF_NPARAM;
+  for (int k = 0; k < kSavedOptions; ++k) {
+    int64_t v = 0;
+    etx_get_option(ctx, k, &v);
+    std::memcpy(o, &v, sizeof v);
+    o += sizeof v;
+  }
+  std::memcpy(o, ctx->blob.data(), ctx->blob.size());
+  *nbytes = need;
+  return ETX_OK;
+}
+
+etx_status etx_load(const void* buf, size_t nbytes, int device, etx_ctx** out) {
+  if (!buf || !out) return ETX_ERR_INVALID_ARG;
+  *out = nullptr;
+  SaveHeader h;
+  if (nbytes < sizeof h) return ETX_ERR_INVALID_ARG;
+  std::memcpy(&h, buf, sizeof h);
+  if (h.magic != kSaveMagic || h.version != 1 || h.config_bytes != sizeof(etx_config) || h.n_scales != N_SCALES ||
+      h.n_pf != 3 * ETX_PF_NPARAM || h.n_options != kSavedOptions)
+    return ETX_ERR_INVALID_ARG;
+  const size_t need = sizeof h + sizeof(etx_config) + sizeof(float) * (N_SCALES + 3 * ETX_PF_NPARAM) +
+                      sizeof(int64_t) * kSavedOptions + h.blob_bytes;
+  if (nbytes != need) return ETX_ERR_INVALID_ARG;
+  const char* p = static_cast<const char*>(buf) + sizeof h;
+  etx_config cfg;
+  std::memcpy(&cfg, p, sizeof cfg);
+  p += sizeof cfg;
+  const char* scales = p;
+  p += sizeof(float) * N_SCALES;
+  const char* pf = p;
+  p += sizeof(float) * 3 * ETX_PF_NPARAM;
+  const char* opts = p;
+  p += sizeof(int64_t) * kSavedOptions;
+  etx_ctx* ctx = nullptr;
+  etx_status st = etx_create(&cfg, p, (size_t)h.blob_bytes, device, &ctx);
+  if (st != ETX_OK) return st;
+  std::memcpy(ctx->host_scales, scales, sizeof(float) * N_SCALES);
+  ctx->calibrated = h.calibrated != 0;
+  hipError_t e = hipMemcpy(ctx->dev_scales, ctx->host_scales, sizeof(float) * N_SCALES, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ctx->dev_pf, pf, sizeof(float) * 3 * ETX_PF_NPARAM, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    note_error("etx_load", e);
+    etx_destroy(ctx);
+    return ETX_ERR_HIP;
+  }
+  ctx->pf_set = h.pf_set != 0;
+  for (int k = 0; k < kSavedOptions; ++k) {
+    int64_t v;
+    std::memcpy(&v, opts + sizeof(int64_t) * k, sizeof v);
+    if (k != ETX_OPT_PROFILE && (st = etx_set_option(ctx, k, v)) != ETX_OK) {
+      etx_destroy(ctx);
+      return st;
+    }
+  }
+  *out = ctx;
   return ETX_OK;
 }
 

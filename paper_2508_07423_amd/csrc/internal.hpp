@@ -33,7 +33,7 @@ struct WeightMap {
 // Byte offsets of the workspace buffers.
 struct WsLayout {
   size_t bucket, plane_off, emb, cnt, slots, row_ptr, scan_tmp, col_ptr, csc, h, ps, pd, msg, e, opart, kept, kept_cnt,
-      calib, pf_keep, pf_tmp, cand_src, cand_dst, pf_prob, pf_part, pf_grad, total;
+      calib, pf_keep, pf_tmp, cand_src, cand_dst, pf_prob, pf_part, pf_grad, pf_polar, total;
   int64_t n_scan_blocks;
 };
 
@@ -69,6 +69,7 @@ struct etx_ctx {
   int outsum_lds = 1;
   int f32_split = 0;               // FP32 runs: edge-kernel GEMMs as split BF16 products
   int radius_single = 1;           // radius graph: one selection pass + slot copy (0: count and emit passes)
+  std::vector<char> blob;          // the weight blob as given (for etx_save)
   int use_graph = 0;
   std::map<etx::GraphKey, hipGraphExec_t> graphs;
   // stage timing with HIP events (ETX_OPT_PROFILE)

@@ -40,6 +40,7 @@ struct PfArgs {
   const float* y;
   const float* z;
   const float* emb;          // [n_hits][16]
+  const float2* polar;       // [n_hits] (r, phi) of every hit
   const int64_t* row_ptr;    // candidate CSR; row_ptr[n_hits] = candidate count
   const int32_t* src;
   const int32_t* dst;
@@ -81,10 +82,20 @@ __device__ inline void stage_params(PfLds& L, const float* __restrict__ p) {
   }
 }
 
+// (r, phi) of every hit, once per batch, so that the per-edge features are
+// differences (the same FP32 values as evaluating them per edge).
+__global__ void k_hit_polar(int64_t n, const float* __restrict__ x, const float* __restrict__ y,
+                            float2* __restrict__ polar, const int64_t* status) {
+  if (status[0] != 0) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    polar[i] = make_float2(hypotf(x[i], y[i]), atan2f(y[i], x[i]));
+}
+
 // Features of a candidate edge (every lane of the column computes them).
 __device__ inline void edge_features(const PfArgs& A, int s, int d, float (&f)[6]) {
   const float xi = A.x[s], yi = A.y[s], zi = A.z[s], xj = A.x[d], yj = A.y[d], zj = A.z[d];
-  float dphi = atan2f(yj, xj) - atan2f(yi, xi);
+  const float2 pi_ = A.polar[s], pj = A.polar[d];
+  float dphi = pj.y - pi_.y;
   const float pi = 3.14159265358979f;
   if (dphi > pi) dphi -= 2.f * pi;
   if (dphi <= -pi) dphi += 2.f * pi;
@@ -103,7 +114,7 @@ __device__ inline void edge_features(const PfArgs& A, int s, int d, float (&f)[6
   f[0] = (xj - xi) * A.inv_r;
   f[1] = (yj - yi) * A.inv_r;
   f[2] = (zj - zi) * A.inv_z;
-  f[3] = (hypotf(xj, yj) - hypotf(xi, yi)) * A.inv_r;
+  f[3] = (pj.x - pi_.x) * A.inv_r;
   f[4] = dphi * (1.0f / pi);
   f[5] = sqrtf(d2);
 }
@@ -283,7 +294,8 @@ __global__ void k_pf_adam(float* __restrict__ p, float* __restrict__ m, float* _
   p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// surviving candidates per source, and their compaction into the output edge list
+// surviving candidates per source, and their compaction into the output edge
+// list; one thread per source (rows hold at most k_max <= 64 candidates)
 template <bool WRITE>
 __global__ __launch_bounds__(256) void k_pf_rows(int64_t n_hits, const int64_t* __restrict__ cand_ptr,
                                                  const uint8_t* __restrict__ keep, int32_t* __restrict__ cnt,
@@ -291,17 +303,20 @@ __global__ __launch_bounds__(256) void k_pf_rows(int64_t n_hits, const int64_t* 
                                                  const int32_t* __restrict__ cdst, int32_t* __restrict__ src,
                                                  int32_t* __restrict__ dst, const int64_t* status) {
   if (status[0] != 0) return;
-  const int lane = threadIdx.x & 63;
-  for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n_hits; i += (int64_t)gridDim.x * 4) {
-    const int64_t cb = cand_ptr[i], len = cand_ptr[i + 1] - cb;     // at most k_max <= 64
-    const bool k = lane < len && keep[cb + lane];
-    const uint64_t m = __ballot(k);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_hits; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t cb = cand_ptr[i], ce = cand_ptr[i + 1];
     if (!WRITE) {
-      if (lane == 0) cnt[i] = __popcll(m);
-    } else if (k) {
-      const int64_t pos = row_ptr[i] + __popcll(m & ((1ull << lane) - 1ull));
-      src[pos] = csrc[cb + lane];
-      dst[pos] = cdst[cb + lane];
+      int c = 0;
+      for (int64_t q = cb; q < ce; ++q) c += keep[q];
+      cnt[i] = c;
+    } else {
+      int64_t pos = row_ptr[i];
+      for (int64_t q = cb; q < ce; ++q)
+        if (keep[q]) {
+          src[pos] = csrc[q];
+          dst[pos] = cdst[q];
+          ++pos;
+        }
     }
   }
 }
@@ -313,6 +328,7 @@ PfArgs pf_args(const RunArgs& a, bool candidates) {
   A.y = a.hits.y;
   A.z = a.hits.z;
   A.emb = reinterpret_cast<const float*>(a.ws + a.L.emb);
+  A.polar = reinterpret_cast<const float2*>(a.ws + a.L.pf_polar);
   A.row_ptr = reinterpret_cast<const int64_t*>(a.ws + (candidates ? a.L.pf_tmp : a.L.row_ptr));
   A.src = candidates ? reinterpret_cast<const int32_t*>(a.ws + a.L.cand_src) : a.out.src;
   A.dst = candidates ? reinterpret_cast<const int32_t*>(a.ws + a.L.cand_dst) : a.out.dst;
@@ -331,15 +347,24 @@ unsigned pf_grid(const etx_ctx* c) { return (unsigned)std::min(c->n_cu * 2, kPfM
 
 }  // namespace
 
+static void launch_polar(const RunArgs& a) {
+  if (a.hits.n_hits == 0) return;
+  const unsigned grid = (unsigned)std::min<int64_t>((a.hits.n_hits + 255) / 256, (int64_t)a.ctx->n_cu * 16);
+  hipLaunchKernelGGL(k_hit_polar, dim3(grid), dim3(256), 0, a.stream, a.hits.n_hits, a.hits.x, a.hits.y,
+                     reinterpret_cast<float2*>(a.ws + a.L.pf_polar), a.out.status);
+}
+
 hipError_t launch_prefilter_infer(const RunArgs& a) {
   PfArgs A = pf_args(a, true);
-  hipLaunchKernelGGL(k_pf<false>, dim3(pf_grid(a.ctx)), dim3(kPfThreads), 0, a.stream, A);
+  launch_polar(a);
+  // inference keeps no per-wave partials: a full grid of persistent waves
+  hipLaunchKernelGGL(k_pf<false>, dim3((unsigned)(a.ctx->n_cu * 4)), dim3(kPfThreads), 0, a.stream, A);
   return hipGetLastError();
 }
 
 hipError_t launch_prefilter_count(const RunArgs& a) {
   if (a.hits.n_hits == 0) return hipSuccess;
-  unsigned grid = (unsigned)std::min<int64_t>((a.hits.n_hits + 3) / 4, 65536);
+  unsigned grid = (unsigned)std::min<int64_t>((a.hits.n_hits + 255) / 256, (int64_t)a.ctx->n_cu * 16);
   hipLaunchKernelGGL(k_pf_rows<false>, dim3(grid), dim3(256), 0, a.stream, a.hits.n_hits,
                      reinterpret_cast<const int64_t*>(a.ws + a.L.pf_tmp),
                      reinterpret_cast<const uint8_t*>(a.ws + a.L.pf_keep), reinterpret_cast<int32_t*>(a.ws + a.L.cnt),
@@ -349,7 +374,7 @@ hipError_t launch_prefilter_count(const RunArgs& a) {
 
 hipError_t launch_prefilter_compact(const RunArgs& a) {
   if (a.hits.n_hits == 0) return hipSuccess;
-  unsigned grid = (unsigned)std::min<int64_t>((a.hits.n_hits + 3) / 4, 65536);
+  unsigned grid = (unsigned)std::min<int64_t>((a.hits.n_hits + 255) / 256, (int64_t)a.ctx->n_cu * 16);
   hipLaunchKernelGGL(k_pf_rows<true>, dim3(grid), dim3(256), 0, a.stream, a.hits.n_hits,
                      reinterpret_cast<const int64_t*>(a.ws + a.L.pf_tmp),
                      reinterpret_cast<const uint8_t*>(a.ws + a.L.pf_keep), nullptr,
@@ -364,6 +389,7 @@ hipError_t launch_prefilter_train(const RunArgs& a, const uint8_t* labels, float
   PfArgs A = pf_args(a, false);
   A.label = labels;
   A.pos_weight = pos_weight;
+  launch_polar(a);
   const unsigned grid = pf_grid(a.ctx);
   hipLaunchKernelGGL(k_pf<true>, dim3(grid), dim3(kPfThreads), 0, a.stream, A);
   float* grad = reinterpret_cast<float*>(a.ws + a.L.pf_grad);

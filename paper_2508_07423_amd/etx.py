@@ -83,6 +83,8 @@ def lib():
             "etx_prefilter_config": [P, i32, C.c_float],
             "etx_quantize": [i32, P, P, i64, C.c_float, P],
             "etx_profile_reset": [P],
+            "etx_save": [P, P, C.POINTER(sz)],
+            "etx_load": [P, sz, C.c_int, C.POINTER(P)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -102,7 +104,7 @@ EXPORTED = ["etx_create", "etx_destroy", "etx_weight_blob_size", "etx_workspace_
             "etx_workspace_view", "etx_set_option", "etx_get_option", "etx_autotune", "etx_calibrate",
             "etx_set_precision", "etx_prefilter_set", "etx_prefilter_get", "etx_prefilter_train_step",
             "etx_prefilter_state", "etx_status_str", "etx_last_error", "etx_profile_read", "etx_profile_reset",
-            "etx_stage_name", "etx_get_scales", "etx_quantize", "etx_prefilter_config"]
+            "etx_stage_name", "etx_get_scales", "etx_quantize", "etx_prefilter_config", "etx_save", "etx_load"]
 
 
 class EtxError(RuntimeError):
@@ -208,6 +210,23 @@ def etx_prefilter_get(ctx) -> np.ndarray:
     p = np.zeros(ETX_PF_NPARAM, np.float32)
     _check(lib().etx_prefilter_get(ctx, p.ctypes.data_as(C.c_void_p), p.size), "etx_prefilter_get")
     return p
+
+
+def etx_save(ctx) -> bytes:
+    """Checkpoint of a context (configuration, weights, scales, prefilter state, options)."""
+    n = C.c_size_t()
+    _check(lib().etx_save(ctx, None, C.byref(n)), "etx_save")
+    buf = C.create_string_buffer(n.value)
+    _check(lib().etx_save(ctx, buf, C.byref(n)), "etx_save")
+    return buf.raw[:n.value]
+
+
+def etx_load(data: bytes, device: int = 0):
+    """A new context from an etx_save checkpoint."""
+    ctx = C.c_void_p()
+    buf = C.create_string_buffer(bytes(data), len(data))
+    _check(lib().etx_load(buf, len(data), device, C.byref(ctx)), "etx_load")
+    return ctx
 
 
 def etx_prefilter_state(ctx, state: Optional[np.ndarray] = None) -> np.ndarray:

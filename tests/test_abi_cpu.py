@@ -83,3 +83,15 @@ def test_status_strings_and_null_handles():
     assert L.etx_run(None, None, None, None, 0, None) == etx.ETX_ERR_INVALID_ARG
     assert L.etx_destroy(None) == etx.ETX_ERR_INVALID_ARG
     assert etx.etx_stage_name(0) == "init" and etx.etx_stage_name(999) == ""
+
+
+def test_checkpoint_load_rejects_foreign_buffers_on_host():
+    """etx_load validates the checkpoint header before touching a device."""
+    L = etx.lib()
+    ctx = C.c_void_p()
+    for bad in (b"", b"ETXS", b"\0" * 64, b"XXXX" + b"\0" * 200):
+        buf = C.create_string_buffer(bad, max(len(bad), 1))
+        assert L.etx_load(buf, len(bad), 0, C.byref(ctx)) == etx.ETX_ERR_INVALID_ARG
+    n = C.c_size_t()
+    assert L.etx_save(None, None, C.byref(n)) == etx.ETX_ERR_INVALID_ARG
+    assert L.etx_load(None, 0, 0, C.byref(ctx)) == etx.ETX_ERR_INVALID_ARG

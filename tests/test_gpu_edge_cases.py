@@ -217,3 +217,34 @@ def test_host_argument_errors():
     with pytest.raises(etx.EtxError) as e:
         etx.etx_run(p.ctx, p.hits_struct(b), out, p.ws_ptr + 4, p.ws_bytes, 0)
     assert e.value.code == etx.ETX_ERR_INVALID_ARG
+
+
+def test_checkpoint_round_trip():
+    """etx_save / etx_load carry weights, FP8 scales, prefilter state and
+    launch options: the loaded context computes the same bits."""
+    etx = _etx()
+    w = synth.C1
+    W = synth.xavier_weights(w)
+    cal = etx.to_device(synth.generate_batch(w, 3, seed_space=1001))
+    batch = synth.generate_batch(w, 1)
+    p = etx.Pipeline(w, W, precision=etx.ETX_FP8_E4M3)
+    p.calibrate(cal)
+    rng = np.random.default_rng(5)
+    state = rng.normal(0, 0.1, 3 * etx.ETX_PF_NPARAM).astype(np.float32)
+    etx.etx_prefilter_state(p.ctx, state)
+    etx.etx_set_option(p.ctx, etx.ETX_OPT_EDGE_PIPELINE, 2)
+    b = etx.to_device(batch)
+    p.run(b)
+    r0 = p.results(b)
+    blob = etx.etx_save(p.ctx)
+    q = etx.Pipeline(w, W, precision=etx.ETX_FP8_E4M3)
+    etx.etx_destroy(q.ctx)
+    q.ctx = etx.etx_load(blob)
+    assert etx.etx_get_option(q.ctx, etx.ETX_OPT_EDGE_PIPELINE) == 2
+    assert np.array_equal(etx.etx_prefilter_state(q.ctx), state)
+    assert np.array_equal(etx.etx_get_scales(q.ctx), etx.etx_get_scales(p.ctx))
+    q.run(b)
+    r1 = q.results(b)
+    for k in ("src", "dst", "score", "labels", "edge_off"):
+        assert np.array_equal(r0[k], r1[k]), k
+    assert etx.etx_save(q.ctx) == blob
