@@ -129,15 +129,32 @@ def copy_calibration(gib):
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}), flush=True)
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, weights, batch, threads):
+    """The FP64 oracle on the host: one thread per event over `threads`
+    events, and one event on a single thread."""
     from oracle import oracle as O
     O.lib()
     n = min(threads, len(batch["hit_off"]) - 1)
     t0 = time.perf_counter()
     O.run_batch(batch, w, weights, events=list(range(n)), threads=threads)
     dt = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    O.run_batch(batch, w, weights, events=[n % max(len(batch["hit_off"]) - 1, 1)], threads=1)
+    dt1 = time.perf_counter() - t1
     return dict(value=n / dt, unit="events/s", cores=threads, kind="oracle",
-                sample=f"first {n} events of the same batch, one oracle thread per event ({dt:.1f} s wall)")
+                sample=f"first {n} events of the same batch, one oracle thread per event ({dt:.1f} s wall)",
+                single_thread_events_per_s=round(1.0 / dt1, 4), cpu_model=cpu_model(), nproc=os.cpu_count())
 
 
 def main():

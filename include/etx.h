@@ -158,9 +158,12 @@ typedef enum {
   ETX_OPT_F32_SPLIT = 11,     /* 1: in FP32 runs the edge kernels compute their GEMMs on the BF16 matrix cores with
                                  every FP32 operand split exactly into three BF16 parts (six partial products,
                                  FP32 accumulation; error at FP32 rounding level); 0: FP32 matrix cores */
-  ETX_OPT_RADIUS_SINGLE_PASS = 12 /* 1 (default): the radius search selects each source's neighbours once into
-                                     k_max workspace slots per hit and the CSR rows are copied after the scan;
-                                     0: a count pass and an emit pass */
+  ETX_OPT_RADIUS_SINGLE_PASS = 12, /* 1 (default): the radius search selects each source's neighbours once into
+                                      k_max workspace slots per hit and the CSR rows are copied after the scan;
+                                      0: a count pass and an emit pass */
+  ETX_OPT_RADIUS_SORT_MIN = 13 /* staged candidate windows with at least this many hits are sorted along their
+                                  widest axis and searched as a cell list; smaller ones are scanned whole
+                                  (default 512; 0: always sort) */
 } etx_option;
 etx_status etx_set_option(etx_ctx* ctx, int32_t key, int64_t value);
 etx_status etx_get_option(const etx_ctx* ctx, int32_t key, int64_t* value);

@@ -194,6 +194,10 @@ __global__ void k_edge_off(const int64_t* __restrict__ hit_off, int64_t n_events
 // CSC: edge ids ordered by (dst, src), per event
 // --------------------------------------------------------------------------
 
+// Long rows (at least kCscRowWalk edges per source on average) are placed a
+// row per step, short rows 64 edges per step; both keep (dst, src) order.
+constexpr int kCscRowWalk = 16;
+
 __global__ __launch_bounds__(256) void k_csc(const int64_t* __restrict__ hit_off, const int64_t* __restrict__ row_ptr,
                                              const int32_t* __restrict__ dst, int64_t* __restrict__ col_ptr,
                                              int32_t* __restrict__ csc, const int64_t* status) {
@@ -223,39 +227,67 @@ __global__ __launch_bounds__(256) void k_csc(const int64_t* __restrict__ hit_off
   if (t == 0) col_ptr[a + n] = ee;
   __syncthreads();
   if (t >= 64) return;
-  // one wave walks the rows in source order; the targets of one row are
-  // distinct, so its lanes never share a cursor.  Row bounds and targets are
-  // loaded kRow rows ahead so that HBM latency overlaps the LDS updates.
-  constexpr int kRow = 8;
-  int64_t rb[kRow + 1];
-  int dd[kRow];
-  auto load_block = [&](int i0, int64_t (&b)[kRow + 1], int (&d)[kRow]) {
+  if (ee - eb >= (int64_t)kCscRowWalk * n) {
+    // one wave walks the rows in source order; the targets of one row are
+    // distinct, so its lanes never share a cursor.  Row bounds and targets are
+    // loaded kRow rows ahead so that HBM latency overlaps the LDS updates.
+    constexpr int kRow = 8;
+    int64_t rb[kRow + 1];
+    int dd[kRow];
+    auto load_block = [&](int i0, int64_t (&b)[kRow + 1], int (&d)[kRow]) {
 #pragma unroll
-    for (int q = 0; q <= kRow; ++q) b[q] = row_ptr[a + min(i0 + q, n)];
+      for (int q = 0; q <= kRow; ++q) b[q] = row_ptr[a + min(i0 + q, n)];
 #pragma unroll
-    for (int q = 0; q < kRow; ++q) d[q] = (b[q] + lane < b[q + 1]) ? dst[b[q] + lane] : 0;
-  };
-  if (n > 0) load_block(0, rb, dd);
-  for (int i0 = 0; i0 < n; i0 += kRow) {
-    int64_t nb[kRow + 1];
-    int nd[kRow];
-    if (i0 + kRow < n) load_block(i0 + kRow, nb, nd);
+      for (int q = 0; q < kRow; ++q) d[q] = (b[q] + lane < b[q + 1]) ? dst[b[q] + lane] : 0;
+    };
+    if (n > 0) load_block(0, rb, dd);
+    for (int i0 = 0; i0 < n; i0 += kRow) {
+      int64_t nb[kRow + 1];
+      int nd[kRow];
+      if (i0 + kRow < n) load_block(i0 + kRow, nb, nd);
 #pragma unroll
-    for (int q = 0; q < kRow; ++q) {
-      if (rb[q] + lane < rb[q + 1]) {
-        const int dl = dd[q] - (int)a;
-        const int pos = cur[dl];
-        cur[dl] = pos + 1;
-        csc[eb + pos] = (int32_t)(rb[q] + lane);
+      for (int q = 0; q < kRow; ++q) {
+        if (rb[q] + lane < rb[q + 1]) {
+          const int dl = dd[q] - (int)a;
+          const int pos = cur[dl];
+          cur[dl] = pos + 1;
+          csc[eb + pos] = (int32_t)(rb[q] + lane);
+        }
+        wave_sync();
       }
-      wave_sync();
-    }
-    if (i0 + kRow < n) {
+      if (i0 + kRow < n) {
 #pragma unroll
-      for (int q = 0; q <= kRow; ++q) rb[q] = nb[q];
+        for (int q = 0; q <= kRow; ++q) rb[q] = nb[q];
 #pragma unroll
-      for (int q = 0; q < kRow; ++q) dd[q] = nd[q];
+        for (int q = 0; q < kRow; ++q) dd[q] = nd[q];
+      }
     }
+    return;
+  }
+  // one wave scatters the edges in source-major order, 64 at a time: a lane's
+  // rank among the lanes of the chunk with the same target (lower lanes are
+  // earlier edges) gives its slot after the target's cursor, and the last of
+  // them advances the cursor, so every column keeps source order.  The next
+  // chunk's targets load while this one is placed.
+  int dn = eb + lane < ee ? dst[eb + lane] - (int)a : -1;
+  for (int64_t q0 = eb; q0 < ee; q0 += 64) {
+    const int64_t q = q0 + lane;
+    const int d = dn;
+    dn = q + 64 < ee ? dst[q + 64] - (int)a : -1;
+    int rank = 0, cnt = 0;
+#pragma unroll
+    for (int k = 0; k < 64; ++k) {
+      const int o = __builtin_amdgcn_readlane(d, k);
+      cnt += o == d ? 1 : 0;
+      rank += (o == d && k < lane) ? 1 : 0;
+    }
+    const int pos = d >= 0 ? cur[d] + rank : 0;
+    wave_sync();
+    if (d >= 0) {
+      csc[eb + pos] = (int32_t)q;
+      if (rank == cnt - 1) cur[d] = pos + 1;
+    }
+    wave_sync();
   }
 }
 

@@ -36,6 +36,7 @@ struct RadiusArgs {
   const float* emb;        // [n_hits][kDpad]
   int n_planes, window, k_max, dim;
   int stage_window;        // 0: always read the window from HBM
+  int sort_min;            // staged windows of at least this many hits are sorted (cell list)
   float r2, r;
   int32_t* cnt;            // count pass output (and the select pass's)
   const int64_t* row_ptr;  // emit pass input
@@ -104,9 +105,22 @@ __global__ __launch_bounds__(kRadiusThreads) void k_radius(RadiusArgs A) {
   }
   const int32_t* wb = A.bucket + a + w0;
   const bool staged = A.stage_window && nwin <= CAP;
+  // small windows are scanned whole: a few 64-wide passes cost less than the
+  // sort and the per-source searches
+  const bool sorted = staged && nwin >= A.sort_min;
   int npow = 1;
   while (npow < nwin) npow <<= 1;
-  if (staged && nwin > 0) {
+  if (staged && !sorted) {
+    for (int c = threadIdx.x; c < nwin; c += kRadiusThreads) {
+      const int j = wb[c];
+      cj[c] = j;
+#pragma unroll
+      for (int q = 0; q < DP; q += 4)
+        *reinterpret_cast<float4*>(cemb + c * DP + q) = *reinterpret_cast<const float4*>(A.emb + (int64_t)j * kDpad + q);
+    }
+    __syncthreads();
+  }
+  if (sorted && nwin > 0) {
     // stage the window and find its widest axis
     float lo[DP], hi[DP];
 #pragma unroll
@@ -184,24 +198,36 @@ __global__ __launch_bounds__(kRadiusThreads) void k_radius(RadiusArgs A) {
       }
     }
   }
-  const int axis = (staged && nwin > 0) ? misc[0] : 0;
+  const int axis = (sorted && nwin > 0) ? misc[0] : 0;
   float* wl2 = ld2 + wave * kList;
   int* wlj = lj + wave * kList;
   int* sl = sel + wave * 64;
   int* hw = hist + wave * 256;
   const unsigned r2bits = __float_as_uint(A.r2);
 
+  // the next source's index and embedding load while this one is processed
+  int32_t i_next = wave < nsrc ? A.bucket[a + s0 + wave] : 0;
+  float4 e_next[DP / 4];
+#pragma unroll
+  for (int q = 0; q < DP / 4; ++q)
+    e_next[q] = wave < nsrc ? *reinterpret_cast<const float4*>(A.emb + (int64_t)i_next * kDpad + 4 * q)
+                            : make_float4(0.f, 0.f, 0.f, 0.f);
   for (int s = wave; s < nsrc; s += kRadiusWaves) {
-    const int32_t i = A.bucket[a + s0 + s];
+    const int32_t i = i_next;
     float se[DP];
 #pragma unroll
-    for (int q = 0; q < DP; q += 4) {
-      float4 v = *reinterpret_cast<const float4*>(A.emb + (int64_t)i * kDpad + q);
-      se[q] = v.x; se[q + 1] = v.y; se[q + 2] = v.z; se[q + 3] = v.w;
+    for (int q = 0; q < DP / 4; ++q) {
+      se[4 * q] = e_next[q].x; se[4 * q + 1] = e_next[q].y; se[4 * q + 2] = e_next[q].z; se[4 * q + 3] = e_next[q].w;
+    }
+    if (s + kRadiusWaves < nsrc) {
+      i_next = A.bucket[a + s0 + s + kRadiusWaves];
+#pragma unroll
+      for (int q = 0; q < DP / 4; ++q)
+        e_next[q] = *reinterpret_cast<const float4*>(A.emb + (int64_t)i_next * kDpad + 4 * q);
     }
     // candidate range [cb, ce)
     int cb = 0, ce = nwin;
-    if (staged && nwin > 0) {
+    if (sorted && nwin > 0) {
       float sa = 0.f;
 #pragma unroll
       for (int k = 0; k < DP; ++k)
@@ -225,7 +251,7 @@ __global__ __launch_bounds__(kRadiusThreads) void k_radius(RadiusArgs A) {
     }
     auto cand = [&](int c, int& j) -> float {
       if (staged) {
-        const int slot = sidx[c];
+        const int slot = sorted ? sidx[c] : c;
         j = cj[slot];
         return dist2<DP>(se, cemb + slot * DP);
       }
@@ -482,6 +508,7 @@ hipError_t launch_radius(const RunArgs& a, int mode, bool candidates) {
   dim3 grid((unsigned)(a.hits.n_events * c.n_planes));
   const bool small = c.emb_dim <= 8;
   A.stage_window = a.ctx->radius_lds;
+  A.sort_min = a.ctx->radius_sort_min;
 #define LAUNCH_R(M_, D_) \
   hipLaunchKernelGGL((k_radius<M_, D_>), grid, dim3(kRadiusThreads), RadiusLds<D_>::bytes, a.stream, A)
 #define BY_MODE(D_)                                  \

@@ -323,6 +323,26 @@ def test_radius_single_pass_identical(wl, n):
         assert np.array_equal(out[0][k], out[1][k]), k
 
 
+@pytest.mark.parametrize("wl,n", [("c1", 1), ("c3", 6), ("c2", 2)])
+def test_radius_sorted_and_scanned_windows_identical(wl, n):
+    """Candidate windows searched as a sorted cell list or scanned whole give
+    the same graph and outputs, bit for bit."""
+    etx = _etx()
+    w = synth.WORKLOADS[wl]
+    W = centred_weights(w)
+    batch = synth.generate_batch(w, n)
+    p = etx.Pipeline(w, W)
+    b = etx.to_device(batch)
+    out = {}
+    for sort_min in (0, 1 << 14):
+        etx.etx_set_option(p.ctx, etx.ETX_OPT_RADIUS_SORT_MIN, sort_min)
+        p.run(b)
+        out[sort_min] = p.results(b)
+    etx.etx_set_option(p.ctx, etx.ETX_OPT_RADIUS_SORT_MIN, 512)
+    for k in ("src", "dst", "score", "labels", "edge_off"):
+        assert np.array_equal(out[0][k], out[1 << 14][k]), k
+
+
 def test_shuffled_hit_order_parity():
     """Hits in random order (no readout locality) give the same results."""
     w = synth.C3.with_(hit_order="shuffled")
