@@ -225,7 +225,9 @@ def main():
                                                                ("edge_wg_per_cu", etx.ETX_OPT_EDGE_WG_PER_CU),
                                                                ("edge_pipeline", etx.ETX_OPT_EDGE_PIPELINE),
                                                                ("node_wg_per_cu", etx.ETX_OPT_NODE_WG_PER_CU),
-                                                               ("segsum_unroll", etx.ETX_OPT_SEGSUM_UNROLL))}
+                                                               ("fuse_messages", etx.ETX_OPT_FUSE_MESSAGES),
+                                                               ("segsum_unroll", etx.ETX_OPT_SEGSUM_UNROLL),
+                                                               ("radius_sort_min", etx.ETX_OPT_RADIUS_SORT_MIN))}
         print(f"[bench] autotuned: {tuned}", file=sys.stderr, flush=True)
     if args.graph:
         etx.etx_set_option(p.ctx, etx.ETX_OPT_USE_GRAPH, 1)
@@ -241,11 +243,16 @@ def main():
             etx.etx_set_option(p.ctx, etx.ETX_OPT_PROFILE, 1)
             etx.etx_profile_reset(p.ctx)
         torch.cuda.synchronize()
+        # HIP events between the passes (on the stream they run on) for the median
+        marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        marks[0].record(stream)
+        for k in range(args.steps):
             p.run(b, stream=stream)
+            marks[k + 1].record(stream)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        step_ms = sorted(marks[k].elapsed_time(marks[k + 1]) for k in range(args.steps))
     res = p.results(b)      # raises on a non-zero device status
     n_edges = int(res["edge_off"][-1])
     dt = t1 - t0
@@ -267,8 +274,10 @@ def main():
     if use_pf:
         # the unpruned pipeline on the same batch: its throughput and efficiency are the reference
         p0 = etx.Pipeline(w, weights, precision=prec)
-        if args.graph:
-            etx.etx_set_option(p0.ctx, etx.ETX_OPT_USE_GRAPH, 1)
+        # the same launch schedule as the pruned pipeline (tuned or default)
+        for key in range(etx.ETX_OPT_FUSE_MESSAGES + 1):
+            if key not in (etx.ETX_OPT_PROFILE,):
+                etx.etx_set_option(p0.ctx, key, etx.etx_get_option(p.ctx, key))
         with torch.cuda.stream(stream):
             for _ in range(args.warmup):
                 p0.run(b, stream=stream)
@@ -299,6 +308,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "ms_per_step_median": round(step_ms[len(step_ms) // 2], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -161,9 +161,11 @@ typedef enum {
   ETX_OPT_RADIUS_SINGLE_PASS = 12, /* 1 (default): the radius search selects each source's neighbours once into
                                       k_max workspace slots per hit and the CSR rows are copied after the scan;
                                       0: a count pass and an emit pass */
-  ETX_OPT_RADIUS_SORT_MIN = 13 /* staged candidate windows with at least this many hits are sorted along their
-                                  widest axis and searched as a cell list; smaller ones are scanned whole
-                                  (default 512; 0: always sort) */
+  ETX_OPT_RADIUS_SORT_MIN = 13, /* staged candidate windows with at least this many hits are sorted along their
+                                   widest axis and searched as a cell list; smaller ones are scanned whole
+                                   (default 512; 0: always sort) */
+  ETX_OPT_FUSE_MESSAGES = 14   /* 1: the node-update kernel gathers its messages itself (no separate message-sum
+                                  kernel, no message buffer round trip); same sums, same order, same bits */
 } etx_option;
 etx_status etx_set_option(etx_ctx* ctx, int32_t key, int64_t value);
 etx_status etx_get_option(const etx_ctx* ctx, int32_t key, int64_t* value);

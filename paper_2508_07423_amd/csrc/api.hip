@@ -645,6 +645,10 @@ etx_status etx_set_option(etx_ctx* ctx, int32_t key, int64_t value) {
       if (value < 0 || value > ETX_MAX_EVENT_HITS) return ETX_ERR_INVALID_ARG;
       ctx->radius_sort_min = (int)value;
       break;
+    case ETX_OPT_FUSE_MESSAGES:
+      if (value != 0 && value != 1) return ETX_ERR_INVALID_ARG;
+      ctx->fuse_messages = (int)value;
+      break;
     default: return ETX_ERR_INVALID_ARG;
   }
   if (key != ETX_OPT_USE_GRAPH) clear_graphs(ctx);
@@ -700,6 +704,7 @@ etx_status etx_get_option(const etx_ctx* ctx, int32_t key, int64_t* value) {
     case ETX_OPT_F32_SPLIT: *value = ctx->f32_split; break;
     case ETX_OPT_RADIUS_SINGLE_PASS: *value = ctx->radius_single; break;
     case ETX_OPT_RADIUS_SORT_MIN: *value = ctx->radius_sort_min; break;
+    case ETX_OPT_FUSE_MESSAGES: *value = ctx->fuse_messages; break;
     case ETX_OPT_PROFILE: *value = ctx->profile; break;
     default: return ETX_ERR_INVALID_ARG;
   }
@@ -862,7 +867,7 @@ struct SaveHeader {
   int32_t calibrated, pf_set;
 };
 constexpr uint32_t kSaveMagic = 0x53585445;   // "ETXS"
-constexpr int kSavedOptions = 14;             // etx_option keys 0 .. 13
+constexpr int kSavedOptions = 15;             // etx_option keys 0 .. 14
 
 size_t save_bytes(const etx_ctx* ctx) {
   return sizeof(SaveHeader) + sizeof(etx_config) + sizeof(float) * (N_SCALES + 3 * ETX_PF_NPARAM) +

@@ -1,9 +1,11 @@
 // Launch-schedule autotuner: times the batch with each candidate setting of
 // the launch knobs (workgroup size and persistent workgroups per CU of the
 // edge kernels, their software-pipeline depth, workgroups per CU of the node
-// kernels, rows in flight of the segmented sums) and keeps the fastest, one
-// knob at a time, judging each knob by the HIP-event time of the stages it
-// drives.
+// kernels, whether the node kernel gathers its own messages, rows in flight
+// of the segmented sums, the window size from which the radius search sorts)
+// and keeps the fastest, one knob at a time, judging
+// each knob by the HIP-event time of the stages it drives.  None of the knobs
+// changes a result bit.
 #include <chrono>
 #include <cstdio>
 #include <string>
@@ -31,8 +33,8 @@ std::string join(const std::vector<int64_t>& v) {
 }
 
 // stage indices as listed by etx_stage_name
-constexpr int ST_NODE_ENC = 9, ST_EDGE_ENC = 10, ST_SEGSUM = 11, ST_NODE_STEP = 12, ST_EDGE_STEP = 13,
-              ST_EDGE_FINAL = 14;
+constexpr int ST_RADIUS_COUNT = 4, ST_RADIUS_EMIT = 6, ST_NODE_ENC = 9, ST_EDGE_ENC = 10, ST_SEGSUM = 11,
+              ST_NODE_STEP = 12, ST_EDGE_STEP = 13, ST_EDGE_FINAL = 14;
 
 double timed_run(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void* ws, size_t ws_bytes, etx_stream stream,
                  const std::vector<int>& stages, etx_status* st) {
@@ -63,8 +65,10 @@ extern "C" etx_status etx_autotune(etx_ctx* ctx, const etx_hits* hits, etx_out* 
        {{512, 1}, {512, 2}, {512, 3}, {512, 4}, {256, 2}, {256, 3}, {256, 4}, {256, 5}, {256, 6}, {256, 8}},
        edge_stages},
       {{ETX_OPT_EDGE_PIPELINE}, "edge_pipeline", {{0}, {1}, {2}}, edge_stages},
-      {{ETX_OPT_NODE_WG_PER_CU}, "node_wg_per_cu", {{1}, {2}}, {ST_NODE_ENC, ST_NODE_STEP}},
-      {{ETX_OPT_SEGSUM_UNROLL}, "segsum_unroll", {{2}, {4}, {8}}, {ST_SEGSUM}},
+      {{ETX_OPT_NODE_WG_PER_CU}, "node_wg_per_cu", {{1}, {2}, {3}, {4}}, {ST_NODE_ENC, ST_NODE_STEP}},
+      {{ETX_OPT_FUSE_MESSAGES}, "fuse_messages", {{0}, {1}}, {ST_SEGSUM, ST_NODE_STEP}},
+      {{ETX_OPT_SEGSUM_UNROLL}, "segsum_unroll", {{1}, {2}, {4}, {8}}, {ST_SEGSUM}},
+      {{ETX_OPT_RADIUS_SORT_MIN}, "radius_sort_min", {{256}, {512}, {1024}}, {ST_RADIUS_COUNT, ST_RADIUS_EMIT}},
   };
   const int prev_profile = ctx->profile, prev_graph = ctx->use_graph;
   ctx->profile = 1;

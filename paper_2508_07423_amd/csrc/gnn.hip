@@ -618,10 +618,57 @@ __global__ __launch_bounds__(256) void k_segsum(GnnArgs A) {
   }
 }
 
+// The messages of the node tile's columns, gathered in the node kernel
+// itself (the fused form of k_segsum, same sums in the same order): lane
+// group g of a column holds features phi(r, g), which are exactly its chunks
+// of every stored edge row, so the in-sum needs no rearrangement; the out-sum
+// comes from the edge kernel's whole-row write or its tile partials.
+template <int H, int P>
+__device__ inline void gather_messages(const GnnArgs& A, int64_t node, bool valid, float* mo, float* mi) {
+  constexpr int U = (StorePrec<P>::value == P_F32 && H == 64) ? 1 : 4;   // rows in flight (register budget)
+#pragma unroll
+  for (int r = 0; r < H / 4; ++r) mo[r] = mi[r] = 0.f;
+  if (!valid) return;
+  const int64_t rb = A.row_ptr[node], re = A.row_ptr[node + 1];
+  if (re > rb) {
+    const int64_t t0 = rb / kCols, t1 = (re - 1) / kCols;
+    if (t0 == t1) {
+      load_cols<H>(mo, A.msg + node * 2 * H, true);
+    } else {
+      for (int64_t i = 0; i <= t1 - t0; ++i) add_cols<H>(mo, A.opart + ((t0 + i) * 2 + (i == 0 ? 1 : 0)) * H, true);
+    }
+  }
+  const int64_t cb = A.col_ptr[node], ce = A.col_ptr[node + 1];
+  for (int64_t t = cb; t < ce; t += U) {
+    RawE<P, H> raw[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int id = t + u < ce ? A.csc[t + u] : -1;
+      if (id >= 0) fetch_e<P, H>(raw[u], A.e, id);
+      else
+#pragma unroll
+        for (int q = 0; q < ELayout<P, H>::NQ; ++q) raw[u].v[q] = make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      float v[H / 4];
+      decode_e<P, H>(v, raw[u], 1.0f);
+#pragma unroll
+      for (int r = 0; r < H / 4; ++r) mi[r] += v[r];
+    }
+  }
+  if constexpr (P == P_FP8) {
+    const float scale = asc(A, Q_E + A.step);
+#pragma unroll
+    for (int r = 0; r < H / 4; ++r) mi[r] *= scale;
+  }
+}
+
 // --------------------------------------------------------------------------
 // node update k (+ edge net k source/target products)
 // --------------------------------------------------------------------------
-template <int H, int P>
+// FUSE: the messages are gathered here (k_segsum is not launched).
+template <int H, int P, bool FUSE>
 __global__ __launch_bounds__(NodeThreads<P>::value) void k_node_step(GnnArgs A) {
   if (A.status[0] != 0) return;
   extern __shared__ float lds[];
@@ -639,8 +686,12 @@ __global__ __launch_bounds__(NodeThreads<P>::value) void k_node_step(GnnArgs A) 
     const bool valid = col < A.n_hits;
     float x[3 * H / 4];
     load_cols<H>(x, A.h + col * H, valid);
-    load_cols<H>(x + H / 4, A.msg + col * 2 * H, valid);
-    load_cols<H>(x + H / 2, A.msg + col * 2 * H + H, valid);
+    if constexpr (FUSE) {
+      gather_messages<H, P>(A, col, valid, x + H / 4, x + H / 2);
+    } else {
+      load_cols<H>(x + H / 4, A.msg + col * 2 * H, valid);
+      load_cols<H>(x + H / 2, A.msg + col * 2 * H + H, valid);
+    }
     observe<H / 4>(A.calib, SC_GNN + Q_H, x, valid);
     observe<H / 4>(A.calib, SC_GNN + Q_MO, x + H / 4, valid);
     observe<H / 4>(A.calib, SC_GNN + Q_MI, x + H / 2, valid);
@@ -931,7 +982,7 @@ hipError_t launch_edge_encode(const RunArgs& a) {
 }
 
 hipError_t launch_segsum(const RunArgs& a, int k) {
-  if (a.hits.n_hits == 0) return hipSuccess;
+  if (a.hits.n_hits == 0 || a.ctx->fuse_messages) return hipSuccess;
   GnnArgs A = gnn_args(a);
   A.step = k;
   const int Hh = a.ctx->cfg.gnn_hidden;
@@ -957,7 +1008,11 @@ hipError_t launch_node_step(const RunArgs& a, int k) {
   A.seg_bytes = SegNode{Hh, kPrecBytes[a.prec]}.size();
   A.step = k;
   unsigned grid = node_grid(a, a.ctx->node_wg_per_cu);
-  DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_node_step<H, P>), dim3(grid), dim3(node_threads(P)), A.seg_bytes, a.stream, A));
+  if (a.ctx->fuse_messages) {
+    DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_node_step<H, P, true>), dim3(grid), dim3(node_threads(P)), A.seg_bytes, a.stream, A));
+  } else {
+    DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_node_step<H, P, false>), dim3(grid), dim3(node_threads(P)), A.seg_bytes, a.stream, A));
+  }
   return hipGetLastError();
 }
 
@@ -1016,7 +1071,8 @@ static void set_gnn_attr(int& bad, size_t max_lds) {
     bad |= hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) != hipSuccess;
   };
   set(reinterpret_cast<const void*>(k_node_encode<H, P>));
-  set(reinterpret_cast<const void*>(k_node_step<H, P>));
+  set(reinterpret_cast<const void*>(k_node_step<H, P, false>));
+  set(reinterpret_cast<const void*>(k_node_step<H, P, true>));
   for (int fin = 0; fin < 2; ++fin)
     for (int pipe = 0; pipe < 3; ++pipe)
       for (int wr = 0; wr < 2; ++wr)

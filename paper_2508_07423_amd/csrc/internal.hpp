@@ -69,6 +69,7 @@ struct etx_ctx {
   int outsum_lds = 1;
   int f32_split = 0;               // FP32 runs: edge-kernel GEMMs as split BF16 products
   int radius_single = 1;           // radius graph: one selection pass + slot copy (0: count and emit passes)
+  int fuse_messages = 0;           // message sums gathered inside the node-update kernel
   int radius_sort_min = 512;       // staged windows from this size on are sorted along their widest axis
   std::vector<char> blob;          // the weight blob as given (for etx_save)
   int use_graph = 0;

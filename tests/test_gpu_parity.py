@@ -343,6 +343,27 @@ def test_radius_sorted_and_scanned_windows_identical(wl, n):
         assert np.array_equal(out[0][k], out[1 << 14][k]), k
 
 
+@pytest.mark.parametrize("wl,n,prec", [("c1", 1, 0), ("c3", 6, 0), ("c3", 6, 1), ("c3", 6, 2), ("c2", 2, 0), ("c2", 2, 1)])
+def test_fused_messages_identical(wl, n, prec):
+    """Messages gathered inside the node kernel equal the separate message-sum
+    kernel's, bit for bit (same sums in the same order)."""
+    etx = _etx()
+    w = synth.WORKLOADS[wl]
+    W = centred_weights(w)
+    batch = synth.generate_batch(w, n)
+    p = etx.Pipeline(w, W, precision=prec)
+    if prec == etx.ETX_FP8_E4M3:
+        p.calibrate(etx.to_device(synth.generate_batch(w, 3, seed_space=1000 + w.cid)))
+    b = etx.to_device(batch)
+    out = {}
+    for fuse in (0, 1):
+        etx.etx_set_option(p.ctx, etx.ETX_OPT_FUSE_MESSAGES, fuse)
+        p.run(b)
+        out[fuse] = p.results(b)
+    for k in ("src", "dst", "score", "labels", "edge_off"):
+        assert np.array_equal(out[0][k], out[1][k]), k
+
+
 def test_shuffled_hit_order_parity():
     """Hits in random order (no readout locality) give the same results."""
     w = synth.C3.with_(hit_order="shuffled")
