@@ -227,7 +227,9 @@ def main():
                                                                ("node_wg_per_cu", etx.ETX_OPT_NODE_WG_PER_CU),
                                                                ("fuse_messages", etx.ETX_OPT_FUSE_MESSAGES),
                                                                ("segsum_unroll", etx.ETX_OPT_SEGSUM_UNROLL),
-                                                               ("radius_sort_min", etx.ETX_OPT_RADIUS_SORT_MIN))}
+                                                               ("radius_sort_min", etx.ETX_OPT_RADIUS_SORT_MIN),
+                                                               ("radius_fast", etx.ETX_OPT_RADIUS_FAST),
+                                                               ("xcd_map", etx.ETX_OPT_XCD_MAP))}
         print(f"[bench] autotuned: {tuned}", file=sys.stderr, flush=True)
     if args.graph:
         etx.etx_set_option(p.ctx, etx.ETX_OPT_USE_GRAPH, 1)
@@ -275,7 +277,7 @@ def main():
         # the unpruned pipeline on the same batch: its throughput and efficiency are the reference
         p0 = etx.Pipeline(w, weights, precision=prec)
         # the same launch schedule as the pruned pipeline (tuned or default)
-        for key in range(etx.ETX_OPT_FUSE_MESSAGES + 1):
+        for key in range(etx.ETX_OPT_XCD_MAP + 1):
             if key not in (etx.ETX_OPT_PROFILE,):
                 etx.etx_set_option(p0.ctx, key, etx.etx_get_option(p.ctx, key))
         with torch.cuda.stream(stream):

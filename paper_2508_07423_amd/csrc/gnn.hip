@@ -69,8 +69,22 @@ struct GnnArgs {
   float* calib;             // amax observers (calibration runs, FP32 only)
   const float* sc;          // per-tensor scales (seg.hpp ScaleSlot)
   int step;
+  int xcd_map;              // 1: logical workgroup ids contiguous per XCD
   const int64_t* status;
 };
+
+// Workgroups of a launch are dispatched to the eight XCDs in turn (b -> b % 8).
+// With the remap the workgroups of one XCD hold a contiguous range of logical
+// ids, so at any time an XCD works on neighbouring tiles of one region of the
+// batch and its own L2 holds the node rows those tiles gather; without it every
+// XCD sees every region in flight.  The map is a bijection on [0, grid), so
+// which tiles run is unchanged.
+constexpr int kXcds = 8;
+__device__ inline int64_t logical_block(const GnnArgs& A) {
+  const int64_t G = gridDim.x, b = blockIdx.x;
+  if (!A.xcd_map || G % kXcds != 0) return b;
+  return (b % kXcds) * (G / kXcds) + b / kXcds;
+}
 
 __device__ inline void stage_bytes(char* dst, const char* src, int n) {
   stage(reinterpret_cast<float*>(dst), reinterpret_cast<const float*>(src), n / 4);
@@ -432,7 +446,7 @@ __global__ __launch_bounds__(NodeThreads<P>::value) void k_node_encode(GnnArgs A
   const float s_ne2 = asc(A, Q_NE2), s_h = asc(A, Q_H);
   const float o_ne2 = s_ne2 * wsc(A, SW_NE2), o_h = s_h * wsc(A, SW_EE1);
   const int64_t ntiles = (A.n_hits + kCols - 1) / kCols;
-  for (int64_t tile = (int64_t)blockIdx.x * nw + wave; tile < ntiles; tile += (int64_t)gridDim.x * nw) {
+  for (int64_t tile = logical_block(A) * nw + wave; tile < ntiles; tile += (int64_t)gridDim.x * nw) {
     const int64_t col = tile * kCols + (lane & 15);
     const bool valid = col < A.n_hits;
     float v0 = 0.f, v1 = 0.f, v2 = 0.f;
@@ -493,7 +507,7 @@ __global__ __launch_bounds__(512) void k_edge_encode(GnnArgs A) {
   const int64_t stride = (int64_t)gridDim.x * nw;
   EdgeFeed<P, H, PIPE> feed{A.src, A.dst, nullptr, A.ps, A.pd, E, stride, lane & 15};
   feed.want_e = false;
-  int64_t tile = (int64_t)blockIdx.x * nw + wave;
+  int64_t tile = logical_block(A) * nw + wave;
   if (tile < ntiles) feed.start(tile);
   for (; tile < ntiles; tile += stride) {
     const int64_t col = tile * kCols + (lane & 15);
@@ -566,7 +580,7 @@ __global__ __launch_bounds__(256) void k_segsum(GnnArgs A) {
   const char* eb = static_cast<const char*>(A.e);
   const float scale = P == P_FP8 ? asc(A, Q_E + A.step) : 1.0f;
   const int64_t stride = (int64_t)gridDim.x * 4 * NPW;
-  for (int64_t node = ((int64_t)blockIdx.x * 4 + wave) * NPW + sg; node - sg < A.n_hits; node += stride) {
+  for (int64_t node = (logical_block(A) * 4 + wave) * NPW + sg; node - sg < A.n_hits; node += stride) {
     const bool live = node < A.n_hits;
     float* out = A.msg + node * 2 * H;
     // out-sum: a source row inside one edge tile was written whole by the edge
@@ -681,7 +695,7 @@ __global__ __launch_bounds__(NodeThreads<P>::value) void k_node_step(GnnArgs A) 
   const float s_h = asc(A, Q_H), s_mo = asc(A, Q_MO), s_mi = asc(A, Q_MI), s_nn2 = asc(A, Q_NN2);
   const float w1s = wsc(A, SW_STEP + 4 * k), w2s = wsc(A, SW_STEP + 4 * k + 1), wes = wsc(A, SW_STEP + 4 * k + 2);
   const int64_t ntiles = (A.n_hits + kCols - 1) / kCols;
-  for (int64_t tile = (int64_t)blockIdx.x * nw + wave; tile < ntiles; tile += (int64_t)gridDim.x * nw) {
+  for (int64_t tile = logical_block(A) * nw + wave; tile < ntiles; tile += (int64_t)gridDim.x * nw) {
     const int64_t col = tile * kCols + (lane & 15);
     const bool valid = col < A.n_hits;
     float x[3 * H / 4];
@@ -761,7 +775,7 @@ __global__ __launch_bounds__(512) void k_edge_step(GnnArgs A) {
     load_wreg<H, H / 16>(wr_e, reinterpret_cast<const float*>(w + S.we()));
     load_wreg<H, H / 16>(wr_2, reinterpret_cast<const float*>(w + S.w2()));
   }
-  int64_t tile = (int64_t)blockIdx.x * nw + wave;
+  int64_t tile = logical_block(A) * nw + wave;
   if (tile < ntiles) feed.start(tile);
   for (; tile < ntiles; tile += stride) {
     const int64_t col = tile * kCols + (lane & 15);
@@ -857,6 +871,7 @@ static GnnArgs gnn_args(const RunArgs& a) {
   A.score = a.out.score;
   A.calib = a.calibrate ? reinterpret_cast<float*>(a.ws + a.L.calib) : nullptr;
   A.sc = c->dev_scales;
+  A.xcd_map = a.ctx->xcd_map;
   A.status = a.out.status;
   return A;
 }

@@ -71,6 +71,8 @@ struct etx_ctx {
   int radius_single = 1;           // radius graph: one selection pass + slot copy (0: count and emit passes)
   int fuse_messages = 0;           // message sums gathered inside the node-update kernel
   int radius_sort_min = 512;       // staged windows from this size on are sorted along their widest axis
+  int radius_fast = 0;             // select pass: 16-lane path for sources with few candidates
+  int xcd_map = 0;                 // tile and node kernels: contiguous work per XCD
   std::vector<char> blob;          // the weight blob as given (for etx_save)
   int use_graph = 0;
   std::map<etx::GraphKey, hipGraphExec_t> graphs;

@@ -37,6 +37,7 @@ struct RadiusArgs {
   int n_planes, window, k_max, dim;
   int stage_window;        // 0: always read the window from HBM
   int sort_min;            // staged windows of at least this many hits are sorted (cell list)
+  int fast;                // select pass: sources with at most 16 in-radius candidates take the 16-lane path
   float r2, r;
   int32_t* cnt;            // count pass output (and the select pass's)
   const int64_t* row_ptr;  // emit pass input
@@ -205,22 +206,81 @@ __global__ __launch_bounds__(kRadiusThreads) void k_radius(RadiusArgs A) {
   int* hw = hist + wave * 256;
   const unsigned r2bits = __float_as_uint(A.r2);
 
+  // Fast path of the select pass over a scanned window: four sources per
+  // wave, one per 16-lane row.  A source with at most 16 in-radius candidates
+  // (and no k_max cut) is finished here: its targets, ranked by index, are
+  // exactly what the full path keeps.  Other sources go to a list (the slot
+  // array of the unsorted window) for the one-wave-per-source path below.
+  const bool fast = MODE == R_SELECT && A.fast && staged && !sorted && nsrc <= CAP;
+  int* hard = sidx;
+  int nwork = nsrc;
+  if (fast) {
+    if (threadIdx.x == 0) misc[1] = 0;
+    __syncthreads();
+    const int sub = lane >> 4, l16 = lane & 15;
+    int* sb = sl + 16 * sub;
+    for (int s4 = wave * 4; s4 < nsrc; s4 += kRadiusWaves * 4) {
+      const int s = s4 + sub;
+      const bool live = s < nsrc;
+      const int32_t i = live ? A.bucket[a + s0 + s] : 0;
+      float se[DP];
+#pragma unroll
+      for (int q = 0; q < DP; q += 4) {
+        const float4 v = *reinterpret_cast<const float4*>(A.emb + (int64_t)i * kDpad + q);
+        se[q] = v.x; se[q + 1] = v.y; se[q + 2] = v.z; se[q + 3] = v.w;
+      }
+      int n = 0;
+      for (int c0 = 0; c0 < nwin; c0 += 16) {
+        const int c = c0 + l16;
+        bool in = false;
+        int j = 0;
+        if (live && c < nwin) {
+          j = cj[c];
+          in = dist2<DP>(se, cemb + c * DP) < A.r2;
+        }
+        const uint32_t m = (uint32_t)(__ballot(in) >> (16 * sub)) & 0xffffu;
+        if (in) {
+          const int pos = n + __popc(m & ((1u << l16) - 1u));
+          if (pos < 16) sb[pos] = j;
+        }
+        n += __popc(m);
+      }
+      wave_sync();
+      const bool done = live && n <= 16 && n <= A.k_max;
+      if (done) {
+        if (l16 < n) {
+          const int my = sb[l16];
+          int rank = 0;
+          for (int q = 0; q < n; ++q) rank += sb[q] < my;
+          A.slots[(int64_t)i * A.k_max + rank] = my;
+        }
+        if (l16 == 0) A.cnt[i] = n;
+      } else if (live && l16 == 0) {
+        hard[atomicAdd(&misc[1], 1)] = s;
+      }
+      wave_sync();
+    }
+    __syncthreads();
+    nwork = misc[1];
+  }
+  auto source_of = [&](int h) { return fast ? hard[h] : h; };
+
   // the next source's index and embedding load while this one is processed
-  int32_t i_next = wave < nsrc ? A.bucket[a + s0 + wave] : 0;
+  int32_t i_next = wave < nwork ? A.bucket[a + s0 + source_of(wave)] : 0;
   float4 e_next[DP / 4];
 #pragma unroll
   for (int q = 0; q < DP / 4; ++q)
-    e_next[q] = wave < nsrc ? *reinterpret_cast<const float4*>(A.emb + (int64_t)i_next * kDpad + 4 * q)
-                            : make_float4(0.f, 0.f, 0.f, 0.f);
-  for (int s = wave; s < nsrc; s += kRadiusWaves) {
+    e_next[q] = wave < nwork ? *reinterpret_cast<const float4*>(A.emb + (int64_t)i_next * kDpad + 4 * q)
+                             : make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int h = wave; h < nwork; h += kRadiusWaves) {
     const int32_t i = i_next;
     float se[DP];
 #pragma unroll
     for (int q = 0; q < DP / 4; ++q) {
       se[4 * q] = e_next[q].x; se[4 * q + 1] = e_next[q].y; se[4 * q + 2] = e_next[q].z; se[4 * q + 3] = e_next[q].w;
     }
-    if (s + kRadiusWaves < nsrc) {
-      i_next = A.bucket[a + s0 + s + kRadiusWaves];
+    if (h + kRadiusWaves < nwork) {
+      i_next = A.bucket[a + s0 + source_of(h + kRadiusWaves)];
 #pragma unroll
       for (int q = 0; q < DP / 4; ++q)
         e_next[q] = *reinterpret_cast<const float4*>(A.emb + (int64_t)i_next * kDpad + 4 * q);
@@ -509,6 +569,7 @@ hipError_t launch_radius(const RunArgs& a, int mode, bool candidates) {
   const bool small = c.emb_dim <= 8;
   A.stage_window = a.ctx->radius_lds;
   A.sort_min = a.ctx->radius_sort_min;
+  A.fast = a.ctx->radius_fast;
 #define LAUNCH_R(M_, D_) \
   hipLaunchKernelGGL((k_radius<M_, D_>), grid, dim3(kRadiusThreads), RadiusLds<D_>::bytes, a.stream, A)
 #define BY_MODE(D_)                                  \

@@ -4,6 +4,8 @@ Workloads: the one-event plain pipeline (10 planes, 50 tracks, embedding
 3-64-64-8, radius 0.1, k 32, hidden 32, 4 steps) and small batches of the
 full-size geometry; tolerances as in gpu_helpers.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -360,6 +362,47 @@ def test_fused_messages_identical(wl, n, prec):
         etx.etx_set_option(p.ctx, etx.ETX_OPT_FUSE_MESSAGES, fuse)
         p.run(b)
         out[fuse] = p.results(b)
+    for k in ("src", "dst", "score", "labels", "edge_off"):
+        assert np.array_equal(out[0][k], out[1][k]), k
+
+
+@pytest.mark.parametrize("wl,n,trained", [("c1", 1, False), ("c3", 6, False), ("c2", 2, False), ("c3", 20, True)])
+def test_radius_fast_path_identical(wl, n, trained):
+    """Sources with few candidates handled four to a wave give the same graph
+    and outputs as the one-wave-per-source path, bit for bit."""
+    etx = _etx()
+    w = synth.WORKLOADS[wl]
+    if trained and not os.path.exists(os.path.join(synth.TRAINED_DIR, f"{w.name}_trained.npz")):
+        pytest.skip("trained weights not built")
+    W = synth.trained_weights(w) if trained else centred_weights(w)
+    batch = synth.generate_batch(w, n)
+    p = etx.Pipeline(w, W)
+    b = etx.to_device(batch)
+    out = {}
+    for fast in (0, 1):
+        etx.etx_set_option(p.ctx, etx.ETX_OPT_RADIUS_FAST, fast)
+        p.run(b)
+        out[fast] = p.results(b)
+    for k in ("src", "dst", "score", "labels", "edge_off"):
+        assert np.array_equal(out[0][k], out[1][k]), k
+
+
+@pytest.mark.parametrize("wl,n,prec", [("c1", 3, 0), ("c3", 40, 0), ("c2", 3, 1), ("c3", 40, 2)])
+def test_xcd_map_identical(wl, n, prec):
+    """Contiguous tile ranges per XCD run the same tiles: same bits."""
+    etx = _etx()
+    w = synth.WORKLOADS[wl]
+    W = centred_weights(w)
+    batch = synth.generate_batch(w, n)
+    p = etx.Pipeline(w, W, precision=prec)
+    if prec == etx.ETX_FP8_E4M3:
+        p.calibrate(etx.to_device(synth.generate_batch(w, 4, seed_space=1000 + w.cid)))
+    b = etx.to_device(batch)
+    out = {}
+    for m in (0, 1):
+        etx.etx_set_option(p.ctx, etx.ETX_OPT_XCD_MAP, m)
+        p.run(b)
+        out[m] = p.results(b)
     for k in ("src", "dst", "score", "labels", "edge_off"):
         assert np.array_equal(out[0][k], out[1][k]), k
 
