@@ -203,17 +203,22 @@ def main():
                        tau=round(sel["tau"], 5), recall_target=args.pf_recall,
                        validation_kept=round(sel["kept_fraction"], 4))
 
-    p = etx.Pipeline(w, weights, precision=prec)
+    stream = torch.cuda.Stream()
+    cal = None
+    if prec == etx.ETX_FP8_E4M3:
+        # static calibration on events of a disjoint seed space (on the unpruned graph, before the prefilter is on)
+        cal = etx.to_device(synth.generate_batch(w, 20, seed_space=1000 + w.cid))
+
+    def calibrated(pipe):
+        if cal is not None:
+            with torch.cuda.stream(stream):
+                pipe.calibrate(cal, stream=stream)
+        return pipe
+
+    p = calibrated(etx.Pipeline(w, weights, precision=prec))
     if use_pf:
         etx.etx_prefilter_set(p.ctx, tr["params"])
         etx.etx_prefilter_config(p.ctx, 1, sel["tau"])
-    stream = torch.cuda.Stream()
-    if prec == etx.ETX_FP8_E4M3:
-        # static calibration on events of a disjoint seed space
-        cal = etx.to_device(synth.generate_batch(w, 20, seed_space=1000 + w.cid))
-        with torch.cuda.stream(stream):
-            p.calibrate(cal, stream=stream)
-        del cal
     b = etx.to_device(batch)
     tuned = None
     if args.autotune:
@@ -229,7 +234,8 @@ def main():
                                                                ("segsum_unroll", etx.ETX_OPT_SEGSUM_UNROLL),
                                                                ("radius_sort_min", etx.ETX_OPT_RADIUS_SORT_MIN),
                                                                ("radius_fast", etx.ETX_OPT_RADIUS_FAST),
-                                                               ("xcd_map", etx.ETX_OPT_XCD_MAP))}
+                                                               ("xcd_map", etx.ETX_OPT_XCD_MAP),
+                                                               ("edge_products", etx.ETX_OPT_EDGE_PRODUCTS))}
         print(f"[bench] autotuned: {tuned}", file=sys.stderr, flush=True)
     if args.graph:
         etx.etx_set_option(p.ctx, etx.ETX_OPT_USE_GRAPH, 1)
@@ -275,9 +281,9 @@ def main():
               file=sys.stderr, flush=True)
     if use_pf:
         # the unpruned pipeline on the same batch: its throughput and efficiency are the reference
-        p0 = etx.Pipeline(w, weights, precision=prec)
+        p0 = calibrated(etx.Pipeline(w, weights, precision=prec))
         # the same launch schedule as the pruned pipeline (tuned or default)
-        for key in range(etx.ETX_OPT_XCD_MAP + 1):
+        for key in range(etx.ETX_OPT_EDGE_PRODUCTS + 1):
             if key not in (etx.ETX_OPT_PROFILE,):
                 etx.etx_set_option(p0.ctx, key, etx.etx_get_option(p.ctx, key))
         with torch.cuda.stream(stream):

@@ -168,9 +168,13 @@ typedef enum {
                                   kernel, no message buffer round trip); same sums, same order, same bits */
   ETX_OPT_RADIUS_FAST = 15,    /* 1: in scanned (unsorted) windows, sources with at most 16 in-radius candidates are
                                   handled four to a wave; the others by the one-wave-per-source path; same bits */
-  ETX_OPT_XCD_MAP = 16         /* 1: the edge, message-sum and node kernels give each of the chip's eight XCDs a
+  ETX_OPT_XCD_MAP = 16,        /* 1: the edge, message-sum and node kernels give each of the chip's eight XCDs a
                                   contiguous range of tiles, so that the node rows a region of the batch gathers stay
                                   in that XCD's L2; which tiles run is unchanged, same bits */
+  ETX_OPT_EDGE_PRODUCTS = 17   /* 0 (default): the node update also writes h W_src and h W_dst per node (layer 1 of
+                                  the edge net split by input block) and the edge update gathers them; 1: the edge
+                                  update gathers the rows of h and forms the same products itself, and the node
+                                  update writes none (less HBM traffic, 2H^2 more multiply-adds per edge; same bits) */
 } etx_option;
 etx_status etx_set_option(etx_ctx* ctx, int32_t key, int64_t value);
 etx_status etx_get_option(const etx_ctx* ctx, int32_t key, int64_t* value);

@@ -58,7 +58,8 @@ struct GnnArgs {
   const int32_t* dst;
   const char* seg;          // weight segment of the kernel
   const char* seg2;         // classifier segment (final edge step)
-  int seg_bytes, seg2_bytes;
+  const char* seg3;         // edge-side products: W_src then W_dst of edge net k, layer 1
+  int seg_bytes, seg2_bytes, seg3_bytes;
   float* h;                 // [n_hits][H]
   float* ps;                // [n_hits][H] h W_src (source product)
   float* pd;                // [n_hits][H] h W_dst (target product)
@@ -188,6 +189,15 @@ __device__ inline void add_rows(float* a, const NodeRows<H>& n) {
 #pragma unroll
   for (int c = 0; c < H / 16; ++c) {
     a[4 * c + 0] += n.d[c].x; a[4 * c + 1] += n.d[c].y; a[4 * c + 2] += n.d[c].z; a[4 * c + 3] += n.d[c].w;
+  }
+}
+
+// a gathered row in column layout (the B operand of the next product)
+template <int H>
+__device__ inline void rows_cols(float* x, const float4 (&r)[H / 16]) {
+#pragma unroll
+  for (int c = 0; c < H / 16; ++c) {
+    x[4 * c + 0] = r[c].x; x[4 * c + 1] = r[c].y; x[4 * c + 2] = r[c].z; x[4 * c + 3] = r[c].w;
   }
 }
 
@@ -682,7 +692,9 @@ __device__ inline void gather_messages(const GnnArgs& A, int64_t node, bool vali
 // node update k (+ edge net k source/target products)
 // --------------------------------------------------------------------------
 // FUSE: the messages are gathered here (k_segsum is not launched).
-template <int H, int P, bool FUSE>
+// NP: also write the node products h W_src and h W_dst of edge net k (else
+// the edge kernel forms them from the gathered rows of h).
+template <int H, int P, bool FUSE, bool NP>
 __global__ __launch_bounds__(NodeThreads<P>::value) void k_node_step(GnnArgs A) {
   if (A.status[0] != 0) return;
   extern __shared__ float lds[];
@@ -730,15 +742,17 @@ __global__ __launch_bounds__(NodeThreads<P>::value) void k_node_step(GnnArgs A) 
     for (int r = 0; r < H / 4; ++r) o[r] += x[r];
     store_cols<H>(A.h + col * H, o, valid);
     observe<H / 4>(A.calib, SC_GNN + Q_H, o, valid);
-    float q[H / 4];
+    if constexpr (NP) {
+      float q[H / 4];
 #pragma unroll
-    for (int r = 0; r < H / 4; ++r) q[r] = 0.f;
-    gemm<P, H, H / 16>(q, o, w + S.ws(), 1.0f / s_h, s_h * wes);
-    store_cols<H>(A.ps + col * H, q, valid);
+      for (int r = 0; r < H / 4; ++r) q[r] = 0.f;
+      gemm<P, H, H / 16>(q, o, w + S.ws(), 1.0f / s_h, s_h * wes);
+      store_cols<H>(A.ps + col * H, q, valid);
 #pragma unroll
-    for (int r = 0; r < H / 4; ++r) q[r] = 0.f;
-    gemm<P, H, H / 16>(q, o, w + S.wd(), 1.0f / s_h, s_h * wes);
-    store_cols<H>(A.pd + col * H, q, valid);
+      for (int r = 0; r < H / 4; ++r) q[r] = 0.f;
+      gemm<P, H, H / 16>(q, o, w + S.wd(), 1.0f / s_h, s_h * wes);
+      store_cols<H>(A.pd + col * H, q, valid);
+    }
   }
 }
 
@@ -747,8 +761,12 @@ __global__ __launch_bounds__(NodeThreads<P>::value) void k_node_step(GnnArgs A) 
 // --------------------------------------------------------------------------
 // WR (FP32 only): both H x H weight matrices stay in registers for the whole
 // persistent loop instead of being read from LDS by every MFMA.  OL as in the
-// edge encoder (steps before the last).
-template <int H, bool FINAL, int P, int PIPE, bool WR, bool OL>
+// edge encoder (steps before the last).  GH: the node-product terms of layer 1
+// are formed here, W_src h_src and W_dst h_dst on the gathered rows of h, and
+// the node kernel writes no products; it trades 2H^2 multiply-adds per edge for
+// the node kernel's product rows (written once, gathered per edge), which pays
+// when edges per node are few and the matrix cores are fast (BF16, FP8).
+template <int H, bool FINAL, int P, int PIPE, bool WR, bool OL, bool GH>
 __global__ __launch_bounds__(512) void k_edge_step(GnnArgs A) {
   if (A.status[0] != 0) return;
   extern __shared__ float lds[];
@@ -756,10 +774,14 @@ __global__ __launch_bounds__(512) void k_edge_step(GnnArgs A) {
   constexpr int ES = PrecBytes<P>::value;
   constexpr SegEdge S{H, ES};
   constexpr SegCls C{H, ES};
+  static_assert(!(GH && WR), "edge-side products use the LDS weights");
   stage_bytes(w, A.seg, A.seg_bytes);
-  if (FINAL) stage_bytes(w + S.size(), A.seg2, A.seg2_bytes);
+  const char* wp = w + A.seg_bytes;                    // W_src, W_dst (GH)
+  const int off = A.seg_bytes + (GH ? A.seg3_bytes : 0);
+  if (GH) stage_bytes(w + A.seg_bytes, A.seg3, A.seg3_bytes);
+  if (FINAL) stage_bytes(w + off, A.seg2, A.seg2_bytes);
   __syncthreads();
-  const char* wc = w + S.size();
+  const char* wc = w + off;
   const int lane = lane_id(), g = lane_group(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int k = A.step;
   const float s_e = asc(A, Q_E + k), s_en2 = asc(A, Q_EN2), s_next = asc(A, Q_E + k + 1);
@@ -767,7 +789,7 @@ __global__ __launch_bounds__(512) void k_edge_step(GnnArgs A) {
   const int64_t E = A.row_ptr[A.n_hits];
   const int64_t ntiles = (E + kCols - 1) / kCols;
   const int64_t stride = (int64_t)gridDim.x * nw;
-  EdgeFeed<P, H, PIPE> feed{A.src, A.dst, A.e, A.ps, A.pd, E, stride, lane & 15};
+  EdgeFeed<P, H, PIPE> feed{A.src, A.dst, A.e, GH ? A.h : A.ps, GH ? A.h : A.pd, E, stride, lane & 15};
   feed.want_e = true;
   static_assert(!WR || P == P_F32, "register-resident weights are FP32 only");
   float wr_e[WR ? H * H / 64 : 1], wr_2[WR ? H * H / 64 : 1];
@@ -802,7 +824,28 @@ __global__ __launch_bounds__(512) void k_edge_step(GnnArgs A) {
       else
         gemm<P, H, H / 16>(a, ef, w + S.we(), 1.f, 1.f);
     }
-    add_rows<H>(a, rows);
+    if constexpr (GH) {
+      // the node kernel's products, formed the same way (its precision, its
+      // weights, a zero start) from the rows of h and added in the same order:
+      // the same bits as gathering them
+      constexpr int PP = P == P_F32X ? P_F32 : P;
+      const float s_h = asc(A, Q_H);
+      float x[H / 4], q[H / 4];
+      rows_cols<H>(x, rows.s);
+#pragma unroll
+      for (int r = 0; r < H / 4; ++r) q[r] = 0.f;
+      gemm<PP, H, H / 16>(q, x, wp, 1.0f / s_h, s_h * w1s);
+#pragma unroll
+      for (int r = 0; r < H / 4; ++r) a[r] += q[r];
+      rows_cols<H>(x, rows.d);
+#pragma unroll
+      for (int r = 0; r < H / 4; ++r) q[r] = 0.f;
+      gemm<PP, H, H / 16>(q, x, wp + H * H * PrecBytes<PP>::value, 1.0f / s_h, s_h * w1s);
+#pragma unroll
+      for (int r = 0; r < H / 4; ++r) a[r] += q[r];
+    } else {
+      add_rows<H>(a, rows);
+    }
     ln_relu<H>(a);
     observe<H / 4>(A.calib, SC_GNN + Q_EN2, a, valid);
     float o[H / 4];
@@ -822,7 +865,7 @@ __global__ __launch_bounds__(512) void k_edge_step(GnnArgs A) {
     if (!FINAL) {
       store_e<P, H>(A.e, col, o, valid, 1.0f / s_next, s_next, o);
       if constexpr (OL)
-        out_sums_lds<H>(A, tile, ti, key, o, reinterpret_cast<float*>(w + A.seg_bytes) + wave * kOutBufFloats);
+        out_sums_lds<H>(A, tile, ti, key, o, reinterpret_cast<float*>(w + off) + wave * kOutBufFloats);
       else
         out_sums<H>(A, tile, ti, key, o);
     } else {
@@ -932,18 +975,27 @@ static const void* edge_encode_kernel(int pipe, bool ol) {
 }
 
 template <int H, int P>
-static const void* edge_step_kernel(bool fin, int pipe, bool wr, bool ol) {
+static const void* edge_step_kernel(bool fin, int pipe, bool wr, bool ol, bool gh) {
   auto pick_o = [&](auto F, auto PI, auto WRC) -> const void* {
     constexpr bool f = decltype(F)::value, wv = decltype(WRC)::value;
     constexpr int pi = decltype(PI)::value;
-    if constexpr (H == 64 && !f) {
-      if (ol) return reinterpret_cast<const void*>(k_edge_step<H, f, P, pi, wv, true>);
+    if constexpr (!wv) {
+      if (gh) {
+        if constexpr (H == 64 && !f) {
+          if (ol) return reinterpret_cast<const void*>(k_edge_step<H, f, P, pi, false, true, true>);
+        }
+        return reinterpret_cast<const void*>(k_edge_step<H, f, P, pi, false, false, true>);
+      }
     }
-    return reinterpret_cast<const void*>(k_edge_step<H, f, P, pi, wv, false>);
+    if constexpr (H == 64 && !f) {
+      if (ol) return reinterpret_cast<const void*>(k_edge_step<H, f, P, pi, wv, true, false>);
+    }
+    return reinterpret_cast<const void*>(k_edge_step<H, f, P, pi, wv, false, false>);
   };
+  // edge-side products take the LDS-weight form
   auto pick_w = [&](auto F, auto PI) -> const void* {
     if constexpr (P == P_F32) {
-      if (wr) return pick_o(F, PI, std::true_type{});
+      if (wr && !gh) return pick_o(F, PI, std::true_type{});
     }
     return pick_o(F, PI, std::false_type{});
   };
@@ -1023,11 +1075,19 @@ hipError_t launch_node_step(const RunArgs& a, int k) {
   A.seg_bytes = SegNode{Hh, kPrecBytes[a.prec]}.size();
   A.step = k;
   unsigned grid = node_grid(a, a.ctx->node_wg_per_cu);
-  if (a.ctx->fuse_messages) {
-    DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_node_step<H, P, true>), dim3(grid), dim3(node_threads(P)), A.seg_bytes, a.stream, A));
+  const bool np = !a.ctx->edge_products;
+#define NODE_K(F_, N_) \
+  DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_node_step<H, P, F_, N_>), dim3(grid), dim3(node_threads(P)), A.seg_bytes, a.stream, A))
+  if (a.ctx->fuse_messages && np) {
+    NODE_K(true, true);
+  } else if (a.ctx->fuse_messages) {
+    NODE_K(true, false);
+  } else if (np) {
+    NODE_K(false, true);
   } else {
-    DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_node_step<H, P, false>), dim3(grid), dim3(node_threads(P)), A.seg_bytes, a.stream, A));
+    NODE_K(false, false);
   }
+#undef NODE_K
   return hipGetLastError();
 }
 
@@ -1042,14 +1102,19 @@ hipError_t launch_edge_step(const RunArgs& a, int k, bool final_step) {
   A.seg_bytes = SegEdge{Hh, kPrecBytes[kp]}.size();
   A.seg2 = base + m.cls;
   A.seg2_bytes = SegCls{Hh, kPrecBytes[kp]}.size();
+  const bool gh = a.ctx->edge_products != 0;
+  // W_src and W_dst of edge net k as the node kernel holds them (node net k's
+  // segment, the node kernels' precision), so the products are the same bits
+  A.seg3 = seg_ptr(a, a.ctx->wmap[a.prec].node[k] + SegNode{Hh, kPrecBytes[a.prec]}.ws());
+  A.seg3_bytes = gh ? 2 * Hh * Hh * kPrecBytes[a.prec] : 0;
   A.step = k;
   const bool ol = !final_step && outsum_lds(a);
-  const size_t lds = A.seg_bytes + (final_step ? A.seg2_bytes : 0) + (ol ? outsum_lds_bytes(a) : 0);
+  const size_t lds = A.seg_bytes + A.seg3_bytes + (final_step ? A.seg2_bytes : 0) + (ol ? outsum_lds_bytes(a) : 0);
   const unsigned grid = (unsigned)(a.ctx->n_cu * a.ctx->edge_wg_per_cu);
   const int pipe = a.ctx->edge_pipeline;
   const bool wr = a.ctx->edge_wreg != 0;
   const void* fn = nullptr;
-#define STEP_K(H_, P_) edge_step_kernel<H_, P_>(final_step, pipe, wr, ol)
+#define STEP_K(H_, P_) edge_step_kernel<H_, P_>(final_step, pipe, wr, ol, gh)
   switch (Hh * 4 + kp) {
     case 32 * 4 + 0: fn = STEP_K(32, 0); break;
     case 32 * 4 + 1: fn = STEP_K(32, 1); break;
@@ -1086,12 +1151,15 @@ static void set_gnn_attr(int& bad, size_t max_lds) {
     bad |= hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) != hipSuccess;
   };
   set(reinterpret_cast<const void*>(k_node_encode<H, P>));
-  set(reinterpret_cast<const void*>(k_node_step<H, P, false>));
-  set(reinterpret_cast<const void*>(k_node_step<H, P, true>));
+  set(reinterpret_cast<const void*>(k_node_step<H, P, false, false>));
+  set(reinterpret_cast<const void*>(k_node_step<H, P, true, false>));
+  set(reinterpret_cast<const void*>(k_node_step<H, P, false, true>));
+  set(reinterpret_cast<const void*>(k_node_step<H, P, true, true>));
   for (int fin = 0; fin < 2; ++fin)
     for (int pipe = 0; pipe < 3; ++pipe)
       for (int wr = 0; wr < 2; ++wr)
-        for (int ol = 0; ol < 2; ++ol) set(edge_step_kernel<H, P>(fin, pipe, wr, ol));
+        for (int ol = 0; ol < 2; ++ol)
+          for (int gh = 0; gh < 2; ++gh) set(edge_step_kernel<H, P>(fin, pipe, wr, ol, gh));
   for (int pipe = 0; pipe < 3; ++pipe)
     for (int ol = 0; ol < 2; ++ol) set(edge_encode_kernel<H, P>(pipe, ol));
 }
@@ -1103,7 +1171,8 @@ static void set_split_attr(int& bad, size_t max_lds) {
   };
   for (int fin = 0; fin < 2; ++fin)
     for (int pipe = 0; pipe < 3; ++pipe)
-      for (int ol = 0; ol < 2; ++ol) set(edge_step_kernel<H, P_F32X>(fin, pipe, false, ol));
+      for (int ol = 0; ol < 2; ++ol)
+        for (int gh = 0; gh < 2; ++gh) set(edge_step_kernel<H, P_F32X>(fin, pipe, false, ol, gh));
   for (int pipe = 0; pipe < 3; ++pipe)
     for (int ol = 0; ol < 2; ++ol) set(edge_encode_kernel<H, P_F32X>(pipe, ol));
 }

@@ -407,6 +407,31 @@ def test_xcd_map_identical(wl, n, prec):
         assert np.array_equal(out[0][k], out[1][k]), k
 
 
+@pytest.mark.parametrize("wl,n,prec,split,fuse", [("c1", 3, 0, 0, 0), ("c3", 30, 0, 0, 1), ("c3", 30, 0, 1, 0),
+                                                  ("c2", 2, 0, 0, 0), ("c3", 30, 1, 0, 1), ("c2", 2, 1, 0, 0),
+                                                  ("c3", 30, 2, 0, 0)])
+def test_edge_products_identical(wl, n, prec, split, fuse):
+    """Node products formed in the edge kernel from gathered rows of h equal
+    the node kernel's stored products: same bits, every precision."""
+    etx = _etx()
+    w = synth.WORKLOADS[wl]
+    W = centred_weights(w)
+    batch = synth.generate_batch(w, n)
+    p = etx.Pipeline(w, W, precision=prec)
+    if prec == etx.ETX_FP8_E4M3:
+        p.calibrate(etx.to_device(synth.generate_batch(w, 4, seed_space=1000 + w.cid)))
+    etx.etx_set_option(p.ctx, etx.ETX_OPT_F32_SPLIT, split)
+    etx.etx_set_option(p.ctx, etx.ETX_OPT_FUSE_MESSAGES, fuse)
+    b = etx.to_device(batch)
+    out = {}
+    for m in (0, 1):
+        etx.etx_set_option(p.ctx, etx.ETX_OPT_EDGE_PRODUCTS, m)
+        p.run(b)
+        out[m] = p.results(b)
+    for k in ("src", "dst", "score", "labels", "edge_off"):
+        assert np.array_equal(out[0][k], out[1][k]), k
+
+
 def test_shuffled_hit_order_parity():
     """Hits in random order (no readout locality) give the same results."""
     w = synth.C3.with_(hit_order="shuffled")
