@@ -235,7 +235,8 @@ def main():
                                                                ("radius_sort_min", etx.ETX_OPT_RADIUS_SORT_MIN),
                                                                ("radius_fast", etx.ETX_OPT_RADIUS_FAST),
                                                                ("xcd_map", etx.ETX_OPT_XCD_MAP),
-                                                               ("edge_products", etx.ETX_OPT_EDGE_PRODUCTS))}
+                                                               ("edge_products", etx.ETX_OPT_EDGE_PRODUCTS),
+                                                               ("csc_place", etx.ETX_OPT_CSC_PLACE))}
         print(f"[bench] autotuned: {tuned}", file=sys.stderr, flush=True)
     if args.graph:
         etx.etx_set_option(p.ctx, etx.ETX_OPT_USE_GRAPH, 1)
@@ -283,7 +284,7 @@ def main():
         # the unpruned pipeline on the same batch: its throughput and efficiency are the reference
         p0 = calibrated(etx.Pipeline(w, weights, precision=prec))
         # the same launch schedule as the pruned pipeline (tuned or default)
-        for key in range(etx.ETX_OPT_EDGE_PRODUCTS + 1):
+        for key in range(etx.ETX_OPT_CSC_PLACE + 1):
             if key not in (etx.ETX_OPT_PROFILE,):
                 etx.etx_set_option(p0.ctx, key, etx.etx_get_option(p.ctx, key))
         with torch.cuda.stream(stream):

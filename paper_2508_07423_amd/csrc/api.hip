@@ -661,6 +661,10 @@ etx_status etx_set_option(etx_ctx* ctx, int32_t key, int64_t value) {
       if (value != 0 && value != 1) return ETX_ERR_INVALID_ARG;
       ctx->edge_products = (int)value;
       break;
+    case ETX_OPT_CSC_PLACE:
+      if (value != 0 && value != 1) return ETX_ERR_INVALID_ARG;
+      ctx->csc_place = (int)value;
+      break;
     default: return ETX_ERR_INVALID_ARG;
   }
   if (key != ETX_OPT_USE_GRAPH) clear_graphs(ctx);
@@ -720,6 +724,7 @@ etx_status etx_get_option(const etx_ctx* ctx, int32_t key, int64_t* value) {
     case ETX_OPT_RADIUS_FAST: *value = ctx->radius_fast; break;
     case ETX_OPT_XCD_MAP: *value = ctx->xcd_map; break;
     case ETX_OPT_EDGE_PRODUCTS: *value = ctx->edge_products; break;
+    case ETX_OPT_CSC_PLACE: *value = ctx->csc_place; break;
     case ETX_OPT_PROFILE: *value = ctx->profile; break;
     default: return ETX_ERR_INVALID_ARG;
   }
@@ -882,7 +887,7 @@ struct SaveHeader {
   int32_t calibrated, pf_set;
 };
 constexpr uint32_t kSaveMagic = 0x53585445;   // "ETXS"
-constexpr int kSavedOptions = 18;             // etx_option keys 0 .. 17
+constexpr int kSavedOptions = 19;             // etx_option keys 0 .. 18
 
 size_t save_bytes(const etx_ctx* ctx) {
   return sizeof(SaveHeader) + sizeof(etx_config) + sizeof(float) * (N_SCALES + 3 * ETX_PF_NPARAM) +

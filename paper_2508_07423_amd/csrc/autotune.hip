@@ -33,7 +33,7 @@ std::string join(const std::vector<int64_t>& v) {
 }
 
 // stage indices as listed by etx_stage_name
-constexpr int ST_RADIUS_COUNT = 4, ST_RADIUS_EMIT = 6, ST_NODE_ENC = 9, ST_EDGE_ENC = 10, ST_SEGSUM = 11,
+constexpr int ST_RADIUS_COUNT = 4, ST_RADIUS_EMIT = 6, ST_CSC = 8, ST_NODE_ENC = 9, ST_EDGE_ENC = 10, ST_SEGSUM = 11,
               ST_NODE_STEP = 12, ST_EDGE_STEP = 13, ST_EDGE_FINAL = 14;
 
 double timed_run(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void* ws, size_t ws_bytes, etx_stream stream,
@@ -73,6 +73,7 @@ extern "C" etx_status etx_autotune(etx_ctx* ctx, const etx_hits* hits, etx_out* 
       {{ETX_OPT_SEGSUM_UNROLL}, "segsum_unroll", {{1}, {2}, {4}, {8}}, {ST_SEGSUM}},
       {{ETX_OPT_RADIUS_SORT_MIN}, "radius_sort_min", {{256}, {512}, {1024}}, {ST_RADIUS_COUNT, ST_RADIUS_EMIT}},
       {{ETX_OPT_RADIUS_FAST}, "radius_fast", {{0}, {1}}, {ST_RADIUS_COUNT, ST_RADIUS_EMIT}},
+      {{ETX_OPT_CSC_PLACE}, "csc_place", {{0}, {1}}, {ST_CSC}},
   };
   const int prev_profile = ctx->profile, prev_graph = ctx->use_graph;
   ctx->profile = 1;

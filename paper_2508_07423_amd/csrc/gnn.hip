@@ -452,7 +452,7 @@ __global__ __launch_bounds__(NodeThreads<P>::value) void k_node_encode(GnnArgs A
   stage_bytes(w, A.seg, A.seg_bytes);
   __syncthreads();
   constexpr SegNodeEnc S{H, PrecBytes<P>::value};
-  const int lane = lane_id(), g = lane_group(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = lane_id(), g = lane_group(), wave = wave_id(), nw = blockDim.x >> 6;
   const float s_ne2 = asc(A, Q_NE2), s_h = asc(A, Q_H);
   const float o_ne2 = s_ne2 * wsc(A, SW_NE2), o_h = s_h * wsc(A, SW_EE1);
   const int64_t ntiles = (A.n_hits + kCols - 1) / kCols;
@@ -509,7 +509,7 @@ __global__ __launch_bounds__(512) void k_edge_encode(GnnArgs A) {
   stage_bytes(w, A.seg, A.seg_bytes);
   __syncthreads();
   constexpr SegEdgeEnc S{H, PrecBytes<P>::value};
-  const int lane = lane_id(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = lane_id(), wave = wave_id(), nw = blockDim.x >> 6;
   const float s_ee2 = asc(A, Q_EE2), o_ee2 = s_ee2 * wsc(A, SW_EE2);
   const float s_e0 = asc(A, Q_E + 0), inv_e0 = 1.0f / s_e0;
   const int64_t E = A.row_ptr[A.n_hits];
@@ -702,7 +702,7 @@ __global__ __launch_bounds__(NodeThreads<P>::value) void k_node_step(GnnArgs A) 
   stage_bytes(w, A.seg, A.seg_bytes);
   __syncthreads();
   constexpr SegNode S{H, PrecBytes<P>::value};
-  const int lane = lane_id(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = lane_id(), wave = wave_id(), nw = blockDim.x >> 6;
   const int k = A.step;
   const float s_h = asc(A, Q_H), s_mo = asc(A, Q_MO), s_mi = asc(A, Q_MI), s_nn2 = asc(A, Q_NN2);
   const float w1s = wsc(A, SW_STEP + 4 * k), w2s = wsc(A, SW_STEP + 4 * k + 1), wes = wsc(A, SW_STEP + 4 * k + 2);
@@ -782,7 +782,7 @@ __global__ __launch_bounds__(512) void k_edge_step(GnnArgs A) {
   if (FINAL) stage_bytes(w + off, A.seg2, A.seg2_bytes);
   __syncthreads();
   const char* wc = w + off;
-  const int lane = lane_id(), g = lane_group(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = lane_id(), g = lane_group(), wave = wave_id(), nw = blockDim.x >> 6;
   const int k = A.step;
   const float s_e = asc(A, Q_E + k), s_en2 = asc(A, Q_EN2), s_next = asc(A, Q_E + k + 1);
   const float w1s = wsc(A, SW_STEP + 4 * k + 2), w2s = wsc(A, SW_STEP + 4 * k + 3), wcs = wsc(A, SW_CLS1);

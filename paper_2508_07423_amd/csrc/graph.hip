@@ -195,12 +195,14 @@ __global__ void k_edge_off(const int64_t* __restrict__ hit_off, int64_t n_events
 // --------------------------------------------------------------------------
 
 // Long rows (at least kCscRowWalk edges per source on average) are placed a
-// row per step, short rows 64 edges per step; both keep (dst, src) order.
+// row per step by one wave; short rows by the whole block through LDS cursors
+// with a sort of every column afterwards (place = 1), or 64 edges per step by
+// one wave (place = 0).  All keep (dst, src) order.
 constexpr int kCscRowWalk = 16;
 
 __global__ __launch_bounds__(256) void k_csc(const int64_t* __restrict__ hit_off, const int64_t* __restrict__ row_ptr,
                                              const int32_t* __restrict__ dst, int64_t* __restrict__ col_ptr,
-                                             int32_t* __restrict__ csc, const int64_t* status) {
+                                             int32_t* __restrict__ csc, int place, const int64_t* status) {
   if (status[0] != 0) return;
   __shared__ int cur[ETX_MAX_EVENT_HITS];
   __shared__ int tmp[4];
@@ -226,6 +228,31 @@ __global__ __launch_bounds__(256) void k_csc(const int64_t* __restrict__ hit_off
   }
   if (t == 0) col_ptr[a + n] = ee;
   __syncthreads();
+  if (place && ee - eb < (int64_t)kCscRowWalk * n) {
+    // short rows, whole block: every thread drops its edges into their columns
+    // through the LDS cursors (any order within a column), then every column
+    // is sorted by edge index, which is source order (insertion sort: fewer
+    // than kCscRowWalk edges per column on average).
+    for (int64_t q = eb + t; q < ee; q += 256) {
+      const int pos = atomicAdd(&cur[dst[q] - (int)a], 1);
+      csc[eb + pos] = (int32_t)q;
+    }
+    __syncthreads();
+    for (int i = t; i < n; i += 256) {
+      const int64_t c0 = col_ptr[a + i], c1 = col_ptr[a + i + 1];
+      for (int64_t j = c0 + 1; j < c1; ++j) {
+        const int32_t v = csc[j];
+        int64_t k = j - 1;
+        for (; k >= c0; --k) {
+          const int32_t u = csc[k];
+          if (u < v) break;
+          csc[k + 1] = u;
+        }
+        csc[k + 1] = v;
+      }
+    }
+    return;
+  }
   if (t >= 64) return;
   if (ee - eb >= (int64_t)kCscRowWalk * n) {
     // one wave walks the rows in source order; the targets of one row are
@@ -420,7 +447,8 @@ hipError_t launch_scan_counts(const RunArgs& a, bool candidates) {
 hipError_t launch_csc(const RunArgs& a) {
   if (a.hits.n_events == 0) return hipSuccess;
   hipLaunchKernelGGL(k_csc, dim3((unsigned)a.hits.n_events), dim3(256), 0, a.stream, a.hits.hit_off,
-                     WS(a, row_ptr, int64_t), a.out.dst, WS(a, col_ptr, int64_t), WS(a, csc, int32_t), a.out.status);
+                     WS(a, row_ptr, int64_t), a.out.dst, WS(a, col_ptr, int64_t), WS(a, csc, int32_t),
+                     a.ctx->csc_place, a.out.status);
   return hipGetLastError();
 }
 

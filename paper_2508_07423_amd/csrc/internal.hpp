@@ -74,6 +74,7 @@ struct etx_ctx {
   int radius_fast = 0;             // select pass: 16-lane path for sources with few candidates
   int xcd_map = 0;                 // tile and node kernels: contiguous work per XCD
   int edge_products = 0;           // 1: edge kernels form the node-product terms from gathered h rows
+  int csc_place = 1;               // short-row CSC placed by the whole block, then columns sorted
   std::vector<char> blob;          // the weight blob as given (for etx_save)
   int use_graph = 0;
   std::map<etx::GraphKey, hipGraphExec_t> graphs;

@@ -29,6 +29,9 @@ __host__ __device__ constexpr int phi(int r, int g) { return 16 * (r / 4) + 4 * 
 
 __device__ inline int lane_id() { return threadIdx.x & 63; }
 __device__ inline int lane_group() { return (threadIdx.x & 63) >> 4; }
+// The wave's index in its workgroup, as a wave-uniform (scalar) value: tile
+// indices derived from it stay in scalar registers.
+__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // Load F features of a row-major [col][F] array into column layout (F/4 registers).
 template <int F>

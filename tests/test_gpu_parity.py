@@ -432,6 +432,30 @@ def test_edge_products_identical(wl, n, prec, split, fuse):
         assert np.array_equal(out[0][k], out[1][k]), k
 
 
+@pytest.mark.parametrize("wl,n,trained", [("c1", 3, False), ("c3", 12, False), ("c3", 30, True), ("c2", 2, False)])
+def test_csc_block_placement_identical(wl, n, trained):
+    """Short-row CSC columns filled by the whole block and then sorted equal
+    the one-wave ranking: same permutation, same outputs."""
+    etx = _etx()
+    w = synth.WORKLOADS[wl]
+    if trained and not os.path.exists(os.path.join(synth.TRAINED_DIR, f"{w.name}_trained.npz")):
+        pytest.skip("trained weights not built")
+    W = synth.trained_weights(w) if trained else centred_weights(w)
+    batch = synth.generate_batch(w, n)
+    p = etx.Pipeline(w, W)
+    b = etx.to_device(batch)
+    out, perm = {}, {}
+    for m in (0, 1):
+        etx.etx_set_option(p.ctx, etx.ETX_OPT_CSC_PLACE, m)
+        p.run(b)
+        out[m] = p.results(b)
+        perm[m] = p.view(b, etx.ETX_VIEW_CSC_EDGE, torch.int32).cpu().numpy()[:int(out[m]["edge_off"][-1])]
+    for m in (1,):
+        assert np.array_equal(perm[0], perm[m])
+        for k in ("src", "dst", "score", "labels", "edge_off"):
+            assert np.array_equal(out[0][k], out[m][k]), k
+
+
 def test_shuffled_hit_order_parity():
     """Hits in random order (no readout locality) give the same results."""
     w = synth.C3.with_(hit_order="shuffled")
