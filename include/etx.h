@@ -161,13 +161,13 @@ typedef enum {
   ETX_OPT_RADIUS_SINGLE_PASS = 12, /* 1 (default): the radius search selects each source's neighbours once into
                                       k_max workspace slots per hit and the CSR rows are copied after the scan;
                                       0: a count pass and an emit pass */
-  ETX_OPT_RADIUS_SORT_MIN = 13, /* staged candidate windows with at least this many hits are sorted along their
-                                   widest axis and searched as a cell list; smaller ones are scanned whole
-                                   (default 512; 0: always sort) */
+  ETX_OPT_RADIUS_SORT_MIN = 13, /* staged candidate windows with at least this many hits are binned along their
+                                   widest axis into cells about r wide and searched as a cell list; smaller ones
+                                   are scanned whole (default 512; 0: always bin) */
   ETX_OPT_FUSE_MESSAGES = 14,  /* 1: the node-update kernel gathers its messages itself (no separate message-sum
                                   kernel, no message buffer round trip); same sums, same order, same bits */
-  ETX_OPT_RADIUS_FAST = 15,    /* 1: in scanned (unsorted) windows, sources with at most 16 in-radius candidates are
-                                  handled four to a wave; the others by the one-wave-per-source path; same bits */
+  ETX_OPT_RADIUS_FAST = 15,    /* 1: in staged windows, sources with at most 16 in-radius candidates are handled four
+                                  to a wave; the others by the one-wave-per-source path; same bits */
   ETX_OPT_XCD_MAP = 16,        /* 1: the edge, message-sum and node kernels give each of the chip's eight XCDs a
                                   contiguous range of tiles, so that the node rows a region of the batch gathers stay
                                   in that XCD's L2; which tiles run is unchanged, same bits */

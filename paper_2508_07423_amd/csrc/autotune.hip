@@ -71,7 +71,7 @@ extern "C" etx_status etx_autotune(etx_ctx* ctx, const etx_hits* hits, etx_out* 
       {{ETX_OPT_NODE_WG_PER_CU}, "node_wg_per_cu", {{1}, {2}, {3}, {4}}, {ST_NODE_ENC, ST_NODE_STEP}},
       {{ETX_OPT_FUSE_MESSAGES}, "fuse_messages", {{0}, {1}}, {ST_SEGSUM, ST_NODE_STEP}},
       {{ETX_OPT_SEGSUM_UNROLL}, "segsum_unroll", {{1}, {2}, {4}, {8}}, {ST_SEGSUM}},
-      {{ETX_OPT_RADIUS_SORT_MIN}, "radius_sort_min", {{256}, {512}, {1024}}, {ST_RADIUS_COUNT, ST_RADIUS_EMIT}},
+      {{ETX_OPT_RADIUS_SORT_MIN}, "radius_sort_min", {{64}, {128}, {256}, {512}, {1024}}, {ST_RADIUS_COUNT, ST_RADIUS_EMIT}},
       {{ETX_OPT_RADIUS_FAST}, "radius_fast", {{0}, {1}}, {ST_RADIUS_COUNT, ST_RADIUS_EMIT}},
       {{ETX_OPT_CSC_PLACE}, "csc_place", {{0}, {1}}, {ST_CSC}},
   };

@@ -4,15 +4,16 @@
 // keeping at most k_max per source: the k_max smallest by (d^2, target index).
 //
 // One workgroup per (event, source plane).  The candidate window (hits of the
-// next planes) is staged in LDS and sorted along its widest embedding axis, a
-// one-dimensional cell list: a source only scans candidates whose coordinate
-// on that axis lies within r of its own, which is exact because a distance
-// below r bounds every coordinate difference.  Each wave handles one source
+// next planes) is staged in LDS and binned along its widest embedding axis into
+// cells about r wide (a counting sort), a one-dimensional cell list: a source
+// only scans the cells its coordinate on that axis reaches within r, which is
+// exact because a distance below r bounds every coordinate difference.  Sources
+// with few candidates are handled four to a wave; otherwise each wave handles one source
 // at a time: in-radius candidates are compacted into an LDS list with a wave
 // ballot and prefix count, the k_max boundary is found by a radix select on
 // the float bits of d^2 (ties at the boundary resolved by the target index), and
 // the kept targets are ranked by index and written as one CSR row.  Windows
-// larger than the LDS capacity are read from HBM without the sort.
+// larger than the LDS capacity are read from HBM without the cell list.
 #include "internal.hpp"
 
 namespace etx {
@@ -22,6 +23,7 @@ namespace {
 constexpr int kRadiusThreads = 512;     // 8 waves
 constexpr int kRadiusWaves = kRadiusThreads / 64;
 constexpr int kList = 256;              // per-wave list of in-radius candidates
+constexpr int kCells = 256;             // most cells of a window's cell list
 
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -83,8 +85,8 @@ __global__ __launch_bounds__(kRadiusThreads) void k_radius(RadiusArgs A) {
   extern __shared__ float lds[];
   float* cemb = lds;                                              // [CAP][DP]
   int* cj = reinterpret_cast<int*>(cemb + CAP * DP);              // [CAP] target hit index
-  float* skey = reinterpret_cast<float*>(cj + CAP);               // [CAP] sorted axis coordinate
-  int* sidx = reinterpret_cast<int*>(skey + CAP);                 // [CAP] slot of the sorted entry
+  float* skey = reinterpret_cast<float*>(cj + CAP);               // [CAP] cell ends, then hard sources
+  int* sidx = reinterpret_cast<int*>(skey + CAP);                 // [CAP] slots in cell order
   float* ld2 = reinterpret_cast<float*>(sidx + CAP);              // [waves][kList]
   int* lj = reinterpret_cast<int*>(ld2 + kRadiusWaves * kList);   // [waves][kList]
   int* sel = lj + kRadiusWaves * kList;                           // [waves][64]
@@ -106,11 +108,18 @@ __global__ __launch_bounds__(kRadiusThreads) void k_radius(RadiusArgs A) {
   }
   const int32_t* wb = A.bucket + a + w0;
   const bool staged = A.stage_window && nwin <= CAP;
-  // small windows are scanned whole: a few 64-wide passes cost less than the
-  // sort and the per-source searches
+  // windows of at least sort_min hits get a cell list along their widest axis
+  // and each source scans only the cells within reach; smaller ones are
+  // scanned whole
   const bool sorted = staged && nwin >= A.sort_min;
-  int npow = 1;
-  while (npow < nwin) npow <<= 1;
+  // cell list of a sorted window (in the key array's place): cend[k] ends up
+  // as the end of cell k in the slot order sidx
+  int* cend = reinterpret_cast<int*>(skey);
+  float cell_lo = 0.f, cell_inv = 0.f;
+  int ncell = 1;
+  auto cell_of = [&](float key) {
+    return min(ncell - 1, max(0, (int)((key - cell_lo) * cell_inv)));
+  };
   if (staged && !sorted) {
     for (int c = threadIdx.x; c < nwin; c += kRadiusThreads) {
       const int j = wb[c];
@@ -171,48 +180,87 @@ __global__ __launch_bounds__(kRadiusThreads) void k_radius(RadiusArgs A) {
         }
       }
       misc[0] = best;
+      float l = INFINITY, h = -INFINITY;
+      for (int w = 0; w < kRadiusWaves; ++w) {
+        l = fminf(l, ld2[w * DP + best]);
+        h = fmaxf(h, ld2[kRadiusWaves * DP + w * DP + best]);
+      }
+      misc[2] = __float_as_int(l);
+      misc[3] = __float_as_int(h);
     }
     __syncthreads();
+    // cell list along that axis: cells about r wide over the window's extent
+    // (at most kCells), counted, scanned and filled through LDS cursors.  The
+    // order inside a cell is arbitrary: what is kept below does not depend on
+    // the order in which candidates are visited.
     const int axis = misc[0];
-    for (int c = threadIdx.x; c < npow; c += kRadiusThreads) {
-      skey[c] = c < nwin ? cemb[c * DP + axis] : INFINITY;
-      sidx[c] = c;
-    }
+    cell_lo = __int_as_float(misc[2]);
+    const float width = __int_as_float(misc[3]) - cell_lo;
+    ncell = width > 0.f ? (int)fminf((float)kCells, width / A.r + 1.0f) : 1;
+    cell_inv = width > 0.f ? (float)ncell / width : 0.f;
+    for (int k = threadIdx.x; k < ncell; k += kRadiusThreads) hist[k] = 0;
     __syncthreads();
-    // bitonic sort of (key, slot) by key, then slot
-    for (int k = 2; k <= npow; k <<= 1) {
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int i = threadIdx.x; i < npow; i += kRadiusThreads) {
-          int ij = i ^ j;
-          if (ij > i) {
-            float ki = skey[i], kk = skey[ij];
-            int ii = sidx[i], ik = sidx[ij];
-            bool gt = ki > kk || (ki == kk && ii > ik);
-            bool up = (i & k) == 0;
-            if (gt == up) {
-              skey[i] = kk; skey[ij] = ki;
-              sidx[i] = ik; sidx[ij] = ii;
-            }
-          }
-        }
-        __syncthreads();
+    for (int c = threadIdx.x; c < nwin; c += kRadiusThreads) atomicAdd(&hist[cell_of(cemb[c * DP + axis])], 1);
+    __syncthreads();
+    if (wave == 0) {
+      // exclusive scan of the counts, four cells per lane
+      int v[kCells / 64], sum = 0;
+#pragma unroll
+      for (int i = 0; i < kCells / 64; ++i) {
+        const int k = lane * (kCells / 64) + i;
+        v[i] = k < ncell ? hist[k] : 0;
+        sum += v[i];
+      }
+      int incl = sum;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(incl, d);
+        if (lane >= d) incl += t;
+      }
+      int run = incl - sum;
+#pragma unroll
+      for (int i = 0; i < kCells / 64; ++i) {
+        const int k = lane * (kCells / 64) + i;
+        if (k < ncell) cend[k] = run;
+        run += v[i];
       }
     }
+    __syncthreads();
+    for (int c = threadIdx.x; c < nwin; c += kRadiusThreads) sidx[atomicAdd(&cend[cell_of(cemb[c * DP + axis])], 1)] = c;
+    __syncthreads();
   }
   const int axis = (sorted && nwin > 0) ? misc[0] : 0;
+  // candidate range [cb, ce) of a source on a sorted window: the cells that
+  // its axis coordinate +- reach falls in (reach covers the rounding of the
+  // coordinates and of d^2, so no candidate within r is missed)
+  auto range = [&](const float (&se)[DP], int& cb, int& ce) {
+    cb = 0;
+    ce = nwin;
+    if (sorted && nwin > 0) {
+      float sa = 0.f;
+#pragma unroll
+      for (int k = 0; k < DP; ++k)
+        if (k == axis) sa = se[k];
+      const float reach = A.r * (1.0f + 1.0f / 65536.0f) + fabsf(sa) * (1.0f / 1048576.0f) + 1e-30f;
+      const int clo = cell_of(sa - reach), chi = cell_of(sa + reach);
+      cb = clo > 0 ? cend[clo - 1] : 0;
+      ce = cend[chi];
+    }
+  };
   float* wl2 = ld2 + wave * kList;
   int* wlj = lj + wave * kList;
   int* sl = sel + wave * 64;
   int* hw = hist + wave * 256;
   const unsigned r2bits = __float_as_uint(A.r2);
 
-  // Fast path of the select pass over a scanned window: four sources per
-  // wave, one per 16-lane row.  A source with at most 16 in-radius candidates
-  // (and no k_max cut) is finished here: its targets, ranked by index, are
-  // exactly what the full path keeps.  Other sources go to a list (the slot
-  // array of the unsorted window) for the one-wave-per-source path below.
-  const bool fast = MODE == R_SELECT && A.fast && staged && !sorted && nsrc <= CAP;
-  int* hard = sidx;
+  // Fast path of the select pass over a staged window: four sources per wave,
+  // one per 16-lane row, each over its own candidate range.  A source with at
+  // most 16 in-radius candidates (and no k_max cut) is finished here: its
+  // targets, ranked by index, are exactly what the full path keeps.  Other
+  // sources go to a list (the slot array of a scanned window, the key array
+  // past the cell ends of a sorted one) for the one-wave-per-source path.
+  const bool fast = MODE == R_SELECT && A.fast && staged && nsrc <= (sorted ? CAP - kCells : CAP);
+  int* hard = sorted ? cend + kCells : sidx;
   int nwork = nsrc;
   if (fast) {
     if (threadIdx.x == 0) misc[1] = 0;
@@ -229,14 +277,21 @@ __global__ __launch_bounds__(kRadiusThreads) void k_radius(RadiusArgs A) {
         const float4 v = *reinterpret_cast<const float4*>(A.emb + (int64_t)i * kDpad + q);
         se[q] = v.x; se[q + 1] = v.y; se[q + 2] = v.z; se[q + 3] = v.w;
       }
+      int cb, ce;
+      range(se, cb, ce);
+      // the longest of the four ranges (rows hold one value each)
+      int len = live ? ce - cb : 0;
+      len = max(len, __shfl_xor(len, 16));
+      len = max(len, __shfl_xor(len, 32));
       int n = 0;
-      for (int c0 = 0; c0 < nwin; c0 += 16) {
-        const int c = c0 + l16;
+      for (int c0 = 0; c0 < len; c0 += 16) {
+        const int c = cb + c0 + l16;
         bool in = false;
         int j = 0;
-        if (live && c < nwin) {
-          j = cj[c];
-          in = dist2<DP>(se, cemb + c * DP) < A.r2;
+        if (live && c < ce) {
+          const int slot = sorted ? sidx[c] : c;
+          j = cj[slot];
+          in = dist2<DP>(se, cemb + slot * DP) < A.r2;
         }
         const uint32_t m = (uint32_t)(__ballot(in) >> (16 * sub)) & 0xffffu;
         if (in) {
@@ -285,30 +340,8 @@ __global__ __launch_bounds__(kRadiusThreads) void k_radius(RadiusArgs A) {
       for (int q = 0; q < DP / 4; ++q)
         e_next[q] = *reinterpret_cast<const float4*>(A.emb + (int64_t)i_next * kDpad + 4 * q);
     }
-    // candidate range [cb, ce)
-    int cb = 0, ce = nwin;
-    if (sorted && nwin > 0) {
-      float sa = 0.f;
-#pragma unroll
-      for (int k = 0; k < DP; ++k)
-        if (k == axis) sa = se[k];
-      // a candidate whose axis coordinate differs by more than `reach` cannot be
-      // inside r; the slack covers the rounding of the coordinates and of d^2
-      const float reach = A.r * (1.0f + 1.0f / 65536.0f) + fabsf(sa) * (1.0f / 1048576.0f) + 1e-30f;
-      const float klo = sa - reach, khi = sa + reach;
-      int lo = 0, hi = nwin;       // first key >= klo
-      while (lo < hi) {
-        int m = (lo + hi) >> 1;
-        if (skey[m] < klo) lo = m + 1; else hi = m;
-      }
-      cb = lo;
-      hi = nwin;                   // first key > khi
-      while (lo < hi) {
-        int m = (lo + hi) >> 1;
-        if (skey[m] <= khi) lo = m + 1; else hi = m;
-      }
-      ce = lo;
-    }
+    int cb, ce;
+    range(se, cb, ce);
     auto cand = [&](int c, int& j) -> float {
       if (staged) {
         const int slot = sorted ? sidx[c] : c;
@@ -513,17 +546,22 @@ __global__ __launch_bounds__(kRadiusThreads) void k_radius(RadiusArgs A) {
 
 // CSR rows from the select pass's slots: thread (source i, rank r) copies
 // slot r of source i when r is below its count.
-__global__ void k_slots_to_csr(const int32_t* __restrict__ slots, const int64_t* __restrict__ row_ptr, int64_t n_hits,
-                               int k_max, int32_t* __restrict__ src, int32_t* __restrict__ dst, const int64_t* status) {
+// One G-lane group per hit: lane j copies the hit's kept slots j, j + G, ...
+// into its CSR row (contiguous writes per row, no per-slot index division).
+template <int G>
+__global__ __launch_bounds__(256) void k_slots_to_csr(const int32_t* __restrict__ slots, const int64_t* __restrict__ row_ptr,
+                                                      int64_t n_hits, int k_max, int32_t* __restrict__ src,
+                                                      int32_t* __restrict__ dst, const int64_t* status) {
   if (status[0] != 0) return;
-  const int64_t total = n_hits * k_max;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = t / k_max;
-    const int r = (int)(t - i * k_max);
+  const int j = threadIdx.x % G;
+  const int64_t stride = (int64_t)gridDim.x * (blockDim.x / G);
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; i < n_hits; i += stride) {
     const int64_t b = row_ptr[i];
-    if (r < row_ptr[i + 1] - b) {
+    const int c = (int)(row_ptr[i + 1] - b);
+    const int32_t* s = slots + i * k_max;
+    for (int r = j; r < c; r += G) {
       src[b + r] = (int32_t)i;
-      dst[b + r] = slots[t];
+      dst[b + r] = s[r];
     }
   }
 }
@@ -534,13 +572,16 @@ hipError_t launch_slots_copy(const RunArgs& a, bool candidates) {
   const int64_t n = a.hits.n_hits;
   if (n == 0) return hipSuccess;
   const int k = a.ctx->cfg.k_max;
-  const int64_t total = n * k;
-  const unsigned grid = (unsigned)std::min<int64_t>((total + 255) / 256, (int64_t)a.ctx->n_cu * 32);
-  hipLaunchKernelGGL(k_slots_to_csr, dim3(grid), dim3(256), 0, a.stream,
-                     reinterpret_cast<const int32_t*>(a.ws + a.L.slots),
-                     reinterpret_cast<const int64_t*>(a.ws + (candidates ? a.L.pf_tmp : a.L.row_ptr)), n, k,
-                     candidates ? reinterpret_cast<int32_t*>(a.ws + a.L.cand_src) : a.out.src,
-                     candidates ? reinterpret_cast<int32_t*>(a.ws + a.L.cand_dst) : a.out.dst, a.out.status);
+  const int G = k > 32 ? 32 : 16;                        // lanes per hit
+  const unsigned grid = (unsigned)std::min<int64_t>((n * G + 255) / 256, (int64_t)a.ctx->n_cu * 32);
+  const int32_t* slots = reinterpret_cast<const int32_t*>(a.ws + a.L.slots);
+  const int64_t* rp = reinterpret_cast<const int64_t*>(a.ws + (candidates ? a.L.pf_tmp : a.L.row_ptr));
+  int32_t* s = candidates ? reinterpret_cast<int32_t*>(a.ws + a.L.cand_src) : a.out.src;
+  int32_t* d = candidates ? reinterpret_cast<int32_t*>(a.ws + a.L.cand_dst) : a.out.dst;
+  if (G == 32)
+    hipLaunchKernelGGL(k_slots_to_csr<32>, dim3(grid), dim3(256), 0, a.stream, slots, rp, n, k, s, d, a.out.status);
+  else
+    hipLaunchKernelGGL(k_slots_to_csr<16>, dim3(grid), dim3(256), 0, a.stream, slots, rp, n, k, s, d, a.out.status);
   return hipGetLastError();
 }
 
