@@ -128,7 +128,8 @@ typedef enum {
   ETX_VIEW_ROW_PTR = 3,      /* int64 [n_hits+1]: CSR by source hit (global edge positions) */
   ETX_VIEW_COL_PTR = 4,      /* int64 [n_hits+1]: CSC by target hit */
   ETX_VIEW_CSC_EDGE = 5,     /* int32 [edge_capacity]: edge ids sorted by (dst, src) */
-  ETX_VIEW_NODE_H = 6,       /* float [n_hits][H]: node encodings after the last step */
+  ETX_VIEW_NODE_H = 6,       /* [n_hits][H] node encodings after the last step: float (FP32 runs) or BF16
+                                bits, uint16 (BF16 and FP8 runs) */
   ETX_VIEW_KEPT_EDGE = 7,    /* int32 [edge_capacity]: kept edge ids, per event from edge_off[e] */
   ETX_VIEW_KEPT_COUNT = 8,   /* int32 [n_events]: kept edges per event */
   ETX_VIEW_CALIB = 9,        /* float [ETX_N_CALIB]: per-tensor amax (calibration observers) */

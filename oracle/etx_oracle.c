@@ -292,8 +292,10 @@ void oracle_radius_margins(int64_t n, const int32_t* plane, const double* emb, i
  *   6 edge-net layer-2 inputs         7 + k: edge encodings e_k, k = 0..S
  * Edge encodings are stored quantised (e_k <- q(e_k) after the encoder and
  * after every update) and enter the edge net and the classifier in that form;
- * the sums are taken in full precision over the stored values; h keeps a full
- * precision residual copy and is quantised where it enters a GEMM. */
+ * the sums are taken in full precision over the stored values.  The node
+ * encodings h are stored rounded to BF16 in both quantised modes (after the
+ * encoder and after every residual update) and are quantised again where they
+ * enter a GEMM (a no-op in qmode 1). */
 enum { Q_NE2 = 0, Q_H = 1, Q_MO = 2, Q_MI = 3, Q_EE2 = 4, Q_NN2 = 5, Q_EN2 = 6, Q_E = 7 };
 
 /* Parameter block order: node encoder (3->H->H), edge encoder (2H->H->H),
@@ -326,6 +328,7 @@ void oracle_gnn(int64_t n, const double* cart, int64_t E, const int32_t* src, co
       observe(amax, Q_NE2, tmp, H);
       linear(tmp, H, W2, b2, H, h + l * H, qmode, SC(Q_NE2), s2);
       layernorm_relu(h + l * H, H);
+      if (qmode) for (int c = 0; c < H; ++c) h[l * H + c] = qv(1, h[l * H + c], 1.0);
     }
     p = b2 + H;
   }
@@ -375,7 +378,7 @@ void oracle_gnn(int64_t n, const double* cart, int64_t E, const int32_t* src, co
         observe(amax, Q_NN2, tmp, H);
         linear(tmp, H, W2, b2, H, out, qmode, SC(Q_NN2), s2);
         layernorm_relu(out, H);
-        for (int c = 0; c < H; ++c) h[l * H + c] += out[c];
+        for (int c = 0; c < H; ++c) h[l * H + c] = qmode ? qv(1, h[l * H + c] + out[c], 1.0) : h[l * H + c] + out[c];
       }
       p = b2 + H;
     }

@@ -60,7 +60,7 @@ struct GnnArgs {
   const char* seg2;         // classifier segment (final edge step)
   const char* seg3;         // edge-side products: W_src then W_dst of edge net k, layer 1
   int seg_bytes, seg2_bytes, seg3_bytes;
-  float* h;                 // [n_hits][H]
+  float* h;                 // [n_hits][H] node encodings (BF16 bits in BF16 and FP8 runs)
   float* ps;                // [n_hits][H] h W_src (source product)
   float* pd;                // [n_hits][H] h W_dst (target product)
   float* msg;               // [n_hits][2H] (out-sum, in-sum)
@@ -94,6 +94,31 @@ __device__ inline void stage_bytes(char* dst, const char* src, int n) {
 // scale of an activation slot and of a weight slot
 __device__ inline float asc(const GnnArgs& A, int q) { return A.sc[SC_GNN + q]; }
 __device__ inline float wsc(const GnnArgs& A, int s) { return A.sc[s]; }
+
+// Node encodings h: FP32 rows in FP32 runs; BF16 rows (round to nearest even)
+// in the BF16 and FP8 runs, which keep node state like edge state, in the low
+// precision.  A store rounds the registers first, so that what a kernel goes
+// on computing with is what the next kernel reads.
+template <int P>
+constexpr bool kHalfH = P == P_BF16 || P == P_FP8;
+
+template <int H, int P>
+__device__ inline void load_h(float* x, const GnnArgs& A, int64_t col, bool valid) {
+  if constexpr (kHalfH<P>)
+    load_cols_bf16<H>(x, reinterpret_cast<const uint16_t*>(A.h) + col * H, valid);
+  else
+    load_cols<H>(x, A.h + col * H, valid);
+}
+
+template <int H, int P>
+__device__ inline void store_h(const GnnArgs& A, int64_t col, float* o, bool valid) {
+  if constexpr (kHalfH<P>) {
+    round_bf16_cols<H>(o);
+    store_cols_bf16<H>(reinterpret_cast<uint16_t*>(A.h) + col * H, o, valid);
+  } else {
+    store_cols<H>(A.h + col * H, o, valid);
+  }
+}
 
 // --------------------------------------------------------------------------
 // edge-encoding rows in the operand format
@@ -167,15 +192,29 @@ __device__ inline void decode_e(float* ef, const RawE<P, H>& r, float scale) {
 template <int H>
 struct NodeRows { float4 s[H / 16], d[H / 16]; };
 
-template <int H>
+// HB: the rows are BF16 node encodings (8 bytes per lane group and block).
+template <int H, bool HB = false>
 __device__ inline void fetch_rows(NodeRows<H>& n, const float* ps, const float* pd, int src, int dst) {
   const int g = lane_group();
-  const float4* rs = reinterpret_cast<const float4*>(ps + (int64_t)src * H);
-  const float4* rd = reinterpret_cast<const float4*>(pd + (int64_t)dst * H);
+  if constexpr (HB) {
+    const uint2* rs = reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(ps) + (int64_t)src * H);
+    const uint2* rd = reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(pd) + (int64_t)dst * H);
+    auto f4 = [](uint2 v) {
+      return make_float4(bf16_value(v.x & 0xffffu), bf16_value(v.x >> 16), bf16_value(v.y & 0xffffu), bf16_value(v.y >> 16));
+    };
 #pragma unroll
-  for (int c = 0; c < H / 16; ++c) {
-    n.s[c] = rs[4 * c + g];
-    n.d[c] = rd[4 * c + g];
+    for (int c = 0; c < H / 16; ++c) {
+      n.s[c] = f4(rs[4 * c + g]);
+      n.d[c] = f4(rd[4 * c + g]);
+    }
+  } else {
+    const float4* rs = reinterpret_cast<const float4*>(ps + (int64_t)src * H);
+    const float4* rd = reinterpret_cast<const float4*>(pd + (int64_t)dst * H);
+#pragma unroll
+    for (int c = 0; c < H / 16; ++c) {
+      n.s[c] = rs[4 * c + g];
+      n.d[c] = rd[4 * c + g];
+    }
   }
 }
 
@@ -215,7 +254,9 @@ struct TileIdx {
   int s, d, before, after;
 };
 
-template <int P, int H, int PIPE>
+// HB: the gathered node rows are BF16 node encodings (edge-side products in
+// the low-precision runs), else FP32 product rows.
+template <int P, int H, int PIPE, bool HB = false>
 struct EdgeFeed {
   const int32_t* src;
   const int32_t* dst;
@@ -249,7 +290,7 @@ struct EdgeFeed {
       idx(t, i0);
     }
     if (want_e) fetch_e<P, H>(raw, e, clamped(t));
-    if constexpr (PIPE == 2) fetch_rows<H>(rows, ps, pd, i0.s, i0.d);
+    if constexpr (PIPE == 2) fetch_rows<H, HB>(rows, ps, pd, i0.s, i0.d);
   }
   __device__ void start(int64_t t) {
     if constexpr (PIPE == 2) idx(t, i1);
@@ -262,11 +303,11 @@ struct EdgeFeed {
     if constexpr (PIPE == 0) {
       fetch(t);
       r = raw;
-      fetch_rows<H>(n, ps, pd, i0.s, i0.d);
+      fetch_rows<H, HB>(n, ps, pd, i0.s, i0.d);
       x = i0;
     } else if constexpr (PIPE == 1) {
       r = raw;
-      fetch_rows<H>(n, ps, pd, i0.s, i0.d);
+      fetch_rows<H, HB>(n, ps, pd, i0.s, i0.d);
       x = i0;
       fetch(t + stride);
     } else {
@@ -482,7 +523,7 @@ __global__ __launch_bounds__(NodeThreads<P>::value) void k_node_encode(GnnArgs A
     bias_cols<H>(hh, reinterpret_cast<const float*>(w + S.b2()));
     gemm<P, H, H / 16>(hh, a, w + S.w2(), 1.0f / s_ne2, o_ne2);
     ln_relu<H>(hh);
-    store_cols<H>(A.h + col * H, hh, valid);
+    store_h<H, P>(A, col, hh, valid);
     observe<H / 4>(A.calib, SC_GNN + Q_H, hh, valid);
     float q[H / 4];
 #pragma unroll
@@ -711,7 +752,7 @@ __global__ __launch_bounds__(NodeThreads<P>::value) void k_node_step(GnnArgs A) 
     const int64_t col = tile * kCols + (lane & 15);
     const bool valid = col < A.n_hits;
     float x[3 * H / 4];
-    load_cols<H>(x, A.h + col * H, valid);
+    load_h<H, P>(x, A, col, valid);
     if constexpr (FUSE) {
       gather_messages<H, P>(A, col, valid, x + H / 4, x + H / 2);
     } else {
@@ -740,7 +781,7 @@ __global__ __launch_bounds__(NodeThreads<P>::value) void k_node_step(GnnArgs A) 
     ln_relu<H>(o);
 #pragma unroll
     for (int r = 0; r < H / 4; ++r) o[r] += x[r];
-    store_cols<H>(A.h + col * H, o, valid);
+    store_h<H, P>(A, col, o, valid);
     observe<H / 4>(A.calib, SC_GNN + Q_H, o, valid);
     if constexpr (NP) {
       float q[H / 4];
@@ -789,7 +830,7 @@ __global__ __launch_bounds__(512) void k_edge_step(GnnArgs A) {
   const int64_t E = A.row_ptr[A.n_hits];
   const int64_t ntiles = (E + kCols - 1) / kCols;
   const int64_t stride = (int64_t)gridDim.x * nw;
-  EdgeFeed<P, H, PIPE> feed{A.src, A.dst, A.e, GH ? A.h : A.ps, GH ? A.h : A.pd, E, stride, lane & 15};
+  EdgeFeed<P, H, PIPE, GH && kHalfH<P>> feed{A.src, A.dst, A.e, GH ? A.h : A.ps, GH ? A.h : A.pd, E, stride, lane & 15};
   feed.want_e = true;
   static_assert(!WR || P == P_F32, "register-resident weights are FP32 only");
   float wr_e[WR ? H * H / 64 : 1], wr_2[WR ? H * H / 64 : 1];

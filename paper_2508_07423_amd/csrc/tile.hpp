@@ -225,6 +225,38 @@ __device__ inline float e4m3_decode(uint32_t c) { return e4m3_byte<0>(c); }
 __device__ inline uint32_t bf16_bits(float x) { return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)x); }
 __device__ inline float bf16_value(uint32_t b) { return __uint_as_float(b << 16); }
 
+// Node rows stored as BF16 (the low-precision runs keep node encodings so):
+// lane group g holds features 16c + 4g .. 16c + 4g + 3, eight bytes per block.
+template <int F>
+__device__ inline void load_cols_bf16(float* a, const uint16_t* __restrict__ row, bool valid) {
+  const int g = lane_group();
+#pragma unroll
+  for (int c = 0; c < F / 16; ++c) {
+    const uint2 v = valid ? *reinterpret_cast<const uint2*>(row + 16 * c + 4 * g) : make_uint2(0u, 0u);
+    a[4 * c + 0] = bf16_value(v.x & 0xffffu);
+    a[4 * c + 1] = bf16_value(v.x >> 16);
+    a[4 * c + 2] = bf16_value(v.y & 0xffffu);
+    a[4 * c + 3] = bf16_value(v.y >> 16);
+  }
+}
+
+template <int F>
+__device__ inline void store_cols_bf16(uint16_t* __restrict__ row, const float* a, bool valid) {
+  const int g = lane_group();
+  if (!valid) return;
+#pragma unroll
+  for (int c = 0; c < F / 16; ++c)
+    *reinterpret_cast<uint2*>(row + 16 * c + 4 * g) =
+        make_uint2(bf16_bits(a[4 * c]) | (bf16_bits(a[4 * c + 1]) << 16), bf16_bits(a[4 * c + 2]) | (bf16_bits(a[4 * c + 3]) << 16));
+}
+
+// The values a BF16 store keeps (round to nearest even).
+template <int F>
+__device__ inline void round_bf16_cols(float* a) {
+#pragma unroll
+  for (int r = 0; r < F / 4; ++r) a[r] = bf16_value(bf16_bits(a[r]));
+}
+
 // FP8 operands, K-steps of 32: lane group g supplies registers 8t..8t+7 as
 // codes of x * inv_s; w holds 8 codes per lane per step (same order as BF16).
 // acc += out_scale * (W_q^T x_q).
