@@ -172,10 +172,11 @@ typedef enum {
   ETX_OPT_XCD_MAP = 16,        /* 1: the edge, message-sum and node kernels give each of the chip's eight XCDs a
                                   contiguous range of tiles, so that the node rows a region of the batch gathers stay
                                   in that XCD's L2; which tiles run is unchanged, same bits */
-  ETX_OPT_EDGE_PRODUCTS = 17,  /* 0 (default): the node update also writes h W_src and h W_dst per node (layer 1 of
-                                  the edge net split by input block) and the edge update gathers them; 1: the edge
-                                  update gathers the rows of h and forms the same products itself, and the node
-                                  update writes none (less HBM traffic, 2H^2 more multiply-adds per edge; same bits) */
+  ETX_OPT_EDGE_PRODUCTS = 17,  /* 0 (default): the node encoder and the node update also write h W_src and h W_dst per
+                                  node (layer 1 of the edge encoder / edge net split by input block) and the edge
+                                  kernels gather them; 1: the edge kernels gather the rows of h and form the same
+                                  products themselves, and the node kernels write none (less HBM traffic, 2H^2 more
+                                  multiply-adds per edge; same bits) */
   ETX_OPT_CSC_PLACE = 18       /* 1 (default): for events with short rows (< 16 edges per hit) the whole block drops
                                   the edges into their CSC columns through LDS cursors and then sorts every column by
                                   edge index (source order); 0: one wave ranks 64 edges at a time; same permutation */

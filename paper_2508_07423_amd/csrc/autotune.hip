@@ -65,7 +65,7 @@ extern "C" etx_status etx_autotune(etx_ctx* ctx, const etx_hits* hits, etx_out* 
        {{512, 1}, {512, 2}, {512, 3}, {512, 4}, {256, 2}, {256, 3}, {256, 4}, {256, 5}, {256, 6}, {256, 8}},
        edge_stages},
       {{ETX_OPT_EDGE_PRODUCTS}, "edge_products", {{0}, {1}},
-       {ST_EDGE_STEP, ST_EDGE_FINAL, ST_NODE_STEP}},
+       {ST_NODE_ENC, ST_EDGE_ENC, ST_EDGE_STEP, ST_EDGE_FINAL, ST_NODE_STEP}},
       {{ETX_OPT_EDGE_PIPELINE}, "edge_pipeline", {{0}, {1}, {2}}, edge_stages},
       {{ETX_OPT_XCD_MAP}, "xcd_map", {{0}, {1}}, {ST_EDGE_ENC, ST_EDGE_STEP, ST_EDGE_FINAL, ST_SEGSUM, ST_NODE_STEP}},
       {{ETX_OPT_NODE_WG_PER_CU}, "node_wg_per_cu", {{1}, {2}, {3}, {4}}, {ST_NODE_ENC, ST_NODE_STEP}},

@@ -485,7 +485,9 @@ __device__ inline void out_sums_lds(const GnnArgs& A, int64_t tile, const TileId
 template <int P>
 struct NodeThreads { static constexpr int value = P == P_F32 ? 1024 : 512; };
 
-template <int H, int P>
+// NP: also write the edge encoder's node products (else the edge encoder forms
+// them from the gathered rows of h).
+template <int H, int P, bool NP>
 __global__ __launch_bounds__(NodeThreads<P>::value) void k_node_encode(GnnArgs A) {
   if (A.status[0] != 0) return;
   extern __shared__ float lds[];
@@ -525,15 +527,17 @@ __global__ __launch_bounds__(NodeThreads<P>::value) void k_node_encode(GnnArgs A
     ln_relu<H>(hh);
     store_h<H, P>(A, col, hh, valid);
     observe<H / 4>(A.calib, SC_GNN + Q_H, hh, valid);
-    float q[H / 4];
+    if constexpr (NP) {
+      float q[H / 4];
 #pragma unroll
-    for (int r = 0; r < H / 4; ++r) q[r] = 0.f;
-    gemm<P, H, H / 16>(q, hh, w + S.ws(), 1.0f / s_h, o_h);
-    store_cols<H>(A.ps + col * H, q, valid);
+      for (int r = 0; r < H / 4; ++r) q[r] = 0.f;
+      gemm<P, H, H / 16>(q, hh, w + S.ws(), 1.0f / s_h, o_h);
+      store_cols<H>(A.ps + col * H, q, valid);
 #pragma unroll
-    for (int r = 0; r < H / 4; ++r) q[r] = 0.f;
-    gemm<P, H, H / 16>(q, hh, w + S.wd(), 1.0f / s_h, o_h);
-    store_cols<H>(A.pd + col * H, q, valid);
+      for (int r = 0; r < H / 4; ++r) q[r] = 0.f;
+      gemm<P, H, H / 16>(q, hh, w + S.wd(), 1.0f / s_h, o_h);
+      store_cols<H>(A.pd + col * H, q, valid);
+    }
   }
 }
 
@@ -542,12 +546,18 @@ __global__ __launch_bounds__(NodeThreads<P>::value) void k_node_encode(GnnArgs A
 // --------------------------------------------------------------------------
 // OL (H = 64): out-sums through an LDS transpose instead of the DPP scan; the
 // wave buffers follow the weight segment in LDS.
-template <int H, int P, int PIPE, bool OL>
+// GH: the node products of layer 1 are formed here from the gathered rows of
+// h (the node encoder's weights, precision and order: the same bits), and the
+// node encoder writes none.
+template <int H, int P, int PIPE, bool OL, bool GH>
 __global__ __launch_bounds__(512) void k_edge_encode(GnnArgs A) {
   if (A.status[0] != 0) return;
   extern __shared__ float lds[];
   char* w = reinterpret_cast<char*>(lds);
   stage_bytes(w, A.seg, A.seg_bytes);
+  const char* wp = w + A.seg_bytes;                    // W_src, W_dst (GH)
+  const int off = A.seg_bytes + (GH ? A.seg3_bytes : 0);
+  if (GH) stage_bytes(w + A.seg_bytes, A.seg3, A.seg3_bytes);
   __syncthreads();
   constexpr SegEdgeEnc S{H, PrecBytes<P>::value};
   const int lane = lane_id(), wave = wave_id(), nw = blockDim.x >> 6;
@@ -556,7 +566,7 @@ __global__ __launch_bounds__(512) void k_edge_encode(GnnArgs A) {
   const int64_t E = A.row_ptr[A.n_hits];
   const int64_t ntiles = (E + kCols - 1) / kCols;
   const int64_t stride = (int64_t)gridDim.x * nw;
-  EdgeFeed<P, H, PIPE> feed{A.src, A.dst, nullptr, A.ps, A.pd, E, stride, lane & 15};
+  EdgeFeed<P, H, PIPE, GH && kHalfH<P>> feed{A.src, A.dst, nullptr, GH ? A.h : A.ps, GH ? A.h : A.pd, E, stride, lane & 15};
   feed.want_e = false;
   int64_t tile = logical_block(A) * nw + wave;
   if (tile < ntiles) feed.start(tile);
@@ -570,7 +580,25 @@ __global__ __launch_bounds__(512) void k_edge_encode(GnnArgs A) {
     feed.next(tile, unused, rows, ti, key);
     float a[H / 4];
     bias_cols<H>(a, reinterpret_cast<const float*>(w + S.b1()));
-    add_rows<H>(a, rows);
+    if constexpr (GH) {
+      constexpr int PP = P == P_F32X ? P_F32 : P;
+      const float s_h = asc(A, Q_H), o_h = s_h * wsc(A, SW_EE1);
+      float x[H / 4], q[H / 4];
+      rows_cols<H>(x, rows.s);
+#pragma unroll
+      for (int r = 0; r < H / 4; ++r) q[r] = 0.f;
+      gemm<PP, H, H / 16>(q, x, wp, 1.0f / s_h, o_h);
+#pragma unroll
+      for (int r = 0; r < H / 4; ++r) a[r] += q[r];
+      rows_cols<H>(x, rows.d);
+#pragma unroll
+      for (int r = 0; r < H / 4; ++r) q[r] = 0.f;
+      gemm<PP, H, H / 16>(q, x, wp + H * H * PrecBytes<PP>::value, 1.0f / s_h, o_h);
+#pragma unroll
+      for (int r = 0; r < H / 4; ++r) a[r] += q[r];
+    } else {
+      add_rows<H>(a, rows);
+    }
     ln_relu<H>(a);
     observe<H / 4>(A.calib, SC_GNN + Q_EE2, a, valid);
     float o[H / 4];
@@ -580,7 +608,7 @@ __global__ __launch_bounds__(512) void k_edge_encode(GnnArgs A) {
     observe<H / 4>(A.calib, SC_GNN + Q_E, o, valid);
     store_e<P, H>(A.e, col, o, valid, inv_e0, s_e0, o);
     if constexpr (OL)
-      out_sums_lds<H>(A, tile, ti, key, o, reinterpret_cast<float*>(w + A.seg_bytes) + wave * kOutBufFloats);
+      out_sums_lds<H>(A, tile, ti, key, o, reinterpret_cast<float*>(w + off) + wave * kOutBufFloats);
     else
       out_sums<H>(A, tile, ti, key, o);
   }
@@ -993,20 +1021,26 @@ hipError_t launch_node_encode(const RunArgs& a) {
   A.seg = seg_ptr(a, m.node_enc);
   A.seg_bytes = SegNodeEnc{Hh, kPrecBytes[a.prec]}.size();
   unsigned grid = node_grid(a, a.ctx->node_wg_per_cu);
-  DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_node_encode<H, P>), dim3(grid), dim3(node_threads(P)), A.seg_bytes, a.stream, A));
+  if (a.ctx->edge_products) {
+    DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_node_encode<H, P, false>), dim3(grid), dim3(node_threads(P)), A.seg_bytes, a.stream, A));
+  } else {
+    DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_node_encode<H, P, true>), dim3(grid), dim3(node_threads(P)), A.seg_bytes, a.stream, A));
+  }
   return hipGetLastError();
 }
 
 // The edge-kernel instantiation for a run-time launch schedule (also used to
 // set the LDS attribute of every instantiation once).
 template <int H, int P>
-static const void* edge_encode_kernel(int pipe, bool ol) {
+static const void* edge_encode_kernel(int pipe, bool ol, bool gh) {
   auto pick = [&](auto PI) -> const void* {
     constexpr int pi = decltype(PI)::value;
     if constexpr (H == 64) {
-      if (ol) return reinterpret_cast<const void*>(k_edge_encode<H, P, pi, true>);
+      if (ol) return gh ? reinterpret_cast<const void*>(k_edge_encode<H, P, pi, true, true>)
+                        : reinterpret_cast<const void*>(k_edge_encode<H, P, pi, true, false>);
     }
-    return reinterpret_cast<const void*>(k_edge_encode<H, P, pi, false>);
+    return gh ? reinterpret_cast<const void*>(k_edge_encode<H, P, pi, false, true>)
+              : reinterpret_cast<const void*>(k_edge_encode<H, P, pi, false, false>);
   };
   switch (pipe) {
     case 0: return pick(std::integral_constant<int, 0>{});
@@ -1067,12 +1101,16 @@ hipError_t launch_edge_encode(const RunArgs& a) {
   const WeightMap& m = a.ctx->wmap[kp];
   A.seg = static_cast<const char*>(a.ctx->seg_base[kp]) + m.edge_enc;
   A.seg_bytes = SegEdgeEnc{Hh, kPrecBytes[kp]}.size();
+  const bool gh = a.ctx->edge_products != 0;
+  // the node encoder's W_src and W_dst (its segment, its precision)
+  A.seg3 = seg_ptr(a, a.ctx->wmap[a.prec].node_enc + SegNodeEnc{Hh, kPrecBytes[a.prec]}.ws());
+  A.seg3_bytes = gh ? 2 * Hh * Hh * kPrecBytes[a.prec] : 0;
   const unsigned grid = (unsigned)(a.ctx->n_cu * a.ctx->edge_wg_per_cu);
-  const size_t lds = A.seg_bytes + outsum_lds_bytes(a);
+  const size_t lds = A.seg_bytes + A.seg3_bytes + outsum_lds_bytes(a);
   const int pipe = a.ctx->edge_pipeline;
   const bool ol = outsum_lds(a);
   const void* fn = nullptr;
-#define ENC_K(H_, P_) edge_encode_kernel<H_, P_>(pipe, ol)
+#define ENC_K(H_, P_) edge_encode_kernel<H_, P_>(pipe, ol, gh)
   switch (Hh * 4 + kp) {
     case 32 * 4 + 0: fn = ENC_K(32, 0); break;
     case 32 * 4 + 1: fn = ENC_K(32, 1); break;
@@ -1191,7 +1229,8 @@ static void set_gnn_attr(int& bad, size_t max_lds) {
   auto set = [&](const void* f) {
     bad |= hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) != hipSuccess;
   };
-  set(reinterpret_cast<const void*>(k_node_encode<H, P>));
+  set(reinterpret_cast<const void*>(k_node_encode<H, P, false>));
+  set(reinterpret_cast<const void*>(k_node_encode<H, P, true>));
   set(reinterpret_cast<const void*>(k_node_step<H, P, false, false>));
   set(reinterpret_cast<const void*>(k_node_step<H, P, true, false>));
   set(reinterpret_cast<const void*>(k_node_step<H, P, false, true>));
@@ -1202,7 +1241,8 @@ static void set_gnn_attr(int& bad, size_t max_lds) {
         for (int ol = 0; ol < 2; ++ol)
           for (int gh = 0; gh < 2; ++gh) set(edge_step_kernel<H, P>(fin, pipe, wr, ol, gh));
   for (int pipe = 0; pipe < 3; ++pipe)
-    for (int ol = 0; ol < 2; ++ol) set(edge_encode_kernel<H, P>(pipe, ol));
+    for (int ol = 0; ol < 2; ++ol)
+      for (int gh = 0; gh < 2; ++gh) set(edge_encode_kernel<H, P>(pipe, ol, gh));
 }
 
 template <int H>
@@ -1215,7 +1255,8 @@ static void set_split_attr(int& bad, size_t max_lds) {
       for (int ol = 0; ol < 2; ++ol)
         for (int gh = 0; gh < 2; ++gh) set(edge_step_kernel<H, P_F32X>(fin, pipe, false, ol, gh));
   for (int pipe = 0; pipe < 3; ++pipe)
-    for (int ol = 0; ol < 2; ++ol) set(edge_encode_kernel<H, P_F32X>(pipe, ol));
+    for (int ol = 0; ol < 2; ++ol)
+      for (int gh = 0; gh < 2; ++gh) set(edge_encode_kernel<H, P_F32X>(pipe, ol, gh));
 }
 
 int gnn_attributes(size_t max_lds) {
