@@ -666,6 +666,7 @@ __global__ __launch_bounds__(256) void k_segsum(GnnArgs A) {
     // kernel; a longer row is its tile partials, first tile's slot 1 then
     // slot 0 of each later tile
     const int64_t rb = live ? A.row_ptr[node] : 0, re = live ? A.row_ptr[node + 1] : 0;
+    const int64_t cb = live ? A.col_ptr[node] : 0, ce = live ? A.col_ptr[node + 1] : 0;   // issued with rb, re
     const int64_t t0 = rb / kCols, t1 = re > rb ? (re - 1) / kCols : t0;
     if (live && (re == rb || t1 > t0)) {
       float mo[OPL];
@@ -687,7 +688,6 @@ __global__ __launch_bounds__(256) void k_segsum(GnnArgs A) {
     float mi[FPL];
 #pragma unroll
     for (int x = 0; x < FPL; ++x) mi[x] = 0.f;
-    const int64_t cb = live ? A.col_ptr[node] : 0, ce = live ? A.col_ptr[node + 1] : 0;
     for (int64_t t = cb; t < ce; t += U) {
       int id[U];
 #pragma unroll
@@ -722,7 +722,13 @@ __device__ inline void gather_messages(const GnnArgs& A, int64_t node, bool vali
 #pragma unroll
   for (int r = 0; r < H / 4; ++r) mo[r] = mi[r] = 0.f;
   if (!valid) return;
+  // both index pairs, then the first in-edge ids, are issued before anything
+  // that depends on them, so the out-sum and in-sum chains overlap
   const int64_t rb = A.row_ptr[node], re = A.row_ptr[node + 1];
+  const int64_t cb = A.col_ptr[node], ce = A.col_ptr[node + 1];
+  int id0[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) id0[u] = cb + u < ce ? A.csc[cb + u] : -1;
   if (re > rb) {
     const int64_t t0 = rb / kCols, t1 = (re - 1) / kCols;
     if (t0 == t1) {
@@ -731,12 +737,11 @@ __device__ inline void gather_messages(const GnnArgs& A, int64_t node, bool vali
       for (int64_t i = 0; i <= t1 - t0; ++i) add_cols<H>(mo, A.opart + ((t0 + i) * 2 + (i == 0 ? 1 : 0)) * H, true);
     }
   }
-  const int64_t cb = A.col_ptr[node], ce = A.col_ptr[node + 1];
   for (int64_t t = cb; t < ce; t += U) {
     RawE<P, H> raw[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int id = t + u < ce ? A.csc[t + u] : -1;
+      const int id = t == cb ? id0[u] : (t + u < ce ? A.csc[t + u] : -1);
       if (id >= 0) fetch_e<P, H>(raw[u], A.e, id);
       else
 #pragma unroll
