@@ -716,19 +716,44 @@ __global__ __launch_bounds__(256) void k_segsum(GnnArgs A) {
 // group g of a column holds features phi(r, g), which are exactly its chunks
 // of every stored edge row, so the in-sum needs no rearrangement; the out-sum
 // comes from the edge kernel's whole-row write or its tile partials.
+// Rows of in-edges in flight per node (register budget).
 template <int H, int P>
-__device__ inline void gather_messages(const GnnArgs& A, int64_t node, bool valid, float* mo, float* mi) {
-  constexpr int U = (StorePrec<P>::value == P_F32 && H == 64) ? 1 : 4;   // rows in flight (register budget)
+constexpr int kGatherU = (StorePrec<P>::value == P_F32 && H == 64) ? 1 : 4;
+
+// A node's message indices: its CSR and CSC ranges and its first in-edge ids.
+template <int H, int P>
+struct MsgIdx {
+  int64_t rb = 0, re = 0, cb = 0, ce = 0;
+  int id0[kGatherU<H, P>];
+};
+
+// All index loads of a node at once (nothing here depends on another load
+// but the ids on the CSC range), so that they can be issued a tile ahead.
+template <int H, int P>
+__device__ inline void fetch_msg_idx(const GnnArgs& A, int64_t node, bool valid, MsgIdx<H, P>& m) {
+  constexpr int U = kGatherU<H, P>;
+  m.rb = m.re = m.cb = m.ce = 0;
+  if (valid) {
+    m.rb = A.row_ptr[node];
+    m.re = A.row_ptr[node + 1];
+    m.cb = A.col_ptr[node];
+    m.ce = A.col_ptr[node + 1];
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) m.id0[u] = m.cb + u < m.ce ? A.csc[m.cb + u] : -1;
+}
+
+// Messages of a node gathered in the node kernel: the out-sum from the edge
+// kernels' tile partials (as k_segsum), the in-sum over the CSC rows in CSC
+// order, so the sums are bit-identical to k_segsum's.
+template <int H, int P>
+__device__ inline void gather_messages(const GnnArgs& A, int64_t node, bool valid, const MsgIdx<H, P>& m, float* mo,
+                                       float* mi) {
+  constexpr int U = kGatherU<H, P>;
 #pragma unroll
   for (int r = 0; r < H / 4; ++r) mo[r] = mi[r] = 0.f;
   if (!valid) return;
-  // both index pairs, then the first in-edge ids, are issued before anything
-  // that depends on them, so the out-sum and in-sum chains overlap
-  const int64_t rb = A.row_ptr[node], re = A.row_ptr[node + 1];
-  const int64_t cb = A.col_ptr[node], ce = A.col_ptr[node + 1];
-  int id0[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) id0[u] = cb + u < ce ? A.csc[cb + u] : -1;
+  const int64_t rb = m.rb, re = m.re, cb = m.cb, ce = m.ce;
   if (re > rb) {
     const int64_t t0 = rb / kCols, t1 = (re - 1) / kCols;
     if (t0 == t1) {
@@ -741,7 +766,7 @@ __device__ inline void gather_messages(const GnnArgs& A, int64_t node, bool vali
     RawE<P, H> raw[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int id = t == cb ? id0[u] : (t + u < ce ? A.csc[t + u] : -1);
+      const int id = t == cb ? m.id0[u] : (t + u < ce ? A.csc[t + u] : -1);
       if (id >= 0) fetch_e<P, H>(raw[u], A.e, id);
       else
 #pragma unroll
@@ -781,13 +806,24 @@ __global__ __launch_bounds__(NodeThreads<P>::value) void k_node_step(GnnArgs A) 
   const float s_h = asc(A, Q_H), s_mo = asc(A, Q_MO), s_mi = asc(A, Q_MI), s_nn2 = asc(A, Q_NN2);
   const float w1s = wsc(A, SW_STEP + 4 * k), w2s = wsc(A, SW_STEP + 4 * k + 1), wes = wsc(A, SW_STEP + 4 * k + 2);
   const int64_t ntiles = (A.n_hits + kCols - 1) / kCols;
-  for (int64_t tile = logical_block(A) * nw + wave; tile < ntiles; tile += (int64_t)gridDim.x * nw) {
+  const int64_t stride = (int64_t)gridDim.x * nw;
+  // with fused messages the next tile's message indices load a tile ahead
+  MsgIdx<H, P> mnext;
+  int64_t tile = logical_block(A) * nw + wave;
+  if constexpr (FUSE) {
+    const int64_t c0 = tile * kCols + (lane & 15);
+    fetch_msg_idx<H, P>(A, c0, tile < ntiles && c0 < A.n_hits, mnext);
+  }
+  for (; tile < ntiles; tile += stride) {
     const int64_t col = tile * kCols + (lane & 15);
     const bool valid = col < A.n_hits;
     float x[3 * H / 4];
     load_h<H, P>(x, A, col, valid);
     if constexpr (FUSE) {
-      gather_messages<H, P>(A, col, valid, x + H / 4, x + H / 2);
+      const MsgIdx<H, P> m = mnext;
+      const int64_t cn = (tile + stride) * kCols + (lane & 15);
+      fetch_msg_idx<H, P>(A, cn, tile + stride < ntiles && cn < A.n_hits, mnext);
+      gather_messages<H, P>(A, col, valid, m, x + H / 4, x + H / 2);
     } else {
       load_cols<H>(x + H / 4, A.msg + col * 2 * H, valid);
       load_cols<H>(x + H / 2, A.msg + col * 2 * H + H, valid);
