@@ -546,22 +546,41 @@ __global__ __launch_bounds__(kRadiusThreads) void k_radius(RadiusArgs A) {
 
 // CSR rows from the select pass's slots: thread (source i, rank r) copies
 // slot r of source i when r is below its count.
-// One G-lane group per hit: lane j copies the hit's kept slots j, j + G, ...
-// into its CSR row (contiguous writes per row, no per-slot index division).
-template <int G>
+// One wave per chunk of 64 hits.  The chunk's CSR rows are one contiguous
+// range of the output, so lane l writes positions l, l + 64, ... of it (every
+// store coalesced, no idle lanes whatever the row lengths); the row of a
+// position is found by a binary search over the chunk's row starts, one per
+// lane, read with lane shuffles.
 __global__ __launch_bounds__(256) void k_slots_to_csr(const int32_t* __restrict__ slots, const int64_t* __restrict__ row_ptr,
                                                       int64_t n_hits, int k_max, int32_t* __restrict__ src,
                                                       int32_t* __restrict__ dst, const int64_t* status) {
   if (status[0] != 0) return;
-  const int j = threadIdx.x % G;
-  const int64_t stride = (int64_t)gridDim.x * (blockDim.x / G);
-  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; i < n_hits; i += stride) {
-    const int64_t b = row_ptr[i];
-    const int c = (int)(row_ptr[i + 1] - b);
-    const int32_t* s = slots + i * k_max;
-    for (int r = j; r < c; r += G) {
-      src[b + r] = (int32_t)i;
-      dst[b + r] = s[r];
+  const int lane = threadIdx.x & 63;
+  const int64_t nchunks = (n_hits + 63) / 64;
+  const int64_t stride = (int64_t)gridDim.x * (blockDim.x / 64);
+  for (int64_t ch = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64; ch < nchunks; ch += stride) {
+    const int64_t h0 = ch * 64;
+    const int64_t base = row_ptr[h0];
+    const int64_t end = row_ptr[min(h0 + 64, n_hits)];
+    // row start of this lane's hit relative to the chunk (past the last hit:
+    // the chunk's end, so that no position maps there)
+    const int rel = (int)((h0 + lane < n_hits ? row_ptr[h0 + lane] : end) - base);
+    const int total = (int)(end - base);
+    // the whole wave runs every round (the shuffles read every lane's rel)
+    for (int q0 = 0; q0 < total; q0 += 64) {
+      const int q = q0 + lane;
+      int lo = 0, hi = 63;                       // largest l with rel_l <= q
+#pragma unroll
+      for (int step = 0; step < 6; ++step) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (__shfl(rel, mid) <= q) lo = mid; else hi = mid - 1;
+      }
+      const int r0 = __shfl(rel, lo);
+      if (q < total) {
+        const int64_t i = h0 + lo;
+        src[base + q] = (int32_t)i;
+        dst[base + q] = slots[i * k_max + (q - r0)];
+      }
     }
   }
 }
@@ -572,16 +591,13 @@ hipError_t launch_slots_copy(const RunArgs& a, bool candidates) {
   const int64_t n = a.hits.n_hits;
   if (n == 0) return hipSuccess;
   const int k = a.ctx->cfg.k_max;
-  const int G = k > 32 ? 32 : 16;                        // lanes per hit
-  const unsigned grid = (unsigned)std::min<int64_t>((n * G + 255) / 256, (int64_t)a.ctx->n_cu * 32);
+  const int64_t chunks = (n + 63) / 64;
+  const unsigned grid = (unsigned)std::min<int64_t>((chunks + 3) / 4, (int64_t)a.ctx->n_cu * 32);
   const int32_t* slots = reinterpret_cast<const int32_t*>(a.ws + a.L.slots);
   const int64_t* rp = reinterpret_cast<const int64_t*>(a.ws + (candidates ? a.L.pf_tmp : a.L.row_ptr));
   int32_t* s = candidates ? reinterpret_cast<int32_t*>(a.ws + a.L.cand_src) : a.out.src;
   int32_t* d = candidates ? reinterpret_cast<int32_t*>(a.ws + a.L.cand_dst) : a.out.dst;
-  if (G == 32)
-    hipLaunchKernelGGL(k_slots_to_csr<32>, dim3(grid), dim3(256), 0, a.stream, slots, rp, n, k, s, d, a.out.status);
-  else
-    hipLaunchKernelGGL(k_slots_to_csr<16>, dim3(grid), dim3(256), 0, a.stream, slots, rp, n, k, s, d, a.out.status);
+  hipLaunchKernelGGL(k_slots_to_csr, dim3(grid), dim3(256), 0, a.stream, slots, rp, n, k, s, d, a.out.status);
   return hipGetLastError();
 }
 
