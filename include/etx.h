@@ -155,7 +155,8 @@ typedef enum {
   ETX_OPT_EDGE_WREG = 8,     /* 1: FP32 edge-update kernels keep their weights in registers (0: read LDS) */
   ETX_OPT_EMBED_PRECISION = 9, /* GEMM operand precision of the embedding MLP (etx_precision), or -1 (default):
                                   the same as the configuration's precision */
-  ETX_OPT_OUTSUM_LDS = 10,    /* 1: hidden size 64 reduces the out-sums through an LDS transpose (0: DPP scan) */
+  ETX_OPT_OUTSUM_LDS = 10,    /* 1 (default): hidden size 64 reduces the out-sums through an LDS transpose; 0: DPP scan
+                                 (the two forms add in different orders: results agree to FP32 rounding, not bitwise) */
   ETX_OPT_F32_SPLIT = 11,     /* 1: in FP32 runs the edge kernels compute their GEMMs on the BF16 matrix cores with
                                  every FP32 operand split exactly into three BF16 parts (six partial products,
                                  FP32 accumulation; error at FP32 rounding level); 0: FP32 matrix cores */

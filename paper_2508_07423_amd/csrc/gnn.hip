@@ -188,24 +188,24 @@ __device__ inline void decode_e(float* ef, const RawE<P, H>& r, float scale) {
   }
 }
 
-// The source and target node-product rows of an edge (FP32), gathered ahead.
-template <int H>
-struct NodeRows { float4 s[H / 16], d[H / 16]; };
-
-// HB: the rows are BF16 node encodings (8 bytes per lane group and block).
+// The source and target rows of an edge, gathered ahead: FP32 node-product
+// rows, or (HB) the BF16 node encodings as stored, four features (8 bytes)
+// per lane group and 16-feature block.
 template <int H, bool HB = false>
-__device__ inline void fetch_rows(NodeRows<H>& n, const float* ps, const float* pd, int src, int dst) {
+struct NodeRows { float4 s[H / 16], d[H / 16]; };
+template <int H>
+struct NodeRows<H, true> { uint2 s[H / 16], d[H / 16]; };
+
+template <int H, bool HB = false>
+__device__ inline void fetch_rows(NodeRows<H, HB>& n, const float* ps, const float* pd, int src, int dst) {
   const int g = lane_group();
   if constexpr (HB) {
     const uint2* rs = reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(ps) + (int64_t)src * H);
     const uint2* rd = reinterpret_cast<const uint2*>(reinterpret_cast<const uint16_t*>(pd) + (int64_t)dst * H);
-    auto f4 = [](uint2 v) {
-      return make_float4(bf16_value(v.x & 0xffffu), bf16_value(v.x >> 16), bf16_value(v.y & 0xffffu), bf16_value(v.y >> 16));
-    };
 #pragma unroll
     for (int c = 0; c < H / 16; ++c) {
-      n.s[c] = f4(rs[4 * c + g]);
-      n.d[c] = f4(rd[4 * c + g]);
+      n.s[c] = rs[4 * c + g];
+      n.d[c] = rd[4 * c + g];
     }
   } else {
     const float4* rs = reinterpret_cast<const float4*>(ps + (int64_t)src * H);
@@ -239,6 +239,27 @@ __device__ inline void rows_cols(float* x, const float4 (&r)[H / 16]) {
     x[4 * c + 0] = r[c].x; x[4 * c + 1] = r[c].y; x[4 * c + 2] = r[c].z; x[4 * c + 3] = r[c].w;
   }
 }
+template <int H>
+__device__ inline void rows_cols(float* x, const uint2 (&r)[H / 16]) {
+#pragma unroll
+  for (int c = 0; c < H / 16; ++c) {
+    x[4 * c + 0] = bf16_value(r[c].x & 0xffffu); x[4 * c + 1] = bf16_value(r[c].x >> 16);
+    x[4 * c + 2] = bf16_value(r[c].y & 0xffffu); x[4 * c + 3] = bf16_value(r[c].y >> 16);
+  }
+}
+
+// One gathered row's product with a BF16 weight block (a zero start): the
+// stored BF16 features of 32-feature step t are the MFMA operand as they are
+// (blocks 2t and 2t+1 in register order), the bits mfma_bf16 would pack.
+template <int H>
+__device__ inline void row_product_bf16(float* q, const uint2 (&r)[H / 16], const bf16x8* __restrict__ w) {
+  uint4 xr[H / 32];
+#pragma unroll
+  for (int t = 0; t < H / 32; ++t) xr[t] = make_uint4(r[2 * t].x, r[2 * t].y, r[2 * t + 1].x, r[2 * t + 1].y);
+#pragma unroll
+  for (int i = 0; i < H / 4; ++i) q[i] = 0.f;
+  mfma_bf16_chunks<H, H / 16>(q, xr, w);
+}
 
 // Software pipeline over a wave's tiles (tile, tile + stride, ...): with
 // depth 0 every tile loads its own operands; depth 1 issues the next tile's
@@ -268,7 +289,8 @@ struct EdgeFeed {
   TileIdx i1{0, 0, -1, -1};     // indices of the next tile (depth 2)
   TileIdx i0{0, 0, -1, -1};     // indices of the fetched tile
   RawE<P, H> raw;
-  NodeRows<H> rows;
+  using Rows = NodeRows<H, HB>;
+  Rows rows;
   bool want_e;
 
   __device__ int64_t col(int64_t t) const { return t * kCols + lane16; }
@@ -298,7 +320,7 @@ struct EdgeFeed {
   }
   // hand out tile t's operands and indices (key: the column's source node,
   // -1 past the last edge) and issue tile t + stride's
-  __device__ void next(int64_t t, RawE<P, H>& r, NodeRows<H>& n, TileIdx& x, int& key) {
+  __device__ void next(int64_t t, RawE<P, H>& r, Rows& n, TileIdx& x, int& key) {
     const bool v = col(t) < E;
     if constexpr (PIPE == 0) {
       fetch(t);
@@ -435,7 +457,9 @@ __device__ inline void out_sums(const GnnArgs& A, int64_t tile, const TileIdx& x
 // rows padded to 20 floats so that the writes of a half-wave hit distinct
 // banks); lane f then adds its row along the columns, closing a run wherever
 // the (wave-uniform) source changes, and writes each run's sum as one
-// coalesced 256-byte row.  Both orders are fixed.
+// coalesced 256-byte row.  Both orders are fixed.  (With hidden size 32 and
+// the short rows of trained networks, many runs per tile, the DPP scan is the
+// faster form.)
 constexpr int kOutRow = 20;                     // floats per transposed feature row
 constexpr int kOutBufFloats = 64 * kOutRow;     // per wave
 
@@ -574,13 +598,21 @@ __global__ __launch_bounds__(512) void k_edge_encode(GnnArgs A) {
     const int64_t col = tile * kCols + (lane & 15);
     const bool valid = col < E;
     RawE<P, H> unused;
-    NodeRows<H> rows;
+    typename decltype(feed)::Rows rows;
     TileIdx ti;
     int key;
     feed.next(tile, unused, rows, ti, key);
     float a[H / 4];
     bias_cols<H>(a, reinterpret_cast<const float*>(w + S.b1()));
-    if constexpr (GH) {
+    if constexpr (GH && P == P_BF16) {
+      float q[H / 4];
+      row_product_bf16<H>(q, rows.s, reinterpret_cast<const bf16x8*>(wp));
+#pragma unroll
+      for (int r = 0; r < H / 4; ++r) a[r] += q[r];
+      row_product_bf16<H>(q, rows.d, reinterpret_cast<const bf16x8*>(wp + H * H * 2));
+#pragma unroll
+      for (int r = 0; r < H / 4; ++r) a[r] += q[r];
+    } else if constexpr (GH) {
       constexpr int PP = P == P_F32X ? P_F32 : P;
       const float s_h = asc(A, Q_H), o_h = s_h * wsc(A, SW_EE1);
       float x[H / 4], q[H / 4];
@@ -913,7 +945,7 @@ __global__ __launch_bounds__(512) void k_edge_step(GnnArgs A) {
     const int64_t col = tile * kCols + (lane & 15);
     const bool valid = col < E;
     RawE<P, H> raw;
-    NodeRows<H> rows;
+    typename decltype(feed)::Rows rows;
     TileIdx ti;
     int key;
     feed.next(tile, raw, rows, ti, key);
@@ -934,7 +966,16 @@ __global__ __launch_bounds__(512) void k_edge_step(GnnArgs A) {
       else
         gemm<P, H, H / 16>(a, ef, w + S.we(), 1.f, 1.f);
     }
-    if constexpr (GH) {
+    if constexpr (GH && P == P_BF16) {
+      // BF16: the stored rows of h are the MFMA operands as they are
+      float q[H / 4];
+      row_product_bf16<H>(q, rows.s, reinterpret_cast<const bf16x8*>(wp));
+#pragma unroll
+      for (int r = 0; r < H / 4; ++r) a[r] += q[r];
+      row_product_bf16<H>(q, rows.d, reinterpret_cast<const bf16x8*>(wp + H * H * 2));
+#pragma unroll
+      for (int r = 0; r < H / 4; ++r) a[r] += q[r];
+    } else if constexpr (GH) {
       // the node kernel's products, formed the same way (its precision, its
       // weights, a zero start) from the rows of h and added in the same order:
       // the same bits as gathering them
