@@ -426,14 +426,20 @@ __device__ inline void seg_scan_cols(float* v, int key) {
   const int k1 = row_shr_i<1>(key), k2 = row_shr_i<2>(key), k4 = row_shr_i<4>(key), k8 = row_shr_i<8>(key);
   const float m1 = ((j >= 1) & (k1 == key)) ? 1.f : 0.f, m2 = ((j >= 2) & (k2 == key)) ? 1.f : 0.f;
   const float m4 = ((j >= 4) & (k4 == key)) ? 1.f : 0.f, m8 = ((j >= 8) & (k8 == key)) ? 1.f : 0.f;
+  // a level whose mask is zero in every lane (no run of the wave's tiles that
+  // long) would add exact zeros to finite values: skipped, wave-uniformly
+  if (__ballot(m1 != 0.f))
 #pragma unroll
-  for (int r = 0; r < N; ++r) v[r] = fmaf(row_shr_f<1>(v[r]), m1, v[r]);
+    for (int r = 0; r < N; ++r) v[r] = fmaf(row_shr_f<1>(v[r]), m1, v[r]);
+  if (__ballot(m2 != 0.f))
 #pragma unroll
-  for (int r = 0; r < N; ++r) v[r] = fmaf(row_shr_f<2>(v[r]), m2, v[r]);
+    for (int r = 0; r < N; ++r) v[r] = fmaf(row_shr_f<2>(v[r]), m2, v[r]);
+  if (__ballot(m4 != 0.f))
 #pragma unroll
-  for (int r = 0; r < N; ++r) v[r] = fmaf(row_shr_f<4>(v[r]), m4, v[r]);
+    for (int r = 0; r < N; ++r) v[r] = fmaf(row_shr_f<4>(v[r]), m4, v[r]);
+  if (__ballot(m8 != 0.f))
 #pragma unroll
-  for (int r = 0; r < N; ++r) v[r] = fmaf(row_shr_f<8>(v[r]), m8, v[r]);
+    for (int r = 0; r < N; ++r) v[r] = fmaf(row_shr_f<8>(v[r]), m8, v[r]);
 }
 
 // q: stored values of this lane's column; key: its source node (-1 past the
