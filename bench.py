@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--pf-recall", type=float, default=0.995, help="c5: positive-edge recall that fixes tau")
     ap.add_argument("--events", type=int, default=None, help="override the number of events")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
+    ap.add_argument("--compact-state", type=int, default=0,
+                    help="bf16/fp8: store node and edge encodings in low precision (default: FP32 master copies)")
     ap.add_argument("--graph", type=int, default=0, help="replay the batch as one captured HIP graph")
     ap.add_argument("--autotune", type=int, default=0, help="tune the launch schedule on the batch before timing")
     ap.add_argument("--copy-gib", type=float, default=0.0,
@@ -52,12 +54,13 @@ def parse():
     return ap.parse_args()
 
 
-def stage_roofline(stage, ms_total, launches, n_edges, n_hits, H, dtype):
+def stage_roofline(stage, ms_total, launches, n_edges, n_hits, H, dtype, compact):
     """Algorithmic work per launch of a stage and its roofline."""
     if launches == 0 or ms_total <= 0:
         return None
     t = ms_total / launches * 1e-3          # seconds per launch
-    es = {"f32": 4, "bf16": 2, "fp8": 1}[dtype]
+    # bytes per stored edge-encoding feature: FP32 master copies unless the state is compact
+    es = {"f32": 4, "bf16": 2, "fp8": 1}[dtype] if compact else 4
     if stage in ("edge_step", "edge_step_final"):
         # edge net: Linear(3H->H) + Linear(H->H) per edge (the last step adds the
         # classifier Linear(H->H) + Linear(H->1)); bytes: e read and written once
@@ -215,7 +218,10 @@ def main():
                 pipe.calibrate(cal, stream=stream)
         return pipe
 
-    p = calibrated(etx.Pipeline(w, weights, precision=prec))
+    compact = bool(args.compact_state) and prec != etx.ETX_FP32
+    p = etx.Pipeline(w, weights, precision=prec)
+    etx.etx_set_option(p.ctx, etx.ETX_OPT_COMPACT_STATE, int(compact))
+    p = calibrated(p)
     if use_pf:
         etx.etx_prefilter_set(p.ctx, tr["params"])
         etx.etx_prefilter_config(p.ctx, 1, sel["tau"])
@@ -274,17 +280,19 @@ def main():
         stages = {k: dict(ms=round(v[0] / args.steps, 3), launches=v[1]) for k, v in prof.items() if v[1] > 0}
         gnn = {k: v for k, v in prof.items() if k in ("edge_step", "edge_step_final", "segsum", "node_step")}
         dom = max(gnn, key=lambda k: gnn[k][0])
-        roof = stage_roofline(dom, gnn[dom][0], gnn[dom][1], n_edges, b.n_hits, w.gnn_hidden, dtype)
+        roof = stage_roofline(dom, gnn[dom][0], gnn[dom][1], n_edges, b.n_hits, w.gnn_hidden, dtype, compact)
         if roof is not None:
             roof = dict(kernel=dom, **{k: (round(v, 4) if isinstance(v, float) else v) for k, v in roof.items()},
-                        traffic=measured_traffic(dom, w.name, dtype))
+                        traffic=measured_traffic(dom, w.name, dtype + ("-compact" if compact else "")))
         print(f"[bench] stages (ms/step): " + ", ".join(f"{k} {v['ms']}" for k, v in stages.items()),
               file=sys.stderr, flush=True)
     if use_pf:
         # the unpruned pipeline on the same batch: its throughput and efficiency are the reference
-        p0 = calibrated(etx.Pipeline(w, weights, precision=prec))
+        p0 = etx.Pipeline(w, weights, precision=prec)
+        etx.etx_set_option(p0.ctx, etx.ETX_OPT_COMPACT_STATE, int(compact))
+        p0 = calibrated(p0)
         # the same launch schedule as the pruned pipeline (tuned or default)
-        for key in range(etx.ETX_OPT_CSC_PLACE + 1):
+        for key in range(etx.ETX_OPT_COMPACT_STATE + 1):
             if key not in (etx.ETX_OPT_PROFILE,):
                 etx.etx_set_option(p0.ctx, key, etx.etx_get_option(p.ctx, key))
         with torch.cuda.stream(stream):
@@ -328,7 +336,7 @@ def main():
             "workload": f"{w.name}: {n_events} events, {w.n_planes} planes, tracks {w.tracks[0]}({w.tracks[1]}), "
                         f"emb 3-{w.emb_hidden}x{w.emb_layers}-{w.emb_dim}, radius {w.radius}, k {w.k_max}, "
                         f"IN hidden {w.gnn_hidden} x {w.gnn_steps} steps, {args.precision}"
-                        + (", hip graph" if args.graph else ""),
+                        + (", compact state" if compact else "") + (", hip graph" if args.graph else ""),
             "events": n_events, "hits": int(b.n_hits), "edges": n_edges, "schedule": tuned,
         },
         "roofline": roof,

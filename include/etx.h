@@ -72,7 +72,8 @@ typedef struct {
   int32_t gnn_hidden;        /* node and edge encoding width: 32 or 64 */
   int32_t gnn_steps;         /* message-passing steps: 1..16 */
   float edge_threshold;      /* keep edge when score >= threshold (0.5) */
-  int32_t precision;         /* etx_precision of the MLP GEMM operands */
+  int32_t precision;         /* etx_precision of the MLP GEMM operands; node and edge encodings stay FP32
+                                between kernels unless ETX_OPT_COMPACT_STATE is set */
   int32_t prefilter;         /* 1: prune candidate edges with the learned prefilter before the GNN */
   float prefilter_tau;       /* prune when prefilter probability < tau */
 } etx_config;
@@ -128,8 +129,8 @@ typedef enum {
   ETX_VIEW_ROW_PTR = 3,      /* int64 [n_hits+1]: CSR by source hit (global edge positions) */
   ETX_VIEW_COL_PTR = 4,      /* int64 [n_hits+1]: CSC by target hit */
   ETX_VIEW_CSC_EDGE = 5,     /* int32 [edge_capacity]: edge ids sorted by (dst, src) */
-  ETX_VIEW_NODE_H = 6,       /* [n_hits][H] node encodings after the last step: float (FP32 runs) or BF16
-                                bits, uint16 (BF16 and FP8 runs) */
+  ETX_VIEW_NODE_H = 6,       /* [n_hits][H] node encodings after the last step: float, or BF16 bits (uint16)
+                                in BF16 and FP8 runs with ETX_OPT_COMPACT_STATE set */
   ETX_VIEW_KEPT_EDGE = 7,    /* int32 [edge_capacity]: kept edge ids, per event from edge_off[e] */
   ETX_VIEW_KEPT_COUNT = 8,   /* int32 [n_events]: kept edges per event */
   ETX_VIEW_CALIB = 9,        /* float [ETX_N_CALIB]: per-tensor amax (calibration observers) */
@@ -178,9 +179,14 @@ typedef enum {
                                   kernels gather them; 1: the edge kernels gather the rows of h and form the same
                                   products themselves, and the node kernels write none (less HBM traffic, 2H^2 more
                                   multiply-adds per edge; same bits) */
-  ETX_OPT_CSC_PLACE = 18       /* 1 (default): for events with short rows (< 16 edges per hit) the whole block drops
+  ETX_OPT_CSC_PLACE = 18,      /* 1 (default): for events with short rows (< 16 edges per hit) the whole block drops
                                   the edges into their CSC columns through LDS cursors and then sorts every column by
                                   edge index (source order); 0: one wave ranks 64 edges at a time; same permutation */
+  ETX_OPT_COMPACT_STATE = 19   /* BF16 and FP8 runs only.  0 (default): the node encodings h and edge encodings e
+                                  are kept in FP32 between kernels (residual master copies) and quantised only where
+                                  they enter a GEMM.  1: both are stored in low precision (h as BF16; e in the
+                                  operand format, FP8 with the e_k scale), which halves or quarters their HBM
+                                  traffic; the residual sums are then rounded at every step (different results) */
 } etx_option;
 etx_status etx_set_option(etx_ctx* ctx, int32_t key, int64_t value);
 etx_status etx_get_option(const etx_ctx* ctx, int32_t key, int64_t* value);

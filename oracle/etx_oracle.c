@@ -290,22 +290,26 @@ void oracle_radius_margins(int64_t n, const int32_t* plane, const double* emb, i
  *   2 out-sums mo                     3 in-sums mi
  *   4 edge-encoder layer-2 input      5 node-net layer-2 inputs
  *   6 edge-net layer-2 inputs         7 + k: edge encodings e_k, k = 0..S
- * Edge encodings are stored quantised (e_k <- q(e_k) after the encoder and
- * after every update) and enter the edge net and the classifier in that form;
- * the sums are taken in full precision over the stored values.  The node
- * encodings h are stored rounded to BF16 in both quantised modes (after the
- * encoder and after every residual update) and are quantised again where they
- * enter a GEMM (a no-op in qmode 1). */
+ * Every GEMM operand is quantised where it enters the GEMM; LayerNorm, the
+ * residual additions, the message sums and the classifier's last layer stay
+ * in full precision, and the node and edge encodings between layers are the
+ * full-precision (master) values.  With `compact` set, the state itself is
+ * stored in low precision instead: the edge encodings e_k <- q(e_k) after the
+ * encoder and after every update (the message sums then run over the stored
+ * values), and the node encodings h rounded to BF16 after the encoder and
+ * after every residual update. */
 enum { Q_NE2 = 0, Q_H = 1, Q_MO = 2, Q_MI = 3, Q_EE2 = 4, Q_NN2 = 5, Q_EN2 = 6, Q_E = 7 };
 
 /* Parameter block order: node encoder (3->H->H), edge encoder (2H->H->H),
  * then per step k: node net k (3H->H->H), edge net k (3H->H->H), then the
  * classifier Block(H->H) and Linear(H->1).  Block(x) = ReLU(LN(x W + b)).
  * qmode 0: plain FP64.  act_scale: [8 + S] slots above (qmode 2).  amax
- * (may be NULL, [8 + S]): running max |x| of every quantised tensor. */
+ * (may be NULL, [8 + S]): running max |x| of every quantised tensor.
+ * compact (qmode 1, 2): store h and e in low precision (above). */
 void oracle_gnn(int64_t n, const double* cart, int64_t E, const int32_t* src, const int32_t* dst,
                 int H, int S, const double* params, double* logit, int qmode, const double* act_scale,
-                double* amax) {
+                double* amax, int compact) {
+  const int qs = qmode && compact;   /* state rounding */
   double* h = (double*)calloc((size_t)n * H + 1, sizeof(double));
   double* e = (double*)calloc((size_t)E * H + 1, sizeof(double));
   double* mo = (double*)calloc((size_t)n * H + 1, sizeof(double));
@@ -328,7 +332,7 @@ void oracle_gnn(int64_t n, const double* cart, int64_t E, const int32_t* src, co
       observe(amax, Q_NE2, tmp, H);
       linear(tmp, H, W2, b2, H, h + l * H, qmode, SC(Q_NE2), s2);
       layernorm_relu(h + l * H, H);
-      if (qmode) for (int c = 0; c < H; ++c) h[l * H + c] = qv(1, h[l * H + c], 1.0);
+      if (qs) for (int c = 0; c < H; ++c) h[l * H + c] = qv(1, h[l * H + c], 1.0);
     }
     p = b2 + H;
   }
@@ -347,7 +351,7 @@ void oracle_gnn(int64_t n, const double* cart, int64_t E, const int32_t* src, co
       linear(tmp, H, W2, b2, H, e + t * H, qmode, SC(Q_EE2), s2);
       layernorm_relu(e + t * H, H);
       observe(amax, Q_E + 0, e + t * H, H);
-      if (qmode) for (int c = 0; c < H; ++c) e[t * H + c] = qv(qmode, e[t * H + c], SC(Q_E + 0));
+      if (qs) for (int c = 0; c < H; ++c) e[t * H + c] = qv(qmode, e[t * H + c], SC(Q_E + 0));
     }
     p = b2 + H;
   }
@@ -378,7 +382,7 @@ void oracle_gnn(int64_t n, const double* cart, int64_t E, const int32_t* src, co
         observe(amax, Q_NN2, tmp, H);
         linear(tmp, H, W2, b2, H, out, qmode, SC(Q_NN2), s2);
         layernorm_relu(out, H);
-        for (int c = 0; c < H; ++c) h[l * H + c] = qmode ? qv(1, h[l * H + c] + out[c], 1.0) : h[l * H + c] + out[c];
+        for (int c = 0; c < H; ++c) h[l * H + c] = qs ? qv(1, h[l * H + c] + out[c], 1.0) : h[l * H + c] + out[c];
       }
       p = b2 + H;
     }
@@ -399,7 +403,7 @@ void oracle_gnn(int64_t n, const double* cart, int64_t E, const int32_t* src, co
         layernorm_relu(out, H);
         for (int c = 0; c < H; ++c) out[c] += e[t * H + c];
         observe(amax, Q_E + k + 1, out, H);
-        for (int c = 0; c < H; ++c) e[t * H + c] = qmode ? qv(qmode, out[c], SC(Q_E + k + 1)) : out[c];
+        for (int c = 0; c < H; ++c) e[t * H + c] = qs ? qv(qmode, out[c], SC(Q_E + k + 1)) : out[c];
       }
       p = b2 + H;
     }

@@ -54,7 +54,7 @@ def lib():
         L.oracle_radius.argtypes = [i64, P, P, i32, dbl, i32, i32, P, P, i64]
         L.oracle_radius.restype = i64
         L.oracle_radius_margins.argtypes = [i64, P, P, i32, dbl, i32, i32, P, P]
-        L.oracle_gnn.argtypes = [i64, P, i64, P, P, i32, i32, P, P, i32, P, P]
+        L.oracle_gnn.argtypes = [i64, P, i64, P, P, i32, i32, P, P, i32, P, P, i32]
         L.oracle_pow2_scale.argtypes = [dbl]
         L.oracle_pow2_scale.restype = dbl
         L.oracle_components.argtypes = [i64, i64, P, P, P, P]
@@ -144,9 +144,12 @@ def gnn_param_blocks(weights) -> list:
     return blocks
 
 
-def gnn(cart, src, dst, weights, H: int, S: int, qmode: int = 0, act_scale=None, amax=None) -> np.ndarray:
+def gnn(cart, src, dst, weights, H: int, S: int, qmode: int = 0, act_scale=None, amax=None,
+        compact: bool = False) -> np.ndarray:
     """Interaction-network logits.  act_scale / amax: the 8 + S activation
-    slots documented in etx_oracle.c (qmode 2 / observers)."""
+    slots documented in etx_oracle.c (qmode 2 / observers).  compact (qmode
+    1, 2): node and edge encodings stored in low precision between layers
+    instead of full-precision masters."""
     cart = _c(cart, np.float64)
     src = _c(src, np.int32); dst = _c(dst, np.int32)
     params = _flat(gnn_param_blocks(weights))
@@ -154,7 +157,7 @@ def gnn(cart, src, dst, weights, H: int, S: int, qmode: int = 0, act_scale=None,
     logit = np.zeros(max(E, 1))
     qs = None if act_scale is None else _c(act_scale, np.float64)
     lib().oracle_gnn(len(cart), _p(cart), E, _p(src), _p(dst), H, S, _p(params), _p(logit), qmode,
-                     _p(qs) if qs is not None else None, _p(amax) if amax is not None else None)
+                     _p(qs) if qs is not None else None, _p(amax) if amax is not None else None, int(compact))
     return logit[:E].copy()
 
 
@@ -204,18 +207,19 @@ def round_e4m3(x: float) -> float:
 # ---------------------------------------------------------------------------
 
 def run_event(ev: Dict[str, np.ndarray], w, weights, with_margins: bool = False, qmode: int = 0,
-              scales=None, emb_qmode: Optional[int] = None) -> Dict[str, np.ndarray]:
+              scales=None, emb_qmode: Optional[int] = None, compact: bool = False) -> Dict[str, np.ndarray]:
     """The full hot path on one event.  ``w`` carries the workload constants
     (r_scale, z_scale, radius, k_max, plane_window, gnn_hidden, gnn_steps,
     threshold); ``weights`` the network parameters.  qmode 1 (BF16) or 2 (FP8,
     ``scales`` from ``calibrate``) quantises the GEMM operands; ``emb_qmode``
-    gives the embedding its own mode (default: qmode)."""
+    gives the embedding its own mode (default: qmode); ``compact`` stores the
+    network's node and edge state in low precision (see ``gnn``)."""
     cyl, cart = features(ev["x"], ev["y"], ev["z"], w.r_scale, w.z_scale)
     es, gs = (scales[0], scales[1]) if scales is not None else (None, None)
     emb = embed(cyl, weights["emb"], qmode if emb_qmode is None else emb_qmode, es)
     r32 = float(np.float32(w.radius))
     src, dst = radius_graph(ev["plane"], emb, r32, w.k_max, w.plane_window)
-    logit = gnn(cart, src, dst, weights, w.gnn_hidden, w.gnn_steps, qmode, gs)
+    logit = gnn(cart, src, dst, weights, w.gnn_hidden, w.gnn_steps, qmode, gs, compact=compact)
     score = sigmoid(logit)
     keep = score >= w.threshold
     labels = components(len(cyl), src, dst, keep)
@@ -228,14 +232,14 @@ def run_event(ev: Dict[str, np.ndarray], w, weights, with_margins: bool = False,
 
 def run_batch(batch: Dict[str, np.ndarray], w, weights, events: Optional[Sequence[int]] = None,
               threads: Optional[int] = None, with_margins: bool = False, qmode: int = 0,
-              scales=None, emb_qmode: Optional[int] = None) -> List[Dict[str, np.ndarray]]:
+              scales=None, emb_qmode: Optional[int] = None, compact: bool = False) -> List[Dict[str, np.ndarray]]:
     hit_off = batch["hit_off"]
     idx = list(range(len(hit_off) - 1)) if events is None else list(events)
 
     def one(i):
         a, b = int(hit_off[i]), int(hit_off[i + 1])
         ev = {k: batch[k][a:b] for k in ("x", "y", "z", "plane")}
-        return run_event(ev, w, weights, with_margins, qmode, scales, emb_qmode)
+        return run_event(ev, w, weights, with_margins, qmode, scales, emb_qmode, compact)
 
     nt = threads or os.cpu_count() or 1
     if nt <= 1 or len(idx) <= 1:

@@ -665,6 +665,10 @@ etx_status etx_set_option(etx_ctx* ctx, int32_t key, int64_t value) {
       if (value != 0 && value != 1) return ETX_ERR_INVALID_ARG;
       ctx->csc_place = (int)value;
       break;
+    case ETX_OPT_COMPACT_STATE:
+      if (value != 0 && value != 1) return ETX_ERR_INVALID_ARG;
+      ctx->compact_state = (int)value;
+      break;
     default: return ETX_ERR_INVALID_ARG;
   }
   if (key != ETX_OPT_USE_GRAPH) clear_graphs(ctx);
@@ -725,10 +729,19 @@ etx_status etx_get_option(const etx_ctx* ctx, int32_t key, int64_t* value) {
     case ETX_OPT_XCD_MAP: *value = ctx->xcd_map; break;
     case ETX_OPT_EDGE_PRODUCTS: *value = ctx->edge_products; break;
     case ETX_OPT_CSC_PLACE: *value = ctx->csc_place; break;
+    case ETX_OPT_COMPACT_STATE: *value = ctx->compact_state; break;
     case ETX_OPT_PROFILE: *value = ctx->profile; break;
     default: return ETX_ERR_INVALID_ARG;
   }
   return ETX_OK;
+}
+
+// Kernel precision of a run: the low-precision GEMM modes keep node and edge
+// state in FP32 unless the compact form is asked for.
+static int kernel_precision(const etx_ctx* ctx) {
+  const int p = ctx->cfg.precision;
+  if (p == ETX_FP32 || ctx->compact_state) return p;
+  return p == ETX_BF16 ? kBf16Master : kFp8Master;
 }
 
 etx_status etx_run(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void* ws, size_t ws_bytes, etx_stream stream) {
@@ -740,7 +753,7 @@ etx_status etx_run(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void* ws, s
   if (ctx->cfg.prefilter && !ctx->pf_set) return ETX_ERR_INVALID_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return ETX_ERR_HIP;
   RunArgs a{ctx, *hits, *out, L, static_cast<char*>(ws), static_cast<hipStream_t>(stream), false,
-            ctx->cfg.precision};
+            kernel_precision(ctx)};
   if (!ctx->use_graph || stream == nullptr) {
     hipError_t e = enqueue_pipeline(a);
     if (e != hipSuccess) {
@@ -887,7 +900,7 @@ struct SaveHeader {
   int32_t calibrated, pf_set;
 };
 constexpr uint32_t kSaveMagic = 0x53585445;   // "ETXS"
-constexpr int kSavedOptions = 19;             // etx_option keys 0 .. 18
+constexpr int kSavedOptions = 20;             // etx_option keys 0 .. 19
 
 size_t save_bytes(const etx_ctx* ctx) {
   return sizeof(SaveHeader) + sizeof(etx_config) + sizeof(float) * (N_SCALES + 3 * ETX_PF_NPARAM) +

@@ -95,7 +95,7 @@ hipError_t launch_embed(const RunArgs& a) {
   if (a.hits.n_hits == 0) return hipSuccess;
   const etx_ctx* c = a.ctx;
   // the embedding may run at its own operand precision (calibration runs stay FP32)
-  const int prec = (!a.calibrate && c->emb_precision >= 0) ? c->emb_precision : a.prec;
+  const int prec = (!a.calibrate && c->emb_precision >= 0) ? c->emb_precision : kSegPrec[a.prec];
   EmbedArgs A;
   A.x = a.hits.x;
   A.y = a.hits.y;

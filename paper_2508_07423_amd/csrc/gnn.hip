@@ -95,10 +95,10 @@ __device__ inline void stage_bytes(char* dst, const char* src, int n) {
 __device__ inline float asc(const GnnArgs& A, int q) { return A.sc[SC_GNN + q]; }
 __device__ inline float wsc(const GnnArgs& A, int s) { return A.sc[s]; }
 
-// Node encodings h: FP32 rows in FP32 runs; BF16 rows (round to nearest even)
-// in the BF16 and FP8 runs, which keep node state like edge state, in the low
-// precision.  A store rounds the registers first, so that what a kernel goes
-// on computing with is what the next kernel reads.
+// Node encodings h: FP32 rows, except in the compact-state BF16 and FP8 runs
+// (P_BF16, P_FP8), which keep node state like edge state in low precision:
+// BF16 rows (round to nearest even).  A store rounds the registers first, so
+// that what a kernel goes on computing with is what the next kernel reads.
 template <int P>
 constexpr bool kHalfH = P == P_BF16 || P == P_FP8;
 
@@ -871,7 +871,7 @@ __global__ __launch_bounds__(NodeThreads<P>::value) void k_node_step(GnnArgs A) 
     observe<H / 4>(A.calib, SC_GNN + Q_MI, x + H / 2, valid);
     float a[H / 4];
     bias_cols<H>(a, reinterpret_cast<const float*>(w + S.b1()));
-    if constexpr (P == P_FP8) {
+    if constexpr (kFp8Ops<P>) {
       // the three input blocks carry their own activation scales
       const uint64_t* w1 = reinterpret_cast<const uint64_t*>(w + S.w1());
       mfma_fp8<3 * H, H / 16, 0, H / 32>(a, x, w1, 1.0f / s_h, s_h * w1s);
@@ -970,7 +970,7 @@ __global__ __launch_bounds__(512) void k_edge_step(GnnArgs A) {
       if constexpr (WR)
         mfma_f32_reg<H, H / 16>(a, ef, wr_e);
       else
-        gemm<P, H, H / 16>(a, ef, w + S.we(), 1.f, 1.f);
+        gemm<P, H, H / 16>(a, ef, w + S.we(), 1.0f / s_e, s_e * w1s);   // scales: FP8 operands only
     }
     if constexpr (GH && P == P_BF16) {
       // BF16: the stored rows of h are the MFMA operands as they are
@@ -1087,17 +1087,21 @@ static unsigned node_grid(const RunArgs& a, int per_cu) {
 }
 
 static const char* seg_ptr(const RunArgs& a, int64_t off) {
-  return static_cast<const char*>(a.ctx->seg_base[a.prec]) + off;
+  return static_cast<const char*>(a.ctx->seg_base[kSegPrec[a.prec]]) + off;
 }
 
 #define DISPATCH_HP(H_, P_, ...)                                            \
-  switch ((H_) * 4 + (P_)) {                                                \
-    case 32 * 4 + 0: { constexpr int H = 32, P = 0; __VA_ARGS__; } break;  \
-    case 32 * 4 + 1: { constexpr int H = 32, P = 1; __VA_ARGS__; } break;  \
-    case 32 * 4 + 2: { constexpr int H = 32, P = 2; __VA_ARGS__; } break;  \
-    case 64 * 4 + 0: { constexpr int H = 64, P = 0; __VA_ARGS__; } break;  \
-    case 64 * 4 + 1: { constexpr int H = 64, P = 1; __VA_ARGS__; } break;  \
-    case 64 * 4 + 2: { constexpr int H = 64, P = 2; __VA_ARGS__; } break;  \
+  switch ((H_) * 8 + (P_)) {                                                \
+    case 32 * 8 + 0: { constexpr int H = 32, P = 0; __VA_ARGS__; } break;  \
+    case 32 * 8 + 1: { constexpr int H = 32, P = 1; __VA_ARGS__; } break;  \
+    case 32 * 8 + 2: { constexpr int H = 32, P = 2; __VA_ARGS__; } break;  \
+    case 32 * 8 + 4: { constexpr int H = 32, P = 4; __VA_ARGS__; } break;  \
+    case 32 * 8 + 5: { constexpr int H = 32, P = 5; __VA_ARGS__; } break;  \
+    case 64 * 8 + 0: { constexpr int H = 64, P = 0; __VA_ARGS__; } break;  \
+    case 64 * 8 + 1: { constexpr int H = 64, P = 1; __VA_ARGS__; } break;  \
+    case 64 * 8 + 2: { constexpr int H = 64, P = 2; __VA_ARGS__; } break;  \
+    case 64 * 8 + 4: { constexpr int H = 64, P = 4; __VA_ARGS__; } break;  \
+    case 64 * 8 + 5: { constexpr int H = 64, P = 5; __VA_ARGS__; } break;  \
     default: return hipErrorInvalidValue;                                   \
   }
 
@@ -1105,7 +1109,7 @@ hipError_t launch_node_encode(const RunArgs& a) {
   if (a.hits.n_hits == 0) return hipSuccess;
   GnnArgs A = gnn_args(a);
   const int Hh = a.ctx->cfg.gnn_hidden;
-  const WeightMap& m = a.ctx->wmap[a.prec];
+  const WeightMap& m = a.ctx->wmap[kSegPrec[a.prec]];
   A.seg = seg_ptr(a, m.node_enc);
   A.seg_bytes = SegNodeEnc{Hh, kPrecBytes[a.prec]}.size();
   unsigned grid = node_grid(a, a.ctx->node_wg_per_cu);
@@ -1186,12 +1190,12 @@ hipError_t launch_edge_encode(const RunArgs& a) {
   GnnArgs A = gnn_args(a);
   const int Hh = a.ctx->cfg.gnn_hidden;
   const int kp = edge_prec(a);
-  const WeightMap& m = a.ctx->wmap[kp];
-  A.seg = static_cast<const char*>(a.ctx->seg_base[kp]) + m.edge_enc;
+  const WeightMap& m = a.ctx->wmap[kSegPrec[kp]];
+  A.seg = static_cast<const char*>(a.ctx->seg_base[kSegPrec[kp]]) + m.edge_enc;
   A.seg_bytes = SegEdgeEnc{Hh, kPrecBytes[kp]}.size();
   const bool gh = a.ctx->edge_products != 0;
   // the node encoder's W_src and W_dst (its segment, its precision)
-  A.seg3 = seg_ptr(a, a.ctx->wmap[a.prec].node_enc + SegNodeEnc{Hh, kPrecBytes[a.prec]}.ws());
+  A.seg3 = seg_ptr(a, a.ctx->wmap[kSegPrec[a.prec]].node_enc + SegNodeEnc{Hh, kPrecBytes[a.prec]}.ws());
   A.seg3_bytes = gh ? 2 * Hh * Hh * kPrecBytes[a.prec] : 0;
   const unsigned grid = (unsigned)(a.ctx->n_cu * a.ctx->edge_wg_per_cu);
   const size_t lds = A.seg_bytes + A.seg3_bytes + outsum_lds_bytes(a);
@@ -1199,15 +1203,19 @@ hipError_t launch_edge_encode(const RunArgs& a) {
   const bool ol = outsum_lds(a);
   const void* fn = nullptr;
 #define ENC_K(H_, P_) edge_encode_kernel<H_, P_>(pipe, ol, gh)
-  switch (Hh * 4 + kp) {
-    case 32 * 4 + 0: fn = ENC_K(32, 0); break;
-    case 32 * 4 + 1: fn = ENC_K(32, 1); break;
-    case 32 * 4 + 2: fn = ENC_K(32, 2); break;
-    case 32 * 4 + 3: fn = ENC_K(32, 3); break;
-    case 64 * 4 + 0: fn = ENC_K(64, 0); break;
-    case 64 * 4 + 1: fn = ENC_K(64, 1); break;
-    case 64 * 4 + 2: fn = ENC_K(64, 2); break;
-    case 64 * 4 + 3: fn = ENC_K(64, 3); break;
+  switch (Hh * 8 + kp) {
+    case 32 * 8 + 0: fn = ENC_K(32, 0); break;
+    case 32 * 8 + 1: fn = ENC_K(32, 1); break;
+    case 32 * 8 + 2: fn = ENC_K(32, 2); break;
+    case 32 * 8 + 3: fn = ENC_K(32, 3); break;
+    case 32 * 8 + 4: fn = ENC_K(32, 4); break;
+    case 32 * 8 + 5: fn = ENC_K(32, 5); break;
+    case 64 * 8 + 0: fn = ENC_K(64, 0); break;
+    case 64 * 8 + 1: fn = ENC_K(64, 1); break;
+    case 64 * 8 + 2: fn = ENC_K(64, 2); break;
+    case 64 * 8 + 3: fn = ENC_K(64, 3); break;
+    case 64 * 8 + 4: fn = ENC_K(64, 4); break;
+    case 64 * 8 + 5: fn = ENC_K(64, 5); break;
     default: return hipErrorInvalidValue;
   }
 #undef ENC_K
@@ -1222,7 +1230,9 @@ hipError_t launch_segsum(const RunArgs& a, int k) {
   const int Hh = a.ctx->cfg.gnn_hidden;
   unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((a.hits.n_hits + 3) / 4, (int64_t)a.ctx->n_cu * 32));
   const int U = a.ctx->segsum_unroll;
-#define SEG_U(U_) DISPATCH_HP(Hh, a.prec, hipLaunchKernelGGL((k_segsum<H, P, U_>), dim3(grid), dim3(256), 0, a.stream, A))
+  // the sums read the stored edge rows: FP32 whenever the state is kept in FP32
+  const int sp = (a.prec == P_BF16 || a.prec == P_FP8) ? a.prec : P_F32;
+#define SEG_U(U_) DISPATCH_HP(Hh, sp, hipLaunchKernelGGL((k_segsum<H, P, U_>), dim3(grid), dim3(256), 0, a.stream, A))
   switch (U) {
     case 1: SEG_U(1); break;
     case 2: SEG_U(2); break;
@@ -1237,7 +1247,7 @@ hipError_t launch_node_step(const RunArgs& a, int k) {
   if (a.hits.n_hits == 0) return hipSuccess;
   GnnArgs A = gnn_args(a);
   const int Hh = a.ctx->cfg.gnn_hidden;
-  const WeightMap& m = a.ctx->wmap[a.prec];
+  const WeightMap& m = a.ctx->wmap[kSegPrec[a.prec]];
   A.seg = seg_ptr(a, m.node[k]);
   A.seg_bytes = SegNode{Hh, kPrecBytes[a.prec]}.size();
   A.step = k;
@@ -1263,8 +1273,8 @@ hipError_t launch_edge_step(const RunArgs& a, int k, bool final_step) {
   GnnArgs A = gnn_args(a);
   const int Hh = a.ctx->cfg.gnn_hidden;
   const int kp = edge_prec(a);
-  const WeightMap& m = a.ctx->wmap[kp];
-  const char* base = static_cast<const char*>(a.ctx->seg_base[kp]);
+  const WeightMap& m = a.ctx->wmap[kSegPrec[kp]];
+  const char* base = static_cast<const char*>(a.ctx->seg_base[kSegPrec[kp]]);
   A.seg = base + m.edge[k];
   A.seg_bytes = SegEdge{Hh, kPrecBytes[kp]}.size();
   A.seg2 = base + m.cls;
@@ -1272,7 +1282,7 @@ hipError_t launch_edge_step(const RunArgs& a, int k, bool final_step) {
   const bool gh = a.ctx->edge_products != 0;
   // W_src and W_dst of edge net k as the node kernel holds them (node net k's
   // segment, the node kernels' precision), so the products are the same bits
-  A.seg3 = seg_ptr(a, a.ctx->wmap[a.prec].node[k] + SegNode{Hh, kPrecBytes[a.prec]}.ws());
+  A.seg3 = seg_ptr(a, a.ctx->wmap[kSegPrec[a.prec]].node[k] + SegNode{Hh, kPrecBytes[a.prec]}.ws());
   A.seg3_bytes = gh ? 2 * Hh * Hh * kPrecBytes[a.prec] : 0;
   A.step = k;
   const bool ol = !final_step && outsum_lds(a);
@@ -1282,15 +1292,19 @@ hipError_t launch_edge_step(const RunArgs& a, int k, bool final_step) {
   const bool wr = a.ctx->edge_wreg != 0;
   const void* fn = nullptr;
 #define STEP_K(H_, P_) edge_step_kernel<H_, P_>(final_step, pipe, wr, ol, gh)
-  switch (Hh * 4 + kp) {
-    case 32 * 4 + 0: fn = STEP_K(32, 0); break;
-    case 32 * 4 + 1: fn = STEP_K(32, 1); break;
-    case 32 * 4 + 2: fn = STEP_K(32, 2); break;
-    case 32 * 4 + 3: fn = STEP_K(32, 3); break;
-    case 64 * 4 + 0: fn = STEP_K(64, 0); break;
-    case 64 * 4 + 1: fn = STEP_K(64, 1); break;
-    case 64 * 4 + 2: fn = STEP_K(64, 2); break;
-    case 64 * 4 + 3: fn = STEP_K(64, 3); break;
+  switch (Hh * 8 + kp) {
+    case 32 * 8 + 0: fn = STEP_K(32, 0); break;
+    case 32 * 8 + 1: fn = STEP_K(32, 1); break;
+    case 32 * 8 + 2: fn = STEP_K(32, 2); break;
+    case 32 * 8 + 3: fn = STEP_K(32, 3); break;
+    case 32 * 8 + 4: fn = STEP_K(32, 4); break;
+    case 32 * 8 + 5: fn = STEP_K(32, 5); break;
+    case 64 * 8 + 0: fn = STEP_K(64, 0); break;
+    case 64 * 8 + 1: fn = STEP_K(64, 1); break;
+    case 64 * 8 + 2: fn = STEP_K(64, 2); break;
+    case 64 * 8 + 3: fn = STEP_K(64, 3); break;
+    case 64 * 8 + 4: fn = STEP_K(64, 4); break;
+    case 64 * 8 + 5: fn = STEP_K(64, 5); break;
     default: return hipErrorInvalidValue;
   }
 #undef STEP_K
@@ -1354,9 +1368,13 @@ int gnn_attributes(size_t max_lds) {
   set_gnn_attr<32, 0>(bad, max_lds);
   set_gnn_attr<32, 1>(bad, max_lds);
   set_gnn_attr<32, 2>(bad, max_lds);
+  set_gnn_attr<32, 4>(bad, max_lds);
+  set_gnn_attr<32, 5>(bad, max_lds);
   set_gnn_attr<64, 0>(bad, max_lds);
   set_gnn_attr<64, 1>(bad, max_lds);
   set_gnn_attr<64, 2>(bad, max_lds);
+  set_gnn_attr<64, 4>(bad, max_lds);
+  set_gnn_attr<64, 5>(bad, max_lds);
   return bad;
 }
 

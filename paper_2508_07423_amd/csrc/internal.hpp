@@ -16,8 +16,13 @@ constexpr int kEdgeTile = 16;      // edges per wave tile of the MLP kernels (th
 constexpr int kDpad = 16;          // padded embedding width in HBM
 constexpr int kScanBlock = 1024;   // elements per block of the device-wide scan
 
-constexpr int kPrecBytes[4] = {4, 2, 1, 6};   // weight bytes: FP32, BF16, FP8, FP32 as three BF16 parts
+// weight bytes: FP32, BF16, FP8, FP32 as three BF16 parts, BF16 and FP8 with FP32 state
+constexpr int kPrecBytes[6] = {4, 2, 1, 6, 2, 1};
+// the weight segments a precision uses (the FP32-state forms share BF16's and FP8's)
+constexpr int kSegPrec[6] = {0, 1, 2, 3, 1, 2};
 constexpr int kF32Split = 3;                  // segment set of the split-FP32 edge kernels
+constexpr int kBf16Master = 4;                // BF16 operands, FP32 node and edge state
+constexpr int kFp8Master = 5;                 // FP8 operands, FP32 node and edge state
 
 // Offsets (in bytes) of the per-kernel weight segments in a precision's device buffer.
 struct WeightMap {
@@ -75,6 +80,7 @@ struct etx_ctx {
   int xcd_map = 0;                 // tile and node kernels: contiguous work per XCD
   int edge_products = 0;           // 1: edge kernels form the node-product terms from gathered h rows
   int csc_place = 1;               // short-row CSC placed by the whole block, then columns sorted
+  int compact_state = 0;           // BF16/FP8 runs: 1 keeps h, e in the operand format, 0 in FP32 (residual masters)
   std::vector<char> blob;          // the weight blob as given (for etx_save)
   int use_graph = 0;
   std::map<etx::GraphKey, hipGraphExec_t> graphs;
@@ -99,7 +105,7 @@ struct RunArgs {
   char* ws;
   hipStream_t stream;
   bool calibrate;                  // record amax observers (FP32 run)
-  int prec;                        // GEMM operand precision of this run (etx_precision)
+  int prec;                        // kernel precision: etx_precision, or kBf16Master / kFp8Master
 };
 
 // launchers (graph.hip)

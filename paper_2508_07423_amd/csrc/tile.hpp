@@ -193,14 +193,23 @@ __device__ inline void mfma_bf16_chunks(float* acc, const uint4* xr, const bf16x
 // ---------------------------------------------------------------------------
 
 // P_F32X: FP32 operands on the BF16 matrix cores, each operand split into
-// three BF16 parts (below); FP32 everywhere else.
-enum Prec { P_F32 = 0, P_BF16 = 1, P_FP8 = 2, P_F32X = 3 };
+// three BF16 parts (below); FP32 everywhere else.  P_BF16M / P_FP8M: BF16 /
+// FP8 GEMM operands with the node and edge state kept in FP32 between kernels
+// (residual masters); P_BF16 / P_FP8 keep that state in the operand format.
+enum Prec { P_F32 = 0, P_BF16 = 1, P_FP8 = 2, P_F32X = 3, P_BF16M = 4, P_FP8M = 5 };
 // bytes per weight element of a GEMM in precision P (P_F32X: three BF16 planes)
 template <int P>
-struct PrecBytes { static constexpr int value = P == P_F32 ? 4 : P == P_BF16 ? 2 : P == P_FP8 ? 1 : 6; };
-// storage format of activations in precision P
+struct PrecBytes {
+  static constexpr int value = P == P_F32 ? 4 : (P == P_BF16 || P == P_BF16M) ? 2 : (P == P_FP8 || P == P_FP8M) ? 1 : 6;
+};
+// storage format of the state (edge encodings) in precision P
 template <int P>
-struct StorePrec { static constexpr int value = P == P_F32X ? P_F32 : P; };
+struct StorePrec { static constexpr int value = (P == P_BF16 || P == P_FP8) ? P : P_F32; };
+// operand formats
+template <int P>
+constexpr bool kBf16Ops = P == P_BF16 || P == P_BF16M;
+template <int P>
+constexpr bool kFp8Ops = P == P_FP8 || P == P_FP8M;
 
 // OCP FP8 E4M3 (bias 7, 3 mantissa bits, subnormals, max 448, no infinity),
 // converted by the gfx950 instructions v_cvt_pk_fp8_f32 (round to nearest
@@ -365,7 +374,7 @@ template <int P, int K, int MB>
 __device__ inline void gemm(float* acc, const float* x, const void* w, float inv_s, float out_scale) {
   if constexpr (P == P_F32) {
     mfma_f32<K, MB>(acc, x, static_cast<const float*>(w));
-  } else if constexpr (P == P_BF16) {
+  } else if constexpr (kBf16Ops<P>) {
     mfma_bf16<K, MB>(acc, x, static_cast<const bf16x8*>(w));
   } else if constexpr (P == P_F32X) {
     mfma_split<K, MB>(acc, x, static_cast<const bf16x8*>(w));

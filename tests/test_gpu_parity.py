@@ -163,15 +163,17 @@ def test_radius_global_fallback_and_unroll_identical(c1_run):
         etx.etx_set_option(p.ctx, etx.ETX_OPT_EDGE_WG_PER_CU, 8)
 
 
-@pytest.mark.parametrize("prec", [0, 1, 2])
-def test_edge_schedules_bit_identical(prec):
+@pytest.mark.parametrize("prec,compact", [(0, 0), (1, 0), (2, 0), (1, 1), (2, 1)])
+def test_edge_schedules_bit_identical(prec, compact):
     """Every software-pipeline depth and workgroup shape of the edge kernels
-    computes the same bits (a multi-event c3 batch: many tiles per wave)."""
+    computes the same bits (a multi-event c3 batch: many tiles per wave),
+    with the low-precision state kept in FP32 or compact."""
     etx = _etx()
     w = synth.C3
     W = centred_weights(w)
     batch = synth.generate_batch(w, 8)
     p = etx.Pipeline(w, W, precision=prec)
+    etx.etx_set_option(p.ctx, etx.ETX_OPT_COMPACT_STATE, compact)
     if prec == etx.ETX_FP8_E4M3:
         p.calibrate(etx.to_device(synth.generate_batch(w, 4, seed_space=1000 + w.cid)))
     b = etx.to_device(batch)
@@ -262,8 +264,8 @@ def check_invariants(w, batch, res):
     assert np.array_equal(lab, O.components(n, src, dst, k))
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_outsum_lds_schedules_bit_identical(prec):
+@pytest.mark.parametrize("prec,compact", [(0, 0), (1, 0), (1, 1)])
+def test_outsum_lds_schedules_bit_identical(prec, compact):
     """Hidden size 64 with the LDS out-sums: every pipeline depth and
     workgroup shape computes the same bits (two full-size events)."""
     etx = _etx()
@@ -271,6 +273,7 @@ def test_outsum_lds_schedules_bit_identical(prec):
     W = centred_weights(w)
     batch = synth.generate_batch(w, 2)
     p = etx.Pipeline(w, W, precision=prec)
+    etx.etx_set_option(p.ctx, etx.ETX_OPT_COMPACT_STATE, compact)
     etx.etx_set_option(p.ctx, etx.ETX_OPT_OUTSUM_LDS, 1)
     b = etx.to_device(batch)
     ref = None
@@ -345,8 +348,10 @@ def test_radius_sorted_and_scanned_windows_identical(wl, n):
         assert np.array_equal(out[0][k], out[1 << 14][k]), k
 
 
-@pytest.mark.parametrize("wl,n,prec", [("c1", 1, 0), ("c3", 6, 0), ("c3", 6, 1), ("c3", 6, 2), ("c2", 2, 0), ("c2", 2, 1)])
-def test_fused_messages_identical(wl, n, prec):
+@pytest.mark.parametrize("wl,n,prec,compact", [("c1", 1, 0, 0), ("c3", 6, 0, 0), ("c3", 6, 1, 0), ("c3", 6, 2, 0),
+                                               ("c2", 2, 0, 0), ("c2", 2, 1, 0), ("c3", 6, 1, 1), ("c3", 6, 2, 1),
+                                               ("c2", 2, 1, 1)])
+def test_fused_messages_identical(wl, n, prec, compact):
     """Messages gathered inside the node kernel equal the separate message-sum
     kernel's, bit for bit (same sums in the same order)."""
     etx = _etx()
@@ -354,6 +359,7 @@ def test_fused_messages_identical(wl, n, prec):
     W = centred_weights(w)
     batch = synth.generate_batch(w, n)
     p = etx.Pipeline(w, W, precision=prec)
+    etx.etx_set_option(p.ctx, etx.ETX_OPT_COMPACT_STATE, compact)
     if prec == etx.ETX_FP8_E4M3:
         p.calibrate(etx.to_device(synth.generate_batch(w, 3, seed_space=1000 + w.cid)))
     b = etx.to_device(batch)
@@ -407,17 +413,20 @@ def test_xcd_map_identical(wl, n, prec):
         assert np.array_equal(out[0][k], out[1][k]), k
 
 
-@pytest.mark.parametrize("wl,n,prec,split,fuse", [("c1", 3, 0, 0, 0), ("c3", 30, 0, 0, 1), ("c3", 30, 0, 1, 0),
-                                                  ("c2", 2, 0, 0, 0), ("c3", 30, 1, 0, 1), ("c2", 2, 1, 0, 0),
-                                                  ("c3", 30, 2, 0, 0)])
-def test_edge_products_identical(wl, n, prec, split, fuse):
+@pytest.mark.parametrize("wl,n,prec,split,fuse,compact",
+                         [("c1", 3, 0, 0, 0, 0), ("c3", 30, 0, 0, 1, 0), ("c3", 30, 0, 1, 0, 0), ("c2", 2, 0, 0, 0, 0),
+                          ("c3", 30, 1, 0, 1, 0), ("c2", 2, 1, 0, 0, 0), ("c3", 30, 2, 0, 0, 0),
+                          ("c3", 30, 1, 0, 1, 1), ("c2", 2, 1, 0, 0, 1), ("c3", 30, 2, 0, 0, 1)])
+def test_edge_products_identical(wl, n, prec, split, fuse, compact):
     """Node products formed in the edge kernel from gathered rows of h equal
-    the node kernel's stored products: same bits, every precision."""
+    the node kernel's stored products: same bits, every precision and state
+    format (compact BF16 state: the stored rows of h are the MFMA operands)."""
     etx = _etx()
     w = synth.WORKLOADS[wl]
     W = centred_weights(w)
     batch = synth.generate_batch(w, n)
     p = etx.Pipeline(w, W, precision=prec)
+    etx.etx_set_option(p.ctx, etx.ETX_OPT_COMPACT_STATE, compact)
     if prec == etx.ETX_FP8_E4M3:
         p.calibrate(etx.to_device(synth.generate_batch(w, 4, seed_space=1000 + w.cid)))
     etx.etx_set_option(p.ctx, etx.ETX_OPT_F32_SPLIT, split)

@@ -75,9 +75,10 @@ def test_bf16_cast_matches_oracle():
     assert len(bad) == 0, [(float(x[i]), got[i], ref[i]) for i in bad[:8]]
 
 
-def _run(w, W, batch, prec, cal=None):
+def _run(w, W, batch, prec, cal=None, compact=0):
     etx = _etx()
     p = etx.Pipeline(w, W, precision=prec)
+    etx.etx_set_option(p.ctx, etx.ETX_OPT_COMPACT_STATE, compact)
     if cal is not None:
         p.calibrate(etx.to_device(cal))
     b = etx.to_device(batch)
@@ -90,14 +91,17 @@ def _score_stats(gpu, ref):
     return dict(max=float(d.max()), mean=float(d.mean()), p99=float(np.quantile(d, 0.99)))
 
 
-def test_bf16_pipeline_against_quantised_oracle():
+@pytest.mark.parametrize("compact", [0, 1])
+def test_bf16_pipeline_against_quantised_oracle(compact):
+    """BF16 operands with FP32 node and edge state (residual masters), or with
+    the compact BF16 state, each against the oracle in the same form."""
     etx = _etx()
     w = synth.C1
     W = synth.xavier_weights(w)
     batch = synth.generate_batch(w, 1)
     ev = synth.event_slice(batch, 0)
-    p, res = _run(w, W, batch, etx.ETX_BF16)
-    ref_q = O.run_event(ev, w, W, qmode=1)
+    p, res = _run(w, W, batch, etx.ETX_BF16, compact=compact)
+    ref_q = O.run_event(ev, w, W, qmode=1, compact=bool(compact))
     ref_64 = O.run_event(ev, w, W)
     assert np.array_equal(res["src"], ref_q["src"]) and np.array_equal(res["dst"], ref_q["dst"])
     sq = _score_stats(res["score"], ref_q["score"])
@@ -114,25 +118,27 @@ def test_bf16_pipeline_against_quantised_oracle():
     assert np.abs(emb[:, :w.emb_dim] - ref_q["emb"]).max() <= 1e-3
 
 
-def test_fp8_calibration_and_pipeline_against_quantised_oracle():
+@pytest.mark.parametrize("compact", [0, 1])
+def test_fp8_calibration_and_pipeline_against_quantised_oracle(compact):
     etx = _etx()
     w = synth.C1
     W = synth.xavier_weights(w)
     cal = synth.generate_batch(w, 3, seed_space=1001)
     batch = synth.generate_batch(w, 1)
     ev = synth.event_slice(batch, 0)
-    p, res = _run(w, W, batch, etx.ETX_FP8_E4M3, cal)
+    p, res = _run(w, W, batch, etx.ETX_FP8_E4M3, cal, compact=compact)
     # the oracle calibrates itself on the same events
     es, gs, _, _ = O.calibrate([synth.event_slice(cal, i) for i in range(3)], w, W)
     sc = etx.etx_get_scales(p.ctx)
     L = w.emb_layers
     assert np.array_equal(sc[1:L + 1], es[1:L + 1].astype(np.float32))
     assert np.array_equal(sc[8:8 + 8 + w.gnn_steps], gs.astype(np.float32))
-    ref_q = O.run_event(ev, w, W, qmode=2, scales=(es, gs))
+    ref_q = O.run_event(ev, w, W, qmode=2, scales=(es, gs), compact=bool(compact))
     common = np.array_equal(res["src"], ref_q["src"]) and np.array_equal(res["dst"], ref_q["dst"])
     _, cart = O.features(ev["x"], ev["y"], ev["z"], w.r_scale, w.z_scale)
     if not common:   # FP8 embedding: compare the GNN on the GPU's own edge list
-        ref_q_s = O.sigmoid(O.gnn(cart, res["src"], res["dst"], W, w.gnn_hidden, w.gnn_steps, 2, gs))
+        ref_q_s = O.sigmoid(O.gnn(cart, res["src"], res["dst"], W, w.gnn_hidden, w.gnn_steps, 2, gs,
+                                  compact=bool(compact)))
     else:
         ref_q_s = ref_q["score"]
     sq = _score_stats(res["score"], ref_q_s)

@@ -207,6 +207,94 @@ def test_gnn_matches_dense_incidence_torch(H, S):
     np.testing.assert_allclose(got, ref, rtol=1e-10, atol=1e-10)
 
 
+def _pow2_at_or_above(m):
+    """2^ceil(log2(m / 448)) for the FP8 per-tensor scales (1 for m = 0)."""
+    if m <= 0:
+        return 1.0
+    f, e = np.frexp(m / 448.0)
+    return float(np.ldexp(1.0, int(e) - 1 if f == 0.5 else int(e)))
+
+
+def _dense_gnn_quantised(cart, src, dst, weights, H, S, qmode, act_scale, compact):
+    """The quantised network in the dense formulation, rounding with torch's
+    own bfloat16 / float8_e4m3fn casts: every GEMM operand is rounded where it
+    enters the GEMM (FP8: per-tensor activation scales, per-matrix weight
+    scales); the 3-wide first layer, LayerNorm, residual additions, sums and
+    the H -> 1 output layer are not.  compact: h is stored as BF16 and e in
+    the operand format after every write."""
+    T = lambda a: torch.tensor(np.asarray(a), dtype=torch.float64)
+    n, E = len(cart), len(src)
+    Bs = torch.zeros(E, n, dtype=torch.float64); Bs[torch.arange(E), torch.tensor(src, dtype=torch.long)] = 1
+    Bd = torch.zeros(E, n, dtype=torch.float64); Bd[torch.arange(E), torch.tensor(dst, dtype=torch.long)] = 1
+
+    def q(x, s):
+        if qmode == 1:
+            return x.to(torch.bfloat16).to(torch.float64)
+        return (x / s).clamp(-448.0, 448.0).to(torch.float8_e4m3fn).to(torch.float64) * s
+
+    def bf(x):
+        return x.to(torch.bfloat16).to(torch.float64)
+
+    def qw(W):
+        W = T(W)
+        return q(W, _pow2_at_or_above(float(W.abs().max())))
+
+    def ln(x):
+        return F.relu(F.layer_norm(x, (H,), eps=1e-5))
+
+    sc = lambda i: float(act_scale[i]) if act_scale is not None else 1.0
+    (W1, b1), (W2, b2) = weights["node_enc"]
+    t = ln(T(cart) @ T(W1) + T(b1))
+    h = ln(q(t, sc(0)) @ qw(W2) + T(b2))
+    if compact:
+        h = bf(h)
+    (W1, b1), (W2, b2) = weights["edge_enc"]
+    t = ln(torch.cat([q(Bs @ h, sc(1)), q(Bd @ h, sc(1))], 1) @ qw(W1) + T(b1))
+    e = ln(q(t, sc(4)) @ qw(W2) + T(b2))
+    if compact:
+        e = q(e, sc(7))
+    for k in range(S):
+        mo, mi = Bs.T @ e, Bd.T @ e
+        (W1, b1), (W2, b2) = weights[f"node{k}"]
+        t = ln(torch.cat([q(h, sc(1)), q(mo, sc(2)), q(mi, sc(3))], 1) @ qw(W1) + T(b1))
+        h = h + ln(q(t, sc(5)) @ qw(W2) + T(b2))
+        if compact:
+            h = bf(h)
+        (W1, b1), (W2, b2) = weights[f"edge{k}"]
+        t = ln(torch.cat([q(e, sc(7 + k)), q(Bs @ h, sc(1)), q(Bd @ h, sc(1))], 1) @ qw(W1) + T(b1))
+        e = e + ln(q(t, sc(6)) @ qw(W2) + T(b2))
+        if compact:
+            e = q(e, sc(8 + k))
+    (W1, b1), (W2, b2) = weights["cls"]
+    c = ln(q(e, sc(7 + S)) @ qw(W1) + T(b1))
+    return (c @ T(W2) + T(b2))[:, 0].numpy()
+
+
+@pytest.mark.parametrize("qmode,compact", [(1, False), (1, True), (2, False), (2, True)])
+def test_gnn_quantised_matches_dense_torch(qmode, compact):
+    """The quantised oracle network (ch. 4 "Quantization"), with node and
+    edge state kept in full precision or stored in low precision."""
+    rng = np.random.default_rng(21 + qmode)
+    n, E, H, S = 30, 120, 32, 3
+    cart = rng.uniform(-1, 1, (n, 3))
+    src = rng.integers(0, n, E).astype(np.int32)
+    dst = rng.integers(0, n, E).astype(np.int32)
+    W = _random_gnn_weights(H, S, 14)
+    scales = None
+    if qmode == 2:
+        amax = np.zeros(8 + S)
+        O.gnn(cart, src, dst, W, H, S, amax=amax)
+        scales = np.array([_pow2_at_or_above(a) for a in amax])
+    got = O.gnn(cart, src, dst, W, H, S, qmode, scales, compact=compact)
+    ref = _dense_gnn_quantised(cart, src, dst, W, H, S, qmode, scales, compact)
+    np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-9)
+    # the two state formats differ, and both stay near the unquantised network
+    other = O.gnn(cart, src, dst, W, H, S, qmode, scales, compact=not compact)
+    full = O.gnn(cart, src, dst, W, H, S)
+    assert np.abs(got - other).max() > 1e-6
+    assert np.abs(got - full).max() < (0.5 if qmode == 1 else 2.0)
+
+
 def test_gnn_permutation_equivariance():
     rng = np.random.default_rng(5)
     n, E, H, S = 50, 200, 32, 3
