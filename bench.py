@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--pf-recall", type=float, default=0.995, help="c5: positive-edge recall that fixes tau")
     ap.add_argument("--events", type=int, default=None, help="override the number of events")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
+    ap.add_argument("--emb-precision", default=None, choices=["fp32", "bf16", "fp8"],
+                    help="the embedding MLP's own operand precision (default: --precision)")
     ap.add_argument("--compact-state", type=int, default=0,
                     help="bf16/fp8: store node and edge encodings in low precision (default: FP32 master copies)")
     ap.add_argument("--graph", type=int, default=0, help="replay the batch as one captured HIP graph")
@@ -219,9 +221,15 @@ def main():
         return pipe
 
     compact = bool(args.compact_state) and prec != etx.ETX_FP32
-    p = etx.Pipeline(w, weights, precision=prec)
-    etx.etx_set_option(p.ctx, etx.ETX_OPT_COMPACT_STATE, int(compact))
-    p = calibrated(p)
+    emb_prec = {"fp32": etx.ETX_FP32, "bf16": etx.ETX_BF16, "fp8": etx.ETX_FP8_E4M3}[args.emb_precision or args.precision]
+
+    def configured(pipe):
+        etx.etx_set_option(pipe.ctx, etx.ETX_OPT_COMPACT_STATE, int(compact))
+        if emb_prec != prec:
+            etx.etx_set_option(pipe.ctx, etx.ETX_OPT_EMBED_PRECISION, emb_prec)
+        return calibrated(pipe)
+
+    p = configured(etx.Pipeline(w, weights, precision=prec))
     if use_pf:
         etx.etx_prefilter_set(p.ctx, tr["params"])
         etx.etx_prefilter_config(p.ctx, 1, sel["tau"])
@@ -288,9 +296,7 @@ def main():
               file=sys.stderr, flush=True)
     if use_pf:
         # the unpruned pipeline on the same batch: its throughput and efficiency are the reference
-        p0 = etx.Pipeline(w, weights, precision=prec)
-        etx.etx_set_option(p0.ctx, etx.ETX_OPT_COMPACT_STATE, int(compact))
-        p0 = calibrated(p0)
+        p0 = configured(etx.Pipeline(w, weights, precision=prec))
         # the same launch schedule as the pruned pipeline (tuned or default)
         for key in range(etx.ETX_OPT_COMPACT_STATE + 1):
             if key not in (etx.ETX_OPT_PROFILE,):
@@ -336,6 +342,7 @@ def main():
             "workload": f"{w.name}: {n_events} events, {w.n_planes} planes, tracks {w.tracks[0]}({w.tracks[1]}), "
                         f"emb 3-{w.emb_hidden}x{w.emb_layers}-{w.emb_dim}, radius {w.radius}, k {w.k_max}, "
                         f"IN hidden {w.gnn_hidden} x {w.gnn_steps} steps, {args.precision}"
+                        + (f", {args.emb_precision} embedding" if emb_prec != prec else "")
                         + (", compact state" if compact else "") + (", hip graph" if args.graph else ""),
             "events": n_events, "hits": int(b.n_hits), "edges": n_edges, "schedule": tuned,
         },
