@@ -26,7 +26,9 @@
  * exactly rounded BF16 (qmode 1) or FP8-E4M3 (qmode 2, value / S rounded, then
  * times S) value before the FP64 product.  Scales are powers of two chosen
  * from the tensor's absolute maximum (static calibration: the maxima come
- * from an unquantised run of this oracle).  qmode 0 disables it.
+ * from an unquantised run of this oracle).  qmode 0 disables it.  The node
+ * and edge state between layers stays full precision unless the network is
+ * asked to store it compactly (see oracle_gnn).
  */
 #include <math.h>
 #include <stdint.h>

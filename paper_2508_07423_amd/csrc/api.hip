@@ -244,7 +244,7 @@ etx_status check_config(const etx_config* c) {
 }
 
 void clear_graphs(etx_ctx* ctx) {
-  for (auto& kv : ctx->graphs) hipGraphExecDestroy(kv.second);
+  for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
   ctx->graphs.clear();
 }
 
@@ -390,15 +390,19 @@ struct StageTimer {
     if (!ctx->profile) return;
     if (ctx->n_marks == ctx->marks.size()) {
       etx_ctx::Mark m{stage, nullptr, nullptr};
-      if (hipEventCreate(&m.start) != hipSuccess || hipEventCreate(&m.end) != hipSuccess) return;
+      if (hipEventCreate(&m.start) != hipSuccess) return;
+      if (hipEventCreate(&m.end) != hipSuccess) {
+        (void)hipEventDestroy(m.start);
+        return;
+      }
       ctx->marks.push_back(m);
     }
     idx = (int)ctx->n_marks++;
     ctx->marks[idx].stage = stage;
-    hipEventRecord(ctx->marks[idx].start, s);
+    (void)hipEventRecord(ctx->marks[idx].start, s);   // a failed record shows up when the marks are read
   }
   ~StageTimer() {
-    if (idx >= 0) hipEventRecord(ctx->marks[idx].end, s);
+    if (idx >= 0) (void)hipEventRecord(ctx->marks[idx].end, s);
   }
 };
 
@@ -541,16 +545,17 @@ etx_status etx_create(const etx_config* cfg, const void* weights, size_t nbytes,
 
 etx_status etx_destroy(etx_ctx* ctx) {
   if (!ctx) return ETX_ERR_INVALID_ARG;
-  hipSetDevice(ctx->device);
+  // teardown is best effort: a failing release cannot be acted on here
+  (void)hipSetDevice(ctx->device);
   clear_graphs(ctx);
   for (auto& m : ctx->marks) {
-    hipEventDestroy(m.start);
-    hipEventDestroy(m.end);
+    (void)hipEventDestroy(m.start);
+    (void)hipEventDestroy(m.end);
   }
   for (int p = 0; p < 4; ++p)
-    if (ctx->seg_base[p]) hipFree(ctx->seg_base[p]);
-  if (ctx->dev_scales) hipFree(ctx->dev_scales);
-  if (ctx->dev_pf) hipFree(ctx->dev_pf);
+    if (ctx->seg_base[p]) (void)hipFree(ctx->seg_base[p]);
+  if (ctx->dev_scales) (void)hipFree(ctx->dev_scales);
+  if (ctx->dev_pf) (void)hipFree(ctx->dev_pf);
   delete ctx;
   return ETX_OK;
 }
@@ -781,12 +786,12 @@ etx_status etx_run(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void* ws, s
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(s, &g);
     if (e1 != hipSuccess || e2 != hipSuccess || !g) {
-      if (g) hipGraphDestroy(g);
+      if (g) (void)hipGraphDestroy(g);
       return ETX_ERR_HIP;
     }
     hipGraphExec_t ex = nullptr;
     hipError_t e3 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);   // the executable graph keeps what it needs
     if (e3 != hipSuccess) return ETX_ERR_HIP;
     it = ctx->graphs.emplace(key, ex).first;
   }

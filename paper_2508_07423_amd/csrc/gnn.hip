@@ -705,6 +705,10 @@ __global__ __launch_bounds__(256) void k_segsum(GnnArgs A) {
     // slot 0 of each later tile
     const int64_t rb = live ? A.row_ptr[node] : 0, re = live ? A.row_ptr[node + 1] : 0;
     const int64_t cb = live ? A.col_ptr[node] : 0, ce = live ? A.col_ptr[node + 1] : 0;   // issued with rb, re
+    // the first in-edge ids load with the out-sum's partials
+    int id[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) id[u] = cb + u < ce ? A.csc[cb + u] : -1;
     const int64_t t0 = rb / kCols, t1 = re > rb ? (re - 1) / kCols : t0;
     if (live && (re == rb || t1 > t0)) {
       float mo[OPL];
@@ -727,14 +731,14 @@ __global__ __launch_bounds__(256) void k_segsum(GnnArgs A) {
 #pragma unroll
     for (int x = 0; x < FPL; ++x) mi[x] = 0.f;
     for (int64_t t = cb; t < ce; t += U) {
-      int id[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) id[u] = t + u < ce ? A.csc[t + u] : -1;
       uint4 v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u)
         v[u] = id[u] >= 0 ? *reinterpret_cast<const uint4*>(eb + ((int64_t)id[u] * H + fl * FPL) * ES)
                           : make_uint4(0u, 0u, 0u, 0u);
+      // the next ids load while these rows are in flight
+#pragma unroll
+      for (int u = 0; u < U; ++u) id[u] = t + U + u < ce ? A.csc[t + U + u] : -1;
 #pragma unroll
       for (int u = 0; u < U; ++u) add_chunk<P>(mi, v[u]);
     }
@@ -800,16 +804,21 @@ __device__ inline void gather_messages(const GnnArgs& A, int64_t node, bool vali
       for (int64_t i = 0; i <= t1 - t0; ++i) add_cols<H>(mo, A.opart + ((t0 + i) * 2 + (i == 0 ? 1 : 0)) * H, true);
     }
   }
+  int id[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) id[u] = m.id0[u];
   for (int64_t t = cb; t < ce; t += U) {
     RawE<P, H> raw[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int id = t == cb ? m.id0[u] : (t + u < ce ? A.csc[t + u] : -1);
-      if (id >= 0) fetch_e<P, H>(raw[u], A.e, id);
+      if (id[u] >= 0) fetch_e<P, H>(raw[u], A.e, id[u]);
       else
 #pragma unroll
         for (int q = 0; q < ELayout<P, H>::NQ; ++q) raw[u].v[q] = make_uint4(0u, 0u, 0u, 0u);
     }
+    // the next ids load while these rows are in flight
+#pragma unroll
+    for (int u = 0; u < U; ++u) id[u] = t + U + u < ce ? A.csc[t + U + u] : -1;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       float v[H / 4];
