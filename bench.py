@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
-PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
+PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "fp8": 5000.0, "int8": 5000.0}   # dense MFMA (int8: TOP/s)
 
 
 def parse():
@@ -41,8 +41,8 @@ def parse():
     ap.add_argument("--pf-train-events", type=int, default=50000, help="c5: prefilter training events")
     ap.add_argument("--pf-recall", type=float, default=0.995, help="c5: positive-edge recall that fixes tau")
     ap.add_argument("--events", type=int, default=None, help="override the number of events")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
-    ap.add_argument("--emb-precision", default=None, choices=["fp32", "bf16", "fp8"],
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8", "int8"])
+    ap.add_argument("--emb-precision", default=None, choices=["fp32", "bf16", "fp8", "int8"],
                     help="the embedding MLP's own operand precision (default: --precision)")
     ap.add_argument("--compact-state", type=int, default=0,
                     help="bf16/fp8: store node and edge encodings in low precision (default: FP32 master copies)")
@@ -62,7 +62,7 @@ def stage_roofline(stage, ms_total, launches, n_edges, n_hits, H, dtype, compact
         return None
     t = ms_total / launches * 1e-3          # seconds per launch
     # bytes per stored edge-encoding feature: FP32 master copies unless the state is compact
-    es = {"f32": 4, "bf16": 2, "fp8": 1}[dtype] if compact else 4
+    es = {"f32": 4, "bf16": 2, "fp8": 1, "int8": 1}[dtype] if compact else 4
     if stage in ("edge_step", "edge_step_final"):
         # edge net: Linear(3H->H) + Linear(H->H) per edge (the last step adds the
         # classifier Linear(H->H) + Linear(H->1)); bytes: e read and written once
@@ -181,8 +181,9 @@ def main():
 
     w = synth.WORKLOADS[args.workload]
     n_events = args.events or w.n_events
-    prec = {"fp32": etx.ETX_FP32, "bf16": etx.ETX_BF16, "fp8": etx.ETX_FP8_E4M3}[args.precision]
-    dtype = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8"}[args.precision]
+    precs = {"fp32": etx.ETX_FP32, "bf16": etx.ETX_BF16, "fp8": etx.ETX_FP8_E4M3, "int8": etx.ETX_INT8}
+    prec = precs[args.precision]
+    dtype = {"fp32": "f32", "bf16": "bf16", "fp8": "fp8", "int8": "int8"}[args.precision]
     t_gen = time.perf_counter()
     batch = synth.generate_batch(w, n_events)
     use_pf = w.name == "c5"
@@ -210,7 +211,7 @@ def main():
 
     stream = torch.cuda.Stream()
     cal = None
-    if prec == etx.ETX_FP8_E4M3:
+    if prec in (etx.ETX_FP8_E4M3, etx.ETX_INT8) or (args.emb_precision in ("fp8", "int8")):
         # static calibration on events of a disjoint seed space (on the unpruned graph, before the prefilter is on)
         cal = etx.to_device(synth.generate_batch(w, 20, seed_space=1000 + w.cid))
 
@@ -220,8 +221,8 @@ def main():
                 pipe.calibrate(cal, stream=stream)
         return pipe
 
-    compact = bool(args.compact_state) and prec != etx.ETX_FP32
-    emb_prec = {"fp32": etx.ETX_FP32, "bf16": etx.ETX_BF16, "fp8": etx.ETX_FP8_E4M3}[args.emb_precision or args.precision]
+    compact = bool(args.compact_state) and prec in (etx.ETX_BF16, etx.ETX_FP8_E4M3)
+    emb_prec = precs[args.emb_precision or args.precision]
 
     def configured(pipe):
         etx.etx_set_option(pipe.ctx, etx.ETX_OPT_COMPACT_STATE, int(compact))

@@ -50,7 +50,7 @@ typedef enum {
   ETX_ERR_HIP = 6            /* a HIP runtime call failed */
 } etx_status;
 
-typedef enum { ETX_FP32 = 0, ETX_BF16 = 1, ETX_FP8_E4M3 = 2 } etx_precision;
+typedef enum { ETX_FP32 = 0, ETX_BF16 = 1, ETX_FP8_E4M3 = 2, ETX_INT8 = 3 } etx_precision;
 
 /* Largest event (hits) the per-event kernels accept. */
 #define ETX_MAX_EVENT_HITS 16384
@@ -208,21 +208,26 @@ etx_status etx_autotune(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void* 
 /* Static calibration for the low-precision modes (thesis ch. 4 "Quantization",
  * static post-training quantisation): runs the FP32 path on `hits`, records
  * the per-tensor absolute maximum of every quantised activation, and sets the
- * per-tensor scales S = amax / 448 (FP8-E4M3).  Synchronises the stream. */
+ * per-tensor scales of both 8-bit formats: FP8-E4M3 the power of two at or
+ * above amax / 448, INT8 S = amax / 127 (symmetric, thesis ch. 4
+ * "Quantization").  Synchronises the stream.  Needed before FP8 or INT8 runs. */
 etx_status etx_calibrate(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void* ws, size_t ws_bytes,
                          etx_stream stream);
 /* Switch the GEMM operand precision (etx_precision) of an existing context
- * (all three weight formats are built at etx_create). */
+ * (every weight format is built at etx_create). */
 etx_status etx_set_precision(etx_ctx* ctx, int32_t precision);
-/* Copy the first n (<= 256) per-tensor scales: activation slots 0..63 (0..7
+/* Copy the first n (<= 512) per-tensor scales: activation slots 0..63 (0..7
  * embedding layer inputs; 8 + {0 node-encoder layer-2 input, 1 node
  * encodings, 2 out-sums, 3 in-sums, 4 edge-encoder layer-2 input, 5 node-net
  * layer-2 inputs, 6 edge-net layer-2 inputs, 7 + k stored edge encodings e_k}),
- * weight slots 64..255.  Every scale is a power of two >= amax / 448. */
+ * weight slots 64..255: the FP8 scales, each a power of two >= amax / 448;
+ * slots 256 + i: the INT8 scales of the same tensors, amax / 127. */
 etx_status etx_get_scales(const etx_ctx* ctx, float* scales, int32_t n);
 /* Round n device floats through the library's operand format: out = in
- * rounded to BF16 (nearest even), or scale * E4M3(in / scale) (nearest even,
- * saturating at +-448); FP32 copies.  Asynchronous on `stream`. */
+ * rounded to BF16 (nearest even), scale * E4M3(in / scale) (nearest even,
+ * saturating at +-448), or scale * clip(round(in * (1 / scale)), -127, 127)
+ * (INT8, nearest even; the product with the FP32 reciprocal is what the GEMMs
+ * quantise); FP32 copies.  Asynchronous on `stream`. */
 etx_status etx_quantize(int32_t precision, const float* in, float* out, int64_t n, float scale, etx_stream stream);
 
 /* Learned edge prefilter: MLP 6 -> 32 -> 32 -> 1 (ReLU) on the candidate-edge

@@ -23,10 +23,12 @@
  *
  * Optional quantisation (thesis ch. 4 "Quantization", symmetric scale
  * x = S x_q with a per-tensor scale): every GEMM operand is replaced by its
- * exactly rounded BF16 (qmode 1) or FP8-E4M3 (qmode 2, value / S rounded, then
- * times S) value before the FP64 product.  Scales are powers of two chosen
- * from the tensor's absolute maximum (static calibration: the maxima come
- * from an unquantised run of this oracle).  qmode 0 disables it.  The node
+ * exactly rounded BF16 (qmode 1), FP8-E4M3 (qmode 2, value / S rounded, then
+ * times S) or INT8 (qmode 3, value / S rounded to an integer in [-127, 127],
+ * then times S) value before the FP64 product.  FP8 scales are powers of two
+ * chosen from the tensor's absolute maximum, INT8 scales are that maximum over
+ * 127 (static calibration: the maxima come from an unquantised run of this
+ * oracle).  qmode 0 disables it.  The node
  * and edge state between layers stays full precision unless the network is
  * asked to store it compactly (see oracle_gnn).
  */
@@ -60,10 +62,17 @@ static double round_format(double x, int mbits, int emin, double maxv) {
 double oracle_round_bf16(double x) { return round_format(x, 7, -126, 3.3895313892515355e38); }
 double oracle_round_e4m3(double x) { return round_format(x, 3, -6, 448.0); }
 
+/* symmetric INT8 code of v (= x / S): round to nearest, ties to even, clipped to +-127 */
+double oracle_round_int8(double v) {
+  double q = nearbyint(v);
+  return q > 127.0 ? 127.0 : (q < -127.0 ? -127.0 : q);
+}
+
 /* quantise a GEMM operand: value -> S * round(value / S) (S = 1 for BF16) */
 static double qv(int mode, double x, double scale) {
   if (mode == 1) return oracle_round_bf16(x);
   if (mode == 2) return scale * oracle_round_e4m3(x / scale);
+  if (mode == 3) return scale * oracle_round_int8(x / scale);
   return x;
 }
 
@@ -76,10 +85,13 @@ double oracle_pow2_scale(double amax) {
   return ldexp(1.0, f == 0.5 ? e - 1 : e);
 }
 
-/* weight scale of a K x M layer */
-static double wscale(const double* W, int64_t n) {
+/* weight scale of a K x M layer: FP8 the power of two at or above max|W| / 448,
+ * INT8 (qmode 3) max|W| / 127, the thesis's symmetric range [-max, max]
+ * mapped onto [-127, 127] */
+static double wscale(int qmode, const double* W, int64_t n) {
   double m = 0.0;
   for (int64_t i = 0; i < n; ++i) m = fabs(W[i]) > m ? fabs(W[i]) : m;
+  if (qmode == 3) return m > 0.0 ? m / 127.0 : 1.0;
   return oracle_pow2_scale(m);
 }
 
@@ -168,7 +180,7 @@ void oracle_embed(int64_t n, const double* cyl, int n_layers, const int* dims, c
   {
     const double* p = params;
     for (int l = 0; l < n_layers && l < 16; ++l) {
-      ws[l] = wscale(p, (int64_t)dims[l] * dims[l + 1]);
+      ws[l] = wscale(qmode, p, (int64_t)dims[l] * dims[l + 1]);
       p += (int64_t)dims[l] * dims[l + 1] + dims[l + 1];
     }
   }
@@ -285,7 +297,7 @@ void oracle_radius_margins(int64_t n, const int32_t* plane, const double* emb, i
 /* interaction network                                                       */
 /* ------------------------------------------------------------------------ */
 
-/* Activation-scale slots of the quantised interaction network (qmode 2) and
+/* Activation-scale slots of the quantised interaction network (qmode 2, 3) and
  * of the amax observers; the same tensors are quantised in qmode 1 (BF16,
  * no scale):
  *   0 node-encoder layer-2 input      1 node encodings h (every GEMM use)
@@ -305,7 +317,7 @@ enum { Q_NE2 = 0, Q_H = 1, Q_MO = 2, Q_MI = 3, Q_EE2 = 4, Q_NN2 = 5, Q_EN2 = 6, 
 /* Parameter block order: node encoder (3->H->H), edge encoder (2H->H->H),
  * then per step k: node net k (3H->H->H), edge net k (3H->H->H), then the
  * classifier Block(H->H) and Linear(H->1).  Block(x) = ReLU(LN(x W + b)).
- * qmode 0: plain FP64.  act_scale: [8 + S] slots above (qmode 2).  amax
+ * qmode 0: plain FP64.  act_scale: [8 + S] slots above (qmode 2, 3).  amax
  * (may be NULL, [8 + S]): running max |x| of every quantised tensor.
  * compact (qmode 1, 2): store h and e in low precision (above). */
 void oracle_gnn(int64_t n, const double* cart, int64_t E, const int32_t* src, const int32_t* dst,
@@ -327,7 +339,7 @@ void oracle_gnn(int64_t n, const double* cart, int64_t E, const int32_t* src, co
   /* node encoder: h0 = Block(Block(x/R, y/R, z/Z)); the 3-wide layer is not quantised */
   {
     const double *W1 = p, *b1 = p + 3 * H, *W2 = b1 + H, *b2 = W2 + HH;
-    double s2 = wscale(W2, HH);
+    double s2 = wscale(qmode, W2, HH);
     for (int64_t l = 0; l < n; ++l) {
       linear(cart + 3 * l, 3, W1, b1, H, tmp, 0, 1.0, 1.0);
       layernorm_relu(tmp, H);
@@ -341,13 +353,13 @@ void oracle_gnn(int64_t n, const double* cart, int64_t E, const int32_t* src, co
   /* edge encoder: e0_ij = Block(Block([h_i, h_j])) */
   {
     const double *W1 = p, *b1 = p + 2 * HH, *W2 = b1 + H, *b2 = W2 + HH;
-    double s1 = wscale(W1, 2 * HH), s2 = wscale(W2, HH);
+    double s1 = wscale(qmode, W1, 2 * HH), s2 = wscale(qmode, W2, HH);
     double sh[2] = {SC(Q_H), SC(Q_H)};
     for (int64_t l = 0; l < n; ++l) observe(amax, Q_H, h + l * H, H);
     for (int64_t t = 0; t < E; ++t) {
       memcpy(in, h + (int64_t)src[t] * H, sizeof(double) * H);
       memcpy(in + H, h + (int64_t)dst[t] * H, sizeof(double) * H);
-      linear_blocks(in, 2, H, W1, b1, H, tmp, qmode, qmode == 2 ? sh : NULL, s1);
+      linear_blocks(in, 2, H, W1, b1, H, tmp, qmode, qmode >= 2 ? sh : NULL, s1);
       layernorm_relu(tmp, H);
       observe(amax, Q_EE2, tmp, H);
       linear(tmp, H, W2, b2, H, e + t * H, qmode, SC(Q_EE2), s2);
@@ -370,7 +382,7 @@ void oracle_gnn(int64_t n, const double* cart, int64_t E, const int32_t* src, co
     /* node update with residual: h <- h + Block(Block([h, mo, mi])) */
     {
       const double *W1 = p, *b1 = p + 3 * HH, *W2 = b1 + H, *b2 = W2 + HH;
-      double s1 = wscale(W1, 3 * HH), s2 = wscale(W2, HH);
+      double s1 = wscale(qmode, W1, 3 * HH), s2 = wscale(qmode, W2, HH);
       double sb[3] = {SC(Q_H), SC(Q_MO), SC(Q_MI)};
       for (int64_t l = 0; l < n; ++l) {
         memcpy(in, h + l * H, sizeof(double) * H);
@@ -379,7 +391,7 @@ void oracle_gnn(int64_t n, const double* cart, int64_t E, const int32_t* src, co
         observe(amax, Q_H, in, H);
         observe(amax, Q_MO, in + H, H);
         observe(amax, Q_MI, in + 2 * H, H);
-        linear_blocks(in, 3, H, W1, b1, H, tmp, qmode, qmode == 2 ? sb : (qmode ? one : NULL), s1);
+        linear_blocks(in, 3, H, W1, b1, H, tmp, qmode, qmode >= 2 ? sb : (qmode ? one : NULL), s1);
         layernorm_relu(tmp, H);
         observe(amax, Q_NN2, tmp, H);
         linear(tmp, H, W2, b2, H, out, qmode, SC(Q_NN2), s2);
@@ -391,14 +403,14 @@ void oracle_gnn(int64_t n, const double* cart, int64_t E, const int32_t* src, co
     /* edge update with residual, using the updated h */
     {
       const double *W1 = p, *b1 = p + 3 * HH, *W2 = b1 + H, *b2 = W2 + HH;
-      double s1 = wscale(W1, 3 * HH), s2 = wscale(W2, HH);
+      double s1 = wscale(qmode, W1, 3 * HH), s2 = wscale(qmode, W2, HH);
       double sb[3] = {SC(Q_E + k), SC(Q_H), SC(Q_H)};
       for (int64_t l = 0; l < n; ++l) observe(amax, Q_H, h + l * H, H);
       for (int64_t t = 0; t < E; ++t) {
         memcpy(in, e + t * H, sizeof(double) * H);
         memcpy(in + H, h + (int64_t)src[t] * H, sizeof(double) * H);
         memcpy(in + 2 * H, h + (int64_t)dst[t] * H, sizeof(double) * H);
-        linear_blocks(in, 3, H, W1, b1, H, tmp, qmode, qmode == 2 ? sb : (qmode ? one : NULL), s1);
+        linear_blocks(in, 3, H, W1, b1, H, tmp, qmode, qmode >= 2 ? sb : (qmode ? one : NULL), s1);
         layernorm_relu(tmp, H);
         observe(amax, Q_EN2, tmp, H);
         linear(tmp, H, W2, b2, H, out, qmode, SC(Q_EN2), s2);
@@ -414,7 +426,7 @@ void oracle_gnn(int64_t n, const double* cart, int64_t E, const int32_t* src, co
   /* classifier: Linear(H->1)(Block(H->H)(e)); the input is the stored e_S */
   {
     const double *W1 = p, *b1 = p + HH, *w2 = b1 + H, *b2 = w2 + H;
-    double s1 = wscale(W1, HH);
+    double s1 = wscale(qmode, W1, HH);
     for (int64_t t = 0; t < E; ++t) {
       linear(e + t * H, H, W1, b1, H, tmp, qmode, SC(Q_E + S), s1);
       layernorm_relu(tmp, H);

@@ -62,6 +62,8 @@ def lib():
         L.oracle_round_bf16.restype = dbl
         L.oracle_round_e4m3.argtypes = [dbl]
         L.oracle_round_e4m3.restype = dbl
+        L.oracle_round_int8.argtypes = [dbl]
+        L.oracle_round_int8.restype = dbl
         L.oracle_prefilter_features.argtypes = [i64, P, P, P, P, P, P, i32, dbl, dbl, P]
         L.oracle_prefilter_forward.argtypes = [i64, P, i32, P, P, i32]
         L.oracle_prefilter_loss_grad.argtypes = [i64, P, P, i32, P, dbl, P, i32]
@@ -202,6 +204,18 @@ def round_e4m3(x: float) -> float:
     return lib().oracle_round_e4m3(float(x))
 
 
+def round_int8(v: float) -> float:
+    """Symmetric INT8 code of v = x / S: nearest integer (ties to even) in [-127, 127]."""
+    return lib().oracle_round_int8(float(v))
+
+
+def int8_scales(amax: np.ndarray) -> np.ndarray:
+    """INT8 per-tensor scales S = amax / 127 (thesis ch. 4 "Quantization",
+    symmetric range); 1 where a tensor is all zero."""
+    amax = np.asarray(amax, np.float64)
+    return np.where(amax > 0, amax / 127.0, 1.0)
+
+
 # ---------------------------------------------------------------------------
 # whole pipeline
 # ---------------------------------------------------------------------------
@@ -210,8 +224,9 @@ def run_event(ev: Dict[str, np.ndarray], w, weights, with_margins: bool = False,
               scales=None, emb_qmode: Optional[int] = None, compact: bool = False) -> Dict[str, np.ndarray]:
     """The full hot path on one event.  ``w`` carries the workload constants
     (r_scale, z_scale, radius, k_max, plane_window, gnn_hidden, gnn_steps,
-    threshold); ``weights`` the network parameters.  qmode 1 (BF16) or 2 (FP8,
-    ``scales`` from ``calibrate``) quantises the GEMM operands; ``emb_qmode``
+    threshold); ``weights`` the network parameters.  qmode 1 (BF16), 2 (FP8,
+    ``scales`` from ``calibrate``) or 3 (INT8, ``scales`` from ``int8_scales``
+    of calibrate's maxima) quantises the GEMM operands; ``emb_qmode``
     gives the embedding its own mode (default: qmode); ``compact`` stores the
     network's node and edge state in low precision (see ``gnn``)."""
     cyl, cart = features(ev["x"], ev["y"], ev["z"], w.r_scale, w.z_scale)

@@ -114,7 +114,7 @@ static float pow2_scale(double amax) {
 }
 
 // Write a row-major [K][M] weight (M padded to Mpad) permuted for the column
-// layout of tile.hpp in operand format `prec`; FP8 stores W / scale.
+// layout of tile.hpp in segment format `prec`; FP8 and INT8 store codes of W / scale.
 static float bf16_float(uint16_t b) {
   const uint32_t u = (uint32_t)b << 16;
   float f;
@@ -122,7 +122,7 @@ static float bf16_float(uint16_t b) {
   return f;
 }
 
-static void put_perm(char* out, const float* W, int K, int M, int Mpad, int prec, float scale) {
+static void put_perm(char* out, const float* W, int K, int M, int Mpad, int prec, double scale) {
   for (int mb = 0; mb < Mpad / 16; ++mb)
     for (int lane = 0; lane < 64; ++lane) {
       const int col = 16 * mb + lane % 16, g = lane / 16;
@@ -151,6 +151,10 @@ static void put_perm(char* out, const float* W, int K, int M, int Mpad, int prec
             } else if (prec == ETX_BF16) {
               uint16_t b = host_bf16(v);
               std::memcpy(out + at * 2, &b, 2);
+            } else if (prec == kI8Seg) {
+              // symmetric INT8: clip(round(W / S), -127, 127), ties to even
+              const double q = std::nearbyint((double)v / scale);
+              out[at] = (char)(int8_t)std::max(-127.0, std::min(127.0, q));
             } else {
               out[at] = (char)host_e4m3((double)v / scale);
             }
@@ -237,7 +241,7 @@ etx_status check_config(const etx_config* c) {
   if (c->gnn_hidden != 32 && c->gnn_hidden != 64) return ETX_ERR_UNSUPPORTED;
   if (c->gnn_steps < 1 || c->gnn_steps > 16) return ETX_ERR_UNSUPPORTED;
   if (!std::isfinite(c->edge_threshold)) return ETX_ERR_INVALID_ARG;
-  if (c->precision < ETX_FP32 || c->precision > ETX_FP8_E4M3) return ETX_ERR_INVALID_ARG;
+  if (c->precision < ETX_FP32 || c->precision > ETX_INT8) return ETX_ERR_INVALID_ARG;
   if (c->prefilter != 0 && c->prefilter != 1) return ETX_ERR_INVALID_ARG;
   if (!std::isfinite(c->prefilter_tau)) return ETX_ERR_INVALID_ARG;
   return ETX_OK;
@@ -254,7 +258,7 @@ void clear_graphs(etx_ctx* ctx) {
 static etx_status build_segments(etx_ctx* ctx, const std::vector<BlobLayer>& Ls, int prec) {
   const etx_config& c = ctx->cfg;
   const int W = c.emb_hidden, H = c.gnn_hidden, S = c.gnn_steps, LE = c.emb_layers;
-  const int ES = kPrecBytes[prec];
+  const int ES = kSegBytes[prec];
   WeightMap& m = ctx->wmap[prec];
   std::vector<char> buf;
   auto reserve = [&](int n) {
@@ -263,7 +267,9 @@ static etx_status build_segments(etx_ctx* ctx, const std::vector<BlobLayer>& Ls,
     return at;
   };
   auto put_vec = [&](int64_t at, const float* v, int n) { std::memcpy(buf.data() + at, v, sizeof(float) * n); };
-  const float* sc = ctx->host_scales;
+  // weight scales of this set (INT8: the exact max|W| / 127 the codes divide by)
+  double sc[N_SCALES] = {};
+  for (int i = 0; i < 256; ++i) sc[i] = prec == kI8Seg ? ctx->i8_wscale[i] : (double)ctx->host_scales[i];
   size_t li = 0;
   {
     SegEmb s{W, LE, ES};
@@ -337,7 +343,8 @@ static etx_status build_segments(etx_ctx* ctx, const std::vector<BlobLayer>& Ls,
   return ETX_OK;
 }
 
-// Per-layer power-of-two weight scales (FP8 operands) into host_scales[64..].
+// Per-layer weight scales into host_scales: FP8 powers of two at 64.., INT8
+// max|W| / 127 at SC_I8 + 64.. (and exactly in i8_wscale).
 static void weight_scales(etx_ctx* ctx, const std::vector<BlobLayer>& Ls) {
   const etx_config& c = ctx->cfg;
   const int S = c.gnn_steps, LE = c.emb_layers;
@@ -356,6 +363,25 @@ static void weight_scales(etx_ctx* ctx, const std::vector<BlobLayer>& Ls) {
   for (int k = 0; k < S; ++k)
     for (int j = 0; j < 4; ++j) sc[SW_STEP + 4 * k + j] = pow2_scale(amax(Ls[li++]));
   sc[SW_CLS1] = pow2_scale(amax(Ls[li++]));
+  // the INT8 set: max|W| / 127 for the same layers (1 for an all-zero layer)
+  for (int i = 0; i < 256; ++i) ctx->i8_wscale[i] = 1.0;
+  li = 0;
+  auto i8 = [&](int slot, const BlobLayer& L) {
+    const double m = amax(L);
+    ctx->i8_wscale[slot] = m > 0.0 ? m / 127.0 : 1.0;
+  };
+  for (int l = 0; l <= LE; ++l) {
+    const BlobLayer& L = Ls[li++];
+    if (l >= 1) i8(SW_EMB + l, L);
+  }
+  li++;
+  i8(SW_NE2, Ls[li++]);
+  i8(SW_EE1, Ls[li++]);
+  i8(SW_EE2, Ls[li++]);
+  for (int k = 0; k < S; ++k)
+    for (int j = 0; j < 4; ++j) i8(SW_STEP + 4 * k + j, Ls[li++]);
+  i8(SW_CLS1, Ls[li++]);
+  for (int i = 0; i < 256; ++i) sc[SC_I8 + i] = (float)ctx->i8_wscale[i];
 }
 
 thread_local std::string g_last_error;
@@ -529,7 +555,7 @@ etx_status etx_create(const etx_config* cfg, const void* weights, size_t nbytes,
   }
   weight_scales(ctx, layers);
   st = ETX_OK;
-  for (int p = 0; p < 4 && st == ETX_OK; ++p) st = build_segments(ctx, layers, p);
+  for (int p = 0; p < kNumSegs && st == ETX_OK; ++p) st = build_segments(ctx, layers, p);
   if (st == ETX_OK && hipMalloc(&ctx->dev_scales, sizeof(float) * N_SCALES) != hipSuccess) st = ETX_ERR_HIP;
   if (st == ETX_OK && hipMemcpy(ctx->dev_scales, ctx->host_scales, sizeof(float) * N_SCALES, hipMemcpyHostToDevice) != hipSuccess)
     st = ETX_ERR_HIP;
@@ -552,7 +578,7 @@ etx_status etx_destroy(etx_ctx* ctx) {
     (void)hipEventDestroy(m.start);
     (void)hipEventDestroy(m.end);
   }
-  for (int p = 0; p < 4; ++p)
+  for (int p = 0; p < kNumSegs; ++p)
     if (ctx->seg_base[p]) (void)hipFree(ctx->seg_base[p]);
   if (ctx->dev_scales) (void)hipFree(ctx->dev_scales);
   if (ctx->dev_pf) (void)hipFree(ctx->dev_pf);
@@ -631,7 +657,7 @@ etx_status etx_set_option(etx_ctx* ctx, int32_t key, int64_t value) {
       ctx->edge_wreg = (int)value;
       break;
     case ETX_OPT_EMBED_PRECISION:
-      if (value < -1 || value > ETX_FP8_E4M3) return ETX_ERR_INVALID_ARG;
+      if (value < -1 || value > ETX_INT8) return ETX_ERR_INVALID_ARG;
       ctx->emb_precision = (int)value;
       break;
     case ETX_OPT_OUTSUM_LDS:
@@ -745,6 +771,7 @@ etx_status etx_get_option(const etx_ctx* ctx, int32_t key, int64_t* value) {
 // state in FP32 unless the compact form is asked for.
 static int kernel_precision(const etx_ctx* ctx) {
   const int p = ctx->cfg.precision;
+  if (p == ETX_INT8) return kI8Master;          // INT8 keeps the state in FP32 only
   if (p == ETX_FP32 || ctx->compact_state) return p;
   return p == ETX_BF16 ? kBf16Master : kFp8Master;
 }
@@ -753,8 +780,8 @@ etx_status etx_run(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void* ws, s
   WsLayout L;
   etx_status st = check_run_args(ctx, hits, out, ws, ws_bytes, &L);
   if (st != ETX_OK) return st;
-  if ((ctx->cfg.precision == ETX_FP8_E4M3 || ctx->emb_precision == ETX_FP8_E4M3) && !ctx->calibrated)
-    return ETX_ERR_INVALID_ARG;
+  auto scaled = [](int p) { return p == ETX_FP8_E4M3 || p == ETX_INT8; };
+  if ((scaled(ctx->cfg.precision) || scaled(ctx->emb_precision)) && !ctx->calibrated) return ETX_ERR_INVALID_ARG;
   if (ctx->cfg.prefilter && !ctx->pf_set) return ETX_ERR_INVALID_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return ETX_ERR_HIP;
   RunArgs a{ctx, *hits, *out, L, static_cast<char*>(ws), static_cast<hipStream_t>(stream), false,
@@ -817,8 +844,11 @@ etx_status etx_calibrate(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void*
     return ETX_ERR_HIP;
   }
   if (status[0] != ETX_OK) return (etx_status)status[0];
-  for (int i = 0; i < ETX_N_CALIB; ++i) ctx->host_scales[i] = pow2_scale(amax[i]);
-  if ((e = hipMemcpy(ctx->dev_scales, ctx->host_scales, sizeof(float) * ETX_N_CALIB, hipMemcpyHostToDevice)) !=
+  for (int i = 0; i < ETX_N_CALIB; ++i) {
+    ctx->host_scales[i] = pow2_scale(amax[i]);
+    ctx->host_scales[SC_I8 + i] = amax[i] > 0.f ? (float)((double)amax[i] / 127.0) : 1.0f;
+  }
+  if ((e = hipMemcpy(ctx->dev_scales, ctx->host_scales, sizeof(float) * N_SCALES, hipMemcpyHostToDevice)) !=
       hipSuccess) {
     note_error("etx_calibrate upload", e);
     return ETX_ERR_HIP;
@@ -829,7 +859,7 @@ etx_status etx_calibrate(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void*
 }
 
 etx_status etx_set_precision(etx_ctx* ctx, int32_t precision) {
-  if (!ctx || precision < ETX_FP32 || precision > ETX_FP8_E4M3) return ETX_ERR_INVALID_ARG;
+  if (!ctx || precision < ETX_FP32 || precision > ETX_INT8) return ETX_ERR_INVALID_ARG;
   ctx->cfg.precision = precision;
   clear_graphs(ctx);
   return ETX_OK;
@@ -842,7 +872,7 @@ etx_status etx_get_scales(const etx_ctx* ctx, float* scales, int32_t n) {
 }
 
 etx_status etx_quantize(int32_t precision, const float* in, float* out, int64_t n, float scale, etx_stream stream) {
-  if (precision < ETX_FP32 || precision > ETX_FP8_E4M3 || n < 0 || (n > 0 && (!in || !out)) || !(scale > 0))
+  if (precision < ETX_FP32 || precision > ETX_INT8 || n < 0 || (n > 0 && (!in || !out)) || !(scale > 0))
     return ETX_ERR_INVALID_ARG;
   if (n == 0) return ETX_OK;
   hipError_t e = launch_quantize(precision, in, out, n, scale, static_cast<hipStream_t>(stream));

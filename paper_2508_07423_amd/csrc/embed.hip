@@ -95,7 +95,9 @@ hipError_t launch_embed(const RunArgs& a) {
   if (a.hits.n_hits == 0) return hipSuccess;
   const etx_ctx* c = a.ctx;
   // the embedding may run at its own operand precision (calibration runs stay FP32)
-  const int prec = (!a.calibrate && c->emb_precision >= 0) ? c->emb_precision : kSegPrec[a.prec];
+  const int ep = (!a.calibrate && c->emb_precision >= 0) ? c->emb_precision : kEtxPrec[a.prec];
+  const int prec = ep == ETX_INT8 ? kI8Seg : ep;                       // weight segment set
+  const int kp = ep == ETX_INT8 ? (int)P_I8M : ep;                     // kernel precision
   EmbedArgs A;
   A.x = a.hits.x;
   A.y = a.hits.y;
@@ -105,26 +107,29 @@ hipError_t launch_embed(const RunArgs& a) {
   A.inv_z = 1.0f / c->cfg.z_scale_mm;
   A.seg = static_cast<const char*>(c->seg_base[prec]) + c->wmap[prec].emb;
   A.layers = c->cfg.emb_layers;
-  A.sc = c->dev_scales;
+  A.sc = c->dev_scales + (ep == ETX_INT8 ? SC_I8 : 0);
   A.emb = reinterpret_cast<float*>(a.ws + a.L.emb);
   A.calib = a.calibrate ? reinterpret_cast<float*>(a.ws + a.L.calib) : nullptr;
   A.status = a.out.status;
   const int W = c->cfg.emb_hidden;
-  A.seg_bytes = SegEmb{W, A.layers, kPrecBytes[prec]}.size();
+  A.seg_bytes = SegEmb{W, A.layers, kSegBytes[prec]}.size();
   size_t lds = A.seg_bytes;
   int64_t tiles = (A.n_hits + kCols - 1) / kCols;
   unsigned grid = (unsigned)std::min<int64_t>((tiles + 3) / 4, (int64_t)c->n_cu * 2);
 #define EMB(W_, P_) hipLaunchKernelGGL((k_embed<W_, P_>), dim3(grid), dim3(256), lds, a.stream, A)
-  switch (W * 4 + prec) {
-    case 32 * 4 + 0: EMB(32, 0); break;
-    case 32 * 4 + 1: EMB(32, 1); break;
-    case 32 * 4 + 2: EMB(32, 2); break;
-    case 64 * 4 + 0: EMB(64, 0); break;
-    case 64 * 4 + 1: EMB(64, 1); break;
-    case 64 * 4 + 2: EMB(64, 2); break;
-    case 128 * 4 + 0: EMB(128, 0); break;
-    case 128 * 4 + 1: EMB(128, 1); break;
-    case 128 * 4 + 2: EMB(128, 2); break;
+  switch (W * 8 + kp) {
+    case 32 * 8 + 0: EMB(32, 0); break;
+    case 32 * 8 + 1: EMB(32, 1); break;
+    case 32 * 8 + 2: EMB(32, 2); break;
+    case 32 * 8 + 6: EMB(32, 6); break;
+    case 64 * 8 + 0: EMB(64, 0); break;
+    case 64 * 8 + 1: EMB(64, 1); break;
+    case 64 * 8 + 2: EMB(64, 2); break;
+    case 64 * 8 + 6: EMB(64, 6); break;
+    case 128 * 8 + 0: EMB(128, 0); break;
+    case 128 * 8 + 1: EMB(128, 1); break;
+    case 128 * 8 + 2: EMB(128, 2); break;
+    case 128 * 8 + 6: EMB(128, 6); break;
     default: return hipErrorInvalidValue;
   }
 #undef EMB
@@ -139,12 +144,15 @@ int embed_attributes(size_t max_lds) {
   set(reinterpret_cast<const void*>(k_embed<32, 0>));
   set(reinterpret_cast<const void*>(k_embed<32, 1>));
   set(reinterpret_cast<const void*>(k_embed<32, 2>));
+  set(reinterpret_cast<const void*>(k_embed<32, 6>));
   set(reinterpret_cast<const void*>(k_embed<64, 0>));
   set(reinterpret_cast<const void*>(k_embed<64, 1>));
   set(reinterpret_cast<const void*>(k_embed<64, 2>));
+  set(reinterpret_cast<const void*>(k_embed<64, 6>));
   set(reinterpret_cast<const void*>(k_embed<128, 0>));
   set(reinterpret_cast<const void*>(k_embed<128, 1>));
   set(reinterpret_cast<const void*>(k_embed<128, 2>));
+  set(reinterpret_cast<const void*>(k_embed<128, 6>));
   return bad;
 }
 

@@ -886,6 +886,11 @@ __global__ __launch_bounds__(NodeThreads<P>::value) void k_node_step(GnnArgs A) 
       mfma_fp8<3 * H, H / 16, 0, H / 32>(a, x, w1, 1.0f / s_h, s_h * w1s);
       mfma_fp8<3 * H, H / 16, H / 32, 2 * H / 32>(a, x, w1, 1.0f / s_mo, s_mo * w1s);
       mfma_fp8<3 * H, H / 16, 2 * H / 32, 3 * H / 32>(a, x, w1, 1.0f / s_mi, s_mi * w1s);
+    } else if constexpr (kI8Ops<P>) {
+      const uint64_t* w1 = reinterpret_cast<const uint64_t*>(w + S.w1());
+      mfma_i8<3 * H, H / 16, 0, H / 32>(a, x, w1, 1.0f / s_h, s_h * w1s);
+      mfma_i8<3 * H, H / 16, H / 32, 2 * H / 32>(a, x, w1, 1.0f / s_mo, s_mo * w1s);
+      mfma_i8<3 * H, H / 16, 2 * H / 32, 3 * H / 32>(a, x, w1, 1.0f / s_mi, s_mi * w1s);
     } else {
       gemm<P, 3 * H, H / 16>(a, x, w + S.w1(), 1.f, 1.f);
     }
@@ -1079,7 +1084,7 @@ static GnnArgs gnn_args(const RunArgs& a) {
   A.opart = reinterpret_cast<float*>(a.ws + a.L.opart);
   A.score = a.out.score;
   A.calib = a.calibrate ? reinterpret_cast<float*>(a.ws + a.L.calib) : nullptr;
-  A.sc = c->dev_scales;
+  A.sc = c->dev_scales + (a.prec == P_I8M ? SC_I8 : 0);   // the INT8 scale set
   A.xcd_map = a.ctx->xcd_map;
   A.status = a.out.status;
   return A;
@@ -1106,11 +1111,13 @@ static const char* seg_ptr(const RunArgs& a, int64_t off) {
     case 32 * 8 + 2: { constexpr int H = 32, P = 2; __VA_ARGS__; } break;  \
     case 32 * 8 + 4: { constexpr int H = 32, P = 4; __VA_ARGS__; } break;  \
     case 32 * 8 + 5: { constexpr int H = 32, P = 5; __VA_ARGS__; } break;  \
+    case 32 * 8 + 6: { constexpr int H = 32, P = 6; __VA_ARGS__; } break;  \
     case 64 * 8 + 0: { constexpr int H = 64, P = 0; __VA_ARGS__; } break;  \
     case 64 * 8 + 1: { constexpr int H = 64, P = 1; __VA_ARGS__; } break;  \
     case 64 * 8 + 2: { constexpr int H = 64, P = 2; __VA_ARGS__; } break;  \
     case 64 * 8 + 4: { constexpr int H = 64, P = 4; __VA_ARGS__; } break;  \
     case 64 * 8 + 5: { constexpr int H = 64, P = 5; __VA_ARGS__; } break;  \
+    case 64 * 8 + 6: { constexpr int H = 64, P = 6; __VA_ARGS__; } break;  \
     default: return hipErrorInvalidValue;                                   \
   }
 
@@ -1219,12 +1226,14 @@ hipError_t launch_edge_encode(const RunArgs& a) {
     case 32 * 8 + 3: fn = ENC_K(32, 3); break;
     case 32 * 8 + 4: fn = ENC_K(32, 4); break;
     case 32 * 8 + 5: fn = ENC_K(32, 5); break;
+    case 32 * 8 + 6: fn = ENC_K(32, 6); break;
     case 64 * 8 + 0: fn = ENC_K(64, 0); break;
     case 64 * 8 + 1: fn = ENC_K(64, 1); break;
     case 64 * 8 + 2: fn = ENC_K(64, 2); break;
     case 64 * 8 + 3: fn = ENC_K(64, 3); break;
     case 64 * 8 + 4: fn = ENC_K(64, 4); break;
     case 64 * 8 + 5: fn = ENC_K(64, 5); break;
+    case 64 * 8 + 6: fn = ENC_K(64, 6); break;
     default: return hipErrorInvalidValue;
   }
 #undef ENC_K
@@ -1308,12 +1317,14 @@ hipError_t launch_edge_step(const RunArgs& a, int k, bool final_step) {
     case 32 * 8 + 3: fn = STEP_K(32, 3); break;
     case 32 * 8 + 4: fn = STEP_K(32, 4); break;
     case 32 * 8 + 5: fn = STEP_K(32, 5); break;
+    case 32 * 8 + 6: fn = STEP_K(32, 6); break;
     case 64 * 8 + 0: fn = STEP_K(64, 0); break;
     case 64 * 8 + 1: fn = STEP_K(64, 1); break;
     case 64 * 8 + 2: fn = STEP_K(64, 2); break;
     case 64 * 8 + 3: fn = STEP_K(64, 3); break;
     case 64 * 8 + 4: fn = STEP_K(64, 4); break;
     case 64 * 8 + 5: fn = STEP_K(64, 5); break;
+    case 64 * 8 + 6: fn = STEP_K(64, 6); break;
     default: return hipErrorInvalidValue;
   }
 #undef STEP_K
@@ -1325,7 +1336,11 @@ __global__ void k_quantize(int prec, const float* __restrict__ in, float* __rest
   const float inv = 1.0f / scale;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const float x = in[i];
-    out[i] = prec == P_BF16 ? bf16_value(bf16_bits(x)) : (prec == P_FP8 ? e4m3_decode(e4m3_encode(x * inv)) * scale : x);
+    float v = x;
+    if (prec == ETX_BF16) v = bf16_value(bf16_bits(x));
+    else if (prec == ETX_FP8_E4M3) v = e4m3_decode(e4m3_encode(x * inv)) * scale;
+    else if (prec == ETX_INT8) v = (float)(int8_t)i8_byte(x * inv) * scale;
+    out[i] = v;
   }
 }
 
@@ -1379,11 +1394,13 @@ int gnn_attributes(size_t max_lds) {
   set_gnn_attr<32, 2>(bad, max_lds);
   set_gnn_attr<32, 4>(bad, max_lds);
   set_gnn_attr<32, 5>(bad, max_lds);
+  set_gnn_attr<32, 6>(bad, max_lds);
   set_gnn_attr<64, 0>(bad, max_lds);
   set_gnn_attr<64, 1>(bad, max_lds);
   set_gnn_attr<64, 2>(bad, max_lds);
   set_gnn_attr<64, 4>(bad, max_lds);
   set_gnn_attr<64, 5>(bad, max_lds);
+  set_gnn_attr<64, 6>(bad, max_lds);
   return bad;
 }
 

@@ -16,13 +16,21 @@ constexpr int kEdgeTile = 16;      // edges per wave tile of the MLP kernels (th
 constexpr int kDpad = 16;          // padded embedding width in HBM
 constexpr int kScanBlock = 1024;   // elements per block of the device-wide scan
 
-// weight bytes: FP32, BF16, FP8, FP32 as three BF16 parts, BF16 and FP8 with FP32 state
-constexpr int kPrecBytes[6] = {4, 2, 1, 6, 2, 1};
-// the weight segments a precision uses (the FP32-state forms share BF16's and FP8's)
-constexpr int kSegPrec[6] = {0, 1, 2, 3, 1, 2};
+// Kernel precisions (tile.hpp's Prec): FP32, BF16, FP8, FP32 as three BF16
+// parts, BF16 / FP8 / INT8 operands with FP32 node and edge state.
+// weight bytes per element
+constexpr int kPrecBytes[7] = {4, 2, 1, 6, 2, 1, 1};
+// the weight segment set a precision uses (the FP32-state forms share BF16's and FP8's)
+constexpr int kSegPrec[7] = {0, 1, 2, 3, 1, 2, 4};
+// the etx_precision of a kernel precision's operands
+constexpr int kEtxPrec[7] = {ETX_FP32, ETX_BF16, ETX_FP8_E4M3, ETX_FP32, ETX_BF16, ETX_FP8_E4M3, ETX_INT8};
 constexpr int kF32Split = 3;                  // segment set of the split-FP32 edge kernels
 constexpr int kBf16Master = 4;                // BF16 operands, FP32 node and edge state
 constexpr int kFp8Master = 5;                 // FP8 operands, FP32 node and edge state
+constexpr int kI8Master = 6;                  // INT8 operands, FP32 node and edge state
+constexpr int kI8Seg = 4;                     // segment set of the INT8 weights
+constexpr int kNumSegs = 5;
+constexpr int kSegBytes[kNumSegs] = {4, 2, 1, 6, 1};   // weight bytes per element of each segment set
 
 // Offsets (in bytes) of the per-kernel weight segments in a precision's device buffer.
 struct WeightMap {
@@ -54,10 +62,11 @@ struct etx_ctx {
   etx_config cfg;
   int device = 0;
   int n_cu = 256;
-  void* seg_base[4] = {};          // weight segments per operand precision (FP32, BF16, FP8, split FP32)
-  etx::WeightMap wmap[4];
-  float* dev_scales = nullptr;     // [256] per-tensor scales: activations 0..63, weights 64..255
-  float host_scales[256] = {};
+  void* seg_base[etx::kNumSegs] = {};   // weight segments per set (FP32, BF16, FP8, split FP32, INT8)
+  etx::WeightMap wmap[etx::kNumSegs];
+  float* dev_scales = nullptr;     // [512] per-tensor scales: FP8 set 0..255, INT8 set 256..511
+  float host_scales[512] = {};
+  double i8_wscale[256] = {};      // INT8 weight scales max|W| / 127 (slots 64..), exact, for the codes
   bool calibrated = false;
   // prefilter (params, Adam m, v) in FP32 on the device
   float* dev_pf = nullptr;

@@ -76,7 +76,8 @@ struct SegCls {
 };
 
 // Slots of the per-tensor scales (ctx->dev_scales): activations 0..63,
-// weights 64..255.  Activation slots follow the oracle's numbering.
+// weights 64..255; the same slots again from SC_I8 for the INT8 scales.
+// Activation slots follow the oracle's numbering.
 enum ScaleSlot {
   SC_EMB = 0,          // + l: input of embedding layer l (l >= 1)
   SC_GNN = 8,          // + Q_* below
@@ -85,7 +86,8 @@ enum ScaleSlot {
   SW_EMB = 64,         // + l
   SW_NE2 = 72, SW_EE1 = 73, SW_EE2 = 74, SW_CLS1 = 75,
   SW_STEP = 80,        // + 4k + {0: node L1, 1: node L2, 2: edge L1, 3: edge L2}
-  N_SCALES = 256
+  SC_I8 = 256,         // INT8 scale set
+  N_SCALES = 512
 };
 
 }  // namespace etx

@@ -21,6 +21,7 @@
 namespace etx {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef int intx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kCols = 16;  // columns per wave tile of the MLP kernels
@@ -196,11 +197,13 @@ __device__ inline void mfma_bf16_chunks(float* acc, const uint4* xr, const bf16x
 // three BF16 parts (below); FP32 everywhere else.  P_BF16M / P_FP8M: BF16 /
 // FP8 GEMM operands with the node and edge state kept in FP32 between kernels
 // (residual masters); P_BF16 / P_FP8 keep that state in the operand format.
-enum Prec { P_F32 = 0, P_BF16 = 1, P_FP8 = 2, P_F32X = 3, P_BF16M = 4, P_FP8M = 5 };
+// P_I8M: symmetric INT8 operands (real per-tensor scales), FP32 state.
+enum Prec { P_F32 = 0, P_BF16 = 1, P_FP8 = 2, P_F32X = 3, P_BF16M = 4, P_FP8M = 5, P_I8M = 6 };
 // bytes per weight element of a GEMM in precision P (P_F32X: three BF16 planes)
 template <int P>
 struct PrecBytes {
-  static constexpr int value = P == P_F32 ? 4 : (P == P_BF16 || P == P_BF16M) ? 2 : (P == P_FP8 || P == P_FP8M) ? 1 : 6;
+  static constexpr int value = P == P_F32 ? 4 : (P == P_BF16 || P == P_BF16M) ? 2
+                             : (P == P_FP8 || P == P_FP8M || P == P_I8M) ? 1 : 6;
 };
 // storage format of the state (edge encodings) in precision P
 template <int P>
@@ -210,6 +213,8 @@ template <int P>
 constexpr bool kBf16Ops = P == P_BF16 || P == P_BF16M;
 template <int P>
 constexpr bool kFp8Ops = P == P_FP8 || P == P_FP8M;
+template <int P>
+constexpr bool kI8Ops = P == P_I8M;
 
 // OCP FP8 E4M3 (bias 7, 3 mantissa bits, subnormals, max 448, no infinity),
 // converted by the gfx950 instructions v_cvt_pk_fp8_f32 (round to nearest
@@ -230,6 +235,16 @@ template <int Q>
 __device__ inline float e4m3_byte(uint32_t w) { return __builtin_amdgcn_cvt_f32_fp8((int)w, Q); }
 
 __device__ inline float e4m3_decode(uint32_t c) { return e4m3_byte<0>(c); }
+
+// Symmetric INT8 (thesis ch. 4 "Quantization"): code = clip(round(x / S),
+// -127, 127) with round to nearest even (v_rndne_f32), value = S * code.  The
+// caller passes x / S (as x * (1 / S)).
+__device__ inline uint32_t i8_byte(float v) {
+  return (uint32_t)(int)__builtin_rintf(fminf(fmaxf(v, -127.f), 127.f)) & 0xffu;
+}
+__device__ inline uint32_t i8_encode4(float a, float b, float c, float d) {
+  return i8_byte(a) | (i8_byte(b) << 8) | (i8_byte(c) << 16) | (i8_byte(d) << 24);
+}
 
 __device__ inline uint32_t bf16_bits(float x) { return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)x); }
 __device__ inline float bf16_value(uint32_t b) { return __uint_as_float(b << 16); }
@@ -315,6 +330,33 @@ __device__ inline void mfma_fp8_codes(float* acc, const uint32_t* xw, const uint
     for (int v = 0; v < 4; ++v) acc[4 * mb + v] = fmaf(out_scale, c[mb][v], acc[4 * mb + v]);
 }
 
+// INT8 operands, K-steps of 32 (the FP8 form's lane layout, 8 codes per lane
+// per step): acc += out_scale * (W_q^T x_q), the integer products summed
+// exactly in INT32 (|sum| <= K * 127^2 < 2^24, so the conversion is exact).
+template <int K, int MB, int T0 = 0, int T1 = K / 32>
+__device__ inline void mfma_i8(float* acc, const float* x, const uint64_t* __restrict__ w, float inv_s,
+                               float out_scale) {
+  static_assert(K * 127 * 127 < (1 << 24), "INT32 sums must convert to FP32 exactly");
+  const int lane = lane_id();
+  intx4 c[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb) c[mb] = intx4{0, 0, 0, 0};
+#pragma unroll
+  for (int t = T0; t < T1; ++t) {
+    const float* xs = x + 8 * t;
+    const uint64_t b = (uint64_t)i8_encode4(xs[0] * inv_s, xs[1] * inv_s, xs[2] * inv_s, xs[3] * inv_s) |
+                       ((uint64_t)i8_encode4(xs[4] * inv_s, xs[5] * inv_s, xs[6] * inv_s, xs[7] * inv_s) << 32);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+      c[mb] = __builtin_amdgcn_mfma_i32_16x16x32_i8((long)w[(mb * (K / 32) + t) * 64 + lane], (long)b, c[mb], 0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[4 * mb + v] = fmaf(out_scale, (float)c[mb][v], acc[4 * mb + v]);
+}
+
 // FP32 product on the BF16 matrix cores.  Each FP32 value is split exactly
 // into three BF16 parts, x = hi + mid + lo (hi = bf16(x), mid = bf16(x - hi),
 // lo = bf16(x - hi - mid); both differences are exact in FP32, and lo is
@@ -369,7 +411,7 @@ __device__ inline void mfma_split(float* acc, const float* x, const bf16x8* __re
 }
 
 // One Linear layer in precision P: acc += W^T x with weights w (permuted for
-// P); FP8 quantises x with inv_s and rescales the product by out_scale.
+// P); FP8 and INT8 quantise x with inv_s and rescale the product by out_scale.
 template <int P, int K, int MB>
 __device__ inline void gemm(float* acc, const float* x, const void* w, float inv_s, float out_scale) {
   if constexpr (P == P_F32) {
@@ -378,6 +420,8 @@ __device__ inline void gemm(float* acc, const float* x, const void* w, float inv
     mfma_bf16<K, MB>(acc, x, static_cast<const bf16x8*>(w));
   } else if constexpr (P == P_F32X) {
     mfma_split<K, MB>(acc, x, static_cast<const bf16x8*>(w));
+  } else if constexpr (kI8Ops<P>) {
+    mfma_i8<K, MB>(acc, x, static_cast<const uint64_t*>(w), inv_s, out_scale);
   } else {
     mfma_fp8<K, MB>(acc, x, static_cast<const uint64_t*>(w), inv_s, out_scale);
   }

@@ -18,7 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libetx.so")
 
 ETX_OK, ETX_ERR_INVALID_ARG, ETX_ERR_CAPACITY, ETX_ERR_INPUT, ETX_ERR_WEIGHTS, ETX_ERR_UNSUPPORTED, ETX_ERR_HIP = range(7)
-ETX_FP32, ETX_BF16, ETX_FP8_E4M3 = 0, 1, 2
+ETX_FP32, ETX_BF16, ETX_FP8_E4M3, ETX_INT8 = 0, 1, 2, 3
+SC_I8 = 256                      # first slot of the INT8 scale set (etx_get_scales)
 ETX_MAX_EVENT_HITS = 16384
 ETX_N_CALIB = 64
 ETX_PF_HIDDEN = 32

@@ -46,7 +46,7 @@ def test_weight_blob_size_matches_packer(name):
     ("emb_dim", 17, etx.ETX_ERR_UNSUPPORTED), ("k_max", 65, etx.ETX_ERR_UNSUPPORTED),
     ("k_max", 0, etx.ETX_ERR_UNSUPPORTED), ("gnn_hidden", 48, etx.ETX_ERR_UNSUPPORTED),
     ("gnn_steps", 0, etx.ETX_ERR_UNSUPPORTED), ("radius", float("nan"), etx.ETX_ERR_INVALID_ARG),
-    ("precision", 3, etx.ETX_ERR_INVALID_ARG), ("plane_window", 5, etx.ETX_ERR_UNSUPPORTED)])
+    ("precision", 4, etx.ETX_ERR_INVALID_ARG), ("plane_window", 5, etx.ETX_ERR_UNSUPPORTED)])
 def test_bad_config_rejected_on_host(field, value, code):
     w = synth.C1
     cfg = etx.make_config(w)

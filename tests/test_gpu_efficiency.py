@@ -67,23 +67,26 @@ def test_fp32_efficiency_matches_oracle_and_bf16_within_half_percent():
 
 
 def _fp8_efficiency_is_the_formats(w, W, batch, m32, ev_idx):
-    """FP8-E4M3 with per-tensor scales costs efficiency with these trained
-    networks (reported, not bounded): the GPU's FP8 efficiency must be the one
-    the quantised FP64 oracle reaches with the same calibration, for the plain
-    FP8 pipeline and for the FP8 network behind a BF16 embedding."""
+    """FP8-E4M3 and INT8 with per-tensor scales cost efficiency with these
+    trained networks (reported, not bounded): the GPU's efficiency must be the
+    one the quantised FP64 oracle reaches with the same calibration, for the
+    plain 8-bit pipelines and for the 8-bit networks behind a BF16 embedding."""
     etx = _etx()
     cal = synth.generate_batch(w, 10, seed_space=1000 + w.cid)
-    es, gs, _, _ = O.calibrate([synth.event_slice(cal, i) for i in range(10)], w, W)
+    es, gs, am_e, am_g = O.calibrate([synth.event_slice(cal, i) for i in range(10)], w, W)
+    scales = {2: (es, gs), 3: (O.int8_scales(am_e), O.int8_scales(am_g))}
     n_or = int(batch["hit_off"][len(ev_idx)])
-    for emb_prec, emb_q, name in ((-1, 2, "fp8"), (etx.ETX_BF16, 1, "fp8 network + bf16 embedding")):
-        p = etx.Pipeline(w, W, precision=etx.ETX_FP8_E4M3)
+    for prec, qmode, emb_prec, emb_q, name in (
+            (etx.ETX_FP8_E4M3, 2, -1, 2, "fp8"), (etx.ETX_FP8_E4M3, 2, etx.ETX_BF16, 1, "fp8 network + bf16 embedding"),
+            (etx.ETX_INT8, 3, -1, 3, "int8"), (etx.ETX_INT8, 3, etx.ETX_BF16, 1, "int8 network + bf16 embedding")):
+        p = etx.Pipeline(w, W, precision=prec)
         p.calibrate(etx.to_device(cal))
         etx.etx_set_option(p.ctx, etx.ETX_OPT_EMBED_PRECISION, emb_prec)
         b = etx.to_device(batch)
         p.run(b)
         r = p.results(b)
         m = evaluate.batch_metrics(r["labels"], batch)
-        refs = O.run_batch(batch, w, W, events=ev_idx, qmode=2, scales=(es, gs), emb_qmode=emb_q)
+        refs = O.run_batch(batch, w, W, events=ev_idx, qmode=qmode, scales=scales[qmode], emb_qmode=emb_q)
         lab = np.concatenate([x["labels"] + int(batch["hit_off"][i]) for i, x in zip(ev_idx, refs)])
         m_or = evaluate.batch_metrics(np.concatenate([lab, np.arange(n_or, len(batch["x"]))]), batch, ev_idx)
         m_gpu = evaluate.batch_metrics(r["labels"], batch, ev_idx)

@@ -195,6 +195,31 @@ def test_edge_schedules_bit_identical(prec, compact):
                     assert np.array_equal(r[k], ref[k]), (wreg, threads, per_cu, pipe, k)
 
 
+def test_batch_composition_independence():
+    """An event's edges, keep decisions and labels do not depend on which
+    events share its batch or where it sits in it; its scores agree to FP32
+    rounding (the out-sum partials follow the 16-edge tiles, whose boundaries
+    move with the event's edge offset)."""
+    from paper_2508_07423_amd import occupancy
+    w = synth.C3
+    W = centred_weights(w)
+    batch = synth.generate_batch(w, 12)
+    _, _, full = run_gpu(w, W, batch)
+    pick = [9, 3, 0, 7]
+    sb = occupancy.sub_batch(batch, pick)
+    _, _, part = run_gpu(w, W, sb)
+    ho, eo, ho2, eo2 = batch["hit_off"], full["edge_off"], sb["hit_off"], part["edge_off"]
+    for j, i in enumerate(pick):
+        a, b, a2, b2 = eo[i], eo[i + 1], eo2[j], eo2[j + 1]
+        assert np.array_equal(full["src"][a:b] - ho[i], part["src"][a2:b2] - ho2[j])
+        assert np.array_equal(full["dst"][a:b] - ho[i], part["dst"][a2:b2] - ho2[j])
+        s1, s2 = full["score"][a:b], part["score"][a2:b2]
+        assert np.abs(s1.astype(np.float64) - s2).max(initial=0.0) <= G.SCORE_TOL
+        if not np.any(np.abs(s1 - 0.5) < 1e-4):
+            assert np.array_equal(s1 >= 0.5, s2 >= 0.5)
+            assert np.array_equal(full["labels"][ho[i]:ho[i + 1]] - ho[i], part["labels"][ho2[j]:ho2[j + 1]] - ho2[j])
+
+
 def test_permutation_equivariance_gpu():
     w = synth.C1
     W = centred_weights(w)

@@ -75,6 +75,23 @@ def test_bf16_cast_matches_oracle():
     assert len(bad) == 0, [(float(x[i]), got[i], ref[i]) for i in bad[:8]]
 
 
+def test_int8_cast_matches_oracle():
+    """INT8 codes of x * (1 / S) (the FP32 product the kernels quantise),
+    rounded to nearest even and clipped to +-127, times S."""
+    etx = _etx()
+    rng = np.random.default_rng(5)
+    for scale in (10.8 / 127, 2.0 ** -5, 0.37):
+        inv = np.float32(1.0) / np.float32(scale)
+        codes = np.concatenate([np.arange(-130, 131), np.arange(-130, 131) + 0.5, rng.normal(0, 60, 4000)])
+        x = (codes.astype(np.float64) * scale).astype(np.float32)
+        x = np.concatenate([x, np.nextafter(x, np.float32(1e9)), np.nextafter(x, np.float32(-1e9))])
+        got = gpu_quantize(etx.ETX_INT8, x, scale)
+        v = x * inv                                       # float32 product, as on the GPU
+        ref = np.array([np.float32(np.float32(scale) * np.float32(O.round_int8(float(t)))) for t in v])
+        bad = np.nonzero(got != ref)[0]
+        assert len(bad) == 0, [(float(x[i]), got[i], ref[i]) for i in bad[:8]]
+
+
 def _run(w, W, batch, prec, cal=None, compact=0):
     etx = _etx()
     p = etx.Pipeline(w, W, precision=prec)
@@ -149,6 +166,35 @@ def test_fp8_calibration_and_pipeline_against_quantised_oracle(compact):
     assert sq["mean"] <= 0.5 * s64s["mean"] and sq["max"] <= 0.1
 
 
+def test_int8_calibration_and_pipeline_against_quantised_oracle():
+    """Symmetric INT8 (S = amax / 127 per tensor, thesis ch. 4 "Quantization")
+    with FP32 node and edge state, against the oracle's INT8 mode calibrated
+    on the same events."""
+    etx = _etx()
+    w = synth.C1
+    W = synth.xavier_weights(w)
+    cal = synth.generate_batch(w, 3, seed_space=1001)
+    batch = synth.generate_batch(w, 1)
+    ev = synth.event_slice(batch, 0)
+    p, res = _run(w, W, batch, etx.ETX_INT8, cal)
+    _, _, am_e, am_g = O.calibrate([synth.event_slice(cal, i) for i in range(3)], w, W)
+    es, gs = O.int8_scales(am_e), O.int8_scales(am_g)
+    sc = etx.etx_get_scales(p.ctx, 512)
+    L = w.emb_layers
+    i8 = etx.SC_I8
+    np.testing.assert_allclose(sc[i8 + 1:i8 + L + 1], es[1:L + 1], rtol=2e-6)
+    np.testing.assert_allclose(sc[i8 + 8:i8 + 8 + 8 + w.gnn_steps], gs, rtol=2e-6)
+    ref_q = O.run_event(ev, w, W, qmode=3, scales=(es, gs))
+    common = np.array_equal(res["src"], ref_q["src"]) and np.array_equal(res["dst"], ref_q["dst"])
+    _, cart = O.features(ev["x"], ev["y"], ev["z"], w.r_scale, w.z_scale)
+    ref_q_s = ref_q["score"] if common else O.sigmoid(O.gnn(cart, res["src"], res["dst"], W, w.gnn_hidden,
+                                                             w.gnn_steps, 3, gs))
+    sq = _score_stats(res["score"], ref_q_s)
+    s64 = _score_stats(res["score"], O.sigmoid(O.gnn(cart, res["src"], res["dst"], W, w.gnn_hidden, w.gnn_steps)))
+    print("int8 edges equal to quantised oracle:", common, "vs quantised oracle", sq, "vs fp64 oracle", s64)
+    assert sq["mean"] <= 0.5 * s64["mean"] and sq["max"] <= 0.05
+
+
 def test_fp8_network_with_bf16_embedding():
     """Per-network precision: an FP8-E4M3 interaction network behind a BF16
     embedding (the embedding's output is compared against the radius, so its
@@ -163,7 +209,7 @@ def test_fp8_network_with_bf16_embedding():
     p.calibrate(etx.to_device(cal))
     etx.etx_set_option(p.ctx, etx.ETX_OPT_EMBED_PRECISION, etx.ETX_BF16)
     assert etx.etx_get_option(p.ctx, etx.ETX_OPT_EMBED_PRECISION) == etx.ETX_BF16
-    for bad in (-2, 3):
+    for bad in (-2, 4):
         with pytest.raises(etx.EtxError):
             etx.etx_set_option(p.ctx, etx.ETX_OPT_EMBED_PRECISION, bad)
     b = etx.to_device(batch)

@@ -217,9 +217,9 @@ def _pow2_at_or_above(m):
 
 def _dense_gnn_quantised(cart, src, dst, weights, H, S, qmode, act_scale, compact):
     """The quantised network in the dense formulation, rounding with torch's
-    own bfloat16 / float8_e4m3fn casts: every GEMM operand is rounded where it
-    enters the GEMM (FP8: per-tensor activation scales, per-matrix weight
-    scales); the 3-wide first layer, LayerNorm, residual additions, sums and
+    own bfloat16 / float8_e4m3fn casts and torch.round (INT8): every GEMM
+    operand is rounded where it enters the GEMM (FP8, INT8: per-tensor
+    activation scales, per-matrix weight scales); the 3-wide first layer, LayerNorm, residual additions, sums and
     the H -> 1 output layer are not.  compact: h is stored as BF16 and e in
     the operand format after every write."""
     T = lambda a: torch.tensor(np.asarray(a), dtype=torch.float64)
@@ -230,6 +230,8 @@ def _dense_gnn_quantised(cart, src, dst, weights, H, S, qmode, act_scale, compac
     def q(x, s):
         if qmode == 1:
             return x.to(torch.bfloat16).to(torch.float64)
+        if qmode == 3:      # torch.round: half to even
+            return torch.round(x / s).clamp(-127.0, 127.0) * s
         return (x / s).clamp(-448.0, 448.0).to(torch.float8_e4m3fn).to(torch.float64) * s
 
     def bf(x):
@@ -237,7 +239,8 @@ def _dense_gnn_quantised(cart, src, dst, weights, H, S, qmode, act_scale, compac
 
     def qw(W):
         W = T(W)
-        return q(W, _pow2_at_or_above(float(W.abs().max())))
+        m = float(W.abs().max())
+        return q(W, m / 127.0 if qmode == 3 else _pow2_at_or_above(m))
 
     def ln(x):
         return F.relu(F.layer_norm(x, (H,), eps=1e-5))
@@ -270,10 +273,11 @@ def _dense_gnn_quantised(cart, src, dst, weights, H, S, qmode, act_scale, compac
     return (c @ T(W2) + T(b2))[:, 0].numpy()
 
 
-@pytest.mark.parametrize("qmode,compact", [(1, False), (1, True), (2, False), (2, True)])
+@pytest.mark.parametrize("qmode,compact", [(1, False), (1, True), (2, False), (2, True), (3, False), (3, True)])
 def test_gnn_quantised_matches_dense_torch(qmode, compact):
-    """The quantised oracle network (ch. 4 "Quantization"), with node and
-    edge state kept in full precision or stored in low precision."""
+    """The quantised oracle network (ch. 4 "Quantization": BF16, FP8-E4M3,
+    symmetric INT8), with node and edge state kept in full precision or stored
+    in low precision."""
     rng = np.random.default_rng(21 + qmode)
     n, E, H, S = 30, 120, 32, 3
     cart = rng.uniform(-1, 1, (n, 3))
@@ -281,10 +285,10 @@ def test_gnn_quantised_matches_dense_torch(qmode, compact):
     dst = rng.integers(0, n, E).astype(np.int32)
     W = _random_gnn_weights(H, S, 14)
     scales = None
-    if qmode == 2:
+    if qmode >= 2:
         amax = np.zeros(8 + S)
         O.gnn(cart, src, dst, W, H, S, amax=amax)
-        scales = np.array([_pow2_at_or_above(a) for a in amax])
+        scales = np.array([_pow2_at_or_above(a) if qmode == 2 else a / 127.0 for a in amax])
     got = O.gnn(cart, src, dst, W, H, S, qmode, scales, compact=compact)
     ref = _dense_gnn_quantised(cart, src, dst, W, H, S, qmode, scales, compact)
     np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-9)
@@ -292,7 +296,7 @@ def test_gnn_quantised_matches_dense_torch(qmode, compact):
     other = O.gnn(cart, src, dst, W, H, S, qmode, scales, compact=not compact)
     full = O.gnn(cart, src, dst, W, H, S)
     assert np.abs(got - other).max() > 1e-6
-    assert np.abs(got - full).max() < (0.5 if qmode == 1 else 2.0)
+    assert np.abs(got - full).max() < (2.0 if qmode == 2 else 0.5)
 
 
 def test_gnn_permutation_equivariance():
@@ -428,10 +432,11 @@ def test_int8_symmetric_example_from_thesis():
     S = g["alpha"] / g["qmax"]
     assert S == pytest.approx(10.8 / 127)
     for x, xq in g["cases"]:
-        # the oracle's rounding primitive with 0 fraction bits below 2^7 is integer RNE
-        q = min(max(round(x / S), -g["qmax"]), g["qmax"])
+        q = O.round_int8(x / S)            # the oracle's INT8 quantiser (qmode 3)
         assert q == xq
         assert abs(S * q - x) <= S / 2 or abs(x) > g["alpha"]
+    # ties go to the even code
+    assert [O.round_int8(v) for v in (0.5, 1.5, 2.5, -0.5, -1.5, 126.5, 127.5)] == [0, 2, 2, 0, -2, 126, 127]
 
 
 # ---------------------------------------------------------------------------
