@@ -251,7 +251,6 @@ __global__ __launch_bounds__(kRadiusThreads) void k_radius(RadiusArgs A) {
   int* wlj = lj + wave * kList;
   int* sl = sel + wave * 64;
   int* hw = hist + wave * 256;
-  const unsigned r2bits = __float_as_uint(A.r2);
 
   // Fast path of the select pass over a staged window: four sources per wave,
   // one per 16-lane row, each over its own candidate range.  A source with at
@@ -408,18 +407,32 @@ __global__ __launch_bounds__(kRadiusThreads) void k_radius(RadiusArgs A) {
     const bool capped = n > A.k_max;
     float T = A.r2;
     int Jt = 0x7fffffff;
-    if (capped && listed) {
-      // radix select of the k-th smallest d2 over the list: four 8-bit digits of
-      // its float bits (non-negative floats order like their bits)
+    if (capped) {
+      // radix select of the k-th smallest d2: four 8-bit digits of its float
+      // bits (non-negative floats order like their bits), over the list, or
+      // with more than kList in-radius candidates over the candidate range
+      // again (four scans)
       unsigned prefix = 0;
       int need = A.k_max, eq = 0;
       for (int pass = 0; pass < 4; ++pass) {
         const int shift = 24 - 8 * pass;
         for (int b = lane; b < 256; b += 64) hw[b] = 0;
         wave_sync();
-        for (int q = lane; q < n; q += 64) {
-          const unsigned key = __float_as_uint(wl2[q]);
+        auto bump = [&](float d2) {
+          const unsigned key = __float_as_uint(d2);
           if (pass == 0 || (key >> (shift + 8)) == (prefix >> (shift + 8))) atomicAdd(&hw[(key >> shift) & 255u], 1);
+        };
+        if (listed) {
+          for (int q = lane; q < n; q += 64) bump(wl2[q]);
+        } else {
+          for (int c0 = cb; c0 < ce; c0 += 64) {
+            const int c = c0 + lane;
+            if (c < ce) {
+              int j;
+              const float d2 = cand(c, j);
+              if (d2 < A.r2) bump(d2);
+            }
+          }
         }
         wave_sync();
         int c[4], sum = 0;
@@ -455,29 +468,6 @@ __global__ __launch_bounds__(kRadiusThreads) void k_radius(RadiusArgs A) {
         wave_sync();
       }
       T = __uint_as_float(prefix);
-      if (eq > need) {
-        // ties at the boundary distance: keep the `need` smallest hit indices
-        int jlo = (int)a, jhi = (int)(A.hit_off[ev + 1] - 1);
-        while (jlo < jhi) {
-          const int mid = jlo + (jhi - jlo) / 2;
-          const int m = count_if([&](float d2, int j) { return d2 == T && j <= mid; });
-          if (m >= need) jhi = mid; else jlo = mid + 1;
-        }
-        Jt = jlo;
-      }
-    } else if (capped) {
-      // smallest T (as float bits) with #{d2 <= T} >= k_max: the k-th smallest d2
-      unsigned lo = 0, hi = r2bits - 1u;
-      while (lo < hi) {
-        const unsigned mid = lo + (hi - lo) / 2;
-        const float fm = __uint_as_float(mid);
-        const int m = count_if([&](float d2, int) { return d2 <= fm; });
-        if (m >= A.k_max) hi = mid; else lo = mid + 1;
-      }
-      T = __uint_as_float(lo);
-      const int less = count_if([&](float d2, int) { return d2 < T; });
-      const int need = A.k_max - less;
-      const int eq = count_if([&](float d2, int) { return d2 == T; });
       if (eq > need) {
         // ties at the boundary distance: keep the `need` smallest hit indices
         int jlo = (int)a, jhi = (int)(A.hit_off[ev + 1] - 1);

@@ -126,10 +126,13 @@ def test_cap_tie_break_by_smaller_index(k_max):
     assert ref["dst"][ref["src"] == 5].tolist() == expect
 
 
-def test_window_larger_than_lds_and_long_lists():
-    """1,100 tracks on 10 planes: candidate windows of ~2,200 hits are read
-    from HBM; a wide radius puts more than 256 candidates inside r."""
-    w = synth.C1.with_(tracks=("fixed", 1100), radius=0.3, k_max=16)
+@pytest.mark.parametrize("tracks", [1100, 400])
+def test_window_larger_than_lds_and_long_lists(tracks):
+    """A wide radius puts more than 256 candidates inside r of most sources
+    (longer than a wave's list: the k_max cut scans the candidates again).
+    1,100 tracks on 10 planes: windows of ~2,200 hits, read from HBM; 400
+    tracks: windows of ~800 hits, staged in LDS."""
+    w = synth.C1.with_(tracks=("fixed", tracks), radius=0.3, k_max=16)
     W = synth.xavier_weights(w)
     batch = synth.generate_batch(w, 1)
     assert batch["hit_off"][-1] < 16384
