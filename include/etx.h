@@ -182,7 +182,7 @@ typedef enum {
   ETX_OPT_CSC_PLACE = 18,      /* 1 (default): for events with short rows (< 16 edges per hit) the whole block drops
                                   the edges into their CSC columns through LDS cursors and then sorts every column by
                                   edge index (source order); 0: one wave ranks 64 edges at a time; same permutation */
-  ETX_OPT_COMPACT_STATE = 19   /* BF16 and FP8 runs only.  0 (default): the node encodings h and edge encodings e
+  ETX_OPT_COMPACT_STATE = 19   /* BF16 and FP8 runs only (FP32 and INT8 runs ignore it).  0 (default): the node encodings h and edge encodings e
                                   are kept in FP32 between kernels (residual master copies) and quantised only where
                                   they enter a GEMM.  1: both are stored in low precision (h as BF16; e in the
                                   operand format, FP8 with the e_k scale), which halves or quarters their HBM

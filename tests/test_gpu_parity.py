@@ -163,7 +163,7 @@ def test_radius_global_fallback_and_unroll_identical(c1_run):
         etx.etx_set_option(p.ctx, etx.ETX_OPT_EDGE_WG_PER_CU, 8)
 
 
-@pytest.mark.parametrize("prec,compact", [(0, 0), (1, 0), (2, 0), (1, 1), (2, 1)])
+@pytest.mark.parametrize("prec,compact", [(0, 0), (1, 0), (2, 0), (1, 1), (2, 1), (3, 0)])
 def test_edge_schedules_bit_identical(prec, compact):
     """Every software-pipeline depth and workgroup shape of the edge kernels
     computes the same bits (a multi-event c3 batch: many tiles per wave),
@@ -174,7 +174,7 @@ def test_edge_schedules_bit_identical(prec, compact):
     batch = synth.generate_batch(w, 8)
     p = etx.Pipeline(w, W, precision=prec)
     etx.etx_set_option(p.ctx, etx.ETX_OPT_COMPACT_STATE, compact)
-    if prec == etx.ETX_FP8_E4M3:
+    if prec in (etx.ETX_FP8_E4M3, etx.ETX_INT8):
         p.calibrate(etx.to_device(synth.generate_batch(w, 4, seed_space=1000 + w.cid)))
     b = etx.to_device(batch)
     ref = None
@@ -375,7 +375,7 @@ def test_radius_sorted_and_scanned_windows_identical(wl, n):
 
 @pytest.mark.parametrize("wl,n,prec,compact", [("c1", 1, 0, 0), ("c3", 6, 0, 0), ("c3", 6, 1, 0), ("c3", 6, 2, 0),
                                                ("c2", 2, 0, 0), ("c2", 2, 1, 0), ("c3", 6, 1, 1), ("c3", 6, 2, 1),
-                                               ("c2", 2, 1, 1)])
+                                               ("c2", 2, 1, 1), ("c3", 6, 3, 0)])
 def test_fused_messages_identical(wl, n, prec, compact):
     """Messages gathered inside the node kernel equal the separate message-sum
     kernel's, bit for bit (same sums in the same order)."""
@@ -385,7 +385,7 @@ def test_fused_messages_identical(wl, n, prec, compact):
     batch = synth.generate_batch(w, n)
     p = etx.Pipeline(w, W, precision=prec)
     etx.etx_set_option(p.ctx, etx.ETX_OPT_COMPACT_STATE, compact)
-    if prec == etx.ETX_FP8_E4M3:
+    if prec in (etx.ETX_FP8_E4M3, etx.ETX_INT8):
         p.calibrate(etx.to_device(synth.generate_batch(w, 3, seed_space=1000 + w.cid)))
     b = etx.to_device(batch)
     out = {}
@@ -426,7 +426,7 @@ def test_xcd_map_identical(wl, n, prec):
     W = centred_weights(w)
     batch = synth.generate_batch(w, n)
     p = etx.Pipeline(w, W, precision=prec)
-    if prec == etx.ETX_FP8_E4M3:
+    if prec in (etx.ETX_FP8_E4M3, etx.ETX_INT8):
         p.calibrate(etx.to_device(synth.generate_batch(w, 4, seed_space=1000 + w.cid)))
     b = etx.to_device(batch)
     out = {}
@@ -441,7 +441,8 @@ def test_xcd_map_identical(wl, n, prec):
 @pytest.mark.parametrize("wl,n,prec,split,fuse,compact",
                          [("c1", 3, 0, 0, 0, 0), ("c3", 30, 0, 0, 1, 0), ("c3", 30, 0, 1, 0, 0), ("c2", 2, 0, 0, 0, 0),
                           ("c3", 30, 1, 0, 1, 0), ("c2", 2, 1, 0, 0, 0), ("c3", 30, 2, 0, 0, 0),
-                          ("c3", 30, 1, 0, 1, 1), ("c2", 2, 1, 0, 0, 1), ("c3", 30, 2, 0, 0, 1)])
+                          ("c3", 30, 1, 0, 1, 1), ("c2", 2, 1, 0, 0, 1), ("c3", 30, 2, 0, 0, 1),
+                          ("c3", 30, 3, 0, 1, 0), ("c2", 2, 3, 0, 0, 0)])
 def test_edge_products_identical(wl, n, prec, split, fuse, compact):
     """Node products formed in the edge kernel from gathered rows of h equal
     the node kernel's stored products: same bits, every precision and state
@@ -452,7 +453,7 @@ def test_edge_products_identical(wl, n, prec, split, fuse, compact):
     batch = synth.generate_batch(w, n)
     p = etx.Pipeline(w, W, precision=prec)
     etx.etx_set_option(p.ctx, etx.ETX_OPT_COMPACT_STATE, compact)
-    if prec == etx.ETX_FP8_E4M3:
+    if prec in (etx.ETX_FP8_E4M3, etx.ETX_INT8):
         p.calibrate(etx.to_device(synth.generate_batch(w, 4, seed_space=1000 + w.cid)))
     etx.etx_set_option(p.ctx, etx.ETX_OPT_F32_SPLIT, split)
     etx.etx_set_option(p.ctx, etx.ETX_OPT_FUSE_MESSAGES, fuse)

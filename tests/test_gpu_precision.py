@@ -226,3 +226,18 @@ def test_fp8_network_with_bf16_embedding():
     s64 = _score_stats(res["score"], O.sigmoid(O.gnn(cart, res["src"], res["dst"], W, w.gnn_hidden, w.gnn_steps)))
     print("fp8 network + bf16 embedding: vs quantised oracle", sq, "vs fp64 oracle", s64)
     assert sq["mean"] <= 0.5 * s64["mean"] and sq["max"] <= 0.1
+
+
+def test_int8_keeps_fp32_state_whatever_the_compact_option():
+    """INT8 has no compact state form: the option leaves its results unchanged."""
+    etx = _etx()
+    w = synth.C1
+    W = synth.xavier_weights(w)
+    cal = synth.generate_batch(w, 3, seed_space=1001)
+    batch = synth.generate_batch(w, 2)
+    out = []
+    for compact in (0, 1):
+        _, res = _run(w, W, batch, etx.ETX_INT8, cal, compact=compact)
+        out.append(res)
+    for k in ("src", "dst", "score", "labels", "edge_off"):
+        assert np.array_equal(out[0][k], out[1][k]), k
