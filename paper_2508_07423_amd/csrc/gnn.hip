@@ -147,6 +147,19 @@ struct ELayout {
 template <int P, int H>
 struct RawE { uint4 v[ELayout<P, H>::NQ]; };
 
+// Non-temporal stores of edge rows (the edge encoder's: its writes then do
+// not push the gathered node-product rows out of L2; measured 17.8 -> 16.1 ms
+// at c2.  In the edge updates, non-temporal loads and stores of the rows cut
+// the read traffic but raised the write traffic and did not pay.)
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ inline void store_stream4(char* p, uint4 v) {
+  __builtin_nontemporal_store(u32x4{v.x, v.y, v.z, v.w}, reinterpret_cast<u32x4*>(p));
+}
+__device__ inline void store_stream2(char* p, uint2 v) {
+  __builtin_nontemporal_store(u32x2{v.x, v.y}, reinterpret_cast<u32x2*>(p));
+}
+
 // col must address a stored row (callers clamp the tail of the last tile).
 template <int P, int H>
 __device__ inline void fetch_e(RawE<P, H>& r, const void* e, int64_t col) {
@@ -344,7 +357,7 @@ struct EdgeFeed {
 
 // Store an edge row in the operand format.  q (if not null) receives the
 // values as stored (FP8: decoded times `scale`), the terms of the message sums.
-template <int P, int H>
+template <int P, int H, bool NT = false>
 __device__ inline void store_e(void* e, int64_t col, const float* o, bool valid, float inv_scale, float scale = 1.f,
                                float* q = nullptr) {
   using L = ELayout<P, H>;
@@ -384,10 +397,15 @@ __device__ inline void store_e(void* e, int64_t col, const float* o, bool valid,
   if (!valid) return;
   if constexpr (L::LB >= 16) {
 #pragma unroll
-    for (int c = 0; c < L::NQ; ++c)
-      *reinterpret_cast<uint4*>(row + 64 * c + 16 * g) = make_uint4(w[4 * c], w[4 * c + 1], w[4 * c + 2], w[4 * c + 3]);
+    for (int c = 0; c < L::NQ; ++c) {
+      const uint4 v = make_uint4(w[4 * c], w[4 * c + 1], w[4 * c + 2], w[4 * c + 3]);
+      if constexpr (NT) store_stream4(row + 64 * c + 16 * g, v);
+      else *reinterpret_cast<uint4*>(row + 64 * c + 16 * g) = v;
+    }
   } else {
-    *reinterpret_cast<uint2*>(row + L::LB * g) = make_uint2(w[0], w[1]);
+    const uint2 v = make_uint2(w[0], w[1]);
+    if constexpr (NT) store_stream2(row + L::LB * g, v);
+    else *reinterpret_cast<uint2*>(row + L::LB * g) = v;
   }
 }
 
@@ -644,7 +662,7 @@ __global__ __launch_bounds__(512) void k_edge_encode(GnnArgs A) {
     gemm<P, H, H / 16>(o, a, w + S.w2(), 1.0f / s_ee2, o_ee2);
     ln_relu<H>(o);
     observe<H / 4>(A.calib, SC_GNN + Q_E, o, valid);
-    store_e<P, H>(A.e, col, o, valid, inv_e0, s_e0, o);
+    store_e<P, H, true>(A.e, col, o, valid, inv_e0, s_e0, o);
     if constexpr (OL)
       out_sums_lds<H>(A, tile, ti, key, o, reinterpret_cast<float*>(w + off) + wave * kOutBufFloats);
     else
