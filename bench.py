@@ -48,6 +48,7 @@ def parse():
                     help="bf16/fp8: store node and edge encodings in low precision (default: FP32 master copies)")
     ap.add_argument("--graph", type=int, default=0, help="replay the batch as one captured HIP graph")
     ap.add_argument("--autotune", type=int, default=0, help="tune the launch schedule on the batch before timing")
+    ap.add_argument("--autotune-log", default=None, help="append the autotuner's trials to this JSON-lines file")
     ap.add_argument("--copy-gib", type=float, default=0.0,
                     help="only run a plain device-to-device copy of this many GiB (counter calibration) and exit")
     ap.add_argument("--cpu-baseline", type=int, default=1)
@@ -239,7 +240,7 @@ def main():
     if args.autotune:
         with torch.cuda.stream(stream):
             out = p.allocate(b)
-            path = os.path.join(ROOT, "gpurun_out", "autotune.jsonl") if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None
+            path = args.autotune_log
             etx.etx_autotune(p.ctx, p.hits_struct(b), out, p.ws_ptr, p.ws_bytes, stream.cuda_stream, path)
         tuned = {k: etx.etx_get_option(p.ctx, v) for k, v in (("edge_threads", etx.ETX_OPT_EDGE_WG_SIZE),
                                                                ("edge_wg_per_cu", etx.ETX_OPT_EDGE_WG_PER_CU),
