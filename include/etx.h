@@ -46,7 +46,7 @@ typedef enum {
   ETX_ERR_CAPACITY = 2,      /* device: more edges than out->edge_capacity; status[1] = edges needed */
   ETX_ERR_INPUT = 3,         /* device: NaN/inf coordinate, plane outside [0, n_planes), bad hit_off */
   ETX_ERR_WEIGHTS = 4,       /* weight blob does not match the configuration */
-  ETX_ERR_UNSUPPORTED = 5,   /* a size this build does not handle (e.g. an event above ETX_MAX_EVENT_HITS) */
+  ETX_ERR_UNSUPPORTED = 5,   /* a size the library does not handle (e.g. an event above ETX_MAX_EVENT_HITS) */
   ETX_ERR_HIP = 6            /* a HIP runtime call failed */
 } etx_status;
 

@@ -1,6 +1,6 @@
 """Track efficiency with trained weights: the FP32 path against the oracle,
 the precision cost of BF16 and FP8 operands, and what the learned prefilter
-gains over the unpruned pipeline (which stays its fallback and judge).
+gains over the unpruned pipeline (which stays its fallback and reference).
 
 The weights come from paper_2508_07423_amd/train_weights.py (generator events
 of a disjoint seed space); with random weights the network keeps all or no
