@@ -208,11 +208,16 @@ def test_gnn_matches_dense_incidence_torch(H, S):
 
 
 def _pow2_at_or_above(m):
-    """2^ceil(log2(m / 448)) for the FP8 per-tensor scales (1 for m = 0)."""
-    if m <= 0:
+    """The FP8 per-tensor scale from its definition: the smallest power of two
+    s with m / s <= 448, found by walking powers of two (1 for m = 0)."""
+    if not m > 0:
         return 1.0
-    f, e = np.frexp(m / 448.0)
-    return float(np.ldexp(1.0, int(e) - 1 if f == 0.5 else int(e)))
+    s = 1.0
+    while m / s > 448.0:
+        s *= 2.0
+    while m / (s / 2.0) <= 448.0:
+        s /= 2.0
+    return s
 
 
 def _dense_gnn_quantised(cart, src, dst, weights, H, S, qmode, act_scale, compact):
