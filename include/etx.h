@@ -136,7 +136,9 @@ typedef enum {
   ETX_VIEW_CALIB = 9,        /* float [ETX_N_CALIB]: per-tensor amax (calibration observers) */
   ETX_VIEW_PF_KEEP = 10,     /* uint8 [edge_capacity]: prefilter decision per candidate edge */
   ETX_VIEW_PF_GRAD = 11,     /* float [ETX_PF_NPARAM + 1]: last prefilter gradient, then the loss */
-  ETX_VIEW_PF_PROB = 12      /* float [edge_capacity]: prefilter probability per candidate edge */
+  ETX_VIEW_PF_PROB = 12,     /* float [edge_capacity]: prefilter probability per candidate edge */
+  ETX_VIEW_PF_FEAT = 13      /* float [edge_capacity][8]: the six prefilter features of every candidate edge (then two
+                                zeros), written only with ETX_OPT_PF_FEATURES set (otherwise ETX_ERR_INVALID_ARG) */
 } etx_view;
 #define ETX_N_CALIB 64
 etx_status etx_workspace_view(const etx_ctx* ctx, int64_t n_events, int64_t n_hits, int64_t edge_capacity,
@@ -182,11 +184,16 @@ typedef enum {
   ETX_OPT_CSC_PLACE = 18,      /* 1 (default): for events with short rows (< 16 edges per hit) the whole block drops
                                   the edges into their CSC columns through LDS cursors and then sorts every column by
                                   edge index (source order); 0: one wave ranks 64 edges at a time; same permutation */
-  ETX_OPT_COMPACT_STATE = 19   /* BF16 and FP8 runs only (FP32 and INT8 runs ignore it).  0 (default): the node encodings h and edge encodings e
+  ETX_OPT_COMPACT_STATE = 19,  /* BF16 and FP8 runs only (FP32 and INT8 runs ignore it).  0 (default): the node encodings h and edge encodings e
                                   are kept in FP32 between kernels (residual master copies) and quantised only where
                                   they enter a GEMM.  1: both are stored in low precision (h as BF16; e in the
                                   operand format, FP8 with the e_k scale), which halves or quarters their HBM
                                   traffic; the residual sums are then rounded at every step (different results) */
+  ETX_OPT_PROFILE_STAGES = 20, /* bit mask of the stages (etx_stage_name indices) that ETX_OPT_PROFILE times; default
+                                  every stage.  Timing one kernel alone leaves the rest of a pass uninstrumented */
+  ETX_OPT_PF_FEATURES = 21     /* 1: the prefilter's inference pass also stores the features of every candidate edge
+                                  (ETX_VIEW_PF_FEAT; the workspace grows by 32 bytes per edge of capacity: set it
+                                  before sizing the workspace); 0 (default): features are formed in registers only */
 } etx_option;
 etx_status etx_set_option(etx_ctx* ctx, int32_t key, int64_t value);
 etx_status etx_get_option(const etx_ctx* ctx, int32_t key, int64_t* value);
@@ -200,10 +207,28 @@ etx_status etx_profile_read(etx_ctx* ctx, int32_t n_stages, double* total_ms, in
 etx_status etx_profile_reset(etx_ctx* ctx);
 const char* etx_stage_name(int32_t stage);   /* "" for an unknown stage */
 
-/* Try each candidate launch schedule on this batch, keep the fastest, and
- * append the choice to `json_path` (may be NULL).  Synchronises the stream. */
+/* Try each candidate launch schedule on this batch (one knob at a time, each
+ * judged by the HIP-event time of the stages it drives; no knob changes a
+ * result bit), keep the fastest, and record it in the context's tuning table
+ * under the batch's key: the configuration and run modes (precision, embedding
+ * precision, compact state, prefilter) plus the shape bucket (hits per event
+ * and events per batch, each rounded to the nearest power of two).  Appends the
+ * trials to `json_path` (JSON lines; may be NULL).  Synchronises the stream.
+ * The device status of the first trial is read back: an error there (edge
+ * capacity, bad input) is returned, and the options in effect before the call
+ * are restored, as after any failure. */
 etx_status etx_autotune(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void* ws, size_t ws_bytes,
                         etx_stream stream, const char* json_path);
+/* Tuning table.  etx_run applies the entry of its batch's key when the table
+ * has one (the options stay until a batch of another key with an entry comes,
+ * or etx_set_option changes them).  etx_tuning_save merges the context's
+ * entries into the text file at `path` (entries of other architectures,
+ * configurations or buckets are kept); etx_tuning_load adds the file's entries
+ * for this device's architecture (ETX_ERR_INVALID_ARG if it cannot be read).
+ * etx_create loads the file named by the environment variable
+ * ETX_TUNING_TABLE, if set and readable. */
+etx_status etx_tuning_save(const etx_ctx* ctx, const char* path);
+etx_status etx_tuning_load(etx_ctx* ctx, const char* path);
 
 /* Static calibration for the low-precision modes (thesis ch. 4 "Quantization",
  * static post-training quantisation): runs the FP32 path on `hits`, records

@@ -4,6 +4,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -67,6 +68,7 @@ WsLayout ws_layout(const etx_ctx* ctx, int64_t n_events, int64_t n_hits, int64_t
   L.pf_part = take(sizeof(float) * (size_t)kPfMaxWaves * kPfGradStride);
   L.pf_grad = take(sizeof(float) * kPfGradStride);
   L.pf_polar = take(sizeof(float) * 2 * n_hits);
+  L.pf_feat = take(ctx->pf_features ? sizeof(float) * 8 * edge_cap : 0);
   L.total = o;
   return L;
 }
@@ -413,7 +415,7 @@ struct StageTimer {
   hipStream_t s;
   int idx = -1;
   StageTimer(const RunArgs& a, int stage) : ctx(const_cast<etx_ctx*>(a.ctx)), s(a.stream) {
-    if (!ctx->profile) return;
+    if (!ctx->profile || !((ctx->profile_mask >> stage) & 1)) return;
     if (ctx->n_marks == ctx->marks.size()) {
       etx_ctx::Mark m{stage, nullptr, nullptr};
       if (hipEventCreate(&m.start) != hipSuccess) return;
@@ -553,6 +555,16 @@ etx_status etx_create(const etx_config* cfg, const void* weights, size_t nbytes,
     delete ctx;
     return ETX_ERR_HIP;
   }
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+      delete ctx;
+      return ETX_ERR_HIP;
+    }
+    ctx->arch = prop.gcnArchName;
+    const size_t colon = ctx->arch.find(':');
+    if (colon != std::string::npos) ctx->arch.resize(colon);
+  }
   weight_scales(ctx, layers);
   st = ETX_OK;
   for (int p = 0; p < kNumSegs && st == ETX_OK; ++p) st = build_segments(ctx, layers, p);
@@ -565,6 +577,8 @@ etx_status etx_create(const etx_config* cfg, const void* weights, size_t nbytes,
     etx_destroy(ctx);
     return st;
   }
+  // a tuning table named by the environment (a missing or unreadable file is no error: no entries)
+  if (const char* table = std::getenv("ETX_TUNING_TABLE")) (void)etx_tuning_load(ctx, table);
   *out = ctx;
   return ETX_OK;
 }
@@ -612,6 +626,11 @@ etx_status etx_workspace_view(const etx_ctx* ctx, int64_t n_events, int64_t n_hi
     case ETX_VIEW_PF_KEEP: *offset = L.pf_keep; *bytes = edge_capacity; break;
     case ETX_VIEW_PF_GRAD: *offset = L.pf_grad; *bytes = sizeof(float) * (ETX_PF_NPARAM + 1); break;
     case ETX_VIEW_PF_PROB: *offset = L.pf_prob; *bytes = sizeof(float) * edge_capacity; break;
+    case ETX_VIEW_PF_FEAT:
+      if (!ctx->pf_features) return ETX_ERR_INVALID_ARG;
+      *offset = L.pf_feat;
+      *bytes = sizeof(float) * 8 * edge_capacity;
+      break;
     default: return ETX_ERR_INVALID_ARG;
   }
   return ETX_OK;
@@ -700,6 +719,14 @@ etx_status etx_set_option(etx_ctx* ctx, int32_t key, int64_t value) {
       if (value != 0 && value != 1) return ETX_ERR_INVALID_ARG;
       ctx->compact_state = (int)value;
       break;
+    case ETX_OPT_PF_FEATURES:
+      if (value != 0 && value != 1) return ETX_ERR_INVALID_ARG;
+      ctx->pf_features = (int)value;
+      break;
+    case ETX_OPT_PROFILE_STAGES:
+      if (value <= 0 || value >= (int64_t(1) << kNumStages)) return ETX_ERR_INVALID_ARG;
+      ctx->profile_mask = value;
+      return ETX_OK;
     default: return ETX_ERR_INVALID_ARG;
   }
   if (key != ETX_OPT_USE_GRAPH) clear_graphs(ctx);
@@ -762,6 +789,8 @@ etx_status etx_get_option(const etx_ctx* ctx, int32_t key, int64_t* value) {
     case ETX_OPT_CSC_PLACE: *value = ctx->csc_place; break;
     case ETX_OPT_COMPACT_STATE: *value = ctx->compact_state; break;
     case ETX_OPT_PROFILE: *value = ctx->profile; break;
+    case ETX_OPT_PROFILE_STAGES: *value = ctx->profile_mask; break;
+    case ETX_OPT_PF_FEATURES: *value = ctx->pf_features; break;
     default: return ETX_ERR_INVALID_ARG;
   }
   return ETX_OK;
@@ -784,6 +813,18 @@ etx_status etx_run(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void* ws, s
   if ((scaled(ctx->cfg.precision) || scaled(ctx->emb_precision)) && !ctx->calibrated) return ETX_ERR_INVALID_ARG;
   if (ctx->cfg.prefilter && !ctx->pf_set) return ETX_ERR_INVALID_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return ETX_ERR_HIP;
+  if (!ctx->tuning.empty()) {
+    // the tuning table's schedule for this batch's shape bucket, when it has one
+    const std::string key = tuning_key(ctx, hits->n_events, hits->n_hits);
+    if (key != ctx->tuning_applied) {
+      auto it = ctx->tuning.find(key);
+      if (it != ctx->tuning.end()) {
+        for (const auto& kv : it->second)
+          if ((st = etx_set_option(ctx, kv.first, kv.second)) != ETX_OK) return st;
+        ctx->tuning_applied = key;
+      }
+    }
+  }
   RunArgs a{ctx, *hits, *out, L, static_cast<char*>(ws), static_cast<hipStream_t>(stream), false,
             kernel_precision(ctx)};
   if (!ctx->use_graph || stream == nullptr) {

@@ -46,7 +46,7 @@ struct WeightMap {
 // Byte offsets of the workspace buffers.
 struct WsLayout {
   size_t bucket, plane_off, emb, cnt, slots, row_ptr, scan_tmp, col_ptr, csc, h, ps, pd, msg, e, opart, kept, kept_cnt,
-      calib, pf_keep, pf_tmp, cand_src, cand_dst, pf_prob, pf_part, pf_grad, pf_polar, total;
+      calib, pf_keep, pf_tmp, cand_src, cand_dst, pf_prob, pf_part, pf_grad, pf_polar, pf_feat, total;
   int64_t n_scan_blocks;
 };
 
@@ -89,17 +89,23 @@ struct etx_ctx {
   int xcd_map = 0;                 // tile and node kernels: contiguous work per XCD
   int edge_products = 0;           // 1: edge kernels form the node-product terms from gathered h rows
   int csc_place = 1;               // short-row CSC placed by the whole block, then columns sorted
+  int pf_features = 0;             // 1: prefilter inference also stores each candidate's features
   int compact_state = 0;           // BF16/FP8 runs: 1 keeps h, e in the operand format, 0 in FP32 (residual masters)
   std::vector<char> blob;          // the weight blob as given (for etx_save)
   int use_graph = 0;
   std::map<etx::GraphKey, hipGraphExec_t> graphs;
   // stage timing with HIP events (ETX_OPT_PROFILE)
   int profile = 0;
+  int64_t profile_mask = 0x7fffffff;   // stages timed when profiling (bit i: stage i)
   struct Mark { int stage; hipEvent_t start, end; };
   std::vector<Mark> marks;
   size_t n_marks = 0;
   double stage_ms[32] = {};
   int64_t stage_launches[32] = {};
+  // tuning table: "signature bucket" -> tuned option values (etx_autotune, etx_tuning_load)
+  std::string arch;                // device architecture name, e.g. "gfx950"
+  std::map<std::string, std::vector<std::pair<int32_t, int64_t>>> tuning;
+  std::string tuning_applied;      // key of the entry whose options are in effect
 };
 
 namespace etx {
@@ -147,5 +153,12 @@ constexpr int kPfMaxWaves = 256 * 2 * 8;                    // partial slots (CU
 hipError_t launch_quantize(int prec, const float* in, float* out, int64_t n, float scale, hipStream_t s);
 
 int set_kernel_attributes();
+
+// Tuning-table key of a batch for this context: the configuration and run
+// modes that change the best schedule, then the shape bucket.
+std::string tuning_key(const etx_ctx* ctx, int64_t n_events, int64_t n_hits);
+// Options the autotuner sets (saved in the tuning table).
+extern const int32_t kTunedOptions[];
+extern const int kNumTunedOptions;
 
 }  // namespace etx

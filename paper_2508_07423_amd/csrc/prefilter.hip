@@ -48,6 +48,7 @@ struct PfArgs {
   float inv_r, inv_z, tau;
   uint8_t* keep;             // inference output [candidates]
   float* prob;               // inference output: probability per candidate
+  float* feat;               // inference output when requested: features per candidate [8] (else null)
   const uint8_t* label;      // training labels [candidates]
   float pos_weight;
   float* partial;            // [waves][kPfGradStride]
@@ -176,6 +177,11 @@ __global__ __launch_bounds__(kPfThreads) void k_pf(PfArgs A) {
       if (valid && g == 0) {
         A.keep[col] = prob >= A.tau ? 1 : 0;
         A.prob[col] = prob;
+        if (A.feat) {
+          float4* fo = reinterpret_cast<float4*>(A.feat + col * 8);
+          fo[0] = make_float4(f[0], f[1], f[2], f[3]);
+          fo[1] = make_float4(f[4], f[5], 0.f, 0.f);
+        }
       }
       continue;
     }
@@ -338,6 +344,7 @@ PfArgs pf_args(const RunArgs& a, bool candidates) {
   A.tau = a.ctx->cfg.prefilter_tau;
   A.keep = reinterpret_cast<uint8_t*>(a.ws + a.L.pf_keep);
   A.prob = reinterpret_cast<float*>(a.ws + a.L.pf_prob);
+  A.feat = a.ctx->pf_features ? reinterpret_cast<float*>(a.ws + a.L.pf_feat) : nullptr;
   A.partial = reinterpret_cast<float*>(a.ws + a.L.pf_part);
   A.status = a.out.status;
   return A;

@@ -26,12 +26,13 @@ ETX_PF_HIDDEN = 32
 ETX_PF_NPARAM = 6 * 32 + 32 + 32 * 32 + 32 + 32 + 1
 (ETX_VIEW_EMBEDDING, ETX_VIEW_BUCKET, ETX_VIEW_PLANE_OFF, ETX_VIEW_ROW_PTR, ETX_VIEW_COL_PTR, ETX_VIEW_CSC_EDGE,
  ETX_VIEW_NODE_H, ETX_VIEW_KEPT_EDGE, ETX_VIEW_KEPT_COUNT, ETX_VIEW_CALIB, ETX_VIEW_PF_KEEP, ETX_VIEW_PF_GRAD,
- ETX_VIEW_PF_PROB) = range(13)
+ ETX_VIEW_PF_PROB, ETX_VIEW_PF_FEAT) = range(14)
 (ETX_OPT_USE_GRAPH, ETX_OPT_EDGE_WG_PER_CU, ETX_OPT_NODE_WG_PER_CU, ETX_OPT_RADIUS_LDS,
  ETX_OPT_SEGSUM_UNROLL, ETX_OPT_PROFILE, ETX_OPT_EDGE_PIPELINE, ETX_OPT_EDGE_WG_SIZE,
  ETX_OPT_EDGE_WREG, ETX_OPT_EMBED_PRECISION, ETX_OPT_OUTSUM_LDS, ETX_OPT_F32_SPLIT,
  ETX_OPT_RADIUS_SINGLE_PASS, ETX_OPT_RADIUS_SORT_MIN, ETX_OPT_FUSE_MESSAGES, ETX_OPT_RADIUS_FAST,
- ETX_OPT_XCD_MAP, ETX_OPT_EDGE_PRODUCTS, ETX_OPT_CSC_PLACE, ETX_OPT_COMPACT_STATE) = range(20)
+ ETX_OPT_XCD_MAP, ETX_OPT_EDGE_PRODUCTS, ETX_OPT_CSC_PLACE, ETX_OPT_COMPACT_STATE,
+ ETX_OPT_PROFILE_STAGES, ETX_OPT_PF_FEATURES) = range(22)
 N_STAGES = 17
 
 
@@ -87,6 +88,8 @@ def lib():
             "etx_profile_reset": [P],
             "etx_save": [P, P, C.POINTER(sz)],
             "etx_load": [P, sz, C.c_int, C.POINTER(P)],
+            "etx_tuning_save": [P, C.c_char_p],
+            "etx_tuning_load": [P, C.c_char_p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -106,7 +109,8 @@ EXPORTED = ["etx_create", "etx_destroy", "etx_weight_blob_size", "etx_workspace_
             "etx_workspace_view", "etx_set_option", "etx_get_option", "etx_autotune", "etx_calibrate",
             "etx_set_precision", "etx_prefilter_set", "etx_prefilter_get", "etx_prefilter_train_step",
             "etx_prefilter_state", "etx_status_str", "etx_last_error", "etx_profile_read", "etx_profile_reset",
-            "etx_stage_name", "etx_get_scales", "etx_quantize", "etx_prefilter_config", "etx_save", "etx_load"]
+            "etx_stage_name", "etx_get_scales", "etx_quantize", "etx_prefilter_config", "etx_save", "etx_load",
+            "etx_tuning_save", "etx_tuning_load"]
 
 
 class EtxError(RuntimeError):
@@ -177,6 +181,14 @@ def etx_get_option(ctx, key: int) -> int:
 def etx_autotune(ctx, hits, out, ws_ptr, ws_bytes, stream, json_path: Optional[str] = None) -> None:
     _check(lib().etx_autotune(ctx, C.byref(hits), C.byref(out), C.c_void_p(ws_ptr), ws_bytes, C.c_void_p(stream),
                               json_path.encode() if json_path else None), "etx_autotune")
+
+
+def etx_tuning_save(ctx, path: str) -> None:
+    _check(lib().etx_tuning_save(ctx, path.encode()), "etx_tuning_save")
+
+
+def etx_tuning_load(ctx, path: str) -> None:
+    _check(lib().etx_tuning_load(ctx, path.encode()), "etx_tuning_load")
 
 
 def etx_calibrate(ctx, hits, out, ws_ptr, ws_bytes, stream) -> None:

@@ -57,21 +57,57 @@ def event_metrics(labels: np.ndarray, particle: np.ndarray, plane: np.ndarray, m
                 purity_sum=float(np.sum(purity)), hit_eff_sum=float(np.sum(hit_eff)), matched=len(purity))
 
 
-def batch_metrics(labels: np.ndarray, batch: Dict[str, np.ndarray], events: Sequence[int] = None) -> Dict[str, float]:
+def batch_metrics(labels: np.ndarray, batch: Dict[str, np.ndarray], events: Sequence[int] = None,
+                  min_hits: int = 3, match_frac: float = 0.7) -> Dict[str, float]:
     """Aggregate metrics over the events of a packed batch (labels may be
-    global indices; only the partition matters)."""
-    ho = batch["hit_off"]
-    idx = range(len(ho) - 1) if events is None else events
-    tot = dict(reconstructible=0, reconstructed=0, tracks=0, fake=0, clone=0, purity_sum=0.0, hit_eff_sum=0.0,
-               matched=0)
-    for i in idx:
-        a, b = int(ho[i]), int(ho[i + 1])
-        m = event_metrics(labels[a:b], batch["particle"][a:b], batch["plane"][a:b])
-        for k in tot:
-            tot[k] += m[k]
-    return dict(efficiency=tot["reconstructed"] / max(tot["reconstructible"], 1),
-                ghost_rate=tot["fake"] / max(tot["tracks"], 1),
-                clone_rate=tot["clone"] / max(tot["tracks"], 1),
-                hit_purity=tot["purity_sum"] / max(tot["matched"], 1),
-                hit_efficiency=tot["hit_eff_sum"] / max(tot["matched"], 1),
-                tracks=tot["tracks"], reconstructible=tot["reconstructible"])
+    global indices or any int32 values; only the partition inside an event
+    matters).  The same definitions as ``event_metrics``, evaluated for every
+    event at once with sorted keys (event, label) and (event, particle)."""
+    ho = np.asarray(batch["hit_off"], np.int64)
+    n_ev = len(ho) - 1
+    idx = np.arange(n_ev) if events is None else np.asarray(list(events), np.int64)
+    cnt = ho[idx + 1] - ho[idx]
+    hit = np.concatenate([np.arange(ho[i], ho[i + 1]) for i in idx]) if events is not None else np.arange(ho[-1])
+    ev = np.repeat(np.arange(len(idx), dtype=np.int64), cnt)
+    lab = np.asarray(labels)[hit].astype(np.int64)
+    part = np.asarray(batch["particle"])[hit].astype(np.int64)
+    pl = np.asarray(batch["plane"])[hit].astype(np.int64)
+    # particles: dense ids over (event, particle); reconstructible on >= min_hits distinct planes
+    real = part >= 0
+    pkey = (ev << 32) | (part & 0xFFFFFFFF)
+    pu, pinv, pcount = np.unique(pkey[real], return_inverse=True, return_counts=True)
+    pdense = np.full(len(part), -1, np.int64)
+    pdense[real] = pinv
+    planes_of = np.bincount(np.unique(pinv * 64 + pl[real]) // 64, minlength=len(pu))
+    reco_able = planes_of >= min_hits
+    # tracks: components of >= min_hits hits
+    lkey = (ev << 32) | ((lab + (1 << 31)) & 0xFFFFFFFF)
+    lu, linv, lcount = np.unique(lkey, return_inverse=True, return_counts=True)
+    is_track = lcount >= min_hits
+    n_tracks = int(is_track.sum())
+    # per track, the particle with the most hits (ties: the smallest particle id)
+    sel = real & is_track[linv]
+    pair = linv[sel] * max(len(pu), 1) + pdense[sel]
+    pairs, pc = np.unique(pair, return_counts=True)
+    ptrack, ppart = pairs // max(len(pu), 1), pairs % max(len(pu), 1)
+    order = np.lexsort((ppart, -pc, ptrack))
+    first = np.ones(len(order), bool)
+    first[1:] = ptrack[order][1:] != ptrack[order][:-1]
+    best = order[first]
+    bt, bp, bn = ptrack[best], ppart[best], pc[best]
+    members = lcount[bt]
+    ok = ~(bn < match_frac * members)
+    bt, bp, bn, members = bt[ok], bp[ok], bn[ok], members[ok]
+    matched_ids = np.unique(bp)
+    n_matched = len(bt)
+    n_fake = n_tracks - n_matched
+    n_clone = n_matched - len(matched_ids)
+    n_reco = int(reco_able[matched_ids].sum())
+    purity_sum = float(np.sum(bn / members))
+    hit_eff_sum = float(np.sum(bn / pcount[bp]))
+    return dict(efficiency=n_reco / max(int(reco_able.sum()), 1),
+                ghost_rate=n_fake / max(n_tracks, 1),
+                clone_rate=n_clone / max(n_tracks, 1),
+                hit_purity=purity_sum / max(n_matched, 1),
+                hit_efficiency=hit_eff_sum / max(n_matched, 1),
+                tracks=n_tracks, reconstructible=int(reco_able.sum()))

@@ -43,13 +43,30 @@ def check_edges(gsrc, gdst, ref, ev_plane, w, emb64):
             assert np.array_equal(g, o), f"row {i}: gpu {g} oracle {o}"
         else:
             n_undec += 1
-            assert len(g) <= w.k_max
-            dp = ev_plane[g] - ev_plane[i]
-            assert np.all((dp >= 1) & (dp <= w.plane_window))
-            d = np.sqrt(((emb64[g] - emb64[i]) ** 2).sum(1))
-            assert np.all(d < r + EDGE_EPS)
-            assert np.all(np.diff(g) > 0)
+            check_undecidable_row(i, g, ev_plane, emb64, r, w)
     return n_undec, ~decidable
+
+
+def check_undecidable_row(i, g, ev_plane, emb64, r, w):
+    """A row with a candidate within EDGE_EPS of r, or a near tie at the k_max
+    boundary: the GPU row holds only possible targets (window, d < r + eps),
+    ascending, at most k_max of them, and every certain target: one with
+    d < r - eps that at most k_max - 1 other possible candidates could precede
+    (d' < d + eps).  It holds at least min(k_max, #(d < r - eps)) targets."""
+    assert len(g) <= w.k_max
+    assert np.all(np.diff(g) > 0)
+    dp = ev_plane - ev_plane[i]
+    win = np.nonzero((dp >= 1) & (dp <= w.plane_window))[0]
+    d = np.sqrt(((emb64[win] - emb64[i]) ** 2).sum(1))
+    possible = win[d < r + EDGE_EPS]
+    assert np.all(np.isin(g, possible)), f"row {i}: {np.setdiff1d(g, possible)} not within r + eps"
+    dpos = np.sort(d[d < r + EDGE_EPS])
+    inside = d < r - EDGE_EPS
+    ahead = np.searchsorted(dpos, d + EDGE_EPS, side="left")     # possible candidates with d' < d + eps
+    certain = win[inside & (ahead <= w.k_max)]
+    missing = np.setdiff1d(certain, g)
+    assert len(missing) == 0, f"row {i}: certain targets {missing} missing"
+    assert len(g) >= min(w.k_max, int(inside.sum())), f"row {i}: {len(g)} targets"
 
 
 def check_scores(gsrc, gdst, gscore, cart64, weights, w, ref=None):

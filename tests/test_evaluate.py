@@ -38,3 +38,43 @@ def test_short_components_are_not_tracks():
     labels = np.array([0, 0, 2, 3, 3, 5])                # every component has < 3 hits
     m = E.batch_metrics(labels, dict(particle=particle, plane=plane, hit_off=np.array([0, 6])))
     assert m["tracks"] == 0 and m["efficiency"] == 0.0
+
+
+def test_batch_metrics_equals_the_per_event_definition():
+    """The vectorised batch aggregate equals the sum of the per-event counts of
+    ``event_metrics`` (random partitions, particles and noise)."""
+    rng = np.random.default_rng(5)
+    ho = [0]
+    parts, planes, labels = [], [], []
+    for ev in range(40):
+        n = int(rng.integers(0, 60))
+        parts.append(rng.integers(-1, 8, n))
+        planes.append(rng.integers(0, 6, n))
+        labels.append(ho[-1] + rng.integers(0, max(n // 3, 1), n))   # global-index-like labels
+        ho.append(ho[-1] + n)
+    batch = dict(particle=np.concatenate(parts), plane=np.concatenate(planes), hit_off=np.array(ho))
+    lab = np.concatenate(labels)
+    tot = dict(reconstructible=0, reconstructed=0, tracks=0, fake=0, clone=0, purity_sum=0.0, hit_eff_sum=0.0,
+               matched=0)
+    for i in range(40):
+        a, b = ho[i], ho[i + 1]
+        m = E.event_metrics(lab[a:b], batch["particle"][a:b], batch["plane"][a:b])
+        for k in tot:
+            tot[k] += m[k]
+    m = E.batch_metrics(lab, batch)
+    assert m["reconstructible"] == tot["reconstructible"] and m["tracks"] == tot["tracks"]
+    assert np.isclose(m["efficiency"], tot["reconstructed"] / tot["reconstructible"])
+    assert np.isclose(m["ghost_rate"], tot["fake"] / tot["tracks"])
+    assert np.isclose(m["clone_rate"], tot["clone"] / tot["tracks"])
+    assert np.isclose(m["hit_purity"], tot["purity_sum"] / tot["matched"])
+    assert np.isclose(m["hit_efficiency"], tot["hit_eff_sum"] / tot["matched"])
+    sub = [3, 7, 11]
+    ms = E.batch_metrics(lab, batch, events=sub)
+    t2 = dict(reconstructible=0, reconstructed=0)
+    for i in sub:
+        a, b = ho[i], ho[i + 1]
+        mm = E.event_metrics(lab[a:b], batch["particle"][a:b], batch["plane"][a:b])
+        t2["reconstructible"] += mm["reconstructible"]
+        t2["reconstructed"] += mm["reconstructed"]
+    assert ms["reconstructible"] == t2["reconstructible"]
+    assert np.isclose(ms["efficiency"], t2["reconstructed"] / max(t2["reconstructible"], 1))
