@@ -310,6 +310,7 @@ def north_star(args, stream):
         if pf is not None:
             etx.etx_prefilter_set(p.ctx, pf["params"])
             etx.etx_prefilter_config(p.ctx, 1, pf["tau"])
+            etx.etx_prefilter_band(p.ctx, *pf["band"])
         b = etx.to_device(batch)
         t0 = time.perf_counter()
         tuned = autotune(etx, p, b, stream, args.autotune_log)
@@ -321,12 +322,18 @@ def north_star(args, stream):
         if st[0] != etx.ETX_OK:
             raise etx.EtxError(int(st[0]), f"{name}: device status")
         r = dict(edge_off=p.edge_off.cpu().numpy(), labels=p.labels[:b.n_hits].cpu().numpy())
+        fallback = None
+        if pf is not None:
+            fallback = int(p.view(b, etx.ETX_VIEW_PF_FALLBACK, torch.int32).sum().item())
         p.close()
         del b
         torch.cuda.empty_cache()
         log(f"[bench] {name}: {eps:.0f} events/s ({ms:.2f} ms per pass, tuning {t_tune:.0f} s)")
-        return dict(events_per_s=round(eps, 1), ms_per_pass=round(ms, 3), ms_per_pass_median=round(med, 3),
-                    steps=steps, edges=int(r["edge_off"][-1]), schedule=tuned, tune_s=round(t_tune, 1)), r
+        out = dict(events_per_s=round(eps, 1), ms_per_pass=round(ms, 3), ms_per_pass_median=round(med, 3),
+                   steps=steps, edges=int(r["edge_off"][-1]), schedule=tuned, tune_s=round(t_tune, 1))
+        if fallback is not None:
+            out["fallback_events"] = fallback
+        return out, r
 
     # c3: uneven batch, plain FP32, random weights
     w3 = synth.WORKLOADS["c3"]
@@ -351,7 +358,7 @@ def north_star(args, stream):
     t_tr = time.perf_counter() - t0
     sel = PT.choose_tau(w5, weights5, tr["params"], synth.generate_batch(w5, 100, seed_space=6000 + w5.cid),
                         recall=args.pf_recall)
-    pf = dict(params=tr["params"], tau=sel["tau"])
+    pf = dict(params=tr["params"], tau=sel["tau"], band=sel["band"])
     log(f"[bench] prefilter: {args.pf_train_events} events, {tr['steps']} steps, {t_tr:.1f} s; "
         f"tau {sel['tau']:.4f} keeps {sel['kept_fraction']:.3f} of validation candidates")
     batch5 = synth.generate_batch(w5, w5.n_events)
@@ -372,7 +379,8 @@ def north_star(args, stream):
                      prefilter=dict(train_events=args.pf_train_events, train_steps=tr["steps"],
                                     train_s=round(t_tr, 1), tau=round(sel["tau"], 5),
                                     recall_target=args.pf_recall,
-                                    validation_kept=round(sel["kept_fraction"], 4)),
+                                    validation_kept=round(sel["kept_fraction"], 4),
+                                    fallback_band=[round(x, 4) for x in sel["band"]]),
                      legs=legs)
     return res
 
@@ -431,6 +439,7 @@ def main():
     if use_pf:
         etx.etx_prefilter_set(p.ctx, tr["params"])
         etx.etx_prefilter_config(p.ctx, 1, sel["tau"])
+        etx.etx_prefilter_band(p.ctx, *sel["band"])
     b = etx.to_device(batch)
     tuned = autotune(etx, p, b, stream, args.autotune_log) if args.autotune else None
     if tuned:

@@ -137,8 +137,10 @@ typedef enum {
   ETX_VIEW_PF_KEEP = 10,     /* uint8 [edge_capacity]: prefilter decision per candidate edge */
   ETX_VIEW_PF_GRAD = 11,     /* float [ETX_PF_NPARAM + 1]: last prefilter gradient, then the loss */
   ETX_VIEW_PF_PROB = 12,     /* float [edge_capacity]: prefilter probability per candidate edge */
-  ETX_VIEW_PF_FEAT = 13      /* float [edge_capacity][8]: the six prefilter features of every candidate edge (then two
+  ETX_VIEW_PF_FEAT = 13,     /* float [edge_capacity][8]: the six prefilter features of every candidate edge (then two
                                 zeros), written only with ETX_OPT_PF_FEATURES set (otherwise ETX_ERR_INVALID_ARG) */
+  ETX_VIEW_PF_FALLBACK = 14  /* int32 [n_events]: 1 where the event fell back to the unpruned graph (its kept fraction
+                                left the prefilter band), else 0; written by prefiltered runs */
 } etx_view;
 #define ETX_N_CALIB 64
 etx_status etx_workspace_view(const etx_ctx* ctx, int64_t n_events, int64_t n_hits, int64_t edge_capacity,
@@ -274,6 +276,13 @@ etx_status etx_prefilter_train_step(etx_ctx* ctx, const etx_hits* hits, etx_out*
                                     size_t ws_bytes, etx_stream stream);
 /* Turn the prefilter on or off and set its threshold (keep when p >= tau). */
 etx_status etx_prefilter_config(etx_ctx* ctx, int32_t enabled, float tau);
+/* Fallback band: an event whose fraction of kept candidate edges lies outside
+ * [lo, hi] (0 <= lo <= hi <= 1) is run unpruned: every candidate of the event
+ * is kept, so its edges, scores and labels are those of the pipeline without
+ * the prefilter.  The band is the range validated with tau (the prefilter's
+ * efficiency loss was measured there); outside it the pruning is not trusted.
+ * Default [0, 1]: no fallback.  Which events fell back: ETX_VIEW_PF_FALLBACK. */
+etx_status etx_prefilter_band(etx_ctx* ctx, float lo, float hi);
 /* Optimiser state for checkpointing: params, Adam m, Adam v (3 * ETX_PF_NPARAM floats). */
 etx_status etx_prefilter_state(etx_ctx* ctx, float* host_state, int64_t n, int32_t set);
 

@@ -124,39 +124,87 @@ void oracle_features(int64_t n, const float* x, const float* y, const float* z,
 /* dense layers                                                              */
 /* ------------------------------------------------------------------------ */
 
-/* out[m] = b[m] + sum_k q(in[k]) q(W[k][m]);  W row-major [K][M] */
-static void linear(const double* in, int K, const double* W, const double* b, int M,
-                   double* out, int qmode, double s_in, double s_w) {
-  for (int m = 0; m < M; ++m) {
-    double acc = 0.0;
-    for (int k = 0; k < K; ++k) acc += qv(qmode, in[k], s_in) * qv(qmode, W[(int64_t)k * M + m], s_w);
-    out[m] = acc + b[m];
+/* FP32 evaluation (f32 set): every arithmetic result is rounded to FP32, as
+ * an FP32 implementation of the same network would round it.  Used only to
+ * measure how far two FP32 evaluations of one (quantised) network fall apart,
+ * which sets the low-precision parity tolerances; f32 = 0 is the oracle. */
+#define RF(f32, x) ((f32) ? (double)(float)(x) : (x))
+
+/* the quantised copy of a weight matrix (each element rounded once) */
+static double* qcopy(int qmode, const double* W, int64_t n, double scale) {
+  double* q = (double*)malloc(sizeof(double) * (n > 0 ? n : 1));
+  for (int64_t i = 0; i < n; ++i) q[i] = qv(qmode, W[i], scale);
+  return q;
+}
+
+/* a GEMM input operand: its quantised value; in FP32 evaluation an INT8 code
+ * is taken from x times the FP32 reciprocal of the scale */
+static double qin(int qmode, double x, double scale, int f32) {
+  if (f32 && qmode == 3) return scale * oracle_round_int8(RF(1, x * RF(1, 1.0 / scale)));
+  return qv(qmode, x, scale);
+}
+
+/* out[m] = b[m] + sum_k q[k] Wq[k][m]: every output's sum runs over k in
+ * order (the outputs are independent; they advance together, row by row of Wq) */
+static void dot_rows(const double* q, int K, const double* Wq, const double* b, int M, double* out, int f32) {
+  double accs[512];
+  float accf[512];
+  double* acc = M <= 512 ? accs : (double*)malloc(sizeof(double) * M);
+  float* af = M <= 512 ? accf : (float*)malloc(sizeof(float) * M);
+  if (!f32) {
+    for (int m = 0; m < M; ++m) acc[m] = 0.0;
+    for (int k = 0; k < K; ++k) {
+      const double qk = q[k];
+      const double* w = Wq + (int64_t)k * M;
+      for (int m = 0; m < M; ++m) acc[m] += qk * w[m];
+    }
+    for (int m = 0; m < M; ++m) out[m] = acc[m] + b[m];
+  } else {
+    for (int m = 0; m < M; ++m) af[m] = 0.f;
+    for (int k = 0; k < K; ++k) {
+      const double qk = q[k];
+      const double* w = Wq + (int64_t)k * M;
+      for (int m = 0; m < M; ++m) af[m] = (float)((double)af[m] + qk * w[m]);
+    }
+    for (int m = 0; m < M; ++m) out[m] = (float)((double)af[m] + b[m]);
   }
+  if (acc != accs) free(acc);
+  if (af != accf) free(af);
+}
+
+/* out[m] = b[m] + sum_k q(in[k]) Wq[k][m]; Wq row-major [K][M], already
+ * quantised; the sum runs over k in order */
+static void linear(const double* in, int K, const double* Wq, const double* b, int M,
+                   double* out, int qmode, double s_in, int f32) {
+  double qs[512];
+  double* q = K <= 512 ? qs : (double*)malloc(sizeof(double) * K);
+  for (int k = 0; k < K; ++k) q[k] = qin(qmode, in[k], s_in, f32);
+  dot_rows(q, K, Wq, b, M, out, f32);
+  if (q != qs) free(q);
 }
 
 /* Same for an input made of `nb` consecutive blocks of `bk` features, block b
  * quantised with its own scale s_in[b] (one weight scale for the matrix). */
-static void linear_blocks(const double* in, int nb, int bk, const double* W, const double* b, int M, double* out,
-                          int qmode, const double* s_in, double s_w) {
-  for (int m = 0; m < M; ++m) {
-    double acc = 0.0;
-    for (int k = 0; k < nb * bk; ++k)
-      acc += qv(qmode, in[k], s_in ? s_in[k / bk] : 1.0) * qv(qmode, W[(int64_t)k * M + m], s_w);
-    out[m] = acc + b[m];
-  }
+static void linear_blocks(const double* in, int nb, int bk, const double* Wq, const double* b, int M, double* out,
+                          int qmode, const double* s_in, int f32) {
+  double qs[512];
+  double* q = nb * bk <= 512 ? qs : (double*)malloc(sizeof(double) * nb * bk);
+  for (int k = 0; k < nb * bk; ++k) q[k] = qin(qmode, in[k], s_in ? s_in[k / bk] : 1.0, f32);
+  dot_rows(q, nb * bk, Wq, b, M, out, f32);
+  if (q != qs) free(q);
 }
 
 /* LayerNorm over the feature axis (biased variance, eps 1e-5, no affine), then ReLU */
-static void layernorm_relu(double* v, int n) {
+static void layernorm_relu(double* v, int n, int f32) {
   double mean = 0.0;
-  for (int i = 0; i < n; ++i) mean += v[i];
-  mean /= n;
+  for (int i = 0; i < n; ++i) mean = RF(f32, mean + v[i]);
+  mean = RF(f32, mean / n);
   double var = 0.0;
-  for (int i = 0; i < n; ++i) var += (v[i] - mean) * (v[i] - mean);
-  var /= n;
-  double inv = 1.0 / sqrt(var + 1e-5);
+  for (int i = 0; i < n; ++i) var = RF(f32, var + RF(f32, (v[i] - mean) * (v[i] - mean)));
+  var = RF(f32, var / n);
+  double inv = RF(f32, 1.0 / sqrt(RF(f32, var + 1e-5)));
   for (int i = 0; i < n; ++i) {
-    double t = (v[i] - mean) * inv;
+    double t = RF(f32, RF(f32, v[i] - mean) * inv);
     v[i] = t > 0.0 ? t : 0.0;
   }
 }
@@ -169,36 +217,39 @@ static void layernorm_relu(double* v, int n) {
  * hidden layers use ReLU, the output layer is linear.  With qmode the GEMM
  * operands of layers l >= 1 are quantised: input with act_scale[l] (FP8),
  * weights with their per-layer power-of-two scale; the 3-wide first layer is
- * not.  amax (may be NULL): running max |input| of layer l in amax[l]. */
+ * not.  amax (may be NULL): running max |input| of layer l in amax[l].
+ * f32: FP32 evaluation (see RF). */
 void oracle_embed(int64_t n, const double* cyl, int n_layers, const int* dims, const double* params, double* emb,
-                  int qmode, const double* act_scale, double* amax) {
+                  int qmode, const double* act_scale, double* amax, int f32) {
   int maxw = 0;
   for (int l = 0; l <= n_layers; ++l) if (dims[l] > maxw) maxw = dims[l];
   double* a = (double*)malloc(sizeof(double) * maxw);
   double* b = (double*)malloc(sizeof(double) * maxw);
-  double ws[16];
+  double* wq[16];
+  const double* bias[16];
   {
     const double* p = params;
     for (int l = 0; l < n_layers && l < 16; ++l) {
-      ws[l] = wscale(qmode, p, (int64_t)dims[l] * dims[l + 1]);
-      p += (int64_t)dims[l] * dims[l + 1] + dims[l + 1];
+      int64_t nw = (int64_t)dims[l] * dims[l + 1];
+      wq[l] = qcopy(l == 0 ? 0 : qmode, p, nw, wscale(qmode, p, nw));
+      bias[l] = p + nw;
+      p += nw + dims[l + 1];
     }
   }
   for (int64_t i = 0; i < n; ++i) {
-    for (int k = 0; k < dims[0]; ++k) a[k] = cyl[3 * i + k];
-    const double* p = params;
+    for (int k = 0; k < dims[0]; ++k) a[k] = RF(f32, cyl[3 * i + k]);
     for (int l = 0; l < n_layers; ++l) {
       int K = dims[l], M = dims[l + 1];
       if (l > 0) observe(amax, l, a, K);
       double si = (act_scale && l > 0) ? act_scale[l] : 1.0;
-      linear(a, K, p, p + (int64_t)K * M, M, b, l == 0 ? 0 : qmode, si, ws[l]);
-      p += (int64_t)K * M + M;
+      linear(a, K, wq[l], bias[l], M, b, l == 0 ? 0 : qmode, si, f32);
       if (l + 1 < n_layers)
         for (int m = 0; m < M; ++m) b[m] = b[m] > 0.0 ? b[m] : 0.0;
       memcpy(a, b, sizeof(double) * M);
     }
     for (int m = 0; m < dims[n_layers]; ++m) emb[i * dims[n_layers] + m] = a[m];
   }
+  for (int l = 0; l < n_layers && l < 16; ++l) free(wq[l]);
   free(a);
   free(b);
 }
@@ -319,10 +370,11 @@ enum { Q_NE2 = 0, Q_H = 1, Q_MO = 2, Q_MI = 3, Q_EE2 = 4, Q_NN2 = 5, Q_EN2 = 6, 
  * classifier Block(H->H) and Linear(H->1).  Block(x) = ReLU(LN(x W + b)).
  * qmode 0: plain FP64.  act_scale: [8 + S] slots above (qmode 2, 3).  amax
  * (may be NULL, [8 + S]): running max |x| of every quantised tensor.
- * compact (qmode 1, 2): store h and e in low precision (above). */
+ * compact (qmode 1, 2): store h and e in low precision (above).
+ * f32: FP32 evaluation (see RF). */
 void oracle_gnn(int64_t n, const double* cart, int64_t E, const int32_t* src, const int32_t* dst,
                 int H, int S, const double* params, double* logit, int qmode, const double* act_scale,
-                double* amax, int compact) {
+                double* amax, int compact, int f32) {
   const int qs = qmode && compact;   /* state rounding */
   double* h = (double*)calloc((size_t)n * H + 1, sizeof(double));
   double* e = (double*)calloc((size_t)E * H + 1, sizeof(double));
@@ -331,6 +383,7 @@ void oracle_gnn(int64_t n, const double* cart, int64_t E, const int32_t* src, co
   double* in = (double*)malloc(sizeof(double) * 3 * H);
   double* tmp = (double*)malloc(sizeof(double) * H);
   double* out = (double*)malloc(sizeof(double) * H);
+  double x3[3];
   const double one[3] = {1.0, 1.0, 1.0};
 #define SC(slot) (act_scale ? act_scale[slot] : 1.0)
   const int64_t HH = (int64_t)H * H;
@@ -339,34 +392,39 @@ void oracle_gnn(int64_t n, const double* cart, int64_t E, const int32_t* src, co
   /* node encoder: h0 = Block(Block(x/R, y/R, z/Z)); the 3-wide layer is not quantised */
   {
     const double *W1 = p, *b1 = p + 3 * H, *W2 = b1 + H, *b2 = W2 + HH;
-    double s2 = wscale(qmode, W2, HH);
+    double* W1q = qcopy(0, W1, 3 * H, 1.0);
+    double* W2q = qcopy(qmode, W2, HH, wscale(qmode, W2, HH));
     for (int64_t l = 0; l < n; ++l) {
-      linear(cart + 3 * l, 3, W1, b1, H, tmp, 0, 1.0, 1.0);
-      layernorm_relu(tmp, H);
+      for (int c = 0; c < 3; ++c) x3[c] = RF(f32, cart[3 * l + c]);
+      linear(x3, 3, W1q, b1, H, tmp, 0, 1.0, f32);
+      layernorm_relu(tmp, H, f32);
       observe(amax, Q_NE2, tmp, H);
-      linear(tmp, H, W2, b2, H, h + l * H, qmode, SC(Q_NE2), s2);
-      layernorm_relu(h + l * H, H);
+      linear(tmp, H, W2q, b2, H, h + l * H, qmode, SC(Q_NE2), f32);
+      layernorm_relu(h + l * H, H, f32);
       if (qs) for (int c = 0; c < H; ++c) h[l * H + c] = qv(1, h[l * H + c], 1.0);
     }
+    free(W1q); free(W2q);
     p = b2 + H;
   }
   /* edge encoder: e0_ij = Block(Block([h_i, h_j])) */
   {
     const double *W1 = p, *b1 = p + 2 * HH, *W2 = b1 + H, *b2 = W2 + HH;
-    double s1 = wscale(qmode, W1, 2 * HH), s2 = wscale(qmode, W2, HH);
+    double* W1q = qcopy(qmode, W1, 2 * HH, wscale(qmode, W1, 2 * HH));
+    double* W2q = qcopy(qmode, W2, HH, wscale(qmode, W2, HH));
     double sh[2] = {SC(Q_H), SC(Q_H)};
     for (int64_t l = 0; l < n; ++l) observe(amax, Q_H, h + l * H, H);
     for (int64_t t = 0; t < E; ++t) {
       memcpy(in, h + (int64_t)src[t] * H, sizeof(double) * H);
       memcpy(in + H, h + (int64_t)dst[t] * H, sizeof(double) * H);
-      linear_blocks(in, 2, H, W1, b1, H, tmp, qmode, qmode >= 2 ? sh : NULL, s1);
-      layernorm_relu(tmp, H);
+      linear_blocks(in, 2, H, W1q, b1, H, tmp, qmode, qmode >= 2 ? sh : NULL, f32);
+      layernorm_relu(tmp, H, f32);
       observe(amax, Q_EE2, tmp, H);
-      linear(tmp, H, W2, b2, H, e + t * H, qmode, SC(Q_EE2), s2);
-      layernorm_relu(e + t * H, H);
+      linear(tmp, H, W2q, b2, H, e + t * H, qmode, SC(Q_EE2), f32);
+      layernorm_relu(e + t * H, H, f32);
       observe(amax, Q_E + 0, e + t * H, H);
       if (qs) for (int c = 0; c < H; ++c) e[t * H + c] = qv(qmode, e[t * H + c], SC(Q_E + 0));
     }
+    free(W1q); free(W2q);
     p = b2 + H;
   }
 
@@ -376,13 +434,14 @@ void oracle_gnn(int64_t n, const double* cart, int64_t E, const int32_t* src, co
     memset(mi, 0, sizeof(double) * n * H);
     for (int64_t t = 0; t < E; ++t)
       for (int c = 0; c < H; ++c) {
-        mo[(int64_t)src[t] * H + c] += e[t * H + c];
-        mi[(int64_t)dst[t] * H + c] += e[t * H + c];
+        mo[(int64_t)src[t] * H + c] = RF(f32, mo[(int64_t)src[t] * H + c] + e[t * H + c]);
+        mi[(int64_t)dst[t] * H + c] = RF(f32, mi[(int64_t)dst[t] * H + c] + e[t * H + c]);
       }
     /* node update with residual: h <- h + Block(Block([h, mo, mi])) */
     {
       const double *W1 = p, *b1 = p + 3 * HH, *W2 = b1 + H, *b2 = W2 + HH;
-      double s1 = wscale(qmode, W1, 3 * HH), s2 = wscale(qmode, W2, HH);
+      double* W1q = qcopy(qmode, W1, 3 * HH, wscale(qmode, W1, 3 * HH));
+      double* W2q = qcopy(qmode, W2, HH, wscale(qmode, W2, HH));
       double sb[3] = {SC(Q_H), SC(Q_MO), SC(Q_MI)};
       for (int64_t l = 0; l < n; ++l) {
         memcpy(in, h + l * H, sizeof(double) * H);
@@ -391,34 +450,38 @@ void oracle_gnn(int64_t n, const double* cart, int64_t E, const int32_t* src, co
         observe(amax, Q_H, in, H);
         observe(amax, Q_MO, in + H, H);
         observe(amax, Q_MI, in + 2 * H, H);
-        linear_blocks(in, 3, H, W1, b1, H, tmp, qmode, qmode >= 2 ? sb : (qmode ? one : NULL), s1);
-        layernorm_relu(tmp, H);
+        linear_blocks(in, 3, H, W1q, b1, H, tmp, qmode, qmode >= 2 ? sb : (qmode ? one : NULL), f32);
+        layernorm_relu(tmp, H, f32);
         observe(amax, Q_NN2, tmp, H);
-        linear(tmp, H, W2, b2, H, out, qmode, SC(Q_NN2), s2);
-        layernorm_relu(out, H);
-        for (int c = 0; c < H; ++c) h[l * H + c] = qs ? qv(1, h[l * H + c] + out[c], 1.0) : h[l * H + c] + out[c];
+        linear(tmp, H, W2q, b2, H, out, qmode, SC(Q_NN2), f32);
+        layernorm_relu(out, H, f32);
+        for (int c = 0; c < H; ++c)
+          h[l * H + c] = qs ? qv(1, RF(f32, h[l * H + c] + out[c]), 1.0) : RF(f32, h[l * H + c] + out[c]);
       }
+      free(W1q); free(W2q);
       p = b2 + H;
     }
     /* edge update with residual, using the updated h */
     {
       const double *W1 = p, *b1 = p + 3 * HH, *W2 = b1 + H, *b2 = W2 + HH;
-      double s1 = wscale(qmode, W1, 3 * HH), s2 = wscale(qmode, W2, HH);
+      double* W1q = qcopy(qmode, W1, 3 * HH, wscale(qmode, W1, 3 * HH));
+      double* W2q = qcopy(qmode, W2, HH, wscale(qmode, W2, HH));
       double sb[3] = {SC(Q_E + k), SC(Q_H), SC(Q_H)};
       for (int64_t l = 0; l < n; ++l) observe(amax, Q_H, h + l * H, H);
       for (int64_t t = 0; t < E; ++t) {
         memcpy(in, e + t * H, sizeof(double) * H);
         memcpy(in + H, h + (int64_t)src[t] * H, sizeof(double) * H);
         memcpy(in + 2 * H, h + (int64_t)dst[t] * H, sizeof(double) * H);
-        linear_blocks(in, 3, H, W1, b1, H, tmp, qmode, qmode >= 2 ? sb : (qmode ? one : NULL), s1);
-        layernorm_relu(tmp, H);
+        linear_blocks(in, 3, H, W1q, b1, H, tmp, qmode, qmode >= 2 ? sb : (qmode ? one : NULL), f32);
+        layernorm_relu(tmp, H, f32);
         observe(amax, Q_EN2, tmp, H);
-        linear(tmp, H, W2, b2, H, out, qmode, SC(Q_EN2), s2);
-        layernorm_relu(out, H);
-        for (int c = 0; c < H; ++c) out[c] += e[t * H + c];
+        linear(tmp, H, W2q, b2, H, out, qmode, SC(Q_EN2), f32);
+        layernorm_relu(out, H, f32);
+        for (int c = 0; c < H; ++c) out[c] = RF(f32, out[c] + e[t * H + c]);
         observe(amax, Q_E + k + 1, out, H);
         for (int c = 0; c < H; ++c) e[t * H + c] = qs ? qv(qmode, out[c], SC(Q_E + k + 1)) : out[c];
       }
+      free(W1q); free(W2q);
       p = b2 + H;
     }
   }
@@ -426,14 +489,15 @@ void oracle_gnn(int64_t n, const double* cart, int64_t E, const int32_t* src, co
   /* classifier: Linear(H->1)(Block(H->H)(e)); the input is the stored e_S */
   {
     const double *W1 = p, *b1 = p + HH, *w2 = b1 + H, *b2 = w2 + H;
-    double s1 = wscale(qmode, W1, HH);
+    double* W1q = qcopy(qmode, W1, HH, wscale(qmode, W1, HH));
     for (int64_t t = 0; t < E; ++t) {
-      linear(e + t * H, H, W1, b1, H, tmp, qmode, SC(Q_E + S), s1);
-      layernorm_relu(tmp, H);
+      linear(e + t * H, H, W1q, b1, H, tmp, qmode, SC(Q_E + S), f32);
+      layernorm_relu(tmp, H, f32);
       double acc = 0.0;
-      for (int c = 0; c < H; ++c) acc += tmp[c] * w2[c];
-      logit[t] = acc + b2[0];
+      for (int c = 0; c < H; ++c) acc = RF(f32, acc + tmp[c] * w2[c]);
+      logit[t] = RF(f32, acc + b2[0]);
     }
+    free(W1q);
   }
 #undef SC
   free(h); free(e); free(mo); free(mi); free(in); free(tmp); free(out);
@@ -518,16 +582,17 @@ void oracle_prefilter_forward(int64_t E, const double* f, int P, const double* p
   const double* b3 = W3 + P;
   double* a1 = (double*)malloc(sizeof(double) * P);
   double* a2 = (double*)malloc(sizeof(double) * P);
+  double* W2q = qcopy(qmode, W2, (int64_t)P * P, 1.0);
   for (int64_t t = 0; t < E; ++t) {
-    linear(f + 6 * t, 6, W1, b1, P, a1, 0, 1.0, 1.0);
+    linear(f + 6 * t, 6, W1, b1, P, a1, 0, 1.0, 0);
     for (int c = 0; c < P; ++c) a1[c] = a1[c] > 0 ? a1[c] : 0;
-    linear(a1, P, W2, b2, P, a2, qmode, 1.0, 1.0);
+    linear(a1, P, W2q, b2, P, a2, qmode, 1.0, 0);
     for (int c = 0; c < P; ++c) a2[c] = a2[c] > 0 ? a2[c] : 0;
     double o;
-    linear(a2, P, W3, b3, 1, &o, 0, 1.0, 1.0);
+    linear(a2, P, W3, b3, 1, &o, 0, 1.0, 0);
     logit[t] = o;
   }
-  free(a1); free(a2);
+  free(a1); free(a2); free(W2q);
 }
 
 /* Mean class-weighted binary cross-entropy over E edges and its gradient
@@ -557,15 +622,16 @@ double oracle_prefilter_loss_grad(int64_t E, const double* f, const uint8_t* lab
   double* a2 = (double*)malloc(sizeof(double) * P);
   double* d1 = (double*)malloc(sizeof(double) * P);
   double* d2 = (double*)malloc(sizeof(double) * P);
+  double* W2q = qcopy(qmode, W2, (int64_t)P * P, 1.0);
   double loss = 0.0;
   for (int64_t t = 0; t < E; ++t) {
     const double* in = f + 6 * t;
-    linear(in, 6, W1, b1, P, a1, 0, 1.0, 1.0);
+    linear(in, 6, W1, b1, P, a1, 0, 1.0, 0);
     for (int c = 0; c < P; ++c) a1[c] = a1[c] > 0 ? a1[c] : 0;
-    linear(a1, P, W2, b2, P, a2, qmode, 1.0, 1.0);
+    linear(a1, P, W2q, b2, P, a2, qmode, 1.0, 0);
     for (int c = 0; c < P; ++c) a2[c] = a2[c] > 0 ? a2[c] : 0;
     double z;
-    linear(a2, P, W3, b3, 1, &z, 0, 1.0, 1.0);
+    linear(a2, P, W3, b3, 1, &z, 0, 1.0, 0);
     double y = label[t] ? 1.0 : 0.0;
     double w = label[t] ? pos_w : 1.0;
     /* softplus(v) = log(1 + exp(v)), evaluated stably */
@@ -584,7 +650,7 @@ double oracle_prefilter_loss_grad(int64_t E, const double* f, const uint8_t* lab
     for (int c = 0; c < P; ++c) gb2[c] += d2[c];
     for (int k = 0; k < P; ++k) {
       double s = 0.0;
-      for (int c = 0; c < P; ++c) s += qv(qmode, W2[k * P + c], 1.0) * qv(qmode, d2[c], 1.0);
+      for (int c = 0; c < P; ++c) s += W2q[k * P + c] * qv(qmode, d2[c], 1.0);
       d1[k] = (a1[k] > 0 ? 1.0 : 0.0) * s;
     }
     /* hidden layer 1 */
@@ -592,7 +658,7 @@ double oracle_prefilter_loss_grad(int64_t E, const double* f, const uint8_t* lab
       for (int c = 0; c < P; ++c) gW1[k * P + c] += in[k] * d1[c];
     for (int c = 0; c < P; ++c) gb1[c] += d1[c];
   }
-  free(a1); free(a2); free(d1); free(d2);
+  free(a1); free(a2); free(d1); free(d2); free(W2q);
   return E > 0 ? loss / (double)E : 0.0;
 }
 

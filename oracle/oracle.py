@@ -50,11 +50,11 @@ def lib():
         P = C.c_void_p
         i64, i32, dbl = C.c_int64, C.c_int, C.c_double
         L.oracle_features.argtypes = [i64, P, P, P, dbl, dbl, P, P]
-        L.oracle_embed.argtypes = [i64, P, i32, P, P, P, i32, P, P]
+        L.oracle_embed.argtypes = [i64, P, i32, P, P, P, i32, P, P, i32]
         L.oracle_radius.argtypes = [i64, P, P, i32, dbl, i32, i32, P, P, i64]
         L.oracle_radius.restype = i64
         L.oracle_radius_margins.argtypes = [i64, P, P, i32, dbl, i32, i32, P, P]
-        L.oracle_gnn.argtypes = [i64, P, i64, P, P, i32, i32, P, P, i32, P, P, i32]
+        L.oracle_gnn.argtypes = [i64, P, i64, P, P, i32, i32, P, P, i32, P, P, i32, i32]
         L.oracle_pow2_scale.argtypes = [dbl]
         L.oracle_pow2_scale.restype = dbl
         L.oracle_components.argtypes = [i64, i64, P, P, P, P]
@@ -101,10 +101,12 @@ def _flat(layers) -> np.ndarray:
     return np.concatenate(parts) if parts else np.zeros(0)
 
 
-def embed(cyl: np.ndarray, layers, qmode: int = 0, act_scale=None, amax=None) -> np.ndarray:
+def embed(cyl: np.ndarray, layers, qmode: int = 0, act_scale=None, amax=None, f32: bool = False) -> np.ndarray:
     """Embedding MLP.  qmode 1/2 quantise the GEMM operands of layers >= 1
     (act_scale[l]: scale of layer l's input in FP8); amax (float64 array of
-    len(layers)) receives the running max |input| of each layer."""
+    len(layers)) receives the running max |input| of each layer.  f32: every
+    arithmetic result rounded to FP32 (an FP32 evaluation of the same network,
+    used to size low-precision tolerances; not the oracle)."""
     cyl = _c(cyl, np.float64)
     dims = np.array([layers[0][0].shape[0]] + [W.shape[1] for W, _ in layers], dtype=np.int32)
     n = len(cyl)
@@ -112,7 +114,7 @@ def embed(cyl: np.ndarray, layers, qmode: int = 0, act_scale=None, amax=None) ->
     params = _flat(layers)
     qs = None if act_scale is None else _c(act_scale, np.float64)
     lib().oracle_embed(n, _p(cyl), len(layers), _p(dims), _p(params), _p(out), qmode,
-                       _p(qs) if qs is not None else None, _p(amax) if amax is not None else None)
+                       _p(qs) if qs is not None else None, _p(amax) if amax is not None else None, int(f32))
     return out
 
 
@@ -147,11 +149,11 @@ def gnn_param_blocks(weights) -> list:
 
 
 def gnn(cart, src, dst, weights, H: int, S: int, qmode: int = 0, act_scale=None, amax=None,
-        compact: bool = False) -> np.ndarray:
+        compact: bool = False, f32: bool = False) -> np.ndarray:
     """Interaction-network logits.  act_scale / amax: the 8 + S activation
     slots documented in etx_oracle.c (qmode 2 / observers).  compact (qmode
     1, 2): node and edge encodings stored in low precision between layers
-    instead of full-precision masters."""
+    instead of full-precision masters.  f32: FP32 evaluation (see embed)."""
     cart = _c(cart, np.float64)
     src = _c(src, np.int32); dst = _c(dst, np.int32)
     params = _flat(gnn_param_blocks(weights))
@@ -159,7 +161,8 @@ def gnn(cart, src, dst, weights, H: int, S: int, qmode: int = 0, act_scale=None,
     logit = np.zeros(max(E, 1))
     qs = None if act_scale is None else _c(act_scale, np.float64)
     lib().oracle_gnn(len(cart), _p(cart), E, _p(src), _p(dst), H, S, _p(params), _p(logit), qmode,
-                     _p(qs) if qs is not None else None, _p(amax) if amax is not None else None, int(compact))
+                     _p(qs) if qs is not None else None, _p(amax) if amax is not None else None, int(compact),
+                     int(f32))
     return logit[:E].copy()
 
 
@@ -221,20 +224,23 @@ def int8_scales(amax: np.ndarray) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 def run_event(ev: Dict[str, np.ndarray], w, weights, with_margins: bool = False, qmode: int = 0,
-              scales=None, emb_qmode: Optional[int] = None, compact: bool = False) -> Dict[str, np.ndarray]:
+              scales=None, emb_qmode: Optional[int] = None, compact: bool = False,
+              f32: bool = False) -> Dict[str, np.ndarray]:
     """The full hot path on one event.  ``w`` carries the workload constants
     (r_scale, z_scale, radius, k_max, plane_window, gnn_hidden, gnn_steps,
     threshold); ``weights`` the network parameters.  qmode 1 (BF16), 2 (FP8,
     ``scales`` from ``calibrate``) or 3 (INT8, ``scales`` from ``int8_scales``
     of calibrate's maxima) quantises the GEMM operands; ``emb_qmode``
     gives the embedding its own mode (default: qmode); ``compact`` stores the
-    network's node and edge state in low precision (see ``gnn``)."""
+    network's node and edge state in low precision (see ``gnn``); ``f32``
+    evaluates the embedding and the network in FP32 arithmetic (see ``embed``;
+    a tolerance instrument, not the oracle)."""
     cyl, cart = features(ev["x"], ev["y"], ev["z"], w.r_scale, w.z_scale)
     es, gs = (scales[0], scales[1]) if scales is not None else (None, None)
-    emb = embed(cyl, weights["emb"], qmode if emb_qmode is None else emb_qmode, es)
+    emb = embed(cyl, weights["emb"], qmode if emb_qmode is None else emb_qmode, es, f32=f32)
     r32 = float(np.float32(w.radius))
     src, dst = radius_graph(ev["plane"], emb, r32, w.k_max, w.plane_window)
-    logit = gnn(cart, src, dst, weights, w.gnn_hidden, w.gnn_steps, qmode, gs, compact=compact)
+    logit = gnn(cart, src, dst, weights, w.gnn_hidden, w.gnn_steps, qmode, gs, compact=compact, f32=f32)
     score = sigmoid(logit)
     keep = score >= w.threshold
     labels = components(len(cyl), src, dst, keep)

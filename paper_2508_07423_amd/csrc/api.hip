@@ -69,6 +69,7 @@ WsLayout ws_layout(const etx_ctx* ctx, int64_t n_events, int64_t n_hits, int64_t
   L.pf_grad = take(sizeof(float) * kPfGradStride);
   L.pf_polar = take(sizeof(float) * 2 * n_hits);
   L.pf_feat = take(ctx->pf_features ? sizeof(float) * 8 * edge_cap : 0);
+  L.pf_fallback = take(sizeof(int32_t) * n_events);
   L.total = o;
   return L;
 }
@@ -461,6 +462,7 @@ static hipError_t enqueue_pipeline(const RunArgs& a) {
     // learned prefilter: keep flags on the candidates, then the surviving
     // edges become the graph of the rest of the path
     STEP(7, launch_prefilter_infer(a));
+    STEP(7, launch_prefilter_band(a));
     STEP(7, launch_prefilter_count(a));
     STEP(7, launch_scan_counts(a, false));
     STEP(7, launch_prefilter_compact(a));
@@ -626,6 +628,7 @@ etx_status etx_workspace_view(const etx_ctx* ctx, int64_t n_events, int64_t n_hi
     case ETX_VIEW_PF_KEEP: *offset = L.pf_keep; *bytes = edge_capacity; break;
     case ETX_VIEW_PF_GRAD: *offset = L.pf_grad; *bytes = sizeof(float) * (ETX_PF_NPARAM + 1); break;
     case ETX_VIEW_PF_PROB: *offset = L.pf_prob; *bytes = sizeof(float) * edge_capacity; break;
+    case ETX_VIEW_PF_FALLBACK: *offset = L.pf_fallback; *bytes = sizeof(int32_t) * n_events; break;
     case ETX_VIEW_PF_FEAT:
       if (!ctx->pf_features) return ETX_ERR_INVALID_ARG;
       *offset = L.pf_feat;
@@ -1110,6 +1113,14 @@ etx_status etx_prefilter_config(etx_ctx* ctx, int32_t enabled, float tau) {
   if (!ctx || (enabled != 0 && enabled != 1) || !std::isfinite(tau)) return ETX_ERR_INVALID_ARG;
   ctx->cfg.prefilter = enabled;
   ctx->cfg.prefilter_tau = tau;
+  clear_graphs(ctx);
+  return ETX_OK;
+}
+
+etx_status etx_prefilter_band(etx_ctx* ctx, float lo, float hi) {
+  if (!ctx || !(lo >= 0.f) || !(hi <= 1.f) || !(lo <= hi)) return ETX_ERR_INVALID_ARG;
+  ctx->pf_band_lo = lo;
+  ctx->pf_band_hi = hi;
   clear_graphs(ctx);
   return ETX_OK;
 }

@@ -46,7 +46,7 @@ struct WeightMap {
 // Byte offsets of the workspace buffers.
 struct WsLayout {
   size_t bucket, plane_off, emb, cnt, slots, row_ptr, scan_tmp, col_ptr, csc, h, ps, pd, msg, e, opart, kept, kept_cnt,
-      calib, pf_keep, pf_tmp, cand_src, cand_dst, pf_prob, pf_part, pf_grad, pf_polar, pf_feat, total;
+      calib, pf_keep, pf_tmp, cand_src, cand_dst, pf_prob, pf_part, pf_grad, pf_polar, pf_feat, pf_fallback, total;
   int64_t n_scan_blocks;
 };
 
@@ -71,6 +71,7 @@ struct etx_ctx {
   // prefilter (params, Adam m, v) in FP32 on the device
   float* dev_pf = nullptr;
   bool pf_set = false;
+  float pf_band_lo = 0.f, pf_band_hi = 1.f;   // validated band of an event's kept fraction
   // tuning
   int edge_wg_per_cu = 8;
   int node_wg_per_cu = 1;
@@ -144,6 +145,7 @@ hipError_t launch_node_step(const RunArgs& a, int k);
 hipError_t launch_edge_step(const RunArgs& a, int k, bool final_step);
 // launchers (prefilter.hip)
 hipError_t launch_prefilter_infer(const RunArgs& a);        // candidates -> keep flags -> compacted edges
+hipError_t launch_prefilter_band(const RunArgs& a);           // events outside the band keep every candidate
 hipError_t launch_prefilter_count(const RunArgs& a);
 hipError_t launch_prefilter_compact(const RunArgs& a);
 hipError_t launch_prefilter_train(const RunArgs& a, const uint8_t* labels, float lr, float pos_weight, int64_t step,

@@ -300,6 +300,35 @@ __global__ void k_pf_adam(float* __restrict__ p, float* __restrict__ m, float* _
   p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
+// Fallback to the unpruned graph: an event whose kept fraction of candidates
+// lies outside [lo, hi] (the band validated when tau was chosen) keeps every
+// candidate.  One workgroup per event: a block sum of its keep flags, then, if
+// the event falls back, every flag of its candidate range set.
+__global__ __launch_bounds__(256) void k_pf_band(int64_t n_events, const int64_t* __restrict__ hit_off,
+                                                 const int64_t* __restrict__ cand_ptr, uint8_t* __restrict__ keep,
+                                                 float lo, float hi, int32_t* __restrict__ fallback,
+                                                 const int64_t* status) {
+  if (status[0] != 0) return;
+  __shared__ int part[4];
+  for (int64_t e = blockIdx.x; e < n_events; e += gridDim.x) {
+    const int64_t c0 = cand_ptr[hit_off[e]], c1 = cand_ptr[hit_off[e + 1]];
+    int cnt = 0;
+    for (int64_t q = c0 + threadIdx.x; q < c1; q += blockDim.x) cnt += keep[q];
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) cnt += __shfl_xor(cnt, m);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    const int64_t total = (int64_t)part[0] + part[1] + part[2] + part[3];
+    const int64_t n = c1 - c0;
+    const double frac = n > 0 ? (double)total / (double)n : 1.0;
+    const bool fb = n > 0 && (frac < (double)lo || frac > (double)hi);
+    if (fb)
+      for (int64_t q = c0 + threadIdx.x; q < c1; q += blockDim.x) keep[q] = 1;
+    if (threadIdx.x == 0) fallback[e] = fb ? 1 : 0;
+    __syncthreads();     // part[] is reused by the next event
+  }
+}
+
 // surviving candidates per source, and their compaction into the output edge
 // list; one thread per source (rows hold at most k_max <= 64 candidates)
 template <bool WRITE>
@@ -366,6 +395,16 @@ hipError_t launch_prefilter_infer(const RunArgs& a) {
   launch_polar(a);
   // inference keeps no per-wave partials: a full grid of persistent waves
   hipLaunchKernelGGL(k_pf<false>, dim3((unsigned)(a.ctx->n_cu * 4)), dim3(kPfThreads), 0, a.stream, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_prefilter_band(const RunArgs& a) {
+  if (a.hits.n_events == 0) return hipSuccess;
+  const unsigned grid = (unsigned)std::min<int64_t>(a.hits.n_events, (int64_t)a.ctx->n_cu * 8);
+  hipLaunchKernelGGL(k_pf_band, dim3(grid), dim3(256), 0, a.stream, a.hits.n_events, a.hits.hit_off,
+                     reinterpret_cast<const int64_t*>(a.ws + a.L.pf_tmp), reinterpret_cast<uint8_t*>(a.ws + a.L.pf_keep),
+                     a.ctx->pf_band_lo, a.ctx->pf_band_hi, reinterpret_cast<int32_t*>(a.ws + a.L.pf_fallback),
+                     a.out.status);
   return hipGetLastError();
 }
 

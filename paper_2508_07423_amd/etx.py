@@ -26,7 +26,7 @@ ETX_PF_HIDDEN = 32
 ETX_PF_NPARAM = 6 * 32 + 32 + 32 * 32 + 32 + 32 + 1
 (ETX_VIEW_EMBEDDING, ETX_VIEW_BUCKET, ETX_VIEW_PLANE_OFF, ETX_VIEW_ROW_PTR, ETX_VIEW_COL_PTR, ETX_VIEW_CSC_EDGE,
  ETX_VIEW_NODE_H, ETX_VIEW_KEPT_EDGE, ETX_VIEW_KEPT_COUNT, ETX_VIEW_CALIB, ETX_VIEW_PF_KEEP, ETX_VIEW_PF_GRAD,
- ETX_VIEW_PF_PROB, ETX_VIEW_PF_FEAT) = range(14)
+ ETX_VIEW_PF_PROB, ETX_VIEW_PF_FEAT, ETX_VIEW_PF_FALLBACK) = range(15)
 (ETX_OPT_USE_GRAPH, ETX_OPT_EDGE_WG_PER_CU, ETX_OPT_NODE_WG_PER_CU, ETX_OPT_RADIUS_LDS,
  ETX_OPT_SEGSUM_UNROLL, ETX_OPT_PROFILE, ETX_OPT_EDGE_PIPELINE, ETX_OPT_EDGE_WG_SIZE,
  ETX_OPT_EDGE_WREG, ETX_OPT_EMBED_PRECISION, ETX_OPT_OUTSUM_LDS, ETX_OPT_F32_SPLIT,
@@ -89,6 +89,7 @@ def lib():
             "etx_save": [P, P, C.POINTER(sz)],
             "etx_load": [P, sz, C.c_int, C.POINTER(P)],
             "etx_tuning_save": [P, C.c_char_p],
+            "etx_prefilter_band": [P, C.c_float, C.c_float],
             "etx_tuning_load": [P, C.c_char_p],
         }
         for name, args in sig.items():
@@ -110,7 +111,7 @@ EXPORTED = ["etx_create", "etx_destroy", "etx_weight_blob_size", "etx_workspace_
             "etx_set_precision", "etx_prefilter_set", "etx_prefilter_get", "etx_prefilter_train_step",
             "etx_prefilter_state", "etx_status_str", "etx_last_error", "etx_profile_read", "etx_profile_reset",
             "etx_stage_name", "etx_get_scales", "etx_quantize", "etx_prefilter_config", "etx_save", "etx_load",
-            "etx_tuning_save", "etx_tuning_load"]
+            "etx_tuning_save", "etx_tuning_load", "etx_prefilter_band"]
 
 
 class EtxError(RuntimeError):
@@ -218,6 +219,10 @@ def etx_prefilter_set(ctx, params: np.ndarray) -> None:
 
 def etx_prefilter_config(ctx, enabled: int, tau: float) -> None:
     _check(lib().etx_prefilter_config(ctx, enabled, tau), "etx_prefilter_config")
+
+
+def etx_prefilter_band(ctx, lo: float, hi: float) -> None:
+    _check(lib().etx_prefilter_band(ctx, lo, hi), "etx_prefilter_band")
 
 
 def etx_prefilter_get(ctx) -> np.ndarray:

@@ -66,8 +66,23 @@ def train_prefilter(w, weights: Dict, n_events: int, batch_events: int = 20, epo
     return dict(params=state[:etx.ETX_PF_NPARAM].copy(), state=state, history=history, steps=step)
 
 
+def fallback_band(kept_per_event: np.ndarray, candidates_per_event: np.ndarray, quantile: float = 0.005,
+                  margin: float = 0.8) -> tuple:
+    """Band of an event's kept fraction inside which the prefilter is trusted:
+    from `margin` times the `quantile` of the validation events' kept fractions
+    up to 1 (keeping more candidates than validated costs time, never
+    efficiency).  Events with no candidates do not count."""
+    kept = np.asarray(kept_per_event, np.float64)
+    cand = np.asarray(candidates_per_event, np.float64)
+    frac = kept[cand > 0] / cand[cand > 0]
+    if len(frac) == 0:
+        return 0.0, 1.0
+    return float(margin * np.quantile(frac, quantile)), 1.0
+
+
 def choose_tau(w, weights: Dict, params: np.ndarray, batch: Dict, recall: float = 0.995, device: int = 0) -> Dict:
-    """Threshold keeping `recall` of the positive edges of a validation batch."""
+    """Threshold keeping `recall` of the positive edges of a validation batch,
+    and the fallback band of the per-event kept fraction at that threshold."""
     import torch
     pipe = etx.Pipeline(w, weights, device=device)
     etx.etx_prefilter_set(pipe.ctx, params)
@@ -81,6 +96,11 @@ def choose_tau(w, weights: Dict, params: np.ndarray, batch: Dict, recall: float 
     pos = np.sort(prob[lab])
     tau = float(pos[int(np.floor((1.0 - recall) * len(pos)))]) if len(pos) else 0.0
     kept = float((prob >= tau).mean()) if E else 1.0
+    eo = pipe.edge_off.cpu().numpy()
+    cand_ev = np.diff(eo)
+    cs = np.concatenate([[0], np.cumsum(prob >= tau)])
+    kept_ev = cs[eo[1:]] - cs[eo[:-1]]
+    lo, hi = fallback_band(kept_ev, cand_ev)
     pipe.close()
     return dict(tau=tau, kept_fraction=kept, positive_fraction=float(lab.mean()) if E else 0.0,
-                positive_recall=float((prob[lab] >= tau).mean()) if lab.any() else 1.0)
+                positive_recall=float((prob[lab] >= tau).mean()) if lab.any() else 1.0, band=(lo, hi))

@@ -2,6 +2,7 @@
 import importlib.util
 import os
 
+import numpy as np
 import pytest
 
 _spec = importlib.util.spec_from_file_location("bench", os.path.join(os.path.dirname(__file__), "..", "bench.py"))
@@ -39,3 +40,12 @@ def test_hbm_stage_fractions():
     assert h["a5_edge_encode"]["bytes"] == E * (H * 4 + 8) + N * 3 * H * 4
     for v in h.values():
         assert 0 < v["frac"] < 1
+
+
+def test_prefilter_fallback_band():
+    from paper_2508_07423_amd.prefilter_train import fallback_band
+    kept = np.array([70, 0, 80, 75, 60])
+    cand = np.array([100, 0, 100, 100, 100])       # the empty event does not count
+    lo, hi = fallback_band(kept, cand, quantile=0.0, margin=0.8)
+    assert hi == 1.0 and lo == pytest.approx(0.8 * 0.6)
+    assert fallback_band(np.zeros(3), np.zeros(3)) == (0.0, 1.0)

@@ -53,7 +53,7 @@ def run_gpu(w, weights, batch, **kw):
     return p, b, res
 
 
-def event_parity(w, weights, batch, res, i):
+def event_parity(w, weights, batch, res, i, score_tol=G.SCORE_TOL):
     a, bnd = int(batch["hit_off"][i]), int(batch["hit_off"][i + 1])
     ev = synth.event_slice(batch, i)
     ref = G.oracle_event(ev, w, weights)
@@ -65,7 +65,7 @@ def event_parity(w, weights, batch, res, i):
     assert np.all(np.diff(gsrc) >= 0)
     n_undec, undec = G.check_edges(gsrc, gdst, ref, ev["plane"], w, ref["emb"])
     _, cart = O.features(ev["x"], ev["y"], ev["z"], w.r_scale, w.z_scale)
-    G.check_scores(gsrc, gdst, gscore, cart, weights, w, ref)
+    G.check_scores(gsrc, gdst, gscore, cart, weights, w, ref, tol=score_tol)
     frac = G.check_labels(bnd - a, gsrc, gdst, gscore, res["labels"][a:bnd] - a, ref)
     return ref, n_undec, frac
 

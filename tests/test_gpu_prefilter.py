@@ -239,3 +239,44 @@ def test_pruning_matches_oracle_and_tau_zero_is_the_plain_path(setup):
     rp = p.results(b)
     for k in ("src", "dst", "score", "labels", "edge_off"):
         assert np.array_equal(rz[k], rp[k]), k
+
+
+def test_fallback_band_runs_events_unpruned(setup):
+    """Events whose kept fraction leaves the validated band run unpruned: their
+    edges are the unpruned pipeline's (scores to FP32 rounding: the batch's
+    tile boundaries move), the other events' are the pruned run's; the
+    fallback flags name exactly the events outside the band."""
+    etx, w, W, batch, ev, src, dst, f, labels, layers, flat, p, b = setup
+    bat = synth.generate_batch(w.with_(tracks=("fixed", 40)), 6, seed_space=9200)
+    bb = etx.to_device(bat)
+
+    def run(tau, band=None, prefilter=1):
+        q = etx.Pipeline(w, W, prefilter=prefilter, prefilter_tau=tau)
+        etx.etx_prefilter_set(q.ctx, flat)
+        if band is not None:
+            etx.etx_prefilter_band(q.ctx, *band)
+        q.run(bb)
+        r = q.results(bb)
+        fb = q.view(bb, etx.ETX_VIEW_PF_FALLBACK, torch.int32).cpu().numpy().copy() if prefilter else None
+        q.close()
+        return r, fb
+
+    unpruned, _ = run(0.0, prefilter=0)
+    pruned, fb0 = run(0.5)
+    assert not fb0.any()
+    frac = np.diff(pruned["edge_off"]) / np.maximum(np.diff(unpruned["edge_off"]), 1)
+    s = np.sort(frac)
+    lo = 0.5 * (s[2] + s[3])              # three events below the band, three inside
+    assert s[2] < lo < s[3]
+    got, fb = run(0.5, (float(lo), 1.0))
+    assert np.array_equal(fb.astype(bool), frac < lo)
+    ho = bat["hit_off"]
+    for e in range(6):
+        ref = unpruned if fb[e] else pruned
+        a0, a1 = got["edge_off"][e], got["edge_off"][e + 1]
+        r0, r1 = ref["edge_off"][e], ref["edge_off"][e + 1]
+        assert np.array_equal(got["src"][a0:a1], ref["src"][r0:r1]), e
+        assert np.array_equal(got["dst"][a0:a1], ref["dst"][r0:r1]), e
+        assert np.abs(got["score"][a0:a1].astype(np.float64) - ref["score"][r0:r1]).max(initial=0) <= 1e-5
+    with pytest.raises(etx.EtxError):
+        etx.etx_prefilter_band(p.ctx, 0.6, 0.5)
