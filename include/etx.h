@@ -121,6 +121,22 @@ etx_status etx_workspace_size(const etx_ctx* ctx, int64_t n_events, int64_t n_hi
  * device memory of at least etx_workspace_size bytes, 256-byte aligned. */
 etx_status etx_run(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void* ws, size_t ws_bytes, etx_stream stream);
 
+/* etx_run without allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same stages and kernels as etx_run, with the library's
+ * static device scratch of ETX_SCRATCH_BYTES as the workspace.  The caller
+ * still owns `hits` and `out`.  A batch whose workspace (etx_workspace_size)
+ * exceeds ETX_SCRATCH_BYTES is rejected with ETX_ERR_UNSUPPORTED before
+ * anything is enqueued.  Each device holds one scratch array for the life of
+ * the process, shared by every call on that device: calls that overlap on one
+ * device (other streams, other threads, other contexts) race and must be
+ * ordered by the caller.  The scratch keeps the last call's contents; no stage
+ * relies on it starting zeroed.  Runs eagerly on `stream` (ETX_OPT_USE_GRAPH,
+ * stage timing and the tuning table are not applied: the options in effect
+ * are used), allocates nothing and never synchronises. */
+#define ETX_SCRATCH_BYTES (128u << 20)
+etx_status etx_run_noalloc(etx_ctx* ctx, const etx_hits* hits, etx_out* out, etx_stream stream);
+
 /* Internal buffers of the workspace, for inspection after etx_run. */
 typedef enum {
   ETX_VIEW_EMBEDDING = 0,    /* float [n_hits][16]: embedding, zero-padded to 16 */

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -416,7 +417,7 @@ struct StageTimer {
   hipStream_t s;
   int idx = -1;
   StageTimer(const RunArgs& a, int stage) : ctx(const_cast<etx_ctx*>(a.ctx)), s(a.stream) {
-    if (!ctx->profile || !((ctx->profile_mask >> stage) & 1)) return;
+    if (!ctx->profile || a.untimed || !((ctx->profile_mask >> stage) & 1)) return;
     if (ctx->n_marks == ctx->marks.size()) {
       etx_ctx::Mark m{stage, nullptr, nullptr};
       if (hipEventCreate(&m.start) != hipSuccess) return;
@@ -496,6 +497,36 @@ static etx_status check_run_args(const etx_ctx* ctx, const etx_hits* hits, const
   return ETX_OK;
 }
 
+// Device scratch of the no-allocation entry point: one array per device (each
+// GPU the library runs on holds its own copy until the process ends), used as
+// the workspace of etx_run_noalloc.  Host code never passes `scratch` itself
+// (in host code it names a host-side stand-in); it passes the device address
+// that hipGetSymbolAddress returned for the device, resolved once per device
+// at context creation with that device current.
+static __device__ __align__(256) char scratch[ETX_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static etx_status scratch_init(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) return ETX_ERR_UNSUPPORTED;
+  if (g_scratch_ptr[device]) return ETX_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    note_error("hipGetSymbolAddress(scratch)", e);
+    return ETX_ERR_HIP;
+  }
+  g_scratch_ptr[device] = ptr;
+  return ETX_OK;
+}
+
+static void* scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return (device >= 0 && device < kMaxDevices) ? g_scratch_ptr[device] : nullptr;
+}
+
 }  // namespace etx
 
 using namespace etx;
@@ -549,6 +580,7 @@ etx_status etx_create(const etx_config* cfg, const void* weights, size_t nbytes,
     g_last_error = "hipFuncSetAttribute(MaxDynamicSharedMemorySize) failed";
     return ETX_ERR_HIP;
   }
+  if ((st = scratch_init(device)) != ETX_OK) return st;
   etx_ctx* ctx = new etx_ctx();
   ctx->cfg = *cfg;
   ctx->device = device;
@@ -867,6 +899,33 @@ etx_status etx_run(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void* ws, s
     it = ctx->graphs.emplace(key, ex).first;
   }
   return hipGraphLaunch(it->second, a.stream) == hipSuccess ? ETX_OK : ETX_ERR_HIP;
+}
+
+etx_status etx_run_noalloc(etx_ctx* ctx, const etx_hits* hits, etx_out* out, etx_stream stream) {
+  if (!ctx || !hits || !out) return ETX_ERR_INVALID_ARG;
+  if (hits->n_events < 0 || hits->n_hits < 0 || out->edge_capacity < 0) return ETX_ERR_INVALID_ARG;
+  void* ptr = scratch_ptr(ctx->device);
+  if (!ptr) return ETX_ERR_HIP;
+  if (ws_layout(ctx, hits->n_events, hits->n_hits, out->edge_capacity).total > (size_t)ETX_SCRATCH_BYTES) {
+    g_last_error = "etx_run_noalloc: the batch needs more workspace than the static scratch holds";
+    return ETX_ERR_UNSUPPORTED;
+  }
+  WsLayout L;
+  etx_status st = check_run_args(ctx, hits, out, ptr, (size_t)ETX_SCRATCH_BYTES, &L);
+  if (st != ETX_OK) return st;
+  auto scaled = [](int p) { return p == ETX_FP8_E4M3 || p == ETX_INT8; };
+  if ((scaled(ctx->cfg.precision) || scaled(ctx->emb_precision)) && !ctx->calibrated) return ETX_ERR_INVALID_ARG;
+  if (ctx->cfg.prefilter && !ctx->pf_set) return ETX_ERR_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return ETX_ERR_HIP;
+  RunArgs a{ctx, *hits, *out, L, static_cast<char*>(ptr), static_cast<hipStream_t>(stream), false,
+            kernel_precision(ctx)};
+  a.untimed = true;
+  const hipError_t e = enqueue_pipeline(a);
+  if (e != hipSuccess) {
+    note_error("etx_run_noalloc launch", e);
+    return ETX_ERR_HIP;
+  }
+  return ETX_OK;
 }
 
 etx_status etx_calibrate(etx_ctx* ctx, const etx_hits* hits, etx_out* out, void* ws, size_t ws_bytes,

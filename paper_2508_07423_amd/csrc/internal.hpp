@@ -122,6 +122,7 @@ struct RunArgs {
   hipStream_t stream;
   bool calibrate;                  // record amax observers (FP32 run)
   int prec;                        // kernel precision: etx_precision, or kBf16Master / kFp8Master
+  bool untimed = false;            // no stage timing even when profiling is on (the no-allocation entry point)
 };
 
 // launchers (graph.hip)

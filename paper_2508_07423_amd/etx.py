@@ -90,6 +90,7 @@ def lib():
             "etx_load": [P, sz, C.c_int, C.POINTER(P)],
             "etx_tuning_save": [P, C.c_char_p],
             "etx_prefilter_band": [P, C.c_float, C.c_float],
+            "etx_run_noalloc": [P, C.POINTER(etx_hits), C.POINTER(etx_out), P],
             "etx_tuning_load": [P, C.c_char_p],
         }
         for name, args in sig.items():
@@ -111,7 +112,7 @@ EXPORTED = ["etx_create", "etx_destroy", "etx_weight_blob_size", "etx_workspace_
             "etx_set_precision", "etx_prefilter_set", "etx_prefilter_get", "etx_prefilter_train_step",
             "etx_prefilter_state", "etx_status_str", "etx_last_error", "etx_profile_read", "etx_profile_reset",
             "etx_stage_name", "etx_get_scales", "etx_quantize", "etx_prefilter_config", "etx_save", "etx_load",
-            "etx_tuning_save", "etx_tuning_load", "etx_prefilter_band"]
+            "etx_tuning_save", "etx_tuning_load", "etx_prefilter_band", "etx_run_noalloc"]
 
 
 class EtxError(RuntimeError):
@@ -219,6 +220,13 @@ def etx_prefilter_set(ctx, params: np.ndarray) -> None:
 
 def etx_prefilter_config(ctx, enabled: int, tau: float) -> None:
     _check(lib().etx_prefilter_config(ctx, enabled, tau), "etx_prefilter_config")
+
+
+def etx_run_noalloc(ctx, hits, out, stream) -> None:
+    _check(lib().etx_run_noalloc(ctx, C.byref(hits), C.byref(out), C.c_void_p(stream)), "etx_run_noalloc")
+
+
+ETX_SCRATCH_BYTES = 128 << 20
 
 
 def etx_prefilter_band(ctx, lo: float, hi: float) -> None:
