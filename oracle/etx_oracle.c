@@ -675,3 +675,367 @@ void oracle_adam(int64_t np, double* p, double* m, double* v, const double* g,
     p[i] -= lr * mh / (sqrt(vh) + eps);
   }
 }
+
+/* ------------------------------------------------------------------------ */
+/* training losses and their gradients (embedding and interaction network)   */
+/* ------------------------------------------------------------------------ */
+
+/* Pairwise hinge embedding loss of thesis ch. 8 (eqs. loss1-loss3) over the
+ * given pairs, with the embedding MLP of oracle_embed (FP64, unquantised):
+ *   L = L_fake + w_gen L_gen,
+ *   L_gen  = (1/|T_gen|)  sum over genuine pairs (q, a) of d^2(q, a),
+ *   L_fake = (1/|T_fake|) sum over fake pairs (q, b) of max(0, m - d^2(q, b)).
+ * grad (layout of params) receives dL/dparams by the chain rule through
+ * every layer (thesis ch. 4 "Backpropagation").  Returns L. */
+double oracle_embed_hinge_loss_grad(int64_t n, const double* cyl, int n_layers, const int* dims,
+                                    const double* params, int64_t n_gen, const int32_t* gsrc, const int32_t* gdst,
+                                    int64_t n_fake, const int32_t* fsrc, const int32_t* fdst, double margin,
+                                    double w_gen, double* grad) {
+  int64_t np = 0, tot = 0;
+  for (int l = 0; l < n_layers; ++l) np += (int64_t)dims[l] * dims[l + 1] + dims[l + 1];
+  for (int l = 0; l <= n_layers; ++l) tot += dims[l];
+  const int D = dims[n_layers];
+  memset(grad, 0, sizeof(double) * np);
+  /* forward: the input of every layer and the output, per hit */
+  double* act = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * tot);
+  int64_t* aoff = (int64_t*)malloc(sizeof(int64_t) * (n_layers + 1));
+  aoff[0] = 0;
+  for (int l = 0; l < n_layers; ++l) aoff[l + 1] = aoff[l] + dims[l];
+  for (int64_t i = 0; i < n; ++i) {
+    double* a = act + i * tot;
+    for (int k = 0; k < dims[0]; ++k) a[k] = cyl[3 * i + k];
+    const double* p = params;
+    for (int l = 0; l < n_layers; ++l) {
+      const int K = dims[l], M = dims[l + 1];
+      const double* in = a + aoff[l];
+      double* out = a + aoff[l + 1];
+      for (int m = 0; m < M; ++m) {
+        double s = p[(int64_t)K * M + m];
+        for (int k = 0; k < K; ++k) s += in[k] * p[(int64_t)k * M + m];
+        out[m] = (l + 1 < n_layers && s < 0.0) ? 0.0 : s;
+      }
+      p += (int64_t)K * M + M;
+    }
+  }
+  /* loss and dL/de per hit */
+  double* de = (double*)calloc((size_t)(n > 0 ? n : 1) * D, sizeof(double));
+  double lg = 0.0, lf = 0.0;
+  for (int64_t t = 0; t < n_gen; ++t) {
+    const double* eq = act + (int64_t)gsrc[t] * tot + aoff[n_layers];
+    const double* ea = act + (int64_t)gdst[t] * tot + aoff[n_layers];
+    double d2 = 0.0;
+    for (int k = 0; k < D; ++k) d2 += (eq[k] - ea[k]) * (eq[k] - ea[k]);
+    lg += d2;
+    const double c = w_gen * 2.0 / (double)n_gen;
+    for (int k = 0; k < D; ++k) {
+      de[(int64_t)gsrc[t] * D + k] += c * (eq[k] - ea[k]);
+      de[(int64_t)gdst[t] * D + k] -= c * (eq[k] - ea[k]);
+    }
+  }
+  for (int64_t t = 0; t < n_fake; ++t) {
+    const double* eq = act + (int64_t)fsrc[t] * tot + aoff[n_layers];
+    const double* eb = act + (int64_t)fdst[t] * tot + aoff[n_layers];
+    double d2 = 0.0;
+    for (int k = 0; k < D; ++k) d2 += (eq[k] - eb[k]) * (eq[k] - eb[k]);
+    if (margin - d2 > 0.0) {
+      lf += margin - d2;
+      const double c = -2.0 / (double)n_fake;
+      for (int k = 0; k < D; ++k) {
+        de[(int64_t)fsrc[t] * D + k] += c * (eq[k] - eb[k]);
+        de[(int64_t)fdst[t] * D + k] -= c * (eq[k] - eb[k]);
+      }
+    }
+  }
+  const double loss = (n_fake > 0 ? lf / (double)n_fake : 0.0) + w_gen * (n_gen > 0 ? lg / (double)n_gen : 0.0);
+  /* backward through the layers, hit by hit */
+  int maxw = 0;
+  for (int l = 0; l <= n_layers; ++l) maxw = dims[l] > maxw ? dims[l] : maxw;
+  double* dcur = (double*)malloc(sizeof(double) * maxw);
+  double* dprev = (double*)malloc(sizeof(double) * maxw);
+  int64_t* poff = (int64_t*)malloc(sizeof(int64_t) * (n_layers + 1));
+  poff[0] = 0;
+  for (int l = 0; l < n_layers; ++l) poff[l + 1] = poff[l] + (int64_t)dims[l] * dims[l + 1] + dims[l + 1];
+  for (int64_t i = 0; i < n; ++i) {
+    const double* a = act + i * tot;
+    for (int k = 0; k < D; ++k) dcur[k] = de[i * D + k];
+    for (int l = n_layers - 1; l >= 0; --l) {
+      const int K = dims[l], M = dims[l + 1];
+      const double* in = a + aoff[l];
+      const double* W = params + poff[l];
+      double* gW = grad + poff[l];
+      double* gb = gW + (int64_t)K * M;
+      for (int k = 0; k < K; ++k)
+        for (int m = 0; m < M; ++m) gW[(int64_t)k * M + m] += in[k] * dcur[m];
+      for (int m = 0; m < M; ++m) gb[m] += dcur[m];
+      if (l > 0) {
+        /* the input of layer l is ReLU(z) of layer l - 1: its derivative is 1 where the value is positive */
+        for (int k = 0; k < K; ++k) {
+          double s = 0.0;
+          for (int m = 0; m < M; ++m) s += W[(int64_t)k * M + m] * dcur[m];
+          dprev[k] = in[k] > 0.0 ? s : 0.0;
+        }
+        for (int k = 0; k < K; ++k) dcur[k] = dprev[k];
+      }
+    }
+  }
+  free(act); free(aoff); free(de); free(dcur); free(dprev); free(poff);
+  return loss;
+}
+
+/* One Block(x) = ReLU(LN(x W + b)) over `rows` rows, saving what its
+ * backward needs: the input rows, the normalised values (before the ReLU) and
+ * the reciprocal standard deviations. */
+typedef struct {
+  int K, M;
+  int64_t rows;
+  const double* W;
+  const double* b;
+  double* x;      /* [rows][K] */
+  double* yhat;   /* [rows][M] */
+  double* rstd;   /* [rows] */
+} blk_t;
+
+static void blk_init(blk_t* B, int K, int M, int64_t rows, const double* W) {
+  B->K = K; B->M = M; B->rows = rows; B->W = W; B->b = W + (int64_t)K * M;
+  B->x = (double*)malloc(sizeof(double) * (size_t)(rows > 0 ? rows : 1) * K);
+  B->yhat = (double*)malloc(sizeof(double) * (size_t)(rows > 0 ? rows : 1) * M);
+  B->rstd = (double*)malloc(sizeof(double) * (size_t)(rows > 0 ? rows : 1));
+}
+
+static void blk_free(blk_t* B) { free(B->x); free(B->yhat); free(B->rstd); }
+
+/* forward of row r: B->x[r] must hold the input; writes the ReLU output to y */
+static void blk_fwd(blk_t* B, int64_t r, double* y) {
+  const int K = B->K, M = B->M;
+  const double* x = B->x + r * K;
+  double* yh = B->yhat + r * M;
+  for (int m = 0; m < M; ++m) {
+    double s = B->b[m];
+    for (int k = 0; k < K; ++k) s += x[k] * B->W[(int64_t)k * M + m];
+    yh[m] = s;
+  }
+  double mean = 0.0, var = 0.0;
+  for (int m = 0; m < M; ++m) mean += yh[m];
+  mean /= M;
+  for (int m = 0; m < M; ++m) var += (yh[m] - mean) * (yh[m] - mean);
+  var /= M;
+  const double rs = 1.0 / sqrt(var + 1e-5);
+  B->rstd[r] = rs;
+  for (int m = 0; m < M; ++m) {
+    yh[m] = (yh[m] - mean) * rs;
+    y[m] = yh[m] > 0.0 ? yh[m] : 0.0;
+  }
+}
+
+/* backward of row r: dy (dL/d output) -> gW, gb accumulated, dx written */
+static void blk_bwd(const blk_t* B, int64_t r, const double* dy, double* gW, double* dx) {
+  const int K = B->K, M = B->M;
+  const double* yh = B->yhat + r * M;
+  const double rs = B->rstd[r];
+  double g[256], dz[256];
+  double mg = 0.0, mgy = 0.0;
+  for (int m = 0; m < M; ++m) {
+    g[m] = yh[m] > 0.0 ? dy[m] : 0.0;             /* through the ReLU */
+    mg += g[m];
+    mgy += g[m] * yh[m];
+  }
+  mg /= M;
+  mgy /= M;
+  /* LayerNorm: z -> (z - mean) rstd; dz = rstd (g - mean(g) - yhat mean(g yhat)) */
+  for (int m = 0; m < M; ++m) dz[m] = rs * (g[m] - mg - yh[m] * mgy);
+  const double* x = B->x + r * K;
+  double* gb = gW + (int64_t)K * M;
+  for (int k = 0; k < K; ++k)
+    for (int m = 0; m < M; ++m) gW[(int64_t)k * M + m] += x[k] * dz[m];
+  for (int m = 0; m < M; ++m) gb[m] += dz[m];
+  if (dx)
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+      for (int m = 0; m < M; ++m) s += B->W[(int64_t)k * M + m] * dz[m];
+      dx[k] = s;
+    }
+}
+
+/* Sigmoid focal loss (Lin et al., cited for eq. gnn-loss in thesis ch. 8) of
+ * one edge with logit z and label y: -alpha_t (1 - p_t)^gamma log p_t with
+ * p = sigmoid(z), p_t = p for y = 1 and 1 - p for y = 0, alpha_t = alpha for
+ * y = 1 and 1 - alpha for y = 0.  *dz receives its derivative in z. */
+static double focal(double z, int y, double alpha, double gamma, double* dz) {
+  const double p = 1.0 / (1.0 + exp(-z));
+  /* log p = -softplus(-z), log(1 - p) = -softplus(z), evaluated stably */
+  const double lp = -(z < 0 ? -z + log1p(exp(z)) : log1p(exp(-z)));
+  const double l1p = -(z > 0 ? z + log1p(exp(-z)) : log1p(exp(z)));
+  if (y) {
+    const double w = pow(1.0 - p, gamma);
+    *dz = alpha * w * (gamma * p * lp - (1.0 - p));
+    return -alpha * w * lp;
+  }
+  const double w = pow(p, gamma);
+  *dz = (1.0 - alpha) * w * (p - gamma * (1.0 - p) * l1p);
+  return -(1.0 - alpha) * w * l1p;
+}
+
+/* Mean sigmoid focal loss of the edge classifier (eq. gnn-loss without the
+ * triplet term) over the E edges with labels y, through the interaction
+ * network of oracle_gnn (FP64, unquantised), and its gradient with respect
+ * to every network parameter (layout of params) by reverse-mode chain rule:
+ * the classifier, then the message-passing steps from the last to the first
+ * (the transpose of a gather by source or target is a sum over that node's
+ * edges, and the transpose of the out-/in-sums a gather), then the encoders.
+ * Returns the loss. */
+double oracle_gnn_focal_loss_grad(int64_t n, const double* cart, int64_t E, const int32_t* src,
+                                  const int32_t* dst, int H, int S, const double* params, const uint8_t* label,
+                                  double alpha, double gamma, double* grad) {
+  const int64_t HH = (int64_t)H * H;
+  /* parameter offsets in the layout of oracle_gnn */
+  const int64_t o_ne1 = 0, o_ne2 = o_ne1 + 3 * H + H, o_ee1 = o_ne2 + HH + H, o_ee2 = o_ee1 + 2 * HH + H;
+  const int64_t o_step = o_ee2 + HH + H, step_sz = 2 * (3 * HH + H + HH + H);
+  const int64_t o_cls = o_step + S * step_sz;
+  const int64_t np = o_cls + HH + H + H + 1;
+  memset(grad, 0, sizeof(double) * np);
+  blk_t ne1, ne2, ee1, ee2, cb;
+  blk_t* nn1 = (blk_t*)malloc(sizeof(blk_t) * (S > 0 ? S : 1));
+  blk_t* nn2 = (blk_t*)malloc(sizeof(blk_t) * (S > 0 ? S : 1));
+  blk_t* en1 = (blk_t*)malloc(sizeof(blk_t) * (S > 0 ? S : 1));
+  blk_t* en2 = (blk_t*)malloc(sizeof(blk_t) * (S > 0 ? S : 1));
+  blk_init(&ne1, 3, H, n, params + o_ne1);
+  blk_init(&ne2, H, H, n, params + o_ne2);
+  blk_init(&ee1, 2 * H, H, E, params + o_ee1);
+  blk_init(&ee2, H, H, E, params + o_ee2);
+  for (int k = 0; k < S; ++k) {
+    const int64_t o = o_step + k * step_sz;
+    blk_init(&nn1[k], 3 * H, H, n, params + o);
+    blk_init(&nn2[k], H, H, n, params + o + 3 * HH + H);
+    blk_init(&en1[k], 3 * H, H, E, params + o + 4 * HH + 2 * H);
+    blk_init(&en2[k], H, H, E, params + o + 7 * HH + 3 * H);
+  }
+  blk_init(&cb, H, H, E, params + o_cls);
+  const double* w2 = params + o_cls + HH + H;
+  const double b2 = w2[H];
+  /* node and edge state per step: h[k] (k = 0..S), e[k] (k = 0..S) */
+  double* h = (double*)calloc((size_t)(S + 1) * (n > 0 ? n : 1) * H, sizeof(double));
+  double* e = (double*)calloc((size_t)(S + 1) * (E > 0 ? E : 1) * H, sizeof(double));
+  double* mo = (double*)calloc((size_t)(n > 0 ? n : 1) * H, sizeof(double));
+  double* mi = (double*)calloc((size_t)(n > 0 ? n : 1) * H, sizeof(double));
+  double* c = (double*)malloc(sizeof(double) * (size_t)(E > 0 ? E : 1) * H);
+  double* tmp = (double*)malloc(sizeof(double) * 3 * H);
+#define HK(k, l) (h + ((int64_t)(k) * n + (l)) * H)
+#define EK(k, t) (e + ((int64_t)(k) * E + (t)) * H)
+  /* forward */
+  for (int64_t l = 0; l < n; ++l) {
+    memcpy(ne1.x + l * 3, cart + 3 * l, sizeof(double) * 3);
+    blk_fwd(&ne1, l, ne2.x + l * H);
+    blk_fwd(&ne2, l, HK(0, l));
+  }
+  for (int64_t t = 0; t < E; ++t) {
+    memcpy(ee1.x + t * 2 * H, HK(0, src[t]), sizeof(double) * H);
+    memcpy(ee1.x + t * 2 * H + H, HK(0, dst[t]), sizeof(double) * H);
+    blk_fwd(&ee1, t, ee2.x + t * H);
+    blk_fwd(&ee2, t, EK(0, t));
+  }
+  for (int k = 0; k < S; ++k) {
+    memset(mo, 0, sizeof(double) * n * H);
+    memset(mi, 0, sizeof(double) * n * H);
+    for (int64_t t = 0; t < E; ++t)
+      for (int q = 0; q < H; ++q) {
+        mo[(int64_t)src[t] * H + q] += EK(k, t)[q];
+        mi[(int64_t)dst[t] * H + q] += EK(k, t)[q];
+      }
+    for (int64_t l = 0; l < n; ++l) {
+      double* x = nn1[k].x + l * 3 * H;
+      memcpy(x, HK(k, l), sizeof(double) * H);
+      memcpy(x + H, mo + l * H, sizeof(double) * H);
+      memcpy(x + 2 * H, mi + l * H, sizeof(double) * H);
+      blk_fwd(&nn1[k], l, nn2[k].x + l * H);
+      blk_fwd(&nn2[k], l, tmp);
+      for (int q = 0; q < H; ++q) HK(k + 1, l)[q] = HK(k, l)[q] + tmp[q];
+    }
+    for (int64_t t = 0; t < E; ++t) {
+      double* x = en1[k].x + t * 3 * H;
+      memcpy(x, EK(k, t), sizeof(double) * H);
+      memcpy(x + H, HK(k + 1, src[t]), sizeof(double) * H);
+      memcpy(x + 2 * H, HK(k + 1, dst[t]), sizeof(double) * H);
+      blk_fwd(&en1[k], t, en2[k].x + t * H);
+      blk_fwd(&en2[k], t, tmp);
+      for (int q = 0; q < H; ++q) EK(k + 1, t)[q] = EK(k, t)[q] + tmp[q];
+    }
+  }
+  double loss = 0.0;
+  double* dlog = (double*)malloc(sizeof(double) * (size_t)(E > 0 ? E : 1));
+  for (int64_t t = 0; t < E; ++t) {
+    memcpy(cb.x + t * H, EK(S, t), sizeof(double) * H);
+    blk_fwd(&cb, t, c + t * H);
+    double z = b2;
+    for (int q = 0; q < H; ++q) z += c[t * H + q] * w2[q];
+    double dz;
+    loss += focal(z, label[t] != 0, alpha, gamma, &dz);
+    dlog[t] = dz / (double)E;
+  }
+  loss = E > 0 ? loss / (double)E : 0.0;
+  /* backward */
+  double* de = (double*)calloc((size_t)(E > 0 ? E : 1) * H, sizeof(double));
+  double* dh = (double*)calloc((size_t)(n > 0 ? n : 1) * H, sizeof(double));
+  double* dx = (double*)malloc(sizeof(double) * 3 * H);
+  double* dy = (double*)malloc(sizeof(double) * H);
+  double* gw2 = grad + o_cls + HH + H;
+  for (int64_t t = 0; t < E; ++t) {
+    for (int q = 0; q < H; ++q) {
+      gw2[q] += c[t * H + q] * dlog[t];
+      dy[q] = w2[q] * dlog[t];
+    }
+    gw2[H] += dlog[t];
+    blk_bwd(&cb, t, dy, grad + o_cls, de + t * H);
+  }
+  double* dmo = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * H);
+  double* dmi = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * H);
+  for (int k = S - 1; k >= 0; --k) {
+    const int64_t o = o_step + k * step_sz;
+    /* edge update k: e_{k+1} = e_k + Block2(Block1([e_k, h_{k+1}[src], h_{k+1}[dst]])) */
+    for (int64_t t = 0; t < E; ++t) {
+      blk_bwd(&en2[k], t, de + t * H, grad + o + 7 * HH + 3 * H, dy);
+      blk_bwd(&en1[k], t, dy, grad + o + 4 * HH + 2 * H, dx);
+      for (int q = 0; q < H; ++q) {
+        de[t * H + q] += dx[q];                      /* residual: de_k = de_{k+1} + the e block of dx */
+        dh[(int64_t)src[t] * H + q] += dx[H + q];
+        dh[(int64_t)dst[t] * H + q] += dx[2 * H + q];
+      }
+    }
+    /* node update k: h_{k+1} = h_k + Block2(Block1([h_k, mo_k, mi_k])) */
+    for (int64_t l = 0; l < n; ++l) {
+      blk_bwd(&nn2[k], l, dh + l * H, grad + o + 3 * HH + H, dy);
+      blk_bwd(&nn1[k], l, dy, grad + o, dx);
+      for (int q = 0; q < H; ++q) {
+        dh[l * H + q] += dx[q];
+        dmo[l * H + q] = dx[H + q];
+        dmi[l * H + q] = dx[2 * H + q];
+      }
+    }
+    /* the out-sum of a node is the sum of its outgoing edges' e_k, the in-sum of its incoming ones */
+    for (int64_t t = 0; t < E; ++t)
+      for (int q = 0; q < H; ++q) de[t * H + q] += dmo[(int64_t)src[t] * H + q] + dmi[(int64_t)dst[t] * H + q];
+  }
+  /* edge encoder: e_0 = Block2(Block1([h_0[src], h_0[dst]])) */
+  for (int64_t t = 0; t < E; ++t) {
+    blk_bwd(&ee2, t, de + t * H, grad + o_ee2, dy);
+    blk_bwd(&ee1, t, dy, grad + o_ee1, dx);
+    for (int q = 0; q < H; ++q) {
+      dh[(int64_t)src[t] * H + q] += dx[q];
+      dh[(int64_t)dst[t] * H + q] += dx[H + q];
+    }
+  }
+  /* node encoder: h_0 = Block2(Block1(x / R, y / R, z / Z)) */
+  for (int64_t l = 0; l < n; ++l) {
+    blk_bwd(&ne2, l, dh + l * H, grad + o_ne2, dy);
+    blk_bwd(&ne1, l, dy, grad + o_ne1, NULL);
+  }
+#undef HK
+#undef EK
+  blk_free(&ne1); blk_free(&ne2); blk_free(&ee1); blk_free(&ee2); blk_free(&cb);
+  for (int k = 0; k < S; ++k) {
+    blk_free(&nn1[k]); blk_free(&nn2[k]); blk_free(&en1[k]); blk_free(&en2[k]);
+  }
+  free(nn1); free(nn2); free(en1); free(en2);
+  free(h); free(e); free(mo); free(mi); free(c); free(tmp); free(dlog); free(de); free(dh); free(dx); free(dy);
+  free(dmo); free(dmi);
+  return loss;
+}

@@ -69,6 +69,10 @@ def lib():
         L.oracle_prefilter_loss_grad.argtypes = [i64, P, P, i32, P, dbl, P, i32]
         L.oracle_prefilter_loss_grad.restype = dbl
         L.oracle_adam.argtypes = [i64, P, P, P, P, dbl, dbl, dbl, dbl, i64]
+        L.oracle_embed_hinge_loss_grad.argtypes = [i64, P, i32, P, P, i64, P, P, i64, P, P, dbl, dbl, P]
+        L.oracle_embed_hinge_loss_grad.restype = dbl
+        L.oracle_gnn_focal_loss_grad.argtypes = [i64, P, i64, P, P, i32, i32, P, P, dbl, dbl, P]
+        L.oracle_gnn_focal_loss_grad.restype = dbl
         _lib = L
     return _lib
 
@@ -308,6 +312,41 @@ def adam(p, m, v, g, lr, b1=0.9, b2=0.999, eps=1e-8, t=1):
         assert a.dtype == np.float64 and a.flags.c_contiguous
     g = _c(g, np.float64)
     lib().oracle_adam(len(p), _p(p), _p(m), _p(v), _p(g), float(lr), float(b1), float(b2), float(eps), int(t))
+
+
+# ---------------------------------------------------------------------------
+# training losses and gradients (embedding and interaction network)
+# ---------------------------------------------------------------------------
+
+def embed_hinge_loss_grad(cyl, layers, gen_pairs, fake_pairs, margin: float, w_gen: float):
+    """Pairwise hinge embedding loss (thesis ch. 8, eqs. loss1-loss3) over the
+    genuine and fake pairs ((src, dst) arrays) and its gradient in the layout
+    of the embedding parameters (W row-major [fan_in][fan_out], then b, per
+    layer)."""
+    cyl = _c(cyl, np.float64)
+    dims = np.array([layers[0][0].shape[0]] + [W.shape[1] for W, _ in layers], dtype=np.int32)
+    params = _flat(layers)
+    g = np.zeros_like(params)
+    gs, gd = _c(gen_pairs[0], np.int32), _c(gen_pairs[1], np.int32)
+    fs, fd = _c(fake_pairs[0], np.int32), _c(fake_pairs[1], np.int32)
+    loss = lib().oracle_embed_hinge_loss_grad(len(cyl), _p(cyl), len(layers), _p(dims), _p(params), len(gs), _p(gs),
+                                              _p(gd), len(fs), _p(fs), _p(fd), float(margin), float(w_gen), _p(g))
+    return loss, g
+
+
+def gnn_focal_loss_grad(cart, src, dst, weights, H: int, S: int, labels, alpha: float = 0.25,
+                        gamma: float = 2.0):
+    """Mean sigmoid focal loss of the edge scores (thesis ch. 8, eq. gnn-loss
+    without the triplet term) and its gradient in the layout of
+    ``gnn_param_blocks`` (flattened)."""
+    cart = _c(cart, np.float64)
+    src = _c(src, np.int32); dst = _c(dst, np.int32)
+    lab = _c(labels, np.uint8)
+    params = _flat(gnn_param_blocks(weights))
+    g = np.zeros_like(params)
+    loss = lib().oracle_gnn_focal_loss_grad(len(cart), _p(cart), len(src), _p(src), _p(dst), H, S, _p(params),
+                                            _p(lab), float(alpha), float(gamma), _p(g))
+    return loss, g
 
 
 if __name__ == "__main__":
