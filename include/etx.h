@@ -302,6 +302,58 @@ etx_status etx_prefilter_band(etx_ctx* ctx, float lo, float hi);
 /* Optimiser state for checkpointing: params, Adam m, Adam v (3 * ETX_PF_NPARAM floats). */
 etx_status etx_prefilter_state(etx_ctx* ctx, float* host_state, int64_t n, int32_t set);
 
+/* In-library training of the embedding MLP and the interaction network
+ * (thesis ch. 8 "Hit Embedding and Rough Graph Construction", eqs. loss1-loss3,
+ * and "Graph Neural Network and Classifiers", eq. gnn-loss without the triplet
+ * term).  The context keeps FP32 master copies of every parameter of the
+ * weight blob with their Adam moments (beta1 0.9, beta2 0.999, eps 1e-8);
+ * forward and backward run in FP32 on the device, the weight gradients are
+ * summed over rows in a fixed order (reproducible to the bit).
+ *
+ * Generator truth of a batch, device pointers, caller-owned: */
+typedef struct {
+  const int32_t* particle;   /* [n_hits] particle of each hit, -1 for noise */
+  const int32_t* succ;       /* [n_hits] the next hit of the same particle along the beam (global index), -1: none */
+  const int32_t* pred;       /* [n_hits] the previous hit, -1: none (pred[succ[i]] == i) */
+  const uint8_t* query;      /* [n_hits] 1: the hit's particle has hits on at least three planes (a training query) */
+  const int32_t* rnd;        /* [n_hits] one random hit of a particle on the next two planes per query, -1: none */
+  const int64_t* rnd_ptr;    /* [n_hits + 1] the random pairs grouped by their second hit: */
+  const int32_t* rnd_src;    /*   rnd_src[rnd_ptr[b] .. rnd_ptr[b+1]-1] are the queries q with rnd[q] == b, ascending */
+} etx_truth;
+/* Copy the context's current weights into the training parameters and clear the moments (allocates them once). */
+etx_status etx_train_begin(etx_ctx* ctx);
+/* Host copy of the training state (set = 0) or its replacement (set = 1): the first n floats of
+ * [params (blob payload order), Adam m, Adam v], n <= 3 x the payload's float count. */
+etx_status etx_train_params(etx_ctx* ctx, float* host, int64_t n, int32_t set);
+/* Rebuild the context's inference weights from the training parameters (every precision's segments and the
+ * weight scales; FP8 / INT8 activation scales must be calibrated again). */
+etx_status etx_train_apply(etx_ctx* ctx);
+/* Workspace bytes of a training step (the etx_run workspace plus the saved activations and gradients). */
+etx_status etx_train_workspace_size(const etx_ctx* ctx, int64_t n_events, int64_t n_hits, int64_t edge_capacity,
+                                    size_t* bytes);
+/* Training buffers of the workspace: 0 = float gradient in blob payload order, 1 = float[4] loss (slot 0),
+ * 2 = uint8 [edge_capacity] edge labels of the last network step. */
+etx_status etx_train_view(const etx_ctx* ctx, int64_t n_events, int64_t n_hits, int64_t edge_capacity, int32_t which,
+                          size_t* offset, size_t* bytes);
+/* One embedding step: the embedding of the training parameters, its radius graph at r_train (at most k_max
+ * targets per hit: the hard negatives), the training set of thesis ch. 8 (genuine pairs (q, succ[q]); fake
+ * pairs: hard negatives of particles other than succ[q], and the random pair), the loss
+ * L_fake + w_gen L_gen with L_gen the mean squared distance of the genuine pairs and L_fake the mean
+ * max(0, margin - d^2) of the fake ones, its gradient, and an Adam step with learning rate lr (lr = 0: the
+ * gradient only) on the embedding parameters.  *loss_dev (device float, may be NULL) receives the loss.
+ * The graph is left in out->src/dst (CSR of the training radius). */
+etx_status etx_train_embed_step(etx_ctx* ctx, const etx_hits* hits, etx_out* out, const etx_truth* truth,
+                                float margin, float w_gen, float r_train, float lr, int64_t step, float* loss_dev,
+                                void* ws, size_t ws_bytes, etx_stream stream);
+/* One network step on the rough graph of the context's inference embedding (radius, k_max): an edge is
+ * genuine when its target is succ[source]; mean sigmoid focal loss (alpha, gamma) of the edge scores, its
+ * gradient through the classifier, the message-passing steps and the encoders, and an Adam step (lr = 0: the
+ * gradient only) on the network parameters.  Synchronises the stream once (the edge count sizes the step);
+ * a device error of the graph building is returned. */
+etx_status etx_train_gnn_step(etx_ctx* ctx, const etx_hits* hits, etx_out* out, const etx_truth* truth, float alpha,
+                              float gamma, float lr, int64_t step, float* loss_dev, void* ws, size_t ws_bytes,
+                              etx_stream stream);
+
 /* Checkpoint of a context: configuration, weight blob, per-tensor scales and
  * calibration flag, prefilter parameters with their Adam moments, and the
  * launch options (the state that training, calibration and tuning build up).

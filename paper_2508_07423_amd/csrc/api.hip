@@ -21,6 +21,7 @@ int gnn_attributes(size_t max_lds);
 int graph_attributes(size_t max_lds);
 int radius_attributes(size_t max_lds);
 int prefilter_attributes(size_t max_lds);
+int train_attributes(size_t max_lds);
 
 bool GraphKey::operator<(const GraphKey& o) const {
   for (int i = 0; i < 16; ++i)
@@ -401,7 +402,7 @@ int set_kernel_attributes() {
   // below the 160 KiB per workgroup so that static LDS still fits beside it
   size_t max_lds = 150 * 1024;
   done = embed_attributes(max_lds) | gnn_attributes(max_lds) | graph_attributes(max_lds) |
-         radius_attributes(max_lds) | prefilter_attributes(max_lds);
+         radius_attributes(max_lds) | prefilter_attributes(max_lds) | train_attributes(max_lds);
   return done;
 }
 
@@ -527,6 +528,39 @@ static void* scratch_ptr(int device) {
   return (device >= 0 && device < kMaxDevices) ? g_scratch_ptr[device] : nullptr;
 }
 
+size_t blob_floats_of(const etx_config& c) { return blob_floats(c); }
+
+etx_status check_run(const etx_ctx* ctx, const etx_hits* hits, const etx_out* out, void* ws, size_t ws_bytes,
+                     WsLayout* L) {
+  return check_run_args(ctx, hits, out, ws, ws_bytes, L);
+}
+
+// Replace the context's weights by a new payload (the blob's floats after its
+// header): every segment set and the weight scales are rebuilt, calibrated
+// activation scales are dropped (they belong to the old weights).
+etx_status rebuild_weights(etx_ctx* ctx, const float* payload) {
+  std::vector<char> blob = ctx->blob;
+  std::memcpy(blob.data() + 32, payload, sizeof(float) * blob_floats(ctx->cfg));
+  std::vector<float> pl;
+  std::vector<BlobLayer> layers;
+  if (!parse_blob(ctx->cfg, blob.data(), blob.size(), pl, layers)) return ETX_ERR_WEIGHTS;
+  clear_graphs(ctx);
+  for (int p = 0; p < kNumSegs; ++p)
+    if (ctx->seg_base[p]) {
+      (void)hipFree(ctx->seg_base[p]);
+      ctx->seg_base[p] = nullptr;
+    }
+  weight_scales(ctx, layers);
+  etx_status st = ETX_OK;
+  for (int p = 0; p < kNumSegs && st == ETX_OK; ++p) st = build_segments(ctx, layers, p);
+  if (st != ETX_OK) return st;
+  if (hipMemcpy(ctx->dev_scales, ctx->host_scales, sizeof(float) * N_SCALES, hipMemcpyHostToDevice) != hipSuccess)
+    return ETX_ERR_HIP;
+  ctx->blob = blob;
+  ctx->calibrated = false;
+  return ETX_OK;
+}
+
 }  // namespace etx
 
 using namespace etx;
@@ -630,6 +664,7 @@ etx_status etx_destroy(etx_ctx* ctx) {
     if (ctx->seg_base[p]) (void)hipFree(ctx->seg_base[p]);
   if (ctx->dev_scales) (void)hipFree(ctx->dev_scales);
   if (ctx->dev_pf) (void)hipFree(ctx->dev_pf);
+  if (ctx->dev_train) (void)hipFree(ctx->dev_train);
   delete ctx;
   return ETX_OK;
 }

@@ -70,6 +70,8 @@ struct etx_ctx {
   bool calibrated = false;
   // prefilter (params, Adam m, v) in FP32 on the device
   float* dev_pf = nullptr;
+  // in-library training: the weight blob's parameters, Adam m, v (FP32, device; etx_train_begin)
+  float* dev_train = nullptr;
   bool pf_set = false;
   float pf_band_lo = 0.f, pf_band_hi = 1.f;   // validated band of an event's kept fraction
   // tuning
@@ -123,6 +125,7 @@ struct RunArgs {
   bool calibrate;                  // record amax observers (FP32 run)
   int prec;                        // kernel precision: etx_precision, or kBf16Master / kFp8Master
   bool untimed = false;            // no stage timing even when profiling is on (the no-allocation entry point)
+  float radius_override = 0.f;     // > 0: the radius graph at this radius instead of the configuration's (training)
 };
 
 // launchers (graph.hip)

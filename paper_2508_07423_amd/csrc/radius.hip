@@ -603,8 +603,8 @@ hipError_t launch_radius(const RunArgs& a, int mode, bool candidates) {
   A.window = c.plane_window;
   A.k_max = c.k_max;
   A.dim = c.emb_dim;
-  A.r = c.radius;
-  A.r2 = c.radius * c.radius;
+  A.r = a.radius_override > 0.f ? a.radius_override : c.radius;
+  A.r2 = A.r * A.r;
   A.cnt = reinterpret_cast<int32_t*>(a.ws + a.L.cnt);
   // with the prefilter the candidate graph goes to workspace buffers first
   A.row_ptr = reinterpret_cast<const int64_t*>(a.ws + (candidates ? a.L.pf_tmp : a.L.row_ptr));

@@ -54,6 +54,11 @@ class etx_out(C.Structure):
                 ("edge_off", C.c_void_p), ("labels", C.c_void_p), ("status", C.c_void_p)]
 
 
+class etx_truth(C.Structure):
+    _fields_ = [("particle", C.c_void_p), ("succ", C.c_void_p), ("pred", C.c_void_p), ("query", C.c_void_p),
+                ("rnd", C.c_void_p), ("rnd_ptr", C.c_void_p), ("rnd_src", C.c_void_p)]
+
+
 _lib = None
 
 
@@ -91,6 +96,15 @@ def lib():
             "etx_tuning_save": [P, C.c_char_p],
             "etx_prefilter_band": [P, C.c_float, C.c_float],
             "etx_run_noalloc": [P, C.POINTER(etx_hits), C.POINTER(etx_out), P],
+            "etx_train_begin": [P],
+            "etx_train_params": [P, P, i64, i32],
+            "etx_train_apply": [P],
+            "etx_train_workspace_size": [P, i64, i64, i64, C.POINTER(sz)],
+            "etx_train_view": [P, i64, i64, i64, i32, C.POINTER(sz), C.POINTER(sz)],
+            "etx_train_embed_step": [P, C.POINTER(etx_hits), C.POINTER(etx_out), C.POINTER(etx_truth), C.c_float,
+                                     C.c_float, C.c_float, C.c_float, i64, P, P, sz, P],
+            "etx_train_gnn_step": [P, C.POINTER(etx_hits), C.POINTER(etx_out), C.POINTER(etx_truth), C.c_float,
+                                   C.c_float, C.c_float, i64, P, P, sz, P],
             "etx_tuning_load": [P, C.c_char_p],
         }
         for name, args in sig.items():
@@ -112,7 +126,9 @@ EXPORTED = ["etx_create", "etx_destroy", "etx_weight_blob_size", "etx_workspace_
             "etx_set_precision", "etx_prefilter_set", "etx_prefilter_get", "etx_prefilter_train_step",
             "etx_prefilter_state", "etx_status_str", "etx_last_error", "etx_profile_read", "etx_profile_reset",
             "etx_stage_name", "etx_get_scales", "etx_quantize", "etx_prefilter_config", "etx_save", "etx_load",
-            "etx_tuning_save", "etx_tuning_load", "etx_prefilter_band", "etx_run_noalloc"]
+            "etx_tuning_save", "etx_tuning_load", "etx_prefilter_band", "etx_run_noalloc",
+            "etx_train_begin", "etx_train_params", "etx_train_apply", "etx_train_workspace_size", "etx_train_view",
+            "etx_train_embed_step", "etx_train_gnn_step"]
 
 
 class EtxError(RuntimeError):
@@ -227,6 +243,40 @@ def etx_run_noalloc(ctx, hits, out, stream) -> None:
 
 
 ETX_SCRATCH_BYTES = 128 << 20
+
+
+def etx_train_begin(ctx) -> None:
+    _check(lib().etx_train_begin(ctx), "etx_train_begin")
+
+
+def etx_train_params(ctx, host: Optional[np.ndarray] = None, n: Optional[int] = None) -> np.ndarray:
+    """The training state (params, Adam m, Adam v in blob payload order): read the
+    first n floats, or replace them with ``host``."""
+    if host is not None:
+        h = np.ascontiguousarray(host, np.float32)
+        _check(lib().etx_train_params(ctx, h.ctypes.data_as(C.c_void_p), h.size, 1), "etx_train_params")
+        return h
+    out = np.zeros(int(n), np.float32)
+    _check(lib().etx_train_params(ctx, out.ctypes.data_as(C.c_void_p), out.size, 0), "etx_train_params")
+    return out
+
+
+def etx_train_apply(ctx) -> None:
+    _check(lib().etx_train_apply(ctx), "etx_train_apply")
+
+
+def etx_train_workspace_size(ctx, n_events: int, n_hits: int, edge_capacity: int) -> int:
+    b = C.c_size_t()
+    _check(lib().etx_train_workspace_size(ctx, n_events, n_hits, edge_capacity, C.byref(b)),
+           "etx_train_workspace_size")
+    return b.value
+
+
+def etx_train_view(ctx, n_events: int, n_hits: int, edge_capacity: int, which: int):
+    off, nb = C.c_size_t(), C.c_size_t()
+    _check(lib().etx_train_view(ctx, n_events, n_hits, edge_capacity, which, C.byref(off), C.byref(nb)),
+           "etx_train_view")
+    return off.value, nb.value
 
 
 def etx_prefilter_band(ctx, lo: float, hi: float) -> None:
