@@ -231,7 +231,7 @@ def xavier_prefilter(seed: int = 7, hidden: int = 32) -> List[Tuple[np.ndarray, 
 
 
 def load_weights(path: str) -> Dict[str, List[Tuple[np.ndarray, np.ndarray]]]:
-    """Weights written by train_weights.save (npz, no pickled objects)."""
+    """Weights written by train.save (npz, no pickled objects)."""
     z = np.load(path, allow_pickle=False)
     out: Dict[str, List[Tuple[np.ndarray, np.ndarray]]] = {}
     keys = sorted({k.rsplit(".", 2)[0] for k in z.files})
@@ -245,6 +245,7 @@ TRAINED_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights"
 
 
 def trained_weights(w: Workload) -> Dict[str, List[Tuple[np.ndarray, np.ndarray]]]:
-    """The committed trained weight set of a workload's network (train_weights.py)."""
+    """The committed trained weight set of a workload's network, trained on the GPU by the library
+    (``python -m paper_2508_07423_amd.train --workload <name> --out <file>``)."""
     name = {"c1": "c3", "c3": "c3", "c5": "c3", "c2": "c2", "c4": "c2"}[w.name]
     return load_weights(os.path.join(TRAINED_DIR, f"{name}_trained.npz"))

@@ -2,7 +2,7 @@
 the precision cost of BF16 and FP8 operands, and what the learned prefilter
 gains over the unpruned pipeline (which stays its fallback and reference).
 
-The weights come from paper_2508_07423_amd/train_weights.py (generator events
+The weights come from the library's own training (paper_2508_07423_amd/train.py, generator events
 of a disjoint seed space); with random weights the network keeps all or no
 edges and efficiency says nothing.
 """
