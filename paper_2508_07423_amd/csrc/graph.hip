@@ -322,21 +322,56 @@ __global__ __launch_bounds__(256) void k_csc(const int64_t* __restrict__ hit_off
 // score cut + compaction (wave ballot + block prefix scan), per event
 // --------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_compact(const int64_t* __restrict__ hit_off, const int64_t* __restrict__ row_ptr,
-                                                 const float* __restrict__ score, float thr, int32_t* __restrict__ kept,
-                                                 int32_t* __restrict__ kept_cnt, const int64_t* status) {
+// One 1024-thread workgroup per event; every wave takes 256 consecutive scores
+// per round (four ballots of 64), so a round covers 4096 edges with one
+// barrier: the wave totals go to LDS (two slots, alternating between rounds,
+// so that no wave overwrites a slot another wave still reads), each wave adds
+// the totals of the waves before it, and every kept edge is written at its
+// rank.  The kept list is in edge order.
+constexpr int kCompactThreads = 1024;
+constexpr int kCompactWaves = kCompactThreads / 64;
+constexpr int kCompactBallots = 4;                   // 64-score ballots per wave per round
+
+__global__ __launch_bounds__(kCompactThreads) void k_compact(const int64_t* __restrict__ hit_off,
+                                                             const int64_t* __restrict__ row_ptr,
+                                                             const float* __restrict__ score, float thr,
+                                                             int32_t* __restrict__ kept,
+                                                             int32_t* __restrict__ kept_cnt, const int64_t* status) {
   if (status[0] != 0) return;
-  __shared__ int tmp[4];
+  __shared__ int tot[2][kCompactWaves];
   const int ev = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t eb = row_ptr[hit_off[ev]], ee = row_ptr[hit_off[ev + 1]];
+  const uint64_t below = (uint64_t(1) << lane) - 1;    // lanes before this one
   int64_t cnt = 0;
-  for (int64_t q0 = eb; q0 < ee; q0 += 256) {
-    int64_t q = q0 + threadIdx.x;
-    int keep = (q < ee && score[q] >= thr) ? 1 : 0;
-    int total;
-    int ex = block_exclusive_scan(keep, tmp, total);
-    if (keep) kept[eb + cnt + ex] = (int32_t)q;
+  int slot = 0;
+  for (int64_t q0 = eb; q0 < ee; q0 += kCompactBallots * kCompactThreads) {
+    const int64_t w0 = q0 + (int64_t)wave * 64 * kCompactBallots;
+    uint64_t m[kCompactBallots];
+    int n = 0;
+#pragma unroll
+    for (int j = 0; j < kCompactBallots; ++j) {
+      const int64_t q = w0 + 64 * j + lane;
+      m[j] = __ballot(q < ee && score[q] >= thr);
+      n += __popcll(m[j]);
+    }
+    if (lane == 0) tot[slot][wave] = n;
+    __syncthreads();
+    int base = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kCompactWaves; ++w) {
+      const int t = tot[slot][w];
+      base += w < wave ? t : 0;
+      total += t;
+    }
+#pragma unroll
+    for (int j = 0; j < kCompactBallots; ++j) {
+      const int64_t q = w0 + 64 * j + lane;
+      if ((m[j] >> lane) & 1) kept[eb + cnt + base + __popcll(m[j] & below)] = (int32_t)q;
+      base += __popcll(m[j]);
+    }
     cnt += total;
+    slot ^= 1;
   }
   if (threadIdx.x == 0) kept_cnt[ev] = (int32_t)cnt;
 }
@@ -454,7 +489,7 @@ hipError_t launch_csc(const RunArgs& a) {
 
 hipError_t launch_compact(const RunArgs& a) {
   if (a.hits.n_events == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_compact, dim3((unsigned)a.hits.n_events), dim3(256), 0, a.stream, a.hits.hit_off,
+  hipLaunchKernelGGL(k_compact, dim3((unsigned)a.hits.n_events), dim3(kCompactThreads), 0, a.stream, a.hits.hit_off,
                      WS(a, row_ptr, int64_t), a.out.score, a.ctx->cfg.edge_threshold, WS(a, kept, int32_t),
                      WS(a, kept_cnt, int32_t), a.out.status);
   return hipGetLastError();
