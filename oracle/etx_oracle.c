@@ -371,10 +371,11 @@ enum { Q_NE2 = 0, Q_H = 1, Q_MO = 2, Q_MI = 3, Q_EE2 = 4, Q_NN2 = 5, Q_EN2 = 6, 
  * qmode 0: plain FP64.  act_scale: [8 + S] slots above (qmode 2, 3).  amax
  * (may be NULL, [8 + S]): running max |x| of every quantised tensor.
  * compact (qmode 1, 2): store h and e in low precision (above).
- * f32: FP32 evaluation (see RF). */
+ * f32: FP32 evaluation (see RF).  e_out (may be NULL, [E][H]): the final edge
+ * encodings e_S. */
 void oracle_gnn(int64_t n, const double* cart, int64_t E, const int32_t* src, const int32_t* dst,
                 int H, int S, const double* params, double* logit, int qmode, const double* act_scale,
-                double* amax, int compact, int f32) {
+                double* amax, int compact, int f32, double* e_out) {
   const int qs = qmode && compact;   /* state rounding */
   double* h = (double*)calloc((size_t)n * H + 1, sizeof(double));
   double* e = (double*)calloc((size_t)E * H + 1, sizeof(double));
@@ -486,6 +487,8 @@ void oracle_gnn(int64_t n, const double* cart, int64_t E, const int32_t* src, co
     }
   }
 
+  /* the final edge encodings e_S (the triplet classifiers' input) */
+  if (e_out) memcpy(e_out, e, sizeof(double) * (size_t)E * H);
   /* classifier: Linear(H->1)(Block(H->H)(e)); the input is the stored e_S */
   {
     const double *W1 = p, *b1 = p + HH, *w2 = b1 + H, *b2 = w2 + H;

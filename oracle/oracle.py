@@ -3,11 +3,14 @@
 TEST INFRASTRUCTURE ONLY: imported by the test-suite, the smoke check and the
 benchmark's CPU-baseline leg, never by the library.  It marshals numpy arrays
 into the C oracle and strings its steps together per event, exactly in the
-order of the thesis's pipeline (ch. 8 "The ETX4VELO Pipeline" without the
-triplet stage, as run on GPU in ch. 9):
+order of the thesis's pipeline (ch. 8 "The ETX4VELO Pipeline"; ch. 9 runs
+it on GPU without the triplet stage):
 
     features -> embedding MLP -> radius graph (k_max cap) -> interaction
-    network -> sigmoid score -> score cut (s >= threshold) -> components.
+    network -> sigmoid score -> score cut (s >= threshold) -> components,
+
+and the triplet stage after the score cut (``run_event_triplets``):
+triplets of the purified graph -> triplet classifiers -> track building.
 
 Events are independent, so ``run_batch`` spreads them over a thread pool
 (ctypes releases the GIL during each C call).
@@ -25,6 +28,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "etx_oracle.c")
+_SRC_TRIPLETS = os.path.join(_HERE, "triplets.c")
 _LIB = os.path.join(_HERE, "_build", "liboracle.so")
 
 _lib = None
@@ -33,10 +37,11 @@ _lib = None
 def build(force: bool = True) -> str:
     """Compile the oracle with plain gcc -O2 (no BLAS, no SIMD intrinsics)."""
     os.makedirs(os.path.dirname(_LIB), exist_ok=True)
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    srcs = [_SRC, _SRC_TRIPLETS]
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in srcs):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fPIC", "-shared",
-                               _SRC, "-o", tmp, "-lm"])
+                               *srcs, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -54,7 +59,7 @@ def lib():
         L.oracle_radius.argtypes = [i64, P, P, i32, dbl, i32, i32, P, P, i64]
         L.oracle_radius.restype = i64
         L.oracle_radius_margins.argtypes = [i64, P, P, i32, dbl, i32, i32, P, P]
-        L.oracle_gnn.argtypes = [i64, P, i64, P, P, i32, i32, P, P, i32, P, P, i32, i32]
+        L.oracle_gnn.argtypes = [i64, P, i64, P, P, i32, i32, P, P, i32, P, P, i32, i32, P]
         L.oracle_pow2_scale.argtypes = [dbl]
         L.oracle_pow2_scale.restype = dbl
         L.oracle_components.argtypes = [i64, i64, P, P, P, P]
@@ -73,6 +78,13 @@ def lib():
         L.oracle_embed_hinge_loss_grad.restype = dbl
         L.oracle_gnn_focal_loss_grad.argtypes = [i64, P, i64, P, P, i32, i32, P, P, dbl, dbl, P]
         L.oracle_gnn_focal_loss_grad.restype = dbl
+        L.oracle_triplets.argtypes = [i64, i64, P, P, P, P, P, P, P, i64]
+        L.oracle_triplets.restype = i64
+        L.oracle_triplet_head_size.argtypes = [i32]
+        L.oracle_triplet_head_size.restype = i64
+        L.oracle_triplet_logits.argtypes = [i64, P, P, P, P, i32, P, P]
+        L.oracle_build_tracks.argtypes = [i64, i64, P, P, P, P, i64, P, P, P, P, P, P, P, P, P, P, i64, i64, P]
+        L.oracle_build_tracks.restype = i64
         _lib = L
     return _lib
 
@@ -153,20 +165,24 @@ def gnn_param_blocks(weights) -> list:
 
 
 def gnn(cart, src, dst, weights, H: int, S: int, qmode: int = 0, act_scale=None, amax=None,
-        compact: bool = False, f32: bool = False) -> np.ndarray:
+        compact: bool = False, f32: bool = False, return_e: bool = False):
     """Interaction-network logits.  act_scale / amax: the 8 + S activation
     slots documented in etx_oracle.c (qmode 2 / observers).  compact (qmode
     1, 2): node and edge encodings stored in low precision between layers
-    instead of full-precision masters.  f32: FP32 evaluation (see embed)."""
+    instead of full-precision masters.  f32: FP32 evaluation (see embed).
+    return_e: also return the final edge encodings e_S ([E][H])."""
     cart = _c(cart, np.float64)
     src = _c(src, np.int32); dst = _c(dst, np.int32)
     params = _flat(gnn_param_blocks(weights))
     E = len(src)
     logit = np.zeros(max(E, 1))
+    e = np.zeros((max(E, 1), H)) if return_e else None
     qs = None if act_scale is None else _c(act_scale, np.float64)
     lib().oracle_gnn(len(cart), _p(cart), E, _p(src), _p(dst), H, S, _p(params), _p(logit), qmode,
                      _p(qs) if qs is not None else None, _p(amax) if amax is not None else None, int(compact),
-                     int(f32))
+                     int(f32), _p(e) if e is not None else None)
+    if return_e:
+        return logit[:E].copy(), e[:E].copy()
     return logit[:E].copy()
 
 
@@ -347,6 +363,94 @@ def gnn_focal_loss_grad(cart, src, dst, weights, H: int, S: int, labels, alpha: 
     loss = lib().oracle_gnn_focal_loss_grad(len(cart), _p(cart), len(src), _p(src), _p(dst), H, S, _p(params),
                                             _p(lab), float(alpha), float(gamma), _p(g))
     return loss, g
+
+
+# ---------------------------------------------------------------------------
+# triplet stage (thesis ch. 8 "Triplet Building" and "Track Building"; the
+# readings are listed at the top of triplets.c)
+# ---------------------------------------------------------------------------
+
+def triplets(n: int, src, dst, plane, keep) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Triplets of the purified graph: (ta, tb, kind), kind 0 articulation,
+    1 left elbow, 2 right elbow; articulations first, then elbows."""
+    src = _c(src, np.int32); dst = _c(dst, np.int32); plane = _c(plane, np.int32)
+    keep = _c(keep, np.uint8)
+    z = np.zeros(1, np.int32)
+    cnt = lib().oracle_triplets(n, len(src), _p(src), _p(dst), _p(plane), _p(keep), _p(z), _p(z),
+                                _p(np.zeros(1, np.uint8)), 0)
+    ta = np.zeros(max(cnt, 1), np.int32); tb = np.zeros(max(cnt, 1), np.int32); kind = np.zeros(max(cnt, 1), np.uint8)
+    lib().oracle_triplets(n, len(src), _p(src), _p(dst), _p(plane), _p(keep), _p(ta), _p(tb), _p(kind), cnt)
+    return ta[:cnt].copy(), tb[:cnt].copy(), kind[:cnt].copy()
+
+
+def triplet_head_size(H: int) -> int:
+    return int(lib().oracle_triplet_head_size(H))
+
+
+def triplet_params(heads) -> np.ndarray:
+    """Flat float64 parameters of the two triplet classifiers: heads["art"],
+    heads["elb"], each [(W1[2H][H], b1), (W2[H][H], b2), (w3[H][1], b3)]."""
+    return np.concatenate([_flat(heads["art"]), _flat(heads["elb"])])
+
+
+def triplet_logits(ta, tb, kind, e, heads) -> np.ndarray:
+    ta = _c(ta, np.int32); tb = _c(tb, np.int32); kind = _c(kind, np.uint8)
+    e = _c(e, np.float64)
+    H = e.shape[1] if e.ndim == 2 else heads["art"][1][0].shape[0]
+    params = triplet_params(heads)
+    assert len(params) == 2 * triplet_head_size(H)
+    out = np.zeros(max(len(ta), 1))
+    lib().oracle_triplet_logits(len(ta), _p(ta), _p(tb), _p(kind), _p(e), H, _p(params), _p(out))
+    return out[:len(ta)].copy()
+
+
+def build_tracks(n: int, src, dst, plane, keep, ta, tb, kind, tkeep) -> Dict[str, object]:
+    """Track building from the purified edge graph.  Returns dup, comp (per
+    edge), tracks (list of ascending hit arrays) and each track's components
+    (c1, c2; c2 = -1 for an untouched component)."""
+    src = _c(src, np.int32); dst = _c(dst, np.int32); plane = _c(plane, np.int32)
+    keep = _c(keep, np.uint8)
+    ta = _c(ta, np.int32); tb = _c(tb, np.int32); kind = _c(kind, np.uint8); tkeep = _c(tkeep, np.uint8)
+    E, T = len(src), len(ta)
+    dup = np.zeros(max(E, 1), np.uint8); comp = np.zeros(max(E, 1), np.int32)
+    tcap = E + T + 1                     # tracks <= components + shared links
+    off = np.zeros(tcap + 1, np.int64)
+    c1 = np.zeros(tcap, np.int32); c2 = np.zeros(tcap, np.int32)
+    nh = C.c_int64(0)
+    hcap = 4 * E + 2
+    while True:
+        hits = np.zeros(hcap, np.int32)
+        nt = lib().oracle_build_tracks(n, E, _p(src), _p(dst), _p(plane), _p(keep), T, _p(ta), _p(tb), _p(kind),
+                                       _p(tkeep), _p(dup), _p(comp), _p(off), _p(hits), _p(c1), _p(c2), tcap, hcap,
+                                       C.byref(nh))
+        if nh.value <= hcap:
+            break
+        hcap = nh.value
+    assert nt <= tcap
+    tracks = [hits[off[k]:off[k + 1]].copy() for k in range(nt)]
+    return dict(dup=dup[:E].copy(), comp=comp[:E].copy(), tracks=tracks, c1=c1[:nt].copy(), c2=c2[:nt].copy())
+
+
+def run_event_triplets(ev: Dict[str, np.ndarray], w, weights, heads) -> Dict[str, np.ndarray]:
+    """The pipeline of run_event followed by the triplet stage: triplets of
+    the purified graph, their classifier scores, and the tracks."""
+    cyl, cart = features(ev["x"], ev["y"], ev["z"], w.r_scale, w.z_scale)
+    emb = embed(cyl, weights["emb"])
+    src, dst = radius_graph(ev["plane"], emb, float(np.float32(w.radius)), w.k_max, w.plane_window)
+    logit, e = gnn(cart, src, dst, weights, w.gnn_hidden, w.gnn_steps, return_e=True)
+    score = sigmoid(logit)
+    keep = score >= w.threshold
+    n = len(cyl)
+    ta, tb, kind = triplets(n, src, dst, ev["plane"], keep)
+    tlogit = triplet_logits(ta, tb, kind, e, heads)
+    tscore = sigmoid(tlogit)
+    tkeep = tscore >= w.threshold
+    tr = build_tracks(n, src, dst, ev["plane"], keep, ta, tb, kind, tkeep)
+    out = dict(emb=emb, src=src, dst=dst, logit=logit, score=score, keep=keep, e=e,
+               labels=components(n, src, dst, keep), ta=ta, tb=tb, kind=kind, tlogit=tlogit, tscore=tscore,
+               tkeep=tkeep)
+    out.update(tr)
+    return out
 
 
 if __name__ == "__main__":

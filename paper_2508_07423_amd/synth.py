@@ -58,6 +58,13 @@ class Workload:
     # plane (the order a module-by-module detector readout delivers, as the
     # thesis's GPU framework stores its hits); "shuffled" = random
     hit_order: str = "readout"
+    # conversion pairs (the thesis's motivation for the triplet stage, ch. 8
+    # "Shared hits"): this fraction of the tracks gets a partner particle that
+    # shares the parent's first `pair_shared` hits (the same hits: too close to
+    # be resolved) and then leaves them at a small opening angle (rad)
+    pair_fraction: float = 0.0
+    pair_shared: Tuple[int, int] = (1, 3)
+    pair_angle: Tuple[float, float] = (0.003, 0.01)
 
     @property
     def n_planes(self) -> int:
@@ -141,6 +148,10 @@ def generate_event(w: Workload, index: int, seed_space: Optional[int] = None) ->
     z = zp[pi]
     part = ti.astype(np.int32)
     plane = pi.astype(np.int32)
+    part2 = np.full(len(x), -1, np.int32)
+    if w.pair_fraction > 0:
+        x, y, z, part, plane, part2 = _add_pairs(w, index, seed_space, x, y, z, part, plane, part2, ti, pi,
+                                                 vz, zp, mask)
     n_noise = int(round(w.noise_fraction * len(x)))
     r0, r1 = w.noise_annulus
     nr = np.sqrt(rng.uniform(r0 * r0, r1 * r1, n_noise))
@@ -151,6 +162,7 @@ def generate_event(w: Workload, index: int, seed_space: Optional[int] = None) ->
     z = np.concatenate([z, zp[npl]])
     plane = np.concatenate([plane, npl])
     part = np.concatenate([part, np.full(n_noise, -1, np.int32)])
+    part2 = np.concatenate([part2, np.full(n_noise, -1, np.int32)])
     order = rng.permutation(len(x))
     if w.hit_order == "readout":
         order = np.lexsort((np.arctan2(y, x), plane))
@@ -158,7 +170,55 @@ def generate_event(w: Workload, index: int, seed_space: Optional[int] = None) ->
         raise ValueError(f"unknown hit order {w.hit_order!r}")
     return dict(x=x[order].astype(np.float32), y=y[order].astype(np.float32),
                 z=z[order].astype(np.float32), plane=plane[order].astype(np.int32),
-                particle=part[order].astype(np.int32))
+                particle=part[order].astype(np.int32), particle2=part2[order].astype(np.int32))
+
+
+def _add_pairs(w: Workload, index: int, seed_space: Optional[int], x, y, z, part, plane, part2, ti, pi, vz, zp,
+               mask):
+    """Partners of a fraction of the tracks (conversion pairs): partner j of
+    parent t shares t's first s hits (particle2 of those hits = j) and then
+    follows t's line turned by a small angle about the last shared hit, with
+    its own efficiency and smearing.  Draws from a stream of its own, so the
+    rest of the event is the one drawn without pairs."""
+    rng = np.random.default_rng(np.random.SeedSequence([w.cid if seed_space is None else seed_space, index, 77]))
+    nt = mask.shape[0]
+    xs, ys, zs, ps, pls = [x], [y], [z], [part], [plane]
+    p2 = part2.copy()
+    next_id = nt
+    for t in range(nt):
+        hit_idx = np.nonzero(ti == t)[0]                 # the parent's hits, plane order
+        u = rng.uniform()
+        s = int(rng.integers(w.pair_shared[0], w.pair_shared[1] + 1))
+        ang = rng.uniform(w.pair_angle[0], w.pair_angle[1])
+        psi = rng.uniform(0.0, 2.0 * np.pi)
+        eff = rng.uniform(0.0, 1.0, len(zp)) < w.hit_efficiency
+        sx = rng.normal(0.0, w.smear_xy, len(zp))
+        sy = rng.normal(0.0, w.smear_xy, len(zp))
+        if u >= w.pair_fraction or len(hit_idx) < s + 2:
+            continue
+        shared = hit_idx[:s]
+        last = shared[-1]
+        z0 = zp[pi[last]]
+        later = np.nonzero((zp > z0) & (zp - vz[t] > 0.0) & eff)[0]
+        # the parent's line at the later planes (without its smearing), turned about the last shared hit
+        tx_t = (x[hit_idx[-1]] - x[last]) / max(zp[pi[hit_idx[-1]]] - z0, 1e-9)
+        ty_t = (y[hit_idx[-1]] - y[last]) / max(zp[pi[hit_idx[-1]]] - z0, 1e-9)
+        dz = zp[later] - z0
+        nx = x[last] + (tx_t + ang * np.cos(psi)) * dz + sx[later]
+        ny = y[last] + (ty_t + ang * np.sin(psi)) * dz + sy[later]
+        if w.acceptance is not None:
+            rr = np.hypot(nx, ny)
+            ok = (rr >= w.acceptance[0]) & (rr <= w.acceptance[1])
+            later, nx, ny = later[ok], nx[ok], ny[ok]
+        if len(later) < 1:
+            continue
+        p2[shared] = next_id
+        xs.append(nx); ys.append(ny); zs.append(zp[later])
+        ps.append(np.full(len(later), next_id, np.int32)); pls.append(later.astype(np.int32))
+        next_id += 1
+    return (np.concatenate(xs), np.concatenate(ys), np.concatenate(zs), np.concatenate(ps).astype(np.int32),
+            np.concatenate(pls).astype(np.int32),
+            np.concatenate([p2, np.full(sum(len(a) for a in xs[1:]), -1, np.int32)]))
 
 
 def generate_batch(w: Workload, n_events: Optional[int] = None, first: int = 0,
@@ -170,16 +230,16 @@ def generate_batch(w: Workload, n_events: Optional[int] = None, first: int = 0,
     hit_off = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(counts, out=hit_off[1:])
     out = {k: (np.concatenate([e[k] for e in evs]) if n else np.zeros(0, evs and evs[0][k].dtype or np.float32))
-           for k in ("x", "y", "z", "plane", "particle")} if n else \
+           for k in ("x", "y", "z", "plane", "particle", "particle2")} if n else \
         dict(x=np.zeros(0, np.float32), y=np.zeros(0, np.float32), z=np.zeros(0, np.float32),
-             plane=np.zeros(0, np.int32), particle=np.zeros(0, np.int32))
+             plane=np.zeros(0, np.int32), particle=np.zeros(0, np.int32), particle2=np.zeros(0, np.int32))
     out["hit_off"] = hit_off
     return out
 
 
 def event_slice(batch: Dict[str, np.ndarray], i: int) -> Dict[str, np.ndarray]:
     a, b = int(batch["hit_off"][i]), int(batch["hit_off"][i + 1])
-    return {k: batch[k][a:b] for k in ("x", "y", "z", "plane", "particle")}
+    return {k: batch[k][a:b] for k in ("x", "y", "z", "plane", "particle", "particle2") if k in batch}
 
 
 # ----------------------------------------------------------------------------
@@ -227,6 +287,27 @@ def xavier_prefilter(seed: int = 7, hidden: int = 32) -> List[Tuple[np.ndarray, 
         rng = np.random.default_rng(np.random.SeedSequence([seed, 1000 + layer]))
         a = np.sqrt(6.0 / (fi + fo))
         out.append((rng.uniform(-a, a, (fi, fo)).astype(np.float32), np.zeros(fo, np.float32)))
+    return out
+
+
+def triplet_shapes(w: Workload) -> List[Tuple[int, int]]:
+    """Layers of one triplet classifier: 2H -> H, H -> H, H -> 1."""
+    H = w.gnn_hidden
+    return [(2 * H, H), (H, H), (H, 1)]
+
+
+def xavier_triplets(w: Workload, seed: Optional[int] = None) -> Dict[str, List[Tuple[np.ndarray, np.ndarray]]]:
+    """Xavier-uniform triplet classifiers (articulations "art", elbows "elb"), zero biases."""
+    s = (w.weight_seed if seed is None else seed) + 1
+    out: Dict[str, List[Tuple[np.ndarray, np.ndarray]]] = {}
+    layer = 0
+    for head in ("art", "elb"):
+        out[head] = []
+        for fi, fo in triplet_shapes(w):
+            rng = np.random.default_rng(np.random.SeedSequence([s, 2000 + layer]))
+            a = np.sqrt(6.0 / (fi + fo))
+            out[head].append((rng.uniform(-a, a, (fi, fo)).astype(np.float32), np.zeros(fo, np.float32)))
+            layer += 1
     return out
 
 
