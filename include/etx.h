@@ -354,6 +354,77 @@ etx_status etx_train_gnn_step(etx_ctx* ctx, const etx_hits* hits, etx_out* out, 
                               float gamma, float lr, int64_t step, float* loss_dev, void* ws, size_t ws_bytes,
                               etx_stream stream);
 
+/* Triplet stage (thesis ch. 8 "The ETX4VELO Pipeline", "Triplet Building" and
+ * "Track Building"): after the score cut, the purified hit graph is turned
+ * into a graph of edges whose links are triplets, two triplet classifiers
+ * purify it, and tracks are built from it; tracks may share hits (the
+ * thesis's reason for the stage: particles that leave the same first hits).
+ *
+ * Triplets around every hit C, from its kept in-edges (by source) and kept
+ * out-edges (by target):
+ *   articulation (A->C, C->B)  every in/out pair            kind 0
+ *   left elbow   (C->A, C->B)  every pair of out-edges      kind 1
+ *   right elbow  (A->C, B->C)  every pair of in-edges       kind 2
+ * The batch lists all its articulations (event by event, hit by hit, in-edge
+ * major) and then all its elbows (same order, a hit's left elbows before its
+ * right ones).  (tri_a, tri_b) is the classifier's input order: the in-edge
+ * first for an articulation, the shorter edge first for an elbow (its other
+ * hit on the plane nearer to C; equal planes: the earlier edge).
+ *
+ * Classifiers: one for articulations, one for both kinds of elbow, each
+ * Linear(H->1)(Block(H->H)(Block(2H->H)([e_a, e_b]))) on the final edge
+ * encodings, Block(x) = ReLU(LN(x W + b)), score = sigmoid; FP32 in every
+ * precision mode.  A triplet is kept when its score >= edge_threshold.
+ *
+ * Track building (four steps): (1) a kept edge that is the longer edge of a
+ * kept left elbow at its source and of a kept right elbow at its target
+ * duplicates the path through the middle hit and leaves the edge graph;
+ * (2) the links are the kept articulations of two remaining edges; a link
+ * (p, q) is shared when another link starts at p or another link ends at q;
+ * weakly connected components over the non-shared links, each named by its
+ * smallest edge index; (3) every component that no shared link touches is a
+ * track, and every shared link (p, q) is a track made of the components of p
+ * and q; (4) a track's hits are the endpoints of its edges, ascending.  Per
+ * event the tracks are the untouched components by name, then the shared
+ * links in triplet order.
+ *
+ * Parameters: float32, the articulation classifier then the elbow classifier,
+ * each W1[2H][H] b1[H] W2[H][H] b2[H] W3[H][1] b3[1]. */
+#define ETX_TRIPLET_NPARAM(H) (2 * (3 * (H) * (H) + 3 * (H) + 1))
+etx_status etx_triplet_set(etx_ctx* ctx, const float* params, int64_t n);   /* host params */
+etx_status etx_triplet_get(const etx_ctx* ctx, float* params, int64_t n);   /* host params */
+
+typedef struct {             /* device pointers, caller-owned, written by etx_run_tracks */
+  int64_t triplet_capacity;  /* length of tri_a, tri_b, tri_score, tri_kind */
+  int32_t* tri_a;            /* first edge of the triplet (global edge index into out->src / out->dst) */
+  int32_t* tri_b;            /* second edge */
+  float* tri_score;          /* triplet classifier score */
+  uint8_t* tri_kind;         /* 0 articulation, 1 left elbow, 2 right elbow */
+  int64_t* art_off;          /* [n_events+1] event e's articulations: art_off[e] .. art_off[e+1]-1 */
+  int64_t* elb_off;          /* [n_events+1] its elbows: elb_off[e] .. elb_off[e+1]-1 (after all articulations) */
+  int64_t track_capacity;    /* tracks */
+  int64_t* event_track_off;  /* [n_events+1] event e's tracks: event_track_off[e] .. event_track_off[e+1]-1 */
+  int64_t* track_off;        /* [track_capacity+1] track t's hits: track_hits[track_off[t] .. track_off[t+1]-1] */
+  int64_t hit_capacity;      /* length of track_hits */
+  int32_t* track_hits;       /* global hit indices, ascending within a track */
+  int64_t* status;           /* [4] status[0] = etx_status of the stage (ETX_ERR_CAPACITY when a capacity is too
+                                small), status[1] = triplets needed, status[2] = tracks needed, status[3] = track
+                                hits needed (each set when its capacity was the one exceeded) */
+} etx_tracks;
+
+/* Workspace bytes of etx_run_tracks: the etx_run workspace of the batch plus
+ * the triplet stage's buffers for these capacities. */
+etx_status etx_tracks_workspace_size(const etx_ctx* ctx, int64_t n_events, int64_t n_hits, int64_t edge_capacity,
+                                     int64_t triplet_capacity, int64_t track_capacity, size_t* bytes);
+/* The whole hot path of etx_run (same outputs in `out`), then the triplet
+ * stage into `tracks`.  Needs the triplet parameters (etx_triplet_set) and
+ * node and edge state in FP32 (FP32 runs, or BF16 / FP8 / INT8 operands
+ * without ETX_OPT_COMPACT_STATE; otherwise ETX_ERR_UNSUPPORTED).  Runs
+ * eagerly on `stream` (ETX_OPT_USE_GRAPH is not applied); asynchronous.  A
+ * device error of etx_run's stages (out->status) skips the triplet stage. */
+etx_status etx_run_tracks(etx_ctx* ctx, const etx_hits* hits, etx_out* out, etx_tracks* tracks, void* ws,
+                          size_t ws_bytes, etx_stream stream);
+
 /* Checkpoint of a context: configuration, weight blob, per-tensor scales and
  * calibration flag, prefilter parameters with their Adam moments, and the
  * launch options (the state that training, calibration and tuning build up).

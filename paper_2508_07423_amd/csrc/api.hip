@@ -22,6 +22,7 @@ int graph_attributes(size_t max_lds);
 int radius_attributes(size_t max_lds);
 int prefilter_attributes(size_t max_lds);
 int train_attributes(size_t max_lds);
+int triplet_attributes(size_t max_lds);
 
 bool GraphKey::operator<(const GraphKey& o) const {
   for (int i = 0; i < 16; ++i)
@@ -402,14 +403,15 @@ int set_kernel_attributes() {
   // below the 160 KiB per workgroup so that static LDS still fits beside it
   size_t max_lds = 150 * 1024;
   done = embed_attributes(max_lds) | gnn_attributes(max_lds) | graph_attributes(max_lds) |
-         radius_attributes(max_lds) | prefilter_attributes(max_lds) | train_attributes(max_lds);
+         radius_attributes(max_lds) | prefilter_attributes(max_lds) | train_attributes(max_lds) |
+         triplet_attributes(max_lds);
   return done;
 }
 
 static const char* kStageNames[] = {"init",      "validate",   "bucket",      "embed",       "radius_count",
                                      "scan",      "radius_emit", "prefilter",  "csc",         "node_encode",
                                      "edge_encode", "segsum",    "node_step",   "edge_step",   "edge_step_final",
-                                     "compact",   "union_find"};
+                                     "compact",   "union_find", "triplets",    "triplet_score", "tracks"};
 constexpr int kNumStages = sizeof(kStageNames) / sizeof(kStageNames[0]);
 
 // Record a pair of HIP events around one stage on the stage's stream.
@@ -665,6 +667,7 @@ etx_status etx_destroy(etx_ctx* ctx) {
   if (ctx->dev_scales) (void)hipFree(ctx->dev_scales);
   if (ctx->dev_pf) (void)hipFree(ctx->dev_pf);
   if (ctx->dev_train) (void)hipFree(ctx->dev_train);
+  if (ctx->dev_tri) (void)hipFree(ctx->dev_tri);
   delete ctx;
   return ETX_OK;
 }
@@ -1016,6 +1019,87 @@ etx_status etx_quantize(int32_t precision, const float* in, float* out, int64_t 
   hipError_t e = launch_quantize(precision, in, out, n, scale, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) {
     note_error("etx_quantize", e);
+    return ETX_ERR_HIP;
+  }
+  return ETX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// triplet stage
+// ---------------------------------------------------------------------------
+
+etx_status etx_triplet_set(etx_ctx* ctx, const float* params, int64_t n) {
+  if (!ctx || !params) return ETX_ERR_INVALID_ARG;
+  const int H = ctx->cfg.gnn_hidden;
+  if (n != ETX_TRIPLET_NPARAM(H)) return ETX_ERR_INVALID_ARG;
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(params[i])) return ETX_ERR_WEIGHTS;
+  if (hipSetDevice(ctx->device) != hipSuccess) return ETX_ERR_HIP;
+  const int hf = tri_head_floats(H);
+  std::vector<float> dev(2 * (size_t)hf);
+  const int64_t per = ETX_TRIPLET_NPARAM(H) / 2;
+  tri_prepare_head(params, H, dev.data());
+  tri_prepare_head(params + per, H, dev.data() + hf);
+  hipError_t e = hipSuccess;
+  if (!ctx->dev_tri) e = hipMalloc(&ctx->dev_tri, sizeof(float) * dev.size());
+  if (e == hipSuccess) e = hipMemcpy(ctx->dev_tri, dev.data(), sizeof(float) * dev.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    note_error("etx_triplet_set", e);
+    return ETX_ERR_HIP;
+  }
+  ctx->tri_host.assign(params, params + n);
+  return ETX_OK;
+}
+
+etx_status etx_triplet_get(const etx_ctx* ctx, float* params, int64_t n) {
+  if (!ctx || !params || ctx->tri_host.empty() || n != (int64_t)ctx->tri_host.size()) return ETX_ERR_INVALID_ARG;
+  std::memcpy(params, ctx->tri_host.data(), sizeof(float) * n);
+  return ETX_OK;
+}
+
+etx_status etx_tracks_workspace_size(const etx_ctx* ctx, int64_t n_events, int64_t n_hits, int64_t edge_capacity,
+                                     int64_t triplet_capacity, int64_t track_capacity, size_t* bytes) {
+  if (!ctx || !bytes || n_events < 0 || n_hits < 0 || edge_capacity < 0 || triplet_capacity < 0 ||
+      track_capacity < 0)
+    return ETX_ERR_INVALID_ARG;
+  *bytes = ws_layout(ctx, n_events, n_hits, edge_capacity).total +
+           tri_layout(n_events, n_hits, edge_capacity, triplet_capacity, track_capacity).total;
+  return ETX_OK;
+}
+
+etx_status etx_run_tracks(etx_ctx* ctx, const etx_hits* hits, etx_out* out, etx_tracks* tracks, void* ws,
+                          size_t ws_bytes, etx_stream stream) {
+  if (!tracks) return ETX_ERR_INVALID_ARG;
+  WsLayout L;
+  etx_status st = check_run_args(ctx, hits, out, ws, ws_bytes, &L);
+  if (st != ETX_OK) return st;
+  const etx_tracks& T = *tracks;
+  if (T.triplet_capacity < 0 || T.track_capacity < 0 || T.hit_capacity < 0 || !T.status || !T.art_off ||
+      !T.elb_off || !T.event_track_off || !T.track_off)
+    return ETX_ERR_INVALID_ARG;
+  if (T.triplet_capacity > 0 && (!T.tri_a || !T.tri_b || !T.tri_score || !T.tri_kind)) return ETX_ERR_INVALID_ARG;
+  if (T.hit_capacity > 0 && !T.track_hits) return ETX_ERR_INVALID_ARG;
+  if (T.triplet_capacity >= 0x7fffffffLL || T.track_capacity >= 0x7fffffffLL) return ETX_ERR_UNSUPPORTED;
+  const TriLayout TL = tri_layout(hits->n_events, hits->n_hits, out->edge_capacity, T.triplet_capacity,
+                                  T.track_capacity);
+  if (ws_bytes < L.total + TL.total) return ETX_ERR_INVALID_ARG;
+  if (ctx->tri_host.empty()) return ETX_ERR_INVALID_ARG;
+  const int prec = kernel_precision(ctx);
+  if (prec == ETX_BF16 || prec == ETX_FP8_E4M3) return ETX_ERR_UNSUPPORTED;   // compact state: e_S not in FP32
+  auto scaled = [](int p) { return p == ETX_FP8_E4M3 || p == ETX_INT8; };
+  if ((scaled(ctx->cfg.precision) || scaled(ctx->emb_precision)) && !ctx->calibrated) return ETX_ERR_INVALID_ARG;
+  if (ctx->cfg.prefilter && !ctx->pf_set) return ETX_ERR_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return ETX_ERR_HIP;
+  RunArgs a{ctx, *hits, *out, L, static_cast<char*>(ws), static_cast<hipStream_t>(stream), false, prec};
+  a.keep_final_e = true;
+  char* tws = static_cast<char*>(ws) + L.total;
+  hipError_t e = enqueue_pipeline(a);
+  for (int part = 0; part < 3 && e == hipSuccess; ++part) {
+    StageTimer timer_(a, 17 + part);
+    e = launch_triplet_stage(a, T, tws, TL, part);
+  }
+  if (e != hipSuccess) {
+    note_error("etx_run_tracks launch", e);
     return ETX_ERR_HIP;
   }
   return ETX_OK;

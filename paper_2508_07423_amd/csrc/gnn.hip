@@ -71,6 +71,7 @@ struct GnnArgs {
   const float* sc;          // per-tensor scales (seg.hpp ScaleSlot)
   int step;
   int xcd_map;              // 1: logical workgroup ids contiguous per XCD
+  int keep_final;           // 1: the final edge step also stores e_S (the triplet classifiers' input)
   const int64_t* status;
 };
 
@@ -1058,6 +1059,7 @@ __global__ __launch_bounds__(512) void k_edge_step(GnnArgs A) {
       else
         out_sums<H>(A, tile, ti, key, o);
     } else {
+      if (A.keep_final) store_e<P, H>(A.e, col, o, valid, 1.0f / s_next, s_next);
       // classifier on the final edge encodings (quantised like a stored e_S)
       float c[H / 4];
       bias_cols<H>(c, reinterpret_cast<const float*>(wc + C.b1()));
@@ -1104,6 +1106,7 @@ static GnnArgs gnn_args(const RunArgs& a) {
   A.calib = a.calibrate ? reinterpret_cast<float*>(a.ws + a.L.calib) : nullptr;
   A.sc = c->dev_scales + (a.prec == P_I8M ? SC_I8 : 0);   // the INT8 scale set
   A.xcd_map = a.ctx->xcd_map;
+  A.keep_final = a.keep_final_e ? 1 : 0;
   A.status = a.out.status;
   return A;
 }

@@ -72,6 +72,9 @@ struct etx_ctx {
   float* dev_pf = nullptr;
   // in-library training: the weight blob's parameters, Adam m, v (FP32, device; etx_train_begin)
   float* dev_train = nullptr;
+  // triplet classifiers: both heads permuted for the column tiles (device), and as given (host)
+  float* dev_tri = nullptr;
+  std::vector<float> tri_host;
   bool pf_set = false;
   float pf_band_lo = 0.f, pf_band_hi = 1.f;   // validated band of an event's kept fraction
   // tuning
@@ -126,7 +129,21 @@ struct RunArgs {
   int prec;                        // kernel precision: etx_precision, or kBf16Master / kFp8Master
   bool untimed = false;            // no stage timing even when profiling is on (the no-allocation entry point)
   float radius_override = 0.f;     // > 0: the radius graph at this radius instead of the configuration's (training)
+  bool keep_final_e = false;       // the final edge step also stores e_S (the triplet classifiers' input)
 };
+
+// Byte offsets (from the start of the triplet area) of the triplet stage's buffers.
+struct TriLayout {
+  size_t deg_in, deg_out, cnt_art, cnt_elb, art_pos, elb_pos, part, lstate, dup, touched, par, comp, ccount, cstart,
+      cedge, ntr, c1, c2, tev, tlen, total;
+};
+TriLayout tri_layout(int64_t n_events, int64_t n_hits, int64_t edge_cap, int64_t triplet_cap, int64_t track_cap);
+// Floats of one triplet classifier in its device form.
+int tri_head_floats(int H);
+// Permute one classifier (host parameters W1 b1 W2 b2 W3 b3) into its device form.
+void tri_prepare_head(const float* p, int H, float* out);
+// The triplet stage in three parts (0: triplets of the purified graph, 1: classifier scores, 2: tracks).
+hipError_t launch_triplet_stage(const RunArgs& a, const etx_tracks& T, char* tws, const TriLayout& TL, int part);
 
 // launchers (graph.hip)
 hipError_t launch_init_status(const RunArgs& a);

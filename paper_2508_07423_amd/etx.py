@@ -33,7 +33,11 @@ ETX_PF_NPARAM = 6 * 32 + 32 + 32 * 32 + 32 + 32 + 1
  ETX_OPT_RADIUS_SINGLE_PASS, ETX_OPT_RADIUS_SORT_MIN, ETX_OPT_FUSE_MESSAGES, ETX_OPT_RADIUS_FAST,
  ETX_OPT_XCD_MAP, ETX_OPT_EDGE_PRODUCTS, ETX_OPT_CSC_PLACE, ETX_OPT_COMPACT_STATE,
  ETX_OPT_PROFILE_STAGES, ETX_OPT_PF_FEATURES) = range(22)
-N_STAGES = 17
+N_STAGES = 20
+
+
+def ETX_TRIPLET_NPARAM(H: int) -> int:
+    return 2 * (3 * H * H + 3 * H + 1)
 
 
 class etx_config(C.Structure):
@@ -57,6 +61,14 @@ class etx_out(C.Structure):
 class etx_truth(C.Structure):
     _fields_ = [("particle", C.c_void_p), ("succ", C.c_void_p), ("pred", C.c_void_p), ("query", C.c_void_p),
                 ("rnd", C.c_void_p), ("rnd_ptr", C.c_void_p), ("rnd_src", C.c_void_p)]
+
+
+class etx_tracks(C.Structure):
+    _fields_ = [("triplet_capacity", C.c_int64), ("tri_a", C.c_void_p), ("tri_b", C.c_void_p),
+                ("tri_score", C.c_void_p), ("tri_kind", C.c_void_p), ("art_off", C.c_void_p),
+                ("elb_off", C.c_void_p), ("track_capacity", C.c_int64), ("event_track_off", C.c_void_p),
+                ("track_off", C.c_void_p), ("hit_capacity", C.c_int64), ("track_hits", C.c_void_p),
+                ("status", C.c_void_p)]
 
 
 _lib = None
@@ -106,6 +118,10 @@ def lib():
             "etx_train_gnn_step": [P, C.POINTER(etx_hits), C.POINTER(etx_out), C.POINTER(etx_truth), C.c_float,
                                    C.c_float, C.c_float, i64, P, P, sz, P],
             "etx_tuning_load": [P, C.c_char_p],
+            "etx_triplet_set": [P, P, i64],
+            "etx_triplet_get": [P, P, i64],
+            "etx_tracks_workspace_size": [P, i64, i64, i64, i64, i64, C.POINTER(sz)],
+            "etx_run_tracks": [P, C.POINTER(etx_hits), C.POINTER(etx_out), C.POINTER(etx_tracks), P, sz, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -128,7 +144,8 @@ EXPORTED = ["etx_create", "etx_destroy", "etx_weight_blob_size", "etx_workspace_
             "etx_stage_name", "etx_get_scales", "etx_quantize", "etx_prefilter_config", "etx_save", "etx_load",
             "etx_tuning_save", "etx_tuning_load", "etx_prefilter_band", "etx_run_noalloc",
             "etx_train_begin", "etx_train_params", "etx_train_apply", "etx_train_workspace_size", "etx_train_view",
-            "etx_train_embed_step", "etx_train_gnn_step"]
+            "etx_train_embed_step", "etx_train_gnn_step", "etx_triplet_set", "etx_triplet_get",
+            "etx_tracks_workspace_size", "etx_run_tracks"]
 
 
 class EtxError(RuntimeError):
@@ -323,6 +340,41 @@ def etx_prefilter_train_step(ctx, hits, out, labels_ptr: int, lr: float, pos_wei
                                           C.c_void_p(stream)), "etx_prefilter_train_step")
 
 
+def etx_triplet_set(ctx, params: np.ndarray) -> None:
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    _check(lib().etx_triplet_set(ctx, p.ctypes.data_as(C.c_void_p), p.size), "etx_triplet_set")
+
+
+def etx_triplet_get(ctx, n: int) -> np.ndarray:
+    p = np.zeros(n, np.float32)
+    _check(lib().etx_triplet_get(ctx, p.ctypes.data_as(C.c_void_p), n), "etx_triplet_get")
+    return p
+
+
+def etx_tracks_workspace_size(ctx, n_events: int, n_hits: int, edge_capacity: int, triplet_capacity: int,
+                              track_capacity: int) -> int:
+    b = C.c_size_t()
+    _check(lib().etx_tracks_workspace_size(ctx, n_events, n_hits, edge_capacity, triplet_capacity, track_capacity,
+                                           C.byref(b)), "etx_tracks_workspace_size")
+    return b.value
+
+
+def etx_run_tracks(ctx, hits, out, tracks, ws_ptr: int, ws_bytes: int, stream: int) -> None:
+    _check(lib().etx_run_tracks(ctx, C.byref(hits), C.byref(out), C.byref(tracks), C.c_void_p(ws_ptr), ws_bytes,
+                                C.c_void_p(stream)), "etx_run_tracks")
+
+
+def pack_triplets(heads: Dict) -> np.ndarray:
+    """The triplet classifiers' parameters in the etx.h order (articulation head, then elbow head; each
+    W1[2H][H] b1 W2[H][H] b2 W3[H][1] b3)."""
+    parts = []
+    for h in ("art", "elb"):
+        for W, b in heads[h]:
+            parts.append(np.ascontiguousarray(W, np.float32).ravel())
+            parts.append(np.ascontiguousarray(b, np.float32).ravel())
+    return np.concatenate(parts)
+
+
 def etx_stage_name(stage: int) -> str:
     return lib().etx_stage_name(stage).decode()
 
@@ -412,10 +464,12 @@ class Pipeline:
         return etx_hits(b.n_events, b.n_hits, b.hit_off.data_ptr(), b.x.data_ptr(), b.y.data_ptr(), b.z.data_ptr(),
                         b.plane.data_ptr())
 
-    def allocate(self, b: Batch, edge_capacity: Optional[int] = None):
+    def allocate(self, b: Batch, edge_capacity: Optional[int] = None, tri_caps: Optional[tuple] = None):
+        """Outputs and workspace for batch ``b``; ``tri_caps`` = (triplets, tracks) sizes the workspace for
+        etx_run_tracks as well (its first part is the etx_run workspace, so the views stay valid)."""
         import torch
         cap = b.n_hits * self.w.k_max if edge_capacity is None else edge_capacity
-        shape = (b.n_events, b.n_hits, cap)
+        shape = (b.n_events, b.n_hits, cap, tri_caps)
         if self._shape != shape:
             dev = torch.device("cuda", self.device)
             self.src = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
@@ -424,7 +478,9 @@ class Pipeline:
             self.edge_off = torch.empty(b.n_events + 1, dtype=torch.int64, device=dev)
             self.labels = torch.empty(max(b.n_hits, 1), dtype=torch.int32, device=dev)
             self.status = torch.zeros(2, dtype=torch.int64, device=dev)
-            nbytes = etx_workspace_size(self.ctx, b.n_events, b.n_hits, cap)
+            nbytes = etx_workspace_size(self.ctx, b.n_events, b.n_hits, cap) if tri_caps is None else \
+                etx_tracks_workspace_size(self.ctx, b.n_events, b.n_hits, cap, tri_caps[0], tri_caps[1])
+            self.ws = None
             self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
             self.ws_ptr = (self.ws.data_ptr() + 255) & ~255
             self.ws_bytes = nbytes
@@ -479,3 +535,80 @@ class Pipeline:
         E = int(eo[-1])
         return dict(edge_off=eo, src=self.src[:E].cpu().numpy(), dst=self.dst[:E].cpu().numpy(),
                     score=self.score[:E].cpu().numpy(), labels=self.labels[:b.n_hits].cpu().numpy())
+
+    # ---- triplet stage ----------------------------------------------------
+
+    def set_triplets(self, heads: Dict) -> None:
+        etx_triplet_set(self.ctx, pack_triplets(heads))
+
+    def allocate_tracks(self, b: Batch, triplet_capacity: int, track_capacity: int, hit_capacity: int):
+        import torch
+        caps = (triplet_capacity, track_capacity, hit_capacity, b.n_events)
+        if getattr(self, "_tshape", None) != caps:
+            dev = torch.device("cuda", self.device)
+            T = max(triplet_capacity, 1)
+            self.tri_a = torch.empty(T, dtype=torch.int32, device=dev)
+            self.tri_b = torch.empty(T, dtype=torch.int32, device=dev)
+            self.tri_score = torch.empty(T, dtype=torch.float32, device=dev)
+            self.tri_kind = torch.empty(T, dtype=torch.uint8, device=dev)
+            self.art_off = torch.empty(b.n_events + 1, dtype=torch.int64, device=dev)
+            self.elb_off = torch.empty(b.n_events + 1, dtype=torch.int64, device=dev)
+            self.event_track_off = torch.empty(b.n_events + 1, dtype=torch.int64, device=dev)
+            self.track_off = torch.empty(track_capacity + 1, dtype=torch.int64, device=dev)
+            self.track_hits = torch.empty(max(hit_capacity, 1), dtype=torch.int32, device=dev)
+            self.tstatus = torch.zeros(4, dtype=torch.int64, device=dev)
+            self._tshape = caps
+        return etx_tracks(triplet_capacity, self.tri_a.data_ptr(), self.tri_b.data_ptr(), self.tri_score.data_ptr(),
+                          self.tri_kind.data_ptr(), self.art_off.data_ptr(), self.elb_off.data_ptr(), track_capacity,
+                          self.event_track_off.data_ptr(), self.track_off.data_ptr(), hit_capacity,
+                          self.track_hits.data_ptr(), self.tstatus.data_ptr())
+
+    def run_tracks(self, b: Batch, triplet_capacity: Optional[int] = None, track_capacity: Optional[int] = None,
+                   hit_capacity: Optional[int] = None, edge_capacity: Optional[int] = None, stream=None):
+        """etx_run_tracks on ``b`` (default capacities: 4 triplets, 1 track, 4 track hits per hit)."""
+        import torch
+        tc = 4 * b.n_hits + 1024 if triplet_capacity is None else triplet_capacity
+        kc = b.n_hits + 1024 if track_capacity is None else track_capacity
+        hc = 4 * b.n_hits + 1024 if hit_capacity is None else hit_capacity
+        out = self.allocate(b, edge_capacity, tri_caps=(tc, kc))
+        tr = self.allocate_tracks(b, tc, kc, hc)
+        s = torch.cuda.current_stream(self.device) if stream is None else stream
+        etx_run_tracks(self.ctx, self.hits_struct(b), out, tr, self.ws_ptr, self.ws_bytes, s.cuda_stream)
+        return out, tr
+
+    def track_status(self) -> np.ndarray:
+        import torch
+        torch.cuda.synchronize(self.device)
+        return self.tstatus.cpu().numpy()
+
+    def run_tracks_sized(self, b: Batch, stream=None, **caps):
+        """run_tracks, run again with the capacities the device asked for while one was too small."""
+        self.run_tracks(b, stream=stream, **caps)
+        for _ in range(3):
+            st = self.track_status()
+            if st[0] != ETX_ERR_CAPACITY:
+                break
+            tc, kc, hc = self._tshape[:3]
+            caps = dict(triplet_capacity=max(tc, int(st[1])), track_capacity=max(kc, int(st[2])),
+                        hit_capacity=max(hc, int(st[3])), edge_capacity=caps.get("edge_capacity"))
+            self.run_tracks(b, stream=stream, **caps)
+
+    def track_results(self, b: Batch) -> Dict[str, object]:
+        """Synchronise; the triplets and tracks of the last etx_run_tracks (tracks per event as hit arrays)."""
+        import torch
+        torch.cuda.synchronize(self.device)
+        st = self.tstatus.cpu().numpy()
+        if st[0] != ETX_OK:
+            raise EtxError(int(st[0]), f"triplet stage status (needed: triplets {int(st[1])}, tracks {int(st[2])}, "
+                                       f"hits {int(st[3])})")
+        ao = self.art_off.cpu().numpy()
+        eo = self.elb_off.cpu().numpy()
+        T = int(eo[-1])
+        eto = self.event_track_off.cpu().numpy()
+        nt = int(eto[-1])
+        to = self.track_off[:nt + 1].cpu().numpy()
+        hits = self.track_hits[:int(to[-1]) if nt else 0].cpu().numpy()
+        return dict(art_off=ao, elb_off=eo, tri_a=self.tri_a[:T].cpu().numpy(), tri_b=self.tri_b[:T].cpu().numpy(),
+                    tri_score=self.tri_score[:T].cpu().numpy(), tri_kind=self.tri_kind[:T].cpu().numpy(),
+                    event_track_off=eto, track_off=to, track_hits=hits,
+                    tracks=[hits[to[k]:to[k + 1]] for k in range(nt)])

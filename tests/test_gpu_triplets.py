@@ -1,0 +1,228 @@
+"""GPU parity of the triplet stage (thesis ch. 8 "Triplet Building" and "Track
+Building") against the FP64 oracle, through the C ABI (etx_run_tracks).
+
+Protocol, per event:
+  triplets  bit-exact: the GPU's list equals the oracle's triplets of the
+            GPU's own purified graph (its edges and score cut), in order
+  scores    |s_gpu - s_oracle| <= 1e-5 with the oracle's classifiers on its
+            FP64 final edge encodings of the GPU's edge list (FP32 path), and
+            the same keep decision wherever |s_oracle - 0.5| > 1e-4
+  tracks    bit-exact: the GPU's tracks (hit lists and order) equal the
+            oracle's track building on the GPU's purified graph and the GPU's
+            triplet decisions
+The etx_run outputs of etx_run_tracks equal etx_run's bit for bit.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2508_07423_amd import synth
+from tests import gpu_helpers as G
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _etx():
+    from paper_2508_07423_amd import etx
+    return etx
+
+
+def run_tracks(w, weights, heads, batch, precision=0, **caps):
+    etx = _etx()
+    p = etx.Pipeline(w, weights, precision=precision)
+    p.set_triplets(heads)
+    b = etx.to_device(batch)
+    p.run_tracks_sized(b, **caps)
+    res = p.results(b)
+    tres = p.track_results(b)
+    return p, b, res, tres
+
+
+def event_triplet_parity(w, weights, heads, batch, res, tres, i, score_tol=G.SCORE_TOL, check_scores=True):
+    a, e = int(batch["hit_off"][i]), int(batch["hit_off"][i + 1])
+    n = e - a
+    e0, e1 = int(res["edge_off"][i]), int(res["edge_off"][i + 1])
+    gs, gd, sc = res["src"][e0:e1] - a, res["dst"][e0:e1] - a, res["score"][e0:e1]
+    plane = batch["plane"][a:e]
+    keep = sc >= np.float32(w.threshold)
+    ta, tb, kind = O.triplets(n, gs, gd, plane, keep)
+    ao, eo = tres["art_off"], tres["elb_off"]
+    sel = np.r_[np.arange(ao[i], ao[i + 1]), np.arange(eo[i], eo[i + 1])].astype(np.int64)
+    g_ta, g_tb = tres["tri_a"][sel] - e0, tres["tri_b"][sel] - e0
+    g_kind, g_ts = tres["tri_kind"][sel], tres["tri_score"][sel]
+    np.testing.assert_array_equal(g_kind, kind)
+    np.testing.assert_array_equal(g_ta, ta)
+    np.testing.assert_array_equal(g_tb, tb)
+    if check_scores and len(ta):
+        _, cart = O.features(batch["x"][a:e], batch["y"][a:e], batch["z"][a:e], w.r_scale, w.z_scale)
+        _, e64 = O.gnn(cart, gs, gd, weights, w.gnn_hidden, w.gnn_steps, return_e=True)
+        ts64 = O.sigmoid(O.triplet_logits(ta, tb, kind, e64, heads))
+        err = np.abs(g_ts.astype(np.float64) - ts64)
+        assert err.max() <= score_tol, f"event {i}: max triplet score error {err.max()}"
+        far = np.abs(ts64 - 0.5) > G.KEEP_BAND
+        assert np.array_equal(g_ts[far] >= 0.5, ts64[far] >= 0.5)
+    tkeep = g_ts >= np.float32(w.threshold)
+    ref = O.build_tracks(n, gs, gd, plane, keep, ta, tb, kind, tkeep)
+    eto = tres["event_track_off"]
+    got = [t - a for t in tres["tracks"][eto[i]:eto[i + 1]]]
+    assert len(got) == len(ref["tracks"]), f"event {i}: {len(got)} tracks, oracle {len(ref['tracks'])}"
+    for k, (g, r) in enumerate(zip(got, ref["tracks"])):
+        assert np.array_equal(g, r), f"event {i} track {k}: gpu {g} oracle {r}"
+    return dict(triplets=len(ta), kept=int(tkeep.sum()), tracks=len(got), dup=int(ref["dup"].sum()),
+                shared=int(np.sum(ref["c2"] >= 0)))
+
+
+def balanced_heads(w, W, batch, seed, event=0):
+    """Xavier triplet classifiers whose output biases put the median logit of
+    each classifier (on the oracle's triplets of one event) at zero, so that
+    about half of the articulations and half of the elbows are kept and every
+    branch of track building is taken."""
+    heads = synth.xavier_triplets(w, seed=seed)
+    ev = synth.event_slice(batch, event)
+    ref = O.run_event_triplets(ev, w, W, heads)
+    out = {}
+    for name, sel in (("art", ref["kind"] == 0), ("elb", ref["kind"] > 0)):
+        layers = [(Wl.copy(), bl.copy()) for Wl, bl in heads[name]]
+        if sel.any():
+            layers[2][1][0] = np.float32(-np.median(ref["tlogit"][sel]))
+        out[name] = layers
+    return out
+
+
+def test_c1_random_heads_triplets_and_tracks():
+    w = synth.C1
+    W = synth.xavier_weights(w)
+    batch = synth.generate_batch(w, 1)
+    heads = balanced_heads(w, W, batch, seed=1)
+    p, b, res, tres = run_tracks(w, W, heads, batch)
+    st = event_triplet_parity(w, W, heads, batch, res, tres, 0)
+    # the dense random-weight graph exercises every branch of track building
+    assert st["triplets"] > 1000 and st["dup"] > 0 and st["shared"] > 0, st
+    # etx_run_tracks leaves etx_run's outputs unchanged
+    p.run(b)
+    ref = p.results(b)
+    for k in ("src", "dst", "score", "labels", "edge_off"):
+        np.testing.assert_array_equal(res[k], ref[k])
+
+
+@pytest.fixture(scope="module")
+def pair_batch():
+    w = synth.C3.with_(pair_fraction=0.15)
+    batch = synth.generate_batch(w, 6, first=40)
+    return w, batch, balanced_heads(w, synth.trained_weights(w), batch, seed=9)
+
+
+def test_uneven_pair_batch_trained_network_triplet_parity(pair_batch):
+    w, batch, heads = pair_batch
+    W = synth.trained_weights(w)
+    p, b, res, tres = run_tracks(w, W, heads, batch)
+    tot = dict(triplets=0, tracks=0, shared=0, kept=0)
+    for i in range(len(batch["hit_off"]) - 1):
+        st = event_triplet_parity(w, W, heads, batch, res, tres, i)
+        for k in tot:
+            tot[k] += st[k]
+    assert tot["triplets"] > 1000 and 0 < tot["kept"] < tot["triplets"] and tot["shared"] > 0, tot
+
+
+def test_full_size_network_triplet_parity():
+    w = synth.C2
+    W = synth.trained_weights(w)
+    batch = synth.generate_batch(w, 1)
+    heads = balanced_heads(w, W, batch, seed=4)
+    p, b, res, tres = run_tracks(w, W, heads, batch)
+    st = event_triplet_parity(w, W, heads, batch, res, tres, 0)
+    assert st["triplets"] > 1000 and 0 < st["kept"] < st["triplets"], st
+
+
+def test_deterministic(pair_batch):
+    w, batch, heads = pair_batch
+    W = synth.trained_weights(w)
+    etx = _etx()
+    p = etx.Pipeline(w, W)
+    p.set_triplets(heads)
+    b = etx.to_device(batch)
+    outs = []
+    for _ in range(2):
+        p.run_tracks_sized(b)
+        t = p.track_results(b)
+        outs.append((t["tri_score"].copy(), t["track_hits"].copy(), t["track_off"].copy()))
+    for x, y in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_bf16_operands_track_building_exact(pair_batch):
+    w, batch, heads = pair_batch
+    W = synth.trained_weights(w)
+    p, b, res, tres = run_tracks(w, W, heads, batch, precision=_etx().ETX_BF16)
+    for i in range(len(batch["hit_off"]) - 1):
+        event_triplet_parity(w, W, heads, batch, res, tres, i, check_scores=False)
+
+
+def test_nothing_kept_gives_no_triplets_and_no_tracks():
+    w = synth.C1.with_(threshold=1.5)
+    W = synth.xavier_weights(w)
+    p, b, res, tres = run_tracks(w, W, synth.xavier_triplets(w), synth.generate_batch(w, 1))
+    assert len(tres["tri_a"]) == 0 and len(tres["tracks"]) == 0
+    assert tres["event_track_off"].tolist() == [0, 0]
+
+
+def test_empty_and_ragged_events():
+    from tests.test_gpu_edge_cases import pack
+    w = synth.C3
+    W = synth.trained_weights(w)
+    heads = synth.xavier_triplets(w, seed=2)
+    evs = [synth.event_slice(synth.generate_batch(w, 1, first=i), 0) for i in (3, 4)]
+    empty = {k: v[:0] for k, v in evs[0].items()}
+    batch = pack([empty, evs[0], empty, evs[1], empty])
+    p, b, res, tres = run_tracks(w, W, heads, batch)
+    for i in range(5):
+        event_triplet_parity(w, W, heads, batch, res, tres, i)
+    eto = tres["event_track_off"]
+    assert eto[1] == eto[0] and eto[3] == eto[2] and eto[5] == eto[4]
+
+
+def test_capacity_errors_report_what_is_needed():
+    etx = _etx()
+    w = synth.C3
+    W = synth.trained_weights(w)
+    heads = synth.xavier_triplets(w, seed=2)
+    batch = synth.generate_batch(w, 3)
+    p = etx.Pipeline(w, W)
+    p.set_triplets(heads)
+    b = etx.to_device(batch)
+    p.run_tracks(b)
+    full = p.track_results(b)
+    n_tri = len(full["tri_a"])
+    n_tracks = len(full["tracks"])
+    n_hits = int(full["track_off"][-1])
+    for caps, slot, need in [(dict(triplet_capacity=n_tri - 1), 1, n_tri),
+                             (dict(track_capacity=n_tracks - 1), 2, n_tracks),
+                             (dict(hit_capacity=n_hits - 1), 3, n_hits)]:
+        p.run_tracks(b, **caps)
+        st = p.track_status()
+        assert st[0] == etx.ETX_ERR_CAPACITY and st[slot] == need, (caps, st)
+    p.run_tracks(b, triplet_capacity=n_tri, track_capacity=n_tracks, hit_capacity=n_hits)
+    exact = p.track_results(b)
+    np.testing.assert_array_equal(exact["track_hits"], full["track_hits"])
+
+
+def test_unsupported_and_invalid_modes():
+    etx = _etx()
+    w = synth.C1
+    W = synth.xavier_weights(w)
+    b = etx.to_device(synth.generate_batch(w, 1))
+    p = etx.Pipeline(w, W)
+    with pytest.raises(etx.EtxError) as ex:          # no triplet parameters
+        p.run_tracks(b)
+    assert ex.value.code == etx.ETX_ERR_INVALID_ARG
+    p.set_triplets(synth.xavier_triplets(w))
+    assert np.array_equal(etx.etx_triplet_get(p.ctx, etx.ETX_TRIPLET_NPARAM(w.gnn_hidden)),
+                          etx.pack_triplets(synth.xavier_triplets(w)))
+    etx.etx_set_precision(p.ctx, etx.ETX_BF16)
+    etx.etx_set_option(p.ctx, etx.ETX_OPT_COMPACT_STATE, 1)
+    with pytest.raises(etx.EtxError) as ex:          # compact state: e_S is not kept in FP32
+        p.run_tracks(b)
+    assert ex.value.code == etx.ETX_ERR_UNSUPPORTED
+    with pytest.raises(etx.EtxError):
+        etx.etx_triplet_set(p.ctx, np.zeros(10, np.float32))
