@@ -886,9 +886,38 @@ static double focal(double z, int y, double alpha, double gamma, double* dz) {
  * (the transpose of a gather by source or target is a sum over that node's
  * edges, and the transpose of the out-/in-sums a gather), then the encoders.
  * Returns the loss. */
+static double gnn_loss_grad(int64_t n, const double* cart, int64_t E, const int32_t* src, const int32_t* dst, int H,
+                            int S, const double* params, const uint8_t* label, int64_t T, const int32_t* ta,
+                            const int32_t* tb, const uint8_t* kind, const uint8_t* tlabel, const double* tparams,
+                            double alpha, double gamma, double* grad, double* tgrad);
+
 double oracle_gnn_focal_loss_grad(int64_t n, const double* cart, int64_t E, const int32_t* src,
                                   const int32_t* dst, int H, int S, const double* params, const uint8_t* label,
                                   double alpha, double gamma, double* grad) {
+  return gnn_loss_grad(n, cart, E, src, dst, H, S, params, label, 0, NULL, NULL, NULL, NULL, NULL, alpha, gamma,
+                       grad, NULL);
+}
+
+/* The loss of eq. gnn-loss with its triplet term: the edge classifier's mean
+ * focal loss plus, for each of the two triplet classifiers (articulations,
+ * kind 0; elbows, kinds 1 and 2), the mean focal loss over its triplets
+ * (ta[t], tb[t]) with labels tlabel; the classifier of a triplet reads
+ * [e_S(ta), e_S(tb)] (the final edge encodings), so its gradient flows back
+ * into the interaction network.  tparams: both classifiers, each W1[2H][H]
+ * b1 W2[H][H] b2 w3[H] b3; tgrad: their gradient in that layout. */
+double oracle_gnn_triplet_loss_grad(int64_t n, const double* cart, int64_t E, const int32_t* src,
+                                    const int32_t* dst, int H, int S, const double* params, const uint8_t* label,
+                                    int64_t T, const int32_t* ta, const int32_t* tb, const uint8_t* kind,
+                                    const uint8_t* tlabel, const double* tparams, double alpha, double gamma,
+                                    double* grad, double* tgrad) {
+  return gnn_loss_grad(n, cart, E, src, dst, H, S, params, label, T, ta, tb, kind, tlabel, tparams, alpha, gamma,
+                       grad, tgrad);
+}
+
+static double gnn_loss_grad(int64_t n, const double* cart, int64_t E, const int32_t* src, const int32_t* dst, int H,
+                            int S, const double* params, const uint8_t* label, int64_t T, const int32_t* ta,
+                            const int32_t* tb, const uint8_t* kind, const uint8_t* tlabel, const double* tparams,
+                            double alpha, double gamma, double* grad, double* tgrad) {
   const int64_t HH = (int64_t)H * H;
   /* parameter offsets in the layout of oracle_gnn */
   const int64_t o_ne1 = 0, o_ne2 = o_ne1 + 3 * H + H, o_ee1 = o_ne2 + HH + H, o_ee2 = o_ee1 + 2 * HH + H;
@@ -988,6 +1017,59 @@ double oracle_gnn_focal_loss_grad(int64_t n, const double* cart, int64_t E, cons
     }
     gw2[H] += dlog[t];
     blk_bwd(&cb, t, dy, grad + o_cls, de + t * H);
+  }
+  /* triplet classifiers on [e_S(ta), e_S(tb)]: forward, focal loss, backward into de */
+  if (tparams) {
+    const int64_t hs = 3 * HH + 3 * H + 1;
+    memset(tgrad, 0, sizeof(double) * 2 * hs);
+    int64_t* rows = (int64_t*)malloc(sizeof(int64_t) * (size_t)(T > 0 ? T : 1));
+    double* y2 = (double*)malloc(sizeof(double) * (size_t)(T > 0 ? T : 1) * H);
+    double* dl = (double*)malloc(sizeof(double) * (size_t)(T > 0 ? T : 1));
+    double* dy1 = (double*)malloc(sizeof(double) * H);
+    double* dx2 = (double*)malloc(sizeof(double) * 2 * H);
+    for (int head = 0; head < 2; ++head) {
+      int64_t nh = 0;
+      for (int64_t t = 0; t < T; ++t)
+        if ((kind[t] == 0) == (head == 0)) rows[nh++] = t;
+      if (nh == 0) continue;
+      const double* hp = tparams + head * hs;
+      double* hg = tgrad + head * hs;
+      const double* w3 = hp + 3 * HH + 2 * H;
+      double* gw3 = hg + 3 * HH + 2 * H;
+      blk_t b1, b2;
+      blk_init(&b1, 2 * H, H, nh, hp);
+      blk_init(&b2, H, H, nh, hp + 2 * HH + H);
+      double lh = 0.0;
+      for (int64_t r = 0; r < nh; ++r) {
+        const int64_t t = rows[r];
+        memcpy(b1.x + r * 2 * H, EK(S, ta[t]), sizeof(double) * H);
+        memcpy(b1.x + r * 2 * H + H, EK(S, tb[t]), sizeof(double) * H);
+        blk_fwd(&b1, r, b2.x + r * H);
+        blk_fwd(&b2, r, y2 + r * H);
+        double z = w3[H];
+        for (int q = 0; q < H; ++q) z += y2[r * H + q] * w3[q];
+        double dz;
+        lh += focal(z, tlabel[t] != 0, alpha, gamma, &dz);
+        dl[r] = dz / (double)nh;
+      }
+      loss += lh / (double)nh;
+      for (int64_t r = 0; r < nh; ++r) {
+        const int64_t t = rows[r];
+        for (int q = 0; q < H; ++q) {
+          gw3[q] += y2[r * H + q] * dl[r];
+          dy[q] = w3[q] * dl[r];
+        }
+        gw3[H] += dl[r];
+        blk_bwd(&b2, r, dy, hg + 2 * HH + H, dy1);
+        blk_bwd(&b1, r, dy1, hg, dx2);
+        for (int q = 0; q < H; ++q) {
+          de[(int64_t)ta[t] * H + q] += dx2[q];
+          de[(int64_t)tb[t] * H + q] += dx2[H + q];
+        }
+      }
+      blk_free(&b1); blk_free(&b2);
+    }
+    free(rows); free(y2); free(dl); free(dy1); free(dx2);
   }
   double* dmo = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * H);
   double* dmi = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * H);

@@ -78,6 +78,9 @@ def lib():
         L.oracle_embed_hinge_loss_grad.restype = dbl
         L.oracle_gnn_focal_loss_grad.argtypes = [i64, P, i64, P, P, i32, i32, P, P, dbl, dbl, P]
         L.oracle_gnn_focal_loss_grad.restype = dbl
+        L.oracle_gnn_triplet_loss_grad.argtypes = [i64, P, i64, P, P, i32, i32, P, P, i64, P, P, P, P, P, dbl, dbl,
+                                                   P, P]
+        L.oracle_gnn_triplet_loss_grad.restype = dbl
         L.oracle_triplets.argtypes = [i64, i64, P, P, P, P, P, P, P, i64]
         L.oracle_triplets.restype = i64
         L.oracle_triplet_head_size.argtypes = [i32]
@@ -429,6 +432,26 @@ def build_tracks(n: int, src, dst, plane, keep, ta, tb, kind, tkeep) -> Dict[str
     assert nt <= tcap
     tracks = [hits[off[k]:off[k + 1]].copy() for k in range(nt)]
     return dict(dup=dup[:E].copy(), comp=comp[:E].copy(), tracks=tracks, c1=c1[:nt].copy(), c2=c2[:nt].copy())
+
+
+def gnn_triplet_loss_grad(cart, src, dst, weights, H: int, S: int, labels, ta, tb, kind, tlabels, heads,
+                          alpha: float = 0.25, gamma: float = 2.0):
+    """eq. gnn-loss with its triplet term: the edge classifier's mean focal
+    loss plus each triplet classifier's mean focal loss over its triplets, and
+    the gradients (network parameters in the layout of ``gnn_param_blocks``;
+    both triplet classifiers in the layout of ``triplet_params``)."""
+    cart = _c(cart, np.float64)
+    src = _c(src, np.int32); dst = _c(dst, np.int32)
+    lab = _c(labels, np.uint8)
+    ta = _c(ta, np.int32); tb = _c(tb, np.int32); kind = _c(kind, np.uint8); tlab = _c(tlabels, np.uint8)
+    params = _flat(gnn_param_blocks(weights))
+    tp = triplet_params(heads)
+    g = np.zeros_like(params)
+    tg = np.zeros_like(tp)
+    loss = lib().oracle_gnn_triplet_loss_grad(len(cart), _p(cart), len(src), _p(src), _p(dst), H, S, _p(params),
+                                              _p(lab), len(ta), _p(ta), _p(tb), _p(kind), _p(tlab), _p(tp),
+                                              float(alpha), float(gamma), _p(g), _p(tg))
+    return loss, g, tg
 
 
 def run_event_triplets(ev: Dict[str, np.ndarray], w, weights, heads) -> Dict[str, np.ndarray]:

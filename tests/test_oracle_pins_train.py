@@ -221,3 +221,134 @@ def test_focal_on_a_generator_event_is_finite_and_matches_oracle_forward():
     ref = F.binary_cross_entropy_with_logits(torch.tensor(r["logit"]), torch.tensor(lab, dtype=torch.float64))
     assert loss == pytest.approx(0.5 * float(ref), rel=1e-10)
     assert np.all(np.isfinite(g))
+
+
+# --------------------------------------------------------------------------
+# eq. gnn-loss with its triplet term (two triplet classifiers on [e_S(a), e_S(b)])
+# --------------------------------------------------------------------------
+
+def _dense_triplet_torch(cart, src, dst, weights, H, S, labels, ta, tb, kind, tlab, heads, alpha, gamma):
+    """The network and both triplet classifiers in torch float64 (dense
+    incidence, every parameter a leaf); each loss term a focal loss built from
+    torch's binary cross-entropy."""
+    T = lambda a: torch.tensor(np.asarray(a), dtype=torch.float64)
+    n, E = len(cart), len(src)
+    Bs = torch.zeros(E, n, dtype=torch.float64); Bs[torch.arange(E), torch.tensor(src, dtype=torch.long)] = 1
+    Bd = torch.zeros(E, n, dtype=torch.float64); Bd[torch.arange(E), torch.tensor(dst, dtype=torch.long)] = 1
+    leaves, tleaves = [], []
+
+    def lin(x, Wb, into):
+        W = T(Wb[0]).requires_grad_(True)
+        b = T(Wb[1]).requires_grad_(True)
+        into.extend([W, b])
+        return x @ W + b
+
+    def blk(x, Wb, into):
+        return torch.relu(F.layer_norm(lin(x, Wb, into), (H,), eps=1e-5))
+
+    def focal(z, y):
+        ce = F.binary_cross_entropy_with_logits(z, y, reduction="none")
+        p = torch.sigmoid(z)
+        pt = p * y + (1 - p) * (1 - y)
+        at = alpha * y + (1 - alpha) * (1 - y)
+        return (at * (1 - pt) ** gamma * ce).mean()
+
+    h = blk(blk(T(cart), weights["node_enc"][0], leaves), weights["node_enc"][1], leaves)
+    e = blk(blk(torch.cat([Bs @ h, Bd @ h], 1), weights["edge_enc"][0], leaves), weights["edge_enc"][1], leaves)
+    for k in range(S):
+        mo, mi = Bs.T @ e, Bd.T @ e
+        x = torch.cat([h, mo, mi], 1)
+        h = h + blk(blk(x, weights[f"node{k}"][0], leaves), weights[f"node{k}"][1], leaves)
+        x = torch.cat([e, Bs @ h, Bd @ h], 1)
+        e = e + blk(blk(x, weights[f"edge{k}"][0], leaves), weights[f"edge{k}"][1], leaves)
+    c = blk(e, weights["cls"][0], leaves)
+    loss = focal(lin(c, weights["cls"][1], leaves)[:, 0], T(labels))
+    ta_t, tb_t = torch.tensor(ta, dtype=torch.long), torch.tensor(tb, dtype=torch.long)
+    for name, sel in (("art", kind == 0), ("elb", kind > 0)):
+        L = heads[name]
+        if not sel.any():
+            # keep the leaf layout: unused classifier parameters get zero gradients
+            for Wb in L:
+                for a in Wb:
+                    tleaves.append(T(a).requires_grad_(True))
+            continue
+        s = torch.tensor(np.nonzero(sel)[0], dtype=torch.long)
+        x = torch.cat([e[ta_t[s]], e[tb_t[s]]], 1)
+        y = blk(blk(x, L[0], tleaves), L[1], tleaves)
+        loss = loss + focal(lin(y, L[2], tleaves)[:, 0], T(tlab)[s])
+    loss.backward()
+    g = np.concatenate([t.grad.numpy().ravel() for t in leaves])
+    tg = np.concatenate([(t.grad.numpy() if t.grad is not None else np.zeros(t.shape)).ravel() for t in tleaves])
+    return float(loss.detach()), g, tg
+
+
+def _triplet_case(seed, H, E=30, n=14, T=40):
+    cart, src, dst, lab = _small_graph(seed, n, E)
+    rng = np.random.default_rng(seed + 100)
+    ta = rng.integers(0, E, T).astype(np.int32)
+    tb = rng.integers(0, E, T).astype(np.int32)
+    kind = rng.integers(0, 3, T).astype(np.uint8)
+    tlab = rng.integers(0, 2, T).astype(np.uint8)
+    heads = {h: [(rng.normal(0, 0.4, (a, b)), rng.normal(0, 0.2, b)) for a, b in [(2 * H, H), (H, H), (H, 1)]]
+             for h in ("art", "elb")}
+    return cart, src, dst, lab, ta, tb, kind, tlab, heads
+
+
+@pytest.mark.parametrize("H,S", [(8, 1), (8, 2), (16, 2)])
+def test_triplet_loss_gradient_matches_torch_autograd(H, S):
+    cart, src, dst, lab, ta, tb, kind, tlab, heads = _triplet_case(H + 3 * S, H)
+    W = _random_gnn_weights(H, S, seed=5 + S)
+    loss, g, tg = O.gnn_triplet_loss_grad(cart, src, dst, W, H, S, lab, ta, tb, kind, tlab, heads, 0.25, 2.0)
+    lt, gt, tgt = _dense_triplet_torch(cart, src, dst, W, H, S, lab, ta, tb, kind, tlab, heads, 0.25, 2.0)
+    assert abs(loss - lt) <= 1e-12 * abs(lt)
+    np.testing.assert_allclose(g, gt, rtol=1e-8, atol=1e-14)
+    np.testing.assert_allclose(tg, tgt, rtol=1e-8, atol=1e-14)
+
+
+def test_triplet_loss_with_one_kind_only_and_without_triplets():
+    H, S = 8, 1
+    cart, src, dst, lab, ta, tb, kind, tlab, heads = _triplet_case(21, H)
+    W = _random_gnn_weights(H, S, seed=2)
+    art = kind == 0
+    loss, g, tg = O.gnn_triplet_loss_grad(cart, src, dst, W, H, S, lab, ta[art], tb[art], kind[art], tlab[art],
+                                          heads)
+    lt, gt, tgt = _dense_triplet_torch(cart, src, dst, W, H, S, lab, ta[art], tb[art], kind[art], tlab[art], heads,
+                                       0.25, 2.0)
+    np.testing.assert_allclose(g, gt, rtol=1e-8, atol=1e-14)
+    np.testing.assert_allclose(tg, tgt, rtol=1e-8, atol=1e-14)
+    hs = len(tg) // 2
+    assert not np.any(tg[hs:]) and np.any(tg[:hs])           # the elbow classifier sees no triplet
+    # no triplets: exactly the edge loss and its gradient
+    z = np.zeros(0, np.int32)
+    l0, g0, tg0 = O.gnn_triplet_loss_grad(cart, src, dst, W, H, S, lab, z, z, z.astype(np.uint8),
+                                          z.astype(np.uint8), heads)
+    le, ge = O.gnn_focal_loss_grad(cart, src, dst, W, H, S, lab)
+    assert l0 == le and np.array_equal(g0, ge) and not np.any(tg0)
+
+
+def test_triplet_head_gradient_matches_central_differences():
+    H, S = 8, 1
+    cart, src, dst, lab, ta, tb, kind, tlab, heads = _triplet_case(33, H)
+    W = _random_gnn_weights(H, S, seed=6)
+    _, _, tg = O.gnn_triplet_loss_grad(cart, src, dst, W, H, S, lab, ta, tb, kind, tlab, heads)
+    flat = O.triplet_params(heads)
+    shapes = [(a.shape, b.shape) for h in ("art", "elb") for a, b in heads[h]]
+
+    def unflat(v):
+        out, o, L = {"art": [], "elb": []}, 0, []
+        for ws, bs in shapes:
+            nw, nb = int(np.prod(ws)), int(np.prod(bs))
+            L.append((v[o:o + nw].reshape(ws), v[o + nw:o + nw + nb]))
+            o += nw + nb
+        out["art"], out["elb"] = L[:3], L[3:]
+        return out
+
+    rng = np.random.default_rng(4)
+    h = 1e-6
+    for i in rng.choice(len(flat), 50, replace=False):
+        vp, vm = flat.copy(), flat.copy()
+        vp[i] += h
+        vm[i] -= h
+        lp = O.gnn_triplet_loss_grad(cart, src, dst, W, H, S, lab, ta, tb, kind, tlab, unflat(vp))[0]
+        lm = O.gnn_triplet_loss_grad(cart, src, dst, W, H, S, lab, ta, tb, kind, tlab, unflat(vm))[0]
+        assert abs((lp - lm) / (2 * h) - tg[i]) <= 2e-6 * max(1e-2, abs(tg[i])), (i, (lp - lm) / (2 * h), tg[i])
