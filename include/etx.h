@@ -319,6 +319,8 @@ typedef struct {
   const int32_t* rnd;        /* [n_hits] one random hit of a particle on the next two planes per query, -1: none */
   const int64_t* rnd_ptr;    /* [n_hits + 1] the random pairs grouped by their second hit: */
   const int32_t* rnd_src;    /*   rnd_src[rnd_ptr[b] .. rnd_ptr[b+1]-1] are the queries q with rnd[q] == b, ascending */
+  const int32_t* particle2;  /* [n_hits] or NULL: the second particle of a hit that two particles share, -1: none */
+  const int32_t* succ2;      /* [n_hits] or NULL: the next hit of that second particle, -1: none */
 } etx_truth;
 /* Copy the context's current weights into the training parameters and clear the moments (allocates them once). */
 etx_status etx_train_begin(etx_ctx* ctx);
@@ -424,6 +426,41 @@ etx_status etx_tracks_workspace_size(const etx_ctx* ctx, int64_t n_events, int64
  * device error of etx_run's stages (out->status) skips the triplet stage. */
 etx_status etx_run_tracks(etx_ctx* ctx, const etx_hits* hits, etx_out* out, etx_tracks* tracks, void* ws,
                           size_t ws_bytes, etx_stream stream);
+
+/* One network step with the triplet term of eq. gnn-loss (thesis ch. 8 "Graph
+ * Neural Network and Classifiers"): the step of etx_train_gnn_step, then the
+ * triplets of the purified graph of the step's own edge scores (score >=
+ * edge_threshold, as in etx_run_tracks), the two triplet classifiers of the
+ * training state on them, and the loss L_edges + L_art + L_elb, each the mean
+ * sigmoid focal loss (alpha, gamma) of its classifier over its items.  A
+ * triplet is genuine when one particle runs through all three hits along its
+ * successor chain (articulation: C = next(A), B = next(C)) or, for an elbow,
+ * when one particle owns all three hits; an edge is genuine when its target
+ * is succ or succ2 of its source.  The triplet classifiers' gradient flows
+ * back through the final edge encodings into the whole network; Adam (lr = 0:
+ * the gradient only) updates the network and both classifiers.  The training
+ * state of the classifiers starts from the context's triplet parameters
+ * (etx_triplet_set) at the first such step after etx_train_begin.
+ * `triplet_capacity` sizes the step's triplet buffers (workspace:
+ * etx_train_triplet_workspace_size); more triplets than that return
+ * ETX_ERR_CAPACITY with *triplets_needed (host, may be NULL) set.  *loss_dev
+ * (device, may be NULL) receives float[3]: L_edges, L_art, L_elb.
+ * Synchronises the stream twice (edge and triplet counts). */
+etx_status etx_train_triplet_workspace_size(const etx_ctx* ctx, int64_t n_events, int64_t n_hits,
+                                            int64_t edge_capacity, int64_t triplet_capacity, size_t* bytes);
+etx_status etx_train_triplet_step(etx_ctx* ctx, const etx_hits* hits, etx_out* out, const etx_truth* truth,
+                                  float alpha, float gamma, float lr, int64_t step, int64_t triplet_capacity,
+                                  int64_t* triplets_needed, float* loss_dev, void* ws, size_t ws_bytes,
+                                  etx_stream stream);
+/* Triplet buffers of that workspace: 0 = float [ETX_TRIPLET_NPARAM(H)] classifier gradient, 1 = uint8 labels,
+ * 2 = int32 first edges, 3 = int32 second edges, 4 = uint8 kinds (the step's triplets, in etx_run_tracks'
+ * order), 5 = int64 [n_events+1] articulation offsets, 6 = int64 [n_events+1] elbow offsets (as in etx_tracks). */
+etx_status etx_train_triplet_view(const etx_ctx* ctx, int64_t n_events, int64_t n_hits, int64_t edge_capacity,
+                                  int64_t triplet_capacity, int32_t which, size_t* offset, size_t* bytes);
+/* Host copy of the triplet classifiers' training state (set = 0) or its replacement (set = 1): the first n
+ * floats of [params, Adam m, Adam v], n <= 3 x ETX_TRIPLET_NPARAM(H).  etx_train_apply also makes the trained
+ * classifiers the context's triplet parameters. */
+etx_status etx_train_triplet_params(etx_ctx* ctx, float* host, int64_t n, int32_t set);
 
 /* Checkpoint of a context: configuration, weight blob, per-tensor scales and
  * calibration flag, prefilter parameters with their Adam moments, and the

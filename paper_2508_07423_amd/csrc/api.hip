@@ -668,6 +668,7 @@ etx_status etx_destroy(etx_ctx* ctx) {
   if (ctx->dev_pf) (void)hipFree(ctx->dev_pf);
   if (ctx->dev_train) (void)hipFree(ctx->dev_train);
   if (ctx->dev_tri) (void)hipFree(ctx->dev_tri);
+  if (ctx->dev_tri_train) (void)hipFree(ctx->dev_tri_train);
   delete ctx;
   return ETX_OK;
 }

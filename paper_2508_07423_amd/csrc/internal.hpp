@@ -75,6 +75,9 @@ struct etx_ctx {
   // triplet classifiers: both heads permuted for the column tiles (device), and as given (host)
   float* dev_tri = nullptr;
   std::vector<float> tri_host;
+  // triplet classifiers in training: params, Adam m, v (FP32, device), allocated at the first triplet step
+  float* dev_tri_train = nullptr;
+  bool tri_train_fresh = false;    // etx_train_begin ran since the classifiers' training state was set
   bool pf_set = false;
   float pf_band_lo = 0.f, pf_band_hi = 1.f;   // validated band of an event's kept fraction
   // tuning
@@ -144,6 +147,11 @@ int tri_head_floats(int H);
 void tri_prepare_head(const float* p, int H, float* out);
 // The triplet stage in three parts (0: triplets of the purified graph, 1: classifier scores, 2: tracks).
 hipError_t launch_triplet_stage(const RunArgs& a, const etx_tracks& T, char* tws, const TriLayout& TL, int part);
+// training: labels of the triplets of part 0, and the triplet rows' input gradients added into dL/de_S
+hipError_t launch_tri_labels(const RunArgs& a, char* tws, const TriLayout& TL, const etx_tracks& T,
+                             const etx_truth& truth, uint8_t* lab);
+hipError_t launch_tri_edge_grad(const RunArgs& a, char* tws, const TriLayout& TL, const etx_tracks& T,
+                                const float* dxa, const float* dxb, float* de);
 
 // launchers (graph.hip)
 hipError_t launch_init_status(const RunArgs& a);

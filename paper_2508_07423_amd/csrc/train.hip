@@ -236,12 +236,13 @@ __global__ void k_cyl(int64_t n, const float* x, const float* y, const float* z,
   }
 }
 
-// an edge is genuine when its target is the source's successor on its particle
+// an edge is genuine when its target is the source's successor on one of its particles
 __global__ void k_edge_labels(int64_t E, const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
-                              const int32_t* __restrict__ succ, uint8_t* __restrict__ lab, const int64_t* status) {
+                              const int32_t* __restrict__ succ, const int32_t* __restrict__ succ2,
+                              uint8_t* __restrict__ lab, const int64_t* status) {
   if (status[0] != 0) return;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < E; t += (int64_t)gridDim.x * blockDim.x)
-    lab[t] = succ[src[t]] == dst[t] ? 1 : 0;
+    lab[t] = (succ[src[t]] == dst[t] || (succ2 && succ2[src[t]] == dst[t])) ? 1 : 0;
 }
 
 // Sigmoid focal loss of every edge (Lin et al.): logit z = c w2 + b2; per-edge
@@ -250,7 +251,7 @@ __global__ __launch_bounds__(256) void k_focal(int64_t E, int H, const float* __
                                                const float* __restrict__ w2, const uint8_t* __restrict__ lab,
                                                float alpha, float gamma, float* __restrict__ dlogit,
                                                float* __restrict__ dc, float* __restrict__ loss_part,
-                                               const int64_t* status) {
+                                               float* __restrict__ score, const int64_t* status) {
   if (status[0] != 0) return;
   __shared__ float part[256];
   float acc = 0.f;
@@ -259,6 +260,7 @@ __global__ __launch_bounds__(256) void k_focal(int64_t E, int H, const float* __
     float z = w2[H];
     for (int q = 0; q < H; ++q) z = fmaf(c[t * H + q], w2[q], z);
     const float p = 1.0f / (1.0f + expf(-z));
+    if (score) score[t] = p;
     const float lp = -(z < 0.f ? -z + log1pf(expf(z)) : log1pf(expf(-z)));     // log p
     const float l1p = -(z > 0.f ? z + log1pf(expf(-z)) : log1pf(expf(z)));     // log (1 - p)
     float l, d;
@@ -539,18 +541,19 @@ hipError_t launch_inputs(int64_t n, const float* x, const float* y, const float*
   return hipGetLastError();
 }
 
-hipError_t launch_edge_labels(int64_t E, const int32_t* src, const int32_t* dst, const int32_t* succ, uint8_t* lab,
-                              const int64_t* status, hipStream_t s, const etx_ctx* c) {
+hipError_t launch_edge_labels(int64_t E, const int32_t* src, const int32_t* dst, const int32_t* succ,
+                              const int32_t* succ2, uint8_t* lab, const int64_t* status, hipStream_t s,
+                              const etx_ctx* c) {
   if (E == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_edge_labels, dim3(flat_grid(E, c)), dim3(256), 0, s, E, src, dst, succ, lab, status);
+  hipLaunchKernelGGL(k_edge_labels, dim3(flat_grid(E, c)), dim3(256), 0, s, E, src, dst, succ, succ2, lab, status);
   return hipGetLastError();
 }
 
 hipError_t launch_focal(int64_t E, int H, const float* cls_out, const float* w2, const uint8_t* lab, float alpha,
                         float gamma, float* dlogit, float* dc, float* loss_part, float* loss_out, int slot,
-                        const int64_t* status, hipStream_t s) {
+                        const int64_t* status, hipStream_t s, float* score) {
   hipLaunchKernelGGL(k_focal, dim3(kTrainLossBlocks), dim3(256), 0, s, E, H, cls_out, w2, lab, alpha, gamma, dlogit,
-                     dc, loss_part, status);
+                     dc, loss_part, score, status);
   hipLaunchKernelGGL(k_sum, dim3(1), dim3(64), 0, s, loss_part, kTrainLossBlocks, loss_out, slot, status);
   return hipGetLastError();
 }

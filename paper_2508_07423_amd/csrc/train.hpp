@@ -100,11 +100,13 @@ hipError_t launch_edge_gather_add(int64_t E, int H, const int32_t* src, const in
                                   const float* B, float* out, const int64_t* status, hipStream_t s, const etx_ctx* c);
 hipError_t launch_inputs(int64_t n, const float* x, const float* y, const float* z, float inv_r, float inv_z,
                          float* cart, float* cyl, const int64_t* status, hipStream_t s, const etx_ctx* c);
-hipError_t launch_edge_labels(int64_t E, const int32_t* src, const int32_t* dst, const int32_t* succ, uint8_t* lab,
-                              const int64_t* status, hipStream_t s, const etx_ctx* c);
+hipError_t launch_edge_labels(int64_t E, const int32_t* src, const int32_t* dst, const int32_t* succ,
+                              const int32_t* succ2, uint8_t* lab, const int64_t* status, hipStream_t s,
+                              const etx_ctx* c);
+// score (may be null) receives sigmoid(z) of every row
 hipError_t launch_focal(int64_t E, int H, const float* cls_out, const float* w2, const uint8_t* lab, float alpha,
                         float gamma, float* dlogit, float* dc, float* loss_part, float* loss_out, int slot,
-                        const int64_t* status, hipStream_t s);
+                        const int64_t* status, hipStream_t s, float* score = nullptr);
 hipError_t launch_adam(int64_t n, float* p, float* m, float* v, const float* g, float lr, int64_t step,
                        const int64_t* status, hipStream_t s, const etx_ctx* c);
 hipError_t launch_hinge(const HingeArgs& A, int D, float* loss_out, hipStream_t s);

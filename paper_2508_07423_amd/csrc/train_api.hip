@@ -97,6 +97,50 @@ TrainLayout train_layout(const etx_ctx* ctx, const WsLayout& L, int64_t n, int64
   return T;
 }
 
+// The triplet part of a network step's workspace (after the TrainLayout).
+struct TripLayout {
+  size_t ta, tb, kind, tscore, art_off, elb_off, tstatus, tri, lab, yh1, y1, rs1, yh2, y2, rs2, dlogit, dc, dz, da,
+      dxa, dxb, tgrad, total;
+  TriLayout TL;
+};
+
+TripLayout trip_layout(const etx_ctx* ctx, size_t base, int64_t n_events, int64_t n, int64_t E, int64_t tcap) {
+  const int64_t H = ctx->cfg.gnn_hidden;
+  TripLayout X{};
+  size_t o = base;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += a256(std::max<size_t>(bytes, 1));
+    return at;
+  };
+  const size_t f = sizeof(float), T = (size_t)tcap;
+  X.ta = take(4 * T);
+  X.tb = take(4 * T);
+  X.kind = take(T);
+  X.tscore = take(f * T);
+  X.art_off = take(8 * (size_t)(n_events + 1));
+  X.elb_off = take(8 * (size_t)(n_events + 1));
+  X.tstatus = take(8 * 4);
+  X.TL = tri_layout(n_events, n, E, tcap, 0);
+  X.tri = take(X.TL.total);
+  X.lab = take(T);
+  X.yh1 = take(f * T * H);
+  X.y1 = take(f * T * H);
+  X.rs1 = take(f * T);
+  X.yh2 = take(f * T * H);
+  X.y2 = take(f * T * H);
+  X.rs2 = take(f * T);
+  X.dlogit = take(f * T);
+  X.dc = take(f * T * H);
+  X.dz = take(f * T * H);
+  X.da = take(f * T * H);
+  X.dxa = take(f * T * H);
+  X.dxb = take(f * T * H);
+  X.tgrad = take(f * ETX_TRIPLET_NPARAM(H));
+  X.total = o;
+  return X;
+}
+
 // offsets (floats) of the parameter blocks in the blob payload
 struct ParamMap {
   int64_t emb[8];           // embedding layer l
@@ -166,6 +210,43 @@ etx_status etx_train_begin(etx_ctx* ctx) {
   if (!ctx->dev_train) HIPCHK(hipMalloc(&ctx->dev_train, sizeof(float) * 3 * n));
   HIPCHK(hipMemcpy(ctx->dev_train, ctx->blob.data() + 32, sizeof(float) * n, hipMemcpyHostToDevice));
   HIPCHK(hipMemset(ctx->dev_train + n, 0, sizeof(float) * 2 * n));
+  ctx->tri_train_fresh = true;
+  return ETX_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// the triplet classifiers' training state, (re)started from the context's
+// triplet parameters after etx_train_begin
+etx_status tri_train_state(etx_ctx* ctx) {
+  const char* what = "triplet training state";
+  if (!ctx->dev_train || ctx->tri_host.empty()) return ETX_ERR_INVALID_ARG;
+  const size_t np = ctx->tri_host.size();
+  if (!ctx->dev_tri_train) HIPCHK(hipMalloc(&ctx->dev_tri_train, sizeof(float) * 3 * np));
+  if (ctx->tri_train_fresh) {
+    HIPCHK(hipMemcpy(ctx->dev_tri_train, ctx->tri_host.data(), sizeof(float) * np, hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(ctx->dev_tri_train + np, 0, sizeof(float) * 2 * np));
+    ctx->tri_train_fresh = false;
+  }
+  return ETX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+etx_status etx_train_triplet_params(etx_ctx* ctx, float* host, int64_t n, int32_t set) {
+  if (!ctx || !host || (set != 0 && set != 1)) return ETX_ERR_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return ETX_ERR_HIP;
+  etx_status st = tri_train_state(ctx);
+  if (st != ETX_OK) return st;
+  const int64_t np = (int64_t)ctx->tri_host.size();
+  if (n < 1 || n > 3 * np) return ETX_ERR_INVALID_ARG;
+  const char* what = "etx_train_triplet_params";
+  HIPCHK(set ? hipMemcpy(ctx->dev_tri_train, host, sizeof(float) * n, hipMemcpyHostToDevice)
+             : hipMemcpy(host, ctx->dev_tri_train, sizeof(float) * n, hipMemcpyDeviceToHost));
   return ETX_OK;
 }
 
@@ -186,7 +267,11 @@ etx_status etx_train_apply(etx_ctx* ctx) {
   if (hipSetDevice(ctx->device) != hipSuccess) return ETX_ERR_HIP;
   std::vector<float> p(blob_floats_of(ctx->cfg));
   HIPCHK(hipMemcpy(p.data(), ctx->dev_train, sizeof(float) * p.size(), hipMemcpyDeviceToHost));
-  return rebuild_weights(ctx, p.data());
+  etx_status st = rebuild_weights(ctx, p.data());
+  if (st != ETX_OK || !ctx->dev_tri_train || ctx->tri_train_fresh) return st;
+  std::vector<float> q(ctx->tri_host.size());
+  HIPCHK(hipMemcpy(q.data(), ctx->dev_tri_train, sizeof(float) * q.size(), hipMemcpyDeviceToHost));
+  return etx_triplet_set(ctx, q.data(), (int64_t)q.size());
 }
 
 etx_status etx_train_workspace_size(const etx_ctx* ctx, int64_t n_events, int64_t n_hits, int64_t edge_capacity,
@@ -194,6 +279,36 @@ etx_status etx_train_workspace_size(const etx_ctx* ctx, int64_t n_events, int64_
   if (!ctx || !bytes || n_events < 0 || n_hits < 0 || edge_capacity < 0) return ETX_ERR_INVALID_ARG;
   const WsLayout L = ws_layout(ctx, n_events, n_hits, edge_capacity);
   *bytes = train_layout(ctx, L, n_hits, edge_capacity).total;
+  return ETX_OK;
+}
+
+etx_status etx_train_triplet_workspace_size(const etx_ctx* ctx, int64_t n_events, int64_t n_hits,
+                                            int64_t edge_capacity, int64_t triplet_capacity, size_t* bytes) {
+  if (!ctx || !bytes || n_events < 0 || n_hits < 0 || edge_capacity < 0 || triplet_capacity < 0)
+    return ETX_ERR_INVALID_ARG;
+  const WsLayout L = ws_layout(ctx, n_events, n_hits, edge_capacity);
+  const TrainLayout T = train_layout(ctx, L, n_hits, edge_capacity);
+  *bytes = trip_layout(ctx, T.total, n_events, n_hits, edge_capacity, triplet_capacity).total;
+  return ETX_OK;
+}
+
+etx_status etx_train_triplet_view(const etx_ctx* ctx, int64_t n_events, int64_t n_hits, int64_t edge_capacity,
+                                  int64_t triplet_capacity, int32_t which, size_t* offset, size_t* bytes) {
+  if (!ctx || !offset || !bytes || triplet_capacity < 0) return ETX_ERR_INVALID_ARG;
+  const WsLayout L = ws_layout(ctx, n_events, n_hits, edge_capacity);
+  const TrainLayout T = train_layout(ctx, L, n_hits, edge_capacity);
+  const TripLayout X = trip_layout(ctx, T.total, n_events, n_hits, edge_capacity, triplet_capacity);
+  const size_t tc = (size_t)triplet_capacity;
+  switch (which) {
+    case 0: *offset = X.tgrad; *bytes = sizeof(float) * ETX_TRIPLET_NPARAM(ctx->cfg.gnn_hidden); break;
+    case 1: *offset = X.lab; *bytes = tc; break;
+    case 2: *offset = X.ta; *bytes = 4 * tc; break;
+    case 3: *offset = X.tb; *bytes = 4 * tc; break;
+    case 4: *offset = X.kind; *bytes = tc; break;
+    case 5: *offset = X.art_off; *bytes = 8 * (size_t)(n_events + 1); break;
+    case 6: *offset = X.elb_off; *bytes = 8 * (size_t)(n_events + 1); break;
+    default: return ETX_ERR_INVALID_ARG;
+  }
   return ETX_OK;
 }
 
@@ -352,12 +467,19 @@ etx_status etx_train_embed_step(etx_ctx* ctx, const etx_hits* hits, etx_out* out
   return ETX_OK;
 }
 
-etx_status etx_train_gnn_step(etx_ctx* ctx, const etx_hits* hits, etx_out* out, const etx_truth* truth, float alpha,
-                              float gamma, float lr, int64_t step, float* loss_dev, void* ws_, size_t ws_bytes,
-                              etx_stream stream) {
-  const char* what = "etx_train_gnn_step";
+}  // extern "C"
+
+namespace {
+
+// One network step; tcap >= 0 adds the triplet term of eq. gnn-loss.
+etx_status gnn_step(etx_ctx* ctx, const etx_hits* hits, etx_out* out, const etx_truth* truth, float alpha,
+                    float gamma, float lr, int64_t step, int64_t tcap, int64_t* needed, float* loss_dev, void* ws_,
+                    size_t ws_bytes, etx_stream stream) {
+  const char* what = tcap >= 0 ? "etx_train_triplet_step" : "etx_train_gnn_step";
   if (!ctx || !hits || !out || !truth || !truth->succ || !ctx->dev_train) return ETX_ERR_INVALID_ARG;
   if (!(alpha >= 0 && alpha <= 1) || !(gamma >= 0) || !(lr >= 0) || step < 1) return ETX_ERR_INVALID_ARG;
+  const bool trip = tcap >= 0;
+  if (trip && (!truth->particle || tcap >= 0x7fffffffLL)) return ETX_ERR_INVALID_ARG;
   const etx_config& c = ctx->cfg;
   WsLayout L;
   etx_status st = check_run(ctx, hits, out, ws_, ws_bytes, &L);
@@ -365,6 +487,13 @@ etx_status etx_train_gnn_step(etx_ctx* ctx, const etx_hits* hits, etx_out* out, 
   const int64_t n = hits->n_hits, cap = out->edge_capacity;
   const TrainLayout T = train_layout(ctx, L, n, cap);
   if (ws_bytes < T.total) return ETX_ERR_INVALID_ARG;
+  TripLayout X{};
+  if (trip) {
+    X = trip_layout(ctx, T.total, hits->n_events, n, cap, tcap);
+    if (ws_bytes < X.total) return ETX_ERR_INVALID_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return ETX_ERR_HIP;
+    if ((st = tri_train_state(ctx)) != ETX_OK) return st;
+  }
   if (hipSetDevice(ctx->device) != hipSuccess) return ETX_ERR_HIP;
   char* ws = static_cast<char*>(ws_);
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -451,7 +580,8 @@ etx_status etx_train_gnn_step(etx_ctx* ctx, const etx_hits* hits, etx_out* out, 
     return launch_wgrad(G, M, grad + goff, s);
   };
   // ---- forward
-  HIPCHK(launch_edge_labels(E, src, dst, truth->succ, reinterpret_cast<uint8_t*>(ws + T.lab), status, s, ctx));
+  HIPCHK(launch_edge_labels(E, src, dst, truth->succ, truth->succ2, reinterpret_cast<uint8_t*>(ws + T.lab), status, s,
+                            ctx));
   HIPCHK(launch_inputs(n, hits->x, hits->y, hits->z, 1.0f / c.r_scale_mm, 1.0f / c.z_scale_mm, F(T.cart), nullptr,
                        status, s, ctx));
   HIPCHK(fwd(n, {seg(F(T.cart), nullptr, 3, 3)}, prm + P.ne1, yhn(0), rsn(0), F(T.y1n), nullptr));
@@ -475,11 +605,84 @@ etx_status etx_train_gnn_step(etx_ctx* ctx, const etx_hits* hits, etx_out* out, 
   const int jc = 2 + 2 * S;
   HIPCHK(fwd(E, {seg(est(S), nullptr, H, H)}, prm + P.cls1, yhe(jc), rse(jc), F(T.cls), nullptr));
   HIPCHK(launch_focal(E, H, F(T.cls), prm + P.cls2, reinterpret_cast<const uint8_t*>(ws + T.lab), alpha, gamma,
-                      F(T.dlogit), F(T.da_e), F(T.lpart), F(T.loss), 0, status, s));
+                      F(T.dlogit), F(T.da_e), F(T.lpart), F(T.loss), 0, status, s, trip ? out->score : nullptr));
+  // ---- triplets of the purified graph of this step's scores, and the two classifiers on them
+  etx_tracks TS{};
+  int64_t nrow[2] = {0, 0};
+  const int64_t hsz = 3 * (int64_t)H * H + 3 * H + 1;
+  float* tprm = ctx->dev_tri_train;
+  auto I32 = [&](size_t off) { return reinterpret_cast<int32_t*>(ws + off); };
+  if (trip) {
+    TS.triplet_capacity = tcap;
+    TS.tri_a = I32(X.ta);
+    TS.tri_b = I32(X.tb);
+    TS.tri_score = F(X.tscore);
+    TS.tri_kind = reinterpret_cast<uint8_t*>(ws + X.kind);
+    TS.art_off = reinterpret_cast<int64_t*>(ws + X.art_off);
+    TS.elb_off = reinterpret_cast<int64_t*>(ws + X.elb_off);
+    TS.status = reinterpret_cast<int64_t*>(ws + X.tstatus);
+    HIPCHK(launch_triplet_stage(a, TS, ws + X.tri, X.TL, 0));
+    int64_t cnt[2];
+    HIPCHK(hipMemcpyAsync(&cnt[0], ws + X.tri + X.TL.art_pos + sizeof(int64_t) * n, sizeof(int64_t),
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&cnt[1], ws + X.tri + X.TL.elb_pos + sizeof(int64_t) * n, sizeof(int64_t),
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (needed) *needed = cnt[0] + cnt[1];
+    if (cnt[0] + cnt[1] > tcap) return ETX_ERR_CAPACITY;
+    nrow[0] = cnt[0];
+    nrow[1] = cnt[1];
+    uint8_t* tlab = reinterpret_cast<uint8_t*>(ws + X.lab);
+    HIPCHK(launch_tri_labels(a, ws + X.tri, X.TL, TS, *truth, tlab));
+    HIPCHK(hipMemsetAsync(F(X.tgrad), 0, sizeof(float) * 2 * hsz, s));
+    HIPCHK(hipMemsetAsync(F(T.loss) + 1, 0, sizeof(float) * 2, s));
+    for (int hd = 0; hd < 2; ++hd) {
+      const int64_t nh = nrow[hd], r0 = hd ? nrow[0] : 0;
+      if (nh == 0) continue;
+      const float* hp = tprm + hd * hsz;
+      HIPCHK(fwd(nh, {seg(est(S), TS.tri_a + r0, H, H), seg(est(S), TS.tri_b + r0, H, H)}, hp, F(X.yh1) + r0 * H,
+                 F(X.rs1) + r0, F(X.y1) + r0 * H, nullptr));
+      HIPCHK(fwd(nh, {seg(F(X.y1) + r0 * H, nullptr, H, H)}, hp + 2 * H * H + H, F(X.yh2) + r0 * H, F(X.rs2) + r0,
+                 F(X.y2) + r0 * H, nullptr));
+      HIPCHK(launch_focal(nh, H, F(X.y2) + r0 * H, hp + 3 * H * H + 2 * H, tlab + r0, alpha, gamma, F(X.dlogit) + r0,
+                          F(X.dc) + r0 * H, F(T.lpart), F(T.loss), 1 + hd, status, s));
+    }
+  }
   // ---- backward
   HIPCHK(wg(E, {seg(F(T.cls), nullptr, H, H)}, F(T.dlogit), 1, P.cls2));
   HIPCHK(bwd(E, F(T.da_e), nullptr, yhe(jc), rse(jc), prm + P.cls1, H, F(T.dz_e), {tout(F(T.de_e), H, H, 0)}));
   HIPCHK(wg(E, {seg(est(S), nullptr, H, H)}, F(T.dz_e), H, P.cls1));
+  if (trip) {
+    auto wgt = [&](int64_t rows, std::initializer_list<TrainSeg> segs, const float* dz, int M, float* gp) {
+      Wgrad G{};
+      G.rows = rows;
+      int i = 0, K = 0;
+      for (const TrainSeg& g : segs) {
+        G.seg[i++] = g;
+        K += g.width;
+      }
+      G.nseg = i;
+      G.K = K;
+      G.dz = dz;
+      G.partial = F(T.part);
+      G.status = status;
+      return launch_wgrad(G, M, gp, s);
+    };
+    for (int hd = 0; hd < 2; ++hd) {
+      const int64_t nh = nrow[hd], r0 = hd ? nrow[0] : 0;
+      if (nh == 0) continue;
+      const float* hp = tprm + hd * hsz;
+      float* hg = F(X.tgrad) + hd * hsz;
+      HIPCHK(wgt(nh, {seg(F(X.y2) + r0 * H, nullptr, H, H)}, F(X.dlogit) + r0, 1, hg + 3 * H * H + 2 * H));
+      HIPCHK(bwd(nh, F(X.dc) + r0 * H, nullptr, F(X.yh2) + r0 * H, F(X.rs2) + r0, hp + 2 * H * H + H, H, F(X.dz),
+                 {tout(F(X.da), H, H, 0)}));
+      HIPCHK(wgt(nh, {seg(F(X.y1) + r0 * H, nullptr, H, H)}, F(X.dz), H, hg + 2 * H * H + H));
+      HIPCHK(bwd(nh, F(X.da), nullptr, F(X.yh1) + r0 * H, F(X.rs1) + r0, hp, 2 * H, F(X.dz),
+                 {tout(F(X.dxa) + r0 * H, H, H, 0), tout(F(X.dxb) + r0 * H, H, H, 0)}));
+      HIPCHK(wgt(nh, {seg(est(S), TS.tri_a + r0, H, H), seg(est(S), TS.tri_b + r0, H, H)}, F(X.dz), H, hg));
+    }
+    HIPCHK(launch_tri_edge_grad(a, ws + X.tri, X.TL, TS, F(X.dxa), F(X.dxb), F(T.de_e)));
+  }
   for (int k = S - 1; k >= 0; --k) {
     float* t1e = F(T.t1e) + k * eH;
     // edge update k
@@ -517,8 +720,30 @@ etx_status etx_train_gnn_step(etx_ctx* ctx, const etx_hits* hits, etx_out* out, 
   const int64_t nb = (int64_t)blob_floats_of(c);
   const int64_t g0 = P.gnn_begin, ng = P.total - P.gnn_begin;
   if (lr > 0) HIPCHK(launch_adam(ng, prm + g0, prm + nb + g0, prm + 2 * nb + g0, grad + g0, lr, step, status, s, ctx));
-  if (loss_dev) HIPCHK(hipMemcpyAsync(loss_dev, F(T.loss), sizeof(float), hipMemcpyDeviceToDevice, s));
+  if (trip && lr > 0)
+    HIPCHK(launch_adam(2 * hsz, tprm, tprm + 2 * hsz, tprm + 4 * hsz, F(X.tgrad), lr, step, status, s, ctx));
+  if (loss_dev)
+    HIPCHK(hipMemcpyAsync(loss_dev, F(T.loss), sizeof(float) * (trip ? 3 : 1), hipMemcpyDeviceToDevice, s));
   return ETX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+etx_status etx_train_gnn_step(etx_ctx* ctx, const etx_hits* hits, etx_out* out, const etx_truth* truth, float alpha,
+                              float gamma, float lr, int64_t step, float* loss_dev, void* ws, size_t ws_bytes,
+                              etx_stream stream) {
+  return gnn_step(ctx, hits, out, truth, alpha, gamma, lr, step, -1, nullptr, loss_dev, ws, ws_bytes, stream);
+}
+
+etx_status etx_train_triplet_step(etx_ctx* ctx, const etx_hits* hits, etx_out* out, const etx_truth* truth,
+                                  float alpha, float gamma, float lr, int64_t step, int64_t triplet_capacity,
+                                  int64_t* triplets_needed, float* loss_dev, void* ws, size_t ws_bytes,
+                                  etx_stream stream) {
+  if (triplet_capacity < 0) return ETX_ERR_INVALID_ARG;
+  return gnn_step(ctx, hits, out, truth, alpha, gamma, lr, step, triplet_capacity, triplets_needed, loss_dev, ws,
+                  ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -678,6 +678,127 @@ __global__ __launch_bounds__(256) void k_track_hits(int64_t n_events, int64_t ca
     for (int64_t u = nt + gtid(); u < cap; u += gstride()) tlen[u] = 0;
 }
 
+// ---------------------------------------------------------------------------
+// training: triplet labels and the triplet classifiers' gradient into the edges
+// ---------------------------------------------------------------------------
+
+struct Truth {
+  const int32_t* particle;
+  const int32_t* particle2;   // may be null
+  const int32_t* succ;
+  const int32_t* succ2;       // may be null
+  __device__ int32_t part(int32_t h, int j) const { return j == 0 ? particle[h] : (particle2 ? particle2[h] : -1); }
+  __device__ bool owns(int32_t h, int32_t p) const { return particle[h] == p || (particle2 && particle2[h] == p); }
+  // the next hit of particle p after hit h (-1: none, or h is not p's)
+  __device__ int32_t next(int32_t h, int32_t p) const {
+    if (particle[h] == p) return succ[h];
+    if (particle2 && particle2[h] == p) return succ2 ? succ2[h] : -1;
+    return -1;
+  }
+};
+
+// genuine: one particle runs A -> C -> B along its successor chain
+// (articulation), or owns all three hits (elbow)
+__global__ __launch_bounds__(256) void k_tri_labels(int64_t n, const int64_t* __restrict__ art_pos,
+                                                    const int64_t* __restrict__ elb_pos,
+                                                    const int32_t* __restrict__ ta, const int32_t* __restrict__ tb,
+                                                    const uint8_t* __restrict__ kind, const int32_t* __restrict__ src,
+                                                    const int32_t* __restrict__ dst, Truth tr,
+                                                    uint8_t* __restrict__ lab, const int64_t* status,
+                                                    const int64_t* tstatus) {
+  if (halted(status, tstatus)) return;
+  const int64_t T = art_pos[n] + elb_pos[n];
+  for (int64_t t = gtid(); t < T; t += gstride()) {
+    const int32_t a = ta[t], b = tb[t];
+    bool g = false;
+    if (kind[t] == 0) {
+      const int32_t A = src[a], C = dst[a], B = dst[b];
+      for (int j = 0; j < 2; ++j) {
+        const int32_t p = tr.part(A, j);
+        if (p >= 0 && tr.next(A, p) == C && tr.next(C, p) == B) g = true;
+      }
+    } else {
+      const bool left = kind[t] == 1;
+      const int32_t C = left ? src[a] : dst[a];
+      const int32_t A = left ? dst[a] : src[a];
+      const int32_t B = left ? dst[b] : src[b];
+      for (int j = 0; j < 2; ++j) {
+        const int32_t p = tr.part(C, j);
+        if (p >= 0 && tr.owns(A, p) && tr.owns(B, p)) g = true;
+      }
+    }
+    lab[t] = g ? 1 : 0;
+  }
+}
+
+// de[d] += the input gradients of every triplet row that reads edge d (dxa
+// where d is the first edge, dxb where it is the second), gathered at the
+// computed positions in a fixed order; H/4 threads per edge, four features each
+template <int H>
+__global__ __launch_bounds__(256) void k_tri_edge_grad(int64_t n, const int64_t* __restrict__ row_ptr,
+                                                       const int64_t* __restrict__ col_ptr,
+                                                       const int32_t* __restrict__ csc,
+                                                       const int32_t* __restrict__ src,
+                                                       const int32_t* __restrict__ dst,
+                                                       const float* __restrict__ score, float thr,
+                                                       const int32_t* __restrict__ deg_in,
+                                                       const int32_t* __restrict__ deg_out,
+                                                       const int64_t* __restrict__ art_pos,
+                                                       const int64_t* __restrict__ elb_pos,
+                                                       const int32_t* __restrict__ ta, const float* __restrict__ dxa,
+                                                       const float* __restrict__ dxb, float* __restrict__ de,
+                                                       const int64_t* status, const int64_t* tstatus) {
+  if (halted(status, tstatus)) return;
+  constexpr int Q = H / 4;
+  const int64_t E = row_ptr[n], n_art = art_pos[n];
+  for (int64_t u = gtid(); u < E * Q; u += gstride()) {
+    const int64_t d = u / Q;
+    const int c4 = (int)(u % Q) * 4;
+    if (!(score[d] >= thr)) continue;
+    const int32_t X = src[d], Y = dst[d];
+    const int64_t bX = deg_out[X], aX = deg_in[X], aY = deg_in[Y], bY = deg_out[Y];
+    int64_t od = 0, id = 0;
+    for (int64_t r = row_ptr[X]; r < d; ++r) od += score[r] >= thr ? 1 : 0;
+    for (int64_t q = col_ptr[Y]; q < col_ptr[Y + 1]; ++q) {
+      if (csc[q] == d) break;
+      id += score[csc[q]] >= thr ? 1 : 0;
+    }
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    auto add = [&](const float* g, int64_t row) {
+      const float4 v = *reinterpret_cast<const float4*>(g + row * H + c4);
+      acc.x += v.x;
+      acc.y += v.y;
+      acc.z += v.z;
+      acc.w += v.w;
+    };
+    for (int64_t o = 0; o < bY; ++o) add(dxa, art_pos[Y] + id * bY + o);          // first edge at C = Y
+    for (int64_t i = 0; i < aX; ++i) add(dxb, art_pos[X] + i * bX + od);          // second edge at C = X
+    if (bX >= 2) {
+      const int64_t base = n_art + elb_pos[X];
+      for (int64_t o = 0; o < bX; ++o) {
+        if (o == od) continue;
+        const int64_t row = base + tri_idx(min(o, od), max(o, od), bX);
+        add(ta[row] == d ? dxa : dxb, row);
+      }
+    }
+    if (aY >= 2) {
+      const int64_t base = n_art + elb_pos[Y] + bY * (bY - 1) / 2;
+      for (int64_t i = 0; i < aY; ++i) {
+        if (i == id) continue;
+        const int64_t row = base + tri_idx(min(i, id), max(i, id), aY);
+        add(ta[row] == d ? dxa : dxb, row);
+      }
+    }
+    float4* out = reinterpret_cast<float4*>(de + d * H + c4);
+    float4 v = *out;
+    v.x += acc.x;
+    v.y += acc.y;
+    v.z += acc.z;
+    v.w += acc.w;
+    *out = v;
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -858,6 +979,36 @@ hipError_t launch_triplet_stage(const RunArgs& a, const etx_tracks& T, char* tws
                      c2, tev, cstart, cedge, src, dst, tlen, T.track_off, T.hit_capacity, T.track_hits, status,
                      tstatus);
 #undef TW
+  return hipGetLastError();
+}
+
+hipError_t launch_tri_labels(const RunArgs& a, char* tws, const TriLayout& TL, const etx_tracks& T,
+                             const etx_truth& truth, uint8_t* lab) {
+  const int64_t n = a.hits.n_hits;
+  const Truth tr{truth.particle, truth.particle2, truth.succ, truth.succ2};
+  hipLaunchKernelGGL(k_tri_labels, dim3(grid_for(T.triplet_capacity, a.ctx->n_cu)), dim3(256), 0, a.stream, n,
+                     reinterpret_cast<const int64_t*>(tws + TL.art_pos), reinterpret_cast<const int64_t*>(tws + TL.elb_pos),
+                     T.tri_a, T.tri_b, T.tri_kind, a.out.src, a.out.dst, tr, lab, a.out.status, T.status);
+  return hipGetLastError();
+}
+
+hipError_t launch_tri_edge_grad(const RunArgs& a, char* tws, const TriLayout& TL, const etx_tracks& T,
+                                const float* dxa, const float* dxb, float* de) {
+  const etx_ctx* ctx = a.ctx;
+  const int64_t n = a.hits.n_hits;
+  const int H = ctx->cfg.gnn_hidden;
+  const int grid = grid_for(a.out.edge_capacity * (H / 4), ctx->n_cu);
+#define ARGS                                                                                                       \
+  n, reinterpret_cast<const int64_t*>(a.ws + a.L.row_ptr), reinterpret_cast<const int64_t*>(a.ws + a.L.col_ptr),   \
+      reinterpret_cast<const int32_t*>(a.ws + a.L.csc), a.out.src, a.out.dst, a.out.score, ctx->cfg.edge_threshold, \
+      reinterpret_cast<const int32_t*>(tws + TL.deg_in), reinterpret_cast<const int32_t*>(tws + TL.deg_out),        \
+      reinterpret_cast<const int64_t*>(tws + TL.art_pos), reinterpret_cast<const int64_t*>(tws + TL.elb_pos),       \
+      T.tri_a, dxa, dxb, de, a.out.status, T.status
+  if (H == 32)
+    hipLaunchKernelGGL(k_tri_edge_grad<32>, dim3(grid), dim3(256), 0, a.stream, ARGS);
+  else
+    hipLaunchKernelGGL(k_tri_edge_grad<64>, dim3(grid), dim3(256), 0, a.stream, ARGS);
+#undef ARGS
   return hipGetLastError();
 }
 

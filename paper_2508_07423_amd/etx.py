@@ -60,7 +60,8 @@ class etx_out(C.Structure):
 
 class etx_truth(C.Structure):
     _fields_ = [("particle", C.c_void_p), ("succ", C.c_void_p), ("pred", C.c_void_p), ("query", C.c_void_p),
-                ("rnd", C.c_void_p), ("rnd_ptr", C.c_void_p), ("rnd_src", C.c_void_p)]
+                ("rnd", C.c_void_p), ("rnd_ptr", C.c_void_p), ("rnd_src", C.c_void_p), ("particle2", C.c_void_p),
+                ("succ2", C.c_void_p)]
 
 
 class etx_tracks(C.Structure):
@@ -122,6 +123,11 @@ def lib():
             "etx_triplet_get": [P, P, i64],
             "etx_tracks_workspace_size": [P, i64, i64, i64, i64, i64, C.POINTER(sz)],
             "etx_run_tracks": [P, C.POINTER(etx_hits), C.POINTER(etx_out), C.POINTER(etx_tracks), P, sz, P],
+            "etx_train_triplet_workspace_size": [P, i64, i64, i64, i64, C.POINTER(sz)],
+            "etx_train_triplet_step": [P, C.POINTER(etx_hits), C.POINTER(etx_out), C.POINTER(etx_truth), C.c_float,
+                                       C.c_float, C.c_float, i64, i64, C.POINTER(i64), P, P, sz, P],
+            "etx_train_triplet_view": [P, i64, i64, i64, i64, i32, C.POINTER(sz), C.POINTER(sz)],
+            "etx_train_triplet_params": [P, P, i64, i32],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -145,7 +151,8 @@ EXPORTED = ["etx_create", "etx_destroy", "etx_weight_blob_size", "etx_workspace_
             "etx_tuning_save", "etx_tuning_load", "etx_prefilter_band", "etx_run_noalloc",
             "etx_train_begin", "etx_train_params", "etx_train_apply", "etx_train_workspace_size", "etx_train_view",
             "etx_train_embed_step", "etx_train_gnn_step", "etx_triplet_set", "etx_triplet_get",
-            "etx_tracks_workspace_size", "etx_run_tracks"]
+            "etx_tracks_workspace_size", "etx_run_tracks", "etx_train_triplet_workspace_size",
+            "etx_train_triplet_step", "etx_train_triplet_view", "etx_train_triplet_params"]
 
 
 class EtxError(RuntimeError):
@@ -364,6 +371,49 @@ def etx_run_tracks(ctx, hits, out, tracks, ws_ptr: int, ws_bytes: int, stream: i
                                 C.c_void_p(stream)), "etx_run_tracks")
 
 
+def etx_train_triplet_workspace_size(ctx, n_events: int, n_hits: int, edge_capacity: int,
+                                     triplet_capacity: int) -> int:
+    b = C.c_size_t()
+    _check(lib().etx_train_triplet_workspace_size(ctx, n_events, n_hits, edge_capacity, triplet_capacity,
+                                                  C.byref(b)), "etx_train_triplet_workspace_size")
+    return b.value
+
+
+def etx_train_triplet_view(ctx, n_events: int, n_hits: int, edge_capacity: int, triplet_capacity: int, which: int):
+    off, nb = C.c_size_t(), C.c_size_t()
+    _check(lib().etx_train_triplet_view(ctx, n_events, n_hits, edge_capacity, triplet_capacity, which,
+                                        C.byref(off), C.byref(nb)), "etx_train_triplet_view")
+    return off.value, nb.value
+
+
+def etx_train_triplet_params(ctx, host: Optional[np.ndarray] = None, n: Optional[int] = None) -> np.ndarray:
+    """The triplet classifiers' training state (params, Adam m, Adam v): read the first n floats, or replace
+    them with ``host``."""
+    if host is not None:
+        h = np.ascontiguousarray(host, np.float32)
+        _check(lib().etx_train_triplet_params(ctx, h.ctypes.data_as(C.c_void_p), h.size, 1),
+               "etx_train_triplet_params")
+        return h
+    out = np.zeros(int(n), np.float32)
+    _check(lib().etx_train_triplet_params(ctx, out.ctypes.data_as(C.c_void_p), out.size, 0),
+           "etx_train_triplet_params")
+    return out
+
+
+def unpack_triplets(p: np.ndarray, H: int) -> Dict:
+    """Inverse of pack_triplets."""
+    out, o = {}, 0
+    for h in ("art", "elb"):
+        out[h] = []
+        for K, M in [(2 * H, H), (H, H), (H, 1)]:
+            W = np.asarray(p[o:o + K * M], np.float32).reshape(K, M).copy()
+            o += K * M
+            b = np.asarray(p[o:o + M], np.float32).copy()
+            o += M
+            out[h].append((W, b))
+    return out
+
+
 def pack_triplets(heads: Dict) -> np.ndarray:
     """The triplet classifiers' parameters in the etx.h order (articulation head, then elbow head; each
     W1[2H][H] b1 W2[H][H] b2 W3[H][1] b3)."""
@@ -544,7 +594,7 @@ class Pipeline:
     def allocate_tracks(self, b: Batch, triplet_capacity: int, track_capacity: int, hit_capacity: int):
         import torch
         caps = (triplet_capacity, track_capacity, hit_capacity, b.n_events)
-        if getattr(self, "_tshape", None) != caps:
+        if getattr(self, "_trk_shape", None) != caps:
             dev = torch.device("cuda", self.device)
             T = max(triplet_capacity, 1)
             self.tri_a = torch.empty(T, dtype=torch.int32, device=dev)
@@ -557,7 +607,7 @@ class Pipeline:
             self.track_off = torch.empty(track_capacity + 1, dtype=torch.int64, device=dev)
             self.track_hits = torch.empty(max(hit_capacity, 1), dtype=torch.int32, device=dev)
             self.tstatus = torch.zeros(4, dtype=torch.int64, device=dev)
-            self._tshape = caps
+            self._trk_shape = caps
         return etx_tracks(triplet_capacity, self.tri_a.data_ptr(), self.tri_b.data_ptr(), self.tri_score.data_ptr(),
                           self.tri_kind.data_ptr(), self.art_off.data_ptr(), self.elb_off.data_ptr(), track_capacity,
                           self.event_track_off.data_ptr(), self.track_off.data_ptr(), hit_capacity,
@@ -588,7 +638,7 @@ class Pipeline:
             st = self.track_status()
             if st[0] != ETX_ERR_CAPACITY:
                 break
-            tc, kc, hc = self._tshape[:3]
+            tc, kc, hc = self._trk_shape[:3]
             caps = dict(triplet_capacity=max(tc, int(st[1])), track_capacity=max(kc, int(st[2])),
                         hit_capacity=max(hc, int(st[3])), edge_capacity=caps.get("edge_capacity"))
             self.run_tracks(b, stream=stream, **caps)

@@ -111,3 +111,82 @@ def batch_metrics(labels: np.ndarray, batch: Dict[str, np.ndarray], events: Sequ
                 hit_purity=purity_sum / max(n_matched, 1),
                 hit_efficiency=hit_eff_sum / max(n_matched, 1),
                 tracks=n_tracks, reconstructible=int(reco_able.sum()))
+
+
+def tracks_from_labels(labels: np.ndarray, batch: Dict[str, np.ndarray]):
+    """Component labels as a track list: (tracks, event_track_off), each track
+    the ascending global hit indices of one label of one event."""
+    ho = np.asarray(batch["hit_off"], np.int64)
+    lab = np.asarray(labels, np.int64)
+    ev = np.repeat(np.arange(len(ho) - 1), np.diff(ho))
+    order = np.lexsort((np.arange(len(lab)), lab, ev))
+    key = (ev[order] << 32) | (lab[order] & 0xFFFFFFFF)
+    cut = np.nonzero(np.diff(key))[0] + 1
+    groups = np.split(order, cut) if len(order) else []
+    tev = ev[order][np.r_[0, cut]] if len(order) else np.zeros(0, np.int64)
+    eto = np.searchsorted(tev, np.arange(len(ho)), side="left").astype(np.int64)
+    return [np.sort(g) for g in groups], eto
+
+
+def track_list_metrics(tracks, event_track_off, batch: Dict[str, np.ndarray], min_hits: int = 3,
+                       match_frac: float = 0.7) -> Dict[str, float]:
+    """The metrics of ``batch_metrics`` for a list of tracks that may share
+    hits (the triplet stage's output), with hits that two particles share
+    (``particle2``) counted for both.  Also the efficiency over the particles
+    that share hits with another (pair_efficiency)."""
+    ho = np.asarray(batch["hit_off"], np.int64)
+    part = np.asarray(batch["particle"], np.int64)
+    part2 = np.asarray(batch.get("particle2", np.full(len(part), -1)), np.int64)
+    plane = np.asarray(batch["plane"], np.int64)
+    ev = np.repeat(np.arange(len(ho) - 1, dtype=np.int64), np.diff(ho))
+    # memberships (hit, particle key)
+    mh = np.r_[np.nonzero(part >= 0)[0], np.nonzero(part2 >= 0)[0]]
+    mp = np.r_[part[part >= 0], part2[part2 >= 0]]
+    mkey = (ev[mh] << 32) | mp
+    pu, pinv = np.unique(mkey, return_inverse=True)
+    pcount = np.bincount(pinv, minlength=len(pu))
+    planes_of = np.bincount(np.unique(pinv * 64 + plane[mh]) // 64, minlength=len(pu))
+    reco_able = planes_of >= min_hits
+    shared_p = np.zeros(len(pu), bool)
+    sh = np.nonzero(part2 >= 0)[0]
+    if len(sh):
+        shared_p[np.searchsorted(pu, (ev[sh] << 32) | part[sh])] = True
+        shared_p[np.searchsorted(pu, (ev[sh] << 32) | part2[sh])] = True
+    # tracks of >= min_hits hits
+    lens = np.array([len(t) for t in tracks], np.int64)
+    is_track = lens >= min_hits
+    n_tracks = int(is_track.sum())
+    hits = np.concatenate([t for t in tracks]) if len(tracks) else np.zeros(0, np.int64)
+    tid = np.repeat(np.arange(len(tracks), dtype=np.int64), lens)
+    # (track, particle) pairs through every membership of every hit
+    first = np.full(len(part), -1, np.int64)
+    second = np.full(len(part), -1, np.int64)
+    m1 = part >= 0
+    first[m1] = np.searchsorted(pu, (ev[m1] << 32) | part[m1])
+    m2 = part2 >= 0
+    second[m2] = np.searchsorted(pu, (ev[m2] << 32) | part2[m2])
+    pt = np.r_[tid, tid]
+    pp = np.r_[first[hits], second[hits]]
+    ok = (pp >= 0) & is_track[pt]
+    npu = max(len(pu), 1)
+    pairs, pc = np.unique(pt[ok] * npu + pp[ok], return_counts=True)
+    ptrack, ppart = pairs // npu, pairs % npu
+    order = np.lexsort((ppart, -pc, ptrack))
+    head = np.ones(len(order), bool)
+    head[1:] = ptrack[order][1:] != ptrack[order][:-1]
+    best = order[head]
+    bt, bp, bn = ptrack[best], ppart[best], pc[best]
+    good = ~(bn < match_frac * lens[bt])
+    bt, bp, bn = bt[good], bp[good], bn[good]
+    matched = np.unique(bp)
+    n_matched = len(bt)
+    n_fake = n_tracks - n_matched
+    reco = np.zeros(len(pu), bool)
+    reco[matched] = True
+    ra = reco_able & shared_p
+    return dict(efficiency=float((reco & reco_able).sum() / max(int(reco_able.sum()), 1)),
+                pair_efficiency=float((reco & ra).sum() / max(int(ra.sum()), 1)),
+                ghost_rate=n_fake / max(n_tracks, 1),
+                clone_rate=(n_matched - len(matched)) / max(n_tracks, 1),
+                hit_purity=float(np.sum(bn / lens[bt]) / max(n_matched, 1)),
+                tracks=n_tracks, reconstructible=int(reco_able.sum()), pair_reconstructible=int(ra.sum()))

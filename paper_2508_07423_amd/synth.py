@@ -99,7 +99,11 @@ C4 = C2.with_(cid=4, name="c4")
 # Learned prefilter: the c3 workload; training events use a disjoint seed space.
 C5 = C3.with_(cid=5, name="c5")
 
-WORKLOADS: Dict[str, Workload] = {w.name: w for w in (C1, C2, C3, C4, C5)}
+# Triplet stage: the c3 workload with conversion pairs (a tenth of the tracks
+# gets a partner that shares its first one to three hits).
+C6 = C3.with_(cid=6, name="c6", pair_fraction=0.1)
+
+WORKLOADS: Dict[str, Workload] = {w.name: w for w in (C1, C2, C3, C4, C5, C6)}
 
 
 def _n_tracks(w: Workload, rng: np.random.Generator) -> int:
@@ -328,5 +332,5 @@ TRAINED_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights"
 def trained_weights(w: Workload) -> Dict[str, List[Tuple[np.ndarray, np.ndarray]]]:
     """The committed trained weight set of a workload's network, trained on the GPU by the library
     (``python -m paper_2508_07423_amd.train --workload <name> --out <file>``)."""
-    name = {"c1": "c3", "c3": "c3", "c5": "c3", "c2": "c2", "c4": "c2"}[w.name]
+    name = {"c1": "c3", "c3": "c3", "c5": "c3", "c2": "c2", "c4": "c2", "c6": "c3"}[w.name]
     return load_weights(os.path.join(TRAINED_DIR, f"{name}_trained.npz"))

@@ -70,8 +70,20 @@ def truth_arrays(batch: Dict[str, np.ndarray], w, rng: np.random.Generator) -> D
     rnd_src = qs[order]
     counts = np.bincount(rnd[qs], minlength=n)
     rnd_ptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    # hits two particles share (conversion pairs): the second particle's successor of each such hit
+    particle2 = batch.get("particle2", np.full(n, -1, np.int32)).astype(np.int32)
+    succ2 = np.full(n, -1, np.int32)
+    for h in np.nonzero(particle2 >= 0)[0]:
+        e = int(np.searchsorted(ho, h, side="right")) - 1
+        a, b = int(ho[e]), int(ho[e + 1])
+        q = particle2[h]
+        chain = np.nonzero((particle[a:b] == q) | (particle2[a:b] == q))[0] + a
+        chain = chain[np.argsort(z[chain], kind="stable")]
+        k = int(np.nonzero(chain == h)[0][0])
+        if k + 1 < len(chain) and plane[chain[k + 1]] > plane[h]:
+            succ2[h] = chain[k + 1]
     return dict(particle=particle, succ=succ, pred=pred, query=query, rnd=rnd, rnd_ptr=rnd_ptr,
-                rnd_src=rnd_src.astype(np.int32))
+                rnd_src=rnd_src.astype(np.int32), particle2=particle2, succ2=succ2)
 
 
 def truth_to_device(t: Dict[str, np.ndarray], device="cuda"):
@@ -80,7 +92,9 @@ def truth_to_device(t: Dict[str, np.ndarray], device="cuda"):
     if d["rnd_src"].numel() == 0:
         d["rnd_src"] = torch.zeros(1, dtype=torch.int32, device=device)
     s = etx.etx_truth(d["particle"].data_ptr(), d["succ"].data_ptr(), d["pred"].data_ptr(), d["query"].data_ptr(),
-                      d["rnd"].data_ptr(), d["rnd_ptr"].data_ptr(), d["rnd_src"].data_ptr())
+                      d["rnd"].data_ptr(), d["rnd_ptr"].data_ptr(), d["rnd_src"].data_ptr(),
+                      d["particle2"].data_ptr() if "particle2" in d else None,
+                      d["succ2"].data_ptr() if "succ2" in d else None)
     return s, d
 
 
@@ -129,6 +143,45 @@ class Trainer(etx.Pipeline):
                                                  etx.C.c_void_p(self.tws_ptr), self.tws_bytes,
                                                  etx.C.c_void_p(s.cuda_stream)), "etx_train_gnn_step")
         return self._loss
+
+    def triplet_step(self, b, truth, alpha: float, gamma: float, lr: float, step: int, stream=None):
+        """One network step with the triplet term of eq. gnn-loss; returns the device float[3] losses (edges,
+        articulations, elbows).  The triplet buffers grow when a step needs more."""
+        import torch
+        out = self.allocate_train(b)
+        if not hasattr(self, "_tcap"):
+            self._tcap = 4 * b.n_hits + 1024
+        if not hasattr(self, "_loss3"):
+            self._loss3 = torch.zeros(3, dtype=torch.float32, device=torch.device("cuda", self.device))
+        s = torch.cuda.current_stream(self.device) if stream is None else stream
+        for _ in range(4):
+            need = etx.etx_train_triplet_workspace_size(self.ctx, b.n_events, b.n_hits, self.cap, self._tcap)
+            if self.tws_bytes < need:
+                self.tws = None
+                self.tws = torch.empty(need + 256, dtype=torch.uint8, device=torch.device("cuda", self.device))
+                self.tws_ptr = (self.tws.data_ptr() + 255) & ~255
+                self.tws_bytes = need
+            needed = etx.C.c_int64(0)
+            code = etx.lib().etx_train_triplet_step(self.ctx, etx.C.byref(self.hits_struct(b)), etx.C.byref(out),
+                                                    etx.C.byref(truth), alpha, gamma, lr, step, self._tcap,
+                                                    etx.C.byref(needed), etx.C.c_void_p(self._loss3.data_ptr()),
+                                                    etx.C.c_void_p(self.tws_ptr), self.tws_bytes,
+                                                    etx.C.c_void_p(s.cuda_stream))
+            if code != etx.ETX_ERR_CAPACITY:
+                etx._check(code, "etx_train_triplet_step")
+                return self._loss3
+            self._tcap = int(needed.value * 1.25) + 1024
+        raise etx.EtxError(etx.ETX_ERR_CAPACITY, "etx_train_triplet_step")
+
+    def triplet_view(self, b, which: int, dtype):
+        off, nbytes = etx.etx_train_triplet_view(self.ctx, b.n_events, b.n_hits, self.cap, self._tcap, which)
+        base = self.tws_ptr - self.tws.data_ptr()
+        return self.tws[base + off: base + off + nbytes].view(dtype)
+
+    def triplet_heads(self) -> Dict:
+        H = self.w.gnn_hidden
+        p = etx.etx_train_triplet_params(self.ctx, n=etx.ETX_TRIPLET_NPARAM(H))
+        return etx.unpack_triplets(p, H)
 
     def iview(self, b, which: int, dtype):
         """An inference buffer (etx_workspace_view) of the training workspace."""
@@ -219,6 +272,41 @@ def train(w, n_events: int = 200, epochs_emb: int = 6, epochs_gnn: int = 6, lr_e
     return dict(weights=weights, history=history, seconds=time.time() - t0)
 
 
+def train_triplets(w, weights: Dict, n_events: int = 200, epochs: int = 6, lr: float = 1e-3, seed: int = 5,
+                   heads: Optional[Dict] = None, seed_space: Optional[int] = None,
+                   log: Callable[[str], None] = print, device: int = 0) -> Dict:
+    """The triplet term of eq. gnn-loss on the GPU: starting from a trained
+    embedding and network (``weights``) and Xavier triplet classifiers, train
+    the network and both classifiers on L_edges + L_art + L_elb, one event per
+    step, on generator events of ``w`` (with conversion pairs when
+    w.pair_fraction > 0).  Returns the network weights, the classifiers and
+    the loss history."""
+    import torch
+    ss = 3000 + w.cid if seed_space is None else seed_space
+    tr = Trainer(w, weights, device=device)
+    tr.set_triplets(synth.xavier_triplets(w, seed) if heads is None else heads)
+    etx.etx_train_begin(tr.ctx)
+    rng = np.random.default_rng(seed)
+    events = [synth.generate_batch(w, 1, first=i, seed_space=ss) for i in range(n_events)]
+    dev = [(etx.to_device(ev, f"cuda:{device}"), truth_to_device(truth_arrays(ev, w, rng), f"cuda:{device}"))
+           for ev in events]
+    t0 = time.time()
+    step = 0
+    history = []
+    for ep in range(epochs):
+        tot = np.zeros(3)
+        for b, (ts, _) in dev:
+            step += 1
+            tot += tr.triplet_step(b, ts, 0.25, 2.0, lr, step).cpu().numpy()
+        history.append((tot / len(dev)).tolist())
+        log(f"[train] triplet epoch {ep} losses edges {tot[0] / len(dev):.5f} articulations {tot[1] / len(dev):.5f} "
+            f"elbows {tot[2] / len(dev):.5f} ({time.time() - t0:.1f} s)")
+    out = dict(weights=tr.weights(), heads=tr.triplet_heads(), history=history, seconds=time.time() - t0)
+    tr.close()
+    torch.cuda.synchronize()
+    return out
+
+
 def save(weights: Dict, path: str) -> None:
     flat = {}
     for k, v in weights.items():
@@ -238,8 +326,18 @@ if __name__ == "__main__":
     ap.add_argument("--epochs-emb", type=int, default=6)
     ap.add_argument("--epochs-gnn", type=int, default=6)
     ap.add_argument("--out", required=True)
+    ap.add_argument("--triplets", action="store_true",
+                    help="train the triplet term from the workload's trained weights; --out receives the network, "
+                         "--out-triplets the classifiers")
+    ap.add_argument("--epochs-tri", type=int, default=6)
+    ap.add_argument("--out-triplets")
     a = ap.parse_args()
     wl = synth.WORKLOADS[a.workload]
-    r = train(wl, a.events, a.epochs_emb, a.epochs_gnn, log=lambda s: print(s, flush=True))
-    save(r["weights"], a.out)
+    if a.triplets:
+        r = train_triplets(wl, synth.trained_weights(wl), a.events, a.epochs_tri, log=lambda s: print(s, flush=True))
+        save(r["weights"], a.out)
+        save(r["heads"], a.out_triplets)
+    else:
+        r = train(wl, a.events, a.epochs_emb, a.epochs_gnn, log=lambda s: print(s, flush=True))
+        save(r["weights"], a.out)
     print(a.out, f"{r['seconds']:.1f} s")

@@ -1,5 +1,6 @@
 """Tracking metrics (thesis ch. 7 definitions) on hand-built events with known truth."""
 import numpy as np
+import pytest
 
 from paper_2508_07423_amd import evaluate as E
 
@@ -78,3 +79,33 @@ def test_batch_metrics_equals_the_per_event_definition():
         t2["reconstructed"] += mm["reconstructed"]
     assert ms["reconstructible"] == t2["reconstructible"]
     assert np.isclose(ms["efficiency"], t2["reconstructed"] / max(t2["reconstructible"], 1))
+
+
+def test_track_list_metrics_equal_batch_metrics_without_shared_hits():
+    from paper_2508_07423_amd import synth
+    w = synth.C3
+    batch = synth.generate_batch(w, 6)
+    rng = np.random.default_rng(2)
+    # a noisy partition: true particles, some merged, some split, noise spread around
+    labels = batch["particle"].astype(np.int64).copy()
+    noise = labels < 0
+    labels[noise] = rng.integers(0, 40, noise.sum())
+    labels[rng.uniform(size=len(labels)) < 0.05] = 7
+    labels = labels + (np.repeat(np.arange(6), np.diff(batch["hit_off"])) << 20)
+    tracks, eto = E.tracks_from_labels(labels, batch)
+    m1 = E.track_list_metrics(tracks, eto, batch)
+    m0 = E.batch_metrics(labels, batch)
+    for k in ("efficiency", "ghost_rate", "clone_rate", "hit_purity", "tracks", "reconstructible"):
+        assert m1[k] == pytest.approx(m0[k], abs=1e-12), k
+
+
+def test_track_list_metrics_count_shared_hits_for_both_particles():
+    # particles 0 and 1 share hits 0, 1 (planes 0, 1); 0 continues on 2, 3, particle 1 on 4, 5
+    batch = dict(hit_off=np.array([0, 6]), particle=np.array([0, 0, 0, 0, 1, 1]),
+                 particle2=np.array([1, 1, -1, -1, -1, -1]), plane=np.array([0, 1, 2, 3, 2, 3]))
+    both = [np.array([0, 1, 2, 3]), np.array([0, 1, 4, 5])]
+    m = E.track_list_metrics(both, np.array([0, 2]), batch)
+    assert m["efficiency"] == 1.0 and m["pair_efficiency"] == 1.0 and m["ghost_rate"] == 0.0
+    merged = [np.arange(6)]             # 4 of 6 hits from either particle: below 70 %, a ghost
+    m = E.track_list_metrics(merged, np.array([0, 1]), batch)
+    assert m["efficiency"] == 0.0 and m["ghost_rate"] == 1.0 and m["tracks"] == 1
