@@ -76,6 +76,9 @@ def parse():
     ap.add_argument("--north-star", type=int, default=None,
                     help="add the uneven-batch and prefilter comparison (default: on for the c2 headline)")
     ap.add_argument("--ns-steps", type=int, default=10, help="timed passes of each north-star leg")
+    ap.add_argument("--triplets-only", type=int, default=0,
+                    help="1: only the conversion-pair comparison (components against the triplet stage), "
+                         "printed as one JSON line")
     return ap.parse_args()
 
 
@@ -374,6 +377,8 @@ def north_star(args, stream):
         r["kept_fraction"] = round(r["edges"] / max(base["edges"], 1), 4)
         r["delta_efficiency_vs_fp32_unpruned"] = round(r["efficiency"] - base["efficiency"], 5)
         r["speedup_vs_fp32_unpruned"] = round(r["events_per_s"] / base["events_per_s"], 3)
+    del batch5
+    res["c6"] = triplet_legs(args, stream)
     res["c5"] = dict(workload=f"c5: {w5.n_events} events as c3, trained weights, learned prefilter "
                               f"6-32-32-1, hip graph, autotuned per leg",
                      prefilter=dict(train_events=args.pf_train_events, train_steps=tr["steps"],
@@ -383,6 +388,107 @@ def north_star(args, stream):
                                     fallback_band=[round(x, 4) for x in sel["band"]]),
                      legs=legs)
     return res
+
+
+def timed_track_passes(p, b, stream, steps, warmup, caps):
+    """timed_passes for etx_run_tracks (eager) with fixed capacities."""
+    import torch
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            p.run_tracks(b, stream=stream, **caps)
+        torch.cuda.synchronize()
+        marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        t0 = time.perf_counter()
+        marks[0].record(stream)
+        for k in range(steps):
+            p.run_tracks(b, stream=stream, **caps)
+            marks[k + 1].record(stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    med = sorted(marks[k].elapsed_time(marks[k + 1]) for k in range(steps))[steps // 2]
+    return b.n_events * steps / (t1 - t0), (t1 - t0) / steps * 1e3, med
+
+
+def triplet_legs(args, stream):
+    """Conversion-pair batch (c6): the plain pipeline's components (the c3
+    network) against the triplet stage's tracks (the network and triplet
+    classifiers trained together on the GPU), events/s and track metrics with
+    shared hits counted for both particles; stage times of the triplet stage
+    from a separate instrumented run, and the triplet classifiers' roofline."""
+    import torch
+    from paper_2508_07423_amd import etx, evaluate, synth
+    w = synth.WORKLOADS["c6"]
+    steps = args.ns_steps
+    t0 = time.perf_counter()
+    batch = synth.generate_batch(w, w.n_events)
+    log(f"[bench] c6: {w.n_events} events, {int(batch['hit_off'][-1])} hits, "
+        f"{int((batch['particle2'] >= 0).sum())} shared (generated in {time.perf_counter() - t0:.1f} s)")
+    b = etx.to_device(batch)
+    out = {}
+    # plain pipeline: components of the kept graph
+    p = etx.Pipeline(w, synth.trained_weights(synth.WORKLOADS["c3"]))
+    tuned = autotune(etx, p, b, stream, args.autotune_log)
+    etx.etx_set_option(p.ctx, etx.ETX_OPT_USE_GRAPH, 1)
+    eps, ms, med = timed_passes(p, b, stream, steps, 2)
+    res = p.results(b)
+    m = evaluate.track_list_metrics(*evaluate.tracks_from_labels(res["labels"], batch), batch)
+    out["components"] = dict(events_per_s=round(eps, 1), ms_per_pass=round(ms, 3), ms_per_pass_median=round(med, 3),
+                             steps=steps, schedule=tuned, **{k: round(v, 5) if isinstance(v, float) else v
+                                                            for k, v in m.items()})
+    log(f"[bench] c6 components: {eps:.0f} events/s ({ms:.2f} ms per pass), efficiency {m['efficiency']:.4f}, "
+        f"pair efficiency {m['pair_efficiency']:.4f}")
+    p.close()
+    # triplet stage
+    p = etx.Pipeline(w, synth.trained_weights(w))
+    p.set_triplets(synth.trained_triplets(w))
+    tuned = autotune(etx, p, b, stream, args.autotune_log)
+    with torch.cuda.stream(stream):
+        p.run_tracks_sized(b, stream=stream)
+    tc, kc, hc = p._trk_shape[:3]
+    caps = dict(triplet_capacity=tc, track_capacity=kc, hit_capacity=hc)
+    eps, ms, med = timed_track_passes(p, b, stream, steps, 2, caps)
+    tres = p.track_results(b)
+    res = p.results(b)
+    m = evaluate.track_list_metrics(tres["tracks"], tres["event_track_off"], batch)
+    n_tri = int(tres["elb_off"][-1])
+    n_art = int(tres["art_off"][-1])
+    # instrumented passes: stage times
+    etx.etx_set_option(p.ctx, etx.ETX_OPT_PROFILE, 1)
+    etx.etx_profile_reset(p.ctx)
+    n_prof = 3
+    with torch.cuda.stream(stream):
+        for _ in range(n_prof):
+            p.run_tracks(b, stream=stream, **caps)
+    torch.cuda.synchronize()
+    prof = etx.etx_profile_read(p.ctx)
+    etx.etx_set_option(p.ctx, etx.ETX_OPT_PROFILE, 0)
+    stage_ms = {k: round(v[0] / n_prof, 3) for k, v in prof.items() if v[1] > 0}
+    H = w.gnn_hidden
+    ms_score = prof["triplet_score"][0] / prof["triplet_score"][1]          # both classifiers' launches of a pass
+    flops = 6 * H * H * n_tri                                              # 2 x (2H x H + H x H) on the matrix cores
+    nbytes = (2 * 4 * H + 12) * n_tri                                      # two gathered rows, the pair, the score
+    out["triplets"] = dict(
+        events_per_s=round(eps, 1), ms_per_pass=round(ms, 3), ms_per_pass_median=round(med, 3), steps=steps,
+        schedule=tuned, triplets=n_tri, articulations=n_art, track_list=len(tres["tracks"]),
+        edges=int(res["edge_off"][-1]), stage_ms=stage_ms,
+        classifier_roofline=dict(kernel="tri_score", bound="mfma", ms_per_pass=round(ms_score, 4),
+                                 achieved=round(flops / ms_score / 1e9, 2), peak=PEAK_TFLOPS["f32"], unit="TFLOP/s",
+                                 frac=round(flops / ms_score / 1e9 / PEAK_TFLOPS["f32"], 4),
+                                 per_unit=f"{6 * H * H} flop/triplet (MFMA)",
+                                 hbm_frac=round(nbytes / ms_score / 1e6 / PEAK_HBM_GBS, 4)),
+        **{k: round(v, 5) if isinstance(v, float) else v for k, v in m.items()})
+    log(f"[bench] c6 triplets: {eps:.0f} events/s ({ms:.2f} ms per pass), efficiency {m['efficiency']:.4f}, "
+        f"pair efficiency {m['pair_efficiency']:.4f}; {n_tri} triplets, stages {stage_ms}")
+    p.close()
+    c, t = out["components"], out["triplets"]
+    out["workload"] = (f"c6: {w.n_events} events as c3 with conversion pairs (a tenth of the tracks shares its first "
+                       f"1-3 hits with a partner), eager triplet stage after an autotuned network")
+    out["delta_efficiency_triplets_vs_components"] = round(t["efficiency"] - c["efficiency"], 5)
+    out["delta_pair_efficiency"] = round(t["pair_efficiency"] - c["pair_efficiency"], 5)
+    out["throughput_ratio"] = round(t["events_per_s"] / c["events_per_s"], 3)
+    del b
+    torch.cuda.empty_cache()
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -404,6 +510,10 @@ def main():
     import torch
     from paper_2508_07423_amd import etx, synth
 
+    if args.triplets_only:
+        stream = torch.cuda.Stream()
+        print(json.dumps(dict(c6=triplet_legs(args, stream))), flush=True)
+        return
     w = synth.WORKLOADS[args.workload]
     n_events = args.events or w.n_events
     precs = {"fp32": etx.ETX_FP32, "bf16": etx.ETX_BF16, "fp8": etx.ETX_FP8_E4M3, "int8": etx.ETX_INT8}

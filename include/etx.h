@@ -406,7 +406,8 @@ typedef struct {             /* device pointers, caller-owned, written by etx_ru
   int64_t* elb_off;          /* [n_events+1] its elbows: elb_off[e] .. elb_off[e+1]-1 (after all articulations) */
   int64_t track_capacity;    /* tracks */
   int64_t* event_track_off;  /* [n_events+1] event e's tracks: event_track_off[e] .. event_track_off[e+1]-1 */
-  int64_t* track_off;        /* [track_capacity+1] track t's hits: track_hits[track_off[t] .. track_off[t+1]-1] */
+  int64_t* track_off;        /* [track_capacity+1] track t's hits: track_hits[track_off[t] .. track_off[t+1]-1]
+                                (entries 0 .. n_tracks are written, n_tracks = event_track_off[n_events]) */
   int64_t hit_capacity;      /* length of track_hits */
   int32_t* track_hits;       /* global hit indices, ascending within a track */
   int64_t* status;           /* [4] status[0] = etx_status of the stage (ETX_ERR_CAPACITY when a capacity is too

@@ -96,7 +96,7 @@ __global__ __launch_bounds__(256) void k_scan_sum(const T* __restrict__ in, int6
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(256) void k_scan_part(int64_t* __restrict__ part, int64_t nb, int64_t* __restrict__ total) {
+__device__ inline void k_scan_part_body(int64_t* __restrict__ part, int64_t nb, int64_t* __restrict__ total) {
   int64_t carry = 0;
   for (int64_t c0 = 0; c0 < nb; c0 += kScanTile) {
     const int64_t i0 = c0 + 4 * threadIdx.x;
@@ -118,6 +118,10 @@ __global__ __launch_bounds__(256) void k_scan_part(int64_t* __restrict__ part, i
   if (threadIdx.x == 0) *total = carry;
 }
 
+__global__ __launch_bounds__(256) void k_scan_part(int64_t* __restrict__ part, int64_t nb, int64_t* __restrict__ total) {
+  k_scan_part_body(part, nb, total);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_scan_apply(const T* __restrict__ in, int64_t n, const int64_t* __restrict__ part,
                                                     int64_t* __restrict__ out) {
@@ -135,6 +139,62 @@ __global__ __launch_bounds__(256) void k_scan_apply(const T* __restrict__ in, in
     if (base + k < n) out[base + k] = run;
     run += v[k];
   }
+}
+
+// The same scan over a length known on the device only (min(*n_ptr, n_max),
+// n_max the buffers' capacity): a fixed grid walks the tiles, so no block is
+// launched for the unused tail of a capacity.
+template <typename T>
+__global__ __launch_bounds__(256) void k_dscan_sum(const T* __restrict__ in, const int64_t* __restrict__ n_ptr,
+                                                   int64_t n_max, int64_t* __restrict__ part) {
+  const int64_t n = min(*n_ptr, n_max), tiles = (n + kScanTile - 1) / kScanTile;
+  for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int64_t base = tile * kScanTile + 4 * threadIdx.x;
+    int64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s += base + k < n ? (int64_t)in[base + k] : 0;
+    int64_t tot;
+    (void)block_excl_scan(s, &tot);
+    if (threadIdx.x == 0) part[tile] = tot;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_dscan_part(int64_t* __restrict__ part, const int64_t* __restrict__ n_ptr,
+                                                    int64_t n_max, int64_t* __restrict__ out) {
+  const int64_t n = min(*n_ptr, n_max);
+  k_scan_part_body(part, (n + kScanTile - 1) / kScanTile, out + n);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_dscan_apply(const T* __restrict__ in, const int64_t* __restrict__ n_ptr,
+                                                     int64_t n_max, const int64_t* __restrict__ part,
+                                                     int64_t* __restrict__ out) {
+  const int64_t n = min(*n_ptr, n_max), tiles = (n + kScanTile - 1) / kScanTile;
+  for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int64_t base = tile * kScanTile + 4 * threadIdx.x;
+    int64_t v[4], s = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] = base + k < n ? (int64_t)in[base + k] : 0;
+      s += v[k];
+    }
+    int64_t tot;
+    int64_t run = part[tile] + block_excl_scan(s, &tot);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (base + k < n) out[base + k] = run;
+      run += v[k];
+    }
+  }
+}
+
+template <typename T>
+hipError_t dscan(const T* in, const int64_t* n_ptr, int64_t n_max, int64_t* out, int64_t* part, int grid,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_dscan_sum<T>, dim3(grid), dim3(256), 0, s, in, n_ptr, n_max, part);
+  hipLaunchKernelGGL(k_dscan_part, dim3(1), dim3(256), 0, s, part, n_ptr, n_max, out);
+  hipLaunchKernelGGL(k_dscan_apply<T>, dim3(grid), dim3(256), 0, s, in, n_ptr, n_max, part, out);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -335,11 +395,15 @@ __global__ __launch_bounds__(256) void k_tri_dup(int64_t n, const int64_t* __res
                                                  const int32_t* __restrict__ deg_out,
                                                  const int64_t* __restrict__ art_pos,
                                                  const int64_t* __restrict__ elb_pos, const float* __restrict__ ts,
-                                                 uint8_t* __restrict__ dup, const int64_t* status,
-                                                 const int64_t* tstatus) {
+                                                 uint8_t* __restrict__ dup, int32_t* __restrict__ par,
+                                                 uint8_t* __restrict__ touched, int32_t* __restrict__ ccount,
+                                                 const int64_t* status, const int64_t* tstatus) {
   if (halted(status, tstatus)) return;
   const int64_t E = row_ptr[n], n_art = art_pos[n];
   for (int64_t d = gtid(); d < E; d += gstride()) {
+    par[d] = (int32_t)d;                 // the union-find starts from singletons
+    touched[d] = 0;
+    ccount[d] = 0;
     bool left = false, right = false;
     if (score[d] >= thr) {
       const int32_t X = src[d], Y = dst[d];
@@ -447,17 +511,6 @@ __device__ inline void g_unite(int32_t* par, int32_t u, int32_t v) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_uf_init(int64_t cap, int32_t* __restrict__ par, uint8_t* __restrict__ touched,
-                                                 int32_t* __restrict__ ccount, const int64_t* status,
-                                                 const int64_t* tstatus) {
-  if (halted(status, tstatus)) return;
-  for (int64_t e = gtid(); e < cap; e += gstride()) {
-    par[e] = (int32_t)e;
-    touched[e] = 0;
-    ccount[e] = 0;
-  }
-}
-
 __global__ __launch_bounds__(256) void k_uf_unite(int64_t n, const int64_t* __restrict__ art_pos,
                                                   const int32_t* __restrict__ ta, const int32_t* __restrict__ tb,
                                                   const uint8_t* __restrict__ lstate, int32_t* par,
@@ -468,15 +521,23 @@ __global__ __launch_bounds__(256) void k_uf_unite(int64_t n, const int64_t* __re
     if (lstate[t] == 1) g_unite(par, ta[t], tb[t]);
 }
 
+// component names (the roots are final once every link is united), and the
+// edge count of every component
 __global__ __launch_bounds__(256) void k_uf_find(int64_t n, const int64_t* __restrict__ row_ptr,
                                                  const float* __restrict__ score, float thr,
                                                  const uint8_t* __restrict__ dup, int32_t* par,
-                                                 int32_t* __restrict__ comp, const int64_t* status,
-                                                 const int64_t* tstatus) {
+                                                 int32_t* __restrict__ comp, int32_t* __restrict__ ccount,
+                                                 const int64_t* status, const int64_t* tstatus) {
   if (halted(status, tstatus)) return;
   const int64_t E = row_ptr[n];
-  for (int64_t e = gtid(); e < E; e += gstride())
-    comp[e] = (score[e] >= thr && !dup[e]) ? g_find(par, (int32_t)e) : -1;
+  for (int64_t e = gtid(); e < E; e += gstride()) {
+    int32_t c = -1;
+    if (score[e] >= thr && !dup[e]) {
+      c = g_find(par, (int32_t)e);
+      atomicAdd(ccount + c, 1);
+    }
+    comp[e] = c;
+  }
 }
 
 // step 3a: components that a shared link touches
@@ -578,17 +639,8 @@ __global__ __launch_bounds__(256) void k_track_fill(int64_t n_events, const int6
       });
 }
 
-// component edge lists: counts, then placement (the order inside a list is
-// free: a track's hits are sorted afterwards)
-__global__ __launch_bounds__(256) void k_comp_count(int64_t n, const int64_t* __restrict__ row_ptr,
-                                                    const int32_t* __restrict__ comp, int32_t* __restrict__ ccount,
-                                                    const int64_t* status, const int64_t* tstatus) {
-  if (halted(status, tstatus)) return;
-  const int64_t E = row_ptr[n];
-  for (int64_t e = gtid(); e < E; e += gstride())
-    if (comp[e] >= 0) atomicAdd(ccount + comp[e], 1);
-}
-
+// component edge lists: placement after the counts of k_uf_find (the order inside
+// a list is free: a track's hits are sorted afterwards)
 __global__ __launch_bounds__(256) void k_comp_place(int64_t n, const int64_t* __restrict__ row_ptr,
                                                     const int32_t* __restrict__ comp, int32_t* __restrict__ ccount,
                                                     const int64_t* __restrict__ cstart, int32_t* __restrict__ cedge,
@@ -601,10 +653,11 @@ __global__ __launch_bounds__(256) void k_comp_place(int64_t n, const int64_t* __
   }
 }
 
-// step 4: the hits of each track, one wave per track through an LDS bitmap of
-// its event's hits.  WRITE = false: hit counts (zeros past the last track);
+// step 4: the hits of each track, 16 lanes per track (four tracks per wave)
+// through an LDS bitmap of its event's hits.  WRITE = false: hit counts;
 // true: the hits, ascending, at track_off.
 constexpr int kBitmapWords = ETX_MAX_EVENT_HITS / 32;
+constexpr int kTrackLanes = 16;
 
 template <bool WRITE>
 __global__ __launch_bounds__(256) void k_track_hits(int64_t n_events, int64_t cap, const int64_t* __restrict__ hit_off,
@@ -620,62 +673,76 @@ __global__ __launch_bounds__(256) void k_track_hits(int64_t n_events, int64_t ca
   if (halted(status, tstatus)) return;
   const int64_t nt = ev_off[n_events];
   if (nt > cap) return;
-  if (WRITE && track_off[cap] > hit_cap) {
+  if (WRITE && track_off[nt] > hit_cap) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-      tstatus[3] = track_off[cap];
+      tstatus[3] = track_off[nt];
       tstatus[0] = ETX_ERR_CAPACITY;
     }
     return;
   }
-  __shared__ uint32_t bitmap[4][kBitmapWords];
+  constexpr int G = kTrackLanes, PER_WAVE = 64 / G;
+  __shared__ uint32_t bitmap[4 * PER_WAVE][kBitmapWords];
   const int lane = lane_id(), wave = wave_id();
-  uint32_t* bm = bitmap[wave];
-  const int64_t waves = (int64_t)gridDim.x * 4;
-  int64_t t = (int64_t)blockIdx.x * 4 + wave;
-  for (; t < nt; t += waves) {
-    const int ev = tev[t];
-    const int64_t a = hit_off[ev];
-    const int words = (int)((hit_off[ev + 1] - a + 31) / 32);
-    for (int w = lane; w < words; w += 64) bm[w] = 0;
+  const int sub = lane / G, l = lane % G;
+  uint32_t* bm = bitmap[wave * PER_WAVE + sub];
+  const int64_t stride = (int64_t)gridDim.x * 4 * PER_WAVE;
+  for (int64_t base = ((int64_t)blockIdx.x * 4 + wave) * PER_WAVE; base < nt; base += stride) {
+    const int64_t t = base + sub;
+    const bool valid = t < nt;
+    int ev = 0, words = 0;
+    int64_t a = 0;
+    if (valid) {
+      ev = tev[t];
+      a = hit_off[ev];
+      words = (int)((hit_off[ev + 1] - a + 31) / 32);
+      for (int w = l; w < words; w += G) bm[w] = 0;
+    }
     wave_sync();
-    const int32_t cs[2] = {c1[t], c2[t]};
-    for (int k = 0; k < 2; ++k) {
-      const int32_t c = cs[k];
-      if (c < 0 || (k == 1 && c == cs[0])) continue;
-      for (int64_t q = cstart[c] + lane; q < cstart[c + 1]; q += 64) {
-        const int32_t e = cedge[q];
-        const int s = (int)(src[e] - a), d = (int)(dst[e] - a);
-        atomicOr(bm + (s >> 5), 1u << (s & 31));
-        atomicOr(bm + (d >> 5), 1u << (d & 31));
+    if (valid) {
+      const int32_t cs[2] = {c1[t], c2[t]};
+      for (int k = 0; k < 2; ++k) {
+        const int32_t c = cs[k];
+        if (c < 0 || (k == 1 && c == cs[0])) continue;
+        for (int64_t q = cstart[c] + l; q < cstart[c + 1]; q += G) {
+          const int32_t e = cedge[q];
+          const int s = (int)(src[e] - a), d = (int)(dst[e] - a);
+          atomicOr(bm + (s >> 5), 1u << (s & 31));
+          atomicOr(bm + (d >> 5), 1u << (d & 31));
+        }
       }
     }
     wave_sync();
-    if (!WRITE) {
-      int cnt = 0;
-      for (int w = lane; w < words; w += 64) cnt += __popc(bm[w]);
+    if (valid) {
+      if (!WRITE) {
+        int cnt = 0;
+        for (int w = l; w < words; w += G) cnt += __popc(bm[w]);
 #pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o);
-      if (lane == 0) tlen[t] = cnt;
-    } else {
-      int64_t run = track_off[t];
-      for (int w0 = 0; w0 < words; w0 += 64) {
-        const int w = w0 + lane;
-        uint32_t m = w < words ? bm[w] : 0u;
-        const int pc = __popc(m);
-        int64_t inc = wave_incl_scan(pc);
-        int64_t at = run + inc - pc;
-        while (m) {
-          const int bit = __ffs(m) - 1;
-          hits[at++] = (int32_t)(a + 32 * w + bit);
-          m &= m - 1;
+        for (int o = G / 2; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, G);
+        if (l == 0) tlen[t] = cnt;
+      } else {
+        int64_t run = track_off[t];
+        for (int w0 = 0; w0 < words; w0 += G) {
+          const int w = w0 + l;
+          uint32_t m = w < words ? bm[w] : 0u;
+          const int pc = __popc(m);
+          int inc = pc;
+#pragma unroll
+          for (int d = 1; d < G; d <<= 1) {
+            const int u = __shfl_up(inc, d, G);
+            if (l >= d) inc += u;
+          }
+          int64_t at = run + inc - pc;
+          while (m) {
+            const int bit = __ffs(m) - 1;
+            hits[at++] = (int32_t)(a + 32 * w + bit);
+            m &= m - 1;
+          }
+          run += __shfl(inc, G - 1, G);   // a round adds at most G x 32 hits
         }
-        run += __shfl((int)inc, 63);   // a round adds at most 64 x 32 hits
       }
     }
     wave_sync();   // every lane is done with the bitmap before the next track clears it
   }
-  if (!WRITE)
-    for (int64_t u = nt + gtid(); u < cap; u += gstride()) tlen[u] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -951,13 +1018,13 @@ hipError_t launch_triplet_stage(const RunArgs& a, const etx_tracks& T, char* tws
   int32_t* tlen = TW(tlen, int32_t);
   const int64_t tcap = T.track_capacity;
   hipLaunchKernelGGL(k_tri_dup, dim3(ge), dim3(256), 0, s, n, row_ptr, col_ptr, csc, src, dst, plane, score, thr,
-                     deg_in, deg_out, art_pos, elb_pos, T.tri_score, dup, status, tstatus);
+                     deg_in, deg_out, art_pos, elb_pos, T.tri_score, dup, par, touched, ccount, status, tstatus);
   hipLaunchKernelGGL(k_tri_links, dim3(gn), dim3(256), 0, s, n, deg_in, deg_out, art_pos, T.tri_a, T.tri_b,
                      T.tri_score, thr, dup, lstate, status, tstatus);
-  hipLaunchKernelGGL(k_uf_init, dim3(ge), dim3(256), 0, s, cap, par, touched, ccount, status, tstatus);
   hipLaunchKernelGGL(k_uf_unite, dim3(ge), dim3(256), 0, s, n, art_pos, T.tri_a, T.tri_b, lstate, par, status,
                      tstatus);
-  hipLaunchKernelGGL(k_uf_find, dim3(ge), dim3(256), 0, s, n, row_ptr, score, thr, dup, par, comp, status, tstatus);
+  hipLaunchKernelGGL(k_uf_find, dim3(ge), dim3(256), 0, s, n, row_ptr, score, thr, dup, par, comp, ccount, status,
+                     tstatus);
   hipLaunchKernelGGL(k_touch, dim3(ge), dim3(256), 0, s, n, art_pos, T.tri_a, T.tri_b, lstate, comp, touched, status,
                      tstatus);
   if (ne > 0)
@@ -967,14 +1034,14 @@ hipError_t launch_triplet_stage(const RunArgs& a, const etx_tracks& T, char* tws
   if (ne > 0)
     hipLaunchKernelGGL(k_track_fill, dim3((unsigned)ne), dim3(256), 0, s, ne, a.hits.hit_off, row_ptr, T.art_off,
                        T.tri_a, T.tri_b, comp, touched, lstate, T.event_track_off, tcap, c1, c2, tev, status, tstatus);
-  hipLaunchKernelGGL(k_comp_count, dim3(ge), dim3(256), 0, s, n, row_ptr, comp, ccount, status, tstatus);
-  if ((err = scan<int32_t>(ccount, cap, cstart, part_buf, s)) != hipSuccess) return err;
+  const int gs = ctx->n_cu * 4;
+  if ((err = dscan<int32_t>(ccount, row_ptr + n, cap, cstart, part_buf, gs, s)) != hipSuccess) return err;
   hipLaunchKernelGGL(k_comp_place, dim3(ge), dim3(256), 0, s, n, row_ptr, comp, ccount, cstart, cedge, status, tstatus);
-  const int gt = grid_for(tcap * 64 / 4, ctx->n_cu);   // a wave per track
+  const int gt = grid_for(tcap * kTrackLanes / 4, ctx->n_cu);   // 16 lanes per track
   hipLaunchKernelGGL(k_track_hits<false>, dim3(gt), dim3(256), 0, s, ne, tcap, a.hits.hit_off, T.event_track_off, c1,
                      c2, tev, cstart, cedge, src, dst, tlen, T.track_off, T.hit_capacity, T.track_hits, status,
                      tstatus);
-  if ((err = scan<int32_t>(tlen, tcap, T.track_off, part_buf, s)) != hipSuccess) return err;
+  if ((err = dscan<int32_t>(tlen, T.event_track_off + ne, tcap, T.track_off, part_buf, gs, s)) != hipSuccess) return err;
   hipLaunchKernelGGL(k_track_hits<true>, dim3(gt), dim3(256), 0, s, ne, tcap, a.hits.hit_off, T.event_track_off, c1,
                      c2, tev, cstart, cedge, src, dst, tlen, T.track_off, T.hit_capacity, T.track_hits, status,
                      tstatus);

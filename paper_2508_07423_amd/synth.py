@@ -185,44 +185,41 @@ def _add_pairs(w: Workload, index: int, seed_space: Optional[int], x, y, z, part
     its own efficiency and smearing.  Draws from a stream of its own, so the
     rest of the event is the one drawn without pairs."""
     rng = np.random.default_rng(np.random.SeedSequence([w.cid if seed_space is None else seed_space, index, 77]))
-    nt = mask.shape[0]
-    xs, ys, zs, ps, pls = [x], [y], [z], [part], [plane]
+    nt, P = mask.shape
+    u = rng.uniform(0.0, 1.0, nt)
+    s = rng.integers(w.pair_shared[0], w.pair_shared[1] + 1, nt)
+    ang = rng.uniform(w.pair_angle[0], w.pair_angle[1], nt)
+    psi = rng.uniform(0.0, 2.0 * np.pi, nt)
+    eff = rng.uniform(0.0, 1.0, (nt, P)) < w.hit_efficiency
+    sx = rng.normal(0.0, w.smear_xy, (nt, P))
+    sy = rng.normal(0.0, w.smear_xy, (nt, P))
+    counts = np.bincount(ti, minlength=nt)                 # hits of each track (ti ascending, planes ascending)
+    starts = np.concatenate([[0], np.cumsum(counts)[:-1]])
+    t = np.nonzero((u < w.pair_fraction) & (counts >= s + 2))[0]
+    last = starts[t] + s[t] - 1                            # the parent's last shared hit
+    end = starts[t] + counts[t] - 1                        # the parent's last hit
+    z0 = zp[pi[last]]
+    span = np.maximum(zp[pi[end]] - z0, 1e-9)
+    tx = (x[end] - x[last]) / span + ang[t] * np.cos(psi[t])
+    ty = (y[end] - y[last]) / span + ang[t] * np.sin(psi[t])
+    dz = zp[None, :] - z0[:, None]
+    later = (dz > 0.0) & (zp[None, :] - vz[t][:, None] > 0.0) & eff[t]
+    nx = x[last][:, None] + tx[:, None] * dz + sx[t]
+    ny = y[last][:, None] + ty[:, None] * dz + sy[t]
+    if w.acceptance is not None:
+        rr = np.hypot(nx, ny)
+        later &= (rr >= w.acceptance[0]) & (rr <= w.acceptance[1])
+    has = later.any(1)
+    t, last, s_t, later, nx, ny = t[has], last[has], s[t][has], later[has], nx[has], ny[has]
+    ids = nt + np.arange(len(t), dtype=np.int32)
     p2 = part2.copy()
-    next_id = nt
-    for t in range(nt):
-        hit_idx = np.nonzero(ti == t)[0]                 # the parent's hits, plane order
-        u = rng.uniform()
-        s = int(rng.integers(w.pair_shared[0], w.pair_shared[1] + 1))
-        ang = rng.uniform(w.pair_angle[0], w.pair_angle[1])
-        psi = rng.uniform(0.0, 2.0 * np.pi)
-        eff = rng.uniform(0.0, 1.0, len(zp)) < w.hit_efficiency
-        sx = rng.normal(0.0, w.smear_xy, len(zp))
-        sy = rng.normal(0.0, w.smear_xy, len(zp))
-        if u >= w.pair_fraction or len(hit_idx) < s + 2:
-            continue
-        shared = hit_idx[:s]
-        last = shared[-1]
-        z0 = zp[pi[last]]
-        later = np.nonzero((zp > z0) & (zp - vz[t] > 0.0) & eff)[0]
-        # the parent's line at the later planes (without its smearing), turned about the last shared hit
-        tx_t = (x[hit_idx[-1]] - x[last]) / max(zp[pi[hit_idx[-1]]] - z0, 1e-9)
-        ty_t = (y[hit_idx[-1]] - y[last]) / max(zp[pi[hit_idx[-1]]] - z0, 1e-9)
-        dz = zp[later] - z0
-        nx = x[last] + (tx_t + ang * np.cos(psi)) * dz + sx[later]
-        ny = y[last] + (ty_t + ang * np.sin(psi)) * dz + sy[later]
-        if w.acceptance is not None:
-            rr = np.hypot(nx, ny)
-            ok = (rr >= w.acceptance[0]) & (rr <= w.acceptance[1])
-            later, nx, ny = later[ok], nx[ok], ny[ok]
-        if len(later) < 1:
-            continue
-        p2[shared] = next_id
-        xs.append(nx); ys.append(ny); zs.append(zp[later])
-        ps.append(np.full(len(later), next_id, np.int32)); pls.append(later.astype(np.int32))
-        next_id += 1
-    return (np.concatenate(xs), np.concatenate(ys), np.concatenate(zs), np.concatenate(ps).astype(np.int32),
-            np.concatenate(pls).astype(np.int32),
-            np.concatenate([p2, np.full(sum(len(a) for a in xs[1:]), -1, np.int32)]))
+    shared = np.repeat(last - s_t + 1, s_t) + (np.arange(int(s_t.sum())) - np.repeat(np.cumsum(s_t) - s_t, s_t))
+    p2[shared] = np.repeat(ids, s_t)
+    r, c = np.nonzero(later)
+    n_new = len(r)
+    return (np.concatenate([x, nx[r, c]]), np.concatenate([y, ny[r, c]]), np.concatenate([z, zp[c]]),
+            np.concatenate([part, ids[r]]).astype(np.int32), np.concatenate([plane, c.astype(np.int32)]),
+            np.concatenate([p2, np.full(n_new, -1, np.int32)]))
 
 
 def generate_batch(w: Workload, n_events: Optional[int] = None, first: int = 0,
@@ -332,5 +329,13 @@ TRAINED_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights"
 def trained_weights(w: Workload) -> Dict[str, List[Tuple[np.ndarray, np.ndarray]]]:
     """The committed trained weight set of a workload's network, trained on the GPU by the library
     (``python -m paper_2508_07423_amd.train --workload <name> --out <file>``)."""
-    name = {"c1": "c3", "c3": "c3", "c5": "c3", "c2": "c2", "c4": "c2", "c6": "c3"}[w.name]
+    name = {"c1": "c3", "c3": "c3", "c5": "c3", "c2": "c2", "c4": "c2", "c6": "c6"}[w.name]
     return load_weights(os.path.join(TRAINED_DIR, f"{name}_trained.npz"))
+
+
+def trained_triplets(w: Workload) -> Dict[str, List[Tuple[np.ndarray, np.ndarray]]]:
+    """The committed triplet classifiers ("art", "elb"), trained on the GPU by the library together with the
+    network of ``trained_weights(C6)`` (``python -m paper_2508_07423_amd.train --workload c6 --triplets ...``)."""
+    if w.gnn_hidden != C6.gnn_hidden:
+        raise ValueError("trained triplet classifiers exist for the hidden size of the c6 network only")
+    return load_weights(os.path.join(TRAINED_DIR, "c6_triplets.npz"))
