@@ -18,6 +18,10 @@
  *   connected components of the kept graph; the label of a hit is the
  *     smallest global hit index in its component     ch. 9 "WCC Implementation"
  *
+ * etx_run_tracks adds the triplet stage of the full method (triplets of the
+ * kept graph, triplet classifiers, tracks that may share hits; ch. 8
+ * "Triplet Building" and "Track Building"), documented at its declaration.
+ *
  * Conventions
  *  - Every entry point returns an etx_status; nothing throws across the ABI.
  *  - "device" pointers are HIP device memory on the context's device; the

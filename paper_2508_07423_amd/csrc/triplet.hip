@@ -141,13 +141,19 @@ __global__ __launch_bounds__(256) void k_scan_apply(const T* __restrict__ in, in
   }
 }
 
-// The same scan over a length known on the device only (min(*n_ptr, n_max),
-// n_max the buffers' capacity): a fixed grid walks the tiles, so no block is
-// launched for the unused tail of a capacity.
+// The same scan over a length known on the device only, clamped to [0, n_max]
+// (n_max the buffers' capacity): a fixed grid walks the tiles, so no block is
+// launched for the unused tail of a capacity.  Skipped, like every kernel of
+// the stage, once a status word holds an error: the length may then never
+// have been written.
+__device__ inline int64_t dscan_len(const int64_t* n_ptr, int64_t n_max) { return max((int64_t)0, min(*n_ptr, n_max)); }
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_dscan_sum(const T* __restrict__ in, const int64_t* __restrict__ n_ptr,
-                                                   int64_t n_max, int64_t* __restrict__ part) {
-  const int64_t n = min(*n_ptr, n_max), tiles = (n + kScanTile - 1) / kScanTile;
+                                                   int64_t n_max, int64_t* __restrict__ part, const int64_t* status,
+                                                   const int64_t* tstatus) {
+  if (halted(status, tstatus)) return;
+  const int64_t n = dscan_len(n_ptr, n_max), tiles = (n + kScanTile - 1) / kScanTile;
   for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     const int64_t base = tile * kScanTile + 4 * threadIdx.x;
     int64_t s = 0;
@@ -160,16 +166,20 @@ __global__ __launch_bounds__(256) void k_dscan_sum(const T* __restrict__ in, con
 }
 
 __global__ __launch_bounds__(256) void k_dscan_part(int64_t* __restrict__ part, const int64_t* __restrict__ n_ptr,
-                                                    int64_t n_max, int64_t* __restrict__ out) {
-  const int64_t n = min(*n_ptr, n_max);
+                                                    int64_t n_max, int64_t* __restrict__ out, const int64_t* status,
+                                                    const int64_t* tstatus) {
+  if (halted(status, tstatus)) return;
+  const int64_t n = dscan_len(n_ptr, n_max);
   k_scan_part_body(part, (n + kScanTile - 1) / kScanTile, out + n);
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_dscan_apply(const T* __restrict__ in, const int64_t* __restrict__ n_ptr,
                                                      int64_t n_max, const int64_t* __restrict__ part,
-                                                     int64_t* __restrict__ out) {
-  const int64_t n = min(*n_ptr, n_max), tiles = (n + kScanTile - 1) / kScanTile;
+                                                     int64_t* __restrict__ out, const int64_t* status,
+                                                     const int64_t* tstatus) {
+  if (halted(status, tstatus)) return;
+  const int64_t n = dscan_len(n_ptr, n_max), tiles = (n + kScanTile - 1) / kScanTile;
   for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     const int64_t base = tile * kScanTile + 4 * threadIdx.x;
     int64_t v[4], s = 0;
@@ -190,10 +200,10 @@ __global__ __launch_bounds__(256) void k_dscan_apply(const T* __restrict__ in, c
 
 template <typename T>
 hipError_t dscan(const T* in, const int64_t* n_ptr, int64_t n_max, int64_t* out, int64_t* part, int grid,
-                 hipStream_t s) {
-  hipLaunchKernelGGL(k_dscan_sum<T>, dim3(grid), dim3(256), 0, s, in, n_ptr, n_max, part);
-  hipLaunchKernelGGL(k_dscan_part, dim3(1), dim3(256), 0, s, part, n_ptr, n_max, out);
-  hipLaunchKernelGGL(k_dscan_apply<T>, dim3(grid), dim3(256), 0, s, in, n_ptr, n_max, part, out);
+                 const int64_t* status, const int64_t* tstatus, hipStream_t s) {
+  hipLaunchKernelGGL(k_dscan_sum<T>, dim3(grid), dim3(256), 0, s, in, n_ptr, n_max, part, status, tstatus);
+  hipLaunchKernelGGL(k_dscan_part, dim3(1), dim3(256), 0, s, part, n_ptr, n_max, out, status, tstatus);
+  hipLaunchKernelGGL(k_dscan_apply<T>, dim3(grid), dim3(256), 0, s, in, n_ptr, n_max, part, out, status, tstatus);
   return hipGetLastError();
 }
 
@@ -672,7 +682,7 @@ __global__ __launch_bounds__(256) void k_track_hits(int64_t n_events, int64_t ca
                                                     int64_t* tstatus) {
   if (halted(status, tstatus)) return;
   const int64_t nt = ev_off[n_events];
-  if (nt > cap) return;
+  if (nt < 0 || nt > cap) return;
   if (WRITE && track_off[nt] > hit_cap) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       tstatus[3] = track_off[nt];
@@ -1035,13 +1045,13 @@ hipError_t launch_triplet_stage(const RunArgs& a, const etx_tracks& T, char* tws
     hipLaunchKernelGGL(k_track_fill, dim3((unsigned)ne), dim3(256), 0, s, ne, a.hits.hit_off, row_ptr, T.art_off,
                        T.tri_a, T.tri_b, comp, touched, lstate, T.event_track_off, tcap, c1, c2, tev, status, tstatus);
   const int gs = ctx->n_cu * 4;
-  if ((err = dscan<int32_t>(ccount, row_ptr + n, cap, cstart, part_buf, gs, s)) != hipSuccess) return err;
+  if ((err = dscan<int32_t>(ccount, row_ptr + n, cap, cstart, part_buf, gs, status, tstatus, s)) != hipSuccess) return err;
   hipLaunchKernelGGL(k_comp_place, dim3(ge), dim3(256), 0, s, n, row_ptr, comp, ccount, cstart, cedge, status, tstatus);
   const int gt = grid_for(tcap * kTrackLanes / 4, ctx->n_cu);   // 16 lanes per track
   hipLaunchKernelGGL(k_track_hits<false>, dim3(gt), dim3(256), 0, s, ne, tcap, a.hits.hit_off, T.event_track_off, c1,
                      c2, tev, cstart, cedge, src, dst, tlen, T.track_off, T.hit_capacity, T.track_hits, status,
                      tstatus);
-  if ((err = dscan<int32_t>(tlen, T.event_track_off + ne, tcap, T.track_off, part_buf, gs, s)) != hipSuccess) return err;
+  if ((err = dscan<int32_t>(tlen, T.event_track_off + ne, tcap, T.track_off, part_buf, gs, status, tstatus, s)) != hipSuccess) return err;
   hipLaunchKernelGGL(k_track_hits<true>, dim3(gt), dim3(256), 0, s, ne, tcap, a.hits.hit_off, T.event_track_off, c1,
                      c2, tev, cstart, cedge, src, dst, tlen, T.track_off, T.hit_capacity, T.track_hits, status,
                      tstatus);
