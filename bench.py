@@ -419,6 +419,7 @@ def triplet_legs(args, stream):
     from paper_2508_07423_amd import etx, evaluate, synth
     w = synth.WORKLOADS["c6"]
     steps = args.ns_steps
+    torch.cuda.empty_cache()
     t0 = time.perf_counter()
     batch = synth.generate_batch(w, w.n_events)
     log(f"[bench] c6: {w.n_events} events, {int(batch['hit_off'][-1])} hits, "
@@ -437,15 +438,22 @@ def triplet_legs(args, stream):
                                                             for k, v in m.items()})
     log(f"[bench] c6 components: {eps:.0f} events/s ({ms:.2f} ms per pass), efficiency {m['efficiency']:.4f}, "
         f"pair efficiency {m['pair_efficiency']:.4f}")
+    # the triplet leg's graph is the same (same embedding): size its edge buffers from it, not from k_max per hit
+    edge_cap = int(res["edge_off"][-1] * 1.25) + 1024
     p.close()
+    del p, res
+    torch.cuda.empty_cache()
     # triplet stage
     p = etx.Pipeline(w, synth.trained_weights(w))
     p.set_triplets(synth.trained_triplets(w))
-    tuned = autotune(etx, p, b, stream, args.autotune_log)
     with torch.cuda.stream(stream):
-        p.run_tracks_sized(b, stream=stream)
+        out_ = p.allocate(b, edge_capacity=edge_cap)
+        etx.etx_autotune(p.ctx, p.hits_struct(b), out_, p.ws_ptr, p.ws_bytes, stream.cuda_stream, args.autotune_log)
+    tuned = schedule(etx, p.ctx)
+    with torch.cuda.stream(stream):
+        p.run_tracks_sized(b, stream=stream, edge_capacity=edge_cap)
     tc, kc, hc = p._trk_shape[:3]
-    caps = dict(triplet_capacity=tc, track_capacity=kc, hit_capacity=hc)
+    caps = dict(triplet_capacity=tc, track_capacity=kc, hit_capacity=hc, edge_capacity=edge_cap)
     eps, ms, med = timed_track_passes(p, b, stream, steps, 2, caps)
     tres = p.track_results(b)
     res = p.results(b)
