@@ -1002,7 +1002,9 @@ hipError_t launch_triplet_stage(const RunArgs& a, const etx_tracks& T, char* tws
   if (part == 1) {
     const float* e = reinterpret_cast<const float*>(a.ws + a.L.e);
     const int H = ctx->cfg.gnn_hidden;
-    const int grid = ctx->n_cu * 2;
+    // enough waves per SIMD to hide the row gathers: 8 workgroups per CU at hidden size 32
+    // (12.7 KiB of weights each), 3 at 64 (50 KiB)
+    const int grid = ctx->n_cu * (H == 32 ? 8 : 3);
     for (int head = 0; head < 2; ++head) {
       if (H == 32)
         hipLaunchKernelGGL(k_tri_score<32>, dim3(grid), dim3(256), sizeof(float) * TriHead<32>::SIZE, s, e, T.tri_a,
