@@ -308,8 +308,8 @@ def north_star(args, stream):
     res = {}
     steps = args.ns_steps
 
-    def leg(w, weights, batch, prec, pf=None, name=""):
-        p = make_pipeline(etx, synth, w, weights, prec, prec, False, None, stream)
+    def leg(w, weights, batch, prec, pf=None, name="", compact=False):
+        p = make_pipeline(etx, synth, w, weights, prec, prec, compact, None, stream)
         if pf is not None:
             etx.etx_prefilter_set(p.ctx, pf["params"])
             etx.etx_prefilter_config(p.ctx, 1, pf["tau"])
@@ -366,9 +366,12 @@ def north_star(args, stream):
         f"tau {sel['tau']:.4f} keeps {sel['kept_fraction']:.3f} of validation candidates")
     batch5 = synth.generate_batch(w5, w5.n_events)
     legs = {}
-    for name, prec, use_pf in (("fp32_unpruned", etx.ETX_FP32, False), ("fp32_pruned", etx.ETX_FP32, True),
-                               ("bf16_pruned", etx.ETX_BF16, True), ("bf16_unpruned", etx.ETX_BF16, False)):
-        r, out = leg(w5, weights5, batch5, prec, pf if use_pf else None, name=f"c5 {name}")
+    for name, prec, use_pf, compact in (("fp32_unpruned", etx.ETX_FP32, False, False),
+                                        ("fp32_pruned", etx.ETX_FP32, True, False),
+                                        ("bf16_pruned", etx.ETX_BF16, True, False),
+                                        ("bf16_compact_pruned", etx.ETX_BF16, True, True),
+                                        ("bf16_unpruned", etx.ETX_BF16, False, False)):
+        r, out = leg(w5, weights5, batch5, prec, pf if use_pf else None, name=f"c5 {name}", compact=compact)
         m = evaluate.batch_metrics(out["labels"], batch5)
         r.update(efficiency=round(m["efficiency"], 5), ghost_rate=round(m["ghost_rate"], 5))
         legs[name] = r
