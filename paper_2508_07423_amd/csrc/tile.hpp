@@ -427,11 +427,18 @@ __device__ inline void gemm(float* acc, const float* x, const void* w, float inv
   }
 }
 
-// Sum over the four lanes of a column.
+// Sum over the four lanes of a column (lanes l, l^16, l^32, l^48) with the
+// gfx950 row swaps: permlane16_swap of a register with itself leaves each lane
+// its own value in one result and its l^16 partner's in the other (which is
+// which depends on the row), so their sum is s + s(l^16) in every lane;
+// permlane32_swap does the same across the halves.  The additions are those
+// of a butterfly through LDS permutes, in the same order and with the same
+// bits, without the LDS round trip.  Called by the whole wave.
 __device__ inline float col_sum(float s) {
-  s += __shfl_xor(s, 16);
-  s += __shfl_xor(s, 32);
-  return s;
+  const auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(s), __float_as_uint(s), false, false);
+  s = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+  const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(s), __float_as_uint(s), false, false);
+  return __uint_as_float(b[0]) + __uint_as_float(b[1]);
 }
 
 // LayerNorm over the F features of each column (biased variance, eps 1e-5,
