@@ -379,8 +379,8 @@ etx_status etx_train_gnn_step(etx_ctx* ctx, const etx_hits* hits, etx_out* out, 
  *
  * Classifiers: one for articulations, one for both kinds of elbow, each
  * Linear(H->1)(Block(H->H)(Block(2H->H)([e_a, e_b]))) on the final edge
- * encodings, Block(x) = ReLU(LN(x W + b)), score = sigmoid; FP32 in every
- * precision mode.  A triplet is kept when its score >= edge_threshold.
+ * encodings, Block(x) = ReLU(LN(x W + b)), score = sigmoid; FP32 arithmetic in
+ * every precision mode.  A triplet is kept when its score >= edge_threshold.
  *
  * Track building (four steps): (1) a kept edge that is the longer edge of a
  * kept left elbow at its source and of a kept right elbow at its target
@@ -424,9 +424,10 @@ typedef struct {             /* device pointers, caller-owned, written by etx_ru
 etx_status etx_tracks_workspace_size(const etx_ctx* ctx, int64_t n_events, int64_t n_hits, int64_t edge_capacity,
                                      int64_t triplet_capacity, int64_t track_capacity, size_t* bytes);
 /* The whole hot path of etx_run (same outputs in `out`), then the triplet
- * stage into `tracks`.  Needs the triplet parameters (etx_triplet_set) and
- * node and edge state in FP32 (FP32 runs, or BF16 / FP8 / INT8 operands
- * without ETX_OPT_COMPACT_STATE; otherwise ETX_ERR_UNSUPPORTED).  Runs
+ * stage into `tracks`.  Needs the triplet parameters (etx_triplet_set); the
+ * classifiers read the final edge encodings as the network stores them (FP32,
+ * or BF16 with ETX_OPT_COMPACT_STATE in BF16 runs); FP8 runs with the compact
+ * state are not supported (ETX_ERR_UNSUPPORTED).  Runs
  * eagerly on `stream` (ETX_OPT_USE_GRAPH is not applied); asynchronous.  A
  * device error of etx_run's stages (out->status) skips the triplet stage. */
 etx_status etx_run_tracks(etx_ctx* ctx, const etx_hits* hits, etx_out* out, etx_tracks* tracks, void* ws,
@@ -468,8 +469,9 @@ etx_status etx_train_triplet_view(const etx_ctx* ctx, int64_t n_events, int64_t 
 etx_status etx_train_triplet_params(etx_ctx* ctx, float* host, int64_t n, int32_t set);
 
 /* Checkpoint of a context: configuration, weight blob, per-tensor scales and
- * calibration flag, prefilter parameters with their Adam moments, and the
- * launch options (the state that training, calibration and tuning build up).
+ * calibration flag, prefilter parameters with their Adam moments and fallback
+ * band, the triplet classifiers (when set), and the launch options (the state
+ * that training, calibration and tuning build up).
  * etx_save with buf == NULL stores the byte count in *nbytes; with a buffer of
  * *nbytes bytes it writes the checkpoint (ETX_ERR_INVALID_ARG and the needed
  * size if it is too small).  The prefilter moments are read from the device,

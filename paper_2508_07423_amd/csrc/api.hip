@@ -1086,7 +1086,7 @@ etx_status etx_run_tracks(etx_ctx* ctx, const etx_hits* hits, etx_out* out, etx_
   if (ws_bytes < L.total + TL.total) return ETX_ERR_INVALID_ARG;
   if (ctx->tri_host.empty()) return ETX_ERR_INVALID_ARG;
   const int prec = kernel_precision(ctx);
-  if (prec == ETX_BF16 || prec == ETX_FP8_E4M3) return ETX_ERR_UNSUPPORTED;   // compact state: e_S not in FP32
+  if (prec == ETX_FP8_E4M3) return ETX_ERR_UNSUPPORTED;   // compact FP8 state: e_S as FP8 codes
   auto scaled = [](int p) { return p == ETX_FP8_E4M3 || p == ETX_INT8; };
   if ((scaled(ctx->cfg.precision) || scaled(ctx->emb_precision)) && !ctx->calibrated) return ETX_ERR_INVALID_ARG;
   if (ctx->cfg.prefilter && !ctx->pf_set) return ETX_ERR_INVALID_ARG;
@@ -1156,13 +1156,17 @@ struct SaveHeader {
   uint32_t magic, version, config_bytes, n_scales, n_pf, n_options;
   uint64_t blob_bytes;
   int32_t calibrated, pf_set;
+  uint32_t n_tri;               // triplet classifier floats (0: none set)
+  float pf_band_lo, pf_band_hi; // prefilter fallback band
+  uint32_t reserved;
 };
 constexpr uint32_t kSaveMagic = 0x53585445;   // "ETXS"
+constexpr uint32_t kSaveVersion = 2;
 constexpr int kSavedOptions = 20;             // etx_option keys 0 .. 19
 
 size_t save_bytes(const etx_ctx* ctx) {
   return sizeof(SaveHeader) + sizeof(etx_config) + sizeof(float) * (N_SCALES + 3 * ETX_PF_NPARAM) +
-         sizeof(int64_t) * kSavedOptions + ctx->blob.size();
+         sizeof(int64_t) * kSavedOptions + ctx->blob.size() + sizeof(float) * ctx->tri_host.size();
 }
 
 }  // namespace
@@ -1179,8 +1183,10 @@ etx_status etx_save(const etx_ctx* ctx, void* buf, size_t* nbytes) {
     return ETX_ERR_INVALID_ARG;
   }
   char* o = static_cast<char*>(buf);
-  SaveHeader h{kSaveMagic, 1, (uint32_t)sizeof(etx_config), (uint32_t)N_SCALES, (uint32_t)(3 * ETX_PF_NPARAM),
-               (uint32_t)kSavedOptions, (uint64_t)ctx->blob.size(), ctx->calibrated ? 1 : 0, ctx->pf_set ? 1 : 0};
+  SaveHeader h{kSaveMagic, kSaveVersion, (uint32_t)sizeof(etx_config), (uint32_t)N_SCALES,
+               (uint32_t)(3 * ETX_PF_NPARAM), (uint32_t)kSavedOptions, (uint64_t)ctx->blob.size(),
+               ctx->calibrated ? 1 : 0, ctx->pf_set ? 1 : 0, (uint32_t)ctx->tri_host.size(), ctx->pf_band_lo,
+               ctx->pf_band_hi, 0u};
   std::memcpy(o, &h, sizeof h);
   o += sizeof h;
   std::memcpy(o, &ctx->cfg, sizeof(etx_config));
@@ -1201,6 +1207,8 @@ etx_status etx_save(const etx_ctx* ctx, void* buf, size_t* nbytes) {
     o += sizeof v;
   }
   std::memcpy(o, ctx->blob.data(), ctx->blob.size());
+  o += ctx->blob.size();
+  if (!ctx->tri_host.empty()) std::memcpy(o, ctx->tri_host.data(), sizeof(float) * ctx->tri_host.size());
   *nbytes = need;
   return ETX_OK;
 }
@@ -1211,11 +1219,11 @@ etx_status etx_load(const void* buf, size_t nbytes, int device, etx_ctx** out) {
   SaveHeader h;
   if (nbytes < sizeof h) return ETX_ERR_INVALID_ARG;
   std::memcpy(&h, buf, sizeof h);
-  if (h.magic != kSaveMagic || h.version != 1 || h.config_bytes != sizeof(etx_config) || h.n_scales != N_SCALES ||
-      h.n_pf != 3 * ETX_PF_NPARAM || h.n_options != kSavedOptions)
+  if (h.magic != kSaveMagic || h.version != kSaveVersion || h.config_bytes != sizeof(etx_config) ||
+      h.n_scales != N_SCALES || h.n_pf != 3 * ETX_PF_NPARAM || h.n_options != kSavedOptions)
     return ETX_ERR_INVALID_ARG;
   const size_t need = sizeof h + sizeof(etx_config) + sizeof(float) * (N_SCALES + 3 * ETX_PF_NPARAM) +
-                      sizeof(int64_t) * kSavedOptions + h.blob_bytes;
+                      sizeof(int64_t) * kSavedOptions + h.blob_bytes + sizeof(float) * (size_t)h.n_tri;
   if (nbytes != need) return ETX_ERR_INVALID_ARG;
   const char* p = static_cast<const char*>(buf) + sizeof h;
   etx_config cfg;
@@ -1227,9 +1235,23 @@ etx_status etx_load(const void* buf, size_t nbytes, int device, etx_ctx** out) {
   p += sizeof(float) * 3 * ETX_PF_NPARAM;
   const char* opts = p;
   p += sizeof(int64_t) * kSavedOptions;
+  const char* tri = p + h.blob_bytes;
+  if (h.n_tri != 0 && h.n_tri != (uint32_t)ETX_TRIPLET_NPARAM(cfg.gnn_hidden)) return ETX_ERR_INVALID_ARG;
   etx_ctx* ctx = nullptr;
   etx_status st = etx_create(&cfg, p, (size_t)h.blob_bytes, device, &ctx);
   if (st != ETX_OK) return st;
+  if (h.n_tri) {
+    std::vector<float> tp(h.n_tri);
+    std::memcpy(tp.data(), tri, sizeof(float) * h.n_tri);
+    if ((st = etx_triplet_set(ctx, tp.data(), (int64_t)h.n_tri)) != ETX_OK) {
+      etx_destroy(ctx);
+      return st;
+    }
+  }
+  if ((st = etx_prefilter_band(ctx, h.pf_band_lo, h.pf_band_hi)) != ETX_OK) {
+    etx_destroy(ctx);
+    return st;
+  }
   std::memcpy(ctx->host_scales, scales, sizeof(float) * N_SCALES);
   ctx->calibrated = h.calibrated != 0;
   hipError_t e = hipMemcpy(ctx->dev_scales, ctx->host_scales, sizeof(float) * N_SCALES, hipMemcpyHostToDevice);

@@ -350,8 +350,27 @@ struct TriHead {
   static constexpr int SIZE = B3 + 4;
 };
 
+// A stored edge row in BF16 (the compact state) into column layout: lane
+// group g's 16-byte chunk c of the row (at byte 64c + 16g) holds its registers
+// 8c .. 8c+7, features phi(r, g) (the edge kernels' row layout).
 template <int H>
-__global__ __launch_bounds__(256) void k_tri_score(const float* __restrict__ e, const int32_t* __restrict__ ta,
+__device__ inline void load_cols_bf16_row(float* x, const char* __restrict__ row, bool valid) {
+  const int g = lane_group();
+#pragma unroll
+  for (int c = 0; c < H / 32; ++c) {
+    const uint4 v = valid ? *reinterpret_cast<const uint4*>(row + 64 * c + 16 * g) : make_uint4(0u, 0u, 0u, 0u);
+    const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      x[8 * c + 2 * i] = bf16_value(u[i] & 0xffffu);
+      x[8 * c + 2 * i + 1] = bf16_value(u[i] >> 16);
+    }
+  }
+}
+
+// BF: the final edge encodings are stored as BF16 (compact state), else FP32.
+template <int H, bool BF>
+__global__ __launch_bounds__(256) void k_tri_score(const void* __restrict__ e_, const int32_t* __restrict__ ta,
                                                    const int32_t* __restrict__ tb, const int64_t* __restrict__ art_pos,
                                                    const int64_t* __restrict__ elb_pos, int64_t n, int head,
                                                    const float* __restrict__ wt, float* __restrict__ ts,
@@ -372,8 +391,15 @@ __global__ __launch_bounds__(256) void k_tri_score(const float* __restrict__ e, 
     const bool valid = r < r1;
     const int64_t ea = valid ? ta[r] : 0, eb = valid ? tb[r] : 0;
     float x[H / 2];
-    load_cols<H>(x, e + ea * H, valid);
-    load_cols<H>(x + H / 4, e + eb * H, valid);
+    if constexpr (BF) {
+      const char* e = static_cast<const char*>(e_);
+      load_cols_bf16_row<H>(x, e + ea * H * 2, valid);
+      load_cols_bf16_row<H>(x + H / 4, e + eb * H * 2, valid);
+    } else {
+      const float* e = static_cast<const float*>(e_);
+      load_cols<H>(x, e + ea * H, valid);
+      load_cols<H>(x + H / 4, e + eb * H, valid);
+    }
     float a1[H / 4];
     bias_cols<H>(a1, w + Hd::B1);
     mfma_f32<2 * H, H / 16>(a1, x, w + Hd::W1);
@@ -953,10 +979,13 @@ void tri_prepare_head(const float* p, int H, float* out) {
 
 int triplet_attributes(size_t max_lds) {
   int bad = 0;
-  bad |= hipFuncSetAttribute(reinterpret_cast<const void*>(k_tri_score<32>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) != hipSuccess;
-  bad |= hipFuncSetAttribute(reinterpret_cast<const void*>(k_tri_score<64>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) != hipSuccess;
+  auto set = [&](const void* f) {
+    bad |= hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) != hipSuccess;
+  };
+  set(reinterpret_cast<const void*>(k_tri_score<32, false>));
+  set(reinterpret_cast<const void*>(k_tri_score<64, false>));
+  set(reinterpret_cast<const void*>(k_tri_score<32, true>));
+  set(reinterpret_cast<const void*>(k_tri_score<64, true>));
   return bad;
 }
 
@@ -1000,18 +1029,22 @@ hipError_t launch_triplet_stage(const RunArgs& a, const etx_tracks& T, char* tws
     return hipGetLastError();
   }
   if (part == 1) {
-    const float* e = reinterpret_cast<const float*>(a.ws + a.L.e);
+    const void* e = a.ws + a.L.e;
     const int H = ctx->cfg.gnn_hidden;
+    const bool bf = a.prec == ETX_BF16;   // compact BF16 state
     // enough waves per SIMD to hide the row gathers: 8 workgroups per CU at hidden size 32
     // (12.7 KiB of weights each), 3 at 64 (50 KiB)
     const int grid = ctx->n_cu * (H == 32 ? 8 : 3);
     for (int head = 0; head < 2; ++head) {
-      if (H == 32)
-        hipLaunchKernelGGL(k_tri_score<32>, dim3(grid), dim3(256), sizeof(float) * TriHead<32>::SIZE, s, e, T.tri_a,
-                           T.tri_b, art_pos, elb_pos, n, head, ctx->dev_tri, T.tri_score, status, tstatus);
-      else
-        hipLaunchKernelGGL(k_tri_score<64>, dim3(grid), dim3(256), sizeof(float) * TriHead<64>::SIZE, s, e, T.tri_a,
-                           T.tri_b, art_pos, elb_pos, n, head, ctx->dev_tri, T.tri_score, status, tstatus);
+#define SCORE(H_, BF_)                                                                                      \
+  hipLaunchKernelGGL((k_tri_score<H_, BF_>), dim3(grid), dim3(256), sizeof(float) * TriHead<H_>::SIZE, s, e, \
+                     T.tri_a, T.tri_b, art_pos, elb_pos, n, head, ctx->dev_tri, T.tri_score, status, tstatus)
+      if (H == 32) {
+        if (bf) SCORE(32, true); else SCORE(32, false);
+      } else {
+        if (bf) SCORE(64, true); else SCORE(64, false);
+      }
+#undef SCORE
     }
     return hipGetLastError();
   }

@@ -223,8 +223,9 @@ def test_host_argument_errors():
 
 
 def test_checkpoint_round_trip():
-    """etx_save / etx_load carry weights, FP8 scales, prefilter state and
-    launch options: the loaded context computes the same bits."""
+    """etx_save / etx_load carry weights, FP8 scales, prefilter state and band,
+    triplet classifiers and launch options: the loaded context computes the
+    same bits, and saves the same checkpoint."""
     etx = _etx()
     w = synth.C1
     W = synth.xavier_weights(w)
@@ -236,6 +237,9 @@ def test_checkpoint_round_trip():
     state = rng.normal(0, 0.1, 3 * etx.ETX_PF_NPARAM).astype(np.float32)
     etx.etx_prefilter_state(p.ctx, state)
     etx.etx_set_option(p.ctx, etx.ETX_OPT_EDGE_PIPELINE, 2)
+    etx.etx_prefilter_band(p.ctx, 0.25, 0.75)
+    heads = synth.xavier_triplets(w, seed=3)
+    p.set_triplets(heads)
     b = etx.to_device(batch)
     p.run(b)
     r0 = p.results(b)
@@ -246,6 +250,7 @@ def test_checkpoint_round_trip():
     assert etx.etx_get_option(q.ctx, etx.ETX_OPT_EDGE_PIPELINE) == 2
     assert np.array_equal(etx.etx_prefilter_state(q.ctx), state)
     assert np.array_equal(etx.etx_get_scales(q.ctx), etx.etx_get_scales(p.ctx))
+    assert np.array_equal(etx.etx_triplet_get(q.ctx, etx.ETX_TRIPLET_NPARAM(w.gnn_hidden)), etx.pack_triplets(heads))
     q.run(b)
     r1 = q.results(b)
     for k in ("src", "dst", "score", "labels", "edge_off"):

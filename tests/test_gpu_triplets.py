@@ -159,6 +159,32 @@ def test_bf16_operands_track_building_exact(pair_batch):
         event_triplet_parity(w, W, heads, batch, res, tres, i, check_scores=False)
 
 
+def test_bf16_compact_state_track_building_exact(pair_batch):
+    """BF16 with the compact state: the classifiers read the BF16 final edge
+    encodings; triplets and tracks still follow the oracle's stage on the
+    GPU's own purified graph and decisions."""
+    w, batch, heads = pair_batch
+    W = synth.trained_weights(w)
+    etx = _etx()
+    p = etx.Pipeline(w, W, precision=etx.ETX_BF16)
+    etx.etx_set_option(p.ctx, etx.ETX_OPT_COMPACT_STATE, 1)
+    p.set_triplets(heads)
+    b = etx.to_device(batch)
+    p.run_tracks_sized(b)
+    res, tres = p.results(b), p.track_results(b)
+    n_tri = 0
+    for i in range(len(batch["hit_off"]) - 1):
+        n_tri += event_triplet_parity(w, W, heads, batch, res, tres, i, check_scores=False)["triplets"]
+    assert n_tri > 1000
+    # the scores follow the FP32-state BF16 run's within the BF16 rounding of e_S
+    q = etx.Pipeline(w, W, precision=etx.ETX_BF16)
+    q.set_triplets(heads)
+    q.run_tracks_sized(b)
+    t32 = q.track_results(b)
+    if np.array_equal(t32["tri_a"], tres["tri_a"]) and np.array_equal(t32["tri_b"], tres["tri_b"]):
+        assert np.max(np.abs(t32["tri_score"] - tres["tri_score"])) < 0.05
+
+
 def test_nothing_kept_gives_no_triplets_and_no_tracks():
     w = synth.C1.with_(threshold=1.5)
     W = synth.xavier_weights(w)
@@ -219,9 +245,9 @@ def test_unsupported_and_invalid_modes():
     p.set_triplets(synth.xavier_triplets(w))
     assert np.array_equal(etx.etx_triplet_get(p.ctx, etx.ETX_TRIPLET_NPARAM(w.gnn_hidden)),
                           etx.pack_triplets(synth.xavier_triplets(w)))
-    etx.etx_set_precision(p.ctx, etx.ETX_BF16)
+    etx.etx_set_precision(p.ctx, etx.ETX_FP8_E4M3)
     etx.etx_set_option(p.ctx, etx.ETX_OPT_COMPACT_STATE, 1)
-    with pytest.raises(etx.EtxError) as ex:          # compact state: e_S is not kept in FP32
+    with pytest.raises(etx.EtxError) as ex:          # compact FP8 state: e_S as FP8 codes
         p.run_tracks(b)
     assert ex.value.code == etx.ETX_ERR_UNSUPPORTED
     with pytest.raises(etx.EtxError):
