@@ -491,6 +491,28 @@ def triplet_legs(args, stream):
     log(f"[bench] c6 triplets: {eps:.0f} events/s ({ms:.2f} ms per pass), efficiency {m['efficiency']:.4f}, "
         f"pair efficiency {m['pair_efficiency']:.4f}; {n_tri} triplets, stages {stage_ms}")
     p.close()
+    del p
+    torch.cuda.empty_cache()
+    # the same with BF16 operands and the compact BF16 state (the classifiers read BF16 edge encodings)
+    p = etx.Pipeline(w, synth.trained_weights(w), precision=etx.ETX_BF16)
+    etx.etx_set_option(p.ctx, etx.ETX_OPT_COMPACT_STATE, 1)
+    p.set_triplets(synth.trained_triplets(w))
+    with torch.cuda.stream(stream):
+        out_ = p.allocate(b, edge_capacity=edge_cap)
+        etx.etx_autotune(p.ctx, p.hits_struct(b), out_, p.ws_ptr, p.ws_bytes, stream.cuda_stream, args.autotune_log)
+        p.run_tracks_sized(b, stream=stream, edge_capacity=edge_cap)
+    tc, kc, hc = p._trk_shape[:3]
+    caps = dict(triplet_capacity=tc, track_capacity=kc, hit_capacity=hc, edge_capacity=edge_cap)
+    eps, ms, med = timed_track_passes(p, b, stream, steps, 2, caps)
+    tres = p.track_results(b)
+    m = evaluate.track_list_metrics(tres["tracks"], tres["event_track_off"], batch)
+    out["triplets_bf16_compact"] = dict(events_per_s=round(eps, 1), ms_per_pass=round(ms, 3),
+                                        ms_per_pass_median=round(med, 3), steps=steps, schedule=schedule(etx, p.ctx),
+                                        triplets=int(tres["elb_off"][-1]),
+                                        **{k: round(v, 5) if isinstance(v, float) else v for k, v in m.items()})
+    log(f"[bench] c6 triplets bf16 compact: {eps:.0f} events/s ({ms:.2f} ms per pass), efficiency "
+        f"{m['efficiency']:.4f}, pair efficiency {m['pair_efficiency']:.4f}")
+    p.close()
     c, t = out["components"], out["triplets"]
     out["workload"] = (f"c6: {w.n_events} events as c3 with conversion pairs (a tenth of the tracks shares its first "
                        f"1-3 hits with a partner), eager triplet stage after an autotuned network")
