@@ -52,7 +52,7 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c5"],
                     help="c5: the c3 workload with trained weights and the learned prefilter, trained before timing")
@@ -75,7 +75,7 @@ def parse():
                     help="instrumented passes before the timed ones (per-stage times, the roofline kernel)")
     ap.add_argument("--north-star", type=int, default=None,
                     help="add the uneven-batch and prefilter comparison (default: on for the c2 headline)")
-    ap.add_argument("--ns-steps", type=int, default=10, help="timed passes of each north-star leg")
+    ap.add_argument("--ns-steps", type=int, default=20, help="timed passes of each north-star leg")
     ap.add_argument("--triplets-only", type=int, default=0,
                     help="1: only the conversion-pair comparison (components against the triplet stage), "
                          "printed as one JSON line")
