@@ -423,43 +423,71 @@ __device__ inline void store_e(void* e, int64_t col, const float* o, bool valid,
 // past it), which the message kernel adds up in tile order.
 
 // Row shifts within the 16-lane DPP rows.  Lanes whose source is outside
-// the row read 0 (values) or -2 (keys); the moves run with the whole wave
-// active, never under a lane-dependent branch, since a lane whose source lane
-// is inactive would read the fallback value too.
-template <int N>
-__device__ inline float row_shr_f(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x110 + N, 0xf, 0xf, true));
-}
+// the row read -2 (keys; 0 for the values of the scan below); the shifts run
+// with the whole wave active, never under a lane-dependent branch, since a
+// lane whose source lane is inactive would read the fallback value too.
 template <int N>
 __device__ inline int row_shr_i(int v) {
   return __builtin_amdgcn_update_dpp(-2, v, 0x110 + N, 0xf, 0xf, false);
 }
 __device__ inline int row_shl1_i(int v) { return __builtin_amdgcn_update_dpp(-2, v, 0x101, 0xf, 0xf, false); }
 
-// inclusive segmented sums along the 16 columns; key is non-decreasing in the
-// column.  Each step is v += (same run ? 1 : 0) * v[column - 2^i], a single
-// multiply-add whose first operand is the row-shifted register.
+// Inclusive segmented sums along the 16 columns of a tile, N registers per
+// lane; key is non-decreasing in the column.  Level i adds, to each column,
+// the value 2^i columns to its left when both belong to the same run:
+// v = fma(v[column - 2^i], m_i, v) with m_i = 1 or 0, one v_fmac_f32 whose
+// first source is read through a DPP row shift (lanes whose source lies
+// outside the 16-lane row read 0).  The compiler keeps a DPP move apart from
+// a multiply-add, two instructions, and copies registers at the joins of
+// per-level branches, so the four levels are written out as one block.  A
+// level whose mask is zero in every lane (no run of the wave's tiles that
+// long) would add exact zeros to finite values: it is skipped on its ballot
+// (wave-uniform scalar branches inside the block).  A DPP read needs two
+// wait states after a vector write of its source and five after a vector
+// write of EXEC: the leading s_nop 4 covers both; inside the block a
+// register is read at least N instructions after it was written.
+#define ETX_FMAC_SHR(i, D, M) \
+  "v_fmac_f32_dpp %" #i ", %" #i ", %" #M " row_shr:" #D " row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+#define ETX_LEVEL8(D, M)                                                                                     \
+  ETX_FMAC_SHR(0, D, M) ETX_FMAC_SHR(1, D, M) ETX_FMAC_SHR(2, D, M) ETX_FMAC_SHR(3, D, M) ETX_FMAC_SHR(4, D, M) \
+  ETX_FMAC_SHR(5, D, M) ETX_FMAC_SHR(6, D, M) ETX_FMAC_SHR(7, D, M)
+#define ETX_LEVEL16(D, M)                                                                                      \
+  ETX_LEVEL8(D, M) ETX_FMAC_SHR(8, D, M) ETX_FMAC_SHR(9, D, M) ETX_FMAC_SHR(10, D, M) ETX_FMAC_SHR(11, D, M)     \
+  ETX_FMAC_SHR(12, D, M) ETX_FMAC_SHR(13, D, M) ETX_FMAC_SHR(14, D, M) ETX_FMAC_SHR(15, D, M)
+#define ETX_SKIP(B, L) "s_cmp_eq_u64 %" #B ", 0\n\ts_cbranch_scc1 " L "%=\n\t"
+#define ETX_SCAN(LEVEL, M1, M2, M4, M8, B1, B2, B4, B8)                                                      \
+  "s_nop 4\n\t" ETX_SKIP(B1, ".Lscan2_") LEVEL(1, M1) ".Lscan2_%=:\n\t" ETX_SKIP(B2, ".Lscan4_") LEVEL(2, M2)   \
+  ".Lscan4_%=:\n\t" ETX_SKIP(B4, ".Lscan8_") LEVEL(4, M4) ".Lscan8_%=:\n\t" ETX_SKIP(B8, ".Lscan_end_")        \
+  LEVEL(8, M8) ".Lscan_end_%=:\n\t"
+
 template <int N>
 __device__ inline void seg_scan_cols(float* v, int key) {
+  static_assert(N == 8 || N == 16, "hidden size 32 or 64");
   const int j = lane_id() & 15;
   const int k1 = row_shr_i<1>(key), k2 = row_shr_i<2>(key), k4 = row_shr_i<4>(key), k8 = row_shr_i<8>(key);
   const float m1 = ((j >= 1) & (k1 == key)) ? 1.f : 0.f, m2 = ((j >= 2) & (k2 == key)) ? 1.f : 0.f;
   const float m4 = ((j >= 4) & (k4 == key)) ? 1.f : 0.f, m8 = ((j >= 8) & (k8 == key)) ? 1.f : 0.f;
-  // a level whose mask is zero in every lane (no run of the wave's tiles that
-  // long) would add exact zeros to finite values: skipped, wave-uniformly
-  if (__ballot(m1 != 0.f))
-#pragma unroll
-    for (int r = 0; r < N; ++r) v[r] = fmaf(row_shr_f<1>(v[r]), m1, v[r]);
-  if (__ballot(m2 != 0.f))
-#pragma unroll
-    for (int r = 0; r < N; ++r) v[r] = fmaf(row_shr_f<2>(v[r]), m2, v[r]);
-  if (__ballot(m4 != 0.f))
-#pragma unroll
-    for (int r = 0; r < N; ++r) v[r] = fmaf(row_shr_f<4>(v[r]), m4, v[r]);
-  if (__ballot(m8 != 0.f))
-#pragma unroll
-    for (int r = 0; r < N; ++r) v[r] = fmaf(row_shr_f<8>(v[r]), m8, v[r]);
+  const uint64_t b1 = __ballot(m1 != 0.f), b2 = __ballot(m2 != 0.f), b4 = __ballot(m4 != 0.f),
+                 b8 = __ballot(m8 != 0.f);
+  if constexpr (N == 8) {
+    asm volatile(ETX_SCAN(ETX_LEVEL8, 8, 9, 10, 11, 12, 13, 14, 15)
+                 : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]), "+v"(v[6]), "+v"(v[7])
+                 : "v"(m1), "v"(m2), "v"(m4), "v"(m8), "s"(b1), "s"(b2), "s"(b4), "s"(b8)
+                 : "scc");
+  } else {
+    asm volatile(ETX_SCAN(ETX_LEVEL16, 16, 17, 18, 19, 20, 21, 22, 23)
+                 : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]), "+v"(v[6]), "+v"(v[7]),
+                   "+v"(v[8]), "+v"(v[9]), "+v"(v[10]), "+v"(v[11]), "+v"(v[12]), "+v"(v[13]), "+v"(v[14]),
+                   "+v"(v[15])
+                 : "v"(m1), "v"(m2), "v"(m4), "v"(m8), "s"(b1), "s"(b2), "s"(b4), "s"(b8)
+                 : "scc");
+  }
 }
+#undef ETX_SCAN
+#undef ETX_SKIP
+#undef ETX_LEVEL16
+#undef ETX_LEVEL8
+#undef ETX_FMAC_SHR
 
 // q: stored values of this lane's column; key: its source node (-1 past the
 // last edge); x.before / x.after: sources of the neighbouring edges of the
