@@ -245,7 +245,8 @@ def cpu_baseline(w, weights, batch, threads):
 
 
 TUNED_KEYS = ("EDGE_WG_SIZE", "EDGE_WG_PER_CU", "EDGE_PIPELINE", "NODE_WG_PER_CU", "FUSE_MESSAGES", "SEGSUM_UNROLL",
-              "RADIUS_SORT_MIN", "RADIUS_FAST", "XCD_MAP", "EDGE_PRODUCTS", "CSC_PLACE")
+              "RADIUS_SORT_MIN", "RADIUS_FAST", "XCD_MAP", "EDGE_PRODUCTS", "CSC_PLACE",
+              "RADIUS_SPLIT")
 
 
 def schedule(etx, ctx):

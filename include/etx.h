@@ -213,9 +213,14 @@ typedef enum {
                                   traffic; the residual sums are then rounded at every step (different results) */
   ETX_OPT_PROFILE_STAGES = 20, /* bit mask of the stages (etx_stage_name indices) that ETX_OPT_PROFILE times; default
                                   every stage.  Timing one kernel alone leaves the rest of a pass uninstrumented */
-  ETX_OPT_PF_FEATURES = 21     /* 1: the prefilter's inference pass also stores the features of every candidate edge
+  ETX_OPT_PF_FEATURES = 21,    /* 1: the prefilter's inference pass also stores the features of every candidate edge
                                   (ETX_VIEW_PF_FEAT; the workspace grows by 32 bytes per edge of capacity: set it
                                   before sizing the workspace); 0 (default): features are formed in registers only */
+  ETX_OPT_RADIUS_SPLIT = 22    /* 1: the radius search runs as two launches over the (event, plane) units: candidate
+                                  windows of up to 512 hits (256 above embedding width 8) in workgroups with half the
+                                  staging LDS (three to a CU at embedding width up to 8), the larger ones as before;
+                                  each launch skips the other's units; the same bits (needs ETX_OPT_RADIUS_LDS = 1).
+                                  0 (default): one launch */
 } etx_option;
 etx_status etx_set_option(etx_ctx* ctx, int32_t key, int64_t value);
 etx_status etx_get_option(const etx_ctx* ctx, int32_t key, int64_t* value);

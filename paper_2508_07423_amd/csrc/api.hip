@@ -777,6 +777,10 @@ etx_status etx_set_option(etx_ctx* ctx, int32_t key, int64_t value) {
       if (value != 0 && value != 1) return ETX_ERR_INVALID_ARG;
       ctx->radius_fast = (int)value;
       break;
+    case ETX_OPT_RADIUS_SPLIT:
+      if (value != 0 && value != 1) return ETX_ERR_INVALID_ARG;
+      ctx->radius_split = (int)value;
+      break;
     case ETX_OPT_XCD_MAP:
       if (value != 0 && value != 1) return ETX_ERR_INVALID_ARG;
       ctx->xcd_map = (int)value;
@@ -858,6 +862,7 @@ etx_status etx_get_option(const etx_ctx* ctx, int32_t key, int64_t* value) {
     case ETX_OPT_RADIUS_SORT_MIN: *value = ctx->radius_sort_min; break;
     case ETX_OPT_FUSE_MESSAGES: *value = ctx->fuse_messages; break;
     case ETX_OPT_RADIUS_FAST: *value = ctx->radius_fast; break;
+    case ETX_OPT_RADIUS_SPLIT: *value = ctx->radius_split; break;
     case ETX_OPT_XCD_MAP: *value = ctx->xcd_map; break;
     case ETX_OPT_EDGE_PRODUCTS: *value = ctx->edge_products; break;
     case ETX_OPT_CSC_PLACE: *value = ctx->csc_place; break;

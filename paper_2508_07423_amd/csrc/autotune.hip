@@ -32,7 +32,7 @@ namespace etx {
 const int32_t kTunedOptions[] = {ETX_OPT_EDGE_WG_SIZE,  ETX_OPT_EDGE_WG_PER_CU,    ETX_OPT_EDGE_PRODUCTS,
                                  ETX_OPT_EDGE_PIPELINE, ETX_OPT_XCD_MAP,           ETX_OPT_NODE_WG_PER_CU,
                                  ETX_OPT_FUSE_MESSAGES, ETX_OPT_SEGSUM_UNROLL,     ETX_OPT_RADIUS_SORT_MIN,
-                                 ETX_OPT_RADIUS_FAST,   ETX_OPT_CSC_PLACE};
+                                 ETX_OPT_RADIUS_FAST,   ETX_OPT_CSC_PLACE,         ETX_OPT_RADIUS_SPLIT};
 const int kNumTunedOptions = sizeof(kTunedOptions) / sizeof(kTunedOptions[0]);
 
 // Shape bucket: hits per event and events per batch, each rounded to the
@@ -199,6 +199,7 @@ extern "C" etx_status etx_autotune(etx_ctx* ctx, const etx_hits* hits, etx_out* 
       {{ETX_OPT_SEGSUM_UNROLL}, "segsum_unroll", {{1}, {2}, {4}, {8}}, {ST_SEGSUM}},
       {{ETX_OPT_RADIUS_SORT_MIN}, "radius_sort_min", {{64}, {128}, {256}, {512}, {1024}}, {ST_RADIUS_COUNT, ST_RADIUS_EMIT}},
       {{ETX_OPT_RADIUS_FAST}, "radius_fast", {{0}, {1}}, {ST_RADIUS_COUNT, ST_RADIUS_EMIT}},
+      {{ETX_OPT_RADIUS_SPLIT}, "radius_split", {{0}, {1}}, {ST_RADIUS_COUNT, ST_RADIUS_EMIT}},
       {{ETX_OPT_CSC_PLACE}, "csc_place", {{0}, {1}}, {ST_CSC}},
   };
   // the options in effect before tuning come back if tuning fails

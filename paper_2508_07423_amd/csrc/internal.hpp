@@ -95,6 +95,7 @@ struct etx_ctx {
   int fuse_messages = 0;           // message sums gathered inside the node-update kernel
   int radius_sort_min = 512;       // staged windows from this size on are sorted along their widest axis
   int radius_fast = 0;             // select pass: 16-lane path for sources with few candidates
+  int radius_split = 0;            // radius search: small windows in a launch of its own with less LDS
   int xcd_map = 0;                 // tile and node kernels: contiguous work per XCD
   int edge_products = 0;           // 1: edge kernels form the node-product terms from gathered h rows
   int csc_place = 1;               // short-row CSC placed by the whole block, then columns sorted

@@ -40,6 +40,7 @@ struct RadiusArgs {
   int stage_window;        // 0: always read the window from HBM
   int sort_min;            // staged windows of at least this many hits are sorted (cell list)
   int fast;                // select pass: sources with at most 16 in-radius candidates take the 16-lane path
+  int split;               // 1: windows up to the small capacity go to the small-LDS launch, the rest to the other
   float r2, r;
   int32_t* cnt;            // count pass output (and the select pass's)
   const int64_t* row_ptr;  // emit pass input
@@ -64,10 +65,16 @@ __device__ inline float dist2(const float (&s)[DP], const float* c) {
   return d2;
 }
 
-// LDS capacity of the staged window for a padded embedding width DP.
-template <int DP>
+// LDS capacity of the staged window for a padded embedding width DP.  The
+// SMALL form stages half as many hits: 48 KiB instead of 72 KiB at width 8,
+// so that three workgroups share a CU instead of two (at width 16 the
+// registers still allow only two).  A workgroup's few hundred distance
+// evaluations on a trained embedding wait mostly on memory latency (one
+// workgroup per CU instead of two nearly doubles the search time), so the
+// small windows gain from the third workgroup in flight.
+template <int DP, bool SMALL = false>
 struct RadiusLds {
-  static constexpr int cap = DP <= 8 ? 1024 : 512;
+  static constexpr int cap = (DP <= 8 ? 1024 : 512) / (SMALL ? 2 : 1);
   static constexpr size_t bytes = (size_t)cap * (DP * 4 + 12) + kRadiusWaves * (kList * 8 + 64 * 4 + 256 * 4) + 64;
 };
 
@@ -77,12 +84,18 @@ struct RadiusLds {
 // count, so that the CSR rows are a copy after the scan.
 enum RadiusMode { R_COUNT = 0, R_EMIT = 1, R_SELECT = 2 };
 
-template <int MODE, int DP>
-__global__ __launch_bounds__(kRadiusThreads) void k_radius(RadiusArgs A) {
+// Window size of an (event, plane) unit: hits on the planes after p within
+// the plane window (0 on the last plane).
+__device__ inline int window_hits(const int32_t* po, int p, int P, int window) {
+  return p + 1 < P ? po[min(p + window, P - 1) + 1] - po[p + 1] : 0;
+}
+
+// One (event, plane) unit: its sources against their candidate window.
+// Entered by the whole workgroup; every early return is workgroup-uniform.
+template <int MODE, int DP, bool SMALL>
+__device__ inline void radius_unit(const RadiusArgs& A, float* lds, int ev, int p) {
   constexpr bool EMIT = MODE != R_COUNT;
-  if (A.status[0] != 0) return;
-  constexpr int CAP = RadiusLds<DP>::cap;
-  extern __shared__ float lds[];
+  constexpr int CAP = RadiusLds<DP, SMALL>::cap;
   float* cemb = lds;                                              // [CAP][DP]
   int* cj = reinterpret_cast<int*>(cemb + CAP * DP);              // [CAP] target hit index
   float* skey = reinterpret_cast<float*>(cj + CAP);               // [CAP] cell ends, then hard sources
@@ -94,18 +107,16 @@ __global__ __launch_bounds__(kRadiusThreads) void k_radius(RadiusArgs A) {
   int* misc = hist + kRadiusWaves * 256;                          // [16]
 
   const int P = A.n_planes;
-  const int ev = blockIdx.x / P, p = blockIdx.x % P;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t a = A.hit_off[ev];
   const int32_t* po = A.plane_off + (int64_t)ev * (P + 1);
   const int s0 = po[p], s1 = po[p + 1];
   const int nsrc = s1 - s0;
   if (nsrc == 0) return;
-  int nwin = 0, w0 = s1;
-  if (p + 1 < P) {
-    w0 = po[p + 1];
-    nwin = po[min(p + A.window, P - 1) + 1] - w0;
-  }
+  const int w0 = s1;
+  const int nwin = window_hits(po, p, P, A.window);
+  // split launches: each unit goes to exactly one of the two
+  if (A.split && (SMALL ? nwin > CAP : nwin <= RadiusLds<DP, true>::cap)) return;
   const int32_t* wb = A.bucket + a + w0;
   const bool staged = A.stage_window && nwin <= CAP;
   // windows of at least sort_min hits get a cell list along their widest axis
@@ -534,6 +545,14 @@ __global__ __launch_bounds__(kRadiusThreads) void k_radius(RadiusArgs A) {
   }
 }
 
+// One workgroup per (event, plane) unit.
+template <int MODE, int DP, bool SMALL>
+__global__ __launch_bounds__(kRadiusThreads) void k_radius(RadiusArgs A) {
+  if (A.status[0] != 0) return;
+  extern __shared__ float lds[];
+  radius_unit<MODE, DP, SMALL>(A, lds, blockIdx.x / A.n_planes, blockIdx.x % A.n_planes);
+}
+
 // CSR rows from the select pass's slots: thread (source i, rank r) copies
 // slot r of source i when r is below its count.
 // One wave per chunk of 64 hits.  The chunk's CSR rows are one contiguous
@@ -617,18 +636,22 @@ hipError_t launch_radius(const RunArgs& a, int mode, bool candidates) {
   A.stage_window = a.ctx->radius_lds;
   A.sort_min = a.ctx->radius_sort_min;
   A.fast = a.ctx->radius_fast;
-#define LAUNCH_R(M_, D_) \
-  hipLaunchKernelGGL((k_radius<M_, D_>), grid, dim3(kRadiusThreads), RadiusLds<D_>::bytes, a.stream, A)
-#define BY_MODE(D_)                                  \
-  switch (mode) {                                    \
-    case R_COUNT: LAUNCH_R(R_COUNT, D_); break;      \
-    case R_EMIT: LAUNCH_R(R_EMIT, D_); break;        \
-    default: LAUNCH_R(R_SELECT, D_); break;          \
+  // the split needs staged windows (it exists for the occupancy of staging)
+  A.split = a.ctx->radius_split && A.stage_window ? 1 : 0;
+#define LAUNCH_R(M_, D_, S_) \
+  hipLaunchKernelGGL((k_radius<M_, D_, S_>), grid, dim3(kRadiusThreads), (RadiusLds<D_, S_>::bytes), a.stream, A)
+#define BY_MODE(D_, S_)                                  \
+  switch (mode) {                                        \
+    case R_COUNT: LAUNCH_R(R_COUNT, D_, S_); break;      \
+    case R_EMIT: LAUNCH_R(R_EMIT, D_, S_); break;        \
+    default: LAUNCH_R(R_SELECT, D_, S_); break;          \
   }
   if (small) {
-    BY_MODE(8);
+    if (A.split) BY_MODE(8, true)
+    BY_MODE(8, false)
   } else {
-    BY_MODE(16);
+    if (A.split) BY_MODE(16, true)
+    BY_MODE(16, false)
   }
 #undef BY_MODE
 #undef LAUNCH_R
@@ -640,12 +663,19 @@ int radius_attributes(size_t max_lds) {
   auto set = [&](const void* f) {
     bad |= hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds) != hipSuccess;
   };
-  set(reinterpret_cast<const void*>(k_radius<R_COUNT, 8>));
-  set(reinterpret_cast<const void*>(k_radius<R_EMIT, 8>));
-  set(reinterpret_cast<const void*>(k_radius<R_SELECT, 8>));
-  set(reinterpret_cast<const void*>(k_radius<R_COUNT, 16>));
-  set(reinterpret_cast<const void*>(k_radius<R_EMIT, 16>));
-  set(reinterpret_cast<const void*>(k_radius<R_SELECT, 16>));
+  for (const void* f : {reinterpret_cast<const void*>(k_radius<R_COUNT, 8, false>),
+                        reinterpret_cast<const void*>(k_radius<R_EMIT, 8, false>),
+                        reinterpret_cast<const void*>(k_radius<R_SELECT, 8, false>),
+                        reinterpret_cast<const void*>(k_radius<R_COUNT, 16, false>),
+                        reinterpret_cast<const void*>(k_radius<R_EMIT, 16, false>),
+                        reinterpret_cast<const void*>(k_radius<R_SELECT, 16, false>),
+                        reinterpret_cast<const void*>(k_radius<R_COUNT, 8, true>),
+                        reinterpret_cast<const void*>(k_radius<R_EMIT, 8, true>),
+                        reinterpret_cast<const void*>(k_radius<R_SELECT, 8, true>),
+                        reinterpret_cast<const void*>(k_radius<R_COUNT, 16, true>),
+                        reinterpret_cast<const void*>(k_radius<R_EMIT, 16, true>),
+                        reinterpret_cast<const void*>(k_radius<R_SELECT, 16, true>)})
+    set(f);
   return bad;
 }
 

@@ -32,7 +32,7 @@ ETX_PF_NPARAM = 6 * 32 + 32 + 32 * 32 + 32 + 32 + 1
  ETX_OPT_EDGE_WREG, ETX_OPT_EMBED_PRECISION, ETX_OPT_OUTSUM_LDS, ETX_OPT_F32_SPLIT,
  ETX_OPT_RADIUS_SINGLE_PASS, ETX_OPT_RADIUS_SORT_MIN, ETX_OPT_FUSE_MESSAGES, ETX_OPT_RADIUS_FAST,
  ETX_OPT_XCD_MAP, ETX_OPT_EDGE_PRODUCTS, ETX_OPT_CSC_PLACE, ETX_OPT_COMPACT_STATE,
- ETX_OPT_PROFILE_STAGES, ETX_OPT_PF_FEATURES) = range(22)
+ ETX_OPT_PROFILE_STAGES, ETX_OPT_PF_FEATURES, ETX_OPT_RADIUS_SPLIT) = range(23)
 N_STAGES = 20
 
 

@@ -66,7 +66,8 @@ def test_autotune_graph_and_table_round_trip(uneven, tmp_path):
     assert "edge_threads_x_wg_per_cu" in rec["choice"] and "radius_sort_min" in rec["choice"]
     tuned = {k: etx.etx_get_option(p.ctx, getattr(etx, "ETX_OPT_" + k))
              for k in ("EDGE_WG_SIZE", "EDGE_WG_PER_CU", "EDGE_PIPELINE", "NODE_WG_PER_CU", "FUSE_MESSAGES",
-                       "SEGSUM_UNROLL", "RADIUS_SORT_MIN", "RADIUS_FAST", "XCD_MAP", "EDGE_PRODUCTS", "CSC_PLACE")}
+                       "SEGSUM_UNROLL", "RADIUS_SORT_MIN", "RADIUS_FAST", "XCD_MAP", "EDGE_PRODUCTS", "CSC_PLACE",
+                       "RADIUS_SPLIT")}
     p.run(b)
     r = p.results(b)
     for k in KEYS:

@@ -418,6 +418,34 @@ def test_radius_fast_path_identical(wl, n, trained):
         assert np.array_equal(out[0][k], out[1][k]), k
 
 
+@pytest.mark.parametrize("wl,n,trained", [("c1", 1, False), ("c3", 6, False), ("c2", 2, False), ("c3", 60, True)])
+def test_radius_split_identical(wl, n, trained):
+    """Small windows in a launch of their own (half the staging LDS) and the
+    rest in the usual launch give the same graph and outputs as one launch,
+    bit for bit, on both select paths and with the two-pass search."""
+    etx = _etx()
+    w = synth.WORKLOADS[wl]
+    if trained and not os.path.exists(os.path.join(synth.TRAINED_DIR, f"{w.name}_trained.npz")):
+        pytest.skip("trained weights not built")
+    W = synth.trained_weights(w) if trained else centred_weights(w)
+    batch = synth.generate_batch(w, n)
+    p = etx.Pipeline(w, W)
+    b = etx.to_device(batch)
+    out = {}
+    for single in (1, 0):
+        for fast in (0, 1):
+            for split in (0, 1):
+                etx.etx_set_option(p.ctx, etx.ETX_OPT_RADIUS_SINGLE_PASS, single)
+                etx.etx_set_option(p.ctx, etx.ETX_OPT_RADIUS_FAST, fast)
+                etx.etx_set_option(p.ctx, etx.ETX_OPT_RADIUS_SPLIT, split)
+                assert etx.etx_get_option(p.ctx, etx.ETX_OPT_RADIUS_SPLIT) == split
+                p.run(b)
+                out[single, fast, split] = p.results(b)
+    for key, r in out.items():
+        for k in ("src", "dst", "score", "labels", "edge_off"):
+            assert np.array_equal(out[1, 0, 0][k], r[k]), (key, k)
+
+
 @pytest.mark.parametrize("wl,n,prec", [("c1", 3, 0), ("c3", 40, 0), ("c2", 3, 1), ("c3", 40, 2)])
 def test_xcd_map_identical(wl, n, prec):
     """Contiguous tile ranges per XCD run the same tiles: same bits."""
