@@ -108,13 +108,17 @@ __device__ inline void radius_unit(const RadiusArgs& A, float* lds, int ev, int 
 
   const int P = A.n_planes;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // the status word is read together with the unit's offsets (all in bounds
+  // whatever their contents); nothing read here is used before the check
+  const int64_t status = A.status[0];
   const int64_t a = A.hit_off[ev];
   const int32_t* po = A.plane_off + (int64_t)ev * (P + 1);
   const int s0 = po[p], s1 = po[p + 1];
+  const int nwin = window_hits(po, p, P, A.window);
+  if (status != 0) return;
   const int nsrc = s1 - s0;
   if (nsrc == 0) return;
   const int w0 = s1;
-  const int nwin = window_hits(po, p, P, A.window);
   // split launches: each unit goes to exactly one of the two
   if (A.split && (SMALL ? nwin > CAP : nwin <= RadiusLds<DP, true>::cap)) return;
   const int32_t* wb = A.bucket + a + w0;
@@ -123,6 +127,24 @@ __device__ inline void radius_unit(const RadiusArgs& A, float* lds, int ev, int 
   // and each source scans only the cells within reach; smaller ones are
   // scanned whole
   const bool sorted = staged && nwin >= A.sort_min;
+  // Fast path of the select pass over a staged window (below): four sources
+  // per wave.  Each row's first source index is loaded now, beside the
+  // window's, and its embedding row once the window is staged, so that both
+  // arrive while the cell list is built; later sources are fetched one
+  // iteration ahead.
+  const bool fast = MODE == R_SELECT && A.fast && staged && nsrc <= (sorted ? CAP - kCells : CAP);
+  const int sub = lane >> 4, l16 = lane & 15;
+  int32_t i_pf = 0;
+  float4 e_pf[DP / 4];
+  if (fast && wave * 4 + sub < nsrc) i_pf = A.bucket[a + s0 + wave * 4 + sub];
+  bool pf_done = false;
+  auto prefetch_row = [&](bool live) {
+#pragma unroll
+    for (int q = 0; q < DP / 4; ++q)
+      e_pf[q] = live ? *reinterpret_cast<const float4*>(A.emb + (int64_t)i_pf * kDpad + 4 * q)
+                     : make_float4(0.f, 0.f, 0.f, 0.f);
+    pf_done = true;
+  };
   // cell list of a sorted window (in the key array's place): cend[k] ends up
   // as the end of cell k in the slot order sidx
   int* cend = reinterpret_cast<int*>(skey);
@@ -139,6 +161,7 @@ __device__ inline void radius_unit(const RadiusArgs& A, float* lds, int ev, int 
       for (int q = 0; q < DP; q += 4)
         *reinterpret_cast<float4*>(cemb + c * DP + q) = *reinterpret_cast<const float4*>(A.emb + (int64_t)j * kDpad + q);
     }
+    if (fast) prefetch_row(wave * 4 + sub < nsrc);
     __syncthreads();
   }
   if (sorted && nwin > 0) {
@@ -162,6 +185,7 @@ __device__ inline void radius_unit(const RadiusArgs& A, float* lds, int ev, int 
         lo[q + 3] = fminf(lo[q + 3], v.w); hi[q + 3] = fmaxf(hi[q + 3], v.w);
       }
     }
+    if (fast) prefetch_row(wave * 4 + sub < nsrc);
     // block max of each axis range through the per-wave lists (reused as scratch)
 #pragma unroll
     for (int k = 0; k < DP; ++k) {
@@ -176,28 +200,28 @@ __device__ inline void radius_unit(const RadiusArgs& A, float* lds, int ev, int 
       }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      int best = 0;
-      float bw = -1.f;
-      for (int k = 0; k < A.dim; ++k) {
-        float l = INFINITY, h = -INFINITY;
-        for (int w = 0; w < kRadiusWaves; ++w) {
-          l = fminf(l, ld2[w * DP + k]);
-          h = fmaxf(h, ld2[kRadiusWaves * DP + w * DP + k]);
-        }
-        if (h - l > bw) {
-          bw = h - l;
-          best = k;
-        }
-      }
-      misc[0] = best;
+    if (wave == 0) {
+      // one lane per axis: its range over the waves (in wave order), then the
+      // widest axis, the first one among equal widths (an axis whose width is
+      // not above -1, or NaN, is never chosen; none: axis 0)
       float l = INFINITY, h = -INFINITY;
-      for (int w = 0; w < kRadiusWaves; ++w) {
-        l = fminf(l, ld2[w * DP + best]);
-        h = fmaxf(h, ld2[kRadiusWaves * DP + w * DP + best]);
+      if (lane < A.dim) {
+        for (int w = 0; w < kRadiusWaves; ++w) {
+          l = fminf(l, ld2[w * DP + lane]);
+          h = fmaxf(h, ld2[kRadiusWaves * DP + w * DP + lane]);
+        }
       }
-      misc[2] = __float_as_int(l);
-      misc[3] = __float_as_int(h);
+      const float wd = h - l;
+      const bool valid = lane < A.dim && wd > -1.f;
+      float m = valid ? wd : -INFINITY;
+      for (int d = 32; d > 0; d >>= 1) m = fmaxf(m, __shfl_xor(m, d));
+      const uint64_t at = __ballot(valid && wd == m);
+      const int best = at ? __ffsll((unsigned long long)at) - 1 : 0;
+      if (lane == best) {
+        misc[0] = best;
+        misc[2] = __float_as_int(l);
+        misc[3] = __float_as_int(h);
+      }
     }
     __syncthreads();
     // cell list along that axis: cells about r wide over the window's extent
@@ -269,24 +293,24 @@ __device__ inline void radius_unit(const RadiusArgs& A, float* lds, int ev, int 
   // targets, ranked by index, are exactly what the full path keeps.  Other
   // sources go to a list (the slot array of a scanned window, the key array
   // past the cell ends of a sorted one) for the one-wave-per-source path.
-  const bool fast = MODE == R_SELECT && A.fast && staged && nsrc <= (sorted ? CAP - kCells : CAP);
   int* hard = sorted ? cend + kCells : sidx;
   int nwork = nsrc;
   if (fast) {
+    if (!pf_done) prefetch_row(wave * 4 + sub < nsrc);
     if (threadIdx.x == 0) misc[1] = 0;
     __syncthreads();
-    const int sub = lane >> 4, l16 = lane & 15;
     int* sb = sl + 16 * sub;
     for (int s4 = wave * 4; s4 < nsrc; s4 += kRadiusWaves * 4) {
       const int s = s4 + sub;
       const bool live = s < nsrc;
-      const int32_t i = live ? A.bucket[a + s0 + s] : 0;
+      const int32_t i = i_pf;
       float se[DP];
 #pragma unroll
-      for (int q = 0; q < DP; q += 4) {
-        const float4 v = *reinterpret_cast<const float4*>(A.emb + (int64_t)i * kDpad + q);
-        se[q] = v.x; se[q + 1] = v.y; se[q + 2] = v.z; se[q + 3] = v.w;
+      for (int q = 0; q < DP / 4; ++q) {
+        se[4 * q] = e_pf[q].x; se[4 * q + 1] = e_pf[q].y; se[4 * q + 2] = e_pf[q].z; se[4 * q + 3] = e_pf[q].w;
       }
+      const bool live_next = s + kRadiusWaves * 4 < nsrc;
+      i_pf = live_next ? A.bucket[a + s0 + s + kRadiusWaves * 4] : 0;
       int cb, ce;
       range(se, cb, ce);
       // the longest of the four ranges (rows hold one value each)
@@ -310,6 +334,7 @@ __device__ inline void radius_unit(const RadiusArgs& A, float* lds, int ev, int 
         }
         n += __popc(m);
       }
+      prefetch_row(live_next);
       wave_sync();
       const bool done = live && n <= 16 && n <= A.k_max;
       if (done) {
@@ -548,7 +573,6 @@ __device__ inline void radius_unit(const RadiusArgs& A, float* lds, int ev, int 
 // One workgroup per (event, plane) unit.
 template <int MODE, int DP, bool SMALL>
 __global__ __launch_bounds__(kRadiusThreads) void k_radius(RadiusArgs A) {
-  if (A.status[0] != 0) return;
   extern __shared__ float lds[];
   radius_unit<MODE, DP, SMALL>(A, lds, blockIdx.x / A.n_planes, blockIdx.x % A.n_planes);
 }
