@@ -92,7 +92,10 @@ __global__ void k_hit_polar(int64_t n, const float* __restrict__ x, const float*
     polar[i] = make_float2(hypotf(x[i], y[i]), atan2f(y[i], x[i]));
 }
 
-// Features of a candidate edge (every lane of the column computes them).
+// Features of a candidate edge.  DP: the embedding width rounded up to 8 or
+// 16; the padding of a row up to 16 floats is zero and would add exact zeros
+// to the squared distance, so it is not read.
+template <int DP>
 __device__ inline void edge_features(const PfArgs& A, int s, int d, float (&f)[6]) {
   const float xi = A.x[s], yi = A.y[s], zi = A.z[s], xj = A.x[d], yj = A.y[d], zj = A.z[d];
   const float2 pi_ = A.polar[s], pj = A.polar[d];
@@ -104,7 +107,7 @@ __device__ inline void edge_features(const PfArgs& A, int s, int d, float (&f)[6
   const float* ei = A.emb + (int64_t)s * kDpad;
   const float* ej = A.emb + (int64_t)d * kDpad;
 #pragma unroll
-  for (int k = 0; k < kDpad; k += 4) {
+  for (int k = 0; k < DP; k += 4) {
     const float4 u = *reinterpret_cast<const float4*>(ei + k), v = *reinterpret_cast<const float4*>(ej + k);
     const float t0 = v.x - u.x, t1 = v.y - u.y, t2 = v.z - u.z, t3 = v.w - u.w;
     d2 = fmaf(t0, t0, d2);
@@ -120,8 +123,9 @@ __device__ inline void edge_features(const PfArgs& A, int s, int d, float (&f)[6
   f[5] = sqrtf(d2);
 }
 
-template <bool TRAIN>
+template <bool TRAIN, int DP>
 __global__ __launch_bounds__(kPfThreads) void k_pf(PfArgs A) {
+  static_assert(DP == 8 || DP == 16, "embedding width rounded up to 8 or 16");
   if (A.status[0] != 0) return;
   __shared__ PfLds L;
   __shared__ float tr[kPfWaves][16 * 32 * 3 + 16 * 16];   // per-wave transposes (training)
@@ -146,91 +150,117 @@ __global__ __launch_bounds__(kPfThreads) void k_pf(PfArgs A) {
     wave_sync();
   }
   const int64_t ntiles = (E + kCols - 1) / kCols;
-  for (int64_t tile = (int64_t)blockIdx.x * kPfWaves + wave; tile < ntiles; tile += (int64_t)gridDim.x * kPfWaves) {
-    const int64_t col = tile * kCols + j;
-    const bool valid = col < E;
-    float f[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if (valid) edge_features(A, A.src[col], A.dst[col], f);
-    float z1[8], a1[8];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const int c = phi(r, g);
-      float acc = L.b1[c];
-#pragma unroll
-      for (int k = 0; k < 6; ++k) acc = fmaf(f[k], L.w1[k * PF + c], acc);
-      z1[r] = acc;
-      a1[r] = fmaxf(acc, 0.f);
+  const int64_t tstride = (int64_t)gridDim.x * kPfWaves;
+  // The wave's tiles are t0, t0 + tstride, ...; per round lane group g
+  // gathers the features of tile t0 + g * tstride (four tiles' loads in
+  // flight), then the four tiles run through the network in order, each
+  // taking its features from its group.  Edge ends are loaded a round ahead.
+  int s_next = 0, d_next = 0;
+  auto fetch_ends = [&](int64_t t0) {
+    const int64_t t = t0 + g * tstride, c = t * kCols + j;
+    if (t < ntiles && c < E) {
+      s_next = A.src[c];
+      d_next = A.dst[c];
     }
-    float z2[8];
-    bias_cols<PF>(z2, L.b2);
-    mfma_bf16<PF, 2>(z2, a1, L.w2p);
-    float a2[8];
-    float dot = 0.f;
+  };
+  const int64_t first = (int64_t)blockIdx.x * kPfWaves + wave;
+  fetch_ends(first);
+  for (int64_t t0 = first; t0 < ntiles; t0 += 4 * tstride) {
+    const int64_t tg = t0 + g * tstride;
+    const bool vg = tg < ntiles && tg * kCols + j < E;
+    const int s_cur = s_next, d_cur = d_next;
+    fetch_ends(t0 + 4 * tstride);
+    float fg[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (vg) edge_features<DP>(A, s_cur, d_cur, fg);
+    for (int u = 0; u < 4; ++u) {
+      const int64_t tile = t0 + u * tstride;
+      if (tile >= ntiles) break;   // wave-uniform
+      const int64_t col = tile * kCols + j;
+      const bool valid = col < E;
+      float f[6];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      a2[r] = fmaxf(z2[r], 0.f);
-      dot = fmaf(a2[r], L.w3[phi(r, g)], dot);
-    }
-    const float z3 = col_sum(dot) + L.b3[0];
-    const float prob = 1.0f / (1.0f + expf(-z3));
-    if (!TRAIN) {
+      for (int k = 0; k < 6; ++k) f[k] = __shfl(fg[k], j + 16 * u);
+      float z1[8], a1[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int c = phi(r, g);
+        float acc = L.b1[c];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) acc = fmaf(f[k], L.w1[k * PF + c], acc);
+        z1[r] = acc;
+        a1[r] = fmaxf(acc, 0.f);
+      }
+      float z2[8];
+      bias_cols<PF>(z2, L.b2);
+      mfma_bf16<PF, 2>(z2, a1, L.w2p);
+      float a2[8];
+      float dot = 0.f;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        a2[r] = fmaxf(z2[r], 0.f);
+        dot = fmaf(a2[r], L.w3[phi(r, g)], dot);
+      }
+      const float z3 = col_sum(dot) + L.b3[0];
+      const float prob = 1.0f / (1.0f + expf(-z3));
+      if (!TRAIN) {
+        if (valid && g == 0) {
+          A.keep[col] = prob >= A.tau ? 1 : 0;
+          A.prob[col] = prob;
+          if (A.feat) {
+            float4* fo = reinterpret_cast<float4*>(A.feat + col * 8);
+            fo[0] = make_float4(f[0], f[1], f[2], f[3]);
+            fo[1] = make_float4(f[4], f[5], 0.f, 0.f);
+          }
+        }
+        continue;
+      }
+      const bool y = valid && A.label[col] != 0;
+      const float wt = y ? A.pos_weight : 1.f;
+      const float dz = valid ? wt * (prob - (y ? 1.f : 0.f)) * inv_n : 0.f;
       if (valid && g == 0) {
-        A.keep[col] = prob >= A.tau ? 1 : 0;
-        A.prob[col] = prob;
-        if (A.feat) {
-          float4* fo = reinterpret_cast<float4*>(A.feat + col * 8);
-          fo[0] = make_float4(f[0], f[1], f[2], f[3]);
-          fo[1] = make_float4(f[4], f[5], 0.f, 0.f);
+        const float v = y ? -z3 : z3;       // softplus(v) = max(v, 0) + log1p(exp(-|v|))
+        loss += wt * (fmaxf(v, 0.f) + log1pf(expf(-fabsf(v))));
+        gb3 += dz;
+      }
+      float d2[8], t1[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        d2[r] = z2[r] > 0.f ? L.w3[phi(r, g)] * dz : 0.f;
+        t1[r] = 0.f;
+      }
+      mfma_bf16<PF, 2>(t1, d2, L.w2tp);     // W2 delta2
+      float d1[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        d1[r] = z1[r] > 0.f ? t1[r] : 0.f;
+        gw3[r] = fmaf(a2[r], dz, gw3[r]);
+        gb2[r] += d2[r];
+        gb1[r] += d1[r];
+        const int c = phi(r, g);
+        a1t[j * 32 + c] = a1[r];
+        d2t[j * 32 + c] = d2[r];
+        d1t[j * 32 + c] = d1[r];
+      }
+      if (g == 0)
+#pragma unroll
+        for (int k = 0; k < 6; ++k) ft[j * 16 + k] = f[k];
+      wave_sync();
+      // weight gradients: sums over the tile's 16 edges as FP32 MFMA with K = edges
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int e = 4 * t + (lane >> 4);
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+          const float b2v = d2t[e * 32 + 16 * nb + (lane & 15)];
+          const float b1v = d1t[e * 32 + 16 * nb + (lane & 15)];
+#pragma unroll
+          for (int mb = 0; mb < 2; ++mb)
+            gw2[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1t[e * 32 + 16 * mb + (lane & 15)], b2v, gw2[mb][nb], 0, 0, 0);
+          gw1[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ft[e * 16 + (lane & 15)], b1v, gw1[nb], 0, 0, 0);
         }
       }
-      continue;
+      wave_sync();
     }
-    const bool y = valid && A.label[col] != 0;
-    const float wt = y ? A.pos_weight : 1.f;
-    const float dz = valid ? wt * (prob - (y ? 1.f : 0.f)) * inv_n : 0.f;
-    if (valid && g == 0) {
-      const float v = y ? -z3 : z3;       // softplus(v) = max(v, 0) + log1p(exp(-|v|))
-      loss += wt * (fmaxf(v, 0.f) + log1pf(expf(-fabsf(v))));
-      gb3 += dz;
-    }
-    float d2[8], t1[8];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      d2[r] = z2[r] > 0.f ? L.w3[phi(r, g)] * dz : 0.f;
-      t1[r] = 0.f;
-    }
-    mfma_bf16<PF, 2>(t1, d2, L.w2tp);     // W2 delta2
-    float d1[8];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      d1[r] = z1[r] > 0.f ? t1[r] : 0.f;
-      gw3[r] = fmaf(a2[r], dz, gw3[r]);
-      gb2[r] += d2[r];
-      gb1[r] += d1[r];
-      const int c = phi(r, g);
-      a1t[j * 32 + c] = a1[r];
-      d2t[j * 32 + c] = d2[r];
-      d1t[j * 32 + c] = d1[r];
-    }
-    if (g == 0)
-#pragma unroll
-      for (int k = 0; k < 6; ++k) ft[j * 16 + k] = f[k];
-    wave_sync();
-    // weight gradients: sums over the tile's 16 edges as FP32 MFMA with K = edges
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int e = 4 * t + (lane >> 4);
-#pragma unroll
-      for (int nb = 0; nb < 2; ++nb) {
-        const float b2v = d2t[e * 32 + 16 * nb + (lane & 15)];
-        const float b1v = d1t[e * 32 + 16 * nb + (lane & 15)];
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
-          gw2[mb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1t[e * 32 + 16 * mb + (lane & 15)], b2v, gw2[mb][nb], 0, 0, 0);
-        gw1[nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ft[e * 16 + (lane & 15)], b1v, gw1[nb], 0, 0, 0);
-      }
-    }
-    wave_sync();
   }
   if (!TRAIN) return;
   float* out = A.partial + ((int64_t)blockIdx.x * kPfWaves + wave) * kPfGradStride;
@@ -274,14 +304,40 @@ __global__ __launch_bounds__(kPfThreads) void k_pf(PfArgs A) {
   }
 }
 
-// gradient = sum of the per-wave partials in wave order (deterministic)
+// Gradient = sum of the per-wave partials in a fixed order (deterministic):
+// the waves are cut into kPfChunks chunks of consecutive waves, each summed
+// in wave order by its own thread per parameter (the result replaces the
+// chunk's first row, which only that thread reads), then the chunk sums are
+// added in chunk order.
+constexpr int kPfChunks = 64;
+
+__global__ void k_pf_reduce_chunks(float* __restrict__ partial, int n_waves, const int64_t* status) {
+  if (status[0] != 0) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int per = (n_waves + kPfChunks - 1) / kPfChunks;
+  const int w0 = blockIdx.y * per, w1 = min(w0 + per, n_waves);
+  if (i > N_P || w0 >= w1) return;
+  float s = 0.f;
+  int w = w0;
+  for (; w + 8 <= w1; w += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = partial[(int64_t)(w + u) * kPfGradStride + i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; w < w1; ++w) s += partial[(int64_t)w * kPfGradStride + i];
+  partial[(int64_t)w0 * kPfGradStride + i] = s;
+}
+
 __global__ void k_pf_reduce(const float* __restrict__ partial, int n_waves, float* __restrict__ grad, float* loss,
                             const int64_t* status) {
   if (status[0] != 0) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i > N_P) return;
+  const int per = (n_waves + kPfChunks - 1) / kPfChunks;
   float s = 0.f;
-  for (int w = 0; w < n_waves; ++w) s += partial[(int64_t)w * kPfGradStride + i];
+  for (int w0 = 0; w0 < n_waves; w0 += per) s += partial[(int64_t)w0 * kPfGradStride + i];
   grad[i] = s;
   if (i == N_P && loss) *loss = s;
 }
@@ -329,29 +385,65 @@ __global__ __launch_bounds__(256) void k_pf_band(int64_t n_events, const int64_t
   }
 }
 
-// surviving candidates per source, and their compaction into the output edge
-// list; one thread per source (rows hold at most k_max <= 64 candidates)
+// Surviving candidates per source (!WRITE) and their compaction into the
+// output edge list (WRITE).  A workgroup takes 256 sources at a time; their
+// candidate rows are one contiguous range, read 256 candidates per round
+// (coalesced).  Counting adds each kept candidate to its source's LDS
+// counter; compaction gives a kept candidate the rank of its keep flag in
+// the range (wave ballots, then the waves' sums in order) past the output
+// offset of the first source, which is where the per-source walk put it.
+constexpr int kPfRowHits = 256;
+
 template <bool WRITE>
-__global__ __launch_bounds__(256) void k_pf_rows(int64_t n_hits, const int64_t* __restrict__ cand_ptr,
-                                                 const uint8_t* __restrict__ keep, int32_t* __restrict__ cnt,
-                                                 const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ csrc,
-                                                 const int32_t* __restrict__ cdst, int32_t* __restrict__ src,
-                                                 int32_t* __restrict__ dst, const int64_t* status) {
+__global__ __launch_bounds__(kPfRowHits) void k_pf_rows(int64_t n_hits, const int64_t* __restrict__ cand_ptr,
+                                                        const uint8_t* __restrict__ keep, int32_t* __restrict__ cnt,
+                                                        const int64_t* __restrict__ row_ptr,
+                                                        const int32_t* __restrict__ csrc, const int32_t* __restrict__ cdst,
+                                                        int32_t* __restrict__ src, int32_t* __restrict__ dst,
+                                                        const int64_t* status) {
   if (status[0] != 0) return;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_hits; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t cb = cand_ptr[i], ce = cand_ptr[i + 1];
+  constexpr int kWaves = kPfRowHits / 64;
+  __shared__ int lc[kPfRowHits];
+  __shared__ int wsum[kWaves];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t h0 = (int64_t)blockIdx.x * kPfRowHits; h0 < n_hits; h0 += (int64_t)gridDim.x * kPfRowHits) {
+    const int64_t h1 = min(h0 + kPfRowHits, n_hits);
+    const int64_t q0 = cand_ptr[h0], q1 = cand_ptr[h1];
     if (!WRITE) {
-      int c = 0;
-      for (int64_t q = cb; q < ce; ++q) c += keep[q];
-      cnt[i] = c;
-    } else {
-      int64_t pos = row_ptr[i];
-      for (int64_t q = cb; q < ce; ++q)
-        if (keep[q]) {
+      lc[threadIdx.x] = 0;
+      __syncthreads();
+    }
+    int64_t out = WRITE ? row_ptr[h0] : 0;
+    for (int64_t b = q0; b < q1; b += kPfRowHits) {
+      const int64_t q = b + threadIdx.x;
+      const bool k = q < q1 && keep[q] != 0;
+      if (!WRITE) {
+        // the candidate's source is its row's hit, one of this block's
+        const int r = k ? csrc[q] - (int)h0 : -1;
+        if (r >= 0 && r < kPfRowHits) atomicAdd(&lc[r], 1);
+      } else {
+        const uint64_t m = __ballot(k);
+        if (lane == 0) wsum[wave] = __popcll(m);
+        __syncthreads();
+        int before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+          before += w < wave ? wsum[w] : 0;
+          total += wsum[w];
+        }
+        if (k) {
+          const int64_t pos = out + before + __popcll(m & ((1ull << lane) - 1ull));
           src[pos] = csrc[q];
           dst[pos] = cdst[q];
-          ++pos;
         }
+        out += total;
+        __syncthreads();   // wsum is reused by the next round
+      }
+    }
+    if (!WRITE) {
+      __syncthreads();
+      if (h0 + threadIdx.x < h1) cnt[h0 + threadIdx.x] = lc[threadIdx.x];
+      __syncthreads();     // lc is cleared for the next block of sources
     }
   }
 }
@@ -394,7 +486,10 @@ hipError_t launch_prefilter_infer(const RunArgs& a) {
   PfArgs A = pf_args(a, true);
   launch_polar(a);
   // inference keeps no per-wave partials: a full grid of persistent waves
-  hipLaunchKernelGGL(k_pf<false>, dim3((unsigned)(a.ctx->n_cu * 4)), dim3(kPfThreads), 0, a.stream, A);
+  if (a.ctx->cfg.emb_dim <= 8)
+    hipLaunchKernelGGL((k_pf<false, 8>), dim3((unsigned)(a.ctx->n_cu * 4)), dim3(kPfThreads), 0, a.stream, A);
+  else
+    hipLaunchKernelGGL((k_pf<false, 16>), dim3((unsigned)(a.ctx->n_cu * 4)), dim3(kPfThreads), 0, a.stream, A);
   return hipGetLastError();
 }
 
@@ -410,18 +505,19 @@ hipError_t launch_prefilter_band(const RunArgs& a) {
 
 hipError_t launch_prefilter_count(const RunArgs& a) {
   if (a.hits.n_hits == 0) return hipSuccess;
-  unsigned grid = (unsigned)std::min<int64_t>((a.hits.n_hits + 255) / 256, (int64_t)a.ctx->n_cu * 16);
-  hipLaunchKernelGGL(k_pf_rows<false>, dim3(grid), dim3(256), 0, a.stream, a.hits.n_hits,
+  unsigned grid = (unsigned)std::min<int64_t>((a.hits.n_hits + kPfRowHits - 1) / kPfRowHits, (int64_t)a.ctx->n_cu * 16);
+  hipLaunchKernelGGL(k_pf_rows<false>, dim3(grid), dim3(kPfRowHits), 0, a.stream, a.hits.n_hits,
                      reinterpret_cast<const int64_t*>(a.ws + a.L.pf_tmp),
                      reinterpret_cast<const uint8_t*>(a.ws + a.L.pf_keep), reinterpret_cast<int32_t*>(a.ws + a.L.cnt),
-                     nullptr, nullptr, nullptr, nullptr, nullptr, a.out.status);
+                     nullptr, reinterpret_cast<const int32_t*>(a.ws + a.L.cand_src), nullptr, nullptr, nullptr,
+                     a.out.status);
   return hipGetLastError();
 }
 
 hipError_t launch_prefilter_compact(const RunArgs& a) {
   if (a.hits.n_hits == 0) return hipSuccess;
-  unsigned grid = (unsigned)std::min<int64_t>((a.hits.n_hits + 255) / 256, (int64_t)a.ctx->n_cu * 16);
-  hipLaunchKernelGGL(k_pf_rows<true>, dim3(grid), dim3(256), 0, a.stream, a.hits.n_hits,
+  unsigned grid = (unsigned)std::min<int64_t>((a.hits.n_hits + kPfRowHits - 1) / kPfRowHits, (int64_t)a.ctx->n_cu * 16);
+  hipLaunchKernelGGL(k_pf_rows<true>, dim3(grid), dim3(kPfRowHits), 0, a.stream, a.hits.n_hits,
                      reinterpret_cast<const int64_t*>(a.ws + a.L.pf_tmp),
                      reinterpret_cast<const uint8_t*>(a.ws + a.L.pf_keep), nullptr,
                      reinterpret_cast<const int64_t*>(a.ws + a.L.row_ptr),
@@ -437,8 +533,13 @@ hipError_t launch_prefilter_train(const RunArgs& a, const uint8_t* labels, float
   A.pos_weight = pos_weight;
   launch_polar(a);
   const unsigned grid = pf_grid(a.ctx);
-  hipLaunchKernelGGL(k_pf<true>, dim3(grid), dim3(kPfThreads), 0, a.stream, A);
+  if (a.ctx->cfg.emb_dim <= 8)
+    hipLaunchKernelGGL((k_pf<true, 8>), dim3(grid), dim3(kPfThreads), 0, a.stream, A);
+  else
+    hipLaunchKernelGGL((k_pf<true, 16>), dim3(grid), dim3(kPfThreads), 0, a.stream, A);
   float* grad = reinterpret_cast<float*>(a.ws + a.L.pf_grad);
+  hipLaunchKernelGGL(k_pf_reduce_chunks, dim3((N_P + 1 + 255) / 256, kPfChunks), dim3(256), 0, a.stream, A.partial,
+                     (int)(grid * kPfWaves), a.out.status);
   hipLaunchKernelGGL(k_pf_reduce, dim3((N_P + 1 + 255) / 256), dim3(256), 0, a.stream, A.partial,
                      (int)(grid * kPfWaves), grad, loss_dev, a.out.status);
   const double b1 = 0.9, b2 = 0.999;
