@@ -42,12 +42,26 @@ __global__ __launch_bounds__(256) void k_embed(EmbedArgs A) {
   const SegEmb S{W, A.layers, PrecBytes<P>::value};
   const int lane = lane_id(), g = lane_group(), wave = threadIdx.x >> 6;
   const int64_t ntiles = (A.n_hits + kCols - 1) / kCols;
-  for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
+  const int64_t tstride = (int64_t)gridDim.x * 4;
+  // the next tile's coordinates are loaded one tile ahead
+  float xn = 0.f, yn = 0.f, zn = 0.f;
+  auto fetch = [&](int64_t t) {
+    const int64_t c = t * kCols + (lane & 15);
+    if (t < ntiles && c < A.n_hits) {
+      xn = A.x[c];
+      yn = A.y[c];
+      zn = A.z[c];
+    }
+  };
+  int64_t tile = (int64_t)blockIdx.x * 4 + wave;
+  fetch(tile);
+  for (; tile < ntiles; tile += tstride) {
     const int64_t col = tile * kCols + (lane & 15);
     const bool valid = col < A.n_hits;
+    const float xx = xn, yy = yn, zz = zn;
+    fetch(tile + tstride);
     float u0 = 0.f, u1 = 0.f, u2 = 0.f;
     if (valid) {
-      const float xx = A.x[col], yy = A.y[col], zz = A.z[col];
       u0 = hypotf(xx, yy) * A.inv_r;
       u1 = atan2f(yy, xx) * 0.318309886183790672f;   // 1/pi
       u2 = zz * A.inv_z;
@@ -115,8 +129,15 @@ hipError_t launch_embed(const RunArgs& a) {
   A.seg_bytes = SegEmb{W, A.layers, kSegBytes[prec]}.size();
   size_t lds = A.seg_bytes;
   int64_t tiles = (A.n_hits + kCols - 1) / kCols;
-  unsigned grid = (unsigned)std::min<int64_t>((tiles + 3) / 4, (int64_t)c->n_cu * 2);
-#define EMB(W_, P_) hipLaunchKernelGGL((k_embed<W_, P_>), dim3(grid), dim3(256), lds, a.stream, A)
+  // as many workgroups as are resident at once (registers or LDS decide)
+  auto resident = [&](const void* f) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 256, lds) != hipSuccess || nb < 1) nb = 2;
+    return (unsigned)std::min<int64_t>((tiles + 3) / 4, (int64_t)c->n_cu * nb);
+  };
+#define EMB(W_, P_)                                                                          \
+  hipLaunchKernelGGL((k_embed<W_, P_>), dim3(resident(reinterpret_cast<const void*>(k_embed<W_, P_>))), dim3(256), \
+                     lds, a.stream, A)
   switch (W * 8 + kp) {
     case 32 * 8 + 0: EMB(32, 0); break;
     case 32 * 8 + 1: EMB(32, 1); break;
