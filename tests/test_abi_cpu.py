@@ -95,3 +95,20 @@ def test_checkpoint_load_rejects_foreign_buffers_on_host():
     n = C.c_size_t()
     assert L.etx_save(None, None, C.byref(n)) == etx.ETX_ERR_INVALID_ARG
     assert L.etx_load(None, 0, 0, C.byref(ctx)) == etx.ETX_ERR_INVALID_ARG
+
+
+def test_binding_constants_match_the_header():
+    """Every enumerator of the header (statuses, precisions, options, views,
+    stages) exists in the binding with the same value, and so do the numeric
+    macros the binding mirrors."""
+    src = open(HEADER).read()
+    enums = re.findall(r"^\s*(ETX_[A-Z0-9_]+)\s*=\s*(-?\d+)", src, re.M)
+    assert len(enums) > 40
+    for name, value in enums:
+        assert getattr(etx, name, None) == int(value), name
+    for name, expr in re.findall(r"^#define\s+(ETX_[A-Z0-9_]+)\s+(\(?[0-9u <()*+-]+\)?)\s*$", src, re.M):
+        if hasattr(etx, name):
+            assert getattr(etx, name) == eval(expr.replace("u", "")), name
+    body = re.search(r"#define\s+ETX_TRIPLET_NPARAM\(H\)\s+(.+)", src).group(1)
+    for h in (32, 64):
+        assert etx.ETX_TRIPLET_NPARAM(h) == eval(body.replace("(H)", f"({h})")), h
