@@ -200,15 +200,29 @@ __global__ void k_edge_off(const int64_t* __restrict__ hit_off, int64_t n_events
 // one wave (place = 0).  All keep (dst, src) order.
 constexpr int kCscRowWalk = 16;
 
+// The per-event kernels that keep one LDS word per hit of the event run as
+// two launches: events of up to kSmallEventHits hits in workgroups with 16 KiB
+// of LDS (eight to a CU, so that their chains of loads and barriers overlap),
+// the larger ones with room for ETX_MAX_EVENT_HITS; each launch skips the
+// other's events.
+constexpr int kSmallEventHits = 4096;
+
+template <int CAP>
+__device__ inline bool event_in_launch(int n) {
+  return CAP == kSmallEventHits ? n <= kSmallEventHits : n > kSmallEventHits;
+}
+
+template <int CAP>
 __global__ __launch_bounds__(256) void k_csc(const int64_t* __restrict__ hit_off, const int64_t* __restrict__ row_ptr,
                                              const int32_t* __restrict__ dst, int64_t* __restrict__ col_ptr,
                                              int32_t* __restrict__ csc, int place, const int64_t* status) {
   if (status[0] != 0) return;
-  __shared__ int cur[ETX_MAX_EVENT_HITS];
+  __shared__ int cur[CAP];
   __shared__ int tmp[4];
   const int ev = blockIdx.x, t = threadIdx.x, lane = t & 63;
   const int64_t a = hit_off[ev];
   const int n = (int)(hit_off[ev + 1] - a);
+  if (!event_in_launch<CAP>(n)) return;
   const int64_t eb = row_ptr[a], ee = row_ptr[a + n];
   for (int i = t; i < n; i += 256) cur[i] = 0;
   __syncthreads();
@@ -404,15 +418,17 @@ __device__ inline void uf_unite(volatile int* par, int u, int v) {
   }
 }
 
+template <int CAP>
 __global__ __launch_bounds__(256) void k_union_find(const int64_t* __restrict__ hit_off, const int64_t* __restrict__ row_ptr,
                                                     const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
                                                     const int32_t* __restrict__ kept, const int32_t* __restrict__ kept_cnt,
                                                     int32_t* __restrict__ labels, const int64_t* status) {
   if (status[0] != 0) return;
-  __shared__ int par[ETX_MAX_EVENT_HITS];
+  __shared__ int par[CAP];
   const int ev = blockIdx.x;
   const int64_t a = hit_off[ev];
   const int n = (int)(hit_off[ev + 1] - a);
+  if (!event_in_launch<CAP>(n)) return;
   const int64_t eb = row_ptr[a];
   const int nk = kept_cnt[ev];
   for (int i = threadIdx.x; i < n; i += 256) par[i] = i;
@@ -481,9 +497,13 @@ hipError_t launch_scan_counts(const RunArgs& a, bool candidates) {
 
 hipError_t launch_csc(const RunArgs& a) {
   if (a.hits.n_events == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_csc, dim3((unsigned)a.hits.n_events), dim3(256), 0, a.stream, a.hits.hit_off,
-                     WS(a, row_ptr, int64_t), a.out.dst, WS(a, col_ptr, int64_t), WS(a, csc, int32_t),
-                     a.ctx->csc_place, a.out.status);
+#define CSC(C_)                                                                                           \
+  hipLaunchKernelGGL(k_csc<C_>, dim3((unsigned)a.hits.n_events), dim3(256), 0, a.stream, a.hits.hit_off,  \
+                     WS(a, row_ptr, int64_t), a.out.dst, WS(a, col_ptr, int64_t), WS(a, csc, int32_t),     \
+                     a.ctx->csc_place, a.out.status)
+  CSC(kSmallEventHits);
+  CSC(ETX_MAX_EVENT_HITS);
+#undef CSC
   return hipGetLastError();
 }
 
@@ -497,9 +517,13 @@ hipError_t launch_compact(const RunArgs& a) {
 
 hipError_t launch_union_find(const RunArgs& a) {
   if (a.hits.n_events == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_union_find, dim3((unsigned)a.hits.n_events), dim3(256), 0, a.stream, a.hits.hit_off,
-                     WS(a, row_ptr, int64_t), a.out.src, a.out.dst, WS(a, kept, int32_t), WS(a, kept_cnt, int32_t),
-                     a.out.labels, a.out.status);
+#define UF(C_)                                                                                                   \
+  hipLaunchKernelGGL(k_union_find<C_>, dim3((unsigned)a.hits.n_events), dim3(256), 0, a.stream, a.hits.hit_off,  \
+                     WS(a, row_ptr, int64_t), a.out.src, a.out.dst, WS(a, kept, int32_t), WS(a, kept_cnt, int32_t), \
+                     a.out.labels, a.out.status)
+  UF(kSmallEventHits);
+  UF(ETX_MAX_EVENT_HITS);
+#undef UF
   return hipGetLastError();
 }
 
