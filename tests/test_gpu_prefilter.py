@@ -280,3 +280,35 @@ def test_fallback_band_runs_events_unpruned(setup):
         assert np.abs(got["score"][a0:a1].astype(np.float64) - ref["score"][r0:r1]).max(initial=0) <= 1e-5
     with pytest.raises(etx.EtxError):
         etx.etx_prefilter_band(p.ctx, 0.6, 0.5)
+
+
+@pytest.mark.parametrize("tau", [0.5, 1.5])
+def test_pruned_graph_is_the_filtered_candidate_list_across_events(tau):
+    """A 30-event batch with an empty event: the pruned graph is exactly the
+    candidate list (the plain path's graph) filtered by the keep flags, in
+    order, with per-event offsets that follow; with tau above every
+    probability nothing is kept and every hit is its own component."""
+    etx = _etx()
+    w = synth.C3
+    W = synth.xavier_weights(w)
+    batch = dict(synth.generate_batch(w, 30))
+    ho = batch["hit_off"]
+    batch["hit_off"] = np.insert(ho, 5, ho[5]).astype(np.int64)
+    _, flat = pf_params()
+    b = etx.to_device(batch)
+    plain = etx.Pipeline(w, W)
+    plain.run(b)
+    rp = plain.results(b)
+    q = etx.Pipeline(w, W, prefilter=1, prefilter_tau=tau)
+    etx.etx_prefilter_set(q.ctx, flat)
+    q.run(b)
+    r = q.results(b)
+    keep = q.view(b, etx.ETX_VIEW_PF_KEEP, torch.uint8).cpu().numpy()[:len(rp["src"])].astype(bool)
+    assert np.array_equal(r["src"], rp["src"][keep]) and np.array_equal(r["dst"], rp["dst"][keep])
+    kept_before = np.concatenate([[0], np.cumsum(keep)])
+    assert np.array_equal(r["edge_off"], kept_before[rp["edge_off"]])
+    if tau > 1:
+        assert len(r["src"]) == 0 and not keep.any()
+        assert np.array_equal(r["labels"], np.arange(len(r["labels"])))
+    else:
+        assert 0 < keep.sum() < len(keep)
