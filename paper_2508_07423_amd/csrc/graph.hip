@@ -359,16 +359,28 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(const int64_t* __re
   const uint64_t below = (uint64_t(1) << lane) - 1;    // lanes before this one
   int64_t cnt = 0;
   int slot = 0;
-  for (int64_t q0 = eb; q0 < ee; q0 += kCompactBallots * kCompactThreads) {
+  // the next round's scores are loaded before this round's barrier
+  constexpr int64_t kRound = (int64_t)kCompactBallots * kCompactThreads;
+  float sc[kCompactBallots];
+  auto load = [&](int64_t q0) {
+#pragma unroll
+    for (int j = 0; j < kCompactBallots; ++j) {
+      const int64_t q = q0 + (int64_t)wave * 64 * kCompactBallots + 64 * j + lane;
+      sc[j] = q < ee ? score[q] : 0.f;
+    }
+  };
+  if (eb < ee) load(eb);
+  for (int64_t q0 = eb; q0 < ee; q0 += kRound) {
     const int64_t w0 = q0 + (int64_t)wave * 64 * kCompactBallots;
     uint64_t m[kCompactBallots];
     int n = 0;
 #pragma unroll
     for (int j = 0; j < kCompactBallots; ++j) {
       const int64_t q = w0 + 64 * j + lane;
-      m[j] = __ballot(q < ee && score[q] >= thr);
+      m[j] = __ballot(q < ee && sc[j] >= thr);
       n += __popcll(m[j]);
     }
+    if (q0 + kRound < ee) load(q0 + kRound);
     if (lane == 0) tot[slot][wave] = n;
     __syncthreads();
     int base = 0, total = 0;
