@@ -49,3 +49,19 @@ def test_prefilter_fallback_band():
     lo, hi = fallback_band(kept, cand, quantile=0.0, margin=0.8)
     assert hi == 1.0 and lo == pytest.approx(0.8 * 0.6)
     assert fallback_band(np.zeros(3), np.zeros(3)) == (0.0, 1.0)
+
+
+def test_measured_traffic_only_for_the_profiled_source(monkeypatch):
+    """The roofline's counter-measured traffic is reported only while the
+    kernel's source hashes to what was profiled; a changed source gives null,
+    and so does a kernel or workload with no record."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(bench.__file__), "profiles", "traffic.json")
+    rec = next(r for r in json.load(open(path))["records"] if r["kernel"] == "edge_step" and r["dtype"] == "f32")
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda kernel: rec["source_sha256"])
+    assert bench.measured_traffic("edge_step", "c2", "f32") == rec["bytes_per_launch"]
+    assert rec["bytes_per_launch"] == rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda kernel: "0" * 64)
+    assert bench.measured_traffic("edge_step", "c2", "f32") is None
+    assert bench.measured_traffic("edge_step", "c9", "f32") is None
