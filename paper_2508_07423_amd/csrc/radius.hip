@@ -44,7 +44,8 @@ struct RadiusArgs {
   float r2, r;
   int32_t* cnt;            // count pass output (and the select pass's)
   const int64_t* row_ptr;  // emit pass input
-  int32_t* slots;          // select pass output: [n_hits][k_max] kept targets, ascending
+  int32_t* slots;          // select pass output: kept targets, ascending (slot_index)
+  int64_t n_hits;
   int32_t* src;
   int32_t* dst;
   const int64_t* status;
@@ -83,6 +84,18 @@ struct RadiusLds {
 // writing each source's kept targets (ascending) to its k_max slots and its
 // count, so that the CSR rows are a copy after the scan.
 enum RadiusMode { R_COUNT = 0, R_EMIT = 1, R_SELECT = 2 };
+
+// Slot of rank r of hit i in the select pass's output: the first kSlotHead
+// ranks of every hit side by side ([n_hits][kSlotHead]), the others after
+// them ([n_hits][k_max - kSlotHead]).  Rows of a trained embedding hold a few
+// targets, so the copy into CSR rows reads the dense head instead of a
+// k_max-wide row per hit; long rows stay contiguous in both parts.
+constexpr int kSlotHead = 4;
+
+__device__ inline int64_t slot_index(int64_t i, int r, int64_t n_hits, int k_max) {
+  const int head = min(kSlotHead, k_max);
+  return r < head ? i * head + r : n_hits * head + i * (k_max - head) + (r - head);
+}
 
 // Window size of an (event, plane) unit: hits on the planes after p within
 // the plane window (0 on the last plane).
@@ -342,7 +355,7 @@ __device__ inline void radius_unit(const RadiusArgs& A, float* lds, int ev, int 
           const int my = sb[l16];
           int rank = 0;
           for (int q = 0; q < n; ++q) rank += sb[q] < my;
-          A.slots[(int64_t)i * A.k_max + rank] = my;
+          A.slots[slot_index(i, rank, A.n_hits, A.k_max)] = my;
         }
         if (l16 == 0) A.cnt[i] = n;
       } else if (live && l16 == 0) {
@@ -559,7 +572,7 @@ __device__ inline void radius_unit(const RadiusArgs& A, float* lds, int ev, int 
       int rank = 0;
       for (int q = 0; q < ns; ++q) rank += sl[q] < my;
       if (MODE == R_SELECT) {
-        A.slots[(int64_t)i * A.k_max + rank] = my;
+        A.slots[slot_index(i, rank, A.n_hits, A.k_max)] = my;
       } else {
         const int64_t pos = A.row_ptr[i] + rank;
         A.src[pos] = i;
@@ -612,7 +625,7 @@ __global__ __launch_bounds__(256) void k_slots_to_csr(const int32_t* __restrict_
       if (q < total) {
         const int64_t i = h0 + lo;
         src[base + q] = (int32_t)i;
-        dst[base + q] = slots[i * k_max + (q - r0)];
+        dst[base + q] = slots[slot_index(i, q - r0, n_hits, k_max)];
       }
     }
   }
@@ -654,6 +667,7 @@ hipError_t launch_radius(const RunArgs& a, int mode, bool candidates) {
   A.src = candidates ? reinterpret_cast<int32_t*>(a.ws + a.L.cand_src) : a.out.src;
   A.dst = candidates ? reinterpret_cast<int32_t*>(a.ws + a.L.cand_dst) : a.out.dst;
   A.slots = reinterpret_cast<int32_t*>(a.ws + a.L.slots);
+  A.n_hits = a.hits.n_hits;
   A.status = a.out.status;
   dim3 grid((unsigned)(a.hits.n_events * c.n_planes));
   const bool small = c.emb_dim <= 8;
