@@ -14,7 +14,7 @@ namespace etx {
 
 constexpr int kEdgeTile = 16;      // edges per wave tile of the MLP kernels (the MFMA column count)
 constexpr int kDpad = 16;          // padded embedding width in HBM
-constexpr int kScanBlock = 1024;   // elements per block of the device-wide scan
+constexpr int kScanBlock = 8192;   // elements per block of the device-wide scan
 
 // Kernel precisions (tile.hpp's Prec): FP32, BF16, FP8, FP32 as three BF16
 // parts, BF16 / FP8 / INT8 operands with FP32 node and edge state.
