@@ -114,6 +114,31 @@ def test_c1_csc_order(c1_run):
     assert np.array_equal(col_ptr, np.concatenate([[0], np.cumsum(np.bincount(res["dst"], minlength=b.n_hits))]))
 
 
+@pytest.mark.parametrize("place", [1, 0])
+def test_csc_order_trained_batch(place):
+    """An uneven trained-weight batch (short rows; events of up to 4,096 hits
+    in the small-LDS launch, the larger ones in the other), with block
+    placement and with the one-wave form: the (dst, src) order of every
+    event."""
+    etx = _etx()
+    w = synth.C3
+    if not os.path.exists(os.path.join(synth.TRAINED_DIR, f"{w.name}_trained.npz")):
+        pytest.skip("trained weights not built")
+    batch = synth.generate_batch(w, 40)
+    p = etx.Pipeline(w, synth.trained_weights(w))
+    etx.etx_set_option(p.ctx, etx.ETX_OPT_CSC_PLACE, place)
+    b = etx.to_device(batch)
+    p.run(b)
+    res = p.results(b)
+    E = int(res["edge_off"][-1])
+    col_ptr = p.view(b, etx.ETX_VIEW_COL_PTR, torch.int64).cpu().numpy()
+    csc = p.view(b, etx.ETX_VIEW_CSC_EDGE, torch.int32).cpu().numpy()[:E]
+    assert np.array_equal(csc, np.lexsort((res["src"], res["dst"])))
+    assert np.array_equal(col_ptr, np.concatenate([[0], np.cumsum(np.bincount(res["dst"], minlength=b.n_hits))]))
+    hits = np.diff(batch["hit_off"])
+    assert (hits <= 4096).sum() >= 10 and hits.max() > 4096   # both launches are exercised
+
+
 def test_c1_kept_compaction(c1_run):
     w, W, batch, p, b, res = c1_run
     kc = p.view(b, _etx().ETX_VIEW_KEPT_COUNT, torch.int32).cpu().numpy()
