@@ -202,7 +202,8 @@ constexpr int kCscRowWalk = 16;
 
 // The per-event kernels that keep one LDS word per hit of the event run as
 // two launches: events of up to kSmallEventHits hits in workgroups with 16 KiB
-// of LDS (eight to a CU, so that their chains of loads and barriers overlap),
+// of LDS (six to eight to a CU, registers deciding, so that their chains of
+// loads and barriers overlap),
 // the larger ones with room for ETX_MAX_EVENT_HITS; each launch skips the
 // other's events.
 constexpr int kSmallEventHits = 4096;
